@@ -1,0 +1,215 @@
+"""CPU FP64 oracle of the WCSPH particle-interaction step (test infrastructure).
+
+A plain, slow, brute-force implementation (``sph_oracle.c``) of Section 2 and
+Section 5.1 of the DualSPHysics v5.0 paper, wrapped with ctypes for numpy
+arrays.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it; the product path never imports it.
+
+Every function is pinned by tests in ``tests/test_oracle_*.py`` against what
+the paper and the mathematics fix (closed forms, invariants, brute-force
+lattice counts, exact special cases).  Long multi-step trajectories are
+"parity unpinned" beyond those pins: the paper's experimental comparisons
+need datasets that are not available.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "sph_oracle.c")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-D_GNU_SOURCE",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("ddt", C.c_int32), ("ncell", C.c_int32 * 3),
+        ("pad", C.c_int32), ("origin", C.c_double * 3),
+        ("inv_cell_size", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
+        ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
+        ("delta", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
+        ("mass_fluid", C.c_double), ("mass_bound", C.c_double),
+        ("gravity", C.c_double * 3), ("motion_amp", C.c_double),
+        ("motion_omega", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        L.orc_wendland_w.restype = C.c_double
+        L.orc_wendland_w.argtypes = [C.c_double, C.c_double, C.c_int32]
+        L.orc_wendland_fab.restype = C.c_double
+        L.orc_wendland_fab.argtypes = [C.c_double, C.c_double, C.c_int32]
+        L.orc_pressure.restype = C.c_double
+        L.orc_pressure.argtypes = [P(OrcParams), C.c_double]
+        L.orc_cell_keys.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_sort_perm.argtypes = [C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_cell_start.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_interact.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_time_step.restype = C.c_double
+        L.orc_time_step.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
+        for name in ("orc_predictor", "orc_corrector"):
+            getattr(L, name).argtypes = [P(OrcParams), C.c_int64, C.c_double,
+                                         C.c_double] + [C.c_void_p] * 9
+        L.orc_run.restype = C.c_int32
+        L.orc_run.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double),
+                              C.c_void_p, P(C.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def params(cp) -> OrcParams:
+    """OrcParams from a ``cases.CaseParams`` (or any object with its fields)."""
+    p = OrcParams()
+    p.dim = int(cp.dim)
+    p.ddt = int(cp.ddt)
+    for k in range(3):
+        p.ncell[k] = int(cp.ncell[k])
+        p.origin[k] = float(cp.origin[k])
+        p.gravity[k] = float(cp.gravity[k])
+    p.inv_cell_size = float(cp.inv_cell_size)
+    for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
+                 "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
+        setattr(p, name, float(getattr(cp, name)))
+    return p
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def wendland_w(r, h, dim):
+    return float(lib().orc_wendland_w(float(r), float(h), int(dim)))
+
+
+def wendland_fab(r, h, dim):
+    return float(lib().orc_wendland_fab(float(r), float(h), int(dim)))
+
+
+def pressure(cp, rho):
+    p = params(cp)
+    return float(lib().orc_pressure(C.byref(p), float(rho)))
+
+
+def cell_keys(cp, pos):
+    pos = _f64(pos)
+    n = pos.shape[1]
+    key = np.zeros(n, np.uint32)
+    p = params(cp)
+    lib().orc_cell_keys(C.byref(p), n, _ptr(pos), _ptr(key))
+    return key
+
+
+def sort_perm(key):
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    perm = np.zeros(key.shape[0], np.uint32)
+    lib().orc_sort_perm(key.shape[0], _ptr(key), _ptr(perm))
+    return perm
+
+
+def cell_start(sorted_key, ncell_total):
+    sk = np.ascontiguousarray(sorted_key, dtype=np.uint32)
+    start = np.zeros(int(ncell_total) + 1, np.uint32)
+    lib().orc_cell_start(sk.shape[0], _ptr(sk), int(ncell_total), _ptr(start))
+    return start
+
+
+def interact(cp, pos, vel, rho, ptype, targets=None):
+    """Brute-force PI for ``targets`` (indices; None = all).  Returns
+    (ace [dim, nt], arho [nt], visc [nt], nbr [nt])."""
+    pos, vel, rho = _f64(pos), _f64(vel), _f64(rho)
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    n = rho.shape[0]
+    dim = int(cp.dim)
+    if targets is None:
+        nt, tptr, tarr = n, None, None
+    else:
+        tarr = np.ascontiguousarray(targets, dtype=np.int64)
+        nt, tptr = tarr.shape[0], _ptr(tarr)
+    ace = np.zeros((dim, nt), np.float64)
+    arho = np.zeros(nt, np.float64)
+    visc = np.zeros(nt, np.float64)
+    nbr = np.zeros(nt, np.uint32)
+    p = params(cp)
+    lib().orc_interact(C.byref(p), n, _ptr(pos), _ptr(vel), _ptr(rho), _ptr(ptype),
+                       nt, tptr, _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr))
+    return ace, arho, visc, nbr
+
+
+def time_step(cp, ptype, ace, visc):
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    ace, visc = _f64(ace), _f64(visc)
+    p = params(cp)
+    return float(lib().orc_time_step(C.byref(p), ptype.shape[0], _ptr(ptype),
+                                     _ptr(ace), _ptr(visc)))
+
+
+def predictor(cp, dt, t, pos, vel, rho, ptype, ace, arho):
+    """Returns (pos, vel, rho) at n+1/2 and the saved (pos_n, vel_n, rho_n)."""
+    pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    ace, arho = _f64(ace), _f64(arho)
+    pn, vn, rn = np.zeros_like(pos), np.zeros_like(vel), np.zeros_like(rho)
+    p = params(cp)
+    lib().orc_predictor(C.byref(p), rho.shape[0], float(dt), float(t), _ptr(pos),
+                        _ptr(vel), _ptr(rho), _ptr(ptype), _ptr(ace), _ptr(arho),
+                        _ptr(pn), _ptr(vn), _ptr(rn))
+    return (pos, vel, rho), (pn, vn, rn)
+
+
+def corrector(cp, dt, t, half, saved, ptype, ace, arho):
+    pos, vel, rho = (_f64(a).copy() for a in half)
+    pn, vn, rn = (_f64(a) for a in saved)
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    ace, arho = _f64(ace), _f64(arho)
+    p = params(cp)
+    lib().orc_corrector(C.byref(p), rho.shape[0], float(dt), float(t), _ptr(pos),
+                        _ptr(vel), _ptr(rho), _ptr(ptype), _ptr(ace), _ptr(arho),
+                        _ptr(pn), _ptr(vn), _ptr(rn))
+    return pos, vel, rho
+
+
+def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0):
+    """nsteps full symplectic steps.  Returns dict with pos, vel, rho, type,
+    t, dt history, interaction count and status."""
+    pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8).copy()
+    t = C.c_double(float(t0))
+    dts = np.zeros(max(int(nsteps), 1), np.float64)
+    inter = C.c_uint64(0)
+    p = params(cp)
+    st = lib().orc_run(C.byref(p), rho.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
+                       _ptr(ptype), int(nsteps), C.byref(t), _ptr(dts), C.byref(inter))
+    return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
+                dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))

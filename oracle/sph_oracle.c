@@ -1,0 +1,360 @@
+/*
+ * CPU oracle for the WCSPH particle-interaction step (test infrastructure).
+ * FP64, brute-force neighbour search, OpenMP over target particles.  See
+ * sph_oracle.h for the conventions.  Each function names the passage of the
+ * DualSPHysics v5.0 paper (arXiv 2104.00537) it follows, and the reading
+ * taken where the printed formula is garbled or silent.
+ *
+ * Compile without floating-point contraction (-ffp-contract=off): the cell
+ * key and the FP64 neighbour test are specified operation by operation.
+ */
+#include "sph_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EXCLUDED 0x80u
+#define ORC_FLUID 0u
+#define ORC_MOVING 2u
+
+static int is_fluid(uint8_t t) { return (t & 0x7fu) == ORC_FLUID; }
+static int is_excluded(uint8_t t) { return (t & ORC_EXCLUDED) != 0; }
+
+/* Normalisation alpha_D of the Wendland C2 kernel, Eq. 11: 7/(4 pi h^2) in
+ * 2-D and 21/(16 pi h^3) in 3-D (the printed "7/4 pi h^2" read as a single
+ * fraction; a unit integral of W pins it). */
+static double wendland_alpha(double h, int32_t dim) {
+  if (dim == 2) return 7.0 / (4.0 * M_PI * h * h);
+  return 21.0 / (16.0 * M_PI * h * h * h);
+}
+
+/* Eq. 11: W(r, h) = alpha_D (1 - q/2)^4 (2q + 1) for 0 <= q <= 2, q = r/h. */
+double orc_wendland_w(double r, double h, int32_t dim) {
+  double q = r / h;
+  if (q < 0.0 || q > 2.0) return 0.0;
+  double w = 1.0 - 0.5 * q;
+  return wendland_alpha(h, dim) * w * w * w * w * (2.0 * q + 1.0);
+}
+
+/* Gradient of Eq. 11 written as grad_a W_ab = F_ab r_ab with r_ab = r_a - r_b.
+ * d/dq [(1 - q/2)^4 (2q + 1)] = -5 q (1 - q/2)^3, and dq/dr = 1/h, so
+ * grad W = alpha_D (1/h) (-5 q (1 - q/2)^3) r_ab / r = -5 alpha_D / h^2
+ * (1 - q/2)^3 r_ab, i.e. F_ab = -5 alpha_D (1 - q/2)^3 / h^2 (finite at r=0). */
+double orc_wendland_fab(double r, double h, int32_t dim) {
+  double q = r / h;
+  if (q < 0.0 || q >= 2.0) return 0.0;
+  double w = 1.0 - 0.5 * q;
+  return -5.0 * wendland_alpha(h, dim) * w * w * w / (h * h);
+}
+
+/* Eq. 28: P = (c^2 rho0 / gamma) [(rho/rho0)^gamma - 1], with the constant
+ * numerical speed of sound c = c0 (Section 2.4). */
+double orc_pressure(const orc_params* p, double rho) {
+  double b = p->c0 * p->c0 * p->rho0 / p->gamma;
+  return b * (pow(rho / p->rho0, p->gamma) - 1.0);
+}
+
+/* Cell key of Section 5.1's cell-linked list: the cell index along each axis
+ * is floor((x - origin) * inv_cell_size) (an FP64 subtraction, then an FP64
+ * multiplication), and cells are numbered with x fastest, then y, then z.  A
+ * particle outside the grid gets the key ncell_total. */
+uint32_t orc_cell_key(const orc_params* p, const double* pos, int64_t n, int64_t i) {
+  int64_t c[3] = {0, 0, 0};
+  for (int k = 0; k < p->dim; ++k) {
+    double d = pos[k * n + i] - p->origin[k];
+    double s = d * p->inv_cell_size;
+    double f = floor(s);
+    if (!(f >= 0.0) || !(f < (double)p->ncell[k]))
+      return (uint32_t)((int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2]);
+    c[k] = (int64_t)f;
+  }
+  return (uint32_t)(c[0] + (int64_t)p->ncell[0] * (c[1] + (int64_t)p->ncell[1] * c[2]));
+}
+
+void orc_cell_keys(const orc_params* p, int64_t n, const double* pos, uint32_t* key) {
+  for (int64_t i = 0; i < n; ++i) key[i] = orc_cell_key(p, pos, n, i);
+}
+
+/* Stable ascending sort of particles by cell key (ties keep input order):
+ * perm[j] is the input index of the j-th particle in sorted order. */
+typedef struct { uint32_t key; uint32_t idx; } key_idx;
+
+static int cmp_key_idx(const void* a, const void* b) {
+  const key_idx* x = (const key_idx*)a;
+  const key_idx* y = (const key_idx*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+  return 0;
+}
+
+void orc_sort_perm(int64_t n, const uint32_t* key, uint32_t* perm) {
+  key_idx* a = (key_idx*)malloc(sizeof(key_idx) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) { a[i].key = key[i]; a[i].idx = (uint32_t)i; }
+  qsort(a, (size_t)n, sizeof(key_idx), cmp_key_idx);
+  for (int64_t i = 0; i < n; ++i) perm[i] = a[i].idx;
+  free(a);
+}
+
+/* First particle of every cell in sorted order (Section 5.1): start[c] is the
+ * number of particles whose key is below c, for c = 0..ncell_total, so cell c
+ * holds sorted particles [start[c], start[c+1]) and start[ncell_total] counts
+ * the particles inside the grid. */
+void orc_cell_start(int64_t n, const uint32_t* sorted_key, int64_t ncell_total,
+                    uint32_t* start) {
+  uint32_t* count = (uint32_t*)calloc((size_t)ncell_total + 2, sizeof(uint32_t));
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t k = sorted_key[i];
+    if ((int64_t)k > ncell_total) k = (uint32_t)ncell_total;
+    count[k]++;
+  }
+  uint32_t run = 0;
+  for (int64_t c = 0; c <= ncell_total; ++c) { start[c] = run; run += count[c]; }
+  free(count);
+}
+
+static double particle_mass(const orc_params* p, uint8_t t) {
+  return is_fluid(t) ? p->mass_fluid : p->mass_bound;
+}
+
+/* One particle-interaction pass (Section 2.3) for the listed targets, by
+ * brute force over every particle b != a with |r_ab|^2 < (2h)^2 (Eq. 4 with
+ * k = 2).  For a target a:
+ *
+ *  a fluid (Eq. 22 with Eq. 21, Eq. 15 with Eq. 17-18):
+ *    dv_a/dt   = g - sum_b m_b [(P_a + P_b)/(rho_a rho_b) + Pi_ab] grad_a W_ab
+ *    Pi_ab     = -alpha c0 mu_ab / rhobar_ab   if v_ab . r_ab < 0, else 0
+ *    mu_ab     = h v_ab . r_ab / (r_ab^2 + eta^2),  rhobar_ab = (rho_a+rho_b)/2
+ *    drho_a/dt = rho_a sum_b (m_b/rho_b) v_ab . grad_a W_ab + D_a
+ *    D_a       = delta h c0 sum_{b in F} psi_ab . grad_a W_ab V_b
+ *    visc_a    = max_b |mu_ab|          (the per-particle term of Eq. 35)
+ *
+ *  a wall (Eq. 36): drho_a/dt = rho_a sum_{b in F} (m_b/rho_b) v_ab.grad_a W_ab
+ *  and no momentum sum (its motion is imposed, Eq. 37).
+ *
+ * Readings: the mean in Eq. 21 is (x_a + x_b)/2; eta^2 = eta2 (the case uses
+ * 0.001 h^2); c_a and cbar_ab are the constant c0; psi_ab of Eq. 18 is taken
+ * along r_ba = r_b - r_a, the diffusive direction of the Molteni-Colagrossi
+ * term, so psi_ab . grad_a W_ab = 2 (rho_b - rho_a)(-F_ab) with F_ab < 0;
+ * density diffusion acts between fluid particles only.
+ *
+ * nbr[a] counts the pairs evaluated for a: all neighbours of a fluid target,
+ * the fluid neighbours of a wall target.  Outputs are indexed by target slot;
+ * ace is [dim][ntarget].  Excluded particles take no part and get zeros. */
+void orc_interact(const orc_params* p, int64_t n, const double* pos,
+                  const double* vel, const double* rho, const uint8_t* type,
+                  int64_t ntarget, const int64_t* target, double* ace,
+                  double* arho, double* visc, uint32_t* nbr) {
+  const int dim = p->dim;
+  const double h = p->h;
+  const double support2 = (2.0 * h) * (2.0 * h);
+
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < ntarget; ++s) {
+    const int64_t a = target ? target[s] : s;
+    double acc[3] = {0.0, 0.0, 0.0};
+    double cont = 0.0, diff = 0.0, vmax = 0.0;
+    uint32_t count = 0;
+    const uint8_t ta = type[a];
+    if (!is_excluded(ta)) {
+      const int fa = is_fluid(ta);
+      const double rho_a = rho[a];
+      const double p_a = orc_pressure(p, rho_a);
+      for (int64_t b = 0; b < n; ++b) {
+        if (b == a) continue;
+        const uint8_t tb = type[b];
+        if (is_excluded(tb)) continue;
+        const int fb = is_fluid(tb);
+        if (!fa && !fb) continue;  /* Eq. 36 sums over fluid b only */
+        double dx[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+        for (int k = 0; k < dim; ++k) {
+          dx[k] = pos[k * n + a] - pos[k * n + b];
+          r2 += dx[k] * dx[k];
+        }
+        if (!(r2 < support2)) continue;
+        const double r = sqrt(r2);
+        const double fab = orc_wendland_fab(r, h, dim);
+        double vr = 0.0;
+        for (int k = 0; k < dim; ++k) vr += (vel[k * n + a] - vel[k * n + b]) * dx[k];
+        const double rho_b = rho[b];
+        const double m_b = particle_mass(p, tb);
+        const double vol_b = m_b / rho_b;
+        cont += vol_b * vr * fab;  /* (m_b/rho_b) v_ab . grad_a W_ab */
+        count++;
+        if (fa) {
+          const double p_b = orc_pressure(p, rho_b);
+          const double mu = h * vr / (r2 + p->eta2);
+          const double rhobar = 0.5 * (rho_a + rho_b);
+          const double pi_ab = vr < 0.0 ? -p->alpha * p->c0 * mu / rhobar : 0.0;
+          const double coef = m_b * ((p_a + p_b) / (rho_a * rho_b) + pi_ab);
+          for (int k = 0; k < dim; ++k) acc[k] -= coef * fab * dx[k];
+          if (fabs(mu) > vmax) vmax = fabs(mu);
+          if (p->ddt && fb) {
+            const double psi_dot_grad = 2.0 * (rho_b - rho_a) * (-fab);
+            diff += psi_dot_grad * vol_b;
+          }
+        }
+      }
+      if (fa) {
+        for (int k = 0; k < dim; ++k) acc[k] += p->gravity[k];
+        arho[s] = rho_a * cont + p->delta * h * p->c0 * diff;
+      } else {
+        arho[s] = rho_a * cont;
+      }
+    } else {
+      arho[s] = 0.0;
+    }
+    for (int k = 0; k < dim; ++k) ace[k * ntarget + s] = acc[k];
+    if (visc) visc[s] = vmax;
+    if (nbr) nbr[s] = count;
+  }
+}
+
+/* Eq. 35 with C_CFL = cfl and c_s = c0: dt_f = min_a sqrt(h/|f_a|) and
+ * dt_cv = min_a h/(c0 + visc_a) over fluid particles (|f_a| is the full
+ * acceleration including gravity); dt = cfl min(dt_f, dt_cv). */
+double orc_time_step(const orc_params* p, int64_t n, const uint8_t* type,
+                     const double* ace, const double* visc) {
+  double dt_f = INFINITY, dt_cv = INFINITY;
+  for (int64_t a = 0; a < n; ++a) {
+    if (!is_fluid(type[a]) || is_excluded(type[a])) continue;
+    double f2 = 0.0;
+    for (int k = 0; k < p->dim; ++k) f2 += ace[k * n + a] * ace[k * n + a];
+    const double f = sqrt(f2);
+    if (f > 0.0) {
+      const double t1 = sqrt(p->h / f);
+      if (t1 < dt_f) dt_f = t1;
+    }
+    const double t2 = p->h / (p->c0 + visc[a]);
+    if (t2 < dt_cv) dt_cv = t2;
+  }
+  const double m = dt_f < dt_cv ? dt_f : dt_cv;
+  return p->cfl * m;
+}
+
+/* Imposed wall motion along x (Eq. 37 with a predefined law): displacement
+ * D(t) = (A/w^2)(1 - cos wt) and velocity (A/w) sin wt, so the wall starts at
+ * rest and its acceleration is A cos wt. */
+static double motion_disp(const orc_params* p, double t) {
+  if (p->motion_omega == 0.0) return 0.0;
+  const double w = p->motion_omega;
+  return p->motion_amp / (w * w) * (1.0 - cos(w * t));
+}
+static double motion_vel(const orc_params* p, double t) {
+  if (p->motion_omega == 0.0) return 0.0;
+  const double w = p->motion_omega;
+  return p->motion_amp / w * sin(w * t);
+}
+
+/* Symplectic predictor, Eq. 33 (first two lines) and Eq. 34 (first line):
+ * saves the state at n, then r^{n+1/2} = r^n + dt/2 v^n,
+ * v^{n+1/2} = v^n + dt/2 F^n, rho^{n+1/2} = rho^n + dt/2 R^n for fluid;
+ * walls update density only, and moving walls take their imposed position
+ * and velocity at t + dt/2. */
+void orc_predictor(const orc_params* p, int64_t n, double dt, double t,
+                   double* pos, double* vel, double* rho, const uint8_t* type,
+                   const double* ace, const double* arho, double* pos_n,
+                   double* vel_n, double* rho_n) {
+  const int dim = p->dim;
+  const double hdt = 0.5 * dt;
+  const double dmove = motion_disp(p, t + hdt) - motion_disp(p, t);
+  const double vmove = motion_vel(p, t + hdt);
+  for (int64_t a = 0; a < n; ++a) {
+    for (int k = 0; k < dim; ++k) {
+      pos_n[k * n + a] = pos[k * n + a];
+      vel_n[k * n + a] = vel[k * n + a];
+    }
+    rho_n[a] = rho[a];
+    if (is_excluded(type[a])) continue;
+    if (is_fluid(type[a])) {
+      for (int k = 0; k < dim; ++k) {
+        pos[k * n + a] = pos_n[k * n + a] + hdt * vel_n[k * n + a];
+        vel[k * n + a] = vel_n[k * n + a] + hdt * ace[k * n + a];
+      }
+    } else if ((type[a] & 0x7fu) == ORC_MOVING) {
+      pos[a] = pos_n[a] + dmove;
+      vel[a] = vmove;
+    }
+    rho[a] = rho_n[a] + hdt * arho[a];
+  }
+}
+
+/* Symplectic corrector, Eq. 33 (last two lines) and Eq. 34 (second line):
+ * v^{n+1} = v^n + dt F^{n+1/2}, r^{n+1} = r^n + dt (v^{n+1} + v^n)/2 for
+ * fluid; for every particle eps = -(R^{n+1/2}/rho^{n+1/2}) dt and
+ * rho^{n+1} = rho^n (2 - eps)/(2 + eps); moving walls take their imposed
+ * position and velocity at t + dt. */
+void orc_corrector(const orc_params* p, int64_t n, double dt, double t,
+                   double* pos, double* vel, double* rho, const uint8_t* type,
+                   const double* ace, const double* arho, const double* pos_n,
+                   const double* vel_n, const double* rho_n) {
+  const int dim = p->dim;
+  const double dmove = motion_disp(p, t + dt) - motion_disp(p, t);
+  const double vmove = motion_vel(p, t + dt);
+  for (int64_t a = 0; a < n; ++a) {
+    if (is_excluded(type[a])) continue;
+    if (is_fluid(type[a])) {
+      for (int k = 0; k < dim; ++k) {
+        const double v1 = vel_n[k * n + a] + dt * ace[k * n + a];
+        pos[k * n + a] = pos_n[k * n + a] + dt * 0.5 * (v1 + vel_n[k * n + a]);
+        vel[k * n + a] = v1;
+      }
+    } else if ((type[a] & 0x7fu) == ORC_MOVING) {
+      pos[a] = pos_n[a] + dmove;
+      vel[a] = vmove;
+    }
+    const double eps = -(arho[a] / rho[a]) * dt;
+    rho[a] = rho_n[a] * (2.0 - eps) / (2.0 + eps);
+  }
+}
+
+/* Marks particles outside the cell grid as excluded (they leave the
+ * computation for good, as the GPU path's binning does). */
+static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
+                          uint8_t* type) {
+  const uint32_t out = (uint32_t)((int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2]);
+  for (int64_t a = 0; a < n; ++a)
+    if (orc_cell_key(p, pos, n, a) == out) type[a] |= ORC_EXCLUDED;
+}
+
+/* nsteps symplectic steps (Section 2.5.2), each: PI at n -> dt (Eq. 35, from
+ * the state at n, used for both half steps) -> predictor -> PI at n+1/2 ->
+ * corrector -> t += dt.  dt_hist[s] receives each step's dt (nullable);
+ * *interactions accumulates the pair count of every PI (nullable).
+ * Returns 0; 1 if a density became non-finite or non-positive; 2 if dt is
+ * not a positive finite number (e.g. no fluid particle is left). */
+int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
+                double* rho, uint8_t* type, int32_t nsteps, double* t,
+                double* dt_hist, uint64_t* interactions) {
+  const int dim = p->dim;
+  size_t nd = (size_t)dim * (size_t)(n > 0 ? n : 1);
+  double* ace = (double*)calloc(nd, sizeof(double));
+  double* arho = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* visc = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  uint32_t* nbr = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+  double* pos_n = (double*)calloc(nd, sizeof(double));
+  double* vel_n = (double*)calloc(nd, sizeof(double));
+  double* rho_n = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  int32_t status = 0;
+  for (int32_t s = 0; s < nsteps && status == 0; ++s) {
+    mark_excluded(p, n, pos, type);
+    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    uint64_t count = 0;
+    for (int64_t a = 0; a < n; ++a) count += nbr[a];
+    const double dt = orc_time_step(p, n, type, ace, visc);
+    if (dt_hist) dt_hist[s] = dt;
+    if (!(dt > 0.0) || !isfinite(dt)) { status = 2; break; }
+    orc_predictor(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
+    mark_excluded(p, n, pos, type);
+    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    for (int64_t a = 0; a < n; ++a) count += nbr[a];
+    orc_corrector(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
+    *t += dt;
+    if (interactions) *interactions += count;
+    for (int64_t a = 0; a < n; ++a)
+      if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
+  }
+  free(ace); free(arho); free(visc); free(nbr);
+  free(pos_n); free(vel_n); free(rho_n);
+  return status;
+}

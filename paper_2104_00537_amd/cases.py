@@ -1,0 +1,301 @@
+"""Seeded synthetic SPH cases: dam breaks (2-D, 3-D) and a sloshing tank.
+
+This module only builds inputs.  It holds none of the solver's arithmetic
+(no kernel, equation of state, interaction sum or time integrator), so both
+the HIP path and the CPU oracle can take their inputs from it.
+
+Geometry conventions
+--------------------
+* Components are ordered (x, [y,] z) with the vertical axis last; a 2-D case
+  stores (x, z).
+* Fluid and wall particles sit on one Cartesian lattice of spacing ``dp``
+  (cell centres at ``(i + 0.5) dp``), as a case generator does for the
+  paper's dynamic boundary condition (Section 2.6.1): two layers of wall
+  particles outside every wall.
+* Every coordinate gets a seeded uniform jitter of +-1e-4 dp.
+* Mass is ``rho0 dp^d`` for every particle; the initial density is the
+  hydrostatic one for the fluid column height H, so that the Tait pressure
+  of Eq. 28 equals rho0 g (H - z) at t = 0 (walls above the free surface
+  start at rho0).  Velocities start at zero.
+* The numerical speed of sound is ``c0 = 10 sqrt(g H)`` (Section 2.4).
+* The cell grid covers the tank plus a margin (open tanks: head room up to
+  2.5 times the initial fluid height for run-up); cell size is ``2h/cell_div``
+  (Section 5.1 uses 2h; Section 5.3 reports cells of size h).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+from typing import Tuple
+
+import numpy as np
+
+FLUID, BOUND_FIXED, BOUND_MOVING = 0, 1, 2
+EXCLUDED = 0x80
+GRAVITY = 9.81
+
+__all__ = ["CaseParams", "Case", "dam_break_2d", "dam_break_3d", "sloshing_3d",
+           "block_case", "random_serving_case", "FLUID", "BOUND_FIXED",
+           "BOUND_MOVING", "EXCLUDED", "GRAVITY"]
+
+
+@dataclass
+class CaseParams:
+    """Scalar constants of one case (plain floats; mirrored by the C ABI)."""
+    name: str
+    dim: int
+    dp: float
+    h: float
+    rho0: float = 1000.0
+    gamma: float = 7.0
+    c0: float = 0.0
+    alpha: float = 0.01
+    delta: float = 0.1
+    eta2: float = 0.0
+    cfl: float = 0.2
+    mass_fluid: float = 0.0
+    mass_bound: float = 0.0
+    gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    ddt: int = 1
+    cell_div: int = 1
+    origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    cell_size: float = 0.0
+    inv_cell_size: float = 0.0
+    ncell: Tuple[int, int, int] = (1, 1, 1)
+    motion_amp: float = 0.0
+    motion_omega: float = 0.0
+    dt_floor: float = 1e-12
+    fluid_height: float = 0.0
+
+    def ncell_total(self) -> int:
+        return int(self.ncell[0]) * int(self.ncell[1]) * int(self.ncell[2])
+
+    def to_dict(self) -> dict:
+        return asdict(self)
+
+
+@dataclass
+class Case:
+    params: CaseParams
+    pos: np.ndarray   # (dim, n) float64
+    vel: np.ndarray   # (dim, n) float32
+    rho: np.ndarray   # (n,) float32
+    type: np.ndarray  # (n,) uint8
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.rho.shape[0])
+
+    @property
+    def n_fluid(self) -> int:
+        return int(np.count_nonzero(self.type == FLUID))
+
+
+# ----------------------------------------------------------------------------
+# lattice helpers
+# ----------------------------------------------------------------------------
+def _grid(*ranges):
+    """Integer lattice indices for the given half-open per-axis ranges."""
+    axes = [np.arange(lo, hi, dtype=np.int64) for lo, hi in ranges]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.reshape(-1) for m in mesh], axis=0)
+
+
+def _walls(dim, nx_tank, ny_tank, nz_tank, closed_top):
+    """Lattice indices of two wall layers around a tank of nx*ny*nz cells.
+
+    The bottom (and the lid of a closed tank) spans the full footprint
+    including the wall thickness; side walls span the tank height.
+    """
+    parts = []
+    if dim == 2:
+        parts.append(_grid((-2, nx_tank + 2), (-2, 0)))                 # bottom
+        if closed_top:
+            parts.append(_grid((-2, nx_tank + 2), (nz_tank, nz_tank + 2)))
+        parts.append(_grid((-2, 0), (0, nz_tank)))                      # x walls
+        parts.append(_grid((nx_tank, nx_tank + 2), (0, nz_tank)))
+    else:
+        parts.append(_grid((-2, nx_tank + 2), (-2, ny_tank + 2), (-2, 0)))
+        if closed_top:
+            parts.append(_grid((-2, nx_tank + 2), (-2, ny_tank + 2),
+                               (nz_tank, nz_tank + 2)))
+        parts.append(_grid((-2, 0), (-2, ny_tank + 2), (0, nz_tank)))
+        parts.append(_grid((nx_tank, nx_tank + 2), (-2, ny_tank + 2), (0, nz_tank)))
+        parts.append(_grid((0, nx_tank), (-2, 0), (0, nz_tank)))
+        parts.append(_grid((0, nx_tank), (ny_tank, ny_tank + 2), (0, nz_tank)))
+    return np.concatenate(parts, axis=1)
+
+
+def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
+            cell_div=1, wall_type=BOUND_FIXED, motion_amp=0.0,
+            motion_omega=0.0, h_factor=1.0, meta=None) -> Case:
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([fluid_idx, wall_idx], axis=1)
+    n = idx.shape[1]
+    pos = (idx.astype(np.float64) + 0.5) * dp
+    pos += rng.uniform(-1e-4 * dp, 1e-4 * dp, size=pos.shape)
+    ptype = np.empty(n, np.uint8)
+    ptype[: fluid_idx.shape[1]] = FLUID
+    ptype[fluid_idx.shape[1]:] = wall_type
+
+    h = h_factor * math.sqrt(dim) * dp
+    rho0, gamma = 1000.0, 7.0
+    c0 = 10.0 * math.sqrt(GRAVITY * fluid_height)
+    b_tait = c0 * c0 * rho0 / gamma
+    depth = np.maximum(fluid_height - pos[dim - 1], 0.0)
+    rho = rho0 * np.power(1.0 + rho0 * GRAVITY * depth / b_tait, 1.0 / gamma)
+    mass = rho0 * dp ** dim
+
+    cs = 2.0 * h / cell_div
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    nc = np.ceil((hi - lo) / cs).astype(np.int64)
+    origin = [float(v) for v in lo] + [0.0] * (3 - dim)
+    ncell = [int(v) for v in nc] + [1] * (3 - dim)
+    grav = [0.0, 0.0, 0.0]
+    grav[dim - 1] = -GRAVITY
+
+    params = CaseParams(
+        name=name, dim=dim, dp=dp, h=h, rho0=rho0, gamma=gamma, c0=c0,
+        alpha=0.01, delta=0.1, eta2=0.001 * h * h, cfl=0.2,
+        mass_fluid=mass, mass_bound=mass, gravity=tuple(grav), ddt=1,
+        cell_div=cell_div, origin=tuple(origin), cell_size=cs,
+        inv_cell_size=1.0 / cs, ncell=tuple(ncell), motion_amp=motion_amp,
+        motion_omega=motion_omega, fluid_height=fluid_height)
+    return Case(params=params, pos=np.ascontiguousarray(pos),
+                vel=np.zeros((dim, n), np.float32),
+                rho=rho.astype(np.float32), type=ptype, meta=dict(meta or {}))
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+def dam_break_2d(dp=0.01, tank=(1.6, 1.0), column=(0.4, 0.8), seed=0,
+                 cell_div=1) -> Case:
+    """2-D dam break: a column at x_min in an open-top tank."""
+    nxt, nzt = int(round(tank[0] / dp)), int(round(tank[1] / dp))
+    nxf, nzf = int(round(column[0] / dp)), int(round(column[1] / dp))
+    fluid = _grid((0, nxf), (0, nzf))
+    walls = _walls(2, nxt, 1, nzt, closed_top=False)
+    lo = (-2.0 * dp - 1e-3 * dp, -2.0 * dp - 1e-3 * dp)
+    hi = (nxt * dp + 2.0 * dp, max(nzt * dp, 2.5 * nzf * dp) + 2.0 * dp)
+    return _finish("dam_break_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
+                   cell_div=cell_div, meta=dict(tank=tank, column=column))
+
+
+def dam_break_3d(dp=0.6 / 126, tank=(1.6, 0.6, 0.6), block=(0.6, 0.6, 0.3),
+                 seed=0, cell_div=1) -> Case:
+    """3-D dam break: a water block at x_min filling the tank width."""
+    nxt, nyt, nzt = (int(round(v / dp)) for v in tank)
+    nxf, nyf, nzf = (int(round(v / dp)) for v in block)
+    fluid = _grid((0, nxf), (0, nyf), (0, nzf))
+    walls = _walls(3, nxt, nyt, nzt, closed_top=False)
+    m = 2.0 * dp + 1e-3 * dp
+    lo = (-m, -m, -m)
+    hi = (nxt * dp + m, nyt * dp + m, max(nzt * dp, 2.5 * nzf * dp) + m)
+    return _finish("dam_break_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
+                   cell_div=cell_div, meta=dict(tank=tank, block=block))
+
+
+def sloshing_3d(dp=0.0025, tank=(2.0, 1.0, 1.0), fill=0.5, seed=0,
+                cell_div=1, accel=0.05 * GRAVITY, freq_hz=0.5) -> Case:
+    """Closed tank, half full, whose walls follow the imposed sinusoidal
+    motion x_B(t) = x_B0 + (A/w^2)(1 - cos wt) (peak acceleration A)."""
+    nxt, nyt, nzt = (int(round(v / dp)) for v in tank)
+    nzf = int(round(fill * tank[2] / dp))
+    fluid = _grid((0, nxt), (0, nyt), (0, nzf))
+    walls = _walls(3, nxt, nyt, nzt, closed_top=True)
+    omega = 2.0 * math.pi * freq_hz
+    travel = 2.0 * accel / omega ** 2
+    m = 2.0 * dp + 1e-3 * dp
+    lo = (-m, -m, -m)
+    hi = (nxt * dp + m + travel, nyt * dp + m, nzt * dp + m)
+    return _finish("sloshing_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
+                   cell_div=cell_div, wall_type=BOUND_MOVING,
+                   motion_amp=accel, motion_omega=omega,
+                   meta=dict(tank=tank, fill=fill))
+
+
+def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
+               vel_scale=0.0, rho_jitter=0.0, margin_cells=2) -> Case:
+    """A fluid block of ``shape`` lattice cells (optionally in a closed box
+    of walls), with optional random velocities and densities.  Used for
+    invariance and parity tests."""
+    fluid = _grid(*[(0, s) for s in shape])
+    if walls:
+        if dim == 3:
+            wall = _walls(3, shape[0], shape[1], shape[2], closed_top=True)
+        else:
+            wall = _walls(2, shape[0], 1, shape[1], closed_top=True)
+    else:
+        wall = np.zeros((dim, 0), np.int64)
+    height = shape[-1] * dp
+    h = math.sqrt(dim) * dp
+    cs = 2.0 * h / cell_div
+    m = 2.0 * dp + margin_cells * cs
+    lo = tuple(-m for _ in range(dim))
+    hi = tuple(s * dp + m for s in shape)
+    case = _finish(f"block{dim}d", dim, dp, fluid, wall, height, lo, hi, seed,
+                   cell_div=cell_div, meta=dict(shape=shape, walls=walls))
+    rng = np.random.default_rng(seed + 7919)
+    if vel_scale:
+        case.vel[:] = rng.uniform(-vel_scale, vel_scale, case.vel.shape).astype(np.float32)
+    if rho_jitter:
+        case.rho[:] = (case.rho * (1.0 + rng.uniform(-rho_jitter, rho_jitter,
+                                                     case.rho.shape))).astype(np.float32)
+    return case
+
+
+def random_serving_case(rng: np.random.Generator, n_min=2000, n_max=500_000,
+                        seed=None) -> Case:
+    """One request of the serving stream: a 2-D or 3-D dam break or sloshing
+    case with a log-uniform fluid particle count, column aspect ratio
+    uniform in [0.5, 2] and fill ratio uniform in [0.3, 0.7]."""
+    dim = int(rng.integers(2, 4))
+    kind = "dam_break" if rng.random() < 0.5 else "sloshing"
+    n_target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    aspect = rng.uniform(0.5, 2.0)
+    fill = rng.uniform(0.3, 0.7)
+    steps = int(rng.integers(1000, 5001))
+    sub_seed = int(rng.integers(0, 2**31 - 1)) if seed is None else seed
+    if kind == "dam_break":
+        length = 1.6
+        width = fill * length / 2.0
+        height = aspect * width
+        tank_h = max(1.0, 1.25 * height)
+        if dim == 2:
+            dp = math.sqrt(width * height / n_target)
+            case = dam_break_2d(dp=dp, tank=(length, tank_h), column=(width, height),
+                                seed=sub_seed)
+        else:
+            depth_y = 0.6
+            dp = (width * depth_y * height / n_target) ** (1.0 / 3.0)
+            case = dam_break_3d(dp=dp, tank=(length, depth_y, tank_h),
+                                block=(width, depth_y, height), seed=sub_seed)
+    else:
+        if dim == 2:
+            dp = math.sqrt(2.0 * fill * 1.0 / n_target)
+            case = _sloshing_2d(dp, fill, sub_seed)
+        else:
+            dp = (2.0 * 1.0 * fill * 1.0 / n_target) ** (1.0 / 3.0)
+            case = sloshing_3d(dp=dp, fill=fill, seed=sub_seed)
+    case.meta.update(kind=kind, steps=steps, aspect=aspect, fill=fill,
+                     n_target=n_target)
+    return case
+
+
+def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
+                 freq_hz=0.5) -> Case:
+    nxt, nzt = int(round(tank[0] / dp)), int(round(tank[1] / dp))
+    nzf = max(1, int(round(fill * tank[1] / dp)))
+    fluid = _grid((0, nxt), (0, nzf))
+    walls = _walls(2, nxt, 1, nzt, closed_top=True)
+    omega = 2.0 * math.pi * freq_hz
+    travel = 2.0 * accel / omega ** 2
+    m = 2.0 * dp + 1e-3 * dp
+    lo = (-m, -m)
+    hi = (nxt * dp + m + travel, nzt * dp + m)
+    return _finish("sloshing_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
+                   wall_type=BOUND_MOVING, motion_amp=accel, motion_omega=omega,
+                   meta=dict(tank=tank, fill=fill))
