@@ -1,0 +1,171 @@
+"""Benchmark: particle interactions/s of the WCSPH hot path on one MI355X.
+
+A step is one full symplectic step of the hot path (two neighbour lists, two
+interaction passes, the time step, predictor and corrector) on the 3-D dam
+break with 1.0M fluid particles (plus 0.32M wall particles), all state
+resident in HBM.  The JSON line reports:
+
+  value      particle interactions (ordered pairs evaluated, the paper's PIPS
+             count) per second over the K timed steps, counted on the device;
+  roofline   the interaction kernel (the dominant one): algorithmic FP32
+             flops per launch / its average duration from HIP events on the
+             launch stream, against the FP32 vector peak;
+  cpu_baseline  the CPU FP64 oracle on a bounded sample of the same pass.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle interactions/s at 3D 1M particles; batched solves/s + p50/p99 latency"
+
+# Algorithmic FP32 flops per evaluated pair (FMA = 2, sqrt and division = 1):
+# fluid target: kernel gradient 15, relative velocity and v.r 8, volume 1,
+# continuity 3, pressure term 3, viscosity mu 3 and Pi 4, coefficient 3,
+# momentum update 6, density diffusion 4  -> 50;
+# wall target (continuity of Eq. 36 only): 15 + 8 + 1 + 3 -> 27.
+FLOPS_FLUID_PAIR = 50
+FLOPS_WALL_PAIR = 27
+# FP32 vector issue peak without packed-FP32 instructions (the build disables
+# them): 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(name, cell_div):
+    from paper_2104_00537_amd import cases
+    if name == "dam_break_3d_1m":
+        return cases.dam_break_3d(cell_div=cell_div)
+    if name == "dam_break_3d_0p5m":
+        return cases.dam_break_3d(dp=0.006, cell_div=cell_div)
+    if name == "dam_break_2d":
+        return cases.dam_break_2d(cell_div=cell_div)
+    if name == "sloshing_3d_64m":
+        return cases.sloshing_3d(cell_div=cell_div)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, sim, seconds):
+    """The oracle (brute force, FP64) on a random sample of targets of the
+    benchmarked state; interactions/s over the sampled targets."""
+    import numpy as np
+    import oracle
+    st = sim.host_state()
+    rng = np.random.default_rng(1234)
+    n = case.n
+    cp = case.params
+    args = (cp, st["pos"], st["vel"].astype(np.float64), st["rho"].astype(np.float64), st["type"])
+    oracle.interact(*args, targets=rng.choice(n, size=min(n, 16), replace=False))  # warm-up
+    probe = rng.choice(n, size=min(n, 128), replace=False)
+    t0 = time.perf_counter()
+    oracle.interact(*args, targets=probe)
+    t_probe = max(time.perf_counter() - t0, 1e-4)
+    k = int(min(n, max(len(probe), len(probe) * seconds / t_probe)))
+    sample = rng.choice(n, size=k, replace=False)
+    t0 = time.perf_counter()
+    _, _, _, nbr = oracle.interact(*args, targets=sample)
+    el = time.perf_counter() - t0
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    cores = min(aff, int(omp)) if omp and omp.isdigit() else aff
+    return {"value": float(nbr.astype(np.int64).sum() / el), "unit": "interactions/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"one interaction pass for {k} random targets of {n} particles "
+                      f"(all {n} as candidate neighbours, brute force FP64), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="dam_break_3d_1m")
+    ap.add_argument("--cell-div", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this path has no multi-GPU mode "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2104_00537_amd.runner import Simulation
+
+    case = workload(args.workload, args.cell_div)
+    sim = Simulation(case, "cuda:0")
+    print(f"[bench] {args.workload}: n={case.n} fluid={case.n_fluid} cells={case.params.ncell}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    if sim.error() != 0:
+        raise SystemExit(f"device error word {sim.error()} after warm-up")
+    inter0 = sim.interactions.clone()
+    timing = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sim.step(timing=timing)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    err = sim.error()
+    if err != 0:
+        raise SystemExit(f"device error word {err} during the timed steps")
+    d_inter = (sim.interactions - inter0).cpu().numpy().astype(np.int64)
+    pairs, wall_pairs = int(d_inter[0]), int(d_inter[1])
+    phase_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in timing.items()}
+    launches = len(timing["interact"])
+    t_int = phase_ms["interact"] * 1e-3
+    flops = (FLOPS_FLUID_PAIR * (pairs - wall_pairs) + FLOPS_WALL_PAIR * wall_pairs) / launches
+    achieved = flops / t_int / 1e12
+    # algorithmic bytes of one interaction launch: per particle the view read
+    # (2 x 16 B), ace + arho written (4 x 4 B), key and cell range reads (8 B)
+    bytes_per_launch = case.n * (32 + 16 + 8)
+    res = {
+        "metric": METRIC,
+        "value": pairs / el,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_particles": case.n, "n_fluid": case.n_fluid,
+                   "dp": case.params.dp, "h": case.params.h, "cell_div": args.cell_div,
+                   "parallelism": "single GPU", "positions": "fp64 state, fp32 cell-relative"},
+        "steps_per_s": args.steps / el,
+        "interactions_per_step": pairs / args.steps,
+        "phase_ms_per_call": phase_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_interact_gather",
+                     "flops_per_launch": flops, "avg_launch_ms": phase_ms["interact"],
+                     "hbm_algorithmic_GBs": bytes_per_launch / t_int / 1e9},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

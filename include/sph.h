@@ -1,0 +1,207 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) WCSPH particle-interaction hot path.
+ *
+ * One simulation step of a weakly compressible SPH solver is split, as in
+ * Section 5.1 of the DualSPHysics v5.0 paper (arXiv 2104.00537), into a
+ * neighbour list (NL), a particle interaction (PI) and a system update (SU):
+ *
+ *   sph_bin_cells        NL: cell keys, stable radix sort, cell ranges, and the
+ *                        particle arrays reordered into sorted SoA (plus the
+ *                        per-particle data the interaction reads).
+ *   sph_interact         PI: continuity and momentum sums over the neighbours
+ *                        within 2h (Eq. 11, 15, 17-18, 21-22, 28, 36), plus the
+ *                        per-particle maxima that set the time step.
+ *   sph_reduce_dt        SU: the variable time step of Eq. 35, kept on the GPU.
+ *   sph_symplectic_step  SU: symplectic predictor / corrector (Eq. 33-34), with
+ *                        imposed motion of moving walls (Eq. 37).
+ *
+ * A full step is: bin, interact, reduce_dt, predictor, bin (carrying the saved
+ * state along), interact, corrector.
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer to memory the caller owns (the
+ *    library allocates nothing and keeps no pointer after a call returns).
+ *  - Arrays are structure-of-arrays and component-major: component k of
+ *    particle i is x[k*n + i].  Positions are FP64, velocity and density FP32.
+ *    2-D cases store (x, z) -- the vertical axis is always the last component.
+ *  - Particle type (uint8): 0 fluid, 1 fixed wall, 2 moving wall; bit 0x80 is
+ *    set by sph_bin_cells on particles outside the cell grid, which then take
+ *    no part in the interaction or the update ("excluded").
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL means
+ *    the default stream).  Calls on distinct workspaces are independent.
+ *  - Every call returns an sph_status synchronously for argument and launch
+ *    errors.  Data-dependent failures (a non-finite or non-positive density,
+ *    a particle leaving the grid, dt below dt_floor) set bits of a device
+ *    error word in the workspace, read with sph_read_error after the stream
+ *    has finished.  No call aborts the process or throws.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sph_status {
+  SPH_OK = 0,
+  SPH_E_ARG = -1,        /* a bad argument: null pointer, size, parameter */
+  SPH_E_WORKSPACE = -2,  /* workspace smaller than sph_workspace_bytes() */
+  SPH_E_HIP = -3         /* a HIP launch or runtime error */
+} sph_status;
+
+enum {
+  SPH_FLUID = 0,
+  SPH_BOUND_FIXED = 1,
+  SPH_BOUND_MOVING = 2,
+  SPH_EXCLUDED = 0x80
+};
+
+/* bits of the device error word */
+enum {
+  SPH_ERR_NONFINITE = 1u,   /* non-finite velocity, or density not in (0, inf) */
+  SPH_ERR_EXCLUDED = 2u,    /* a particle left the cell grid and was excluded */
+  SPH_ERR_DT_FLOOR = 4u     /* dt fell below dt_floor, or is not finite */
+};
+
+/* flags of sph_interact */
+enum {
+  /* nbr_count uses an FP64 distance test on the FP64 positions (bit-exact
+   * neighbour counts); the sums always use the FP32 cell-relative test. */
+  SPH_DIAG_COUNT_F64 = 1u
+};
+
+/* Case constants, passed by pointer to host memory and copied by value into
+ * the launches. */
+typedef struct sph_params {
+  int32_t dim;            /* 2 or 3 */
+  int32_t cell_div;       /* 1: cells of size 2h, search +-1 cell (Section 5.1);
+                             2: cells of size h, search +-2 cells (Section 5.3) */
+  int32_t ddt;            /* 0: no density diffusion; 1: Eq. 17 with Eq. 18 */
+  int32_t ncell[3];       /* cells per axis; ncell[2] = 1 in 2-D.  Keys are
+                             cx + ncell[0]*(cy + ncell[1]*cz) (x fastest); the
+                             key of a particle outside the grid is the total
+                             cell count.  total + 1 must be < 2^32. */
+  double origin[3];       /* grid origin (components beyond dim ignored) */
+  double cell_size;       /* cs = 2h / cell_div */
+  double inv_cell_size;   /* 1/cs, computed once by the caller; the cell index
+                             is floor((x - origin) * inv_cell_size) in FP64 */
+  double h;               /* smoothing length; support radius 2h */
+  double rho0;            /* reference density (Eq. 28) */
+  double gamma;           /* polytropic index (Eq. 28) */
+  double c0;              /* numerical speed of sound (Section 2.4) */
+  double alpha;           /* artificial viscosity coefficient (Eq. 21) */
+  double delta;           /* density diffusion coefficient (Eq. 17) */
+  double eta2;            /* eta^2 in the denominators of Eq. 21 and Eq. 35 */
+  double cfl;             /* Courant number C_CFL (Eq. 35) */
+  double mass_fluid;      /* particle masses of fluid / wall particles */
+  double mass_bound;
+  double gravity[3];      /* body force f of Eq. 13 */
+  double motion_amp;      /* moving walls: x(t) = x0 + (A/w^2)(1 - cos wt),   */
+  double motion_omega;    /*   A = motion_amp, w = motion_omega (0: no motion) */
+  double dt_floor;        /* smallest acceptable dt (error bit below it) */
+} sph_params;
+
+/* Particle state (SoA device arrays of n particles). */
+typedef struct sph_state {
+  double* pos;      /* [dim][n] FP64 positions */
+  float* vel;       /* [dim][n] velocities */
+  float* rho;       /* [n] densities */
+  uint8_t* type;    /* [n] particle type, see SPH_FLUID ... */
+  uint32_t* id;     /* [n] particle identity, carried through the sort
+                       (nullable: then not carried) */
+} sph_state;
+
+/* Bytes of workspace the calls need for a case of n particles. */
+size_t sph_workspace_bytes(const sph_params* p, int64_t n);
+
+/* NL (Section 5.1).  For every particle of `in`: the cell key (see
+ * sph_params.ncell), a stable ascending sort of the keys (ties keep input
+ * order), the index of the first sorted particle of every cell, and the state
+ * gathered into sorted order.
+ *   key[n]            out: sorted keys (particles outside the grid, or already
+ *                     excluded, get the key C = total cells and sort last)
+ *   perm[n]           out: perm[j] = input index of the j-th sorted particle
+ *   cell_start[C+1]   out: C = total cells; cell c holds sorted particles
+ *                     [cell_start[c], cell_start[c+1]); cell_start[C] is the
+ *                     number of particles inside the grid
+ *   out               out: `in` gathered by perm (pos, vel, rho, type, id);
+ *                     newly excluded particles get the 0x80 type bit
+ *   carry_in/out      nullable pair: a second state (pos, vel, rho only)
+ *                     gathered by the same perm -- the saved state n during
+ *                     the corrector's NL.
+ * `in` and `out` must not alias. */
+sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in,
+                         sph_state* out, const sph_state* carry_in,
+                         sph_state* carry_out, uint32_t* key, uint32_t* perm,
+                         uint32_t* cell_start, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* PI (Section 2.3, Eq. 11, 15, 17-18, 21-22, 28, 36) on a state that
+ * sph_bin_cells sorted (s, key, cell_start from the same call; the call also
+ * left in the workspace the per-particle data this pass reads -- cell-relative
+ * FP32 positions, velocities, densities and Tait pressures -- so nothing may
+ * change the state in between, and the workspace must be the same).  For every
+ * non-excluded particle a, over neighbours b != a with |r_ab| < 2h:
+ *   fluid a:  ace[a]  = g - sum_b m_b [(P_a+P_b)/(rho_a rho_b) + Pi_ab] grad_a W_ab
+ *             arho[a] = rho_a sum_b (m_b/rho_b) v_ab.grad_a W_ab + D_a
+ *             with D_a = 2 delta h c0 sum_{b fluid} (rho_b - rho_a)|F_ab| m_b/rho_b
+ *             (the diffusive reading of Eq. 18) and P from Eq. 28;
+ *   wall a:   arho[a] = rho_a sum_{b fluid} (m_b/rho_b) v_ab.grad_a W_ab, ace = 0.
+ *   ace[dim][n], arho[n]   out (FP32, sorted order; excluded particles get 0)
+ *   visc[n]                out, nullable: max_b |h v_ab.r_ab|/(r_ab^2+eta^2)
+ *   nbr_count[n]           out, nullable: pairs evaluated for a (all neighbours
+ *                          of a fluid target, fluid neighbours of a wall)
+ * Arithmetic is FP32 on cell-relative FP32 positions (Section 5.1, precision
+ * paragraph).  Per-block maxima of |ace| and visc over fluid targets and the
+ * interaction count go to the workspace for sph_reduce_dt. */
+sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s,
+                        const uint32_t* key, const uint32_t* cell_start,
+                        float* ace, float* arho, float* visc,
+                        uint32_t* nbr_count, uint32_t flags, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* SU, Eq. 35: dt = cfl * min(sqrt(h / max_a |f_a|), h / (c0 + max_a visc_a))
+ * over fluid particles, reduced from the last sph_interact on this workspace.
+ *   dt[1]            out: FP64, device
+ *   interactions[2]  in/out, nullable: the pass's pair count is ADDED to [0],
+ *                    the part of it with a wall target (continuity only) to [1]
+ *   maxima[2]        out, nullable: {max |f_a|, max visc_a} (FP32)
+ * Sets SPH_ERR_DT_FLOOR if dt < dt_floor or dt is not finite. */
+sph_status sph_reduce_dt(const sph_params* p, int64_t n, double* dt,
+                         uint64_t* interactions, float* maxima, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* SU, Eq. 33-34, symplectic position Verlet, on the sorted state.
+ *   phase 0 (predictor): saves s into `saved` (pos, vel, rho), then for fluid
+ *     r += dt/2 v, v += dt/2 ace, and for all rho += dt/2 arho;
+ *   phase 1 (corrector): with ace, arho evaluated at n+1/2 and `saved` holding
+ *     state n (in the current sorted order): fluid v = v_n + dt ace,
+ *     r = r_n + dt (v + v_n)/2; all: eps = -(arho/rho) dt,
+ *     rho = rho_n (2 - eps)/(2 + eps); then *t += dt.
+ *   Moving walls take x = x_n + D(t') - D(t), v_x = (A/w) sin(w t') at
+ *   t' = t + dt/2 (predictor) or t + dt (corrector), D(t) = (A/w^2)(1-cos wt).
+ *   dt, t: device FP64 scalars (t is read by both phases, advanced by phase 1).
+ * Position arithmetic is FP64; velocity and density are stored in FP32. */
+sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase,
+                               const double* dt, double* t, sph_state* saved,
+                               sph_state* s, const float* ace,
+                               const float* arho, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* Reads the device error word (SPH_ERR_* bits) of a workspace.  Synchronises
+ * the device.  Returns a negative sph_status on failure. */
+int32_t sph_read_error(const void* ws);
+
+/* Enqueues clearing of the workspace's error word (a fill kernel). */
+sph_status sph_clear_error(void* ws, void* stream);
+
+/* Static description of a status code. */
+const char* sph_strerror(sph_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

@@ -1,0 +1,172 @@
+// The C ABI of libsph (declared in include/sph.h): argument checks, workspace
+// carving and kernel launches.  No call allocates device memory.
+#include <math.h>
+#include <string.h>
+
+#include "sph_kernels.h"
+
+namespace sph {
+
+KParams make_kparams(const sph_params& p) {
+  KParams k{};
+  k.dim = p.dim;
+  k.cell_div = p.cell_div;
+  k.ddt = p.ddt;
+  k.ncx = p.ncell[0];
+  k.ncy = p.ncell[1];
+  k.ncz = p.ncell[2];
+  k.ncell_total = (uint32_t)((uint64_t)p.ncell[0] * p.ncell[1] * p.ncell[2]);
+  k.ox = p.origin[0];
+  k.oy = p.origin[1];
+  k.oz = p.origin[2];
+  k.cs = p.cell_size;
+  k.inv_cs = p.inv_cell_size;
+  k.h = p.h;
+  k.rho0 = p.rho0;
+  k.gamma = p.gamma;
+  k.c0 = p.c0;
+  k.b_tait = p.c0 * p.c0 * p.rho0 / p.gamma;
+  k.cfl = p.cfl;
+  k.dt_floor = p.dt_floor;
+  k.mass_f = p.mass_fluid;
+  k.mass_b = p.mass_bound;
+  k.gx = p.gravity[0];
+  k.gy = p.gravity[1];
+  k.gz = p.gravity[2];
+  k.motion_amp = p.motion_amp;
+  k.motion_omega = p.motion_omega;
+  k.support2 = (2.0 * p.h) * (2.0 * p.h);
+  // Wendland C2 (Eq. 11): alpha_D = 7/(4 pi h^2) in 2-D, 21/(16 pi h^3) in 3-D;
+  // grad_a W_ab = -5 alpha_D (1 - q/2)^3 / h^2 * r_ab.
+  const double alpha_d = p.dim == 2 ? 7.0 / (4.0 * M_PI * p.h * p.h)
+                                    : 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
+  k.h_f = (float)p.h;
+  k.inv_h_f = (float)(1.0 / p.h);
+  k.support2_f = (float)k.support2;
+  k.kfab_f = (float)(-5.0 * alpha_d / (p.h * p.h));
+  k.eta2_f = (float)p.eta2;
+  k.visc_coef_f = (float)(p.alpha * p.c0);
+  k.ddt_coef_f = p.ddt ? (float)(2.0 * p.delta * p.h * p.c0) : 0.f;
+  k.mass_f_f = (float)p.mass_fluid;
+  k.mass_b_f = (float)p.mass_bound;
+  k.cs_f = (float)p.cell_size;
+  k.gx_f = (float)p.gravity[0];
+  k.gy_f = (float)p.gravity[1];
+  k.gz_f = (float)p.gravity[2];
+  return k;
+}
+
+static bool params_ok(const sph_params* p) {
+  if (!p) return false;
+  if (p->dim != 2 && p->dim != 3) return false;
+  if (p->cell_div != 1 && p->cell_div != 2) return false;
+  for (int k = 0; k < 3; ++k)
+    if (p->ncell[k] < 1) return false;
+  if (p->dim == 2 && p->ncell[2] != 1) return false;
+  const uint64_t total = (uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
+  if (total + 1 >= 0xffffffffull) return false;
+  if (!(p->h > 0) || !(p->rho0 > 0) || !(p->gamma > 0) || !(p->c0 > 0)) return false;
+  if (!(p->cell_size > 0) || !(p->inv_cell_size > 0)) return false;
+  // the +-cell_div cell stencil must cover the 2h support
+  if (p->cell_size * p->cell_div < 2.0 * p->h * (1.0 - 1e-12)) return false;
+  if (!(p->cfl > 0) || !(p->eta2 >= 0) || !(p->mass_fluid > 0) || !(p->mass_bound > 0))
+    return false;
+  return true;
+}
+
+static bool n_ok(int64_t n) { return n >= 0 && n < (int64_t)0xfffffff0ll; }
+
+static bool state_ok(const sph_state* s, bool need_type) {
+  return s && s->pos && s->vel && s->rho && (!need_type || s->type);
+}
+
+static sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" {
+
+size_t sph_workspace_bytes(const sph_params* p, int64_t n) {
+  (void)p;
+  if (!n_ok(n)) return 0;
+  return ws_layout(n).total;
+}
+
+sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in, sph_state* out,
+                         const sph_state* carry_in, sph_state* carry_out, uint32_t* key,
+                         uint32_t* perm, uint32_t* cell_start, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !cell_start || !ws) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(in, true) || !state_ok(out, true) || !key || !perm)) return SPH_E_ARG;
+  if (n > 0 && in->pos == out->pos) return SPH_E_ARG;
+  if ((carry_in == nullptr) != (carry_out == nullptr)) return SPH_E_ARG;
+  if (carry_in && n > 0 && (!state_ok(carry_in, false) || !state_ok(carry_out, false)))
+    return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  const KParams kp = make_kparams(*p);
+  sph_state i0 = n > 0 ? *in : sph_state{}, o0 = n > 0 ? *out : sph_state{};
+  return hip_status(launch_bin_cells(kp, n, i0, o0, carry_in, carry_out, key, perm, cell_start,
+                                     ws, (hipStream_t)stream));
+}
+
+sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, const uint32_t* key,
+                        const uint32_t* cell_start, float* ace, float* arho, float* visc,
+                        uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !cell_start || !ws) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
+  if (flags & ~(uint32_t)SPH_DIAG_COUNT_F64) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  const KParams kp = make_kparams(*p);
+  sph_state s0 = n > 0 ? *s : sph_state{};
+  return hip_status(launch_interact(kp, n, s0, key, cell_start, ace, arho, visc, nbr_count, flags,
+                                    ws, (hipStream_t)stream));
+}
+
+sph_status sph_reduce_dt(const sph_params* p, int64_t n, double* dt, uint64_t* interactions,
+                         float* maxima, void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !dt || !ws) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  return hip_status(
+      launch_reduce_dt(make_kparams(*p), n, dt, interactions, maxima, ws, (hipStream_t)stream));
+}
+
+sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase, const double* dt,
+                               double* t, sph_state* saved, sph_state* s, const float* ace,
+                               const float* arho, void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !dt || !t || !ws) return SPH_E_ARG;
+  if (phase != 0 && phase != 1) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !state_ok(saved, false) || !ace || !arho))
+    return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state sv = n > 0 ? *saved : sph_state{}, st = n > 0 ? *s : sph_state{};
+  return hip_status(launch_symplectic(make_kparams(*p), n, phase, dt, t, sv, st, ace, arho, ws,
+                                      (hipStream_t)stream));
+}
+
+int32_t sph_read_error(const void* ws) {
+  if (!ws) return SPH_E_ARG;
+  uint32_t v = 0;
+  if (hipDeviceSynchronize() != hipSuccess) return SPH_E_HIP;
+  if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
+  return (int32_t)(v & 0x7fffffffu);
+}
+
+sph_status sph_clear_error(void* ws, void* stream) {
+  if (!ws) return SPH_E_ARG;
+  return hip_status(launch_clear_error(ws, (hipStream_t)stream));
+}
+
+const char* sph_strerror(sph_status s) {
+  switch (s) {
+    case SPH_OK: return "ok";
+    case SPH_E_ARG: return "invalid argument";
+    case SPH_E_WORKSPACE: return "workspace too small";
+    case SPH_E_HIP: return "HIP runtime or launch error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+// Neighbour list (Section 5.1 of the DualSPHysics v5.0 paper): cell keys,
+// an in-house stable LSD radix sort in LDS, cell ranges and the reorder of
+// the particle state into sorted structure-of-arrays.
+#include "sph_kernels.h"
+
+namespace sph {
+
+// -------------------------------------------------------------- cell keys --
+// Cell index per axis = floor((x - origin) * inv_cs): one FP64 subtraction and
+// one FP64 multiplication (no contraction is possible), x fastest.  Outside
+// the grid, and for particles excluded earlier, the key is ncell_total, so
+// they sort last and lie in no cell range.
+__global__ void k_cell_keys(KParams kp, int64_t n, const double* __restrict__ pos,
+                            const uint8_t* __restrict__ type, uint32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (is_excluded(type[i])) {
+    key[i] = kp.ncell_total;
+    return;
+  }
+  const double org[3] = {kp.ox, kp.oy, kp.oz};
+  const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
+  int c[3] = {0, 0, 0};
+  bool inside = true;
+  for (int k = 0; k < kp.dim; ++k) {
+    const double d = __dsub_rn(pos[k * n + i], org[k]);
+    const double s = __dmul_rn(d, kp.inv_cs);
+    const double f = floor(s);
+    if (!(f >= 0.0) || !(f < (double)nc[k])) inside = false;
+    else c[k] = (int)f;
+  }
+  key[i] = inside ? (uint32_t)(c[0] + nc[0] * (c[1] + nc[1] * c[2])) : kp.ncell_total;
+}
+
+// ------------------------------------------------------- exclusive scans --
+// Exclusive prefix sum of one value per thread over a 256-thread block.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, all = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wave) base += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return base + x - v;
+}
+
+// Tile-local exclusive scan of kScanTile values; the tile total goes to part[].
+__global__ void k_scan_tiles(uint32_t* __restrict__ data, int64_t len,
+                             uint32_t* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  uint32_t v[8], s = 0;
+  for (int k = 0; k < 8; ++k) {
+    v[k] = (base + k < len) ? data[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, &total);
+  for (int k = 0; k < 8; ++k) {
+    if (base + k < len) data[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile totals in one block (loops over chunks).
+__global__ void k_scan_parts(uint32_t* __restrict__ part, int64_t parts) {
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c = 0; c < parts; c += kBlock) {
+    const int64_t i = c + threadIdx.x;
+    const uint32_t v = i < parts ? part[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, &total);
+    const uint32_t cin = carry;
+    if (i < parts) part[i] = cin + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = cin + total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ data, int64_t len,
+                           const uint32_t* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 8;
+  const uint32_t add = part[blockIdx.x];
+  for (int k = 0; k < 8; ++k)
+    if (base + k < len) data[base + k] += add;
+}
+
+void exclusive_scan(uint32_t* data, int64_t len, uint32_t* part, hipStream_t st) {
+  const int64_t parts = (len + kScanTile - 1) / kScanTile;
+  if (parts == 0) return;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)parts), dim3(kBlock), 0, st, data, len, part);
+  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, part, parts);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)parts), dim3(kBlock), 0, st, data, len, part);
+}
+
+// ------------------------------------------------------------ radix sort --
+// One LSD pass over digit (key >> shift) & (2^bits - 1), bits <= 8.  Tiles of
+// kSortTile keys; inside a tile the keys are visited in rounds of 256, round
+// by round, wave by wave, lane by lane, which is the input order -- so the
+// ranks below are stable.
+__global__ void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                             int bits, uint32_t* __restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t h[256];
+  const int bins = 1 << bits;
+  for (int b = threadIdx.x; b < bins; b += kBlock) h[b] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < bins; b += kBlock) hist[(int64_t)b * nblk + blockIdx.x] = h[b];
+}
+
+__global__ void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                int64_t n, int shift, int bits,
+                                const uint32_t* __restrict__ offs, int64_t nblk) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wbase[kBlock / 64][256];
+  const int bins = 1 << bits;
+  const uint32_t mask = (uint32_t)bins - 1u;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int b = threadIdx.x; b < bins; b += kBlock) run[b] = offs[(int64_t)b * nblk + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t d = (key >> shift) & mask;
+    // lanes of this wave holding the same digit
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(valid && bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    for (int b = threadIdx.x; b < bins; b += kBlock)
+      for (int w = 0; w < kBlock / 64; ++w) wbase[w][b] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wbase[wave][d] = cnt;
+    __syncthreads();
+    for (int b = threadIdx.x; b < bins; b += kBlock) {
+      uint32_t s = run[b];
+      for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t c = wbase[w][b];
+        wbase[w][b] = s;
+        s += c;
+      }
+      run[b] = s;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t dst = wbase[wave][d] + rank;
+      kout[dst] = key;
+      vout[dst] = vin ? vin[i] : (uint32_t)i;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ cell ranges --
+// cell_start[c] = first sorted index whose key is >= c (lower bound), for
+// c = 0..ncell_total.
+__global__ void k_cell_start(const uint32_t* __restrict__ key, int64_t n, uint32_t ncell_total,
+                             uint32_t* __restrict__ start) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > (int64_t)ncell_total) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  start[c] = (uint32_t)lo;
+}
+
+// --------------------------------------------------------------- reorder --
+// Gathers the state into sorted order and writes, per sorted particle, the
+// two float4 the interaction reads (the "view"):
+//   pr = {cell-relative position (dim components), 0, +rho fluid / -rho wall}
+//   vp = {velocity (dim components), 0, P}
+// The cell-relative FP32 offset is x - (origin + c cs) evaluated in FP64 (the
+// precision scheme of Section 5.1: FP64 positions, FP32 distances inside the
+// cell).  P is the Tait pressure of Eq. 28, per particle in FP64; for
+// gamma = 7 as the expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the
+// small pressures of a nearly incompressible fluid free of cancellation.
+__global__ void k_reorder(KParams kp, int64_t n, const uint32_t* __restrict__ perm,
+                          const uint32_t* __restrict__ key, sph_state in, sph_state out,
+                          sph_state cin, sph_state cout, int carry, float4* __restrict__ pr,
+                          float4* __restrict__ vp, uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t src = perm[i];
+  const uint32_t k = key[i];
+  double x[3] = {0.0, 0.0, 0.0};
+  float v[3] = {0.f, 0.f, 0.f};
+  for (int d = 0; d < kp.dim; ++d) {
+    x[d] = in.pos[d * n + src];
+    v[d] = in.vel[d * n + src];
+    out.pos[d * n + i] = x[d];
+    out.vel[d * n + i] = v[d];
+  }
+  const float rho = in.rho[src];
+  out.rho[i] = rho;
+  uint8_t t = in.type[src];
+  if (k == kp.ncell_total && !(t & SPH_EXCLUDED)) {
+    t |= SPH_EXCLUDED;
+    set_error(err, SPH_ERR_EXCLUDED);
+  }
+  out.type[i] = t;
+  if (in.id && out.id) out.id[i] = in.id[src];
+  if (carry) {
+    for (int d = 0; d < kp.dim; ++d) {
+      cout.pos[d * n + i] = cin.pos[d * n + src];
+      cout.vel[d * n + i] = cin.vel[d * n + src];
+    }
+    cout.rho[i] = cin.rho[src];
+  }
+  if (t & SPH_EXCLUDED) {
+    pr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const int c0 = (int)(k % (uint32_t)kp.ncx);
+  const uint32_t rest = k / (uint32_t)kp.ncx;
+  const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
+  const double org[3] = {kp.ox, kp.oy, kp.oz};
+  float o[3] = {0.f, 0.f, 0.f};
+  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)c[d] * kp.cs));
+  const double r = (double)rho;
+  const double u = r / kp.rho0 - 1.0;
+  double pw;
+  if (kp.gamma == 7.0)
+    pw = u * (7.0 + u * (21.0 + u * (35.0 + u * (35.0 + u * (21.0 + u * (7.0 + u))))));
+  else
+    pw = pow(r / kp.rho0, kp.gamma) - 1.0;
+  pr[i] = make_float4(o[0], o[1], o[2], is_fluid(t) ? rho : -rho);
+  vp[i] = make_float4(v[0], v[1], v[2], (float)(kp.b_tait * pw));
+}
+
+// ------------------------------------------------------------------ host --
+int key_bits(uint32_t ncell_total) {
+  int bits = 1;
+  while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)ncell_total) ++bits;
+  return bits;  // enough bits for keys 0..ncell_total
+}
+
+hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, sph_state& out,
+                            const sph_state* cin, sph_state* cout, uint32_t* key,
+                            uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n);
+  uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
+  const unsigned gridn = (unsigned)((n + kBlock - 1) / kBlock);
+  if (n > 0) {
+    uint32_t* kA = ws_ptr<uint32_t>(ws, L.keyA);
+    uint32_t* vA = ws_ptr<uint32_t>(ws, L.valA);
+    uint32_t* kB = ws_ptr<uint32_t>(ws, L.keyB);
+    uint32_t* vB = ws_ptr<uint32_t>(ws, L.valB);
+    uint32_t* hist = ws_ptr<uint32_t>(ws, L.hist);
+    uint32_t* part = ws_ptr<uint32_t>(ws, L.scan_part);
+    hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type, kA);
+    const int total_bits = key_bits(kp.ncell_total);
+    const int passes = (total_bits + 7) / 8;
+    const int per = (total_bits + passes - 1) / passes;
+    if (per < 1 || per > 8 || (passes - 1) * per >= total_bits) return hipErrorInvalidValue;
+    const uint32_t* ksrc = kA;
+    const uint32_t* vsrc = nullptr;  // identity on the first pass
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * per;
+      const int bits = (shift + per <= total_bits) ? per : (total_bits - shift);
+      const bool last = (p == passes - 1);
+      uint32_t* kdst = last ? key : ((p & 1) ? kA : kB);
+      uint32_t* vdst = last ? perm : ((p & 1) ? vA : vB);
+      const int64_t nblk = L.nblk_sort;
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, n,
+                         shift, bits, hist, nblk);
+      exclusive_scan(hist, (int64_t)(1 << bits) * nblk, part, st);
+      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc,
+                         vsrc, kdst, vdst, n, shift, bits, hist, nblk);
+      ksrc = kdst;
+      vsrc = vdst;
+    }
+  }
+  const int64_t nc1 = (int64_t)kp.ncell_total + 1;
+  hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((nc1 + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, st, key, n, kp.ncell_total, cell_start);
+  if (n > 0) {
+    sph_state ci{}, co{};
+    const int carry = (cin && cout) ? 1 : 0;
+    if (carry) { ci = *cin; co = *cout; }
+    hipLaunchKernelGGL(k_reorder, dim3(gridn), dim3(kBlock), 0, st, kp, n, perm, key, in, out,
+                       ci, co, carry, ws_ptr<float4>(ws, L.view_pr), ws_ptr<float4>(ws, L.view_vp),
+                       err);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sph

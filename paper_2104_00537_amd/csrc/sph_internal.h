@@ -1,0 +1,108 @@
+// Internal definitions shared by the gfx950 kernels of libsph: the launch
+// parameter block, the workspace layout and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kSortItems = 8;      // keys per thread per radix tile
+constexpr int kSortTile = kBlock * kSortItems;
+constexpr int kScanTile = kBlock * 8;
+
+// Per-launch constants derived once on the host from sph_params.
+struct KParams {
+  int dim, cell_div, ddt, pad;
+  int ncx, ncy, ncz;
+  uint32_t ncell_total;          // also the key of particles outside the grid
+  double ox, oy, oz;             // grid origin
+  double cs, inv_cs;
+  double h, rho0, gamma, c0, b_tait, cfl, dt_floor;
+  double mass_f, mass_b;
+  double gx, gy, gz;
+  double motion_amp, motion_omega;
+  double support2;               // (2h)^2 in FP64, for the diagnostic count
+  // FP32 copies for the interaction kernel
+  float h_f, inv_h_f, support2_f, kfab_f;    // kfab = -5 alpha_D / h^2
+  float eta2_f, visc_coef_f, ddt_coef_f;     // alpha*c0 ; 2*delta*h*c0
+  float mass_f_f, mass_b_f, cs_f;
+  float gx_f, gy_f, gz_f;
+};
+
+// Per-block partial results of the interaction (reduced by sph_reduce_dt).
+struct BlockRed {
+  float fmax;          // max |dv/dt| over fluid targets of the block
+  float vmax;          // max visc over fluid targets of the block
+  uint32_t count;      // interactions evaluated by the block
+  uint32_t count_wall; // ... of which with a wall target (continuity only)
+  uint32_t nfluid;     // fluid targets in the block
+  uint32_t pad;
+};
+
+// Workspace layout (offsets in bytes, each region 256-aligned).
+struct WsLayout {
+  size_t err;        // uint32 error word (offset 0)
+  size_t keyA, valA, keyB, valB;   // radix sort ping-pong buffers, n each
+  size_t hist;       // uint32 [bins * nblk_sort] digit counts / offsets
+  size_t scan_part;  // uint32 partial sums of the offset scan
+  size_t view_pr;    // float4 [n]: cell-relative position, signed density
+  size_t view_vp;    // float4 [n]: velocity, pressure
+  size_t red;        // BlockRed [nblk_interact]
+  size_t total;
+  int64_t nblk_sort, nblk_interact, hist_len, scan_parts;
+};
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+inline WsLayout ws_layout(int64_t n) {
+  WsLayout L{};
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  L.nblk_sort = (n + kSortTile - 1) / kSortTile;
+  if (L.nblk_sort < 1) L.nblk_sort = 1;
+  L.nblk_interact = (n + kBlock - 1) / kBlock;
+  if (L.nblk_interact < 1) L.nblk_interact = 1;
+  L.hist_len = 256 * L.nblk_sort;
+  L.scan_parts = (L.hist_len + kScanTile - 1) / kScanTile;
+  size_t off = 0;
+  L.err = off; off = align_up(off + 256);
+  L.keyA = off; off = align_up(off + 4 * nn);
+  L.valA = off; off = align_up(off + 4 * nn);
+  L.keyB = off; off = align_up(off + 4 * nn);
+  L.valB = off; off = align_up(off + 4 * nn);
+  L.hist = off; off = align_up(off + 4 * (size_t)L.hist_len);
+  L.scan_part = off; off = align_up(off + 4 * (size_t)L.scan_parts + 4);
+  L.view_pr = off; off = align_up(off + 16 * nn);
+  L.view_vp = off; off = align_up(off + 16 * nn);
+  L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+inline T* ws_ptr(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---------------------------------------------------------------- device ----
+__device__ inline bool is_excluded(uint8_t t) { return (t & SPH_EXCLUDED) != 0; }
+__device__ inline bool is_fluid(uint8_t t) { return (t & 0x7f) == SPH_FLUID; }
+
+__device__ inline void set_error(uint32_t* err, uint32_t bits) {
+  atomicOr(err, bits);
+}
+
+// Wave-wide reductions over the 64 lanes of a wavefront.
+__device__ inline float wave_max(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline uint32_t wave_sum(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace sph

@@ -1,0 +1,172 @@
+// System update (Section 5.1): the variable time step of Eq. 35 and the
+// symplectic position-Verlet update of Eq. 33-34, with the imposed motion of
+// moving walls (Eq. 37).
+#include "sph_kernels.h"
+
+namespace sph {
+
+// Eq. 35 from the per-block partials of the last interaction pass; one block.
+__global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red, int64_t nblk,
+                            double* __restrict__ dt, uint64_t* __restrict__ inter,
+                            float* __restrict__ maxima, uint32_t* __restrict__ err) {
+  __shared__ float sf[kBlock / 64], sv[kBlock / 64];
+  __shared__ unsigned long long sc[kBlock / 64], sw[kBlock / 64], sn[kBlock / 64];
+  float fmax = 0.f, vmax = 0.f;
+  unsigned long long cnt = 0, cntw = 0, nfl = 0;
+  for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
+    const BlockRed r = red[b];
+    fmax = fmaxf(fmax, r.fmax);
+    vmax = fmaxf(vmax, r.vmax);
+    cnt += r.count;
+    cntw += r.count_wall;
+    nfl += r.nfluid;
+  }
+  fmax = wave_max(fmax);
+  vmax = wave_max(vmax);
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_xor(cnt, off, 64);
+    cntw += __shfl_xor(cntw, off, 64);
+    nfl += __shfl_xor(nfl, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { sf[wave] = fmax; sv[wave] = vmax; sc[wave] = cnt; sw[wave] = cntw; sn[wave] = nfl; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < kBlock / 64; ++w) {
+    sf[0] = fmaxf(sf[0], sf[w]);
+    sv[0] = fmaxf(sv[0], sv[w]);
+    sc[0] += sc[w];
+    sw[0] += sw[w];
+    sn[0] += sn[w];
+  }
+  const double f = (double)sf[0], v = (double)sv[0];
+  double d = INFINITY;
+  if (sn[0] > 0) {
+    const double dtf = f > 0.0 ? sqrt(kp.h / f) : INFINITY;
+    const double dtcv = kp.h / (kp.c0 + v);
+    d = kp.cfl * (dtf < dtcv ? dtf : dtcv);
+  }
+  *dt = d;
+  if (!(d >= kp.dt_floor) || !isfinite(d)) set_error(err, SPH_ERR_DT_FLOOR);
+  if (inter) {
+    inter[0] += (uint64_t)sc[0];
+    inter[1] += (uint64_t)sw[0];
+  }
+  if (maxima) { maxima[0] = sf[0]; maxima[1] = sv[0]; }
+}
+
+// Imposed wall motion along x: D(t) = (A/w^2)(1 - cos wt), v(t) = (A/w) sin wt.
+__device__ inline double motion_disp(const KParams& kp, double t) {
+  if (kp.motion_omega == 0.0) return 0.0;
+  const double w = kp.motion_omega;
+  return kp.motion_amp / (w * w) * (1.0 - cos(w * t));
+}
+__device__ inline double motion_vel(const KParams& kp, double t) {
+  if (kp.motion_omega == 0.0) return 0.0;
+  return kp.motion_amp / kp.motion_omega * sin(kp.motion_omega * t);
+}
+
+// phase 0: predictor (Eq. 33 lines 1-2, Eq. 34 line 1), saving state n;
+// phase 1: corrector (Eq. 33 lines 3-4, Eq. 34 line 2) from the saved state.
+template <int PHASE>
+__global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ dtp,
+                             const double* __restrict__ tp, sph_state saved, sph_state s,
+                             const float* __restrict__ ace, const float* __restrict__ arho,
+                             uint32_t* __restrict__ err) {
+  __shared__ double shm[3];
+  if (threadIdx.x == 0) {
+    const double dt = *dtp, t = *tp;
+    const double t1 = PHASE == 0 ? t + 0.5 * dt : t + dt;
+    shm[0] = dt;
+    shm[1] = motion_disp(kp, t1) - motion_disp(kp, t);
+    shm[2] = motion_vel(kp, t1);
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dt = shm[0];
+  const uint8_t t = s.type[i];
+  if (PHASE == 0) {
+    for (int d = 0; d < kp.dim; ++d) {
+      saved.pos[d * n + i] = s.pos[d * n + i];
+      saved.vel[d * n + i] = s.vel[d * n + i];
+    }
+    saved.rho[i] = s.rho[i];
+  }
+  if (is_excluded(t)) return;
+  bool bad = false;
+  if (is_fluid(t)) {
+    for (int d = 0; d < kp.dim; ++d) {
+      const double a = (double)ace[d * n + i];
+      if (PHASE == 0) {
+        const double v = (double)s.vel[d * n + i];
+        s.pos[d * n + i] = s.pos[d * n + i] + 0.5 * dt * v;
+        const float v1 = (float)(v + 0.5 * dt * a);
+        s.vel[d * n + i] = v1;
+        bad |= !isfinite(v1);
+      } else {
+        const double vn = (double)saved.vel[d * n + i];
+        const double v1 = vn + dt * a;
+        s.pos[d * n + i] = saved.pos[d * n + i] + dt * 0.5 * (v1 + vn);
+        const float v1f = (float)v1;
+        s.vel[d * n + i] = v1f;
+        bad |= !isfinite(v1f);
+      }
+    }
+  } else if ((t & 0x7f) == SPH_BOUND_MOVING) {
+    s.pos[i] = saved.pos[i] + shm[1];
+    s.vel[i] = (float)shm[2];
+  }
+  double r;
+  if (PHASE == 0) {
+    r = (double)s.rho[i] + 0.5 * dt * (double)arho[i];
+  } else {
+    const double eps = -((double)arho[i] / (double)s.rho[i]) * dt;
+    r = (double)saved.rho[i] * (2.0 - eps) / (2.0 + eps);
+  }
+  const float rf = (float)r;
+  s.rho[i] = rf;
+  if (bad || !(rf > 0.f) || !isfinite(rf)) set_error(err, SPH_ERR_NONFINITE);
+}
+
+__global__ void k_advance_time(const double* __restrict__ dt, double* __restrict__ t) {
+  if (threadIdx.x == 0) *t = *t + *dt;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t len, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = v;
+}
+
+hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* interactions,
+                            float* maxima, void* ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n);
+  hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(kBlock), 0, st, kp, ws_ptr<BlockRed>(ws, L.red),
+                     L.nblk_interact, dt, interactions, maxima, ws_ptr<uint32_t>(ws, L.err));
+  return hipGetLastError();
+}
+
+hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const double* dt, double* t,
+                             sph_state& saved, sph_state& s, const float* ace, const float* arho,
+                             void* ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n);
+  uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  if (n > 0) {
+    if (phase == 0)
+      hipLaunchKernelGGL(k_symplectic<0>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
+                         ace, arho, err);
+    else
+      hipLaunchKernelGGL(k_symplectic<1>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
+                         ace, arho, err);
+  }
+  if (phase == 1) hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_error(void* ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws_ptr<uint32_t>(ws, 0), (int64_t)1, 0u);
+  return hipGetLastError();
+}
+
+}  // namespace sph

@@ -1,0 +1,133 @@
+"""One-case step loop over the libsph C ABI (NL -> PI -> SU, Section 5.1).
+
+A symplectic step (Section 2.5.2) is
+    bin(n) -> interact(n) -> reduce_dt -> predictor -> bin(n+1/2, carrying the
+    saved state n) -> interact(n+1/2) -> corrector (t += dt)
+with dt and t kept in device memory, so a step enqueues no host work and can
+be captured once in a HIP graph and replayed.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import sph as S
+
+
+class Simulation:
+    def __init__(self, case, device="cuda", cell_div: Optional[int] = None):
+        cp = case.params
+        if cell_div is not None and cell_div != cp.cell_div:
+            raise ValueError("cell_div is fixed by the case's grid")
+        self.case = case
+        self.cp = cp
+        self.params = S.make_params(cp)
+        self.dim = int(cp.dim)
+        self.n = n = case.n
+        dev = torch.device(device)
+        self.device = dev
+        self.states = [S.DeviceState.from_case(case, dev),
+                       S.DeviceState.empty(self.dim, n, dev)]
+        self.saved = [S.DeviceState.empty(self.dim, n, dev, with_type=False, with_id=False)
+                      for _ in range(2)]
+        self.key = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.cell_start = torch.empty(cp.ncell_total() + 1, dtype=torch.int32, device=dev)
+        self.ace = torch.zeros((self.dim, max(n, 1)), dtype=torch.float32, device=dev)
+        self.arho = torch.zeros(max(n, 1), dtype=torch.float32, device=dev)
+        self.ws = torch.zeros(S.sph_workspace_bytes(self.params, n), dtype=torch.uint8, device=dev)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.dt_half = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.interactions = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.steps_done = 0
+        self.graph = None
+
+    # ------------------------------------------------------------------ step
+    @property
+    def state(self) -> S.DeviceState:
+        return self.states[0]
+
+    def step(self, stream=None, timing: Optional[dict] = None):
+        """One symplectic step.  With `timing` (a dict), HIP events are
+        recorded on the stream around each call, appended to
+        timing[name] as (start, end) pairs."""
+        P, n = self.params, self.n
+        a, b = self.states
+        s0, s1 = self.saved
+
+        def call(name, fn, *args, **kw):
+            if timing is None:
+                fn(*args, **kw)
+                return
+            st = stream if stream is not None else torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn(*args, **kw)
+            e1.record(st)
+            timing.setdefault(name, []).append((e0, e1))
+
+        call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
+             self.ws, stream=stream)
+        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
+             self.ws, stream=stream)
+        call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
+             interactions=self.interactions, stream=stream)
+        call("symplectic", S.sph_symplectic_step, P, n, 0, self.dt, self.t, s0, b, self.ace,
+             self.arho, self.ws, stream=stream)
+        call("bin_cells", S.sph_bin_cells, P, n, b, a, self.key, self.perm, self.cell_start,
+             self.ws, carry_in=s0, carry_out=s1, stream=stream)
+        call("interact", S.sph_interact, P, n, a, self.key, self.cell_start, self.ace, self.arho,
+             self.ws, stream=stream)
+        # pair count of the second pass (its dt is not used: Eq. 35 is taken
+        # at state n for both half steps)
+        call("reduce_dt", S.sph_reduce_dt, P, n, self.dt_half, self.ws,
+             interactions=self.interactions, stream=stream)
+        call("symplectic", S.sph_symplectic_step, P, n, 1, self.dt, self.t, s1, a, self.ace,
+             self.arho, self.ws, stream=stream)
+        self.steps_done += 1
+
+    def run(self, nsteps: int):
+        for _ in range(int(nsteps)):
+            self.step()
+
+    # ----------------------------------------------------------- HIP graphs
+    def capture(self, steps_per_graph: int = 1):
+        """Captures `steps_per_graph` steps in one HIP graph (warm up first)."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(steps_per_graph):
+                self.step()
+        self.steps_done -= steps_per_graph  # capture does not execute
+        self.graph = (g, steps_per_graph)
+        return g
+
+    def replay(self, times: int = 1):
+        g, k = self.graph
+        for _ in range(times):
+            g.replay()
+        self.steps_done += k * times
+
+    # ------------------------------------------------------------- readback
+    def error(self) -> int:
+        return S.sph_read_error(self.ws)
+
+    def time(self) -> float:
+        return float(self.t.item())
+
+    def host_state(self) -> dict:
+        """State in the case's original particle order (numpy, FP64/FP32)."""
+        st = self.state
+        ids = st.id.cpu().numpy().view(np.uint32).astype(np.int64)
+        inv = np.empty_like(ids)
+        inv[ids] = np.arange(ids.shape[0])
+        return dict(pos=st.pos.cpu().numpy()[:, inv], vel=st.vel.cpu().numpy()[:, inv],
+                    rho=st.rho.cpu().numpy()[inv], type=st.type.cpu().numpy()[inv],
+                    t=self.time())
+
+    def interaction_count(self) -> int:
+        return int(self.interactions[0].item())

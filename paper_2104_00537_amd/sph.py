@@ -1,0 +1,199 @@
+"""Thin ctypes binding of libsph (include/sph.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libsph.so``.  PyTorch supplies device memory and streams.  Importing this
+module fails loudly if the library has not been built (there is no CPU
+fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsph.so")
+
+SPH_OK, SPH_E_ARG, SPH_E_WORKSPACE, SPH_E_HIP = 0, -1, -2, -3
+SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_EXCLUDED = 0, 1, 2, 0x80
+SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR = 1, 2, 4
+SPH_DIAG_COUNT_F64 = 1
+
+EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
+           "sph_symplectic_step", "sph_read_error", "sph_clear_error", "sph_strerror")
+
+
+class SphParams(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("cell_div", C.c_int32), ("ddt", C.c_int32),
+        ("ncell", C.c_int32 * 3), ("origin", C.c_double * 3),
+        ("cell_size", C.c_double), ("inv_cell_size", C.c_double),
+        ("h", C.c_double), ("rho0", C.c_double), ("gamma", C.c_double),
+        ("c0", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
+        ("eta2", C.c_double), ("cfl", C.c_double), ("mass_fluid", C.c_double),
+        ("mass_bound", C.c_double), ("gravity", C.c_double * 3),
+        ("motion_amp", C.c_double), ("motion_omega", C.c_double),
+        ("dt_floor", C.c_double),
+    ]
+
+
+class SphState(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("rho", C.c_void_p),
+                ("type", C.c_void_p), ("id", C.c_void_p)]
+
+
+class SphError(RuntimeError):
+    pass
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libsph.so not found at {LIB_PATH}: build it with "
+            "`python -m paper_2104_00537_amd.build` (there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, VP = C.POINTER, C.c_void_p
+    L.sph_workspace_bytes.restype = C.c_size_t
+    L.sph_workspace_bytes.argtypes = [P(SphParams), C.c_int64]
+    L.sph_bin_cells.restype = C.c_int32
+    L.sph_bin_cells.argtypes = [P(SphParams), C.c_int64, P(SphState), P(SphState),
+                                P(SphState), P(SphState), VP, VP, VP, VP, C.c_size_t, VP]
+    L.sph_interact.restype = C.c_int32
+    L.sph_interact.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP, VP,
+                               C.c_uint32, VP, C.c_size_t, VP]
+    L.sph_reduce_dt.restype = C.c_int32
+    L.sph_reduce_dt.argtypes = [P(SphParams), C.c_int64, VP, VP, VP, VP, C.c_size_t, VP]
+    L.sph_symplectic_step.restype = C.c_int32
+    L.sph_symplectic_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP,
+                                      P(SphState), P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_read_error.restype = C.c_int32
+    L.sph_read_error.argtypes = [VP]
+    L.sph_clear_error.restype = C.c_int32
+    L.sph_clear_error.argtypes = [VP, VP]
+    L.sph_strerror.restype = C.c_char_p
+    L.sph_strerror.argtypes = [C.c_int32]
+    return L
+
+
+lib = _load()
+
+
+def _check(st: int, what: str):
+    if st != SPH_OK:
+        raise SphError(f"{what}: {lib.sph_strerror(st).decode()} ({st})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> Optional[C.c_void_p]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_params(cp) -> SphParams:
+    """SphParams from a ``cases.CaseParams``."""
+    p = SphParams()
+    p.dim, p.cell_div, p.ddt = int(cp.dim), int(cp.cell_div), int(cp.ddt)
+    for k in range(3):
+        p.ncell[k] = int(cp.ncell[k])
+        p.origin[k] = float(cp.origin[k])
+        p.gravity[k] = float(cp.gravity[k])
+    for name in ("cell_size", "inv_cell_size", "h", "rho0", "gamma", "c0", "alpha", "delta",
+                 "eta2", "cfl", "mass_fluid", "mass_bound", "motion_amp", "motion_omega",
+                 "dt_floor"):
+        setattr(p, name, float(getattr(cp, name)))
+    return p
+
+
+@dataclass
+class DeviceState:
+    """SoA particle state in device memory (torch tensors)."""
+    pos: torch.Tensor            # (dim, n) float64
+    vel: torch.Tensor            # (dim, n) float32
+    rho: torch.Tensor            # (n,) float32
+    type: Optional[torch.Tensor] = None  # (n,) uint8
+    id: Optional[torch.Tensor] = None    # (n,) int32 (bit pattern of uint32)
+
+    @staticmethod
+    def empty(dim: int, n: int, device, with_type=True, with_id=True) -> "DeviceState":
+        return DeviceState(
+            pos=torch.empty((dim, n), dtype=torch.float64, device=device),
+            vel=torch.empty((dim, n), dtype=torch.float32, device=device),
+            rho=torch.empty((n,), dtype=torch.float32, device=device),
+            type=torch.empty((n,), dtype=torch.uint8, device=device) if with_type else None,
+            id=torch.empty((n,), dtype=torch.int32, device=device) if with_id else None)
+
+    @staticmethod
+    def from_case(case, device) -> "DeviceState":
+        n = case.n
+        return DeviceState(
+            pos=torch.from_numpy(case.pos).to(device),
+            vel=torch.from_numpy(case.vel).to(device),
+            rho=torch.from_numpy(case.rho).to(device),
+            type=torch.from_numpy(case.type).to(device),
+            id=torch.arange(n, dtype=torch.int32, device=device))
+
+    def c(self) -> SphState:
+        return SphState(self.pos.data_ptr(), self.vel.data_ptr(), self.rho.data_ptr(),
+                        None if self.type is None else self.type.data_ptr(),
+                        None if self.id is None else self.id.data_ptr())
+
+    @property
+    def n(self) -> int:
+        return int(self.rho.shape[0])
+
+
+def sph_workspace_bytes(params: SphParams, n: int) -> int:
+    return int(lib.sph_workspace_bytes(C.byref(params), int(n)))
+
+
+def sph_bin_cells(params: SphParams, n: int, src: DeviceState, dst: DeviceState,
+                  key: torch.Tensor, perm: torch.Tensor, cell_start: torch.Tensor,
+                  ws: torch.Tensor, carry_in: Optional[DeviceState] = None,
+                  carry_out: Optional[DeviceState] = None, stream=None):
+    ci = C.byref(carry_in.c()) if carry_in is not None else None
+    co = C.byref(carry_out.c()) if carry_out is not None else None
+    _check(lib.sph_bin_cells(C.byref(params), int(n), C.byref(src.c()), C.byref(dst.c()), ci, co,
+                             _ptr(key), _ptr(perm), _ptr(cell_start), _ptr(ws), ws.numel(),
+                             _stream(stream)), "sph_bin_cells")
+
+
+def sph_interact(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                 cell_start: torch.Tensor, ace: torch.Tensor, arho: torch.Tensor,
+                 ws: torch.Tensor, visc: Optional[torch.Tensor] = None,
+                 nbr: Optional[torch.Tensor] = None, flags: int = 0, stream=None):
+    _check(lib.sph_interact(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
+                            _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), int(flags), _ptr(ws),
+                            ws.numel(), _stream(stream)), "sph_interact")
+
+
+def sph_reduce_dt(params: SphParams, n: int, dt: torch.Tensor, ws: torch.Tensor,
+                  interactions: Optional[torch.Tensor] = None,
+                  maxima: Optional[torch.Tensor] = None, stream=None):
+    _check(lib.sph_reduce_dt(C.byref(params), int(n), _ptr(dt), _ptr(interactions), _ptr(maxima),
+                             _ptr(ws), ws.numel(), _stream(stream)), "sph_reduce_dt")
+
+
+def sph_symplectic_step(params: SphParams, n: int, phase: int, dt: torch.Tensor,
+                        t: torch.Tensor, saved: DeviceState, s: DeviceState, ace: torch.Tensor,
+                        arho: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib.sph_symplectic_step(C.byref(params), int(n), int(phase), _ptr(dt), _ptr(t),
+                                   C.byref(saved.c()), C.byref(s.c()), _ptr(ace), _ptr(arho),
+                                   _ptr(ws), ws.numel(), _stream(stream)), "sph_symplectic_step")
+
+
+def sph_read_error(ws: torch.Tensor) -> int:
+    v = int(lib.sph_read_error(_ptr(ws)))
+    if v < 0:
+        _check(v, "sph_read_error")
+    return v
+
+
+def sph_clear_error(ws: torch.Tensor, stream=None):
+    _check(lib.sph_clear_error(_ptr(ws), _stream(stream)), "sph_clear_error")

@@ -1,0 +1,125 @@
+"""Host-side checks of libsph that need no GPU: the library loads, exports
+every symbol include/sph.h declares, the ctypes structs match the C layout,
+and argument validation rejects bad calls before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2104_00537_amd import sph
+    return sph
+
+
+def test_library_exports_every_declared_symbol(S):
+    decl = _declared()
+    assert decl == sorted(S.EXPORTS)
+    lib = C.CDLL(S.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header(S, tmp_path):
+    """The ctypes mirrors have the C compiler's size and field offsets."""
+    fields = [f for f, _ in S.SphParams._fields_]
+    sfields = [f for f, _ in S.SphState._fields_]
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "sph.h"', "int main(void){",
+            'printf("%zu %zu\\n", sizeof(sph_params), sizeof(sph_state));']
+    prog += [f'printf("%zu\\n", offsetof(sph_params, {f}));' for f in fields]
+    prog += [f'printf("%zu\\n", offsetof(sph_state, {f}));' for f in sfields]
+    prog += ["return 0;}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == C.sizeof(S.SphParams) and vals[1] == C.sizeof(S.SphState)
+    assert vals[2:2 + len(fields)] == [getattr(S.SphParams, f).offset for f in fields]
+    assert vals[2 + len(fields):] == [getattr(S.SphState, f).offset for f in sfields]
+
+
+def test_workspace_bytes_monotone(S):
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d().params)
+    sizes = [S.sph_workspace_bytes(P, n) for n in (0, 1, 1000, 100000, 10 ** 7)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] > 10 ** 7 * 48
+    assert S.sph_workspace_bytes(P, -1) == 0
+
+
+def _bad_params(S, **kw):
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d().params)
+    for k, v in kw.items():
+        if k == "ncell":
+            for i, x in enumerate(v):
+                P.ncell[i] = x
+        else:
+            setattr(P, k, v)
+    return P
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=4), dict(dim=1), dict(cell_div=3), dict(h=0.0), dict(c0=-1.0),
+    dict(ncell=(0, 5, 1)), dict(ncell=(5, 5, 2)), dict(cell_size=0.001),
+    dict(ncell=(70000, 70000, 1)), dict(mass_fluid=0.0), dict(gamma=0.0),
+])
+def test_argument_validation_without_device(S, kw):
+    """Bad parameters are rejected with SPH_E_ARG before any HIP call."""
+    P = _bad_params(S, **kw)
+    dummy = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, None)
+    lib = S.lib
+    r = lib.sph_bin_cells(C.byref(P), 10, C.byref(st), C.byref(st), None, None, dummy, dummy,
+                          dummy, dummy, 1 << 30, None)
+    assert r == S.SPH_E_ARG
+    r = lib.sph_interact(C.byref(P), 10, C.byref(st), dummy, dummy, dummy, dummy, None, None, 0,
+                         dummy, 1 << 30, None)
+    assert r == S.SPH_E_ARG
+    r = lib.sph_reduce_dt(C.byref(P), 10, dummy, None, None, dummy, 1 << 30, None)
+    assert r == S.SPH_E_ARG
+    r = lib.sph_symplectic_step(C.byref(P), 10, 0, dummy, dummy, C.byref(st), C.byref(st), dummy,
+                                dummy, dummy, 1 << 30, None)
+    assert r == S.SPH_E_ARG
+
+
+def test_workspace_and_pointer_checks_without_device(S):
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d().params)
+    lib = S.lib
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, None)
+    st2 = S.SphState(32, 16, 16, 16, None)
+    need = S.sph_workspace_bytes(P, 1000)
+    assert lib.sph_bin_cells(C.byref(P), 1000, C.byref(st), C.byref(st2), None, None, d, d, d, d,
+                             need - 1, None) == S.SPH_E_WORKSPACE
+    # in and out aliasing
+    assert lib.sph_bin_cells(C.byref(P), 1000, C.byref(st), C.byref(st), None, None, d, d, d, d,
+                             need, None) == S.SPH_E_ARG
+    # only one side of the carry pair
+    assert lib.sph_bin_cells(C.byref(P), 1000, C.byref(st), C.byref(st2), C.byref(st), None, d, d,
+                             d, d, need, None) == S.SPH_E_ARG
+    # null outputs
+    assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, None, d, None, None, 0, d, need,
+                            None) == S.SPH_E_ARG
+    assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, 0x10, d, need,
+                            None) == S.SPH_E_ARG
+    assert lib.sph_symplectic_step(C.byref(P), 1000, 2, d, d, C.byref(st), C.byref(st), d, d, d,
+                                   need, None) == S.SPH_E_ARG
+    assert lib.sph_read_error(None) == S.SPH_E_ARG
+    assert lib.sph_strerror(S.SPH_E_WORKSPACE) == b"workspace too small"

@@ -1,0 +1,396 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bars:
+  * cell keys, sort permutation, cell ranges, reorder and FP64-diagnostic
+    neighbour counts: bit-exact;
+  * one interaction pass: |GPU - oracle| <= 1e-4 * max|oracle| per output
+    (dv/dt over fluid targets, drho/dt over all targets, visc), evaluated on
+    identical inputs (the GPU's sorted state read back);
+  * dt: relative 1e-5;
+  * one full step: v and rho within the 1e-4 rate tolerance times dt plus
+    FP32 storage rounding, positions within dt times the velocity bound;
+  * multi-step: the dam-break front within 1e-3 of the tank length.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2104_00537_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2104_00537_amd import sph as S
+    from paper_2104_00537_amd.runner import Simulation
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+class Binned:
+    """Runs sph_bin_cells on a case and keeps the device buffers."""
+
+    def __init__(self, case, carry=False):
+        self.case = case
+        cp = case.params
+        self.P = S.make_params(cp)
+        self.n = n = case.n
+        self.src = S.DeviceState.from_case(case, DEV)
+        self.dst = S.DeviceState.empty(cp.dim, n, DEV)
+        self.key = torch.full((max(n, 1),), -1, dtype=torch.int32, device=DEV)
+        self.perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=DEV)
+        self.start = torch.full((cp.ncell_total() + 1,), -1, dtype=torch.int32, device=DEV)
+        self.ws = torch.zeros(S.sph_workspace_bytes(self.P, n), dtype=torch.uint8, device=DEV)
+        ci = co = None
+        if carry:
+            ci = S.DeviceState.from_case(case, DEV)
+            ci.vel.normal_()
+            ci.rho.uniform_(990.0, 1010.0)
+            ci.pos.uniform_(0.0, 1.0)
+            co = S.DeviceState.empty(cp.dim, n, DEV, with_type=False, with_id=False)
+        self.carry_in, self.carry_out = ci, co
+        S.sph_clear_error(self.ws)
+        S.sph_bin_cells(self.P, n, self.src, self.dst, self.key, self.perm, self.start, self.ws,
+                        carry_in=ci, carry_out=co)
+        torch.cuda.synchronize()
+
+    def sorted_host(self):
+        d = self.dst
+        return (d.pos.cpu().numpy(), d.vel.cpu().numpy().astype(np.float64),
+                d.rho.cpu().numpy().astype(np.float64), d.type.cpu().numpy())
+
+    def interact(self, flags=0):
+        n, dim = self.n, self.case.params.dim
+        ace = torch.full((dim, max(n, 1)), float("nan"), dtype=torch.float32, device=DEV)
+        arho = torch.full((max(n, 1),), float("nan"), dtype=torch.float32, device=DEV)
+        visc = torch.full((max(n, 1),), float("nan"), dtype=torch.float32, device=DEV)
+        nbr = torch.full((max(n, 1),), -1, dtype=torch.int32, device=DEV)
+        S.sph_interact(self.P, n, self.dst, self.key, self.start, ace, arho, self.ws, visc=visc,
+                       nbr=nbr, flags=flags)
+        torch.cuda.synchronize()
+        return (ace.cpu().numpy()[:, :n].astype(np.float64), arho.cpu().numpy()[:n].astype(np.float64),
+                visc.cpu().numpy()[:n].astype(np.float64), _u32(nbr)[:n])
+
+
+def _check_binning(case, carry=False):
+    b = Binned(case, carry=carry)
+    cp, n = case.params, case.n
+    key_ref = oracle.cell_keys(cp, case.pos)
+    perm_ref = oracle.sort_perm(key_ref)
+    skey_ref = key_ref[perm_ref]
+    start_ref = oracle.cell_start(skey_ref, cp.ncell_total())
+    assert np.array_equal(_u32(b.key)[:n], skey_ref)
+    assert np.array_equal(_u32(b.perm)[:n], perm_ref)
+    assert np.array_equal(_u32(b.start), start_ref)
+    pos, vel, rho, typ = b.sorted_host()
+    assert np.array_equal(pos, case.pos[:, perm_ref])
+    assert np.array_equal(vel, case.vel[:, perm_ref].astype(np.float64))
+    assert np.array_equal(rho, case.rho[perm_ref].astype(np.float64))
+    out = skey_ref == cp.ncell_total()
+    typ_ref = case.type[perm_ref] | np.where(out, cases.EXCLUDED, 0).astype(np.uint8)
+    assert np.array_equal(typ, typ_ref)
+    assert np.array_equal(_u32(b.dst.id)[:n], perm_ref)
+    if carry:
+        ci, co = b.carry_in, b.carry_out
+        assert torch.equal(co.pos, ci.pos[:, perm_ref])
+        assert torch.equal(co.vel, ci.vel[:, perm_ref])
+        assert torch.equal(co.rho, ci.rho[perm_ref])
+    err = S.sph_read_error(b.ws)
+    assert bool(err & S.SPH_ERR_EXCLUDED) == bool(out.any())
+    return b
+
+
+def _scramble(case, seed):
+    """Same particles in a random input order (the sort must not rely on the
+    generator's lattice order)."""
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(case.n)
+    return cases.Case(case.params, np.ascontiguousarray(case.pos[:, p]),
+                      np.ascontiguousarray(case.vel[:, p]), case.rho[p].copy(), case.type[p].copy(),
+                      dict(case.meta))
+
+
+# ------------------------------------------------------------------ binning
+@pytest.mark.parametrize("cell_div", [1, 2])
+def test_bin_cells_2d_dam_break(cell_div):
+    _say("bin 2d dam break cell_div", cell_div)
+    _check_binning(_scramble(cases.dam_break_2d(cell_div=cell_div), 1), carry=True)
+
+
+def test_bin_cells_3d_block_ragged():
+    _say("bin 3d ragged")
+    c = cases.block_case(3, (23, 19, 13), walls=True, seed=3)  # ~5.7k + walls
+    _check_binning(_scramble(c, 2))
+
+
+def test_bin_cells_out_of_grid_and_edges():
+    _say("bin edge cases")
+    base = cases.dam_break_2d(dp=0.02)
+    cp = base.params
+    rng = np.random.default_rng(7)
+    for n in [0, 1, 2, 63, 2047, 2048, 2049, 5000]:
+        lo = np.array(cp.origin[:2])
+        hi = lo + np.array(cp.ncell[:2]) * cp.cell_size
+        pos = rng.uniform(lo[:, None] - 0.05, hi[:, None] + 0.05, size=(2, n))
+        c = cases.Case(cp, pos, np.zeros((2, n), np.float32),
+                       np.full(n, 1000.0, np.float32), rng.integers(0, 3, n).astype(np.uint8))
+        _check_binning(c)
+
+
+def test_bin_cells_all_same_cell_is_stable():
+    _say("bin same cell")
+    base = cases.dam_break_2d(dp=0.02)
+    cp = base.params
+    n = 9000
+    pos = np.tile(np.array([[0.3], [0.2]]), (1, n)) + np.random.default_rng(1).uniform(0, 1e-5, (2, n))
+    c = cases.Case(cp, pos, np.zeros((2, n), np.float32), np.full(n, 1000.0, np.float32),
+                   np.zeros(n, np.uint8))
+    b = _check_binning(c)
+    assert np.array_equal(_u32(b.perm)[:n], np.arange(n))
+
+
+# -------------------------------------------------------------- interaction
+def _perturbed(case, seed, vel=0.5, drho=0.003):
+    rng = np.random.default_rng(seed)
+    c = cases.Case(case.params, case.pos.copy(), case.vel.copy(), case.rho.copy(), case.type.copy(),
+                   dict(case.meta))
+    c.vel[:] = rng.uniform(-vel, vel, c.vel.shape).astype(np.float32)
+    c.rho[:] = (c.rho * (1 + rng.uniform(-drho, drho, c.n))).astype(np.float32)
+    return c
+
+
+def _check_interact(case, label):
+    _say("interact", label, "n", case.n)
+    b = Binned(case)
+    pos, vel, rho, typ = b.sorted_host()
+    cp = case.params
+    ace_g, arho_g, visc_g, nbr_g = b.interact(flags=S.SPH_DIAG_COUNT_F64)
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(cp, pos, vel, rho, typ)
+    fl = (typ & 0x7F) == cases.FLUID
+    fl &= (typ & cases.EXCLUDED) == 0
+    # neighbour counts (FP64 test): bit-exact
+    assert np.array_equal(nbr_g, nbr_o)
+    # force and density rate: 1e-4 of the largest magnitude
+    ea = np.abs(ace_g - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+    er = np.abs(arho_g - arho_o).max() / max(np.abs(arho_o).max(), 1e-30)
+    vmax = np.abs(visc_o).max()
+    ev = (np.abs(visc_g - visc_o).max() / vmax) if vmax > 0 else np.abs(visc_g).max()
+    _say(f"  rel err ace {ea:.2e} arho {er:.2e} visc {ev:.2e}")
+    assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
+    assert np.all(ace_g[:, ~fl] == 0.0)
+    # production (FP32 test) counts may differ from FP64 only at |r| ~ 2h
+    _, _, _, nbr32 = b.interact(flags=0)
+    flips = int(np.abs(nbr32.astype(np.int64) - nbr_o.astype(np.int64)).sum())
+    _say(f"  fp32 count flips {flips} of {int(nbr_o.sum())}")
+    assert flips <= 1e-4 * nbr_o.sum() + 2
+    return b, (ace_o, arho_o, visc_o, nbr_o), typ
+
+
+@pytest.mark.parametrize("cell_div", [1, 2])
+def test_interact_2d_dam_break_initial(cell_div):
+    _check_interact(cases.dam_break_2d(cell_div=cell_div), f"2d t0 cd{cell_div}")
+
+
+@pytest.mark.parametrize("cell_div", [1, 2])
+def test_interact_2d_perturbed(cell_div):
+    _check_interact(_perturbed(cases.dam_break_2d(cell_div=cell_div), 5), f"2d pert cd{cell_div}")
+
+
+@pytest.mark.parametrize("cell_div", [1, 2])
+def test_interact_3d_block_with_walls(cell_div):
+    c = cases.block_case(3, (21, 17, 15), walls=True, seed=4, cell_div=cell_div)
+    _check_interact(_perturbed(c, 6, vel=0.3), f"3d walls cd{cell_div}")
+
+
+def test_interact_moving_walls_and_excluded():
+    c = cases.sloshing_3d(dp=0.05, seed=2)
+    c = _perturbed(c, 9, vel=0.2)
+    # push a few particles out of the grid: they must be excluded everywhere
+    c.pos[2, :3] = 50.0
+    b, _, typ = _check_interact(c, "sloshing coarse")
+    assert np.count_nonzero(typ & cases.EXCLUDED) == 3
+    assert S.sph_read_error(b.ws) & S.SPH_ERR_EXCLUDED
+
+
+def test_interact_empty_and_single():
+    for n in [0, 1]:
+        base = cases.dam_break_2d(dp=0.02)
+        c = cases.Case(base.params, base.pos[:, :n].copy(), base.vel[:, :n].copy(),
+                       base.rho[:n].copy(), base.type[:n].copy())
+        b = Binned(c)
+        ace, arho, visc, nbr = b.interact(flags=S.SPH_DIAG_COUNT_F64)
+        if n == 1:
+            assert np.allclose(ace[:, 0], base.params.gravity[:2]) and arho[0] == 0 and nbr[0] == 0
+        dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+        S.sph_reduce_dt(b.P, n, dt, b.ws)
+        torch.cuda.synchronize()
+        if n == 0:
+            # no fluid particle: Eq. 35 has no minimiser
+            assert math.isinf(dt.item()) and S.sph_read_error(b.ws) & S.SPH_ERR_DT_FLOOR
+
+
+# ------------------------------------------------------------------ dt, step
+def test_reduce_dt_and_interaction_count():
+    c = _perturbed(cases.dam_break_2d(), 11, vel=1.0)
+    b = Binned(c)
+    pos, vel, rho, typ = b.sorted_host()
+    ace_o, _, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ)
+    dt_o = oracle.time_step(c.params, typ, ace_o, visc_o)
+    ace_g, _, _, nbr_g = b.interact(flags=0)
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    inter = torch.zeros(2, dtype=torch.int64, device=DEV)
+    maxima = torch.zeros(2, dtype=torch.float32, device=DEV)
+    S.sph_reduce_dt(b.P, c.n, dt, b.ws, interactions=inter, maxima=maxima)
+    torch.cuda.synchronize()
+    assert dt.item() == pytest.approx(dt_o, rel=1e-5)
+    assert inter[0].item() == int(nbr_g.astype(np.int64).sum())
+    assert inter[1].item() == int(nbr_g[typ != 0].astype(np.int64).sum())
+    fl = typ == 0
+    assert maxima[0].item() == pytest.approx(np.hypot(*ace_o[:, fl]).max(), rel=1e-4)
+    assert maxima[1].item() == pytest.approx(visc_o[fl].max(), rel=1e-4)
+
+
+def _oracle_step(cp, st, dt=None, t=0.0):
+    pos, vel, rho, typ = st
+    ace, arho, visc, _ = oracle.interact(cp, pos, vel, rho, typ)
+    dt_n = oracle.time_step(cp, typ, ace, visc)
+    if dt is None:
+        dt = dt_n
+    half, saved = oracle.predictor(cp, dt, t, pos, vel, rho, typ, ace, arho)
+    ace2, arho2, _, _ = oracle.interact(cp, half[0], half[1], half[2], typ)
+    fl = typ == cases.FLUID
+    amax = max(np.abs(ace[:, fl]).max(), np.abs(ace2[:, fl]).max())
+    rmax = max(np.abs(arho).max(), np.abs(arho2).max())
+    out = oracle.corrector(cp, dt, t, half, saved, typ, ace2, arho2)
+    return out, dt_n, amax, rmax
+
+
+@pytest.mark.parametrize("maker", ["dam2d", "slosh3d"])
+def test_one_symplectic_step(maker):
+    """One full step (NL, PI, dt, predictor, NL with carry, PI, corrector)
+    against the oracle's step from the same state, with the GPU's dt.  The
+    bound: the 1e-4 force/density-rate tolerance times dt, plus FP32 storage
+    of v and rho."""
+    _say("one step", maker)
+    if maker == "dam2d":
+        c = _perturbed(cases.dam_break_2d(), 13, vel=0.5)
+    else:
+        c = _perturbed(cases.sloshing_3d(dp=0.04, seed=1), 14, vel=0.2)
+    sim = Simulation(c, DEV)
+    sim.t.fill_(0.3)  # moving walls away from t = 0
+    sim.step()
+    torch.cuda.synchronize()
+    assert sim.error() == 0
+    g = sim.host_state()
+    dt_g = sim.dt.item()
+    st = (c.pos, c.vel.astype(np.float64), c.rho.astype(np.float64), c.type)
+    (pos_o, vel_o, rho_o), dt_n, amax, rmax = _oracle_step(c.params, st, dt=dt_g, t=0.3)
+    assert dt_g == pytest.approx(dt_n, rel=1e-5)
+    vmax = np.abs(vel_o).max()
+    tol_v = 2e-4 * amax * dt_g + 2 * 6e-8 * vmax
+    tol_x = dt_g * tol_v + 1e-12
+    tol_r = 2e-4 * rmax * dt_g + 2.5e-4
+    ev, ex, er = (np.abs(g["vel"] - vel_o).max(), np.abs(g["pos"] - pos_o).max(),
+                  np.abs(g["rho"] - rho_o).max())
+    _say(f"  errors pos {ex:.2e}/{tol_x:.2e} vel {ev:.2e}/{tol_v:.2e} rho {er:.2e}/{tol_r:.2e}")
+    assert ex < tol_x and ev < tol_v and er < tol_r
+    assert g["t"] == pytest.approx(0.3 + dt_g, rel=1e-15)
+
+
+def test_dam_break_2d_front_1000_steps():
+    """configs[0]-shaped run: 1000 symplectic steps; the front x_f =
+    max_{fluid} x stays within 1e-3 of the tank length of the oracle's."""
+    _say("2d dam break 1000 steps")
+    c = cases.dam_break_2d()
+    sim = Simulation(c, DEV)
+    fronts_g = []
+    for k in range(10):
+        sim.run(100)
+        st = sim.host_state()
+        fronts_g.append(st["pos"][0][st["type"] == 0].max())
+    assert sim.error() == 0
+    out = dict(pos=c.pos, vel=c.vel, rho=c.rho, type=c.type, t=0.0)
+    fronts_o = []
+    for k in range(10):
+        out = oracle.run(c.params, out["pos"], out["vel"], out["rho"], out["type"], 100, t0=out["t"])
+        assert out["status"] == 0
+        fronts_o.append(out["pos"][0][out["type"] == 0].max())
+    _say("  fronts gpu", np.round(fronts_g, 5))
+    _say("  fronts orc", np.round(fronts_o, 5))
+    assert np.abs(np.array(fronts_g) - np.array(fronts_o)).max() < 1e-3 * 1.6
+    assert st["t"] == pytest.approx(out["t"], rel=1e-4)
+    # the column has started to collapse
+    assert fronts_o[-1] > 0.4 + 0.005
+
+
+def test_determinism_and_graph_replay():
+    c = _perturbed(cases.dam_break_2d(dp=0.015), 21, vel=0.3)
+    a = Simulation(c, DEV)
+    b = Simulation(c, DEV)
+    a.run(5)
+    b.run(2)
+    b.capture(1)
+    for _ in range(3):
+        b.replay(1)
+        torch.cuda.synchronize()
+        _ = b.state.rho.sum().item()   # eager work between replays
+    torch.cuda.synchronize()
+    sa, sb = a.host_state(), b.host_state()
+    for k in ("pos", "vel", "rho", "type"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sa["t"] == sb["t"]
+
+
+def test_failure_words():
+    """Host-forced failures: a NaN density sets SPH_ERR_NONFINITE, a
+    particle outside the grid sets SPH_ERR_EXCLUDED; the run itself returns."""
+    c = cases.dam_break_2d(dp=0.02)
+    c.rho[10] = np.float32("nan")
+    sim = Simulation(c, DEV)
+    sim.step()
+    assert sim.error() & S.SPH_ERR_NONFINITE
+    c2 = cases.dam_break_2d(dp=0.02)
+    c2.pos[1, 5] = 100.0
+    sim2 = Simulation(c2, DEV)
+    sim2.step()
+    assert sim2.error() == S.SPH_ERR_EXCLUDED
+    st = sim2.host_state()
+    assert st["type"][5] & cases.EXCLUDED and st["pos"][1, 5] == 100.0
+
+
+# ------------------------------------------------------- full-size sampling
+def test_dam_break_3d_1m_sampled():
+    """The 1M-fluid 3-D dam break at full size, in the launch configuration
+    the benchmark times: keys/perm/ranges bit-exact against the oracle,
+    interaction outputs on 600 sampled targets."""
+    _say("3d 1M sampled")
+    c = cases.dam_break_3d()
+    b = Binned(c)
+    n = c.n
+    key_ref = oracle.cell_keys(c.params, c.pos)
+    perm_ref = oracle.sort_perm(key_ref)
+    assert np.array_equal(_u32(b.key)[:n], key_ref[perm_ref])
+    assert np.array_equal(_u32(b.perm)[:n], perm_ref)
+    assert np.array_equal(_u32(b.start), oracle.cell_start(key_ref[perm_ref], c.params.ncell_total()))
+    pos, vel, rho, typ = b.sorted_host()
+    ace_g, arho_g, visc_g, nbr_g = b.interact(flags=S.SPH_DIAG_COUNT_F64)
+    rng = np.random.default_rng(0)
+    tg = np.concatenate([rng.choice(np.flatnonzero(typ == 0), 500, replace=False),
+                         rng.choice(np.flatnonzero(typ != 0), 100, replace=False)])
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ, targets=tg)
+    assert np.array_equal(nbr_g[tg], nbr_o)
+    fl = typ[tg] == 0
+    ea = np.abs(ace_g[:, tg] - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+    er = np.abs(arho_g[tg] - arho_o).max() / np.abs(arho_o).max()
+    _say(f"  rel err ace {ea:.2e} arho {er:.2e}; interior nbr {np.median(nbr_o[fl])}")
+    assert ea < 1e-4 and er < 1e-4
