@@ -94,7 +94,7 @@ typedef struct sph_params {
   double c0;              /* numerical speed of sound (Section 2.4) */
   double alpha;           /* artificial viscosity coefficient (Eq. 21) */
   double delta;           /* density diffusion coefficient (Eq. 17) */
-  double eta2;            /* eta^2 in the denominators of Eq. 21 and Eq. 35 */
+  double eta2;            /* eta^2 > 0 in the denominators of Eq. 21 and 35 */
   double cfl;             /* Courant number C_CFL (Eq. 35) */
   double mass_fluid;      /* particle masses of fluid / wall particles */
   double mass_bound;

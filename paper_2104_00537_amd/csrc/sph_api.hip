@@ -69,7 +69,8 @@ static bool params_ok(const sph_params* p) {
   if (!(p->cell_size > 0) || !(p->inv_cell_size > 0)) return false;
   // the +-cell_div cell stencil must cover the 2h support
   if (p->cell_size * p->cell_div < 2.0 * p->h * (1.0 - 1e-12)) return false;
-  if (!(p->cfl > 0) || !(p->eta2 >= 0) || !(p->mass_fluid > 0) || !(p->mass_bound > 0))
+  // eta^2 > 0 keeps Eq. 21 non-singular (also for coincident particles)
+  if (!(p->cfl > 0) || !(p->eta2 > 0) || !(p->mass_fluid > 0) || !(p->mass_bound > 0))
     return false;
   return true;
 }

@@ -1,25 +1,97 @@
 // Particle interaction (Section 2.3 of the DualSPHysics v5.0 paper): the
 // continuity and momentum sums over neighbours within 2h, on gfx950.
+//
+// Four kernels share the pair arithmetic:
+//  * k_interact_sgpr (production): a wave walks one candidate stream for its
+//    64 targets with candidates in SGPRs; hits go to per-lane LDS lists.
+//  * k_interact_compact: one lane per target walking its own
+//    cells, hits compacted into per-lane LDS lists, pair terms run densely.
+//  * k_interact_tile: a wavefront takes kTileG consecutive sorted
+//    targets with kTileTPL lanes per target.  The union of their neighbour-cell
+//    rows is staged in LDS in a frame common to the wave; each lane tests every
+//    kTileTPL-th staged candidate against its target and appends the hits to
+//    its own LDS list; the pair terms then run densely over the lists.  The
+//    partial sums of the lanes of a target are combined at the end.
+//  * k_interact_gather: one lane per target walking its own cells in global
+//    memory.  It also offers the FP64 diagnostic neighbour count.
+// Sums are gathered per target (no atomics): results are deterministic.
+#include <stdlib.h>
+
 #include "sph_kernels.h"
 
 namespace sph {
 
+struct PairAcc {
+  float ax, ay, az;  // sum of -m_b [(P_a+P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
+  float cont;        // sum of (m_b/rho_b) F_ab v_ab.r_ab
+  float diff;        // sum over fluid b of (rho_b - rho_a)|F_ab| m_b/rho_b
+  float vmax;        // max of |h v_ab.r_ab/(r^2+eta^2)|
+  uint32_t cnt;      // pairs evaluated
+};
+
+struct TargetData {
+  bool fluid;
+  float rho, irho, p;
+  float vx, vy, vz;
+};
+
+// The pair terms of Eq. 11 (gradient), 15, 17-18, 21-22 and 36 for one pair
+// (a, b) with r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pb.w is +rho_b for a
+// fluid particle and -rho_b for a wall; vb.w is P_b.  The caller has already
+// dropped wall-wall pairs (Eq. 36 sums over fluid neighbours only).
+template <int DIM>
+__device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
+                                           float dy, float dz, float r2, const float4& pb,
+                                           const float4& vb, PairAcc& acc) {
+  const bool fb = pb.w > 0.f;
+  const float rhob = fabsf(pb.w);
+  const float vr = (a.vx - vb.x) * dx + (a.vy - vb.y) * dy + (DIM == 3 ? (a.vz - vb.z) * dz : 0.f);
+  const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h_f;
+  const float w = 1.f - 0.5f * q;
+  const float fab = kp.kfab_f * w * w * w;  // grad_a W_ab = fab r_ab, fab <= 0
+  const float irhob = __builtin_amdgcn_rcpf(rhob);
+  const float mb = fb ? kp.mass_f_f : kp.mass_b_f;
+  const float fv = fab * (mb * irhob);
+  acc.cont += fv * vr;
+  acc.cnt += 1u;
+  if (a.fluid) {
+    const float pterm = (a.p + vb.w) * (a.irho * irhob);
+    const float mu = kp.h_f * vr * __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
+    // Pi_ab = -alpha c0 mu / ((rho_a + rho_b)/2) for approaching pairs (Eq. 21)
+    const float pi =
+        vr < 0.f ? -2.f * kp.visc_coef_f * mu * __builtin_amdgcn_rcpf(a.rho + rhob) : 0.f;
+    const float coef = mb * (pterm + pi) * fab;
+    acc.ax -= coef * dx;
+    acc.ay -= coef * dy;
+    if (DIM == 3) acc.az -= coef * dz;
+    acc.vmax = fmaxf(acc.vmax, fabsf(mu));
+    if (fb) acc.diff -= (rhob - a.rho) * fv;
+  }
+}
+
 // ------------------------------------------------- block partial results --
+template <int WAVES>
 __device__ inline void write_block_red(float fmag, float vmax, uint32_t cnt, uint32_t cntw,
-                                       uint32_t nfl, BlockRed* red) {
-  __shared__ float sf[kBlock / 64], sv[kBlock / 64];
-  __shared__ uint32_t sc[kBlock / 64], sw[kBlock / 64], sn[kBlock / 64];
+                                       uint32_t nfl, BlockRed* red, WsHeader* hdr) {
+  __shared__ float sf[WAVES], sv[WAVES];
+  __shared__ uint32_t sc[WAVES], sw[WAVES], sn[WAVES];
   fmag = wave_max(fmag);
   vmax = wave_max(vmax);
   cnt = wave_sum(cnt);
   cntw = wave_sum(cntw);
   nfl = wave_sum(nfl);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { sf[wave] = fmag; sv[wave] = vmax; sc[wave] = cnt; sw[wave] = cntw; sn[wave] = nfl; }
+  if (lane == 0) {
+    sf[wave] = fmag;
+    sv[wave] = vmax;
+    sc[wave] = cnt;
+    sw[wave] = cntw;
+    sn[wave] = nfl;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     BlockRed b{0.f, 0.f, 0u, 0u, 0u, 0u};
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
       b.fmax = fmaxf(b.fmax, sf[w]);
       b.vmax = fmaxf(b.vmax, sv[w]);
       b.count += sc[w];
@@ -27,35 +99,551 @@ __device__ inline void write_block_red(float fmag, float vmax, uint32_t cnt, uin
       b.nfluid += sn[w];
     }
     red[blockIdx.x] = b;
+    if (blockIdx.x == 0) hdr->nred = gridDim.x;
   }
 }
 
-// ------------------------------------------------- interaction, version 1 --
+// Per-target outputs: dv/dt (with gravity) for fluid targets, drho/dt, visc
+// and the pair count; returns |dv/dt|, visc and the fluid flag for the block
+// partial results.
+template <int DIM>
+__device__ __forceinline__ void write_target(const KParams& kp, int64_t n, int64_t a,
+                                             const TargetData& t, const PairAcc& acc,
+                                             uint32_t count_out, float* ace, float* arho,
+                                             float* visc, uint32_t* nbr, float& fmag,
+                                             float& vmax_out, uint32_t& nfl) {
+  float ax = 0.f, ay = 0.f, az = 0.f;
+  float ar = t.rho * acc.cont;
+  if (t.fluid) {
+    ax = acc.ax + kp.gx_f;
+    ay = acc.ay + kp.gy_f;
+    az = DIM == 3 ? acc.az + kp.gz_f : 0.f;
+    ar += kp.ddt_coef_f * acc.diff;
+    fmag = sqrtf(ax * ax + ay * ay + az * az);
+    vmax_out = acc.vmax;
+    nfl = 1;
+  }
+  ace[a] = ax;
+  ace[n + a] = ay;
+  if (DIM == 3) ace[2 * n + a] = az;
+  arho[a] = ar;
+  if (visc) visc[a] = acc.vmax;
+  if (nbr) nbr[a] = count_out;
+}
+
+template <int DIM>
+__device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, float* arho,
+                                           float* visc, uint32_t* nbr) {
+  ace[a] = 0.f;
+  ace[n + a] = 0.f;
+  if (DIM == 3) ace[2 * n + a] = 0.f;
+  arho[a] = 0.f;
+  if (visc) visc[a] = 0.f;
+  if (nbr) nbr[a] = 0u;
+}
+
+// Orders this wave's LDS writes before its later LDS reads (no block barrier:
+// the waves of a block progress independently).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// ------------------------------------------------ interaction: LDS tiles --
+constexpr int kTileWaves = 2;            // independent waves per block
+constexpr int kTileTPL = 4;              // lanes per target
+constexpr int kTileG = 64 / kTileTPL;    // targets per wave
+constexpr int kTileMaxC = 512;           // staged candidates per wave
+constexpr int kTileLCap = 64;            // hit-list entries per lane
+constexpr int kTileKCh = 16;             // candidates per lane between list checks
+static_assert(kTileWaves * kTileG == kTileTargets, "tile size");
+
+struct TileLds {
+  float4 cpos[kTileMaxC];          // candidate position in the wave frame, +-rho
+  float4 cvel[kTileMaxC];          // candidate velocity, pressure
+  uint16_t list[kTileLCap * 64];   // list[k*64 + lane]: staged index of hit k
+};
+
+template <int DIM, int R>
+__global__ __launch_bounds__(64 * kTileWaves) void k_interact_tile(
+    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
+    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+  __shared__ TileLds lds_all[kTileWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  TileLds& L = lds_all[wv];
+  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
+  const int tl = lane / kTileTPL, sub = lane % kTileTPL;
+  const int64_t a = ((int64_t)blockIdx.x * kTileWaves + wv) * kTileG + tl;
+  const bool valid = a < nvalid;
+
+  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    pa = pr[a];
+    const float4 va = vp[a];
+    const uint32_t k = key[a];
+    cx = (int)(k % (uint32_t)kp.ncx);
+    const uint32_t rest = k / (uint32_t)kp.ncx;
+    cy = (int)(rest % (uint32_t)kp.ncy);
+    cz = (int)(rest / (uint32_t)kp.ncy);
+    T.fluid = pa.w > 0.f;
+    T.rho = fabsf(pa.w);
+    T.irho = __builtin_amdgcn_rcpf(T.rho);
+    T.p = va.w;
+    T.vx = va.x;
+    T.vy = va.y;
+    T.vz = va.z;
+  }
+  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  bool todo = valid;
+  while (__ballot(todo) != 0ull) {
+    // the cell row (cy, cz) of the first remaining target, and the x extent
+    // of the remaining targets in that row
+    const uint64_t rem = __ballot(todo);
+    const int leader = (int)__builtin_ctzll(rem);
+    const int ry = __builtin_amdgcn_readlane(cy, leader);
+    const int rz = __builtin_amdgcn_readlane(cz, leader);
+    const bool inrow = todo && cy == ry && cz == rz;
+    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+      xmn = min(xmn, __shfl_xor(xmn, off, 64));
+      xmx = max(xmx, __shfl_xor(xmx, off, 64));
+    }
+    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
+    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
+    // the target in the wave frame: its cell-relative offset shifted to cell xmin
+    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
+    const float ya = pa.y, za = pa.z;
+    const bool fa = T.fluid;
+
+    // hit list of this lane: tests staged candidates sub, sub + TPL, ...
+    int cnt = 0;
+    auto drain = [&]() {
+      wave_sync();
+      int m = cnt;
+      for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+      m = __builtin_amdgcn_readfirstlane(m);
+      for (int k = 0; k < m; ++k) {
+        if (k < cnt) {
+          const int s = L.list[k * 64 + lane];
+          const float4 pb = L.cpos[s];
+          const float4 vb = L.cvel[s];
+          const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
+        }
+      }
+      wave_sync();
+      cnt = 0;
+    };
+    auto flush = [&](int nbuf) {
+      wave_sync();
+      const int kmax = (nbuf + kTileTPL - 1) / kTileTPL;
+      for (int k0 = 0; k0 < kmax; k0 += kTileKCh) {
+        if (__ballot(cnt > kTileLCap - kTileKCh) != 0ull) drain();
+        const int k1 = min(k0 + kTileKCh, kmax);
+        for (int k = k0; k < k1; ++k) {
+          const int s = k * kTileTPL + sub;
+          if (s < nbuf) {
+            const float4 pb = L.cpos[s];
+            const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (inrow && r2 < kp.support2_f && (fa || pb.w > 0.f)) {
+              L.list[cnt * 64 + lane] = (uint16_t)s;
+              ++cnt;
+            }
+          }
+        }
+      }
+      drain();
+    };
+
+    int nbuf = 0;
+    const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      const int z = rz + dz;
+      if (z < 0 || z >= kp.ncz) continue;
+      for (int dy = -R; dy <= R; ++dy) {
+        const int y = ry + dy;
+        if (y < 0 || y >= kp.ncy) continue;
+        const int xlo = max(xmin - R, 0), xhi = min(xmax + R, kp.ncx - 1);
+        const uint32_t rowbase = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+        const uint32_t j1 = cstart[rowbase + xhi + 1];
+        uint32_t jj = cstart[rowbase + xlo];
+        const float sy = (float)dy * kp.cs_f, sz = (float)dz * kp.cs_f;
+        while (jj < j1) {
+          const uint32_t take = min(min(j1 - jj, (uint32_t)(kTileMaxC - nbuf)), 64u);
+          if ((uint32_t)lane < take) {
+            const uint32_t j = jj + lane;
+            const float4 p = pr[j];
+            const float4 v = vp[j];
+            const float sx = (float)((int)(key[j] - rowbase) - xmin) * kp.cs_f;
+            L.cpos[nbuf + lane] = make_float4(p.x + sx, p.y + sy, p.z + sz, p.w);
+            L.cvel[nbuf + lane] = v;
+          }
+          nbuf += (int)take;
+          jj += take;
+          if (nbuf == kTileMaxC) {
+            flush(nbuf);
+            nbuf = 0;
+          }
+        }
+      }
+    }
+    if (nbuf > 0) flush(nbuf);
+    todo = todo && !inrow;
+  }
+
+  // combine the partial sums of the lanes of each target (adjacent lanes)
+  for (int off = 1; off < kTileTPL; off <<= 1) {
+    acc.ax += __shfl_xor(acc.ax, off, 64);
+    acc.ay += __shfl_xor(acc.ay, off, 64);
+    acc.az += __shfl_xor(acc.az, off, 64);
+    acc.cont += __shfl_xor(acc.cont, off, 64);
+    acc.diff += __shfl_xor(acc.diff, off, 64);
+    acc.vmax = fmaxf(acc.vmax, __shfl_xor(acc.vmax, off, 64));
+    acc.cnt += __shfl_xor(acc.cnt, off, 64);
+  }
+  float fmag = 0.f, vmax_out = 0.f;
+  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
+  if (valid && sub == 0) {
+    // a fluid target finds itself among its hits (r = 0: every term is zero);
+    // it is not its own neighbour
+    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
+    write_target<DIM>(kp, n, a, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+    cnt_out = c;
+    cnt_wall = T.fluid ? 0u : c;
+  }
+  // excluded particles (sorted after the valid ones) get zeros
+  if (!valid && a < n && sub == 0) write_zero<DIM>(n, a, ace, arho, visc, nbr);
+  write_block_red<kTileWaves>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
+}
+
+// -------------------------------------- interaction: compacted own walk --
+// One lane per target particle (sorted order), as in the gather kernel, but
+// the lane only tests candidates while walking its (2R+1)^d cells: hits go to
+// a per-lane LDS list (global index + cell offset code), and the pair terms
+// run densely over the lists when a list is about to fill and at the end.
+// The candidate loop of each cell runs to the wave's largest cell count so
+// that the wave stays converged and can drain its lists together.
+constexpr int kCompLCap = 30;   // list entries per lane (4 blocks of 256 fit the LDS)
+constexpr int kCompU = 4;       // candidates per lane between list checks
+
+template <int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_interact_compact(
+    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
+    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+  __shared__ uint32_t list_j[kCompLCap][kBlock];
+  __shared__ uint8_t list_c[kCompLCap][kBlock];
+  constexpr int W = 2 * R + 1;
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + tid;
+  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
+  const bool valid = i < nvalid;
+  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    pa = pr[i];
+    const float4 va = vp[i];
+    const uint32_t k = key[i];
+    cx = (int)(k % (uint32_t)kp.ncx);
+    const uint32_t rest = k / (uint32_t)kp.ncx;
+    cy = (int)(rest % (uint32_t)kp.ncy);
+    cz = (int)(rest / (uint32_t)kp.ncy);
+    T.fluid = pa.w > 0.f;
+    T.rho = fabsf(pa.w);
+    T.irho = __builtin_amdgcn_rcpf(T.rho);
+    T.p = va.w;
+    T.vx = va.x;
+    T.vy = va.y;
+    T.vz = va.z;
+  }
+  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  int cnt = 0;
+  auto drain = [&]() {
+    wave_sync();
+    int m = cnt;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    m = __builtin_amdgcn_readfirstlane(m);
+    for (int k = 0; k < m; ++k) {
+      if (k < cnt) {
+        const uint32_t j = list_j[k][tid];
+        const int code = list_c[k][tid];
+        const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+        const float4 pb = pr[j];
+        const float4 vb = vp[j];
+        const float dx = pa.x - (pb.x + (float)ox * kp.cs_f);
+        const float dy = pa.y - (pb.y + (float)oy * kp.cs_f);
+        const float dz = DIM == 3 ? pa.z - (pb.z + (float)oz * kp.cs_f) : 0.f;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
+      }
+    }
+    wave_sync();
+    cnt = 0;
+  };
+  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+  for (int oz = zlo; oz <= zhi; ++oz) {
+    for (int oy = -R; oy <= R; ++oy) {
+      for (int ox = -R; ox <= R; ++ox) {
+        const int x = cx + ox, y = cy + oy, z = cz + oz;
+        uint32_t j0 = 0, len = 0;
+        if (valid && x >= 0 && x < kp.ncx && y >= 0 && y < kp.ncy && z >= 0 && z < kp.ncz) {
+          const uint32_t c = (uint32_t)x + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+          j0 = cstart[c];
+          len = cstart[c + 1] - j0;
+        }
+        uint32_t m = len;
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+        m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+        if (m == 0) continue;
+        const float sx = (float)ox * kp.cs_f, sy = (float)oy * kp.cs_f, sz = (float)oz * kp.cs_f;
+        const float xa = pa.x - sx, ya = pa.y - sy, za = pa.z - sz;
+        const uint8_t code = (uint8_t)((ox + R) + W * ((oy + R) + W * (oz + R)));
+        for (uint32_t k0 = 0; k0 < m; k0 += kCompU) {
+          if (__ballot(cnt > kCompLCap - kCompU) != 0ull) drain();
+#pragma unroll
+          for (int u = 0; u < kCompU; ++u) {
+            const uint32_t k = k0 + u;
+            if (k < len) {
+              const uint32_t j = j0 + k;
+              const float4 pb = pr[j];
+              const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
+              const float r2 = dx * dx + dy * dy + dz * dz;
+              if (r2 < kp.support2_f && (T.fluid || pb.w > 0.f)) {
+                list_j[cnt][tid] = j;
+                list_c[cnt][tid] = code;
+                ++cnt;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  drain();
+  float fmag = 0.f, vmax_out = 0.f;
+  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
+  if (valid) {
+    // a fluid target finds itself among its hits (r = 0: every term is zero);
+    // it is not its own neighbour
+    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
+    write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+    cnt_out = c;
+    cnt_wall = T.fluid ? 0u : c;
+  } else if (i < n) {
+    write_zero<DIM>(n, i, ace, arho, visc, nbr);
+  }
+  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
+}
+
+// ------------------------------------ interaction: scalar candidate stream --
+// A wavefront takes 64 consecutive sorted targets (one per lane).  For the
+// targets of one cell row it walks the union of their neighbour cells as a
+// single candidate stream that is the same for every lane: candidate data is
+// fetched with scalar loads into SGPRs and used directly as VALU operands, so
+// no per-lane memory traffic is spent on candidates that fail the distance
+// test.  Each lane appends its hits (global index + index of the cell's frame
+// shift) to its own LDS list; the pair terms then run densely over the lists.
+constexpr int kSgLCap = 36;      // list entries per lane (4 blocks of 256 fit the LDS)
+constexpr int kSgCells = 32;     // cell shifts kept per wave between drains
+constexpr int kSgJBits = 27;     // list entry: j (27 bits) | cell slot (5 bits)
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+struct SgLds {
+  uint32_t list[kSgLCap][64];
+  float4 shift[kSgCells];
+};
+
+template <int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_interact_sgpr(
+    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
+    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+  __shared__ SgLds lds_all[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  SgLds& L = lds_all[wv];
+  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
+  const int64_t a = ((int64_t)blockIdx.x * (kBlock / 64) + wv) * 64 + lane;
+  const bool valid = a < nvalid;
+  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    pa = pr[a];
+    const float4 va = vp[a];
+    const uint32_t k = key[a];
+    cx = (int)(k % (uint32_t)kp.ncx);
+    const uint32_t rest = k / (uint32_t)kp.ncx;
+    cy = (int)(rest % (uint32_t)kp.ncy);
+    cz = (int)(rest / (uint32_t)kp.ncy);
+    T.fluid = pa.w > 0.f;
+    T.rho = fabsf(pa.w);
+    T.irho = __builtin_amdgcn_rcpf(T.rho);
+    T.p = va.w;
+    T.vx = va.x;
+    T.vy = va.y;
+    T.vz = va.z;
+  }
+  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  bool todo = valid;
+  while (__ballot(todo) != 0ull) {
+    const uint64_t rem = __ballot(todo);
+    const int leader = (int)__builtin_ctzll(rem);
+    const int ry = __builtin_amdgcn_readlane(cy, leader);
+    const int rz = __builtin_amdgcn_readlane(cz, leader);
+    const bool inrow = todo && cy == ry && cz == rz;
+    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+      xmn = min(xmn, __shfl_xor(xmn, off, 64));
+      xmx = max(xmx, __shfl_xor(xmx, off, 64));
+    }
+    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
+    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
+    // the target in the wave frame (cell-relative offset moved to cell xmin)
+    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
+    const float ya = pa.y, za = pa.z;
+    // support radius test folded with the membership rules: lanes whose
+    // target is not in this row, and wall targets facing wall candidates,
+    // compare against -1
+    const float thr_any = inrow ? kp.support2_f : -1.f;
+    const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
+    // this lane's list: entry k at list[k][lane]; wp points past the last hit
+    // (an LDS-address-space pointer, so appends are single ds_write ops)
+    lds_u32* const lbase = (lds_u32*)&L.list[0][lane];
+    lds_u32* wp = lbase;
+    int ncs = 0;       // cell shifts in use (uniform)
+    auto drain = [&]() {
+      wave_sync();
+      const int cnt = (int)(wp - lbase) / 64;
+      int m = cnt;
+      for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+      m = __builtin_amdgcn_readfirstlane(m);
+      for (int k = 0; k < m; ++k) {
+        if (k < cnt) {
+          const uint32_t e = L.list[k][lane];
+          const uint32_t j = e & ((1u << kSgJBits) - 1u);
+          const float4 sh = L.shift[e >> kSgJBits];
+          const float4 pb = pr[j];
+          const float4 vb = vp[j];
+          const float dx = (xa - sh.x) - pb.x;
+          const float dy = (ya - sh.y) - pb.y;
+          const float dz = DIM == 3 ? (za - sh.z) - pb.z : 0.f;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
+        }
+      }
+      wave_sync();
+      wp = lbase;
+    };
+    const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      const int z = rz + dz;
+      if (z < 0 || z >= kp.ncz) continue;
+      for (int dy = -R; dy <= R; ++dy) {
+        const int y = ry + dy;
+        if (y < 0 || y >= kp.ncy) continue;
+        const int xlo = max(xmin - R, 0), xhi = min(xmax + R, kp.ncx - 1);
+        const uint32_t rowbase = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+        for (int x = xlo; x <= xhi; ++x) {
+          const uint32_t j0 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x]);
+          const uint32_t j1 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x + 1]);
+          if (j0 == j1) continue;
+          if (ncs == kSgCells) {
+            drain();
+            ncs = 0;
+          }
+          const float sx = (float)(x - xmin) * kp.cs_f, sy = (float)dy * kp.cs_f,
+                      sz = (float)dz * kp.cs_f;
+          if (lane == 0) L.shift[ncs] = make_float4(sx, sy, sz, 0.f);
+          const uint32_t tag = (uint32_t)ncs << kSgJBits;
+          ++ncs;
+          const float xs = xa - sx, ys = ya - sy, zs = za - sz;
+          // candidates in groups of 4 (one 64-B scalar load), the next group
+          // prefetched; the views are padded so a group may run past j1
+          float4 q0 = pr[j0], q1 = pr[j0 + 1], q2 = pr[j0 + 2], q3 = pr[j0 + 3];
+          for (uint32_t j = j0; j < j1; j += 4) {
+            const float4 c4[4] = {q0, q1, q2, q3};
+            if (j + 4 < j1) {
+              q0 = pr[j + 4];
+              q1 = pr[j + 5];
+              q2 = pr[j + 6];
+              q3 = pr[j + 7];
+            }
+            const uint32_t left = j1 - j;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if ((uint32_t)u < left) {
+                const float4 pb = c4[u];
+                const float dx = xs - pb.x, dy_ = ys - pb.y, dz_ = DIM == 3 ? zs - pb.z : 0.f;
+                const float r2 = dx * dx + dy_ * dy_ + dz_ * dz_;
+                // wall candidates count for fluid targets only (Eq. 36)
+                const float thr = __float_as_int(pb.w) > 0 ? thr_any : thr_fluid;
+                if (r2 < thr) {
+                  *wp = (j + u) | tag;
+                  wp += 64;
+                }
+              }
+            }
+            if (__ballot(wp > lbase + 64 * (kSgLCap - 4)) != 0ull) drain();
+          }
+        }
+      }
+    }
+    drain();
+    todo = todo && !inrow;
+  }
+  float fmag = 0.f, vmax_out = 0.f;
+  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
+  if (valid) {
+    // a fluid target finds itself among its hits (r = 0: every term is zero);
+    // it is not its own neighbour
+    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
+    write_target<DIM>(kp, n, a, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+    cnt_out = c;
+    cnt_wall = T.fluid ? 0u : c;
+  } else if (a < n) {
+    write_zero<DIM>(n, a, ace, arho, visc, nbr);
+  }
+  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
+}
+
+// ------------------------------------------- interaction: gather (simple) --
 // One lane per target particle (sorted order).  The lane walks the (2R+1)^d
 // cells around its own cell (R = cell_div), reads each candidate's view from
-// global memory, and accumulates in registers; sums are gathered per target,
-// so results are deterministic.
+// global memory and accumulates in registers.
 template <int DIM, int R>
 __global__ __launch_bounds__(kBlock) void k_interact_gather(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
     const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    uint32_t flags, BlockRed* __restrict__ red) {
+    uint32_t flags, BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   if (i < n) {
-    float acc[3] = {0.f, 0.f, 0.f};
-    float cont = 0.f, diff = 0.f, vmax = 0.f, rhoa = 0.f;
-    uint32_t c32 = 0, c64 = 0;
-    bool fa = false;
-    const bool active = !is_excluded(type[i]);
-    if (active) {
+    PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t c64 = 0;
+    if (!is_excluded(type[i])) {
       const float4 pa = pr[i], va = vp[i];
-      fa = pa.w > 0.f;
-      rhoa = fabsf(pa.w);
-      const float Pa = va.w;
+      T.fluid = pa.w > 0.f;
+      T.rho = fabsf(pa.w);
+      T.irho = __builtin_amdgcn_rcpf(T.rho);
+      T.p = va.w;
+      T.vx = va.x;
+      T.vy = va.y;
+      T.vz = va.z;
       const uint32_t k = key[i];
       const int cx = (int)(k % (uint32_t)kp.ncx);
       const uint32_t rest = k / (uint32_t)kp.ncx;
@@ -83,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
               if ((int64_t)j == i) continue;
               const float4 pb = pr[j];
               const bool fb = pb.w > 0.f;
-              if (!fa && !fb) continue;  // Eq. 36: walls see fluid only
+              if (!T.fluid && !fb) continue;  // Eq. 36: walls see fluid only
               const float dx = pa.x - (pb.x + sx);
               const float dy_ = pa.y - (pb.y + sy);
               const float dz_ = DIM == 3 ? pa.z - (pb.z + sz) : 0.f;
@@ -97,53 +685,33 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
                 c64 += (r2d < kp.support2) ? 1u : 0u;
               }
               if (!(r2 < kp.support2_f)) continue;
-              const float4 vb = vp[j];
-              const float rhob = fabsf(pb.w);
-              const float vr = (va.x - vb.x) * dx + (va.y - vb.y) * dy_ +
-                               (DIM == 3 ? (va.z - vb.z) * dz_ : 0.f);
-              const float q = sqrtf(r2) * kp.inv_h_f;
-              const float w = 1.f - 0.5f * q;
-              const float fab = kp.kfab_f * w * w * w;  // grad_a W_ab = fab r_ab
-              const float mb = fb ? kp.mass_f_f : kp.mass_b_f;
-              const float volb = mb / rhob;
-              cont += volb * fab * vr;
-              ++c32;
-              if (fa) {
-                const float pterm = (Pa + vb.w) / (rhoa * rhob);
-                const float mu = kp.h_f * vr / (r2 + kp.eta2_f);
-                const float pi = vr < 0.f ? -kp.visc_coef_f * mu / (0.5f * (rhoa + rhob)) : 0.f;
-                const float coef = mb * (pterm + pi) * fab;
-                acc[0] -= coef * dx;
-                acc[1] -= coef * dy_;
-                if (DIM == 3) acc[2] -= coef * dz_;
-                vmax = fmaxf(vmax, fabsf(mu));
-                if (fb) diff += (rhob - rhoa) * (-fab) * volb;
-              }
+              pair_terms<DIM>(kp, T, dx, dy_, dz_, r2, pb, vp[j], acc);
             }
           }
         }
       }
-    }
-    float ar = rhoa * cont;
-    if (active && fa) {
-      acc[0] += kp.gx_f;
-      acc[1] += kp.gy_f;
-      if (DIM == 3) acc[2] += kp.gz_f;
-      ar += kp.ddt_coef_f * diff;
-      fmag = sqrtf(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
-      vmax_out = vmax;
-      nfl = 1;
+      const uint32_t c = diag ? c64 : acc.cnt;
+      write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+      cnt_out = acc.cnt;
+      cnt_wall = T.fluid ? 0u : acc.cnt;
     } else {
-      acc[0] = acc[1] = acc[2] = 0.f;
+      write_zero<DIM>(n, i, ace, arho, visc, nbr);
     }
-    for (int d = 0; d < DIM; ++d) ace[d * n + i] = acc[d];
-    arho[i] = ar;
-    if (visc) visc[i] = vmax;
-    if (nbr) nbr[i] = (flags & SPH_DIAG_COUNT_F64) ? c64 : c32;
-    cnt_out = c32;
-    cnt_wall = (active && !fa) ? c32 : 0u;
   }
-  write_block_red(fmag, vmax_out, cnt_out, cnt_wall, nfl, red);
+  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
+}
+
+// Kernel choice: SPH_INTERACT_KERNEL = gather | tile | compact | sgpr (default
+// sgpr) for comparisons; the FP64 diagnostic count always uses gather.
+enum { kKGather = 0, kKTile = 1, kKCompact = 2, kKSgpr = 3 };
+static int kernel_choice(uint32_t flags, int64_t n) {
+  if (flags & SPH_DIAG_COUNT_F64) return kKGather;
+  const char* e = getenv("SPH_INTERACT_KERNEL");
+  if (e && e[0] == 'g') return kKGather;
+  if (e && e[0] == 't') return kKTile;
+  if (e && e[0] == 'c') return kKCompact;
+  // the scalar-stream kernel packs the particle index in kSgJBits bits
+  return n < ((int64_t)1 << kSgJBits) ? kKSgpr : kKGather;
 }
 
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
@@ -153,16 +721,56 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   const float4* pr = ws_ptr<float4>(ws, L.view_pr);
   const float4* vp = ws_ptr<float4>(ws, L.view_vp);
   BlockRed* red = ws_ptr<BlockRed>(ws, L.red);
-  const unsigned grid = (unsigned)L.nblk_interact;
+  WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
+  const int choice = kernel_choice(flags, n);
+  if (choice == kKSgpr) {
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
 #define SPH_LAUNCH(D, RR)                                                                      \
-  hipLaunchKernelGGL((k_interact_gather<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
-                     key, cell_start, s.type, s.pos, ace, arho, visc, nbr, flags, red)
-  if (kp.dim == 2) {
-    if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
-  } else {
-    if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
-  }
+  hipLaunchKernelGGL((k_interact_sgpr<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
+                     key, cell_start, ace, arho, visc, nbr, red, hdr)
+    if (kp.dim == 2) {
+      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+    } else {
+      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+    }
 #undef SPH_LAUNCH
+  } else if (choice == kKCompact) {
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
+#define SPH_LAUNCH(D, RR)                                                                         \
+  hipLaunchKernelGGL((k_interact_compact<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
+                     key, cell_start, ace, arho, visc, nbr, red, hdr)
+    if (kp.dim == 2) {
+      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+    } else {
+      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+    }
+#undef SPH_LAUNCH
+  } else if (choice == kKGather) {
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
+#define SPH_LAUNCH(D, RR)                                                                        \
+  hipLaunchKernelGGL((k_interact_gather<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
+                     key, cell_start, s.type, s.pos, ace, arho, visc, nbr, flags, red, hdr)
+    if (kp.dim == 2) {
+      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+    } else {
+      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+    }
+#undef SPH_LAUNCH
+  } else {
+    const unsigned grid = (unsigned)L.nblk_interact;
+#define SPH_LAUNCH(D, RR)                                                                        \
+  hipLaunchKernelGGL((k_interact_tile<D, RR>), dim3(grid), dim3(64 * kTileWaves), 0, st, kp, n, \
+                     pr, vp, key, cell_start, ace, arho, visc, nbr, red, hdr)
+    if (kp.dim == 2) {
+      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+    } else {
+      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+    }
+#undef SPH_LAUNCH
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kSortItems = 8;      // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kScanTile = kBlock * 8;
+constexpr int kTileTargets = 32;   // targets per block of the tiled interaction
+constexpr int kViewPad = 8;        // spare float4 entries after each interaction view
 
 // Per-launch constants derived once on the host from sph_params.
 struct KParams {
@@ -43,9 +45,16 @@ struct BlockRed {
   uint32_t pad;
 };
 
+// Fixed header at offset 0 of the workspace.
+struct WsHeader {
+  uint32_t err;      // SPH_ERR_* bits
+  uint32_t nred;     // BlockRed entries written by the last interaction pass
+  uint32_t pad[62];
+};
+
 // Workspace layout (offsets in bytes, each region 256-aligned).
 struct WsLayout {
-  size_t err;        // uint32 error word (offset 0)
+  size_t err;        // the WsHeader (offset 0)
   size_t keyA, valA, keyB, valB;   // radix sort ping-pong buffers, n each
   size_t hist;       // uint32 [bins * nblk_sort] digit counts / offsets
   size_t scan_part;  // uint32 partial sums of the offset scan
@@ -63,20 +72,24 @@ inline WsLayout ws_layout(int64_t n) {
   const size_t nn = (size_t)(n > 0 ? n : 1);
   L.nblk_sort = (n + kSortTile - 1) / kSortTile;
   if (L.nblk_sort < 1) L.nblk_sort = 1;
-  L.nblk_interact = (n + kBlock - 1) / kBlock;
+  // the smallest interaction tile (kTileTargets targets per block) bounds the
+  // number of per-block partial results
+  L.nblk_interact = (n + kTileTargets - 1) / kTileTargets;
   if (L.nblk_interact < 1) L.nblk_interact = 1;
   L.hist_len = 256 * L.nblk_sort;
   L.scan_parts = (L.hist_len + kScanTile - 1) / kScanTile;
   size_t off = 0;
-  L.err = off; off = align_up(off + 256);
+  L.err = off; off = align_up(off + sizeof(WsHeader));
   L.keyA = off; off = align_up(off + 4 * nn);
   L.valA = off; off = align_up(off + 4 * nn);
   L.keyB = off; off = align_up(off + 4 * nn);
   L.valB = off; off = align_up(off + 4 * nn);
   L.hist = off; off = align_up(off + 4 * (size_t)L.hist_len);
   L.scan_part = off; off = align_up(off + 4 * (size_t)L.scan_parts + 4);
-  L.view_pr = off; off = align_up(off + 16 * nn);
-  L.view_vp = off; off = align_up(off + 16 * nn);
+  // the views carry kViewPad spare entries: the interaction reads candidates
+  // in groups of 4 with scalar loads that may run past the last particle
+  L.view_pr = off; off = align_up(off + 16 * (nn + kViewPad));
+  L.view_vp = off; off = align_up(off + 16 * (nn + kViewPad));
   L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
   L.total = off;
   return L;

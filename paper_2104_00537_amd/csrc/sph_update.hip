@@ -6,9 +6,11 @@
 namespace sph {
 
 // Eq. 35 from the per-block partials of the last interaction pass; one block.
-__global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red, int64_t nblk,
-                            double* __restrict__ dt, uint64_t* __restrict__ inter,
-                            float* __restrict__ maxima, uint32_t* __restrict__ err) {
+__global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red,
+                            WsHeader* __restrict__ hdr, double* __restrict__ dt,
+                            uint64_t* __restrict__ inter, float* __restrict__ maxima) {
+  uint32_t* err = &hdr->err;
+  const int64_t nblk = hdr->nred;
   __shared__ float sf[kBlock / 64], sv[kBlock / 64];
   __shared__ unsigned long long sc[kBlock / 64], sw[kBlock / 64], sn[kBlock / 64];
   float fmax = 0.f, vmax = 0.f;
@@ -142,7 +144,7 @@ hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* 
                             float* maxima, void* ws, hipStream_t st) {
   const WsLayout L = ws_layout(n);
   hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(kBlock), 0, st, kp, ws_ptr<BlockRed>(ws, L.red),
-                     L.nblk_interact, dt, interactions, maxima, ws_ptr<uint32_t>(ws, L.err));
+                     ws_ptr<WsHeader>(ws, L.err), dt, interactions, maxima);
   return hipGetLastError();
 }
 
