@@ -87,6 +87,37 @@ def cpu_baseline(case, sim, seconds):
                       f"(all {n} as candidate neighbours, brute force FP64), {el:.1f} s"}
 
 
+def serving(args):
+    """The request stream through the batched engine and the plain
+    one-case-at-a-time path (same seeded trace, same GPU)."""
+    import torch
+    from paper_2104_00537_amd import serve as V
+    kw = dict(n_min=args.serve_n_min, n_max=args.serve_n_max, steps_min=1000, steps_max=5000,
+              steps_scale=args.serve_steps_scale)
+    out = {"stream": dict(requests=args.serve_requests, rate_per_s=args.serve_rate,
+                          n_range=[args.serve_n_min, args.serve_n_max],
+                          steps="uniform 1000-5000 x %g" % args.serve_steps_scale, seed=7)}
+    reqs = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
+    out["stream"]["particles_mean"] = float(np.mean([r.n for r in reqs]))
+    out["stream"]["steps_mean"] = float(np.mean([r.steps for r in reqs]))
+    cap_n = max(4 * max(r.n for r in reqs), args.serve_cap_particles)
+    eng = V.BatchEngine(cap_particles=cap_n, cap_cells=args.serve_cap_cells,
+                        max_slots=args.serve_slots, device="cuda:0")
+    # warm-up of the code paths (first kernel launches, graph capture)
+    warm = V.make_stream(2, 1e6, seed=99, n_min=2000, n_max=3000, steps_min=4, steps_max=4)
+    V.serve_batched(warm, eng)
+    V.serve_plain(V.make_stream(1, 1e6, seed=98, n_min=2000, n_max=3000, steps_min=4,
+                                steps_max=4))
+    torch.cuda.synchronize()
+    out["batched"] = V.serve_batched(reqs, eng)
+    reqs2 = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
+    out["plain"] = V.serve_plain(reqs2)
+    out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
+    out["p50_ratio_plain_over_batched"] = out["plain"]["p50_latency_s"] / out["batched"]["p50_latency_s"]
+    out["p99_ratio_plain_over_batched"] = out["plain"]["p99_latency_s"] / out["batched"]["p99_latency_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +127,15 @@ def main():
     ap.add_argument("--cell-div", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-steps-scale", type=float, default=0.2)
+    ap.add_argument("--serve-n-min", type=int, default=2000)
+    ap.add_argument("--serve-n-max", type=int, default=500_000)
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-cap-particles", type=int, default=6_000_000)
+    ap.add_argument("--serve-cap-cells", type=int, default=40_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -163,6 +203,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
+    if not args.no_serve:
+        del sim
+        torch.cuda.empty_cache()
+        res["serving"] = serving(args)
     print(json.dumps(res), flush=True)
     return 0
 

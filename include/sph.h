@@ -191,6 +191,76 @@ sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase,
                                const float* arho, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* ---------------------------------------------------------------- batches --
+ * Continuous batching: n_slots independent cases packed into one set of
+ * arrays advance together through the calls below, each case ("slot") with
+ * its own constants, dt and t.  Slot s owns particles [offsets[s],
+ * offsets[s+1]) of the packed arrays and the cell keys [cbase_s, cbase_s +
+ * C_s] (C_s = its total cells; the last key is for its particles outside its
+ * grid), with cbase_s the sum of C + 1 over the slots before it.  So one
+ * radix sort, one set of cell ranges, one interaction launch and one update
+ * serve every case, and every slot keeps its particle range through every
+ * sort; results of a case do not depend on the other cases in the batch.
+ * Packed arrays always have three components: a 2-D case (x, z) is stored as
+ * (x, 0, z) and gets one cell across y.  All slots share cell_div; at most
+ * 2^27 - 1 particles in total.
+ */
+#define SPH_BATCH_MAX_SLOTS 4096
+
+typedef struct sph_batch {
+  int32_t n_slots;
+  int32_t cell_div;
+  int64_t n_total;      /* offsets[n_slots] */
+  int64_t key_cells;    /* sum over slots of (cells + 1): cell_start has
+                           key_cells + 1 entries */
+  const void* table;    /* DEVICE copy of the slot table (see below) */
+} sph_batch;
+
+/* Bytes of the slot table for n_slots cases. */
+size_t sph_batch_table_bytes(int32_t n_slots);
+
+/* Host only (no device call): writes the slot table of the cases params[s]
+ * with particle ranges offsets[0..n_slots] (offsets[0] = 0, non-decreasing)
+ * to table_host and fills *batch except batch->table.  The caller copies the
+ * table to device memory and sets batch->table before the calls below.  The
+ * table stays valid while the slots keep their ranges. */
+sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
+                              void* table_host, size_t table_bytes, sph_batch* batch);
+
+/* Bytes of workspace for a batch (the single-case workspace of n_total
+ * particles plus per-slot accumulators, motion and error words). */
+size_t sph_batch_workspace_bytes(const sph_batch* b);
+
+/* As sph_bin_cells, over all slots (keys offset per slot, see above). */
+sph_status sph_batch_bin_cells(const sph_batch* b, const sph_state* in, sph_state* out,
+                               const sph_state* carry_in, sph_state* carry_out, uint32_t* key,
+                               uint32_t* perm, uint32_t* cell_start, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* As sph_interact, over all slots in one launch (ace is [3][n_total]);
+ * per-slot maxima and pair counts go to the workspace. */
+sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint32_t* key,
+                              const uint32_t* cell_start, float* ace, float* arho, float* visc,
+                              uint32_t* nbr_count, void* ws, size_t ws_bytes, void* stream);
+
+/* Eq. 35 per slot: dt[n_slots] out (device); interactions[n_slots][2]
+ * in/out, nullable: each slot's pair count and wall-target count are added. */
+sph_status sph_batch_reduce_dt(const sph_batch* b, double* dt, uint64_t* interactions, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* As sph_symplectic_step with per-slot dt[n_slots] and t[n_slots] (device). */
+sph_status sph_batch_symplectic_step(const sph_batch* b, int32_t phase, const double* dt,
+                                     double* t, sph_state* saved, sph_state* s, const float* ace,
+                                     const float* arho, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-slot error words (SPH_ERR_* bits) to host slot_errors[n_slots], after
+ * synchronising the device; the workspace's global error word (read with
+ * sph_read_error) holds their union. */
+sph_status sph_batch_read_errors(const sph_batch* b, const void* ws, uint32_t* slot_errors);
+
+/* Enqueues clearing of the global and the per-slot error words. */
+sph_status sph_batch_clear_errors(const sph_batch* b, void* ws, void* stream);
+
 /* Reads the device error word (SPH_ERR_* bits) of a workspace.  Synchronises
  * the device.  Returns a negative sph_status on failure. */
 int32_t sph_read_error(const void* ws);

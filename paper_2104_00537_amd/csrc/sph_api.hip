@@ -56,6 +56,29 @@ KParams make_kparams(const sph_params& p) {
   return k;
 }
 
+// The constants of a case in the batch's 3-D layout: a 2-D case (x, z) is
+// stored as (x, 0, z) with a single cell across y centred on y = 0; its kernel
+// normalisation stays the 2-D one.
+KParams make_slot_kparams(const sph_params& p) {
+  KParams k = make_kparams(p);
+  if (p.dim == 2) {
+    k.dim = 3;
+    k.ncx = p.ncell[0];
+    k.ncy = 1;
+    k.ncz = p.ncell[1];
+    k.ox = p.origin[0];
+    k.oy = -0.5 * p.cell_size;
+    k.oz = p.origin[1];
+    k.gx = p.gravity[0];
+    k.gy = 0.0;
+    k.gz = p.gravity[1];
+    k.gx_f = (float)k.gx;
+    k.gy_f = 0.f;
+    k.gz_f = (float)k.gz;
+  }
+  return k;
+}
+
 static bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
@@ -158,6 +181,122 @@ int32_t sph_read_error(const void* ws) {
 sph_status sph_clear_error(void* ws, void* stream) {
   if (!ws) return SPH_E_ARG;
   return hip_status(launch_clear_error(ws, (hipStream_t)stream));
+}
+
+// ---------------------------------------------------------------- batches --
+static bool batch_ok(const sph_batch* b) {
+  return b && b->n_slots >= 1 && b->n_slots <= SPH_BATCH_MAX_SLOTS && b->table &&
+         (b->cell_div == 1 || b->cell_div == 2) && b->n_total >= 0 &&
+         b->n_total < ((int64_t)1 << 27) && b->key_cells >= 1 &&
+         b->key_cells < (int64_t)0xfffffff0ll;
+}
+
+static BatchDesc batch_desc(const sph_batch* b) {
+  return BatchDesc{b->n_slots, b->cell_div, b->n_total, b->key_cells, b->table};
+}
+
+size_t sph_batch_table_bytes(int32_t n_slots) {
+  if (n_slots < 1 || n_slots > SPH_BATCH_MAX_SLOTS) return 0;
+  return sizeof(SlotEntry) * (size_t)n_slots;
+}
+
+sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
+                              void* table_host, size_t table_bytes, sph_batch* batch) {
+  if (!params || !offsets || !table_host || !batch) return SPH_E_ARG;
+  if (n_slots < 1 || n_slots > SPH_BATCH_MAX_SLOTS) return SPH_E_ARG;
+  if (table_bytes < sph_batch_table_bytes(n_slots)) return SPH_E_ARG;
+  if (offsets[0] != 0) return SPH_E_ARG;
+  SlotEntry* tab = (SlotEntry*)table_host;
+  uint64_t cbase = 0;
+  for (int s = 0; s < n_slots; ++s) {
+    const sph_params* p = &params[s];
+    if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
+    if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
+    SlotEntry e{};
+    e.kp = make_slot_kparams(*p);
+    e.cbase = (uint32_t)cbase;
+    e.off = offsets[s];
+    e.n = offsets[s + 1] - offsets[s];
+    tab[s] = e;
+    cbase += (uint64_t)e.kp.ncell_total + 1;
+    if (cbase >= 0xfffffff0ull) return SPH_E_ARG;
+  }
+  if (offsets[n_slots] >= ((int64_t)1 << 27)) return SPH_E_ARG;
+  batch->n_slots = n_slots;
+  batch->cell_div = params[0].cell_div;
+  batch->n_total = offsets[n_slots];
+  batch->key_cells = (int64_t)cbase;
+  batch->table = nullptr;
+  return SPH_OK;
+}
+
+size_t sph_batch_workspace_bytes(const sph_batch* b) {
+  if (!b || b->n_slots < 1 || b->n_total < 0) return 0;
+  return batch_ws_layout(b->n_slots, b->n_total).total;
+}
+
+sph_status sph_batch_bin_cells(const sph_batch* b, const sph_state* in, sph_state* out,
+                               const sph_state* carry_in, sph_state* carry_out, uint32_t* key,
+                               uint32_t* perm, uint32_t* cell_start, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (!batch_ok(b) || !cell_start || !ws) return SPH_E_ARG;
+  const int64_t n = b->n_total;
+  if (n > 0 && (!state_ok(in, true) || !state_ok(out, true) || !key || !perm)) return SPH_E_ARG;
+  if (n > 0 && in->pos == out->pos) return SPH_E_ARG;
+  if ((carry_in == nullptr) != (carry_out == nullptr)) return SPH_E_ARG;
+  if (carry_in && n > 0 && (!state_ok(carry_in, false) || !state_ok(carry_out, false)))
+    return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, n).total) return SPH_E_WORKSPACE;
+  sph_state i0 = n > 0 ? *in : sph_state{}, o0 = n > 0 ? *out : sph_state{};
+  return hip_status(launch_batch_bin_cells(batch_desc(b), i0, o0, carry_in, carry_out, key, perm,
+                                           cell_start, ws, (hipStream_t)stream));
+}
+
+sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint32_t* key,
+                              const uint32_t* cell_start, float* ace, float* arho, float* visc,
+                              uint32_t* nbr_count, void* ws, size_t ws_bytes, void* stream) {
+  if (!batch_ok(b) || !cell_start || !ws) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
+  return hip_status(launch_batch_interact(batch_desc(b), key, cell_start, ace, arho, visc,
+                                          nbr_count, ws, (hipStream_t)stream));
+}
+
+sph_status sph_batch_reduce_dt(const sph_batch* b, double* dt, uint64_t* interactions, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!batch_ok(b) || !dt || !ws) return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
+  return hip_status(
+      launch_batch_reduce_dt(batch_desc(b), dt, interactions, ws, (hipStream_t)stream));
+}
+
+sph_status sph_batch_symplectic_step(const sph_batch* b, int32_t phase, const double* dt,
+                                     double* t, sph_state* saved, sph_state* s, const float* ace,
+                                     const float* arho, void* ws, size_t ws_bytes, void* stream) {
+  if (!batch_ok(b) || !dt || !t || !ws) return SPH_E_ARG;
+  if (phase != 0 && phase != 1) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !state_ok(saved, false) || !ace || !arho))
+    return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
+  sph_state sv = b->n_total > 0 ? *saved : sph_state{}, st = b->n_total > 0 ? *s : sph_state{};
+  return hip_status(launch_batch_symplectic(batch_desc(b), phase, dt, t, sv, st, ace, arho, ws,
+                                            (hipStream_t)stream));
+}
+
+sph_status sph_batch_read_errors(const sph_batch* b, const void* ws, uint32_t* slot_errors) {
+  if (!b || b->n_slots < 1 || b->n_slots > SPH_BATCH_MAX_SLOTS || !ws || !slot_errors)
+    return SPH_E_ARG;
+  const BatchWsLayout W = batch_ws_layout(b->n_slots, b->n_total);
+  if (hipDeviceSynchronize() != hipSuccess) return SPH_E_HIP;
+  if (hipMemcpy(slot_errors, (const char*)ws + W.slot_err, sizeof(uint32_t) * b->n_slots,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return SPH_E_HIP;
+  return SPH_OK;
+}
+
+sph_status sph_batch_clear_errors(const sph_batch* b, void* ws, void* stream) {
+  if (!b || b->n_slots < 1 || b->n_slots > SPH_BATCH_MAX_SLOTS || !ws) return SPH_E_ARG;
+  return hip_status(launch_batch_clear_errors(batch_desc(b), ws, (hipStream_t)stream));
 }
 
 const char* sph_strerror(sph_status s) {

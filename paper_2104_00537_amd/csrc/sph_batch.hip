@@ -1,0 +1,334 @@
+// Batched cases (continuous batching): n_slots independent cases packed into
+// one set of arrays.  Slot s owns particles [off_s, off_s + n_s) and cell keys
+// [cbase_s, cbase_s + ncell_s] (the last one for its particles outside its
+// grid), so one radix sort, one set of cell ranges, one interaction launch
+// and one update serve every case with its own constants, dt and t, and
+// every slot keeps its particle range through every sort.
+#include "sph_dev.h"
+#include "sph_kernels.h"
+#include "sph_pair.h"
+
+namespace sph {
+
+// The slot owning packed particle i: the last slot with off <= i (slots are
+// in particle order; an empty slot shares its offset with the next one).
+__device__ inline int find_slot(const SlotEntry* __restrict__ tab, int ns, int64_t i) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].off <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_batch_cell_keys(const SlotEntry* __restrict__ tab, int ns, int64_t n,
+                                  const double* __restrict__ pos, const uint8_t* __restrict__ type,
+                                  uint32_t* __restrict__ key, SlotAccum* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
+  if (i >= n) return;
+  const int s = find_slot(tab, ns, i);
+  key[i] = tab[s].cbase + cell_key_local(tab[s].kp, pos, type, n, i);
+}
+
+__global__ void k_batch_reorder(const SlotEntry* __restrict__ tab, int ns, int64_t n,
+                                const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+                                sph_state in, sph_state out, sph_state cin, sph_state cout,
+                                int carry, float4* __restrict__ pr, float4* __restrict__ vp,
+                                uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = find_slot(tab, ns, i);
+  if (reorder_one(tab[s].kp, n, i, perm[i], key[i] - tab[s].cbase, in, out, cin, cout, carry, pr,
+                  vp)) {
+    set_error(err, SPH_ERR_EXCLUDED);
+    set_error(&slot_err[s], SPH_ERR_EXCLUDED);
+  }
+}
+
+// The scalar-stream interaction over all slots: as k_interact_sgpr, with the
+// row loop also splitting a wave's targets by slot and each row using its
+// slot's constants.  Per-slot maxima and pair counts are combined with
+// order-independent atomics (max of non-negative float bits, integer adds).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_batch_interact(
+    const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
+    const float4* __restrict__ vp, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
+    float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc) {
+  __shared__ SgLds lds_all[kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  SgLds& L = lds_all[wv];
+  const int64_t a = ((int64_t)blockIdx.x * (kBlock / 64) + wv) * 64 + lane;
+  int sa = -1;
+  bool valid = false;
+  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
+  int cx = 0, cy = 0, cz = 0;
+  if (a < n) {
+    sa = find_slot(tab, ns, a);
+    const uint32_t lk = key[a] - tab[sa].cbase;
+    const int ncx = tab[sa].kp.ncx, ncy = tab[sa].kp.ncy;
+    valid = lk < tab[sa].kp.ncell_total;
+    if (valid) {
+      pa = pr[a];
+      const float4 va = vp[a];
+      cx = (int)(lk % (uint32_t)ncx);
+      const uint32_t rest = lk / (uint32_t)ncx;
+      cy = (int)(rest % (uint32_t)ncy);
+      cz = (int)(rest / (uint32_t)ncy);
+      T.fluid = pa.w > 0.f;
+      T.rho = fabsf(pa.w);
+      T.irho = __builtin_amdgcn_rcpf(T.rho);
+      T.p = va.w;
+      T.vx = va.x;
+      T.vy = va.y;
+      T.vz = va.z;
+    }
+  }
+  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  float gx = 0.f, gy = 0.f, gz = 0.f, ddt = 0.f;
+  bool todo = valid;
+  while (__ballot(todo) != 0ull) {
+    const uint64_t rem = __ballot(todo);
+    const int leader = (int)__builtin_ctzll(rem);
+    const int rs = __builtin_amdgcn_readlane(sa, leader);
+    const int ry = __builtin_amdgcn_readlane(cy, leader);
+    const int rz = __builtin_amdgcn_readlane(cz, leader);
+    const bool inrow = todo && sa == rs && cy == ry && cz == rz;
+    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
+    for (int off = 32; off > 0; off >>= 1) {
+      xmn = min(xmn, __shfl_xor(xmn, off, 64));
+      xmx = max(xmx, __shfl_xor(xmx, off, 64));
+    }
+    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
+    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
+    const KParams kp = tab[rs].kp;
+    const uint32_t cbase = tab[rs].cbase;
+    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
+    const float thr_any = inrow ? kp.support2_f : -1.f;
+    const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
+    if (inrow) {
+      gx = kp.gx_f;
+      gy = kp.gy_f;
+      gz = kp.gz_f;
+      ddt = kp.ddt_coef_f;
+    }
+    sgpr_row<3, R>(kp, cbase, ry, rz, xmin, xmax, xa, pa.y, pa.z, thr_any, thr_fluid, T, L, lane,
+                   pr, vp, cstart, acc);
+    todo = todo && !inrow;
+  }
+  float fmag = 0.f, vmx = 0.f;
+  uint32_t cnt = 0, cntw = 0, nfl = 0;
+  if (valid) {
+    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);  // the target is not its own neighbour
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    float ar = T.rho * acc.cont;
+    if (T.fluid) {
+      ax = acc.ax + gx;
+      ay = acc.ay + gy;
+      az = acc.az + gz;
+      ar += ddt * acc.diff;
+      fmag = sqrtf(ax * ax + ay * ay + az * az);
+      vmx = acc.vmax;
+      nfl = 1;
+    }
+    ace[a] = ax;
+    ace[n + a] = ay;
+    ace[2 * n + a] = az;
+    arho[a] = ar;
+    if (visc) visc[a] = acc.vmax;
+    if (nbr) nbr[a] = c;
+    cnt = c;
+    cntw = T.fluid ? 0u : c;
+  } else if (a < n) {
+    write_zero<3>(n, a, ace, arho, visc, nbr);
+  }
+  // per-slot combination: one pass per distinct slot among the wave's lanes
+  bool pend = a < n;
+  while (__ballot(pend) != 0ull) {
+    const int leader = (int)__builtin_ctzll(__ballot(pend));
+    const int rs = __builtin_amdgcn_readlane(sa, leader);
+    const bool mine = pend && sa == rs;
+    float f = mine ? fmag : 0.f, v = mine ? vmx : 0.f;
+    uint32_t c = mine ? cnt : 0u, w = mine ? cntw : 0u, k = mine ? nfl : 0u;
+    f = wave_max(f);
+    v = wave_max(v);
+    c = wave_sum(c);
+    w = wave_sum(w);
+    k = wave_sum(k);
+    if (lane == leader) {
+      SlotAccum* A = &sacc[rs];
+      atomicMax(&A->fmax_bits, __float_as_uint(f));
+      atomicMax(&A->vmax_bits, __float_as_uint(v));
+      atomicAdd(&A->nfluid, k);
+      atomicAdd(&A->count, (unsigned long long)c);
+      atomicAdd(&A->count_wall, (unsigned long long)w);
+    }
+    pend = pend && !mine;
+  }
+}
+
+// Eq. 35 per slot.
+__global__ void k_batch_reduce_dt(const SlotEntry* __restrict__ tab, int ns,
+                                  const SlotAccum* __restrict__ sacc, double* __restrict__ dt,
+                                  uint64_t* __restrict__ inter, uint32_t* __restrict__ err,
+                                  uint32_t* __restrict__ slot_err) {
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    const KParams& kp = tab[s].kp;
+    const SlotAccum A = sacc[s];
+    const double f = (double)__uint_as_float(A.fmax_bits);
+    const double v = (double)__uint_as_float(A.vmax_bits);
+    double d = INFINITY;
+    if (A.nfluid > 0) {
+      const double dtf = f > 0.0 ? sqrt(kp.h / f) : INFINITY;
+      const double dtcv = kp.h / (kp.c0 + v);
+      d = kp.cfl * (dtf < dtcv ? dtf : dtcv);
+    }
+    dt[s] = d;
+    if (!(d >= kp.dt_floor) || !isfinite(d)) {
+      set_error(err, SPH_ERR_DT_FLOOR);
+      set_error(&slot_err[s], SPH_ERR_DT_FLOOR);
+    }
+    if (inter) {
+      inter[2 * s] += (uint64_t)A.count;
+      inter[2 * s + 1] += (uint64_t)A.count_wall;
+    }
+  }
+}
+
+template <int PHASE>
+__global__ void k_batch_motion(const SlotEntry* __restrict__ tab, int ns,
+                               const double* __restrict__ dt, const double* __restrict__ t,
+                               SlotMotion* __restrict__ mot) {
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    const KParams& kp = tab[s].kp;
+    const double d = dt[s], t0 = t[s];
+    const double t1 = PHASE == 0 ? t0 + 0.5 * d : t0 + d;
+    mot[s] = SlotMotion{d, motion_disp(kp, t1) - motion_disp(kp, t0), motion_vel(kp, t1), 0.0};
+  }
+}
+
+template <int PHASE>
+__global__ void k_batch_symplectic(const SlotEntry* __restrict__ tab, int ns, int64_t n,
+                                   const SlotMotion* __restrict__ mot, sph_state saved,
+                                   sph_state s, const float* __restrict__ ace,
+                                   const float* __restrict__ arho, uint32_t* __restrict__ err,
+                                   uint32_t* __restrict__ slot_err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int sl = find_slot(tab, ns, i);
+  const SlotMotion M = mot[sl];
+  if (symplectic_one<PHASE>(tab[sl].kp, n, i, M.dt, M.dmove, M.vmove, saved, s, ace, arho)) {
+    set_error(err, SPH_ERR_NONFINITE);
+    set_error(&slot_err[sl], SPH_ERR_NONFINITE);
+  }
+}
+
+__global__ void k_batch_advance(int ns, const double* __restrict__ dt, double* __restrict__ t) {
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) t[s] = t[s] + dt[s];
+}
+
+__global__ void k_batch_clear_errors(int ns, uint32_t* __restrict__ err,
+                                     uint32_t* __restrict__ slot_err) {
+  if (threadIdx.x == 0) *err = 0u;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) slot_err[s] = 0u;
+}
+
+// ------------------------------------------------------------------ host --
+static unsigned grid_for(int64_t n) {
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_state& out,
+                                  const sph_state* cin, sph_state* cout, uint32_t* key,
+                                  uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st) {
+  const int64_t n = B.n_total;
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
+  const SlotEntry* tab = (const SlotEntry*)B.table;
+  SlotAccum* sacc = ws_ptr<SlotAccum>(ws, W.accum);
+  const int64_t nk = n > B.n_slots ? n : B.n_slots;
+  hipLaunchKernelGGL(k_batch_cell_keys, dim3(grid_for(nk)), dim3(kBlock), 0, st, tab, B.n_slots,
+                     n, in.pos, in.type, ws_ptr<uint32_t>(ws, W.base.keyA), sacc);
+  const uint32_t last_key = (uint32_t)(B.key_cells - 1);
+  if (n > 0) {
+    const hipError_t e = radix_sort(n, last_key, key, perm, ws, st);
+    if (e != hipSuccess) return e;
+  }
+  launch_cell_start(key, n, last_key + 1, cell_start, st);
+  if (n > 0) {
+    sph_state ci{}, co{};
+    const int carry = (cin && cout) ? 1 : 0;
+    if (carry) {
+      ci = *cin;
+      co = *cout;
+    }
+    hipLaunchKernelGGL(k_batch_reorder, dim3(grid_for(n)), dim3(kBlock), 0, st, tab, B.n_slots, n,
+                       perm, key, in, out, ci, co, carry, ws_ptr<float4>(ws, W.base.view_pr),
+                       ws_ptr<float4>(ws, W.base.view_vp), ws_ptr<uint32_t>(ws, W.base.err),
+                       ws_ptr<uint32_t>(ws, W.slot_err));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
+                                 const uint32_t* cell_start, float* ace, float* arho, float* visc,
+                                 uint32_t* nbr, void* ws, hipStream_t st) {
+  const int64_t n = B.n_total;
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
+  const SlotEntry* tab = (const SlotEntry*)B.table;
+  const unsigned grid = grid_for(n);
+  if (B.cell_div == 1)
+    hipLaunchKernelGGL(k_batch_interact<1>, dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n,
+                       ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key,
+                       cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum));
+  else
+    hipLaunchKernelGGL(k_batch_interact<2>, dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n,
+                       ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key,
+                       cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce_dt(const BatchDesc& B, double* dt, uint64_t* interactions, void* ws,
+                                  hipStream_t st) {
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, B.n_total);
+  hipLaunchKernelGGL(k_batch_reduce_dt, dim3(1), dim3(kBlock), 0, st,
+                     (const SlotEntry*)B.table, B.n_slots, ws_ptr<SlotAccum>(ws, W.accum), dt,
+                     interactions, ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* dt, double* t,
+                                   sph_state& saved, sph_state& s, const float* ace,
+                                   const float* arho, void* ws, hipStream_t st) {
+  const int64_t n = B.n_total;
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
+  const SlotEntry* tab = (const SlotEntry*)B.table;
+  SlotMotion* mot = ws_ptr<SlotMotion>(ws, W.motion);
+  uint32_t* err = ws_ptr<uint32_t>(ws, W.base.err);
+  uint32_t* serr = ws_ptr<uint32_t>(ws, W.slot_err);
+  if (phase == 0) {
+    hipLaunchKernelGGL(k_batch_motion<0>, dim3(1), dim3(kBlock), 0, st, tab, B.n_slots, dt, t, mot);
+    if (n > 0)
+      hipLaunchKernelGGL(k_batch_symplectic<0>, dim3(grid_for(n)), dim3(kBlock), 0, st, tab,
+                         B.n_slots, n, mot, saved, s, ace, arho, err, serr);
+  } else {
+    hipLaunchKernelGGL(k_batch_motion<1>, dim3(1), dim3(kBlock), 0, st, tab, B.n_slots, dt, t, mot);
+    if (n > 0)
+      hipLaunchKernelGGL(k_batch_symplectic<1>, dim3(grid_for(n)), dim3(kBlock), 0, st, tab,
+                         B.n_slots, n, mot, saved, s, ace, arho, err, serr);
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(kBlock), 0, st, B.n_slots, dt, t);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_clear_errors(const BatchDesc& B, void* ws, hipStream_t st) {
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, B.n_total);
+  hipLaunchKernelGGL(k_batch_clear_errors, dim3(1), dim3(kBlock), 0, st, B.n_slots,
+                     ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err));
+  return hipGetLastError();
+}
+
+}  // namespace sph

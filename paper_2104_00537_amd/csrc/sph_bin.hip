@@ -1,35 +1,17 @@
 // Neighbour list (Section 5.1 of the DualSPHysics v5.0 paper): cell keys,
 // an in-house stable LSD radix sort in LDS, cell ranges and the reorder of
 // the particle state into sorted structure-of-arrays.
+#include "sph_dev.h"
 #include "sph_kernels.h"
 
 namespace sph {
 
 // -------------------------------------------------------------- cell keys --
-// Cell index per axis = floor((x - origin) * inv_cs): one FP64 subtraction and
-// one FP64 multiplication (no contraction is possible), x fastest.  Outside
-// the grid, and for particles excluded earlier, the key is ncell_total, so
-// they sort last and lie in no cell range.
 __global__ void k_cell_keys(KParams kp, int64_t n, const double* __restrict__ pos,
                             const uint8_t* __restrict__ type, uint32_t* __restrict__ key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (is_excluded(type[i])) {
-    key[i] = kp.ncell_total;
-    return;
-  }
-  const double org[3] = {kp.ox, kp.oy, kp.oz};
-  const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
-  int c[3] = {0, 0, 0};
-  bool inside = true;
-  for (int k = 0; k < kp.dim; ++k) {
-    const double d = __dsub_rn(pos[k * n + i], org[k]);
-    const double s = __dmul_rn(d, kp.inv_cs);
-    const double f = floor(s);
-    if (!(f >= 0.0) || !(f < (double)nc[k])) inside = false;
-    else c[k] = (int)f;
-  }
-  key[i] = inside ? (uint32_t)(c[0] + nc[0] * (c[1] + nc[1] * c[2])) : kp.ncell_total;
+  key[i] = cell_key_local(kp, pos, type, n, i);
 }
 
 // ------------------------------------------------------- exclusive scans --
@@ -194,67 +176,14 @@ __global__ void k_cell_start(const uint32_t* __restrict__ key, int64_t n, uint32
 }
 
 // --------------------------------------------------------------- reorder --
-// Gathers the state into sorted order and writes, per sorted particle, the
-// two float4 the interaction reads (the "view"):
-//   pr = {cell-relative position (dim components), 0, +rho fluid / -rho wall}
-//   vp = {velocity (dim components), 0, P}
-// The cell-relative FP32 offset is x - (origin + c cs) evaluated in FP64 (the
-// precision scheme of Section 5.1: FP64 positions, FP32 distances inside the
-// cell).  P is the Tait pressure of Eq. 28, per particle in FP64; for
-// gamma = 7 as the expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the
-// small pressures of a nearly incompressible fluid free of cancellation.
 __global__ void k_reorder(KParams kp, int64_t n, const uint32_t* __restrict__ perm,
                           const uint32_t* __restrict__ key, sph_state in, sph_state out,
                           sph_state cin, sph_state cout, int carry, float4* __restrict__ pr,
                           float4* __restrict__ vp, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t src = perm[i];
-  const uint32_t k = key[i];
-  double x[3] = {0.0, 0.0, 0.0};
-  float v[3] = {0.f, 0.f, 0.f};
-  for (int d = 0; d < kp.dim; ++d) {
-    x[d] = in.pos[d * n + src];
-    v[d] = in.vel[d * n + src];
-    out.pos[d * n + i] = x[d];
-    out.vel[d * n + i] = v[d];
-  }
-  const float rho = in.rho[src];
-  out.rho[i] = rho;
-  uint8_t t = in.type[src];
-  if (k == kp.ncell_total && !(t & SPH_EXCLUDED)) {
-    t |= SPH_EXCLUDED;
+  if (reorder_one(kp, n, i, perm[i], key[i], in, out, cin, cout, carry, pr, vp))
     set_error(err, SPH_ERR_EXCLUDED);
-  }
-  out.type[i] = t;
-  if (in.id && out.id) out.id[i] = in.id[src];
-  if (carry) {
-    for (int d = 0; d < kp.dim; ++d) {
-      cout.pos[d * n + i] = cin.pos[d * n + src];
-      cout.vel[d * n + i] = cin.vel[d * n + src];
-    }
-    cout.rho[i] = cin.rho[src];
-  }
-  if (t & SPH_EXCLUDED) {
-    pr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
-  const int c0 = (int)(k % (uint32_t)kp.ncx);
-  const uint32_t rest = k / (uint32_t)kp.ncx;
-  const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
-  const double org[3] = {kp.ox, kp.oy, kp.oz};
-  float o[3] = {0.f, 0.f, 0.f};
-  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)c[d] * kp.cs));
-  const double r = (double)rho;
-  const double u = r / kp.rho0 - 1.0;
-  double pw;
-  if (kp.gamma == 7.0)
-    pw = u * (7.0 + u * (21.0 + u * (35.0 + u * (35.0 + u * (21.0 + u * (7.0 + u))))));
-  else
-    pw = pow(r / kp.rho0, kp.gamma) - 1.0;
-  pr[i] = make_float4(o[0], o[1], o[2], is_fluid(t) ? rho : -rho);
-  vp[i] = make_float4(v[0], v[1], v[2], (float)(kp.b_tait * pw));
 }
 
 // ------------------------------------------------------------------ host --
@@ -264,6 +193,49 @@ int key_bits(uint32_t ncell_total) {
   return bits;  // enough bits for keys 0..ncell_total
 }
 
+// Stable LSD radix sort of the keys in the workspace's keyA buffer (values
+// 0..max_key): sorted keys to key_out, the permutation to perm_out.
+hipError_t radix_sort(int64_t n, uint32_t max_key, uint32_t* key_out, uint32_t* perm_out,
+                      void* ws, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const WsLayout L = ws_layout(n);
+  uint32_t* kA = ws_ptr<uint32_t>(ws, L.keyA);
+  uint32_t* vA = ws_ptr<uint32_t>(ws, L.valA);
+  uint32_t* kB = ws_ptr<uint32_t>(ws, L.keyB);
+  uint32_t* vB = ws_ptr<uint32_t>(ws, L.valB);
+  uint32_t* hist = ws_ptr<uint32_t>(ws, L.hist);
+  uint32_t* part = ws_ptr<uint32_t>(ws, L.scan_part);
+  const int total_bits = key_bits(max_key);
+  const int passes = (total_bits + 7) / 8;
+  const int per = (total_bits + passes - 1) / passes;
+  if (per < 1 || per > 8 || (passes - 1) * per >= total_bits) return hipErrorInvalidValue;
+  const uint32_t* ksrc = kA;
+  const uint32_t* vsrc = nullptr;  // identity on the first pass
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * per;
+    const int bits = (shift + per <= total_bits) ? per : (total_bits - shift);
+    const bool last = (p == passes - 1);
+    uint32_t* kdst = last ? key_out : ((p & 1) ? kA : kB);
+    uint32_t* vdst = last ? perm_out : ((p & 1) ? vA : vB);
+    const int64_t nblk = L.nblk_sort;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, n, shift,
+                       bits, hist, nblk);
+    exclusive_scan(hist, (int64_t)(1 << bits) * nblk, part, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, vsrc,
+                       kdst, vdst, n, shift, bits, hist, nblk);
+    ksrc = kdst;
+    vsrc = vdst;
+  }
+  return hipSuccess;
+}
+
+void launch_cell_start(const uint32_t* key, int64_t n, uint32_t last_key, uint32_t* cell_start,
+                       hipStream_t st) {
+  const int64_t nc1 = (int64_t)last_key + 1;
+  hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((nc1 + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, st, key, n, last_key, cell_start);
+}
+
 hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, sph_state& out,
                             const sph_state* cin, sph_state* cout, uint32_t* key,
                             uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st) {
@@ -271,42 +243,19 @@ hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, s
   uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
   const unsigned gridn = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
-    uint32_t* kA = ws_ptr<uint32_t>(ws, L.keyA);
-    uint32_t* vA = ws_ptr<uint32_t>(ws, L.valA);
-    uint32_t* kB = ws_ptr<uint32_t>(ws, L.keyB);
-    uint32_t* vB = ws_ptr<uint32_t>(ws, L.valB);
-    uint32_t* hist = ws_ptr<uint32_t>(ws, L.hist);
-    uint32_t* part = ws_ptr<uint32_t>(ws, L.scan_part);
-    hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type, kA);
-    const int total_bits = key_bits(kp.ncell_total);
-    const int passes = (total_bits + 7) / 8;
-    const int per = (total_bits + passes - 1) / passes;
-    if (per < 1 || per > 8 || (passes - 1) * per >= total_bits) return hipErrorInvalidValue;
-    const uint32_t* ksrc = kA;
-    const uint32_t* vsrc = nullptr;  // identity on the first pass
-    for (int p = 0; p < passes; ++p) {
-      const int shift = p * per;
-      const int bits = (shift + per <= total_bits) ? per : (total_bits - shift);
-      const bool last = (p == passes - 1);
-      uint32_t* kdst = last ? key : ((p & 1) ? kA : kB);
-      uint32_t* vdst = last ? perm : ((p & 1) ? vA : vB);
-      const int64_t nblk = L.nblk_sort;
-      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, n,
-                         shift, bits, hist, nblk);
-      exclusive_scan(hist, (int64_t)(1 << bits) * nblk, part, st);
-      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc,
-                         vsrc, kdst, vdst, n, shift, bits, hist, nblk);
-      ksrc = kdst;
-      vsrc = vdst;
-    }
+    hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type,
+                       ws_ptr<uint32_t>(ws, L.keyA));
+    const hipError_t e = radix_sort(n, kp.ncell_total, key, perm, ws, st);
+    if (e != hipSuccess) return e;
   }
-  const int64_t nc1 = (int64_t)kp.ncell_total + 1;
-  hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((nc1 + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, st, key, n, kp.ncell_total, cell_start);
+  launch_cell_start(key, n, kp.ncell_total, cell_start, st);
   if (n > 0) {
     sph_state ci{}, co{};
     const int carry = (cin && cout) ? 1 : 0;
-    if (carry) { ci = *cin; co = *cout; }
+    if (carry) {
+      ci = *cin;
+      co = *cout;
+    }
     hipLaunchKernelGGL(k_reorder, dim3(gridn), dim3(kBlock), 0, st, kp, n, perm, key, in, out,
                        ci, co, carry, ws_ptr<float4>(ws, L.view_pr), ws_ptr<float4>(ws, L.view_vp),
                        err);

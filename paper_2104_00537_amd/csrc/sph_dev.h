@@ -1,0 +1,160 @@
+// Per-particle device routines shared by the single-case and the batched
+// kernels: the cell key, the sorted-order gather with its interaction view,
+// and the symplectic update (Sections 2.5.2 and 5.1 of the DualSPHysics v5.0
+// paper).
+#pragma once
+
+#include "sph_internal.h"
+
+namespace sph {
+
+// Cell index per axis = floor((x - origin) * inv_cs): one FP64 subtraction and
+// one FP64 multiplication (no contraction is possible), x fastest.  Outside
+// the grid, and for particles excluded earlier, the key is ncell_total, so
+// they sort last and lie in no cell range.
+__device__ inline uint32_t cell_key_local(const KParams& kp, const double* __restrict__ pos,
+                                          const uint8_t* __restrict__ type, int64_t n,
+                                          int64_t i) {
+  if (is_excluded(type[i])) return kp.ncell_total;
+  const double org[3] = {kp.ox, kp.oy, kp.oz};
+  const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
+  int c[3] = {0, 0, 0};
+  for (int k = 0; k < kp.dim; ++k) {
+    const double d = __dsub_rn(pos[k * n + i], org[k]);
+    const double s = __dmul_rn(d, kp.inv_cs);
+    const double f = floor(s);
+    if (!(f >= 0.0) || !(f < (double)nc[k])) return kp.ncell_total;
+    c[k] = (int)f;
+  }
+  return (uint32_t)(c[0] + nc[0] * (c[1] + nc[1] * c[2]));
+}
+
+// Gathers particle src into sorted slot i and writes the two float4 the
+// interaction reads (the "view"):
+//   pr = {cell-relative position (dim components), 0, +rho fluid / -rho wall}
+//   vp = {velocity (dim components), 0, P}
+// lkey is the particle's key relative to its case.  The cell-relative FP32
+// offset is x - (origin + c cs) evaluated in FP64 (the precision scheme of
+// Section 5.1: FP64 positions, FP32 distances inside the cell).  P is the
+// Tait pressure of Eq. 28, per particle in FP64; for gamma = 7 as the
+// expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the small pressures
+// of a nearly incompressible fluid free of cancellation.  Returns true if the
+// particle was excluded by this call (it left the grid).
+__device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int64_t src,
+                                   uint32_t lkey, const sph_state& in, const sph_state& out,
+                                   const sph_state& cin, const sph_state& cout, int carry,
+                                   float4* __restrict__ pr, float4* __restrict__ vp) {
+  double x[3] = {0.0, 0.0, 0.0};
+  float v[3] = {0.f, 0.f, 0.f};
+  for (int d = 0; d < kp.dim; ++d) {
+    x[d] = in.pos[d * n + src];
+    v[d] = in.vel[d * n + src];
+    out.pos[d * n + i] = x[d];
+    out.vel[d * n + i] = v[d];
+  }
+  const float rho = in.rho[src];
+  out.rho[i] = rho;
+  uint8_t t = in.type[src];
+  bool newly = false;
+  if (lkey == kp.ncell_total && !(t & SPH_EXCLUDED)) {
+    t |= SPH_EXCLUDED;
+    newly = true;
+  }
+  out.type[i] = t;
+  if (in.id && out.id) out.id[i] = in.id[src];
+  if (carry) {
+    for (int d = 0; d < kp.dim; ++d) {
+      cout.pos[d * n + i] = cin.pos[d * n + src];
+      cout.vel[d * n + i] = cin.vel[d * n + src];
+    }
+    cout.rho[i] = cin.rho[src];
+  }
+  if (t & SPH_EXCLUDED) {
+    pr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return newly;
+  }
+  const int c0 = (int)(lkey % (uint32_t)kp.ncx);
+  const uint32_t rest = lkey / (uint32_t)kp.ncx;
+  const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
+  const double org[3] = {kp.ox, kp.oy, kp.oz};
+  float o[3] = {0.f, 0.f, 0.f};
+  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)c[d] * kp.cs));
+  const double r = (double)rho;
+  const double u = r / kp.rho0 - 1.0;
+  double pw;
+  if (kp.gamma == 7.0)
+    pw = u * (7.0 + u * (21.0 + u * (35.0 + u * (35.0 + u * (21.0 + u * (7.0 + u))))));
+  else
+    pw = pow(r / kp.rho0, kp.gamma) - 1.0;
+  pr[i] = make_float4(o[0], o[1], o[2], is_fluid(t) ? rho : -rho);
+  vp[i] = make_float4(v[0], v[1], v[2], (float)(kp.b_tait * pw));
+  return newly;
+}
+
+// Imposed wall motion along x: D(t) = (A/w^2)(1 - cos wt), v(t) = (A/w) sin wt.
+__device__ inline double motion_disp(const KParams& kp, double t) {
+  if (kp.motion_omega == 0.0) return 0.0;
+  const double w = kp.motion_omega;
+  return kp.motion_amp / (w * w) * (1.0 - cos(w * t));
+}
+__device__ inline double motion_vel(const KParams& kp, double t) {
+  if (kp.motion_omega == 0.0) return 0.0;
+  return kp.motion_amp / kp.motion_omega * sin(kp.motion_omega * t);
+}
+
+// One particle of the symplectic update: PHASE 0 is the predictor (Eq. 33
+// lines 1-2, Eq. 34 line 1) and saves state n; PHASE 1 the corrector (Eq. 33
+// lines 3-4, Eq. 34 line 2) from the saved state.  dmove / vmove are the
+// imposed wall displacement since t and velocity at the phase's end time.
+// Returns true if the new state is not finite or the density not positive.
+template <int PHASE>
+__device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, double dt,
+                                      double dmove, double vmove, const sph_state& saved,
+                                      const sph_state& s, const float* __restrict__ ace,
+                                      const float* __restrict__ arho) {
+  const uint8_t t = s.type[i];
+  if (PHASE == 0) {
+    for (int d = 0; d < kp.dim; ++d) {
+      saved.pos[d * n + i] = s.pos[d * n + i];
+      saved.vel[d * n + i] = s.vel[d * n + i];
+    }
+    saved.rho[i] = s.rho[i];
+  }
+  if (is_excluded(t)) return false;
+  bool bad = false;
+  if (is_fluid(t)) {
+    for (int d = 0; d < kp.dim; ++d) {
+      const double a = (double)ace[d * n + i];
+      if (PHASE == 0) {
+        const double v = (double)s.vel[d * n + i];
+        s.pos[d * n + i] = s.pos[d * n + i] + 0.5 * dt * v;
+        const float v1 = (float)(v + 0.5 * dt * a);
+        s.vel[d * n + i] = v1;
+        bad |= !isfinite(v1);
+      } else {
+        const double vn = (double)saved.vel[d * n + i];
+        const double v1 = vn + dt * a;
+        s.pos[d * n + i] = saved.pos[d * n + i] + dt * 0.5 * (v1 + vn);
+        const float v1f = (float)v1;
+        s.vel[d * n + i] = v1f;
+        bad |= !isfinite(v1f);
+      }
+    }
+  } else if ((t & 0x7f) == SPH_BOUND_MOVING) {
+    s.pos[i] = saved.pos[i] + dmove;
+    s.vel[i] = (float)vmove;
+  }
+  double r;
+  if (PHASE == 0) {
+    r = (double)s.rho[i] + 0.5 * dt * (double)arho[i];
+  } else {
+    const double eps = -((double)arho[i] / (double)s.rho[i]) * dt;
+    r = (double)saved.rho[i] * (2.0 - eps) / (2.0 + eps);
+  }
+  const float rf = (float)r;
+  s.rho[i] = rf;
+  return bad || !(rf > 0.f) || !isfinite(rf);
+}
+
+}  // namespace sph

@@ -52,6 +52,30 @@ struct WsHeader {
   uint32_t pad[62];
 };
 
+// ---------------------------------------------------------------- batches --
+// One case ("slot") of a batch: its constants (in 3-D geometry: a 2-D case
+// is stored as (x, 0, z) with one cell across y), its first cell key and its
+// particle range in the packed arrays.
+struct SlotEntry {
+  KParams kp;
+  uint32_t cbase;    // keys of the slot: cbase .. cbase + kp.ncell_total
+  uint32_t pad;
+  int64_t off;       // first particle of the slot
+  int64_t n;         // particles of the slot
+};
+
+// Per-slot results of one interaction pass (cleared by each binning);
+// maxima of non-negative floats are kept as their bit patterns.
+struct SlotAccum {
+  uint32_t fmax_bits, vmax_bits, nfluid, pad;
+  unsigned long long count, count_wall;
+};
+
+// Per-slot time step and imposed wall motion of the current update phase.
+struct SlotMotion {
+  double dt, dmove, vmove, pad;
+};
+
 // Workspace layout (offsets in bytes, each region 256-aligned).
 struct WsLayout {
   size_t err;        // the WsHeader (offset 0)
@@ -93,6 +117,25 @@ inline WsLayout ws_layout(int64_t n) {
   L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
   L.total = off;
   return L;
+}
+
+// A batch workspace: the single-case layout for all packed particles, then
+// per-slot accumulators, motion table and error words.
+struct BatchWsLayout {
+  WsLayout base;
+  size_t accum, motion, slot_err, total;
+};
+
+inline BatchWsLayout batch_ws_layout(int32_t n_slots, int64_t n) {
+  BatchWsLayout B{};
+  B.base = ws_layout(n);
+  const size_t ns = (size_t)(n_slots > 0 ? n_slots : 1);
+  size_t off = B.base.total;
+  B.accum = off; off = align_up(off + sizeof(SlotAccum) * ns);
+  B.motion = off; off = align_up(off + sizeof(SlotMotion) * ns);
+  B.slot_err = off; off = align_up(off + sizeof(uint32_t) * ns);
+  B.total = off;
+  return B;
 }
 
 template <typename T>

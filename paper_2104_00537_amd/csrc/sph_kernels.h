@@ -6,8 +6,22 @@
 namespace sph {
 
 KParams make_kparams(const sph_params& p);
+KParams make_slot_kparams(const sph_params& p);
+
+// Host view of a batch (see sph_batch in sph.h).
+struct BatchDesc {
+  int n_slots;
+  int cell_div;
+  int64_t n_total;
+  int64_t key_cells;
+  const void* table;  // device SlotEntry[n_slots]
+};
 int key_bits(uint32_t ncell_total);
 void exclusive_scan(uint32_t* data, int64_t len, uint32_t* part, hipStream_t st);
+hipError_t radix_sort(int64_t n, uint32_t max_key, uint32_t* key_out, uint32_t* perm_out,
+                      void* ws, hipStream_t st);
+void launch_cell_start(const uint32_t* key, int64_t n, uint32_t last_key, uint32_t* cell_start,
+                       hipStream_t st);
 
 hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, sph_state& out,
                             const sph_state* cin, sph_state* cout, uint32_t* key,
@@ -21,5 +35,18 @@ hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const doub
                              sph_state& saved, sph_state& s, const float* ace, const float* arho,
                              void* ws, hipStream_t st);
 hipError_t launch_clear_error(void* ws, hipStream_t st);
+
+hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_state& out,
+                                  const sph_state* cin, sph_state* cout, uint32_t* key,
+                                  uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st);
+hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
+                                 const uint32_t* cell_start, float* ace, float* arho, float* visc,
+                                 uint32_t* nbr, void* ws, hipStream_t st);
+hipError_t launch_batch_reduce_dt(const BatchDesc& B, double* dt, uint64_t* interactions, void* ws,
+                                  hipStream_t st);
+hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* dt, double* t,
+                                   sph_state& saved, sph_state& s, const float* ace,
+                                   const float* arho, void* ws, hipStream_t st);
+hipError_t launch_batch_clear_errors(const BatchDesc& B, void* ws, hipStream_t st);
 
 }  // namespace sph

@@ -1,0 +1,256 @@
+// Device code shared by the single-case and the batched interaction kernels:
+// the pair terms of the WCSPH interaction and the scalar-candidate-stream
+// machinery (Section 2.3 of the DualSPHysics v5.0 paper).
+#pragma once
+
+#include "sph_internal.h"
+
+namespace sph {
+
+struct PairAcc {
+  float ax, ay, az;  // sum of -m_b [(P_a+P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
+  float cont;        // sum of (m_b/rho_b) F_ab v_ab.r_ab
+  float diff;        // sum over fluid b of (rho_b - rho_a)|F_ab| m_b/rho_b
+  float vmax;        // max of |h v_ab.r_ab/(r^2+eta^2)|
+  uint32_t cnt;      // pairs evaluated
+};
+
+struct TargetData {
+  bool fluid;
+  float rho, irho, p;
+  float vx, vy, vz;
+};
+
+// The pair terms of Eq. 11 (gradient), 15, 17-18, 21-22 and 36 for one pair
+// (a, b) with r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pb.w is +rho_b for a
+// fluid particle and -rho_b for a wall; vb.w is P_b.  The caller has already
+// dropped wall-wall pairs (Eq. 36 sums over fluid neighbours only).
+template <int DIM>
+__device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
+                                           float dy, float dz, float r2, const float4& pb,
+                                           const float4& vb, PairAcc& acc) {
+  const bool fb = pb.w > 0.f;
+  const float rhob = fabsf(pb.w);
+  const float vr = (a.vx - vb.x) * dx + (a.vy - vb.y) * dy + (DIM == 3 ? (a.vz - vb.z) * dz : 0.f);
+  const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h_f;
+  const float w = 1.f - 0.5f * q;
+  const float fab = kp.kfab_f * w * w * w;  // grad_a W_ab = fab r_ab, fab <= 0
+  const float irhob = __builtin_amdgcn_rcpf(rhob);
+  const float mb = fb ? kp.mass_f_f : kp.mass_b_f;
+  const float fv = fab * (mb * irhob);
+  acc.cont += fv * vr;
+  acc.cnt += 1u;
+  if (a.fluid) {
+    const float pterm = (a.p + vb.w) * (a.irho * irhob);
+    const float mu = kp.h_f * vr * __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
+    // Pi_ab = -alpha c0 mu / ((rho_a + rho_b)/2) for approaching pairs (Eq. 21)
+    const float pi =
+        vr < 0.f ? -2.f * kp.visc_coef_f * mu * __builtin_amdgcn_rcpf(a.rho + rhob) : 0.f;
+    const float coef = mb * (pterm + pi) * fab;
+    acc.ax -= coef * dx;
+    acc.ay -= coef * dy;
+    if (DIM == 3) acc.az -= coef * dz;
+    acc.vmax = fmaxf(acc.vmax, fabsf(mu));
+    if (fb) acc.diff -= (rhob - a.rho) * fv;
+  }
+}
+
+// ------------------------------------------------- block partial results --
+template <int WAVES>
+__device__ inline void write_block_red(float fmag, float vmax, uint32_t cnt, uint32_t cntw,
+                                       uint32_t nfl, BlockRed* red, WsHeader* hdr) {
+  __shared__ float sf[WAVES], sv[WAVES];
+  __shared__ uint32_t sc[WAVES], sw[WAVES], sn[WAVES];
+  fmag = wave_max(fmag);
+  vmax = wave_max(vmax);
+  cnt = wave_sum(cnt);
+  cntw = wave_sum(cntw);
+  nfl = wave_sum(nfl);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sf[wave] = fmag;
+    sv[wave] = vmax;
+    sc[wave] = cnt;
+    sw[wave] = cntw;
+    sn[wave] = nfl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BlockRed b{0.f, 0.f, 0u, 0u, 0u, 0u};
+    for (int w = 0; w < WAVES; ++w) {
+      b.fmax = fmaxf(b.fmax, sf[w]);
+      b.vmax = fmaxf(b.vmax, sv[w]);
+      b.count += sc[w];
+      b.count_wall += sw[w];
+      b.nfluid += sn[w];
+    }
+    red[blockIdx.x] = b;
+    if (blockIdx.x == 0) hdr->nred = gridDim.x;
+  }
+}
+
+// Per-target outputs: dv/dt (with gravity) for fluid targets, drho/dt, visc
+// and the pair count; returns |dv/dt|, visc and the fluid flag for the block
+// partial results.
+template <int DIM>
+__device__ __forceinline__ void write_target(const KParams& kp, int64_t n, int64_t a,
+                                             const TargetData& t, const PairAcc& acc,
+                                             uint32_t count_out, float* ace, float* arho,
+                                             float* visc, uint32_t* nbr, float& fmag,
+                                             float& vmax_out, uint32_t& nfl) {
+  float ax = 0.f, ay = 0.f, az = 0.f;
+  float ar = t.rho * acc.cont;
+  if (t.fluid) {
+    ax = acc.ax + kp.gx_f;
+    ay = acc.ay + kp.gy_f;
+    az = DIM == 3 ? acc.az + kp.gz_f : 0.f;
+    ar += kp.ddt_coef_f * acc.diff;
+    fmag = sqrtf(ax * ax + ay * ay + az * az);
+    vmax_out = acc.vmax;
+    nfl = 1;
+  }
+  ace[a] = ax;
+  ace[n + a] = ay;
+  if (DIM == 3) ace[2 * n + a] = az;
+  arho[a] = ar;
+  if (visc) visc[a] = acc.vmax;
+  if (nbr) nbr[a] = count_out;
+}
+
+template <int DIM>
+__device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, float* arho,
+                                           float* visc, uint32_t* nbr) {
+  ace[a] = 0.f;
+  ace[n + a] = 0.f;
+  if (DIM == 3) ace[2 * n + a] = 0.f;
+  arho[a] = 0.f;
+  if (visc) visc[a] = 0.f;
+  if (nbr) nbr[a] = 0u;
+}
+
+// Orders this wave's LDS writes before its later LDS reads (no block barrier:
+// the waves of a block progress independently).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// ------------------------------------------------ scalar candidate stream --
+// A wavefront takes 64 consecutive sorted targets (one per lane).  For the
+// targets of one cell row it walks the union of their neighbour cells as a
+// single candidate stream that is the same for every lane: candidate data is
+// fetched with scalar loads into SGPRs and used directly as VALU operands, so
+// no per-lane memory traffic is spent on candidates that fail the distance
+// test.  Each lane appends its hits (global index + index of the cell's frame
+// shift) to its own LDS list; the pair terms then run densely over the lists.
+constexpr int kSgLCap = 36;      // list entries per lane (4 blocks of 256 fit the LDS)
+constexpr int kSgCells = 32;     // cell shifts kept per wave between drains
+constexpr int kSgJBits = 27;     // list entry: j (27 bits) | cell slot (5 bits)
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+struct SgLds {
+  uint32_t list[kSgLCap][64];
+  float4 shift[kSgCells];
+};
+
+// Streams the neighbour cells of one cell row of targets (slot-local cell
+// coordinates ry, rz and x extent [xmin, xmax]; cell indices are offset by
+// cbase) through the scalar candidate pipeline, accumulating each in-row
+// lane's pair terms into acc.  Uniform across the wave; lanes whose target is
+// not in the row carry thresholds of -1 and take no hits.
+template <int DIM, int R>
+__device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int ry, int rz,
+                                         int xmin, int xmax, float xa, float ya, float za,
+                                         float thr_any, float thr_fluid, const TargetData& T,
+                                         SgLds& L, int lane, const float4* __restrict__ pr,
+                                         const float4* __restrict__ vp,
+                                         const uint32_t* __restrict__ cstart, PairAcc& acc) {
+  // this lane's list: entry k at list[k][lane]; wp points past the last hit
+  // (an LDS-address-space pointer, so appends are single ds_write ops)
+  lds_u32* const lbase = (lds_u32*)&L.list[0][lane];
+  lds_u32* wp = lbase;
+  int ncs = 0;  // cell shifts in use (uniform)
+  auto drain = [&]() {
+    wave_sync();
+    const int cnt = (int)(wp - lbase) / 64;
+    int m = cnt;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    m = __builtin_amdgcn_readfirstlane(m);
+    for (int k = 0; k < m; ++k) {
+      if (k < cnt) {
+        const uint32_t e = L.list[k][lane];
+        const uint32_t j = e & ((1u << kSgJBits) - 1u);
+        const float4 sh = L.shift[e >> kSgJBits];
+        const float4 pb = pr[j];
+        const float4 vb = vp[j];
+        const float dx = (xa - sh.x) - pb.x;
+        const float dy = (ya - sh.y) - pb.y;
+        const float dz = DIM == 3 ? (za - sh.z) - pb.z : 0.f;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
+      }
+    }
+    wave_sync();
+    wp = lbase;
+  };
+  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = rz + dz;
+    if (z < 0 || z >= kp.ncz) continue;
+    for (int dy = -R; dy <= R; ++dy) {
+      const int y = ry + dy;
+      if (y < 0 || y >= kp.ncy) continue;
+      const int xlo = max(xmin - R, 0), xhi = min(xmax + R, kp.ncx - 1);
+      const uint32_t rowbase =
+          cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+      for (int x = xlo; x <= xhi; ++x) {
+        const uint32_t j0 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x]);
+        const uint32_t j1 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x + 1]);
+        if (j0 == j1) continue;
+        if (ncs == kSgCells) {
+          drain();
+          ncs = 0;
+        }
+        const float sx = (float)(x - xmin) * kp.cs_f, sy = (float)dy * kp.cs_f,
+                    sz = (float)dz * kp.cs_f;
+        if (lane == 0) L.shift[ncs] = make_float4(sx, sy, sz, 0.f);
+        const uint32_t tag = (uint32_t)ncs << kSgJBits;
+        ++ncs;
+        const float xs = xa - sx, ys = ya - sy, zs = za - sz;
+        // candidates in groups of 4 (one 64-B scalar load), the next group
+        // prefetched; the views are padded so a group may run past j1
+        float4 q0 = pr[j0], q1 = pr[j0 + 1], q2 = pr[j0 + 2], q3 = pr[j0 + 3];
+        for (uint32_t j = j0; j < j1; j += 4) {
+          const float4 c4[4] = {q0, q1, q2, q3};
+          if (j + 4 < j1) {
+            q0 = pr[j + 4];
+            q1 = pr[j + 5];
+            q2 = pr[j + 6];
+            q3 = pr[j + 7];
+          }
+          const uint32_t left = j1 - j;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if ((uint32_t)u < left) {
+              const float4 pb = c4[u];
+              const float dx = xs - pb.x, dy_ = ys - pb.y, dz_ = DIM == 3 ? zs - pb.z : 0.f;
+              const float r2 = dx * dx + dy_ * dy_ + dz_ * dz_;
+              // wall candidates count for fluid targets only (Eq. 36)
+              const float thr = __float_as_int(pb.w) > 0 ? thr_any : thr_fluid;
+              if (r2 < thr) {
+                *wp = (j + u) | tag;
+                wp += 64;
+              }
+            }
+          }
+          if (__ballot(wp > lbase + 64 * (kSgLCap - 4)) != 0ull) drain();
+        }
+      }
+    }
+  }
+  drain();
+}
+
+}  // namespace sph

@@ -1,21 +1,24 @@
 // System update (Section 5.1): the variable time step of Eq. 35 and the
 // symplectic position-Verlet update of Eq. 33-34, with the imposed motion of
 // moving walls (Eq. 37).
+#include "sph_dev.h"
 #include "sph_kernels.h"
 
 namespace sph {
 
 // Eq. 35 from the per-block partials of the last interaction pass; one block.
-__global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red,
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red,
                             WsHeader* __restrict__ hdr, double* __restrict__ dt,
                             uint64_t* __restrict__ inter, float* __restrict__ maxima) {
   uint32_t* err = &hdr->err;
   const int64_t nblk = hdr->nred;
-  __shared__ float sf[kBlock / 64], sv[kBlock / 64];
-  __shared__ unsigned long long sc[kBlock / 64], sw[kBlock / 64], sn[kBlock / 64];
+  __shared__ float sf[kRedThreads / 64], sv[kRedThreads / 64];
+  __shared__ unsigned long long sc[kRedThreads / 64], sw[kRedThreads / 64], sn[kRedThreads / 64];
   float fmax = 0.f, vmax = 0.f;
   unsigned long long cnt = 0, cntw = 0, nfl = 0;
-  for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
+  for (int64_t b = threadIdx.x; b < nblk; b += kRedThreads) {
     const BlockRed r = red[b];
     fmax = fmaxf(fmax, r.fmax);
     vmax = fmaxf(vmax, r.vmax);
@@ -34,7 +37,7 @@ __global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red,
   if (lane == 0) { sf[wave] = fmax; sv[wave] = vmax; sc[wave] = cnt; sw[wave] = cntw; sn[wave] = nfl; }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int w = 1; w < kBlock / 64; ++w) {
+  for (int w = 1; w < kRedThreads / 64; ++w) {
     sf[0] = fmaxf(sf[0], sf[w]);
     sv[0] = fmaxf(sv[0], sv[w]);
     sc[0] += sc[w];
@@ -57,19 +60,7 @@ __global__ void k_reduce_dt(KParams kp, const BlockRed* __restrict__ red,
   if (maxima) { maxima[0] = sf[0]; maxima[1] = sv[0]; }
 }
 
-// Imposed wall motion along x: D(t) = (A/w^2)(1 - cos wt), v(t) = (A/w) sin wt.
-__device__ inline double motion_disp(const KParams& kp, double t) {
-  if (kp.motion_omega == 0.0) return 0.0;
-  const double w = kp.motion_omega;
-  return kp.motion_amp / (w * w) * (1.0 - cos(w * t));
-}
-__device__ inline double motion_vel(const KParams& kp, double t) {
-  if (kp.motion_omega == 0.0) return 0.0;
-  return kp.motion_amp / kp.motion_omega * sin(kp.motion_omega * t);
-}
-
-// phase 0: predictor (Eq. 33 lines 1-2, Eq. 34 line 1), saving state n;
-// phase 1: corrector (Eq. 33 lines 3-4, Eq. 34 line 2) from the saved state.
+// phase 0: predictor, saving state n; phase 1: corrector from the saved state.
 template <int PHASE>
 __global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ dtp,
                              const double* __restrict__ tp, sph_state saved, sph_state s,
@@ -86,49 +77,8 @@ __global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ d
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double dt = shm[0];
-  const uint8_t t = s.type[i];
-  if (PHASE == 0) {
-    for (int d = 0; d < kp.dim; ++d) {
-      saved.pos[d * n + i] = s.pos[d * n + i];
-      saved.vel[d * n + i] = s.vel[d * n + i];
-    }
-    saved.rho[i] = s.rho[i];
-  }
-  if (is_excluded(t)) return;
-  bool bad = false;
-  if (is_fluid(t)) {
-    for (int d = 0; d < kp.dim; ++d) {
-      const double a = (double)ace[d * n + i];
-      if (PHASE == 0) {
-        const double v = (double)s.vel[d * n + i];
-        s.pos[d * n + i] = s.pos[d * n + i] + 0.5 * dt * v;
-        const float v1 = (float)(v + 0.5 * dt * a);
-        s.vel[d * n + i] = v1;
-        bad |= !isfinite(v1);
-      } else {
-        const double vn = (double)saved.vel[d * n + i];
-        const double v1 = vn + dt * a;
-        s.pos[d * n + i] = saved.pos[d * n + i] + dt * 0.5 * (v1 + vn);
-        const float v1f = (float)v1;
-        s.vel[d * n + i] = v1f;
-        bad |= !isfinite(v1f);
-      }
-    }
-  } else if ((t & 0x7f) == SPH_BOUND_MOVING) {
-    s.pos[i] = saved.pos[i] + shm[1];
-    s.vel[i] = (float)shm[2];
-  }
-  double r;
-  if (PHASE == 0) {
-    r = (double)s.rho[i] + 0.5 * dt * (double)arho[i];
-  } else {
-    const double eps = -((double)arho[i] / (double)s.rho[i]) * dt;
-    r = (double)saved.rho[i] * (2.0 - eps) / (2.0 + eps);
-  }
-  const float rf = (float)r;
-  s.rho[i] = rf;
-  if (bad || !(rf > 0.f) || !isfinite(rf)) set_error(err, SPH_ERR_NONFINITE);
+  if (symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s, ace, arho))
+    set_error(err, SPH_ERR_NONFINITE);
 }
 
 __global__ void k_advance_time(const double* __restrict__ dt, double* __restrict__ t) {
@@ -143,7 +93,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t len, uint32_t v) {
 hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* interactions,
                             float* maxima, void* ws, hipStream_t st) {
   const WsLayout L = ws_layout(n);
-  hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(kBlock), 0, st, kp, ws_ptr<BlockRed>(ws, L.red),
+  hipLaunchKernelGGL(k_reduce_dt, dim3(1), dim3(kRedThreads), 0, st, kp, ws_ptr<BlockRed>(ws, L.red),
                      ws_ptr<WsHeader>(ws, L.err), dt, interactions, maxima);
   return hipGetLastError();
 }

@@ -23,7 +23,11 @@ SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR = 1, 2, 4
 SPH_DIAG_COUNT_F64 = 1
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
-           "sph_symplectic_step", "sph_read_error", "sph_clear_error", "sph_strerror")
+           "sph_symplectic_step", "sph_read_error", "sph_clear_error", "sph_strerror",
+           "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
+           "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
+           "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
+SPH_BATCH_MAX_SLOTS = 4096
 
 
 class SphParams(C.Structure):
@@ -43,6 +47,11 @@ class SphParams(C.Structure):
 class SphState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("rho", C.c_void_p),
                 ("type", C.c_void_p), ("id", C.c_void_p)]
+
+
+class SphBatch(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("cell_div", C.c_int32), ("n_total", C.c_int64),
+                ("key_cells", C.c_int64), ("table", C.c_void_p)]
 
 
 class SphError(RuntimeError):
@@ -75,6 +84,28 @@ def _load() -> C.CDLL:
     L.sph_clear_error.argtypes = [VP, VP]
     L.sph_strerror.restype = C.c_char_p
     L.sph_strerror.argtypes = [C.c_int32]
+    L.sph_batch_table_bytes.restype = C.c_size_t
+    L.sph_batch_table_bytes.argtypes = [C.c_int32]
+    L.sph_batch_describe.restype = C.c_int32
+    L.sph_batch_describe.argtypes = [P(SphParams), P(C.c_int64), C.c_int32, VP, C.c_size_t,
+                                     P(SphBatch)]
+    L.sph_batch_workspace_bytes.restype = C.c_size_t
+    L.sph_batch_workspace_bytes.argtypes = [P(SphBatch)]
+    L.sph_batch_bin_cells.restype = C.c_int32
+    L.sph_batch_bin_cells.argtypes = [P(SphBatch), P(SphState), P(SphState), P(SphState),
+                                      P(SphState), VP, VP, VP, VP, C.c_size_t, VP]
+    L.sph_batch_interact.restype = C.c_int32
+    L.sph_batch_interact.argtypes = [P(SphBatch), P(SphState), VP, VP, VP, VP, VP, VP, VP,
+                                     C.c_size_t, VP]
+    L.sph_batch_reduce_dt.restype = C.c_int32
+    L.sph_batch_reduce_dt.argtypes = [P(SphBatch), VP, VP, VP, C.c_size_t, VP]
+    L.sph_batch_symplectic_step.restype = C.c_int32
+    L.sph_batch_symplectic_step.argtypes = [P(SphBatch), C.c_int32, VP, VP, P(SphState),
+                                            P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_batch_read_errors.restype = C.c_int32
+    L.sph_batch_read_errors.argtypes = [P(SphBatch), VP, VP]
+    L.sph_batch_clear_errors.restype = C.c_int32
+    L.sph_batch_clear_errors.argtypes = [P(SphBatch), VP, VP]
     return L
 
 
@@ -197,3 +228,67 @@ def sph_read_error(ws: torch.Tensor) -> int:
 
 def sph_clear_error(ws: torch.Tensor, stream=None):
     _check(lib.sph_clear_error(_ptr(ws), _stream(stream)), "sph_clear_error")
+
+
+# ------------------------------------------------------------------ batches
+def sph_batch_describe(params_list, offsets):
+    """Host-side slot table of a batch.  Returns (SphBatch without table,
+    table bytes as a uint8 numpy array)."""
+    import numpy as np
+    ns = len(params_list)
+    arr = (SphParams * ns)(*params_list)
+    offs = (C.c_int64 * (ns + 1))(*[int(o) for o in offsets])
+    nbytes = int(lib.sph_batch_table_bytes(ns))
+    if nbytes == 0:
+        raise SphError(f"sph_batch_table_bytes: bad slot count {ns}")
+    host = np.zeros(nbytes, np.uint8)
+    b = SphBatch()
+    _check(lib.sph_batch_describe(arr, offs, ns, host.ctypes.data_as(C.c_void_p), nbytes,
+                                  C.byref(b)), "sph_batch_describe")
+    return b, host
+
+
+def sph_batch_workspace_bytes(batch: SphBatch) -> int:
+    return int(lib.sph_batch_workspace_bytes(C.byref(batch)))
+
+
+def sph_batch_bin_cells(batch: SphBatch, src: DeviceState, dst: DeviceState, key, perm,
+                        cell_start, ws, carry_in=None, carry_out=None, stream=None):
+    ci = C.byref(carry_in.c()) if carry_in is not None else None
+    co = C.byref(carry_out.c()) if carry_out is not None else None
+    _check(lib.sph_batch_bin_cells(C.byref(batch), C.byref(src.c()), C.byref(dst.c()), ci, co,
+                                   _ptr(key), _ptr(perm), _ptr(cell_start), _ptr(ws), ws.numel(),
+                                   _stream(stream)), "sph_batch_bin_cells")
+
+
+def sph_batch_interact(batch: SphBatch, s: DeviceState, key, cell_start, ace, arho, ws,
+                       visc=None, nbr=None, stream=None):
+    _check(lib.sph_batch_interact(C.byref(batch), C.byref(s.c()), _ptr(key), _ptr(cell_start),
+                                  _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "sph_batch_interact")
+
+
+def sph_batch_reduce_dt(batch: SphBatch, dt, ws, interactions=None, stream=None):
+    _check(lib.sph_batch_reduce_dt(C.byref(batch), _ptr(dt), _ptr(interactions), _ptr(ws),
+                                   ws.numel(), _stream(stream)), "sph_batch_reduce_dt")
+
+
+def sph_batch_symplectic_step(batch: SphBatch, phase, dt, t, saved: DeviceState, s: DeviceState,
+                              ace, arho, ws, stream=None):
+    _check(lib.sph_batch_symplectic_step(C.byref(batch), int(phase), _ptr(dt), _ptr(t),
+                                         C.byref(saved.c()), C.byref(s.c()), _ptr(ace),
+                                         _ptr(arho), _ptr(ws), ws.numel(), _stream(stream)),
+           "sph_batch_symplectic_step")
+
+
+def sph_batch_read_errors(batch: SphBatch, ws):
+    import numpy as np
+    out = np.zeros(batch.n_slots, np.uint32)
+    _check(lib.sph_batch_read_errors(C.byref(batch), _ptr(ws), out.ctypes.data_as(C.c_void_p)),
+           "sph_batch_read_errors")
+    return out
+
+
+def sph_batch_clear_errors(batch: SphBatch, ws, stream=None):
+    _check(lib.sph_batch_clear_errors(C.byref(batch), _ptr(ws), _stream(stream)),
+           "sph_batch_clear_errors")

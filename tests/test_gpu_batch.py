@@ -1,0 +1,136 @@
+"""The batched path (continuous batching) on the GPU: per-case results are
+bit-identical alone and in a mix, agree with the single-case path and with
+the oracle, and a small request stream is served end to end."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2104_00537_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2104_00537_amd import serve as V
+    from paper_2104_00537_amd import sph as S
+    from paper_2104_00537_amd.runner import Simulation
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _mix_cases():
+    rng = np.random.default_rng(5)
+    out = [cases.dam_break_2d(dp=0.02, seed=1),
+           cases.block_case(3, (12, 10, 9), walls=True, seed=2),
+           cases.sloshing_3d(dp=0.06, seed=3),
+           cases.dam_break_3d(dp=0.03, seed=4)]
+    for c in out:
+        c.vel[:] = rng.uniform(-0.2, 0.2, c.vel.shape).astype(np.float32)
+    return out
+
+
+def _run_engine(cs, steps, graph):
+    eng = V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
+                        cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
+                        max_slots=8, device=DEV, use_graph=graph)
+    reqs = [V.Request(rid=k, case=c, steps=steps, arrival=0.0) for k, c in enumerate(cs)]
+    eng.repack([], reqs)
+    eng.run(steps)
+    torch.cuda.synchronize()
+    errs = S.sph_batch_read_errors(eng.batch, eng.ws)
+    return [eng.slot_result(k) for k in range(len(cs))], errs, eng
+
+
+def test_batch_alone_vs_mix_bit_identical():
+    cs = _mix_cases()
+    _say("mix of", [c.n for c in cs])
+    mix, errs, _ = _run_engine(cs, 6, graph=True)
+    assert not errs.any()
+    for k, c in enumerate(cs):
+        alone, e1, _ = _run_engine([c], 6, graph=False)
+        assert not e1.any()
+        for f in ("pos", "vel", "rho", "type"):
+            assert np.array_equal(mix[k][f], alone[0][f]), (k, f)
+        assert mix[k]["t"] == alone[0]["t"]
+
+
+def test_batch_matches_single_case_path():
+    cs = _mix_cases()
+    mix, errs, _ = _run_engine(cs, 4, graph=False)
+    assert not errs.any()
+    for k, c in enumerate(cs):
+        sim = Simulation(c, DEV)
+        sim.run(4)
+        g = sim.host_state()
+        assert sim.error() == 0
+        b = mix[k]
+        assert b["t"] == pytest.approx(g["t"], rel=1e-6)
+        scale = max(np.abs(g["vel"]).max(), 1e-3)
+        dv = np.abs(b["vel"] - g["vel"]).max()
+        dx = np.abs(b["pos"] - g["pos"]).max()
+        dr = np.abs(b["rho"].astype(np.float64) - g["rho"]).max()
+        _say(f"  slot {k} (dim {c.params.dim}): |dv| {dv:.2e} |dx| {dx:.2e} |drho| {dr:.2e}")
+        assert dv <= 1e-4 * scale + 1e-6 and dx <= 1e-7 and dr <= 1e-2
+        assert np.array_equal(b["type"], g["type"])
+
+
+def test_batch_interaction_matches_oracle():
+    cs = _mix_cases()
+    eng = V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
+                        cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
+                        max_slots=8, device=DEV, use_graph=False)
+    reqs = [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)]
+    eng.repack([], reqs)
+    b = eng.batch
+    n = b.n_total
+    a, bb = eng._dev_state(0, n), eng._dev_state(1, n)
+    key, perm = eng._key.view(n), eng._perm.view(n)
+    ace, arho = eng._ace.view(n), eng._arho.view(n)
+    nbr = torch.zeros(n, dtype=torch.int32, device=DEV)
+    S.sph_batch_bin_cells(b, a, bb, key, perm, eng.cell_start, eng.ws)
+    S.sph_batch_interact(b, bb, key, eng.cell_start, ace, arho, eng.ws, nbr=nbr)
+    torch.cuda.synchronize()
+    pos_all = bb.pos.cpu().numpy()
+    vel_all = bb.vel.cpu().numpy().astype(np.float64)
+    rho_all = bb.rho.cpu().numpy().astype(np.float64)
+    typ_all = bb.type.cpu().numpy()
+    ace_all = ace.cpu().numpy().astype(np.float64)
+    arho_all = arho.cpu().numpy().astype(np.float64)
+    nbr_all = nbr.cpu().numpy().astype(np.int64)
+    for k, c in enumerate(cs):
+        o0, o1 = eng.offsets[k], eng.offsets[k + 1]
+        pos, vel = V.from_3d(c.params.dim, pos_all[:, o0:o1], vel_all[:, o0:o1])
+        typ = typ_all[o0:o1]
+        ace_o, arho_o, _, nbr_o = oracle.interact(c.params, pos, vel, rho_all[o0:o1], typ)
+        ace_g = ace_all[:, o0:o1] if c.params.dim == 3 else ace_all[[0, 2], o0:o1]
+        fl = typ == cases.FLUID
+        ea = np.abs(ace_g - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+        er = np.abs(arho_all[o0:o1] - arho_o).max() / np.abs(arho_o).max()
+        flips = np.abs(nbr_all[o0:o1] - nbr_o.astype(np.int64)).sum()
+        _say(f"  slot {k}: rel err ace {ea:.2e} arho {er:.2e} count flips {flips}")
+        assert ea < 1e-4 and er < 1e-4 and flips <= 5e-4 * nbr_o.sum() + 2
+
+
+def test_served_stream_small():
+    """A short stream through the batched and the plain path: every request
+    completes without error and gets the same answer either way."""
+    reqs = V.make_stream(6, rate=50.0, seed=3, n_min=800, n_max=6000, steps_min=5,
+                         steps_max=20)
+    eng = V.BatchEngine(cap_particles=200_000, cap_cells=2_000_000, max_slots=8, device=DEV)
+    sb = V.serve_batched(reqs, eng, max_chunk=7, keep_results=True)
+    res_b = {r.rid: r.result for r in reqs}
+    assert sb["errors"] == 0 and all(r.finish is not None for r in reqs)
+    reqs2 = V.make_stream(6, rate=50.0, seed=3, n_min=800, n_max=6000, steps_min=5,
+                          steps_max=20)
+    sp = V.serve_plain(reqs2, device=DEV, keep_results=True)
+    assert sp["errors"] == 0
+    for r in reqs2:
+        a, b = res_b[r.rid], r.result
+        assert a["t"] == pytest.approx(b["t"], rel=1e-6)
+        assert np.abs(a["pos"] - b["pos"]).max() < 1e-6
+    _say("  batched", {k: round(v, 4) for k, v in sb.items() if isinstance(v, float)})
+    _say("  plain  ", {k: round(v, 4) for k, v in sp.items() if isinstance(v, float)})
