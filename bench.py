@@ -118,6 +118,50 @@ def serving(args):
     return out
 
 
+def profile_mode(args):
+    """Kernel-only modes for counter runs: 'interact' bins the workload once
+    and launches the interaction kernel --steps times; 'copy' copies a 1 GiB
+    buffer --steps times (the reference for the HBM byte counters)."""
+    import torch
+    if args.mode == "copy":
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": x.numel() * 4,
+                          "bytes_written_per_launch": y.numel() * 4}), flush=True)
+        return 0
+    from paper_2104_00537_amd import sph as S
+    case = workload(args.workload, args.cell_div)
+    P = S.make_params(case.params)
+    n = case.n
+    src = S.DeviceState.from_case(case, "cuda:0")
+    dst = S.DeviceState.empty(case.params.dim, n, "cuda:0")
+    key = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    perm = torch.empty_like(key)
+    start = torch.empty(case.params.ncell_total() + 1, dtype=torch.int32, device="cuda:0")
+    ws = torch.zeros(S.sph_workspace_bytes(P, n), dtype=torch.uint8, device="cuda:0")
+    ace = torch.empty((case.params.dim, n), dtype=torch.float32, device="cuda:0")
+    arho = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    S.sph_bin_cells(P, n, src, dst, key, perm, start, ws)
+    inter = torch.zeros(2, dtype=torch.int64, device="cuda:0")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        S.sph_interact(P, n, dst, key, start, ace, arho, ws)
+    e1.record()
+    S.sph_reduce_dt(P, n, dt, ws, interactions=inter)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "interact", "workload": args.workload, "n": n,
+                      "pairs_per_launch": int(inter[0].item()),
+                      "wall_pairs_per_launch": int(inter[1].item()),
+                      "ms_per_launch": e0.elapsed_time(e1) / max(args.steps, 1)}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +170,8 @@ def main():
     ap.add_argument("--workload", default="dam_break_3d_1m")
     ap.add_argument("--cell-div", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mode", choices=["step", "interact", "copy"], default="step",
+                    help="step: the benchmark; interact/copy: kernel-only runs for counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -141,6 +187,9 @@ def main():
         print(f"bench.py runs on one GPU only: this path has no multi-GPU mode "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         return 2
+
+    if args.mode != "step":
+        return profile_mode(args)
 
     import numpy as np
     import torch

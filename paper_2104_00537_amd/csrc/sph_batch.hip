@@ -106,7 +106,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const int xmax = __builtin_amdgcn_readfirstlane(xmx);
     const KParams kp = tab[rs].kp;
     const uint32_t cbase = tab[rs].cbase;
-    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
     const float thr_any = inrow ? kp.support2_f : -1.f;
     const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
     if (inrow) {
@@ -115,8 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
       gz = kp.gz_f;
       ddt = kp.ddt_coef_f;
     }
-    sgpr_row<3, R>(kp, cbase, ry, rz, xmin, xmax, xa, pa.y, pa.z, thr_any, thr_fluid, T, L, lane,
-                   pr, vp, cstart, acc);
+    sgpr_row<3, R>(kp, cbase, ry, rz, xmin, xmax, pa.x, cx, pa.y, pa.z, thr_any, thr_fluid, T, L,
+                   lane, pr, vp, cstart, acc);
     todo = todo && !inrow;
   }
   float fmag = 0.f, vmx = 0.f;

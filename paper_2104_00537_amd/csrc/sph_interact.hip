@@ -365,15 +365,13 @@ __global__ __launch_bounds__(kBlock) void k_interact_sgpr(
     }
     const int xmin = __builtin_amdgcn_readfirstlane(xmn);
     const int xmax = __builtin_amdgcn_readfirstlane(xmx);
-    // the target in the wave frame (cell-relative offset moved to cell xmin);
     // the support test is folded with the membership rules: lanes whose
     // target is not in this row, and wall targets facing wall candidates,
     // compare against -1
-    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
     const float thr_any = inrow ? kp.support2_f : -1.f;
     const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
-    sgpr_row<DIM, R>(kp, 0u, ry, rz, xmin, xmax, xa, pa.y, pa.z, thr_any, thr_fluid, T, L, lane,
-                     pr, vp, cstart, acc);
+    sgpr_row<DIM, R>(kp, 0u, ry, rz, xmin, xmax, pa.x, cx, pa.y, pa.z, thr_any, thr_fluid, T, L,
+                     lane, pr, vp, cstart, acc);
     todo = todo && !inrow;
   }
   float fmag = 0.f, vmax_out = 0.f;

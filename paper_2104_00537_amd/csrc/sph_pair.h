@@ -159,12 +159,19 @@ struct SgLds {
 // coordinates ry, rz and x extent [xmin, xmax]; cell indices are offset by
 // cbase) through the scalar candidate pipeline, accumulating each in-row
 // lane's pair terms into acc.  Uniform across the wave; lanes whose target is
-// not in the row carry thresholds of -1 and take no hits.
+// not in the row carry thresholds of -1 and take no hits.  pax is the
+// target's cell-relative x offset and cx its cell's x index.
+//
+// Relative positions are taken in the frame of the target's own cell:
+// r_ab = (x_a - (c_b - c_a) cs) - x_b with cell-relative offsets, so a pair's
+// arithmetic does not depend on which targets share the wave (results are
+// the same whatever the launch packs together).
 template <int DIM, int R>
 __device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int ry, int rz,
-                                         int xmin, int xmax, float xa, float ya, float za,
-                                         float thr_any, float thr_fluid, const TargetData& T,
-                                         SgLds& L, int lane, const float4* __restrict__ pr,
+                                         int xmin, int xmax, float pax, int cx, float ya,
+                                         float za, float thr_any, float thr_fluid,
+                                         const TargetData& T, SgLds& L, int lane,
+                                         const float4* __restrict__ pr,
                                          const float4* __restrict__ vp,
                                          const uint32_t* __restrict__ cstart, PairAcc& acc) {
   // this lane's list: entry k at list[k][lane]; wp points past the last hit
@@ -185,7 +192,8 @@ __device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int 
         const float4 sh = L.shift[e >> kSgJBits];
         const float4 pb = pr[j];
         const float4 vb = vp[j];
-        const float dx = (xa - sh.x) - pb.x;
+        const float sx = (float)(__float_as_int(sh.x) - cx) * kp.cs_f;
+        const float dx = (pax - sx) - pb.x;
         const float dy = (ya - sh.y) - pb.y;
         const float dz = DIM == 3 ? (za - sh.z) - pb.z : 0.f;
         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -213,12 +221,13 @@ __device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int 
           drain();
           ncs = 0;
         }
-        const float sx = (float)(x - xmin) * kp.cs_f, sy = (float)dy * kp.cs_f,
-                    sz = (float)dz * kp.cs_f;
-        if (lane == 0) L.shift[ncs] = make_float4(sx, sy, sz, 0.f);
+        // the shift table keeps the cell's x index (as bits) and its y, z shifts
+        const float sy = (float)dy * kp.cs_f, sz = (float)dz * kp.cs_f;
+        if (lane == 0) L.shift[ncs] = make_float4(__int_as_float(x), sy, sz, 0.f);
         const uint32_t tag = (uint32_t)ncs << kSgJBits;
         ++ncs;
-        const float xs = xa - sx, ys = ya - sy, zs = za - sz;
+        const float sx = (float)(x - cx) * kp.cs_f;
+        const float xs = pax - sx, ys = ya - sy, zs = za - sz;
         // candidates in groups of 4 (one 64-B scalar load), the next group
         // prefetched; the views are padded so a group may run past j1
         float4 q0 = pr[j0], q1 = pr[j0 + 1], q2 = pr[j0 + 2], q3 = pr[j0 + 3];

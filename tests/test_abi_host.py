@@ -123,3 +123,48 @@ def test_workspace_and_pointer_checks_without_device(S):
                                    need, None) == S.SPH_E_ARG
     assert lib.sph_read_error(None) == S.SPH_E_ARG
     assert lib.sph_strerror(S.SPH_E_WORKSPACE) == b"workspace too small"
+
+
+def test_batch_describe_host_only(S):
+    """The slot table is built on the host: key ranges are the cells of the
+    slots before plus one each, offsets are validated, cell_div must agree."""
+    from paper_2104_00537_amd import cases
+    cs = [cases.dam_break_2d(dp=0.02), cases.block_case(3, (5, 4, 3)),
+          cases.dam_break_2d(dp=0.04)]
+    P = [S.make_params(c.params) for c in cs]
+    offs = [0]
+    for c in cs:
+        offs.append(offs[-1] + c.n)
+    b, host = S.sph_batch_describe(P, offs)
+    assert b.n_slots == 3 and b.n_total == offs[-1] and b.cell_div == 1
+    assert b.key_cells == sum(c.params.ncell_total() + 1 for c in cs)
+    assert host.size == S.lib.sph_batch_table_bytes(3) > 0
+    assert S.sph_batch_workspace_bytes(b) >= S.sph_workspace_bytes(P[0], offs[-1])
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe(P, [1] + offs[1:])            # offsets[0] != 0
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe(P, [0, offs[2], offs[1], offs[3]])   # decreasing
+    cd2 = cases.dam_break_2d(dp=0.02, cell_div=2)
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe([P[0], S.make_params(cd2.params)], [0, 10, 20])
+    assert S.lib.sph_batch_table_bytes(0) == 0
+    assert S.lib.sph_batch_table_bytes(S.SPH_BATCH_MAX_SLOTS + 1) == 0
+
+
+def test_batch_calls_validate_without_device(S):
+    lib = S.lib
+    b = S.SphBatch(2, 1, 100, 50, None)   # no table: rejected
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, None)
+    st2 = S.SphState(32, 16, 16, 16, None)
+    assert lib.sph_batch_bin_cells(C.byref(b), C.byref(st), C.byref(st2), None, None, d, d, d, d,
+                                   1 << 30, None) == S.SPH_E_ARG
+    b.table = 16
+    assert lib.sph_batch_bin_cells(C.byref(b), C.byref(st), C.byref(st2), None, None, d, d, d, d,
+                                   16, None) == S.SPH_E_WORKSPACE
+    b.n_total = 1 << 27                    # beyond the packed-index range
+    assert lib.sph_batch_interact(C.byref(b), C.byref(st), d, d, d, d, None, None, d, 1 << 40,
+                                  None) == S.SPH_E_ARG
+    b.n_total = 100
+    assert lib.sph_batch_symplectic_step(C.byref(b), 3, d, d, C.byref(st), C.byref(st), d, d, d,
+                                         1 << 30, None) == S.SPH_E_ARG
