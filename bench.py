@@ -90,6 +90,7 @@ def cpu_baseline(case, sim, seconds):
 def serving(args):
     """The request stream through the batched engine and the plain
     one-case-at-a-time path (same seeded trace, same GPU)."""
+    import numpy as np
     import torch
     from paper_2104_00537_amd import serve as V
     kw = dict(n_min=args.serve_n_min, n_max=args.serve_n_max, steps_min=1000, steps_max=5000,
@@ -109,7 +110,9 @@ def serving(args):
     V.serve_plain(V.make_stream(1, 1e6, seed=98, n_min=2000, n_max=3000, steps_min=4,
                                 steps_max=4))
     torch.cuda.synchronize()
+    print("[bench] serving: batched engine", file=sys.stderr, flush=True)
     out["batched"] = V.serve_batched(reqs, eng)
+    print("[bench] serving: plain path", file=sys.stderr, flush=True)
     reqs2 = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
     out["plain"] = V.serve_plain(reqs2)
     out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
@@ -168,7 +171,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="dam_break_3d_1m")
-    ap.add_argument("--cell-div", type=int, default=1)
+    ap.add_argument("--cell-div", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mode", choices=["step", "interact", "copy"], default="step",
                     help="step: the benchmark; interact/copy: kernel-only runs for counters")
@@ -250,6 +253,8 @@ def main():
                      "flops_per_launch": flops, "avg_launch_ms": phase_ms["interact"],
                      "hbm_algorithmic_GBs": bytes_per_launch / t_int / 1e9},
     }
+    print(f"[bench] timed {args.steps} steps: {pairs / el:.4g} interactions/s", file=sys.stderr,
+          flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:

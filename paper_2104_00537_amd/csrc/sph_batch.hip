@@ -47,9 +47,10 @@ __global__ void k_batch_reorder(const SlotEntry* __restrict__ tab, int ns, int64
   }
 }
 
-// The scalar-stream interaction over all slots: as k_interact_sgpr, with the
-// row loop also splitting a wave's targets by slot and each row using its
-// slot's constants.  Per-slot maxima and pair counts are combined with
+// The interaction over all slots in one launch: one lane per target walking
+// its own cells (gather_walk), with the constants of the target's slot.  The
+// lanes of a wave are processed slot by slot (almost always one slot), so the
+// constants stay uniform.  Per-slot maxima and pair counts are combined with
 // order-independent atomics (max of non-negative float bits, integer adds).
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_batch_interact(
@@ -57,92 +58,46 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const float4* __restrict__ vp, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
     float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc) {
-  __shared__ SgLds lds_all[kBlock / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  SgLds& L = lds_all[wv];
-  const int64_t a = ((int64_t)blockIdx.x * (kBlock / 64) + wv) * 64 + lane;
-  int sa = -1;
-  bool valid = false;
-  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
-  int cx = 0, cy = 0, cz = 0;
-  if (a < n) {
-    sa = find_slot(tab, ns, a);
-    const uint32_t lk = key[a] - tab[sa].cbase;
-    const int ncx = tab[sa].kp.ncx, ncy = tab[sa].kp.ncy;
-    valid = lk < tab[sa].kp.ncell_total;
-    if (valid) {
-      pa = pr[a];
-      const float4 va = vp[a];
-      cx = (int)(lk % (uint32_t)ncx);
-      const uint32_t rest = lk / (uint32_t)ncx;
-      cy = (int)(rest % (uint32_t)ncy);
-      cz = (int)(rest / (uint32_t)ncy);
-      T.fluid = pa.w > 0.f;
-      T.rho = fabsf(pa.w);
-      T.irho = __builtin_amdgcn_rcpf(T.rho);
-      T.p = va.w;
-      T.vx = va.x;
-      T.vy = va.y;
-      T.vz = va.z;
-    }
-  }
-  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-  float gx = 0.f, gy = 0.f, gz = 0.f, ddt = 0.f;
-  bool todo = valid;
-  while (__ballot(todo) != 0ull) {
-    const uint64_t rem = __ballot(todo);
-    const int leader = (int)__builtin_ctzll(rem);
-    const int rs = __builtin_amdgcn_readlane(sa, leader);
-    const int ry = __builtin_amdgcn_readlane(cy, leader);
-    const int rz = __builtin_amdgcn_readlane(cz, leader);
-    const bool inrow = todo && sa == rs && cy == ry && cz == rz;
-    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
-    for (int off = 32; off > 0; off >>= 1) {
-      xmn = min(xmn, __shfl_xor(xmn, off, 64));
-      xmx = max(xmx, __shfl_xor(xmx, off, 64));
-    }
-    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
-    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
-    const KParams kp = tab[rs].kp;
-    const uint32_t cbase = tab[rs].cbase;
-    const float thr_any = inrow ? kp.support2_f : -1.f;
-    const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
-    if (inrow) {
-      gx = kp.gx_f;
-      gy = kp.gy_f;
-      gz = kp.gz_f;
-      ddt = kp.ddt_coef_f;
-    }
-    sgpr_row<3, R>(kp, cbase, ry, rz, xmin, xmax, pa.x, cx, pa.y, pa.z, thr_any, thr_fluid, T, L,
-                   lane, pr, vp, cstart, acc);
-    todo = todo && !inrow;
-  }
+  const int lane = threadIdx.x & 63;
+  const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int sa = a < n ? find_slot(tab, ns, a) : -1;
   float fmag = 0.f, vmx = 0.f;
   uint32_t cnt = 0, cntw = 0, nfl = 0;
-  if (valid) {
-    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);  // the target is not its own neighbour
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    float ar = T.rho * acc.cont;
-    if (T.fluid) {
-      ax = acc.ax + gx;
-      ay = acc.ay + gy;
-      az = acc.az + gz;
-      ar += ddt * acc.diff;
-      fmag = sqrtf(ax * ax + ay * ay + az * az);
-      vmx = acc.vmax;
-      nfl = 1;
+  bool todo = a < n;
+  while (__ballot(todo) != 0ull) {
+    const int leader = (int)__builtin_ctzll(__ballot(todo));
+    const int rs = __builtin_amdgcn_readlane(sa, leader);
+    const bool mine = todo && sa == rs;
+    const KParams kp = tab[rs].kp;
+    const uint32_t cbase = tab[rs].cbase;
+    if (mine) {
+      const uint32_t lk = key[a] - cbase;
+      if (lk < kp.ncell_total) {
+        PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+        TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const float4 pa = pr[a], va = vp[a];
+        T.fluid = pa.w > 0.f;
+        T.rho = fabsf(pa.w);
+        T.irho = __builtin_amdgcn_rcpf(T.rho);
+        T.p = va.w;
+        T.vx = va.x;
+        T.vy = va.y;
+        T.vz = va.z;
+        const int cx = (int)(lk % (uint32_t)kp.ncx);
+        const uint32_t rest = lk / (uint32_t)kp.ncx;
+        const int cy = (int)(rest % (uint32_t)kp.ncy);
+        const int cz = (int)(rest / (uint32_t)kp.ncy);
+        uint32_t c64 = 0;
+        gather_walk<3, R, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
+                                 acc, c64);
+        write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
+        cnt = acc.cnt;
+        cntw = T.fluid ? 0u : acc.cnt;
+      } else {
+        write_zero<3>(n, a, ace, arho, visc, nbr);
+      }
     }
-    ace[a] = ax;
-    ace[n + a] = ay;
-    ace[2 * n + a] = az;
-    arho[a] = ar;
-    if (visc) visc[a] = acc.vmax;
-    if (nbr) nbr[a] = c;
-    cnt = c;
-    cntw = T.fluid ? 0u : c;
-  } else if (a < n) {
-    write_zero<3>(n, a, ace, arho, visc, nbr);
+    todo = todo && !mine;
   }
   // per-slot combination: one pass per distinct slot among the wave's lanes
   bool pend = a < n;

@@ -2,8 +2,12 @@
 // continuity and momentum sums over neighbours within 2h, on gfx950.
 //
 // Four kernels share the pair arithmetic:
-//  * k_interact_sgpr (production): a wave walks one candidate stream for its
-//    64 targets with candidates in SGPRs; hits go to per-lane LDS lists.
+//  * k_interact_gather (production): one lane per target walking its own
+//    cells; candidates are loaded in groups of 4 (all loads in flight at
+//    once), then the velocities of the group's neighbours.  It also offers the
+//    FP64 diagnostic neighbour count.
+//  * k_interact_sgpr: a wave walks one candidate stream for its 64 targets
+//    with candidates in SGPRs; hits go to per-lane LDS lists.
 //  * k_interact_compact: one lane per target walking its own
 //    cells, hits compacted into per-lane LDS lists, pair terms run densely.
 //  * k_interact_tile: a wavefront takes kTileG consecutive sorted
@@ -12,8 +16,6 @@
 //    kTileTPL-th staged candidate against its target and appends the hits to
 //    its own LDS list; the pair terms then run densely over the lists.  The
 //    partial sums of the lanes of a target are combined at the end.
-//  * k_interact_gather: one lane per target walking its own cells in global
-//    memory.  It also offers the FP64 diagnostic neighbour count.
 // Sums are gathered per target (no atomics): results are deterministic.
 #include <stdlib.h>
 
@@ -238,19 +240,32 @@ __global__ __launch_bounds__(kBlock) void k_interact_compact(
     T.vz = va.z;
   }
   PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  // wall targets ignore wall candidates (Eq. 36)
+  const float thr_fluid = T.fluid ? kp.support2_f : -1.f;
   int cnt = 0;
   auto drain = [&]() {
     wave_sync();
     int m = cnt;
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
     m = __builtin_amdgcn_readfirstlane(m);
+    // software pipeline: the next hit's entry and data are fetched while the
+    // current pair is computed; lanes past their count fetch particle 0 (always
+    // readable: the views are padded), never a stale or unwritten entry
+    uint32_t jn = cnt > 0 ? list_j[0][tid] : 0u;
+    int cn = cnt > 0 ? list_c[0][tid] : 0;
+    float4 pbn = pr[jn], vbn = vp[jn];
     for (int k = 0; k < m; ++k) {
+      const float4 pb = pbn, vb = vbn;
+      const int code = cn;
+      if (k + 1 < m) {
+        const bool more = k + 1 < cnt;
+        jn = more ? list_j[k + 1][tid] : 0u;
+        cn = more ? list_c[k + 1][tid] : 0;
+        pbn = pr[jn];
+        vbn = vp[jn];
+      }
       if (k < cnt) {
-        const uint32_t j = list_j[k][tid];
-        const int code = list_c[k][tid];
         const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
-        const float4 pb = pr[j];
-        const float4 vb = vp[j];
         const float dx = pa.x - (pb.x + (float)ox * kp.cs_f);
         const float dy = pa.y - (pb.y + (float)oy * kp.cs_f);
         const float dz = DIM == 3 ? pa.z - (pb.z + (float)oz * kp.cs_f) : 0.f;
@@ -281,19 +296,25 @@ __global__ __launch_bounds__(kBlock) void k_interact_compact(
         const uint8_t code = (uint8_t)((ox + R) + W * ((oy + R) + W * (oz + R)));
         for (uint32_t k0 = 0; k0 < m; k0 += kCompU) {
           if (__ballot(cnt > kCompLCap - kCompU) != 0ull) drain();
+          // all loads of the group in flight together; indices clamped into
+          // the lane's own cell (or to 0 for an empty one)
+          float4 pbs[kCompU];
 #pragma unroll
           for (int u = 0; u < kCompU; ++u) {
             const uint32_t k = k0 + u;
-            if (k < len) {
-              const uint32_t j = j0 + k;
-              const float4 pb = pr[j];
-              const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
-              const float r2 = dx * dx + dy * dy + dz * dz;
-              if (r2 < kp.support2_f && (T.fluid || pb.w > 0.f)) {
-                list_j[cnt][tid] = j;
-                list_c[cnt][tid] = code;
-                ++cnt;
-              }
+            pbs[u] = pr[len == 0 ? 0u : j0 + (k < len ? k : len - 1)];
+          }
+#pragma unroll
+          for (int u = 0; u < kCompU; ++u) {
+            const uint32_t k = k0 + u;
+            const float4 pb = pbs[u];
+            const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float thr = __float_as_int(pb.w) > 0 ? kp.support2_f : thr_fluid;
+            if (k < len && r2 < thr) {
+              list_j[cnt][tid] = j0 + k;
+              list_c[cnt][tid] = code;
+              ++cnt;
             }
           }
         }
@@ -389,17 +410,15 @@ __global__ __launch_bounds__(kBlock) void k_interact_sgpr(
   write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
 }
 
-// ------------------------------------------- interaction: gather (simple) --
-// One lane per target particle (sorted order).  The lane walks the (2R+1)^d
-// cells around its own cell (R = cell_div), reads each candidate's view from
-// global memory and accumulates in registers.
-template <int DIM, int R>
+// ------------------------------------------------- interaction: gather --
+// One lane per target particle (sorted order): the production kernel.
+template <int DIM, int R, bool DIAG>
 __global__ __launch_bounds__(kBlock) void k_interact_gather(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
     const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    uint32_t flags, BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
@@ -421,48 +440,8 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
       const uint32_t rest = k / (uint32_t)kp.ncx;
       const int cy = (int)(rest % (uint32_t)kp.ncy);
       const int cz = (int)(rest / (uint32_t)kp.ncy);
-      const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
-      double pa64[3] = {0.0, 0.0, 0.0};
-      if (diag)
-        for (int d = 0; d < DIM; ++d) pa64[d] = pos64[d * n + i];
-      const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-      for (int dz = zlo; dz <= zhi; ++dz) {
-        const int z = cz + dz;
-        if (z < 0 || z >= kp.ncz) continue;
-        for (int dy = -R; dy <= R; ++dy) {
-          const int y = cy + dy;
-          if (y < 0 || y >= kp.ncy) continue;
-          const int x0 = cx - R < 0 ? 0 : cx - R;
-          const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
-          const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-          const float sy = (float)dy * kp.cs_f, sz = (float)dz * kp.cs_f;
-          for (int x = x0; x <= x1; ++x) {
-            const uint32_t j0 = cstart[row + x], j1 = cstart[row + x + 1];
-            const float sx = (float)(x - cx) * kp.cs_f;
-            for (uint32_t j = j0; j < j1; ++j) {
-              if ((int64_t)j == i) continue;
-              const float4 pb = pr[j];
-              const bool fb = pb.w > 0.f;
-              if (!T.fluid && !fb) continue;  // Eq. 36: walls see fluid only
-              const float dx = pa.x - (pb.x + sx);
-              const float dy_ = pa.y - (pb.y + sy);
-              const float dz_ = DIM == 3 ? pa.z - (pb.z + sz) : 0.f;
-              const float r2 = dx * dx + dy_ * dy_ + dz_ * dz_;
-              if (diag) {
-                double r2d = 0.0;
-                for (int d = 0; d < DIM; ++d) {
-                  const double e = __dsub_rn(pa64[d], pos64[d * n + j]);
-                  r2d = __dadd_rn(r2d, __dmul_rn(e, e));
-                }
-                c64 += (r2d < kp.support2) ? 1u : 0u;
-              }
-              if (!(r2 < kp.support2_f)) continue;
-              pair_terms<DIM>(kp, T, dx, dy_, dz_, r2, pb, vp[j], acc);
-            }
-          }
-        }
-      }
-      const uint32_t c = diag ? c64 : acc.cnt;
+      gather_walk<DIM, R, DIAG>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart, pos64, acc, c64);
+      const uint32_t c = DIAG ? c64 : acc.cnt;
       write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
       cnt_out = acc.cnt;
       cnt_wall = T.fluid ? 0u : acc.cnt;
@@ -474,7 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
 }
 
 // Kernel choice: SPH_INTERACT_KERNEL = gather | tile | compact | sgpr (default
-// sgpr) for comparisons; the FP64 diagnostic count always uses gather.
+// gather, the fastest measured) for comparisons; the FP64 diagnostic count
+// always uses gather.
 enum { kKGather = 0, kKTile = 1, kKCompact = 2, kKSgpr = 3 };
 static int kernel_choice(uint32_t flags, int64_t n) {
   if (flags & SPH_DIAG_COUNT_F64) return kKGather;
@@ -483,7 +463,8 @@ static int kernel_choice(uint32_t flags, int64_t n) {
   if (e && e[0] == 't') return kKTile;
   if (e && e[0] == 'c') return kKCompact;
   // the scalar-stream kernel packs the particle index in kSgJBits bits
-  return n < ((int64_t)1 << kSgJBits) ? kKSgpr : kKGather;
+  if (e && e[0] == 's' && n < ((int64_t)1 << kSgJBits)) return kKSgpr;
+  return kKGather;
 }
 
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
@@ -522,13 +503,22 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   } else if (choice == kKGather) {
     const int64_t nb = (n + kBlock - 1) / kBlock;
     const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
-#define SPH_LAUNCH(D, RR)                                                                        \
-  hipLaunchKernelGGL((k_interact_gather<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
-                     key, cell_start, s.type, s.pos, ace, arho, visc, nbr, flags, red, hdr)
+#define SPH_LAUNCH(D, RR, G)                                                                   \
+  hipLaunchKernelGGL((k_interact_gather<D, RR, G>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
+                     vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr)
+    const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
     if (kp.dim == 2) {
-      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+      if (kp.cell_div == 1) {
+        if (diag) SPH_LAUNCH(2, 1, true); else SPH_LAUNCH(2, 1, false);
+      } else {
+        if (diag) SPH_LAUNCH(2, 2, true); else SPH_LAUNCH(2, 2, false);
+      }
     } else {
-      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+      if (kp.cell_div == 1) {
+        if (diag) SPH_LAUNCH(3, 1, true); else SPH_LAUNCH(3, 1, false);
+      } else {
+        if (diag) SPH_LAUNCH(3, 2, true); else SPH_LAUNCH(3, 2, false);
+      }
     }
 #undef SPH_LAUNCH
   } else {

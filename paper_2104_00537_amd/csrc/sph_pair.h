@@ -185,13 +185,22 @@ __device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int 
     int m = cnt;
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
     m = __builtin_amdgcn_readfirstlane(m);
+    // software pipeline: the next hit's entry and data are fetched while the
+    // current pair is computed; lanes past their count fetch particle 0 (always
+    // readable: the views are padded), never a stale or unwritten entry
+    uint32_t en = cnt > 0 ? L.list[0][lane] : 0u;
+    float4 pbn = pr[en & ((1u << kSgJBits) - 1u)], vbn = vp[en & ((1u << kSgJBits) - 1u)];
     for (int k = 0; k < m; ++k) {
+      const uint32_t e = en;
+      const float4 pb = pbn, vb = vbn;
+      if (k + 1 < m) {
+        en = k + 1 < cnt ? L.list[k + 1][lane] : 0u;
+        const uint32_t jn = en & ((1u << kSgJBits) - 1u);
+        pbn = pr[jn];
+        vbn = vp[jn];
+      }
       if (k < cnt) {
-        const uint32_t e = L.list[k][lane];
-        const uint32_t j = e & ((1u << kSgJBits) - 1u);
         const float4 sh = L.shift[e >> kSgJBits];
-        const float4 pb = pr[j];
-        const float4 vb = vp[j];
         const float sx = (float)(__float_as_int(sh.x) - cx) * kp.cs_f;
         const float dx = (pax - sx) - pb.x;
         const float dy = (ya - sh.y) - pb.y;
@@ -260,6 +269,81 @@ __device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int 
     }
   }
   drain();
+}
+
+// ---------------------------------------------------------- gather walk --
+// The candidate walk of one target lane over its (2R+1)^d neighbour cells
+// (cell indices offset by cbase): candidates are read in groups of 4 with all
+// loads in flight together (the views are padded, so a group may run past the
+// cell), tested, then the velocities of the group's neighbours are loaded
+// together and their pair terms accumulated.  Relative positions are taken in
+// the frame of the target's cell.  DIAG also counts neighbours with an FP64
+// test on the FP64 positions (c64).  Wall targets ignore wall candidates
+// (Eq. 36); the target itself is skipped.
+template <int DIM, int R, bool DIAG>
+__device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
+                                            int64_t i, const float4& pa, const TargetData& T,
+                                            int cx, int cy, int cz,
+                                            const float4* __restrict__ pr,
+                                            const float4* __restrict__ vp,
+                                            const uint32_t* __restrict__ cstart,
+                                            const double* __restrict__ pos64, PairAcc& acc,
+                                            uint32_t& c64) {
+  double pa64[3] = {0.0, 0.0, 0.0};
+  if (DIAG)
+    for (int d = 0; d < DIM; ++d) pa64[d] = pos64[d * n + i];
+  const float thr_any = kp.support2_f;
+  const float thr_fluid = T.fluid ? kp.support2_f : -1.f;
+  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = cz + dz;
+    if (z < 0 || z >= kp.ncz) continue;
+    for (int dy = -R; dy <= R; ++dy) {
+      const int y = cy + dy;
+      if (y < 0 || y >= kp.ncy) continue;
+      const int x0 = cx - R < 0 ? 0 : cx - R;
+      const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
+      const uint32_t row =
+          cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+      const float ys = pa.y - (float)dy * kp.cs_f, zs = pa.z - (float)dz * kp.cs_f;
+      for (int x = x0; x <= x1; ++x) {
+        const uint32_t j0 = cstart[row + x], j1 = cstart[row + x + 1];
+        const float xs = pa.x - (float)(x - cx) * kp.cs_f;
+        for (uint32_t j = j0; j < j1; j += 4) {
+          float4 pb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pb[u] = pr[j + u];
+          bool hit[4];
+          float dxs[4], dys[4], dzs[4], r2s[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t jj = j + u;
+            dxs[u] = xs - pb[u].x;
+            dys[u] = ys - pb[u].y;
+            dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
+            r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
+            const float thr = __float_as_int(pb[u].w) > 0 ? thr_any : thr_fluid;
+            hit[u] = jj < j1 && (int64_t)jj != i && r2s[u] < thr;
+            if (DIAG && jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
+              double r2d = 0.0;
+              for (int d = 0; d < DIM; ++d) {
+                const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
+                r2d = __dadd_rn(r2d, __dmul_rn(e, e));
+              }
+              c64 += (r2d < kp.support2) ? 1u : 0u;
+            }
+          }
+          float4 vb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (hit[u]) vb[u] = vp[j + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (hit[u]) pair_terms<DIM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u], vb[u], acc);
+        }
+      }
+    }
+  }
 }
 
 }  // namespace sph
