@@ -42,6 +42,31 @@ PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
 
+def measured_traffic(kernel, workload_name):
+    """HBM bytes per launch of the interaction kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload_name}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch",
+                                                  "kernel_source_sha256", "kernel_sources"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for src in fields["kernel_sources"].split():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != fields["kernel_source_sha256"]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def workload(name, cell_div):
     from paper_2104_00537_amd import cases
     if name == "dam_break_3d_1m":
@@ -228,6 +253,8 @@ def main():
     # algorithmic bytes of one interaction launch: per particle the view read
     # (2 x 16 B), ace + arho written (4 x 4 B), key and cell range reads (8 B)
     bytes_per_launch = case.n * (32 + 16 + 8)
+    kernel = "k_interact_gather"
+    traffic = measured_traffic(kernel, args.workload) if args.cell_div == 2 else None
     res = {
         "metric": METRIC,
         "value": pairs / el,
@@ -248,9 +275,10 @@ def main():
         "interactions_per_step": pairs / args.steps,
         "phase_ms_per_call": phase_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_interact_gather",
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "bytes/launch", "kernel": kernel,
                      "flops_per_launch": flops, "avg_launch_ms": phase_ms["interact"],
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
                      "hbm_algorithmic_GBs": bytes_per_launch / t_int / 1e9},
     }
     print(f"[bench] timed {args.steps} steps: {pairs / el:.4g} interactions/s", file=sys.stderr,
