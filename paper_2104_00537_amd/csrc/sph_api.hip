@@ -50,6 +50,8 @@ KParams make_kparams(const sph_params& p) {
   k.mass_f_f = (float)p.mass_fluid;
   k.mass_b_f = (float)p.mass_bound;
   k.cs_f = (float)p.cell_size;
+  k.frame_f = (float)(kFrameCells * p.cell_size);
+  k.inv_frame_f = (float)(1.0 / (kFrameCells * p.cell_size));
   k.gx_f = (float)p.gravity[0];
   k.gy_f = (float)p.gravity[1];
   k.gz_f = (float)p.gravity[2];

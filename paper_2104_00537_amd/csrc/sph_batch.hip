@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
     float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc) {
   const int lane = threadIdx.x & 63;
-  const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t a = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int sa = a < n ? find_slot(tab, ns, a) : -1;
   float fmag = 0.f, vmx = 0.f;
   uint32_t cnt = 0, cntw = 0, nfl = 0;

@@ -31,11 +31,13 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
 
 // Gathers particle src into sorted slot i and writes the two float4 the
 // interaction reads (the "view"):
-//   pr = {cell-relative position (dim components), 0, +rho fluid / -rho wall}
+//   pr = {local position (dim components), 0, +rho fluid / -rho wall}
 //   vp = {velocity (dim components), 0, P}
-// lkey is the particle's key relative to its case.  The cell-relative FP32
-// offset is x - (origin + c cs) evaluated in FP64 (the precision scheme of
-// Section 5.1: FP64 positions, FP32 distances inside the cell).  P is the
+// lkey is the particle's key relative to its case.  The local FP32 offset is
+// x - (origin + c cs) evaluated in FP64, with c the particle's cell along y
+// and z and the first cell of its block of kFrameCells cells along x (the
+// precision scheme of Section 5.1: FP64 positions, FP32 distances within a
+// few cells, so the FP32 error does not grow with the domain).  P is the
 // Tait pressure of Eq. 28, per particle in FP64; for gamma = 7 as the
 // expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the small pressures
 // of a nearly incompressible fluid free of cancellation.  Returns true if the
@@ -79,7 +81,9 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
   const double org[3] = {kp.ox, kp.oy, kp.oz};
   float o[3] = {0.f, 0.f, 0.f};
-  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)c[d] * kp.cs));
+  // x: offset from the first cell of the particle's block of kFrameCells cells
+  const int cb[3] = {c0 - c0 % kFrameCells, c[1], c[2]};
+  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)cb[d] * kp.cs));
   const double r = (double)rho;
   const double u = r / kp.rho0 - 1.0;
   double pw;

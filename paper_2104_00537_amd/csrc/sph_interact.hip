@@ -1,414 +1,16 @@
 // Particle interaction (Section 2.3 of the DualSPHysics v5.0 paper): the
 // continuity and momentum sums over neighbours within 2h, on gfx950.
 //
-// Four kernels share the pair arithmetic:
-//  * k_interact_gather (production): one lane per target walking its own
-//    cells; candidates are loaded in groups of 4 (all loads in flight at
-//    once), then the velocities of the group's neighbours.  It also offers the
-//    FP64 diagnostic neighbour count.
-//  * k_interact_sgpr: a wave walks one candidate stream for its 64 targets
-//    with candidates in SGPRs; hits go to per-lane LDS lists.
-//  * k_interact_compact: one lane per target walking its own
-//    cells, hits compacted into per-lane LDS lists, pair terms run densely.
-//  * k_interact_tile: a wavefront takes kTileG consecutive sorted
-//    targets with kTileTPL lanes per target.  The union of their neighbour-cell
-//    rows is staged in LDS in a frame common to the wave; each lane tests every
-//    kTileTPL-th staged candidate against its target and appends the hits to
-//    its own LDS list; the pair terms then run densely over the lists.  The
-//    partial sums of the lanes of a target are combined at the end.
-// Sums are gathered per target (no atomics): results are deterministic.
-#include <stdlib.h>
-
+// One lane per target particle in sorted order walks the rows of its
+// neighbour cells (gather_walk).  Consecutive blocks cover consecutive targets
+// and are placed so that each XCD runs one contiguous share of them: the
+// neighbour views a block reads were then mostly brought into that XCD's L2
+// by its predecessors.  Sums are gathered per target (no atomics): results are
+// deterministic.
 #include "sph_kernels.h"
 #include "sph_pair.h"
 
 namespace sph {
-
-// ------------------------------------------------ interaction: LDS tiles --
-constexpr int kTileWaves = 2;            // independent waves per block
-constexpr int kTileTPL = 4;              // lanes per target
-constexpr int kTileG = 64 / kTileTPL;    // targets per wave
-constexpr int kTileMaxC = 512;           // staged candidates per wave
-constexpr int kTileLCap = 64;            // hit-list entries per lane
-constexpr int kTileKCh = 16;             // candidates per lane between list checks
-static_assert(kTileWaves * kTileG == kTileTargets, "tile size");
-
-struct TileLds {
-  float4 cpos[kTileMaxC];          // candidate position in the wave frame, +-rho
-  float4 cvel[kTileMaxC];          // candidate velocity, pressure
-  uint16_t list[kTileLCap * 64];   // list[k*64 + lane]: staged index of hit k
-};
-
-template <int DIM, int R>
-__global__ __launch_bounds__(64 * kTileWaves) void k_interact_tile(
-    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
-    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
-    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
-  __shared__ TileLds lds_all[kTileWaves];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  TileLds& L = lds_all[wv];
-  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
-  const int tl = lane / kTileTPL, sub = lane % kTileTPL;
-  const int64_t a = ((int64_t)blockIdx.x * kTileWaves + wv) * kTileG + tl;
-  const bool valid = a < nvalid;
-
-  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
-  int cx = 0, cy = 0, cz = 0;
-  if (valid) {
-    pa = pr[a];
-    const float4 va = vp[a];
-    const uint32_t k = key[a];
-    cx = (int)(k % (uint32_t)kp.ncx);
-    const uint32_t rest = k / (uint32_t)kp.ncx;
-    cy = (int)(rest % (uint32_t)kp.ncy);
-    cz = (int)(rest / (uint32_t)kp.ncy);
-    T.fluid = pa.w > 0.f;
-    T.rho = fabsf(pa.w);
-    T.irho = __builtin_amdgcn_rcpf(T.rho);
-    T.p = va.w;
-    T.vx = va.x;
-    T.vy = va.y;
-    T.vz = va.z;
-  }
-  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-  bool todo = valid;
-  while (__ballot(todo) != 0ull) {
-    // the cell row (cy, cz) of the first remaining target, and the x extent
-    // of the remaining targets in that row
-    const uint64_t rem = __ballot(todo);
-    const int leader = (int)__builtin_ctzll(rem);
-    const int ry = __builtin_amdgcn_readlane(cy, leader);
-    const int rz = __builtin_amdgcn_readlane(cz, leader);
-    const bool inrow = todo && cy == ry && cz == rz;
-    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
-    for (int off = 32; off > 0; off >>= 1) {
-      xmn = min(xmn, __shfl_xor(xmn, off, 64));
-      xmx = max(xmx, __shfl_xor(xmx, off, 64));
-    }
-    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
-    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
-    // the target in the wave frame: its cell-relative offset shifted to cell xmin
-    const float xa = pa.x + (float)(cx - xmin) * kp.cs_f;
-    const float ya = pa.y, za = pa.z;
-    const bool fa = T.fluid;
-
-    // hit list of this lane: tests staged candidates sub, sub + TPL, ...
-    int cnt = 0;
-    auto drain = [&]() {
-      wave_sync();
-      int m = cnt;
-      for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-      m = __builtin_amdgcn_readfirstlane(m);
-      for (int k = 0; k < m; ++k) {
-        if (k < cnt) {
-          const int s = L.list[k * 64 + lane];
-          const float4 pb = L.cpos[s];
-          const float4 vb = L.cvel[s];
-          const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
-        }
-      }
-      wave_sync();
-      cnt = 0;
-    };
-    auto flush = [&](int nbuf) {
-      wave_sync();
-      const int kmax = (nbuf + kTileTPL - 1) / kTileTPL;
-      for (int k0 = 0; k0 < kmax; k0 += kTileKCh) {
-        if (__ballot(cnt > kTileLCap - kTileKCh) != 0ull) drain();
-        const int k1 = min(k0 + kTileKCh, kmax);
-        for (int k = k0; k < k1; ++k) {
-          const int s = k * kTileTPL + sub;
-          if (s < nbuf) {
-            const float4 pb = L.cpos[s];
-            const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (inrow && r2 < kp.support2_f && (fa || pb.w > 0.f)) {
-              L.list[cnt * 64 + lane] = (uint16_t)s;
-              ++cnt;
-            }
-          }
-        }
-      }
-      drain();
-    };
-
-    int nbuf = 0;
-    const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
-      const int z = rz + dz;
-      if (z < 0 || z >= kp.ncz) continue;
-      for (int dy = -R; dy <= R; ++dy) {
-        const int y = ry + dy;
-        if (y < 0 || y >= kp.ncy) continue;
-        const int xlo = max(xmin - R, 0), xhi = min(xmax + R, kp.ncx - 1);
-        const uint32_t rowbase = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-        const uint32_t j1 = cstart[rowbase + xhi + 1];
-        uint32_t jj = cstart[rowbase + xlo];
-        const float sy = (float)dy * kp.cs_f, sz = (float)dz * kp.cs_f;
-        while (jj < j1) {
-          const uint32_t take = min(min(j1 - jj, (uint32_t)(kTileMaxC - nbuf)), 64u);
-          if ((uint32_t)lane < take) {
-            const uint32_t j = jj + lane;
-            const float4 p = pr[j];
-            const float4 v = vp[j];
-            const float sx = (float)((int)(key[j] - rowbase) - xmin) * kp.cs_f;
-            L.cpos[nbuf + lane] = make_float4(p.x + sx, p.y + sy, p.z + sz, p.w);
-            L.cvel[nbuf + lane] = v;
-          }
-          nbuf += (int)take;
-          jj += take;
-          if (nbuf == kTileMaxC) {
-            flush(nbuf);
-            nbuf = 0;
-          }
-        }
-      }
-    }
-    if (nbuf > 0) flush(nbuf);
-    todo = todo && !inrow;
-  }
-
-  // combine the partial sums of the lanes of each target (adjacent lanes)
-  for (int off = 1; off < kTileTPL; off <<= 1) {
-    acc.ax += __shfl_xor(acc.ax, off, 64);
-    acc.ay += __shfl_xor(acc.ay, off, 64);
-    acc.az += __shfl_xor(acc.az, off, 64);
-    acc.cont += __shfl_xor(acc.cont, off, 64);
-    acc.diff += __shfl_xor(acc.diff, off, 64);
-    acc.vmax = fmaxf(acc.vmax, __shfl_xor(acc.vmax, off, 64));
-    acc.cnt += __shfl_xor(acc.cnt, off, 64);
-  }
-  float fmag = 0.f, vmax_out = 0.f;
-  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
-  if (valid && sub == 0) {
-    // a fluid target finds itself among its hits (r = 0: every term is zero);
-    // it is not its own neighbour
-    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
-    write_target<DIM>(kp, n, a, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
-    cnt_out = c;
-    cnt_wall = T.fluid ? 0u : c;
-  }
-  // excluded particles (sorted after the valid ones) get zeros
-  if (!valid && a < n && sub == 0) write_zero<DIM>(n, a, ace, arho, visc, nbr);
-  write_block_red<kTileWaves>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
-}
-
-// -------------------------------------- interaction: compacted own walk --
-// One lane per target particle (sorted order), as in the gather kernel, but
-// the lane only tests candidates while walking its (2R+1)^d cells: hits go to
-// a per-lane LDS list (global index + cell offset code), and the pair terms
-// run densely over the lists when a list is about to fill and at the end.
-// The candidate loop of each cell runs to the wave's largest cell count so
-// that the wave stays converged and can drain its lists together.
-constexpr int kCompLCap = 30;   // list entries per lane (4 blocks of 256 fit the LDS)
-constexpr int kCompU = 4;       // candidates per lane between list checks
-
-template <int DIM, int R>
-__global__ __launch_bounds__(kBlock) void k_interact_compact(
-    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
-    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
-    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
-  __shared__ uint32_t list_j[kCompLCap][kBlock];
-  __shared__ uint8_t list_c[kCompLCap][kBlock];
-  constexpr int W = 2 * R + 1;
-  const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + tid;
-  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
-  const bool valid = i < nvalid;
-  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
-  int cx = 0, cy = 0, cz = 0;
-  if (valid) {
-    pa = pr[i];
-    const float4 va = vp[i];
-    const uint32_t k = key[i];
-    cx = (int)(k % (uint32_t)kp.ncx);
-    const uint32_t rest = k / (uint32_t)kp.ncx;
-    cy = (int)(rest % (uint32_t)kp.ncy);
-    cz = (int)(rest / (uint32_t)kp.ncy);
-    T.fluid = pa.w > 0.f;
-    T.rho = fabsf(pa.w);
-    T.irho = __builtin_amdgcn_rcpf(T.rho);
-    T.p = va.w;
-    T.vx = va.x;
-    T.vy = va.y;
-    T.vz = va.z;
-  }
-  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-  // wall targets ignore wall candidates (Eq. 36)
-  const float thr_fluid = T.fluid ? kp.support2_f : -1.f;
-  int cnt = 0;
-  auto drain = [&]() {
-    wave_sync();
-    int m = cnt;
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    m = __builtin_amdgcn_readfirstlane(m);
-    // software pipeline: the next hit's entry and data are fetched while the
-    // current pair is computed; lanes past their count fetch particle 0 (always
-    // readable: the views are padded), never a stale or unwritten entry
-    uint32_t jn = cnt > 0 ? list_j[0][tid] : 0u;
-    int cn = cnt > 0 ? list_c[0][tid] : 0;
-    float4 pbn = pr[jn], vbn = vp[jn];
-    for (int k = 0; k < m; ++k) {
-      const float4 pb = pbn, vb = vbn;
-      const int code = cn;
-      if (k + 1 < m) {
-        const bool more = k + 1 < cnt;
-        jn = more ? list_j[k + 1][tid] : 0u;
-        cn = more ? list_c[k + 1][tid] : 0;
-        pbn = pr[jn];
-        vbn = vp[jn];
-      }
-      if (k < cnt) {
-        const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
-        const float dx = pa.x - (pb.x + (float)ox * kp.cs_f);
-        const float dy = pa.y - (pb.y + (float)oy * kp.cs_f);
-        const float dz = DIM == 3 ? pa.z - (pb.z + (float)oz * kp.cs_f) : 0.f;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
-      }
-    }
-    wave_sync();
-    cnt = 0;
-  };
-  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-  for (int oz = zlo; oz <= zhi; ++oz) {
-    for (int oy = -R; oy <= R; ++oy) {
-      for (int ox = -R; ox <= R; ++ox) {
-        const int x = cx + ox, y = cy + oy, z = cz + oz;
-        uint32_t j0 = 0, len = 0;
-        if (valid && x >= 0 && x < kp.ncx && y >= 0 && y < kp.ncy && z >= 0 && z < kp.ncz) {
-          const uint32_t c = (uint32_t)x + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-          j0 = cstart[c];
-          len = cstart[c + 1] - j0;
-        }
-        uint32_t m = len;
-        for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
-        m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
-        if (m == 0) continue;
-        const float sx = (float)ox * kp.cs_f, sy = (float)oy * kp.cs_f, sz = (float)oz * kp.cs_f;
-        const float xa = pa.x - sx, ya = pa.y - sy, za = pa.z - sz;
-        const uint8_t code = (uint8_t)((ox + R) + W * ((oy + R) + W * (oz + R)));
-        for (uint32_t k0 = 0; k0 < m; k0 += kCompU) {
-          if (__ballot(cnt > kCompLCap - kCompU) != 0ull) drain();
-          // all loads of the group in flight together; indices clamped into
-          // the lane's own cell (or to 0 for an empty one)
-          float4 pbs[kCompU];
-#pragma unroll
-          for (int u = 0; u < kCompU; ++u) {
-            const uint32_t k = k0 + u;
-            pbs[u] = pr[len == 0 ? 0u : j0 + (k < len ? k : len - 1)];
-          }
-#pragma unroll
-          for (int u = 0; u < kCompU; ++u) {
-            const uint32_t k = k0 + u;
-            const float4 pb = pbs[u];
-            const float dx = xa - pb.x, dy = ya - pb.y, dz = DIM == 3 ? za - pb.z : 0.f;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float thr = __float_as_int(pb.w) > 0 ? kp.support2_f : thr_fluid;
-            if (k < len && r2 < thr) {
-              list_j[cnt][tid] = j0 + k;
-              list_c[cnt][tid] = code;
-              ++cnt;
-            }
-          }
-        }
-      }
-    }
-  }
-  drain();
-  float fmag = 0.f, vmax_out = 0.f;
-  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
-  if (valid) {
-    // a fluid target finds itself among its hits (r = 0: every term is zero);
-    // it is not its own neighbour
-    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
-    write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
-    cnt_out = c;
-    cnt_wall = T.fluid ? 0u : c;
-  } else if (i < n) {
-    write_zero<DIM>(n, i, ace, arho, visc, nbr);
-  }
-  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
-}
-
-// ------------------------------------ interaction: scalar candidate stream --
-template <int DIM, int R>
-__global__ __launch_bounds__(kBlock) void k_interact_sgpr(
-    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
-    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart, float* __restrict__ ace,
-    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
-  __shared__ SgLds lds_all[kBlock / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  SgLds& L = lds_all[wv];
-  const int64_t nvalid = (int64_t)cstart[kp.ncell_total];
-  const int64_t a = ((int64_t)blockIdx.x * (kBlock / 64) + wv) * 64 + lane;
-  const bool valid = a < nvalid;
-  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float4 pa = make_float4(0.f, 0.f, 0.f, 0.f);
-  int cx = 0, cy = 0, cz = 0;
-  if (valid) {
-    pa = pr[a];
-    const float4 va = vp[a];
-    const uint32_t k = key[a];
-    cx = (int)(k % (uint32_t)kp.ncx);
-    const uint32_t rest = k / (uint32_t)kp.ncx;
-    cy = (int)(rest % (uint32_t)kp.ncy);
-    cz = (int)(rest / (uint32_t)kp.ncy);
-    T.fluid = pa.w > 0.f;
-    T.rho = fabsf(pa.w);
-    T.irho = __builtin_amdgcn_rcpf(T.rho);
-    T.p = va.w;
-    T.vx = va.x;
-    T.vy = va.y;
-    T.vz = va.z;
-  }
-  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-  bool todo = valid;
-  while (__ballot(todo) != 0ull) {
-    // the cell row of the first remaining target and the x extent of the
-    // remaining targets in that row
-    const uint64_t rem = __ballot(todo);
-    const int leader = (int)__builtin_ctzll(rem);
-    const int ry = __builtin_amdgcn_readlane(cy, leader);
-    const int rz = __builtin_amdgcn_readlane(cz, leader);
-    const bool inrow = todo && cy == ry && cz == rz;
-    int xmn = inrow ? cx : 0x7fffffff, xmx = inrow ? cx : -1;
-    for (int off = 32; off > 0; off >>= 1) {
-      xmn = min(xmn, __shfl_xor(xmn, off, 64));
-      xmx = max(xmx, __shfl_xor(xmx, off, 64));
-    }
-    const int xmin = __builtin_amdgcn_readfirstlane(xmn);
-    const int xmax = __builtin_amdgcn_readfirstlane(xmx);
-    // the support test is folded with the membership rules: lanes whose
-    // target is not in this row, and wall targets facing wall candidates,
-    // compare against -1
-    const float thr_any = inrow ? kp.support2_f : -1.f;
-    const float thr_fluid = (inrow && T.fluid) ? kp.support2_f : -1.f;
-    sgpr_row<DIM, R>(kp, 0u, ry, rz, xmin, xmax, pa.x, cx, pa.y, pa.z, thr_any, thr_fluid, T, L,
-                     lane, pr, vp, cstart, acc);
-    todo = todo && !inrow;
-  }
-  float fmag = 0.f, vmax_out = 0.f;
-  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
-  if (valid) {
-    // a fluid target finds itself among its hits (r = 0: every term is zero);
-    // it is not its own neighbour
-    const uint32_t c = acc.cnt - (T.fluid ? 1u : 0u);
-    write_target<DIM>(kp, n, a, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
-    cnt_out = c;
-    cnt_wall = T.fluid ? 0u : c;
-  } else if (a < n) {
-    write_zero<DIM>(n, a, ace, arho, visc, nbr);
-  }
-  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
-}
 
 // ------------------------------------------------- interaction: gather --
 // One lane per target particle (sorted order): the production kernel.
@@ -419,7 +21,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
     const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
     BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   if (i < n) {
@@ -452,21 +54,6 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
 }
 
-// Kernel choice: SPH_INTERACT_KERNEL = gather | tile | compact | sgpr (default
-// gather, the fastest measured) for comparisons; the FP64 diagnostic count
-// always uses gather.
-enum { kKGather = 0, kKTile = 1, kKCompact = 2, kKSgpr = 3 };
-static int kernel_choice(uint32_t flags, int64_t n) {
-  if (flags & SPH_DIAG_COUNT_F64) return kKGather;
-  const char* e = getenv("SPH_INTERACT_KERNEL");
-  if (e && e[0] == 'g') return kKGather;
-  if (e && e[0] == 't') return kKTile;
-  if (e && e[0] == 'c') return kKCompact;
-  // the scalar-stream kernel packs the particle index in kSgJBits bits
-  if (e && e[0] == 's' && n < ((int64_t)1 << kSgJBits)) return kKSgpr;
-  return kKGather;
-}
-
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, float* ace, float* arho, float* visc,
                            uint32_t* nbr, uint32_t flags, void* ws, hipStream_t st) {
@@ -475,64 +62,25 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   const float4* vp = ws_ptr<float4>(ws, L.view_vp);
   BlockRed* red = ws_ptr<BlockRed>(ws, L.red);
   WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
-  const int choice = kernel_choice(flags, n);
-  if (choice == kKSgpr) {
-    const int64_t nb = (n + kBlock - 1) / kBlock;
-    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
-#define SPH_LAUNCH(D, RR)                                                                      \
-  hipLaunchKernelGGL((k_interact_sgpr<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
-                     key, cell_start, ace, arho, visc, nbr, red, hdr)
-    if (kp.dim == 2) {
-      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
-    } else {
-      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
-    }
-#undef SPH_LAUNCH
-  } else if (choice == kKCompact) {
-    const int64_t nb = (n + kBlock - 1) / kBlock;
-    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
-#define SPH_LAUNCH(D, RR)                                                                         \
-  hipLaunchKernelGGL((k_interact_compact<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, vp, \
-                     key, cell_start, ace, arho, visc, nbr, red, hdr)
-    if (kp.dim == 2) {
-      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
-    } else {
-      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
-    }
-#undef SPH_LAUNCH
-  } else if (choice == kKGather) {
-    const int64_t nb = (n + kBlock - 1) / kBlock;
-    const unsigned grid = (unsigned)(nb > 0 ? nb : 1);
+  const unsigned grid = (unsigned)L.nblk_interact;
+  const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
 #define SPH_LAUNCH(D, RR, G)                                                                   \
   hipLaunchKernelGGL((k_interact_gather<D, RR, G>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
                      vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr)
-    const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
-    if (kp.dim == 2) {
-      if (kp.cell_div == 1) {
-        if (diag) SPH_LAUNCH(2, 1, true); else SPH_LAUNCH(2, 1, false);
-      } else {
-        if (diag) SPH_LAUNCH(2, 2, true); else SPH_LAUNCH(2, 2, false);
-      }
+  if (kp.dim == 2) {
+    if (kp.cell_div == 1) {
+      if (diag) SPH_LAUNCH(2, 1, true); else SPH_LAUNCH(2, 1, false);
     } else {
-      if (kp.cell_div == 1) {
-        if (diag) SPH_LAUNCH(3, 1, true); else SPH_LAUNCH(3, 1, false);
-      } else {
-        if (diag) SPH_LAUNCH(3, 2, true); else SPH_LAUNCH(3, 2, false);
-      }
+      if (diag) SPH_LAUNCH(2, 2, true); else SPH_LAUNCH(2, 2, false);
     }
-#undef SPH_LAUNCH
   } else {
-    const unsigned grid = (unsigned)L.nblk_interact;
-#define SPH_LAUNCH(D, RR)                                                                        \
-  hipLaunchKernelGGL((k_interact_tile<D, RR>), dim3(grid), dim3(64 * kTileWaves), 0, st, kp, n, \
-                     pr, vp, key, cell_start, ace, arho, visc, nbr, red, hdr)
-    if (kp.dim == 2) {
-      if (kp.cell_div == 1) SPH_LAUNCH(2, 1); else SPH_LAUNCH(2, 2);
+    if (kp.cell_div == 1) {
+      if (diag) SPH_LAUNCH(3, 1, true); else SPH_LAUNCH(3, 1, false);
     } else {
-      if (kp.cell_div == 1) SPH_LAUNCH(3, 1); else SPH_LAUNCH(3, 2);
+      if (diag) SPH_LAUNCH(3, 2, true); else SPH_LAUNCH(3, 2, false);
     }
-#undef SPH_LAUNCH
   }
+#undef SPH_LAUNCH
   return hipGetLastError();
 }
 

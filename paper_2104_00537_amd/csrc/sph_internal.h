@@ -13,8 +13,9 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kSortItems = 8;      // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kScanTile = kBlock * 8;
-constexpr int kTileTargets = 32;   // targets per block of the tiled interaction
 constexpr int kViewPad = 8;        // spare float4 entries after each interaction view
+constexpr int kFrameCells = 8;     // x offsets in the views are taken per block of 8 cells
+constexpr uint32_t kXcds = 8;      // accelerator complex dies of the MI355X
 
 // Per-launch constants derived once on the host from sph_params.
 struct KParams {
@@ -32,6 +33,7 @@ struct KParams {
   float h_f, inv_h_f, support2_f, kfab_f;    // kfab = -5 alpha_D / h^2
   float eta2_f, visc_coef_f, ddt_coef_f;     // alpha*c0 ; 2*delta*h*c0
   float mass_f_f, mass_b_f, cs_f;
+  float frame_f, inv_frame_f;               // kFrameCells*cs and its inverse
   float gx_f, gy_f, gz_f;
 };
 
@@ -96,9 +98,8 @@ inline WsLayout ws_layout(int64_t n) {
   const size_t nn = (size_t)(n > 0 ? n : 1);
   L.nblk_sort = (n + kSortTile - 1) / kSortTile;
   if (L.nblk_sort < 1) L.nblk_sort = 1;
-  // the smallest interaction tile (kTileTargets targets per block) bounds the
-  // number of per-block partial results
-  L.nblk_interact = (n + kTileTargets - 1) / kTileTargets;
+  // one per-block partial result per interaction block of kBlock targets
+  L.nblk_interact = (n + kBlock - 1) / kBlock;
   if (L.nblk_interact < 1) L.nblk_interact = 1;
   L.hist_len = 256 * L.nblk_sort;
   L.scan_parts = (L.hist_len + kScanTile - 1) / kScanTile;
@@ -149,6 +150,16 @@ __device__ inline bool is_fluid(uint8_t t) { return (t & 0x7f) == SPH_FLUID; }
 
 __device__ inline void set_error(uint32_t* err, uint32_t bits) {
   atomicOr(err, bits);
+}
+
+// The dispatcher hands workgroup b to XCD b % kXcds.  Returns the logical
+// block index that gives each XCD one contiguous share of the nb blocks (XCD
+// x runs shares x in order), so that blocks working on neighbouring data
+// share one L2.  A bijection of [0, nb).
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t x = b % kXcds, k = b / kXcds;
+  const uint32_t q = nb / kXcds, r = nb % kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
 // Wave-wide reductions over the 64 lanes of a wavefront.

@@ -1,6 +1,6 @@
 // Device code shared by the single-case and the batched interaction kernels:
-// the pair terms of the WCSPH interaction and the scalar-candidate-stream
-// machinery (Section 2.3 of the DualSPHysics v5.0 paper).
+// the pair terms of the WCSPH interaction and the per-lane neighbour walk
+// (Section 2.3 of the DualSPHysics v5.0 paper).
 #pragma once
 
 #include "sph_internal.h"
@@ -128,158 +128,21 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
   if (nbr) nbr[a] = 0u;
 }
 
-// Orders this wave's LDS writes before its later LDS reads (no block barrier:
-// the waves of a block progress independently).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// ------------------------------------------------ scalar candidate stream --
-// A wavefront takes 64 consecutive sorted targets (one per lane).  For the
-// targets of one cell row it walks the union of their neighbour cells as a
-// single candidate stream that is the same for every lane: candidate data is
-// fetched with scalar loads into SGPRs and used directly as VALU operands, so
-// no per-lane memory traffic is spent on candidates that fail the distance
-// test.  Each lane appends its hits (global index + index of the cell's frame
-// shift) to its own LDS list; the pair terms then run densely over the lists.
-constexpr int kSgLCap = 36;      // list entries per lane (4 blocks of 256 fit the LDS)
-constexpr int kSgCells = 32;     // cell shifts kept per wave between drains
-constexpr int kSgJBits = 27;     // list entry: j (27 bits) | cell slot (5 bits)
-
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-
-struct SgLds {
-  uint32_t list[kSgLCap][64];
-  float4 shift[kSgCells];
-};
-
-// Streams the neighbour cells of one cell row of targets (slot-local cell
-// coordinates ry, rz and x extent [xmin, xmax]; cell indices are offset by
-// cbase) through the scalar candidate pipeline, accumulating each in-row
-// lane's pair terms into acc.  Uniform across the wave; lanes whose target is
-// not in the row carry thresholds of -1 and take no hits.  pax is the
-// target's cell-relative x offset and cx its cell's x index.
-//
-// Relative positions are taken in the frame of the target's own cell:
-// r_ab = (x_a - (c_b - c_a) cs) - x_b with cell-relative offsets, so a pair's
-// arithmetic does not depend on which targets share the wave (results are
-// the same whatever the launch packs together).
-template <int DIM, int R>
-__device__ __forceinline__ void sgpr_row(const KParams& kp, uint32_t cbase, int ry, int rz,
-                                         int xmin, int xmax, float pax, int cx, float ya,
-                                         float za, float thr_any, float thr_fluid,
-                                         const TargetData& T, SgLds& L, int lane,
-                                         const float4* __restrict__ pr,
-                                         const float4* __restrict__ vp,
-                                         const uint32_t* __restrict__ cstart, PairAcc& acc) {
-  // this lane's list: entry k at list[k][lane]; wp points past the last hit
-  // (an LDS-address-space pointer, so appends are single ds_write ops)
-  lds_u32* const lbase = (lds_u32*)&L.list[0][lane];
-  lds_u32* wp = lbase;
-  int ncs = 0;  // cell shifts in use (uniform)
-  auto drain = [&]() {
-    wave_sync();
-    const int cnt = (int)(wp - lbase) / 64;
-    int m = cnt;
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    m = __builtin_amdgcn_readfirstlane(m);
-    // software pipeline: the next hit's entry and data are fetched while the
-    // current pair is computed; lanes past their count fetch particle 0 (always
-    // readable: the views are padded), never a stale or unwritten entry
-    uint32_t en = cnt > 0 ? L.list[0][lane] : 0u;
-    float4 pbn = pr[en & ((1u << kSgJBits) - 1u)], vbn = vp[en & ((1u << kSgJBits) - 1u)];
-    for (int k = 0; k < m; ++k) {
-      const uint32_t e = en;
-      const float4 pb = pbn, vb = vbn;
-      if (k + 1 < m) {
-        en = k + 1 < cnt ? L.list[k + 1][lane] : 0u;
-        const uint32_t jn = en & ((1u << kSgJBits) - 1u);
-        pbn = pr[jn];
-        vbn = vp[jn];
-      }
-      if (k < cnt) {
-        const float4 sh = L.shift[e >> kSgJBits];
-        const float sx = (float)(__float_as_int(sh.x) - cx) * kp.cs_f;
-        const float dx = (pax - sx) - pb.x;
-        const float dy = (ya - sh.y) - pb.y;
-        const float dz = DIM == 3 ? (za - sh.z) - pb.z : 0.f;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        pair_terms<DIM>(kp, T, dx, dy, dz, r2, pb, vb, acc);
-      }
-    }
-    wave_sync();
-    wp = lbase;
-  };
-  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
-    const int z = rz + dz;
-    if (z < 0 || z >= kp.ncz) continue;
-    for (int dy = -R; dy <= R; ++dy) {
-      const int y = ry + dy;
-      if (y < 0 || y >= kp.ncy) continue;
-      const int xlo = max(xmin - R, 0), xhi = min(xmax + R, kp.ncx - 1);
-      const uint32_t rowbase =
-          cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-      for (int x = xlo; x <= xhi; ++x) {
-        const uint32_t j0 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x]);
-        const uint32_t j1 = __builtin_amdgcn_readfirstlane(cstart[rowbase + x + 1]);
-        if (j0 == j1) continue;
-        if (ncs == kSgCells) {
-          drain();
-          ncs = 0;
-        }
-        // the shift table keeps the cell's x index (as bits) and its y, z shifts
-        const float sy = (float)dy * kp.cs_f, sz = (float)dz * kp.cs_f;
-        if (lane == 0) L.shift[ncs] = make_float4(__int_as_float(x), sy, sz, 0.f);
-        const uint32_t tag = (uint32_t)ncs << kSgJBits;
-        ++ncs;
-        const float sx = (float)(x - cx) * kp.cs_f;
-        const float xs = pax - sx, ys = ya - sy, zs = za - sz;
-        // candidates in groups of 4 (one 64-B scalar load), the next group
-        // prefetched; the views are padded so a group may run past j1
-        float4 q0 = pr[j0], q1 = pr[j0 + 1], q2 = pr[j0 + 2], q3 = pr[j0 + 3];
-        for (uint32_t j = j0; j < j1; j += 4) {
-          const float4 c4[4] = {q0, q1, q2, q3};
-          if (j + 4 < j1) {
-            q0 = pr[j + 4];
-            q1 = pr[j + 5];
-            q2 = pr[j + 6];
-            q3 = pr[j + 7];
-          }
-          const uint32_t left = j1 - j;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if ((uint32_t)u < left) {
-              const float4 pb = c4[u];
-              const float dx = xs - pb.x, dy_ = ys - pb.y, dz_ = DIM == 3 ? zs - pb.z : 0.f;
-              const float r2 = dx * dx + dy_ * dy_ + dz_ * dz_;
-              // wall candidates count for fluid targets only (Eq. 36)
-              const float thr = __float_as_int(pb.w) > 0 ? thr_any : thr_fluid;
-              if (r2 < thr) {
-                *wp = (j + u) | tag;
-                wp += 64;
-              }
-            }
-          }
-          if (__ballot(wp > lbase + 64 * (kSgLCap - 4)) != 0ull) drain();
-        }
-      }
-    }
-  }
-  drain();
-}
-
 // ---------------------------------------------------------- gather walk --
-// The candidate walk of one target lane over its (2R+1)^d neighbour cells
-// (cell indices offset by cbase): candidates are read in groups of 4 with all
-// loads in flight together (the views are padded, so a group may run past the
-// cell), tested, then the velocities of the group's neighbours are loaded
-// together and their pair terms accumulated.  Relative positions are taken in
-// the frame of the target's cell.  DIAG also counts neighbours with an FP64
-// test on the FP64 positions (c64).  Wall targets ignore wall candidates
-// (Eq. 36); the target itself is skipped.
+// The candidate walk of one target lane over the (2R+1)^(d-1) rows of its
+// neighbour cells (cell indices offset by cbase).  The 2R+1 cells of a row
+// are consecutive in the sorted order, so each row is one candidate range.
+// Candidates are read in groups of 4 with all loads in flight together (the
+// views are padded, so a group may run past the range), tested, then the
+// velocities of the group's neighbours are loaded together and their pair
+// terms accumulated.  Along x the view holds the offset from the start of the
+// particle's block of kFrameCells cells; the difference of two such offsets
+// is off by a whole block length when the pair straddles a block edge, which
+// the rounding to the nearest block multiple removes exactly (|x_ab| is below
+// (R+1) cells, under half a block).  Along y and z the offsets are
+// cell-relative and the row's cell shift is applied by the target.  DIAG also
+// counts neighbours with an FP64 test on the FP64 positions (c64).  Wall
+// targets ignore wall candidates (Eq. 36); the target itself is skipped.
 template <int DIM, int R, bool DIAG>
 __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
                                             int64_t i, const float4& pa, const TargetData& T,
@@ -289,11 +152,14 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
                                             const uint32_t* __restrict__ cstart,
                                             const double* __restrict__ pos64, PairAcc& acc,
                                             uint32_t& c64) {
+  static_assert(2 * (R + 1) < kFrameCells, "frame block must exceed twice the stencil reach");
   double pa64[3] = {0.0, 0.0, 0.0};
   if (DIAG)
     for (int d = 0; d < DIM; ++d) pa64[d] = pos64[d * n + i];
   const float thr_any = kp.support2_f;
   const float thr_fluid = T.fluid ? kp.support2_f : -1.f;
+  const int x0 = cx - R < 0 ? 0 : cx - R;
+  const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     const int z = cz + dz;
@@ -301,46 +167,42 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
     for (int dy = -R; dy <= R; ++dy) {
       const int y = cy + dy;
       if (y < 0 || y >= kp.ncy) continue;
-      const int x0 = cx - R < 0 ? 0 : cx - R;
-      const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
       const uint32_t row =
           cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+      const uint32_t j0 = cstart[row + x0], j1 = cstart[row + x1 + 1];
       const float ys = pa.y - (float)dy * kp.cs_f, zs = pa.z - (float)dz * kp.cs_f;
-      for (int x = x0; x <= x1; ++x) {
-        const uint32_t j0 = cstart[row + x], j1 = cstart[row + x + 1];
-        const float xs = pa.x - (float)(x - cx) * kp.cs_f;
-        for (uint32_t j = j0; j < j1; j += 4) {
-          float4 pb[4];
+      for (uint32_t j = j0; j < j1; j += 4) {
+        float4 pb[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) pb[u] = pr[j + u];
-          bool hit[4];
-          float dxs[4], dys[4], dzs[4], r2s[4];
+        for (int u = 0; u < 4; ++u) pb[u] = pr[j + u];
+        bool hit[4];
+        float dxs[4], dys[4], dzs[4], r2s[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t jj = j + u;
-            dxs[u] = xs - pb[u].x;
-            dys[u] = ys - pb[u].y;
-            dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
-            r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
-            const float thr = __float_as_int(pb[u].w) > 0 ? thr_any : thr_fluid;
-            hit[u] = jj < j1 && (int64_t)jj != i && r2s[u] < thr;
-            if (DIAG && jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
-              double r2d = 0.0;
-              for (int d = 0; d < DIM; ++d) {
-                const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
-                r2d = __dadd_rn(r2d, __dmul_rn(e, e));
-              }
-              c64 += (r2d < kp.support2) ? 1u : 0u;
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t jj = j + u;
+          const float ex = pa.x - pb[u].x;
+          dxs[u] = fmaf(-kp.frame_f, rintf(ex * kp.inv_frame_f), ex);
+          dys[u] = ys - pb[u].y;
+          dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
+          r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
+          const float thr = __float_as_int(pb[u].w) > 0 ? thr_any : thr_fluid;
+          hit[u] = jj < j1 && (int64_t)jj != i && r2s[u] < thr;
+          if (DIAG && jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
+            double r2d = 0.0;
+            for (int d = 0; d < DIM; ++d) {
+              const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
+              r2d = __dadd_rn(r2d, __dmul_rn(e, e));
             }
+            c64 += (r2d < kp.support2) ? 1u : 0u;
           }
-          float4 vb[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (hit[u]) vb[u] = vp[j + u];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (hit[u]) pair_terms<DIM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u], vb[u], acc);
         }
+        float4 vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (hit[u]) vb[u] = vp[j + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (hit[u]) pair_terms<DIM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u], vb[u], acc);
       }
     }
   }

@@ -218,27 +218,32 @@ def _check_interact(case, label):
     return b, (ace_o, arho_o, visc_o, nbr_o), typ
 
 
+def test_interaction_stencils_agree():
+    """Cells of 2h (3x3x3 stencil) and of h (5x5x5 stencil) visit different
+    candidate sets but the same neighbours: the sums agree to rounding and the
+    FP32 counts differ only at near-ties (the x frames differ with the cell
+    size)."""
+    outs = []
+    for cd in (1, 2):
+        c = _perturbed(cases.block_case(3, (19, 15, 13), walls=True, seed=31, cell_div=cd),
+                       32, vel=0.4)
+        outs.append(Binned(c).interact(flags=0))
+    g, t = outs
+    flips = int(np.abs(t[3].astype(np.int64) - g[3].astype(np.int64)).sum())
+    _say(f"  cd2 vs cd1 count flips {flips} of {int(g[3].sum())}")
+    assert flips <= FLIP_FRACTION * g[3].sum() + 2
+    for i in range(3):
+        scale = max(np.abs(g[i]).max(), 1e-30)
+        assert np.abs(t[i] - g[i]).max() <= 2e-5 * scale
+
+
 @pytest.mark.parametrize("cell_div", [1, 2])
-def test_interaction_kernels_agree(monkeypatch, cell_div):
-    """The interaction kernels (sgpr, compact, tile, gather) test |r| < 2h in
-    FP32 but round r_ab differently (cell frame vs wave frame): counts may
-    differ only at near-ties; sums agree to rounding (different order)."""
-    c = _perturbed(cases.block_case(3, (19, 15, 13), walls=True, seed=31, cell_div=cell_div),
-                   32, vel=0.4)
-    b = Binned(c)
-    outs = {}
-    for k in ("gather", "tile", "compact", "sgpr"):
-        monkeypatch.setenv("SPH_INTERACT_KERNEL", k)
-        outs[k] = b.interact(flags=0)
-    g = outs["gather"]
-    for k in ("tile", "compact", "sgpr"):
-        t = outs[k]
-        flips = int(np.abs(t[3].astype(np.int64) - g[3].astype(np.int64)).sum())
-        _say(f"  {k} vs gather count flips {flips} of {int(g[3].sum())}")
-        assert flips <= FLIP_FRACTION * g[3].sum() + 2
-        for i in range(3):
-            scale = max(np.abs(g[i]).max(), 1e-30)
-            assert np.abs(t[i] - g[i]).max() <= 2e-5 * scale
+def test_interact_long_x_frame_blocks(cell_div):
+    """A block long along x spans many blocks of 8 cells of the x frame, so
+    many pairs straddle a frame edge (the block-length correction)."""
+    c = cases.block_case(3, (120, 7, 6), walls=True, seed=12, cell_div=cell_div)
+    assert c.params.ncell[0] >= 4 * 8
+    _check_interact(_perturbed(c, 13, vel=0.3), f"3d long x cd{cell_div}")
 
 
 @pytest.mark.parametrize("cell_div", [1, 2])
