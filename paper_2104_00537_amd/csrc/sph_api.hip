@@ -40,18 +40,20 @@ KParams make_kparams(const sph_params& p) {
   // grad_a W_ab = -5 alpha_D (1 - q/2)^3 / h^2 * r_ab.
   const double alpha_d = p.dim == 2 ? 7.0 / (4.0 * M_PI * p.h * p.h)
                                     : 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
+  const double kfab = -5.0 * alpha_d / (p.h * p.h);
+  k.inv_frame = 1.0 / (kFrameCells * p.cell_size);
   k.h_f = (float)p.h;
-  k.inv_h_f = (float)(1.0 / p.h);
+  k.mhalf_inv_h_f = (float)(-0.5 / p.h);
   k.support2_f = (float)k.support2;
-  k.kfab_f = (float)(-5.0 * alpha_d / (p.h * p.h));
+  k.kfab_mf_f = (float)(kfab * p.mass_fluid);
+  k.kfab_mb_f = (float)(kfab * p.mass_bound);
+  k.kpi_mf_f = (float)(-2.0 * p.alpha * p.c0 * kfab * p.mass_fluid);
+  k.kpi_mb_f = (float)(-2.0 * p.alpha * p.c0 * kfab * p.mass_bound);
   k.eta2_f = (float)p.eta2;
-  k.visc_coef_f = (float)(p.alpha * p.c0);
   k.ddt_coef_f = p.ddt ? (float)(2.0 * p.delta * p.h * p.c0) : 0.f;
-  k.mass_f_f = (float)p.mass_fluid;
-  k.mass_b_f = (float)p.mass_bound;
   k.cs_f = (float)p.cell_size;
-  k.frame_f = (float)(kFrameCells * p.cell_size);
-  k.inv_frame_f = (float)(1.0 / (kFrameCells * p.cell_size));
+  k.inv_cs_f = (float)p.inv_cell_size;
+  k.unit_x_f = (float)(kFrameCells * p.cell_size / 4294967296.0);
   k.gx_f = (float)p.gravity[0];
   k.gy_f = (float)p.gravity[1];
   k.gz_f = (float)p.gravity[2];

@@ -33,11 +33,12 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
 // interaction reads (the "view"):
 //   pr = {local position (dim components), 0, +rho fluid / -rho wall}
 //   vp = {velocity (dim components), 0, P}
-// lkey is the particle's key relative to its case.  The local FP32 offset is
-// x - (origin + c cs) evaluated in FP64, with c the particle's cell along y
-// and z and the first cell of its block of kFrameCells cells along x (the
-// precision scheme of Section 5.1: FP64 positions, FP32 distances within a
-// few cells, so the FP32 error does not grow with the domain).  P is the
+// lkey is the particle's key relative to its case.  Local positions follow
+// the precision scheme of Section 5.1 (FP64 positions, short FP32 distances,
+// so the error does not grow with the domain): along y and z the FP32 offset
+// x - (origin + c cs) from the particle's cell, evaluated in FP64; along x a
+// 32-bit fixed-point position modulo kFrameCells cells (the bits are stored
+// in the float slot), whose differences are exact modulo that period.  P is the
 // Tait pressure of Eq. 28, per particle in FP64; for gamma = 7 as the
 // expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the small pressures
 // of a nearly incompressible fluid free of cancellation.  Returns true if the
@@ -81,9 +82,11 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
   const double org[3] = {kp.ox, kp.oy, kp.oz};
   float o[3] = {0.f, 0.f, 0.f};
-  // x: offset from the first cell of the particle's block of kFrameCells cells
-  const int cb[3] = {c0 - c0 % kFrameCells, c[1], c[2]};
-  for (int d = 0; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)cb[d] * kp.cs));
+  for (int d = 1; d < kp.dim; ++d) o[d] = (float)(x[d] - (org[d] + (double)c[d] * kp.cs));
+  // x: fixed-point position modulo kFrameCells cells, 2^32 units per period
+  const double fr = (x[0] - org[0]) * kp.inv_frame;
+  const double f = fr - floor(fr);
+  o[0] = __uint_as_float((uint32_t)(uint64_t)(f * 4294967296.0));
   const double r = (double)rho;
   const double u = r / kp.rho0 - 1.0;
   double pw;

@@ -30,10 +30,12 @@ struct KParams {
   double motion_amp, motion_omega;
   double support2;               // (2h)^2 in FP64, for the diagnostic count
   // FP32 copies for the interaction kernel
-  float h_f, inv_h_f, support2_f, kfab_f;    // kfab = -5 alpha_D / h^2
-  float eta2_f, visc_coef_f, ddt_coef_f;     // alpha*c0 ; 2*delta*h*c0
-  float mass_f_f, mass_b_f, cs_f;
-  float frame_f, inv_frame_f;               // kFrameCells*cs and its inverse
+  double inv_frame;               // 1 / (kFrameCells cs)
+  float h_f, mhalf_inv_h_f, support2_f;      // h, -1/(2h), 4h^2
+  float kfab_mf_f, kfab_mb_f;                // kfab m_fluid, kfab m_wall; kfab = -5 alpha_D / h^2
+  float kpi_mf_f, kpi_mb_f;                  // -2 alpha c0 kfab m (Eq. 21 with Eq. 22)
+  float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
+  float cs_f, inv_cs_f, unit_x_f;            // cell size, inverse, x offset unit
   float gx_f, gy_f, gz_f;
 };
 

@@ -22,36 +22,42 @@ struct TargetData {
 };
 
 // The pair terms of Eq. 11 (gradient), 15, 17-18, 21-22 and 36 for one pair
-// (a, b) with r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pb.w is +rho_b for a
+// (a, b) with r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pbw is +rho_b for a
 // fluid particle and -rho_b for a wall; vb.w is P_b.  The caller has already
 // dropped wall-wall pairs (Eq. 36 sums over fluid neighbours only).
-template <int DIM>
+//   F_ab = kfab (1 - q/2)^3, fv = V_b F_ab with V_b = m_b / rho_b;
+//   continuity:  fv v_ab.r_ab;
+//   momentum:    -m_b [(P_a + P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
+//              = -[fv (P_a + P_b) / rho_a + m_b Pi_ab F_ab] r_ab,
+//   with Pi_ab = -2 alpha c0 mu_ab / (rho_a + rho_b) for approaching pairs
+//   (mu_ab = h v_ab.r_ab / (r^2 + eta^2) < 0) and 0 otherwise (Eq. 21);
+//   diffusion:   -(rho_b - rho_a) fv over fluid b.
+// EQM: fluid and wall particles have the same mass (no per-pair select).
+template <int DIM, bool EQM>
 __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
-                                           float dy, float dz, float r2, const float4& pb,
+                                           float dy, float dz, float r2, float pbw,
                                            const float4& vb, PairAcc& acc) {
-  const bool fb = pb.w > 0.f;
-  const float rhob = fabsf(pb.w);
+  const bool fb = pbw > 0.f;
+  const float rhob = fabsf(pbw);
   const float vr = (a.vx - vb.x) * dx + (a.vy - vb.y) * dy + (DIM == 3 ? (a.vz - vb.z) * dz : 0.f);
-  const float q = __builtin_amdgcn_sqrtf(r2) * kp.inv_h_f;
-  const float w = 1.f - 0.5f * q;
-  const float fab = kp.kfab_f * w * w * w;  // grad_a W_ab = fab r_ab, fab <= 0
+  const float w = fmaf(__builtin_amdgcn_sqrtf(r2), kp.mhalf_inv_h_f, 1.f);  // 1 - q/2
+  const float w3 = w * w * w;
   const float irhob = __builtin_amdgcn_rcpf(rhob);
-  const float mb = fb ? kp.mass_f_f : kp.mass_b_f;
-  const float fv = fab * (mb * irhob);
-  acc.cont += fv * vr;
+  const float kmb = EQM ? kp.kfab_mf_f : (fb ? kp.kfab_mf_f : kp.kfab_mb_f);  // kfab m_b
+  const float fv = (w3 * irhob) * kmb;
+  acc.cont = fmaf(fv, vr, acc.cont);
   acc.cnt += 1u;
   if (a.fluid) {
-    const float pterm = (a.p + vb.w) * (a.irho * irhob);
     const float mu = kp.h_f * vr * __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
-    // Pi_ab = -alpha c0 mu / ((rho_a + rho_b)/2) for approaching pairs (Eq. 21)
-    const float pi =
-        vr < 0.f ? -2.f * kp.visc_coef_f * mu * __builtin_amdgcn_rcpf(a.rho + rhob) : 0.f;
-    const float coef = mb * (pterm + pi) * fab;
-    acc.ax -= coef * dx;
-    acc.ay -= coef * dy;
-    if (DIM == 3) acc.az -= coef * dz;
     acc.vmax = fmaxf(acc.vmax, fabsf(mu));
-    if (fb) acc.diff -= (rhob - a.rho) * fv;
+    const float kpi = EQM ? kp.kpi_mf_f : (fb ? kp.kpi_mf_f : kp.kpi_mb_f);  // -2 alpha c0 kfab m_b
+    const float piw = fminf(mu, 0.f) * __builtin_amdgcn_rcpf(a.rho + rhob) * (w3 * kpi);
+    const float coef = fmaf(fv * (a.p + vb.w), a.irho, piw);
+    acc.ax = fmaf(-coef, dx, acc.ax);
+    acc.ay = fmaf(-coef, dy, acc.ay);
+    if (DIM == 3) acc.az = fmaf(-coef, dz, acc.az);
+    const float drho = fb ? rhob - a.rho : 0.f;
+    acc.diff = fmaf(-drho, fv, acc.diff);
   }
 }
 
@@ -129,21 +135,78 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
 }
 
 // ---------------------------------------------------------- gather walk --
-// The candidate walk of one target lane over the (2R+1)^(d-1) rows of its
-// neighbour cells (cell indices offset by cbase).  The 2R+1 cells of a row
-// are consecutive in the sorted order, so each row is one candidate range.
-// Candidates are read in groups of 4 with all loads in flight together (the
-// views are padded, so a group may run past the range), tested, then the
-// velocities of the group's neighbours are loaded together and their pair
-// terms accumulated.  Along x the view holds the offset from the start of the
-// particle's block of kFrameCells cells; the difference of two such offsets
-// is off by a whole block length when the pair straddles a block edge, which
-// the rounding to the nearest block multiple removes exactly (|x_ab| is below
-// (R+1) cells, under half a block).  Along y and z the offsets are
-// cell-relative and the row's cell shift is applied by the target.  DIAG also
-// counts neighbours with an FP64 test on the FP64 positions (c64).  Wall
-// targets ignore wall candidates (Eq. 36); the target itself is skipped.
-template <int DIM, int R, bool DIAG>
+// One group of 4 consecutive candidates j..j+3 of a row for one target lane:
+// the candidate positions are loaded together, tested, then the velocities of
+// the hits are loaded together and their pair terms accumulated.  TAIL masks
+// candidates at or past j1 (the views are padded, so the loads stay in
+// bounds).  Along x the views hold fixed-point offsets (units of
+// kFrameCells*cs / 2^32, periodic over kFrameCells cells): the 32-bit
+// difference of two offsets, read as signed, is x_a - x_b exactly modulo the
+// period, which exceeds twice the reach of the stencil.  Along y and z the
+// offsets are cell-relative and (ys, zs) carry the row's cell shift.  Wall
+// targets skip wall candidates (Eq. 36).
+template <int DIM, bool DIAG, bool EQM, bool TAIL>
+__device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64_t i,
+                                             uint32_t xa, float ys, float zs,
+                                             const TargetData& T, uint32_t j, uint32_t j1,
+                                             const float4* __restrict__ pr,
+                                             const float4* __restrict__ vp,
+                                             const double* pa64,
+                                             const double* __restrict__ pos64, PairAcc& acc,
+                                             uint32_t& c64) {
+  const float4* q = pr + j;
+  float4 pb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) pb[u] = q[u];
+  bool hit[4];
+  float dxs[4], dys[4], dzs[4], r2s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    dxs[u] = (float)(int32_t)(xa - __float_as_uint(pb[u].x)) * kp.unit_x_f;
+    dys[u] = ys - pb[u].y;
+    dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
+    r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
+    hit[u] = (T.fluid || pb[u].w > 0.f) && r2s[u] < kp.support2_f;
+    if (TAIL) hit[u] = hit[u] && j + u < j1;
+    if (DIAG) {
+      const uint32_t jj = j + u;
+      if (jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
+        double r2d = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+          const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
+          r2d = __dadd_rn(r2d, __dmul_rn(e, e));
+        }
+        c64 += (r2d < kp.support2) ? 1u : 0u;
+      }
+    }
+  }
+  const float4* qv = vp + j;
+  float4 vb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (hit[u]) vb[u] = qv[u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (hit[u]) pair_terms<DIM, EQM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u].w, vb[u], acc);
+}
+
+// The candidate walk of one target lane over the rows of its neighbour cells
+// (cell indices offset by cbase).  The 2R+1 cells of a row along x are
+// consecutive in the sorted order, so a row is one candidate range; a row is
+// cut to the cells that the support sphere of the target reaches: with e_y,
+// e_z the distances from the target to the row's cell extent along y and z,
+// only |x_ab| < sqrt(4h^2 - e_y^2 - e_z^2) can hold a neighbour (rows with a
+// negative radicand are skipped).  The cut uses a support enlarged by 1e-4
+// relative, far above the FP32 error of the offsets, so that no pair within
+// 2h is ever cut.  Each range runs as whole groups of 4 and one masked tail
+// group.
+//
+// The target is not excluded from its own candidates: its self pair adds
+// exactly zero to every sum (v_aa = 0, r_aa = 0 and rho_a - rho_a = 0) and is
+// taken off the count here (fluid targets meet themselves; wall targets skip
+// wall candidates).  DIAG also counts neighbours with an FP64 test on the
+// FP64 positions (c64, self excluded).
+template <int DIM, int R, bool DIAG, bool EQM>
 __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
                                             int64_t i, const float4& pa, const TargetData& T,
                                             int cx, int cy, int cz,
@@ -152,60 +215,51 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
                                             const uint32_t* __restrict__ cstart,
                                             const double* __restrict__ pos64, PairAcc& acc,
                                             uint32_t& c64) {
-  static_assert(2 * (R + 1) < kFrameCells, "frame block must exceed twice the stencil reach");
+  static_assert(2 * (R + 1) < kFrameCells, "the x period must exceed twice the stencil reach");
+  static_assert(kFrameCells == 8, "x offsets use 2^29 units per cell");
   double pa64[3] = {0.0, 0.0, 0.0};
   if (DIAG)
     for (int d = 0; d < DIM; ++d) pa64[d] = pos64[d * n + i];
-  const float thr_any = kp.support2_f;
-  const float thr_fluid = T.fluid ? kp.support2_f : -1.f;
-  const int x0 = cx - R < 0 ? 0 : cx - R;
-  const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
+  const float cs = kp.cs_f;
+  const float cull2 = kp.support2_f * 1.0002f;
+  const uint32_t xa = __float_as_uint(pa.x);
+  // the target's offset inside its own cell along x
+  const float fx = (float)(int32_t)(xa - ((uint32_t)(cx % kFrameCells) << 29)) * kp.unit_x_f;
+  const int xlo = cx - R < 0 ? 0 : cx - R;
+  const int xhi = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     const int z = cz + dz;
     if (z < 0 || z >= kp.ncz) continue;
+    const float ez0 = (float)dz * cs - pa.z;  // lower edge of the row's z extent
+    const float ez = dz > 0 ? ez0 : (dz < 0 ? -(ez0 + cs) : 0.f);
     for (int dy = -R; dy <= R; ++dy) {
       const int y = cy + dy;
       if (y < 0 || y >= kp.ncy) continue;
+      const float ey0 = (float)dy * cs - pa.y;
+      const float ey = dy > 0 ? ey0 : (dy < 0 ? -(ey0 + cs) : 0.f);
+      const float w2 = cull2 - ey * ey - ez * ez;
+      if (!(w2 > 0.f)) continue;
+      const float w = __builtin_amdgcn_sqrtf(w2);
+      int x0 = cx + (int)floorf((fx - w) * kp.inv_cs_f);
+      int x1 = cx + (int)floorf((fx + w) * kp.inv_cs_f);
+      x0 = x0 < xlo ? xlo : x0;
+      x1 = x1 > xhi ? xhi : x1;
       const uint32_t row =
           cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const uint32_t j0 = cstart[row + x0], j1 = cstart[row + x1 + 1];
-      const float ys = pa.y - (float)dy * kp.cs_f, zs = pa.z - (float)dz * kp.cs_f;
-      for (uint32_t j = j0; j < j1; j += 4) {
-        float4 pb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pb[u] = pr[j + u];
-        bool hit[4];
-        float dxs[4], dys[4], dzs[4], r2s[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint32_t jj = j + u;
-          const float ex = pa.x - pb[u].x;
-          dxs[u] = fmaf(-kp.frame_f, rintf(ex * kp.inv_frame_f), ex);
-          dys[u] = ys - pb[u].y;
-          dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
-          r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
-          const float thr = __float_as_int(pb[u].w) > 0 ? thr_any : thr_fluid;
-          hit[u] = jj < j1 && (int64_t)jj != i && r2s[u] < thr;
-          if (DIAG && jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
-            double r2d = 0.0;
-            for (int d = 0; d < DIM; ++d) {
-              const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
-              r2d = __dadd_rn(r2d, __dmul_rn(e, e));
-            }
-            c64 += (r2d < kp.support2) ? 1u : 0u;
-          }
-        }
-        float4 vb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (hit[u]) vb[u] = vp[j + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (hit[u]) pair_terms<DIM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u], vb[u], acc);
-      }
+      const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
+      uint32_t j = j0;
+      for (; j + 4 <= j1; j += 4)
+        gather_group<DIM, DIAG, EQM, false>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64, pos64,
+                                            acc, c64);
+      if (j < j1)
+        gather_group<DIM, DIAG, EQM, true>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64, pos64,
+                                           acc, c64);
     }
   }
+  // the self pair (fluid targets only) was counted and added nothing
+  if (T.fluid) acc.cnt -= 1u;
 }
 
 }  // namespace sph
