@@ -70,7 +70,16 @@ enum {
 enum {
   /* nbr_count uses an FP64 distance test on the FP64 positions (bit-exact
    * neighbour counts); the sums always use the FP32 cell-relative test. */
-  SPH_DIAG_COUNT_F64 = 1u
+  SPH_DIAG_COUNT_F64 = 1u,
+  /* Precision-study arms (Section 5.1), not the production path and several
+   * times slower; at most one flag may be given.  F64: every pair in FP64
+   * from the FP64 positions, pressure recomputed in FP64 from the density.
+   * ABS_F32: distances from positions rounded to FP32 as absolute
+   * coordinates, the rest FP32 (the scheme that cell-relative positions
+   * replace).  Velocities and densities are the stored FP32 values in both;
+   * the outputs and the workspace partials are as in the production pass. */
+  SPH_INTERACT_F64 = 2u,
+  SPH_INTERACT_ABS_F32 = 4u
 };
 
 /* Case constants, passed by pointer to host memory and copied by value into

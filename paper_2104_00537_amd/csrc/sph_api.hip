@@ -42,6 +42,10 @@ KParams make_kparams(const sph_params& p) {
                                     : 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
   const double kfab = -5.0 * alpha_d / (p.h * p.h);
   k.inv_frame = 1.0 / (kFrameCells * p.cell_size);
+  k.kfab = kfab;
+  k.alpha_c0 = p.alpha * p.c0;
+  k.ddt_coef = p.ddt ? 2.0 * p.delta * p.h * p.c0 : 0.0;
+  k.eta2 = p.eta2;
   k.h_f = (float)p.h;
   k.mhalf_inv_h_f = (float)(-0.5 / p.h);
   k.support2_f = (float)k.support2;
@@ -145,7 +149,10 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
                         void* stream) {
   if (!params_ok(p) || !n_ok(n) || !cell_start || !ws) return SPH_E_ARG;
   if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
-  if (flags & ~(uint32_t)SPH_DIAG_COUNT_F64) return SPH_E_ARG;
+  // one of: none, the FP64 diagnostic count, or one precision-study arm
+  if (flags != 0 && flags != SPH_DIAG_COUNT_F64 && flags != SPH_INTERACT_F64 &&
+      flags != SPH_INTERACT_ABS_F32)
+    return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   const KParams kp = make_kparams(*p);
   sph_state s0 = n > 0 ? *s : sph_state{};

@@ -29,6 +29,17 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
   return (uint32_t)(c[0] + nc[0] * (c[1] + nc[1] * c[2]));
 }
 
+// (rho/rho0)^gamma - 1 of the Tait equation (Eq. 28: P = B_t times this), in
+// FP64; for gamma = 7 as the expansion of (1+u)^7 - 1 in u = rho/rho0 - 1,
+// which keeps the small pressures of a nearly incompressible fluid free of
+// cancellation.
+__device__ inline double tait_ratio(const KParams& kp, double r) {
+  const double u = r / kp.rho0 - 1.0;
+  if (kp.gamma == 7.0)
+    return u * (7.0 + u * (21.0 + u * (35.0 + u * (35.0 + u * (21.0 + u * (7.0 + u))))));
+  return pow(r / kp.rho0, kp.gamma) - 1.0;
+}
+
 // Gathers particle src into sorted slot i and writes the two float4 the
 // interaction reads (the "view"):
 //   pr = {local position (dim components), 0, +rho fluid / -rho wall}
@@ -39,10 +50,8 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
 // x - (origin + c cs) from the particle's cell, evaluated in FP64; along x a
 // 32-bit fixed-point position modulo kFrameCells cells (the bits are stored
 // in the float slot), whose differences are exact modulo that period.  P is the
-// Tait pressure of Eq. 28, per particle in FP64; for gamma = 7 as the
-// expansion (1+u)^7 - 1 in u = rho/rho0 - 1, which keeps the small pressures
-// of a nearly incompressible fluid free of cancellation.  Returns true if the
-// particle was excluded by this call (it left the grid).
+// Tait pressure of Eq. 28, per particle in FP64 (tait_ratio).  Returns true if
+// the particle was excluded by this call (it left the grid).
 __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int64_t src,
                                    uint32_t lkey, const sph_state& in, const sph_state& out,
                                    const sph_state& cin, const sph_state& cout, int carry,
@@ -87,13 +96,7 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   const double fr = (x[0] - org[0]) * kp.inv_frame;
   const double f = fr - floor(fr);
   o[0] = __uint_as_float((uint32_t)(uint64_t)(f * 4294967296.0));
-  const double r = (double)rho;
-  const double u = r / kp.rho0 - 1.0;
-  double pw;
-  if (kp.gamma == 7.0)
-    pw = u * (7.0 + u * (21.0 + u * (35.0 + u * (35.0 + u * (21.0 + u * (7.0 + u))))));
-  else
-    pw = pow(r / kp.rho0, kp.gamma) - 1.0;
+  const double pw = tait_ratio(kp, (double)rho);
   pr[i] = make_float4(o[0], o[1], o[2], is_fluid(t) ? rho : -rho);
   vp[i] = make_float4(v[0], v[1], v[2], (float)(kp.b_tait * pw));
   return newly;

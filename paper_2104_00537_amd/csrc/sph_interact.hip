@@ -8,6 +8,7 @@
 // by its predecessors.  Sums are gathered per target (no atomics): results are
 // deterministic.
 #include "sph_kernels.h"
+#include "sph_dev.h"
 #include "sph_pair.h"
 
 namespace sph {
@@ -54,6 +55,124 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
 }
 
+// ---------------------------------------------- precision-study arms --
+// Two reference forms of the interaction for the precision study of
+// Section 5.1 (not the production path): with T = double every pair is
+// evaluated in FP64 from the FP64 positions, with the pressure recomputed in
+// FP64 from the density (Eq. 28); with T = float the distances come from
+// positions rounded to FP32 as absolute coordinates (the scheme the
+// cell-relative offsets replace) and the rest is FP32.  Velocities and
+// densities are the stored FP32 values in both.  Every candidate of the
+// (2R+1)^d neighbour cells is tested against (2h)^2 and the pair terms of
+// Eq. 11, 15, 17-18, 21-22 and 36 are applied as written, with plain division
+// and square root.
+template <typename T>
+struct ArmAcc {
+  T ax, ay, az, cont, diff, vmax;
+  uint32_t cnt;
+};
+
+template <int DIM, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_interact_arm(
+    KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
+    const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
+    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  float fmag = 0.f, vmax_out = 0.f;
+  uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
+  if (i < n) {
+    if (!is_excluded(type[i])) {
+      const float4 pa = pr[i], va = vp[i];
+      const bool fa = pa.w > 0.f;
+      const T rho_a = (T)fabsf(pa.w);
+      const T p_a = sizeof(T) == 8 ? (T)(kp.b_tait * tait_ratio(kp, (double)rho_a)) : (T)va.w;
+      const T v_a[3] = {(T)va.x, (T)va.y, (T)va.z};
+      T x_a[3] = {0, 0, 0};
+      for (int d = 0; d < DIM; ++d) x_a[d] = (T)pos64[d * n + i];
+      const T h = (T)kp.h, support2 = (T)kp.support2, kfab = (T)kp.kfab;
+      ArmAcc<T> acc{0, 0, 0, 0, 0, 0, 0u};
+      const uint32_t k = key[i];
+      const int cx = (int)(k % (uint32_t)kp.ncx);
+      const uint32_t rest = k / (uint32_t)kp.ncx;
+      const int cy = (int)(rest % (uint32_t)kp.ncy);
+      const int cz = (int)(rest / (uint32_t)kp.ncy);
+      const int x0 = cx - R < 0 ? 0 : cx - R;
+      const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
+      const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+      for (int dz = zlo; dz <= zhi; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= kp.ncz) continue;
+        for (int dy = -R; dy <= R; ++dy) {
+          const int y = cy + dy;
+          if (y < 0 || y >= kp.ncy) continue;
+          const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+          const uint32_t j1 = cstart[row + x1 + 1];
+          for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
+            if ((int64_t)j == i) continue;
+            const float4 pb = pr[j];
+            const bool fb = pb.w > 0.f;
+            if (!fa && !fb) continue;  // Eq. 36: walls see fluid neighbours only
+            T r[3] = {0, 0, 0};
+            T r2 = 0;
+            for (int d = 0; d < DIM; ++d) {
+              r[d] = x_a[d] - (T)pos64[d * n + j];
+              r2 += r[d] * r[d];
+            }
+            if (!(r2 < support2)) continue;
+            const float4 vb = vp[j];
+            const T rho_b = (T)fabsf(pb.w);
+            const T p_b = sizeof(T) == 8 ? (T)(kp.b_tait * tait_ratio(kp, (double)rho_b)) : (T)vb.w;
+            const T v_b[3] = {(T)vb.x, (T)vb.y, (T)vb.z};
+            const T m_b = (T)(fb ? kp.mass_f : kp.mass_b);
+            const T q = sqrt(r2) / h;
+            const T w = (T)1 - q / (T)2;
+            const T fab = kfab * w * w * w;  // grad_a W_ab = fab r_ab
+            T vr = 0;
+            for (int d = 0; d < DIM; ++d) vr += (v_a[d] - v_b[d]) * r[d];
+            const T vol_b = m_b / rho_b;
+            acc.cont += vol_b * fab * vr;
+            acc.cnt += 1u;
+            if (fa) {
+              const T mu = h * vr / (r2 + (T)kp.eta2);
+              const T pi = vr < 0 ? -(T)kp.alpha_c0 * mu / ((rho_a + rho_b) / (T)2) : (T)0;
+              const T coef = m_b * ((p_a + p_b) / (rho_a * rho_b) + pi) * fab;
+              acc.ax -= coef * r[0];
+              acc.ay -= coef * r[1];
+              if (DIM == 3) acc.az -= coef * r[2];
+              acc.vmax = fmax(acc.vmax, fabs(mu));
+              if (fb) acc.diff += (rho_b - rho_a) * fabs(fab) * vol_b;
+            }
+          }
+        }
+      }
+      T ax = 0, ay = 0, az = 0;
+      T ar = rho_a * acc.cont;
+      if (fa) {
+        ax = acc.ax + (T)kp.gx;
+        ay = acc.ay + (T)kp.gy;
+        az = DIM == 3 ? acc.az + (T)kp.gz : (T)0;
+        ar += (T)kp.ddt_coef * acc.diff;
+        fmag = (float)sqrt(ax * ax + ay * ay + az * az);
+        vmax_out = (float)acc.vmax;
+        nfl = 1;
+      }
+      ace[i] = (float)ax;
+      ace[n + i] = (float)ay;
+      if (DIM == 3) ace[2 * n + i] = (float)az;
+      arho[i] = (float)ar;
+      if (visc) visc[i] = (float)acc.vmax;
+      if (nbr) nbr[i] = acc.cnt;
+      cnt_out = acc.cnt;
+      cnt_wall = fa ? 0u : acc.cnt;
+    } else {
+      write_zero<DIM>(n, i, ace, arho, visc, nbr);
+    }
+  }
+  write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
+}
+
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, float* ace, float* arho, float* visc,
                            uint32_t* nbr, uint32_t flags, void* ws, hipStream_t st) {
@@ -63,6 +182,22 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   BlockRed* red = ws_ptr<BlockRed>(ws, L.red);
   WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
   const unsigned grid = (unsigned)L.nblk_interact;
+  if (flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) {
+    const bool f64 = flags == SPH_INTERACT_F64;
+#define SPH_ARM(D, RR, T)                                                                  \
+  hipLaunchKernelGGL((k_interact_arm<D, RR, T>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
+                     vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr)
+#define SPH_ARM_T(D, RR) \
+  if (f64) SPH_ARM(D, RR, double); else SPH_ARM(D, RR, float)
+    if (kp.dim == 2) {
+      if (kp.cell_div == 1) SPH_ARM_T(2, 1); else SPH_ARM_T(2, 2);
+    } else {
+      if (kp.cell_div == 1) SPH_ARM_T(3, 1); else SPH_ARM_T(3, 2);
+    }
+#undef SPH_ARM_T
+#undef SPH_ARM
+    return hipGetLastError();
+  }
   const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
   const bool eqm = kp.mass_f == kp.mass_b;
 #define SPH_LAUNCH(D, RR, G, PP)                                                               \

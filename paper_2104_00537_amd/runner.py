@@ -17,7 +17,7 @@ from . import sph as S
 
 
 class Simulation:
-    def __init__(self, case, device="cuda", cell_div: Optional[int] = None):
+    def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0):
         cp = case.params
         if cell_div is not None and cell_div != cp.cell_div:
             raise ValueError("cell_div is fixed by the case's grid")
@@ -44,6 +44,9 @@ class Simulation:
         self.interactions = torch.zeros(2, dtype=torch.int64, device=dev)
         self.steps_done = 0
         self.graph = None
+        # sph_interact flags: 0 for the production pass, or a precision-study
+        # arm (S.SPH_INTERACT_F64 / S.SPH_INTERACT_ABS_F32)
+        self.flags = int(flags)
 
     # ------------------------------------------------------------------ step
     @property
@@ -73,7 +76,7 @@ class Simulation:
         call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
              self.ws, stream=stream)
         call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
-             self.ws, stream=stream)
+             self.ws, flags=self.flags, stream=stream)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
              interactions=self.interactions, stream=stream)
         call("symplectic", S.sph_symplectic_step, P, n, 0, self.dt, self.t, s0, b, self.ace,
@@ -81,7 +84,7 @@ class Simulation:
         call("bin_cells", S.sph_bin_cells, P, n, b, a, self.key, self.perm, self.cell_start,
              self.ws, carry_in=s0, carry_out=s1, stream=stream)
         call("interact", S.sph_interact, P, n, a, self.key, self.cell_start, self.ace, self.arho,
-             self.ws, stream=stream)
+             self.ws, flags=self.flags, stream=stream)
         # pair count of the second pass (its dt is not used: Eq. 35 is taken
         # at state n for both half steps)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt_half, self.ws,

@@ -21,6 +21,8 @@ SPH_OK, SPH_E_ARG, SPH_E_WORKSPACE, SPH_E_HIP = 0, -1, -2, -3
 SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_EXCLUDED = 0, 1, 2, 0x80
 SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR = 1, 2, 4
 SPH_DIAG_COUNT_F64 = 1
+SPH_INTERACT_F64 = 2
+SPH_INTERACT_ABS_F32 = 4
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
            "sph_symplectic_step", "sph_read_error", "sph_clear_error", "sph_strerror",

@@ -1,0 +1,107 @@
+"""The precision-study arms of the interaction (Section 5.1) against the CPU
+FP64 oracle, through the C ABI: every pair in FP64 (SPH_INTERACT_F64), the
+production scheme (FP32 offsets from fixed-point / cell-relative positions),
+and FP32 absolute positions (SPH_INTERACT_ABS_F32).
+
+Bars (each derived from the arithmetic of the arm):
+  * FP64 arm: neighbour counts equal to the oracle's (same FP64 test, up to
+    the rounding of the last bit of |r|^2, i.e. no flips expected on jittered
+    lattices); rates within 1e-6 of max|oracle| (FP32 rounding of the
+    outputs, ~6e-8, and of the FP32-stored velocities and densities, which
+    the oracle shares);
+  * production arm: 1e-4 (the parity bar);
+  * absolute-FP32 arm: its error is the measured quantity of the study; the
+    test only bounds it loosely (5e-2) and reports it, and checks that it is
+    not smaller than the production arm's on the 1M case.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2104_00537_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2104_00537_amd import sph as S
+    from paper_2104_00537_amd.runner import Simulation
+    from test_gpu_parity import Binned, _perturbed, _say
+
+
+def _errs(g, o, fl):
+    ace_g, arho_g, visc_g = g
+    ace_o, arho_o, visc_o = o
+    ea = np.abs(ace_g - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+    er = np.abs(arho_g - arho_o).max() / max(np.abs(arho_o).max(), 1e-30)
+    vm = np.abs(visc_o).max()
+    ev = np.abs(visc_g - visc_o).max() / vm if vm > 0 else np.abs(visc_g).max()
+    return ea, er, ev
+
+
+ARMS = {"f64": 2, "offset_f32": 0, "abs_f32": 4}
+BARS = {"f64": 1e-6, "offset_f32": 1e-4, "abs_f32": 5e-2}
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+def test_arms_against_oracle(which):
+    if which == "2d":
+        c = _perturbed(cases.dam_break_2d(cell_div=2), 41)
+    else:
+        c = _perturbed(cases.block_case(3, (17, 13, 11), walls=True, seed=8, cell_div=1), 42, vel=0.3)
+    b = Binned(c)
+    pos, vel, rho, typ = b.sorted_host()
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ)
+    fl = (typ & 0x7F) == cases.FLUID
+    for arm, flag in ARMS.items():
+        ace, arho, visc, nbr = b.interact(flags=flag)
+        ea, er, ev = _errs((ace, arho, visc), (ace_o, arho_o, visc_o), fl)
+        flips = int(np.abs(nbr.astype(np.int64) - nbr_o.astype(np.int64)).sum())
+        _say(f"  {which} {arm:10s} rel err ace {ea:.2e} arho {er:.2e} visc {ev:.2e} flips {flips}")
+        assert max(ea, er, ev) < BARS[arm]
+        if arm == "f64":
+            assert flips <= 2
+
+
+def test_arms_1m_sampled():
+    """Per-particle dv/dt and drho/dt of each arm on the 1M dam break, on 600
+    sampled targets of the state after 20 steps (moving fluid)."""
+    c = cases.dam_break_3d()
+    sim = Simulation(c, "cuda:0")
+    sim.run(20)
+    torch.cuda.synchronize()
+    st = sim.host_state()
+    c2 = cases.Case(c.params, st["pos"], st["vel"], st["rho"], st["type"], dict(c.meta))
+    b = Binned(c2)
+    pos, vel, rho, typ = b.sorted_host()
+    rng = np.random.default_rng(3)
+    tg = np.concatenate([rng.choice(np.flatnonzero(typ == 0), 500, replace=False),
+                         rng.choice(np.flatnonzero(typ != 0), 100, replace=False)])
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ, targets=tg)
+    fl = typ[tg] == 0
+    res = {}
+    for arm, flag in ARMS.items():
+        ace, arho, visc, nbr = b.interact(flags=flag)
+        res[arm] = _errs((ace[:, tg], arho[tg], visc[tg]), (ace_o, arho_o, visc_o), fl)
+        _say(f"  1M {arm:10s} rel err ace {res[arm][0]:.2e} arho {res[arm][1]:.2e} "
+             f"visc {res[arm][2]:.2e}")
+        assert max(res[arm]) < BARS[arm]
+        if arm == "f64":
+            assert np.array_equal(nbr[tg], nbr_o)
+    assert max(res["abs_f32"]) >= max(res["f64"])
+
+
+def test_arm_steps_2d():
+    """Each arm runs the 2-D dam break for 300 steps; the fronts agree with
+    the FP64 arm within 1e-3 of the tank length."""
+    fronts = {}
+    for arm, flag in ARMS.items():
+        sim = Simulation(cases.dam_break_2d(), "cuda:0", flags=flag)
+        sim.run(300)
+        torch.cuda.synchronize()
+        assert sim.error() == 0
+        st = sim.host_state()
+        fronts[arm] = float(st["pos"][0][st["type"] == cases.FLUID].max())
+    _say(f"  2d fronts after 300 steps {fronts}")
+    for arm in ARMS:
+        assert abs(fronts[arm] - fronts["f64"]) <= 1e-3 * 1.6
