@@ -91,22 +91,27 @@ def cpu_baseline(case, sim, seconds):
     cp = case.params
     args = (cp, st["pos"], st["vel"].astype(np.float64), st["rho"].astype(np.float64), st["type"])
     oracle.interact(*args, targets=rng.choice(n, size=min(n, 16), replace=False))  # warm-up
-    probe = rng.choice(n, size=min(n, 128), replace=False)
-    t0 = time.perf_counter()
-    oracle.interact(*args, targets=probe)
-    t_probe = max(time.perf_counter() - t0, 1e-4)
-    k = int(min(n, max(len(probe), len(probe) * seconds / t_probe)))
-    sample = rng.choice(n, size=k, replace=False)
-    t0 = time.perf_counter()
-    _, _, _, nbr = oracle.interact(*args, targets=sample)
-    el = time.perf_counter() - t0
+    # random targets in chunks until about `seconds` of CPU work is done
+    order = rng.permutation(n)
+    done, pairs, el, chunk = 0, 0, 0.0, 256
+    while done < n and el < seconds:
+        tg = order[done:done + chunk]
+        t0 = time.perf_counter()
+        _, _, _, nbr = oracle.interact(*args, targets=tg)
+        dt = time.perf_counter() - t0
+        el += dt
+        pairs += int(nbr.astype(np.int64).sum())
+        done += len(tg)
+        chunk = int(min(max(chunk, len(tg) * max(seconds - el, 0.0) / max(dt, 1e-6) / 4), 1 << 16))
+        chunk = max(chunk, 64)
+    k = done
     try:
         aff = len(os.sched_getaffinity(0))
     except AttributeError:
         aff = os.cpu_count() or 1
     omp = os.environ.get("OMP_NUM_THREADS")
     cores = min(aff, int(omp)) if omp and omp.isdigit() else aff
-    return {"value": float(nbr.astype(np.int64).sum() / el), "unit": "interactions/s",
+    return {"value": float(pairs / el), "unit": "interactions/s",
             "cores": cores, "kind": "oracle",
             "sample": f"one interaction pass for {k} random targets of {n} particles "
                       f"(all {n} as candidate neighbours, brute force FP64), {el:.1f} s"}

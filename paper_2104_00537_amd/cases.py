@@ -248,7 +248,7 @@ def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
 
 
 def random_serving_case(rng: np.random.Generator, n_min=2000, n_max=500_000,
-                        seed=None) -> Case:
+                        seed=None, cell_div=2) -> Case:
     """One request of the serving stream: a 2-D or 3-D dam break or sloshing
     case with a log-uniform fluid particle count, column aspect ratio
     uniform in [0.5, 2] and fill ratio uniform in [0.3, 0.7]."""
@@ -267,26 +267,27 @@ def random_serving_case(rng: np.random.Generator, n_min=2000, n_max=500_000,
         if dim == 2:
             dp = math.sqrt(width * height / n_target)
             case = dam_break_2d(dp=dp, tank=(length, tank_h), column=(width, height),
-                                seed=sub_seed)
+                                seed=sub_seed, cell_div=cell_div)
         else:
             depth_y = 0.6
             dp = (width * depth_y * height / n_target) ** (1.0 / 3.0)
             case = dam_break_3d(dp=dp, tank=(length, depth_y, tank_h),
-                                block=(width, depth_y, height), seed=sub_seed)
+                                block=(width, depth_y, height), seed=sub_seed,
+                                cell_div=cell_div)
     else:
         if dim == 2:
             dp = math.sqrt(2.0 * fill * 1.0 / n_target)
-            case = _sloshing_2d(dp, fill, sub_seed)
+            case = _sloshing_2d(dp, fill, sub_seed, cell_div=cell_div)
         else:
             dp = (2.0 * 1.0 * fill * 1.0 / n_target) ** (1.0 / 3.0)
-            case = sloshing_3d(dp=dp, fill=fill, seed=sub_seed)
+            case = sloshing_3d(dp=dp, fill=fill, seed=sub_seed, cell_div=cell_div)
     case.meta.update(kind=kind, steps=steps, aspect=aspect, fill=fill,
                      n_target=n_target)
     return case
 
 
 def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
-                 freq_hz=0.5) -> Case:
+                 freq_hz=0.5, cell_div=1) -> Case:
     nxt, nzt = int(round(tank[0] / dp)), int(round(tank[1] / dp))
     nzf = max(1, int(round(fill * tank[1] / dp)))
     fluid = _grid((0, nxt), (0, nzf))
@@ -298,4 +299,4 @@ def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
     hi = (nxt * dp + m + travel, nzt * dp + m)
     return _finish("sloshing_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
                    wall_type=BOUND_MOVING, motion_amp=accel, motion_omega=omega,
-                   meta=dict(tank=tank, fill=fill))
+                   cell_div=cell_div, meta=dict(tank=tank, fill=fill))

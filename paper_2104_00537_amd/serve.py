@@ -120,6 +120,8 @@ class BatchEngine:
         self.graph = None
         self.steps_run = 0
         self.repacks = 0
+        self.repack_s = 0.0    # host time spent repacking (copies, table upload)
+        self.capture_s = 0.0   # host time spent capturing step graphs
 
     # ------------------------------------------------------------ capacity
     def fits(self, slots: List[Request], req: Request) -> bool:
@@ -143,6 +145,13 @@ class BatchEngine:
     def repack(self, keep: List[Request], add: List[Request]):
         """New composition: surviving slots (their current state) followed by
         the new cases (uploaded).  Per-slot t carries over."""
+        t0 = time.perf_counter()
+        try:
+            self._repack(keep, add)
+        finally:
+            self.repack_s += time.perf_counter() - t0
+
+    def _repack(self, keep: List[Request], add: List[Request]):
         old_n = self.offsets[-1]
         old_index = {id(r): k for k, r in enumerate(self.slots)}
         src = self._dev_state(0, old_n) if old_n > 0 else None
@@ -223,11 +232,13 @@ class BatchEngine:
             return
         if self.use_graph:
             if self.graph is None:
+                t0 = time.perf_counter()
                 torch.cuda.synchronize()
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
                     self._step()
                 self.graph = g
+                self.capture_s += time.perf_counter() - t0
             for _ in range(k):
                 self.graph.replay()
         else:
@@ -324,7 +335,9 @@ def serve_batched(reqs: List[Request], engine: BatchEngine, max_chunk: int = 64,
     makespan = time.perf_counter() - t0
     inter_total = sum(r.interactions for r in reqs)
     return _summary(reqs, makespan, inter_total, dict(repacks=engine.repacks,
-                                                      batch_steps=engine.steps_run))
+                                                      batch_steps=engine.steps_run,
+                                                      repack_s=engine.repack_s,
+                                                      capture_s=engine.capture_s))
 
 
 def serve_plain(reqs: List[Request], device="cuda", use_graph: bool = True,
