@@ -207,14 +207,14 @@ def main():
                     help="step: the benchmark; interact/copy: kernel-only runs for counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
-    ap.add_argument("--serve-steps-scale", type=float, default=0.2)
+    ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--serve-n-min", type=int, default=2000)
     ap.add_argument("--serve-n-max", type=int, default=500_000)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-cap-particles", type=int, default=6_000_000)
-    ap.add_argument("--serve-cap-cells", type=int, default=40_000_000)
+    ap.add_argument("--serve-cap-cells", type=int, default=60_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this path has no multi-GPU mode "
