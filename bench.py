@@ -67,16 +67,17 @@ def measured_traffic(kernel, workload_name):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def workload(name, cell_div):
+def workload(name, cell_div, x_sub):
     from paper_2104_00537_amd import cases
+    kw = dict(cell_div=cell_div, x_sub=x_sub)
     if name == "dam_break_3d_1m":
-        return cases.dam_break_3d(cell_div=cell_div)
+        return cases.dam_break_3d(**kw)
     if name == "dam_break_3d_0p5m":
-        return cases.dam_break_3d(dp=0.006, cell_div=cell_div)
+        return cases.dam_break_3d(dp=0.006, **kw)
     if name == "dam_break_2d":
-        return cases.dam_break_2d(cell_div=cell_div)
+        return cases.dam_break_2d(**kw)
     if name == "sloshing_3d_64m":
-        return cases.sloshing_3d(cell_div=cell_div)
+        return cases.sloshing_3d(**kw)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -166,7 +167,7 @@ def profile_mode(args):
                           "bytes_written_per_launch": y.numel() * 4}), flush=True)
         return 0
     from paper_2104_00537_amd import sph as S
-    case = workload(args.workload, args.cell_div)
+    case = workload(args.workload, args.cell_div, args.x_sub)
     P = S.make_params(case.params)
     n = case.n
     src = S.DeviceState.from_case(case, "cuda:0")
@@ -202,6 +203,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="dam_break_3d_1m")
     ap.add_argument("--cell-div", type=int, default=2)
+    ap.add_argument("--x-sub", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mode", choices=["step", "interact", "copy"], default="step",
                     help="step: the benchmark; interact/copy: kernel-only runs for counters")
@@ -214,7 +216,7 @@ def main():
     ap.add_argument("--serve-n-max", type=int, default=500_000)
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-cap-particles", type=int, default=6_000_000)
-    ap.add_argument("--serve-cap-cells", type=int, default=60_000_000)
+    ap.add_argument("--serve-cap-cells", type=int, default=120_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -228,7 +230,7 @@ def main():
     import torch
     from paper_2104_00537_amd.runner import Simulation
 
-    case = workload(args.workload, args.cell_div)
+    case = workload(args.workload, args.cell_div, args.x_sub)
     sim = Simulation(case, "cuda:0")
     print(f"[bench] {args.workload}: n={case.n} fluid={case.n_fluid} cells={case.params.ncell}",
           file=sys.stderr, flush=True)
@@ -259,7 +261,8 @@ def main():
     # (2 x 16 B), ace + arho written (4 x 4 B), key and cell range reads (8 B)
     bytes_per_launch = case.n * (32 + 16 + 8)
     kernel = "k_interact_gather"
-    traffic = measured_traffic(kernel, args.workload) if args.cell_div == 2 else None
+    traffic = (measured_traffic(kernel, args.workload)
+               if (args.cell_div, args.x_sub) == (2, 4) else None)
     res = {
         "metric": METRIC,
         "value": pairs / el,
@@ -275,7 +278,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": case.n, "n_fluid": case.n_fluid,
                    "dp": case.params.dp, "h": case.params.h, "cell_div": args.cell_div,
-                   "parallelism": "single GPU", "positions": "fp64 state, fp32 cell-relative"},
+                   "x_sub": args.x_sub,
+                   "parallelism": "single GPU", "positions": "fp64 state; fp32 offsets (fixed-point x, cell-relative y, z)"},
         "steps_per_s": args.steps / el,
         "interactions_per_step": pairs / args.steps,
         "phase_ms_per_call": phase_ms,

@@ -89,14 +89,21 @@ typedef struct sph_params {
   int32_t cell_div;       /* 1: cells of size 2h, search +-1 cell (Section 5.1);
                              2: cells of size h, search +-2 cells (Section 5.3) */
   int32_t ddt;            /* 0: no density diffusion; 1: Eq. 17 with Eq. 18 */
-  int32_t ncell[3];       /* cells per axis; ncell[2] = 1 in 2-D.  Keys are
+  int32_t ncell[3];       /* key cells per axis; ncell[2] = 1 in 2-D.  Keys are
                              cx + ncell[0]*(cy + ncell[1]*cz) (x fastest); the
                              key of a particle outside the grid is the total
                              cell count.  total + 1 must be < 2^32. */
+  int32_t x_sub;          /* 1, 2, 4 or 8: key cells per cell along x (cells
+                             of cs/x_sub along x, cs along y and z); finer x
+                             cells let the interaction cut each row of
+                             neighbour cells closer to the support sphere */
+  int32_t reserved;       /* 0 */
   double origin[3];       /* grid origin (components beyond dim ignored) */
   double cell_size;       /* cs = 2h / cell_div */
   double inv_cell_size;   /* 1/cs, computed once by the caller; the cell index
-                             is floor((x - origin) * inv_cell_size) in FP64 */
+                             is floor((x - origin) * inv_cell_size) in FP64
+                             along y and z, and floor((x - origin) *
+                             (inv_cell_size * x_sub)) along x */
   double h;               /* smoothing length; support radius 2h */
   double rho0;            /* reference density (Eq. 28) */
   double gamma;           /* polytropic index (Eq. 28) */

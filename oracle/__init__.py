@@ -40,7 +40,7 @@ def build(force: bool = False) -> str:
 class OrcParams(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("ddt", C.c_int32), ("ncell", C.c_int32 * 3),
-        ("pad", C.c_int32), ("origin", C.c_double * 3),
+        ("x_sub", C.c_int32), ("origin", C.c_double * 3),
         ("inv_cell_size", C.c_double), ("h", C.c_double), ("rho0", C.c_double),
         ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
         ("delta", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
@@ -95,6 +95,7 @@ def params(cp) -> OrcParams:
         p.origin[k] = float(cp.origin[k])
         p.gravity[k] = float(cp.gravity[k])
     p.inv_cell_size = float(cp.inv_cell_size)
+    p.x_sub = int(getattr(cp, "x_sub", 1))
     for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
                  "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
         setattr(p, name, float(getattr(cp, name)))

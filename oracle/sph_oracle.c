@@ -56,14 +56,17 @@ double orc_pressure(const orc_params* p, double rho) {
 }
 
 /* Cell key of Section 5.1's cell-linked list: the cell index along each axis
- * is floor((x - origin) * inv_cell_size) (an FP64 subtraction, then an FP64
- * multiplication), and cells are numbered with x fastest, then y, then z.  A
- * particle outside the grid gets the key ncell_total. */
+ * is floor((x - origin) * inv) (an FP64 subtraction, then an FP64
+ * multiplication) with inv the inverse cell size of that axis
+ * (inv_cell_size, times x_sub along x), and cells are numbered with x
+ * fastest, then y, then z.  A particle outside the grid gets the key
+ * ncell_total. */
 uint32_t orc_cell_key(const orc_params* p, const double* pos, int64_t n, int64_t i) {
   int64_t c[3] = {0, 0, 0};
   for (int k = 0; k < p->dim; ++k) {
     double d = pos[k * n + i] - p->origin[k];
-    double s = d * p->inv_cell_size;
+    double inv = p->inv_cell_size * (k == 0 && p->x_sub > 1 ? (double)p->x_sub : 1.0);
+    double s = d * inv;
     double f = floor(s);
     if (!(f >= 0.0) || !(f < (double)p->ncell[k]))
       return (uint32_t)((int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2]);

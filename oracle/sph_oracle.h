@@ -33,7 +33,8 @@ typedef struct orc_params {
   int32_t dim;             /* 2 or 3 */
   int32_t ddt;             /* 0: no density diffusion, 1: Eq. 18 */
   int32_t ncell[3];        /* cells per axis; ncell[2] = 1 in 2-D */
-  int32_t pad;
+  int32_t x_sub;           /* key cells per cell along x (cells of
+                              1/(inv_cell_size*x_sub) along x) */
   double origin[3];        /* grid origin */
   double inv_cell_size;    /* 1 / cell size, as the case defines it */
   double h, rho0, gamma, c0, alpha, delta, eta2, cfl;

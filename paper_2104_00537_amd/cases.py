@@ -58,6 +58,7 @@ class CaseParams:
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     ddt: int = 1
     cell_div: int = 1
+    x_sub: int = 1
     origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     cell_size: float = 0.0
     inv_cell_size: float = 0.0
@@ -128,7 +129,7 @@ def _walls(dim, nx_tank, ny_tank, nz_tank, closed_top):
 
 
 def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
-            cell_div=1, wall_type=BOUND_FIXED, motion_amp=0.0,
+            cell_div=1, x_sub=1, wall_type=BOUND_FIXED, motion_amp=0.0,
             motion_omega=0.0, h_factor=1.0, meta=None) -> Case:
     rng = np.random.default_rng(seed)
     idx = np.concatenate([fluid_idx, wall_idx], axis=1)
@@ -151,6 +152,7 @@ def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
     nc = np.ceil((hi - lo) / cs).astype(np.int64)
+    nc[0] *= x_sub  # key cells of cs/x_sub along x
     origin = [float(v) for v in lo] + [0.0] * (3 - dim)
     ncell = [int(v) for v in nc] + [1] * (3 - dim)
     grav = [0.0, 0.0, 0.0]
@@ -160,7 +162,7 @@ def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
         name=name, dim=dim, dp=dp, h=h, rho0=rho0, gamma=gamma, c0=c0,
         alpha=0.01, delta=0.1, eta2=0.001 * h * h, cfl=0.2,
         mass_fluid=mass, mass_bound=mass, gravity=tuple(grav), ddt=1,
-        cell_div=cell_div, origin=tuple(origin), cell_size=cs,
+        cell_div=cell_div, x_sub=x_sub, origin=tuple(origin), cell_size=cs,
         inv_cell_size=1.0 / cs, ncell=tuple(ncell), motion_amp=motion_amp,
         motion_omega=motion_omega, fluid_height=fluid_height)
     return Case(params=params, pos=np.ascontiguousarray(pos),
@@ -172,7 +174,7 @@ def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
 # the workloads
 # ----------------------------------------------------------------------------
 def dam_break_2d(dp=0.01, tank=(1.6, 1.0), column=(0.4, 0.8), seed=0,
-                 cell_div=1) -> Case:
+                 cell_div=1, x_sub=1) -> Case:
     """2-D dam break: a column at x_min in an open-top tank."""
     nxt, nzt = int(round(tank[0] / dp)), int(round(tank[1] / dp))
     nxf, nzf = int(round(column[0] / dp)), int(round(column[1] / dp))
@@ -181,11 +183,11 @@ def dam_break_2d(dp=0.01, tank=(1.6, 1.0), column=(0.4, 0.8), seed=0,
     lo = (-2.0 * dp - 1e-3 * dp, -2.0 * dp - 1e-3 * dp)
     hi = (nxt * dp + 2.0 * dp, max(nzt * dp, 2.5 * nzf * dp) + 2.0 * dp)
     return _finish("dam_break_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
-                   cell_div=cell_div, meta=dict(tank=tank, column=column))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, column=column))
 
 
 def dam_break_3d(dp=0.6 / 126, tank=(1.6, 0.6, 0.6), block=(0.6, 0.6, 0.3),
-                 seed=0, cell_div=1) -> Case:
+                 seed=0, cell_div=1, x_sub=1) -> Case:
     """3-D dam break: a water block at x_min filling the tank width."""
     nxt, nyt, nzt = (int(round(v / dp)) for v in tank)
     nxf, nyf, nzf = (int(round(v / dp)) for v in block)
@@ -195,11 +197,11 @@ def dam_break_3d(dp=0.6 / 126, tank=(1.6, 0.6, 0.6), block=(0.6, 0.6, 0.3),
     lo = (-m, -m, -m)
     hi = (nxt * dp + m, nyt * dp + m, max(nzt * dp, 2.5 * nzf * dp) + m)
     return _finish("dam_break_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
-                   cell_div=cell_div, meta=dict(tank=tank, block=block))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, block=block))
 
 
 def sloshing_3d(dp=0.0025, tank=(2.0, 1.0, 1.0), fill=0.5, seed=0,
-                cell_div=1, accel=0.05 * GRAVITY, freq_hz=0.5) -> Case:
+                cell_div=1, accel=0.05 * GRAVITY, freq_hz=0.5, x_sub=1) -> Case:
     """Closed tank, half full, whose walls follow the imposed sinusoidal
     motion x_B(t) = x_B0 + (A/w^2)(1 - cos wt) (peak acceleration A)."""
     nxt, nyt, nzt = (int(round(v / dp)) for v in tank)
@@ -212,13 +214,13 @@ def sloshing_3d(dp=0.0025, tank=(2.0, 1.0, 1.0), fill=0.5, seed=0,
     lo = (-m, -m, -m)
     hi = (nxt * dp + m + travel, nyt * dp + m, nzt * dp + m)
     return _finish("sloshing_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
-                   cell_div=cell_div, wall_type=BOUND_MOVING,
+                   cell_div=cell_div, x_sub=x_sub, wall_type=BOUND_MOVING,
                    motion_amp=accel, motion_omega=omega,
                    meta=dict(tank=tank, fill=fill))
 
 
 def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
-               vel_scale=0.0, rho_jitter=0.0, margin_cells=2) -> Case:
+               vel_scale=0.0, rho_jitter=0.0, margin_cells=2, x_sub=1) -> Case:
     """A fluid block of ``shape`` lattice cells (optionally in a closed box
     of walls), with optional random velocities and densities.  Used for
     invariance and parity tests."""
@@ -237,7 +239,7 @@ def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
     lo = tuple(-m for _ in range(dim))
     hi = tuple(s * dp + m for s in shape)
     case = _finish(f"block{dim}d", dim, dp, fluid, wall, height, lo, hi, seed,
-                   cell_div=cell_div, meta=dict(shape=shape, walls=walls))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(shape=shape, walls=walls))
     rng = np.random.default_rng(seed + 7919)
     if vel_scale:
         case.vel[:] = rng.uniform(-vel_scale, vel_scale, case.vel.shape).astype(np.float32)
@@ -248,7 +250,7 @@ def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
 
 
 def random_serving_case(rng: np.random.Generator, n_min=2000, n_max=500_000,
-                        seed=None, cell_div=2) -> Case:
+                        seed=None, cell_div=2, x_sub=4) -> Case:
     """One request of the serving stream: a 2-D or 3-D dam break or sloshing
     case with a log-uniform fluid particle count, column aspect ratio
     uniform in [0.5, 2] and fill ratio uniform in [0.3, 0.7]."""
@@ -267,27 +269,27 @@ def random_serving_case(rng: np.random.Generator, n_min=2000, n_max=500_000,
         if dim == 2:
             dp = math.sqrt(width * height / n_target)
             case = dam_break_2d(dp=dp, tank=(length, tank_h), column=(width, height),
-                                seed=sub_seed, cell_div=cell_div)
+                                seed=sub_seed, cell_div=cell_div, x_sub=x_sub)
         else:
             depth_y = 0.6
             dp = (width * depth_y * height / n_target) ** (1.0 / 3.0)
             case = dam_break_3d(dp=dp, tank=(length, depth_y, tank_h),
                                 block=(width, depth_y, height), seed=sub_seed,
-                                cell_div=cell_div)
+                                cell_div=cell_div, x_sub=x_sub)
     else:
         if dim == 2:
             dp = math.sqrt(2.0 * fill * 1.0 / n_target)
-            case = _sloshing_2d(dp, fill, sub_seed, cell_div=cell_div)
+            case = _sloshing_2d(dp, fill, sub_seed, cell_div=cell_div, x_sub=x_sub)
         else:
             dp = (2.0 * 1.0 * fill * 1.0 / n_target) ** (1.0 / 3.0)
-            case = sloshing_3d(dp=dp, fill=fill, seed=sub_seed, cell_div=cell_div)
+            case = sloshing_3d(dp=dp, fill=fill, seed=sub_seed, cell_div=cell_div, x_sub=x_sub)
     case.meta.update(kind=kind, steps=steps, aspect=aspect, fill=fill,
                      n_target=n_target)
     return case
 
 
 def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
-                 freq_hz=0.5, cell_div=1) -> Case:
+                 freq_hz=0.5, cell_div=1, x_sub=1) -> Case:
     nxt, nzt = int(round(tank[0] / dp)), int(round(tank[1] / dp))
     nzf = max(1, int(round(fill * tank[1] / dp)))
     fluid = _grid((0, nxt), (0, nzf))
@@ -299,4 +301,4 @@ def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
     hi = (nxt * dp + m + travel, nzt * dp + m)
     return _finish("sloshing_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
                    wall_type=BOUND_MOVING, motion_amp=accel, motion_omega=omega,
-                   cell_div=cell_div, meta=dict(tank=tank, fill=fill))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, fill=fill))

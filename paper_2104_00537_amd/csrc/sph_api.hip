@@ -21,6 +21,9 @@ KParams make_kparams(const sph_params& p) {
   k.oz = p.origin[2];
   k.cs = p.cell_size;
   k.inv_cs = p.inv_cell_size;
+  k.x_sub = p.x_sub;
+  k.lg_xsub = p.x_sub == 8 ? 3 : p.x_sub == 4 ? 2 : p.x_sub == 2 ? 1 : 0;
+  k.inv_csx = p.inv_cell_size * (double)p.x_sub;
   k.h = p.h;
   k.rho0 = p.rho0;
   k.gamma = p.gamma;
@@ -56,7 +59,7 @@ KParams make_kparams(const sph_params& p) {
   k.eta2_f = (float)p.eta2;
   k.ddt_coef_f = p.ddt ? (float)(2.0 * p.delta * p.h * p.c0) : 0.f;
   k.cs_f = (float)p.cell_size;
-  k.inv_cs_f = (float)p.inv_cell_size;
+  k.inv_csx_f = (float)(p.inv_cell_size * (double)p.x_sub);
   k.unit_x_f = (float)(kFrameCells * p.cell_size / 4294967296.0);
   k.gx_f = (float)p.gravity[0];
   k.gy_f = (float)p.gravity[1];
@@ -91,6 +94,7 @@ static bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
   if (p->cell_div != 1 && p->cell_div != 2) return false;
+  if (p->x_sub != 1 && p->x_sub != 2 && p->x_sub != 4 && p->x_sub != 8) return false;
   for (int k = 0; k < 3; ++k)
     if (p->ncell[k] < 1) return false;
   if (p->dim == 2 && p->ncell[2] != 1) return false;

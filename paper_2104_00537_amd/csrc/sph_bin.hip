@@ -161,18 +161,52 @@ __global__ void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t
 
 // ------------------------------------------------------------ cell ranges --
 // cell_start[c] = first sorted index whose key is >= c (lower bound), for
-// c = 0..ncell_total.
-__global__ void k_cell_start(const uint32_t* __restrict__ key, int64_t n, uint32_t ncell_total,
-                             uint32_t* __restrict__ start) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > (int64_t)ncell_total) return;
-  int64_t lo = 0, hi = n;
+// c = 0..ncell_total.  A block takes kCsCells consecutive cells: two of its
+// lanes find the lower bounds of its first cell and of the next block's first
+// cell in the whole key array; the keys between them (the block's particles)
+// are staged in LDS when they fit, and each cell's lower bound is then found
+// there; otherwise within that range in global memory.  Writes are coalesced.
+constexpr int kCsCells = 2048;
+constexpr int kCsKeys = 4096;
+
+__device__ inline int64_t lower_bound_u32(const uint32_t* __restrict__ a, int64_t lo, int64_t hi,
+                                          int64_t v) {
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)key[mid] < c) lo = mid + 1;
+    if ((int64_t)a[mid] < v) lo = mid + 1;
     else hi = mid;
   }
-  start[c] = (uint32_t)lo;
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_start(const uint32_t* __restrict__ key,
+                                                       int64_t n, uint32_t ncell_total,
+                                                       uint32_t* __restrict__ start) {
+  __shared__ uint32_t sk[kCsKeys];
+  __shared__ int64_t bound[2];
+  const int64_t c0 = (int64_t)blockIdx.x * kCsCells;
+  const int64_t c1 = c0 + kCsCells < (int64_t)ncell_total + 1 ? c0 + kCsCells
+                                                               : (int64_t)ncell_total + 1;
+  if (threadIdx.x < 2) bound[threadIdx.x] = lower_bound_u32(key, 0, n, threadIdx.x ? c1 : c0);
+  __syncthreads();
+  const int64_t lo = bound[0], hi = bound[1];
+  const int64_t m = hi - lo;
+  if (m <= kCsKeys) {
+    for (int64_t k = threadIdx.x; k < m; k += kBlock) sk[k] = key[lo + k];
+    __syncthreads();
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += kBlock) {
+      int a = 0, b = (int)m;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if ((int64_t)sk[mid] < c) a = mid + 1;
+        else b = mid;
+      }
+      start[c] = (uint32_t)(lo + a);
+    }
+  } else {
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += kBlock)
+      start[c] = (uint32_t)lower_bound_u32(key, lo, hi, c);
+  }
 }
 
 // --------------------------------------------------------------- reorder --
@@ -232,8 +266,8 @@ hipError_t radix_sort(int64_t n, uint32_t max_key, uint32_t* key_out, uint32_t* 
 void launch_cell_start(const uint32_t* key, int64_t n, uint32_t last_key, uint32_t* cell_start,
                        hipStream_t st) {
   const int64_t nc1 = (int64_t)last_key + 1;
-  hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((nc1 + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, st, key, n, last_key, cell_start);
+  hipLaunchKernelGGL(k_cell_start, dim3((unsigned)((nc1 + kCsCells - 1) / kCsCells)),
+                     dim3(kBlock), 0, st, key, n, last_key, cell_start);
 }
 
 hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, sph_state& out,

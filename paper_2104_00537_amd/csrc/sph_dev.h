@@ -8,8 +8,9 @@
 
 namespace sph {
 
-// Cell index per axis = floor((x - origin) * inv_cs): one FP64 subtraction and
-// one FP64 multiplication (no contraction is possible), x fastest.  Outside
+// Cell index per axis = floor((x - origin) * inv): one FP64 subtraction and
+// one FP64 multiplication (no contraction is possible), x fastest; inv is the
+// inverse cell size, times x_sub along x.  Outside
 // the grid, and for particles excluded earlier, the key is ncell_total, so
 // they sort last and lie in no cell range.
 __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __restrict__ pos,
@@ -21,7 +22,7 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
   int c[3] = {0, 0, 0};
   for (int k = 0; k < kp.dim; ++k) {
     const double d = __dsub_rn(pos[k * n + i], org[k]);
-    const double s = __dmul_rn(d, kp.inv_cs);
+    const double s = __dmul_rn(d, k == 0 ? kp.inv_csx : kp.inv_cs);
     const double f = floor(s);
     if (!(f >= 0.0) || !(f < (double)nc[k])) return kp.ncell_total;
     c[k] = (int)f;

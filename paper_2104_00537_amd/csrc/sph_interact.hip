@@ -98,8 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_interact_arm(
       const uint32_t rest = k / (uint32_t)kp.ncx;
       const int cy = (int)(rest % (uint32_t)kp.ncy);
       const int cz = (int)(rest / (uint32_t)kp.ncy);
-      const int x0 = cx - R < 0 ? 0 : cx - R;
-      const int x1 = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
+      const int reach = R * kp.x_sub;  // key cells along x
+      const int x0 = cx - reach < 0 ? 0 : cx - reach;
+      const int x1 = cx + reach >= kp.ncx ? kp.ncx - 1 : cx + reach;
       const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
       for (int dz = zlo; dz <= zhi; ++dz) {
         const int z = cz + dz;

@@ -19,11 +19,12 @@ constexpr uint32_t kXcds = 8;      // accelerator complex dies of the MI355X
 
 // Per-launch constants derived once on the host from sph_params.
 struct KParams {
-  int dim, cell_div, ddt, pad;
+  int dim, cell_div, ddt, x_sub;   // x_sub: key cells per cell along x
+  int lg_xsub, pad2;
   int ncx, ncy, ncz;
   uint32_t ncell_total;          // also the key of particles outside the grid
   double ox, oy, oz;             // grid origin
-  double cs, inv_cs;
+  double cs, inv_cs, inv_csx;     // cell size, its inverse, inverse along x (times x_sub)
   double h, rho0, gamma, c0, b_tait, cfl, dt_floor;
   double mass_f, mass_b;
   double gx, gy, gz;
@@ -36,7 +37,7 @@ struct KParams {
   float kfab_mf_f, kfab_mb_f;                // kfab m_fluid, kfab m_wall; kfab = -5 alpha_D / h^2
   float kpi_mf_f, kpi_mb_f;                  // -2 alpha c0 kfab m (Eq. 21 with Eq. 22)
   float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
-  float cs_f, inv_cs_f, unit_x_f;            // cell size, inverse, x offset unit
+  float cs_f, inv_csx_f, unit_x_f;           // cell size, inverse key-cell size along x, x offset unit
   float gx_f, gy_f, gz_f;
 };
 

@@ -191,9 +191,10 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 }
 
 // The candidate walk of one target lane over the rows of its neighbour cells
-// (cell indices offset by cbase).  The 2R+1 cells of a row along x are
-// consecutive in the sorted order, so a row is one candidate range; a row is
-// cut to the cells that the support sphere of the target reaches: with e_y,
+// (cell indices offset by cbase).  The key cells of a row along x (2R+1
+// cells of cs, each split into x_sub key cells) are consecutive in the sorted
+// order, so a row is one candidate range; a row is cut to the key cells that
+// the support sphere of the target reaches: with e_y,
 // e_z the distances from the target to the row's cell extent along y and z,
 // only |x_ab| < sqrt(4h^2 - e_y^2 - e_z^2) can hold a neighbour (rows with a
 // negative radicand are skipped).  The cut uses a support enlarged by 1e-4
@@ -223,10 +224,14 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
   const float cs = kp.cs_f;
   const float cull2 = kp.support2_f * 1.0002f;
   const uint32_t xa = __float_as_uint(pa.x);
-  // the target's offset inside its own cell along x
-  const float fx = (float)(int32_t)(xa - ((uint32_t)(cx % kFrameCells) << 29)) * kp.unit_x_f;
-  const int xlo = cx - R < 0 ? 0 : cx - R;
-  const int xhi = cx + R >= kp.ncx ? kp.ncx - 1 : cx + R;
+  // the target's offset inside its own key cell along x (key cells of
+  // cs/x_sub: 2^(29 - lg x_sub) fixed-point units each)
+  const int fcells = kFrameCells << kp.lg_xsub;
+  const float fx =
+      (float)(int32_t)(xa - ((uint32_t)(cx % fcells) << (29 - kp.lg_xsub))) * kp.unit_x_f;
+  const int reach = R * kp.x_sub;  // the stencil's reach in key cells along x
+  const int xlo = cx - reach < 0 ? 0 : cx - reach;
+  const int xhi = cx + reach >= kp.ncx ? kp.ncx - 1 : cx + reach;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     const int z = cz + dz;
@@ -241,8 +246,8 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
       const float w2 = cull2 - ey * ey - ez * ez;
       if (!(w2 > 0.f)) continue;
       const float w = __builtin_amdgcn_sqrtf(w2);
-      int x0 = cx + (int)floorf((fx - w) * kp.inv_cs_f);
-      int x1 = cx + (int)floorf((fx + w) * kp.inv_cs_f);
+      int x0 = cx + (int)floorf((fx - w) * kp.inv_csx_f);
+      int x1 = cx + (int)floorf((fx + w) * kp.inv_csx_f);
       x0 = x0 < xlo ? xlo : x0;
       x1 = x1 > xhi ? xhi : x1;
       const uint32_t row =

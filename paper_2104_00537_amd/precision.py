@@ -38,11 +38,11 @@ ARMS = {"f64": S.SPH_INTERACT_F64, "offset_f32": 0, "abs_f32": S.SPH_INTERACT_AB
 
 def _case(name):
     if name == "dam_break_3d_1m":
-        return cases.dam_break_3d(cell_div=2)
+        return cases.dam_break_3d(cell_div=2, x_sub=4)
     if name == "dam_break_3d_0p5m":
-        return cases.dam_break_3d(dp=0.006, cell_div=2)
+        return cases.dam_break_3d(dp=0.006, cell_div=2, x_sub=4)
     if name == "dam_break_2d":
-        return cases.dam_break_2d(cell_div=2)
+        return cases.dam_break_2d(cell_div=2, x_sub=4)
     raise SystemExit(f"unknown workload {name}")
 
 

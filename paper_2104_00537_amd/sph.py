@@ -35,7 +35,8 @@ SPH_BATCH_MAX_SLOTS = 4096
 class SphParams(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("cell_div", C.c_int32), ("ddt", C.c_int32),
-        ("ncell", C.c_int32 * 3), ("origin", C.c_double * 3),
+        ("ncell", C.c_int32 * 3), ("x_sub", C.c_int32), ("reserved", C.c_int32),
+        ("origin", C.c_double * 3),
         ("cell_size", C.c_double), ("inv_cell_size", C.c_double),
         ("h", C.c_double), ("rho0", C.c_double), ("gamma", C.c_double),
         ("c0", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
@@ -133,6 +134,7 @@ def make_params(cp) -> SphParams:
     """SphParams from a ``cases.CaseParams``."""
     p = SphParams()
     p.dim, p.cell_div, p.ddt = int(cp.dim), int(cp.cell_div), int(cp.ddt)
+    p.x_sub = int(getattr(cp, "x_sub", 1))
     for k in range(3):
         p.ncell[k] = int(cp.ncell[k])
         p.origin[k] = float(cp.origin[k])

@@ -129,15 +129,17 @@ def _scramble(case, seed):
 
 
 # ------------------------------------------------------------------ binning
-@pytest.mark.parametrize("cell_div", [1, 2])
-def test_bin_cells_2d_dam_break(cell_div):
-    _say("bin 2d dam break cell_div", cell_div)
-    _check_binning(_scramble(cases.dam_break_2d(cell_div=cell_div), 1), carry=True)
+@pytest.mark.parametrize("grid", [(1, 1), (2, 1), (2, 4)])
+def test_bin_cells_2d_dam_break(grid):
+    _say("bin 2d dam break cell_div, x_sub", grid)
+    c = cases.dam_break_2d(cell_div=grid[0], x_sub=grid[1])
+    _check_binning(_scramble(c, 1), carry=True)
 
 
-def test_bin_cells_3d_block_ragged():
-    _say("bin 3d ragged")
-    c = cases.block_case(3, (23, 19, 13), walls=True, seed=3)  # ~5.7k + walls
+@pytest.mark.parametrize("x_sub", [1, 8])
+def test_bin_cells_3d_block_ragged(x_sub):
+    _say("bin 3d ragged x_sub", x_sub)
+    c = cases.block_case(3, (23, 19, 13), walls=True, seed=3, cell_div=2, x_sub=x_sub)
     _check_binning(_scramble(c, 2))
 
 
@@ -219,14 +221,14 @@ def _check_interact(case, label):
 
 
 def test_interaction_stencils_agree():
-    """Cells of 2h (3x3x3 stencil) and of h (5x5x5 stencil) visit different
-    candidate sets but the same neighbours: the sums agree to rounding and the
-    FP32 counts differ only at near-ties (the x frames differ with the cell
-    size)."""
+    """Cells of 2h (3x3x3 stencil), of h (5x5x5 stencil) and of h split in 4
+    along x visit different candidate sets but the same neighbours: the sums
+    agree to rounding and the FP32 counts differ only at near-ties (the x
+    offsets are rounded in different frames)."""
     outs = []
-    for cd in (1, 2):
-        c = _perturbed(cases.block_case(3, (19, 15, 13), walls=True, seed=31, cell_div=cd),
-                       32, vel=0.4)
+    for grid in ((1, 1), (2, 1), (2, 4)):
+        c = _perturbed(cases.block_case(3, (19, 15, 13), walls=True, seed=31, cell_div=grid[0],
+                                        x_sub=grid[1]), 32, vel=0.4)
         b = Binned(c)
         perm = _u32(b.perm)[:c.n].astype(np.int64)  # sorted slot -> input index
         res = []
@@ -235,22 +237,23 @@ def test_interaction_stencils_agree():
             u[..., perm] = r
             res.append(u)
         outs.append(res)
-    g, t = outs
-    flips = int(np.abs(t[3].astype(np.int64) - g[3].astype(np.int64)).sum())
-    _say(f"  cd2 vs cd1 count flips {flips} of {int(g[3].sum())}")
-    assert flips <= FLIP_FRACTION * g[3].sum() + 2
-    for i in range(3):
-        scale = max(np.abs(g[i]).max(), 1e-30)
-        assert np.abs(t[i] - g[i]).max() <= 2e-5 * scale
+    g = outs[0]
+    for t in outs[1:]:
+        flips = int(np.abs(t[3].astype(np.int64) - g[3].astype(np.int64)).sum())
+        _say(f"  count flips against 2h cells {flips} of {int(g[3].sum())}")
+        assert flips <= FLIP_FRACTION * g[3].sum() + 2
+        for i in range(3):
+            scale = max(np.abs(g[i]).max(), 1e-30)
+            assert np.abs(t[i] - g[i]).max() <= 2e-5 * scale
 
 
-@pytest.mark.parametrize("cell_div", [1, 2])
-def test_interact_long_x_frame_blocks(cell_div):
-    """A block long along x spans many blocks of 8 cells of the x frame, so
-    many pairs straddle a frame edge (the block-length correction)."""
-    c = cases.block_case(3, (120, 7, 6), walls=True, seed=12, cell_div=cell_div)
-    assert c.params.ncell[0] >= 4 * 8
-    _check_interact(_perturbed(c, 13, vel=0.3), f"3d long x cd{cell_div}")
+@pytest.mark.parametrize("grid", [(1, 1), (2, 1), (2, 4)])
+def test_interact_long_x_frame_blocks(grid):
+    """A block long along x spans many periods (8 cells) of the fixed-point x
+    offsets, so many pairs straddle a period edge (the 32-bit wrap)."""
+    c = cases.block_case(3, (120, 7, 6), walls=True, seed=12, cell_div=grid[0], x_sub=grid[1])
+    assert c.params.ncell[0] >= 4 * 8 * grid[1]
+    _check_interact(_perturbed(c, 13, vel=0.3), f"3d long x {grid}")
 
 
 @pytest.mark.parametrize("cell_div", [1, 2])
@@ -258,15 +261,16 @@ def test_interact_2d_dam_break_initial(cell_div):
     _check_interact(cases.dam_break_2d(cell_div=cell_div), f"2d t0 cd{cell_div}")
 
 
-@pytest.mark.parametrize("cell_div", [1, 2])
-def test_interact_2d_perturbed(cell_div):
-    _check_interact(_perturbed(cases.dam_break_2d(cell_div=cell_div), 5), f"2d pert cd{cell_div}")
+@pytest.mark.parametrize("grid", [(1, 1), (2, 1), (2, 4)])
+def test_interact_2d_perturbed(grid):
+    c = cases.dam_break_2d(cell_div=grid[0], x_sub=grid[1])
+    _check_interact(_perturbed(c, 5), f"2d pert {grid}")
 
 
-@pytest.mark.parametrize("cell_div", [1, 2])
-def test_interact_3d_block_with_walls(cell_div):
-    c = cases.block_case(3, (21, 17, 15), walls=True, seed=4, cell_div=cell_div)
-    _check_interact(_perturbed(c, 6, vel=0.3), f"3d walls cd{cell_div}")
+@pytest.mark.parametrize("grid", [(1, 1), (2, 1), (2, 2), (2, 4), (2, 8)])
+def test_interact_3d_block_with_walls(grid):
+    c = cases.block_case(3, (21, 17, 15), walls=True, seed=4, cell_div=grid[0], x_sub=grid[1])
+    _check_interact(_perturbed(c, 6, vel=0.3), f"3d walls {grid}")
 
 
 def test_interact_moving_walls_and_excluded():
@@ -431,7 +435,7 @@ def test_dam_break_3d_1m_sampled():
     the benchmark times: keys/perm/ranges bit-exact against the oracle,
     interaction outputs on 600 sampled targets."""
     _say("3d 1M sampled")
-    c = cases.dam_break_3d()
+    c = cases.dam_break_3d(cell_div=2, x_sub=4)
     b = Binned(c)
     n = c.n
     key_ref = oracle.cell_keys(c.params, c.pos)

@@ -105,19 +105,27 @@ def test_eos_hydrostatic_initial_state():
 # --------------------------------------------------------------------------
 # cell-linked list, Section 5.1
 # --------------------------------------------------------------------------
+def _axis_cell(cp, ax):
+    """Key-cell size along an axis: cs, or cs/x_sub along x."""
+    return cp.cell_size / (cp.x_sub if ax == 0 else 1)
+
+
 def _random_in_grid(cp, n, rng, outside=0):
     lo = np.array(cp.origin[: cp.dim])
-    hi = lo + np.array(cp.ncell[: cp.dim]) * cp.cell_size
+    hi = lo + np.array(cp.ncell[: cp.dim]) * np.array([_axis_cell(cp, a) for a in range(cp.dim)])
     pos = rng.uniform(lo[:, None], hi[:, None], size=(cp.dim, n))
     if outside:
         pos[:, :outside] = hi[:, None] + 0.1
     return pos
 
 
-@pytest.mark.parametrize("maker", [cases.dam_break_2d, lambda: cases.block_case(3, (9, 7, 5))])
+@pytest.mark.parametrize("maker", [cases.dam_break_2d, lambda: cases.block_case(3, (9, 7, 5)),
+                                   lambda: cases.dam_break_2d(cell_div=2, x_sub=2),
+                                   lambda: cases.block_case(3, (9, 7, 5), cell_div=2, x_sub=4)])
 def test_cell_keys_contain_particle(maker):
     """Every key names the cell that contains the particle (x fastest, then y,
-    then z); particles outside the grid get ncell_total."""
+    then z; key cells of cs/x_sub along x); particles outside the grid get
+    ncell_total."""
     cp = maker().params
     rng = np.random.default_rng(3)
     pos = _random_in_grid(cp, 4000, rng, outside=5)
@@ -129,13 +137,14 @@ def test_cell_keys_contain_particle(maker):
         c = [k % nc[0], (k // nc[0]) % nc[1], k // (nc[0] * nc[1])]
         for ax in range(cp.dim):
             x = Fraction(pos[ax, i]) - Fraction(cp.origin[ax])
-            cs = Fraction(cp.cell_size)
+            cs = Fraction(cp.cell_size) / (cp.x_sub if ax == 0 else 1)
             # within one rounding of the cell's bounds
             slack = Fraction(1, 10 ** 12) * cs
             assert c[ax] * cs - slack <= x < (c[ax] + 1) * cs + slack
     # same FP64 operations evaluated by numpy: bit-identical keys
     lo = np.array(cp.origin[: cp.dim])[:, None]
-    cidx = np.floor((pos - lo) * cp.inv_cell_size).astype(np.int64)
+    inv = np.array([cp.inv_cell_size * (cp.x_sub if a == 0 else 1) for a in range(cp.dim)])
+    cidx = np.floor((pos - lo) * inv[:, None]).astype(np.int64)
     inside = np.all((cidx >= 0) & (cidx < np.array(nc[: cp.dim])[:, None]), axis=0)
     if cp.dim == 2:
         ref = cidx[0] + nc[0] * cidx[1]
