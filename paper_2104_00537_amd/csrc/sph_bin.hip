@@ -83,6 +83,7 @@ __global__ void k_scan_add(uint32_t* __restrict__ data, int64_t len,
 void exclusive_scan(uint32_t* data, int64_t len, uint32_t* part, hipStream_t st) {
   const int64_t parts = (len + kScanTile - 1) / kScanTile;
   if (parts == 0) return;
+
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)parts), dim3(kBlock), 0, st, data, len, part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kBlock), 0, st, part, parts);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)parts), dim3(kBlock), 0, st, data, len, part);
@@ -109,24 +110,54 @@ __global__ void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int s
   for (int b = threadIdx.x; b < bins; b += kBlock) hist[(int64_t)b * nblk + blockIdx.x] = h[b];
 }
 
-__global__ void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                int64_t n, int shift, int bits,
-                                const uint32_t* __restrict__ offs, int64_t nblk) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wbase[kBlock / 64][256];
+// Scatter of one pass.  Wave w of a block owns keys [w*512, (w+1)*512) of the
+// block's tile (8 rounds of 64); a wave ranks the keys of a round among
+// themselves with ballots (lanes holding the same digit, in lane order) and
+// keeps a running count per digit in its own LDS row, so each key gets its
+// position within the wave's digit run without block barriers.  The tile is
+// then sorted by digit in LDS (digit-major, then wave, then position) and
+// written out from there, so that consecutive threads store consecutive
+// addresses of a digit's run.  Tile order is wave-major, round, lane -- the
+// input order -- so the pass is stable.
+//
+// offs holds the digit-major per-tile offsets; with part != nullptr they are
+// scanned only within scan tiles of kScanTile entries and part[] holds the
+// scan tiles' totals (at most kFusedParts of them), whose prefix each block
+// forms itself.
+constexpr int kFusedParts = 2 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift, int bits,
+    const uint32_t* __restrict__ offs, int64_t nblk, const uint32_t* __restrict__ part,
+    int64_t parts) {
+  __shared__ uint32_t wrun[kBlock / 64][256];  // per-wave digit counts, then local bases
+  __shared__ uint32_t dstart[256];             // first local position of each digit
+  __shared__ uint32_t gbase[256];              // global position of each digit's run
+  __shared__ uint32_t pp[kFusedParts];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  if (part) {
+    const int64_t p0 = 2 * (int64_t)threadIdx.x;
+    const uint32_t v0 = p0 < parts ? part[p0] : 0u;
+    const uint32_t v1 = p0 + 1 < parts ? part[p0 + 1] : 0u;
+    const uint32_t ex = block_exclusive_scan(v0 + v1, nullptr);
+    pp[p0] = ex;
+    pp[p0 + 1] = ex + v0;
+  }
   const int bins = 1 << bits;
   const uint32_t mask = (uint32_t)bins - 1u;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int b = threadIdx.x; b < bins; b += kBlock) run[b] = offs[(int64_t)b * nblk + blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int b = lane; b < 256; b += 64) wrun[wave][b] = 0;
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = tile0 + (int64_t)wave * (64 * kSortItems);
+  uint32_t kk[kSortItems], vv[kSortItems], pos[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t i = base + r * kBlock + threadIdx.x;
+    const int64_t i = base + r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
     const uint32_t d = (key >> shift) & mask;
-    // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
@@ -134,35 +165,56 @@ __global__ void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t
       peers &= bit ? bal : ~bal;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    for (int b = threadIdx.x; b < bins; b += kBlock)
-      for (int w = 0; w < kBlock / 64; ++w) wbase[w][b] = 0;
-    __syncthreads();
-    if (valid && rank == 0) wbase[wave][d] = cnt;
-    __syncthreads();
-    for (int b = threadIdx.x; b < bins; b += kBlock) {
-      uint32_t s = run[b];
-      for (int w = 0; w < kBlock / 64; ++w) {
-        const uint32_t c = wbase[w][b];
-        wbase[w][b] = s;
-        s += c;
-      }
-      run[b] = s;
+    const uint32_t prior = wrun[wave][d];
+    pos[r] = prior + rank;
+    // the first lane of each digit group advances the wave's running count
+    // (this wave's reads of the round came first, in program order)
+    if (valid && rank == 0) wrun[wave][d] = prior + (uint32_t)__popcll(peers);
+    kk[r] = key;
+    vv[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+  }
+  __syncthreads();
+  // digit totals of the tile, their exclusive scan, and the per-wave bases
+  const int b = threadIdx.x;  // one digit per thread (bins <= kBlock)
+  uint32_t tot = 0;
+  if (b < bins)
+    for (int w = 0; w < kBlock / 64; ++w) tot += wrun[w][b];
+  const uint32_t ds = block_exclusive_scan(b < bins ? tot : 0u, nullptr);
+  if (b < bins) {
+    dstart[b] = ds;
+    const int64_t o = (int64_t)b * nblk + blockIdx.x;
+    gbase[b] = offs[o] + (part ? pp[o / kScanTile] : 0u);
+    uint32_t s = ds;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const uint32_t c = wrun[w][b];
+      wrun[w][b] = s;
+      s += c;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t dst = wbase[wave][d] + rank;
-      kout[dst] = key;
-      vout[dst] = vin ? vin[i] : (uint32_t)i;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (base + r * 64 + lane < n) {
+      const uint32_t lp = wrun[wave][(kk[r] >> shift) & mask] + pos[r];
+      sk[lp] = kk[r];
+      sv[lp] = vv[r];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  const int64_t cnt = n - tile0 < kSortTile ? n - tile0 : kSortTile;
+  for (int p = threadIdx.x; p < cnt; p += kBlock) {
+    const uint32_t key = sk[p];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t dst = gbase[d] + ((uint32_t)p - dstart[d]);
+    kout[dst] = key;
+    vout[dst] = sv[p];
   }
 }
 
 // ------------------------------------------------------------ cell ranges --
 // cell_start[c] = first sorted index whose key is >= c (lower bound), for
 // c = 0..ncell_total.  A block takes kCsCells consecutive cells: two of its
-// lanes find the lower bounds of its first cell and of the next block's first
+// waves find the lower bounds of its first cell and of the next block's first
 // cell in the whole key array; the keys between them (the block's particles)
 // are staged in LDS when they fit, and each cell's lower bound is then found
 // there; otherwise within that range in global memory.  Writes are coalesced.
@@ -187,7 +239,26 @@ __global__ __launch_bounds__(kBlock) void k_cell_start(const uint32_t* __restric
   const int64_t c0 = (int64_t)blockIdx.x * kCsCells;
   const int64_t c1 = c0 + kCsCells < (int64_t)ncell_total + 1 ? c0 + kCsCells
                                                                : (int64_t)ncell_total + 1;
-  if (threadIdx.x < 2) bound[threadIdx.x] = lower_bound_u32(key, 0, n, threadIdx.x ? c1 : c0);
+  // waves 0 and 1 find the lower bounds of c0 and c1 by a 64-ary search:
+  // each round probes 64 evenly spaced keys of the current range, and the
+  // probes below the target (a prefix, the keys being sorted) narrow it to
+  // one gap between probes
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < 2) {
+    const int64_t c = wave == 0 ? c0 : c1;
+    int64_t lo = 0, hi = n;
+    while (hi > lo) {
+      const int64_t step = (hi - lo + 63) / 64;
+      const int64_t p = lo + (int64_t)lane * step;
+      const bool below = p < hi && (int64_t)key[p] < c;
+      const int64_t cnt = __popcll(__ballot(below));
+      const int64_t pc = lo + cnt * step;
+      const int64_t nlo = cnt == 0 ? lo : lo + (cnt - 1) * step + 1;
+      hi = pc < hi ? pc : hi;
+      lo = nlo;
+    }
+    if (lane == 0) bound[wave] = lo;
+  }
   __syncthreads();
   const int64_t lo = bound[0], hi = bound[1];
   const int64_t m = hi - lo;
@@ -254,9 +325,19 @@ hipError_t radix_sort(int64_t n, uint32_t max_key, uint32_t* key_out, uint32_t* 
     const int64_t nblk = L.nblk_sort;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, n, shift,
                        bits, hist, nblk);
-    exclusive_scan(hist, (int64_t)(1 << bits) * nblk, part, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, vsrc,
-                       kdst, vdst, n, shift, bits, hist, nblk);
+    const int64_t hlen = (int64_t)(1 << bits) * nblk;
+    const int64_t hparts = (hlen + kScanTile - 1) / kScanTile;
+    if (hparts <= kFusedParts) {
+      // tile-local scans here; the scatter adds the tiles' prefix itself
+      hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)hparts), dim3(kBlock), 0, st, hist, hlen,
+                         part);
+      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, vsrc,
+                         kdst, vdst, n, shift, bits, hist, nblk, part, hparts);
+    } else {
+      exclusive_scan(hist, hlen, part, st);
+      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, st, ksrc, vsrc,
+                         kdst, vdst, n, shift, bits, hist, nblk, nullptr, (int64_t)0);
+    }
     ksrc = kdst;
     vsrc = vdst;
   }
