@@ -77,6 +77,12 @@ def lib():
         for name in ("orc_predictor", "orc_corrector"):
             getattr(L, name).argtypes = [P(OrcParams), C.c_int64, C.c_double,
                                          C.c_double] + [C.c_void_p] * 9
+        L.orc_verlet.argtypes = [P(OrcParams), C.c_int64, C.c_double, C.c_double,
+                                 C.c_int32] + [C.c_void_p] * 8
+        L.orc_run_verlet.restype = C.c_int32
+        L.orc_run_verlet.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     P(C.c_double), C.c_void_p, P(C.c_uint64)]
         L.orc_run.restype = C.c_int32
         L.orc_run.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double),
@@ -214,3 +220,34 @@ def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0):
                        _ptr(ptype), int(nsteps), C.byref(t), _ptr(dts), C.byref(inter))
     return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
                 dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
+
+
+def verlet(cp, dt, t, mode, pos, vel, rho, vel_prev, rho_prev, ptype, ace, arho):
+    """One Verlet update (Section 2.5.1; mode 0: Eq. 30, mode 1: Eq. 31).
+    Returns (pos, vel, rho) at n+1 and (vel_prev, rho_prev) = state n."""
+    pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
+    vp, rp = _f64(vel_prev).copy(), _f64(rho_prev).copy()
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    ace, arho = _f64(ace), _f64(arho)
+    p = params(cp)
+    lib().orc_verlet(C.byref(p), rho.shape[0], float(dt), float(t), int(mode), _ptr(pos),
+                     _ptr(vel), _ptr(rho), _ptr(vp), _ptr(rp), _ptr(ptype), _ptr(ace),
+                     _ptr(arho))
+    return (pos, vel, rho), (vp, rp)
+
+
+def run_verlet(cp, pos, vel, rho, ptype, nsteps, ns=40, t0=0.0):
+    """nsteps Verlet steps (Eq. 31 on the first step and every ns-th).
+    Returns the same dict as run()."""
+    pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8).copy()
+    t = C.c_double(float(t0))
+    dts = np.zeros(max(int(nsteps), 1), np.float64)
+    inter = C.c_uint64(0)
+    p = params(cp)
+    st = lib().orc_run_verlet(C.byref(p), rho.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
+                              _ptr(ptype), int(nsteps), int(ns), C.byref(t), _ptr(dts),
+                              C.byref(inter))
+    return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
+                dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
+

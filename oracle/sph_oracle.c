@@ -311,6 +311,42 @@ void orc_corrector(const orc_params* p, int64_t n, double dt, double t,
   }
 }
 
+/* Verlet step, Section 2.5.1, from state n (pos, vel, rho) with the state of
+ * step n-1 (vel_p, rho_p) and the rates F^n (ace), R^n (arho):
+ *   mode 0 (Eq. 30): v^{n+1} = v^{n-1} + 2 dt F^n, rho^{n+1} = rho^{n-1} + 2 dt R^n;
+ *   mode 1 (Eq. 31, the intermediate step, also the first step):
+ *     v^{n+1} = v^n + dt F^n, rho^{n+1} = rho^n + dt R^n;
+ *   both: r^{n+1} = r^n + dt v^n + dt^2/2 F^n.
+ * Positions and velocities change for fluid particles only; moving walls
+ * take their imposed position and velocity at t + dt; density evolves for
+ * every particle.  Afterwards vel_p, rho_p hold state n. */
+void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mode,
+                double* pos, double* vel, double* rho, double* vel_p, double* rho_p,
+                const uint8_t* type, const double* ace, const double* arho) {
+  const int dim = p->dim;
+  const double dmove = motion_disp(p, t + dt) - motion_disp(p, t);
+  const double vmove = motion_vel(p, t + dt);
+  for (int64_t a = 0; a < n; ++a) {
+    if (is_excluded(type[a])) continue;
+    for (int k = 0; k < dim; ++k) {
+      const double vn = vel[k * n + a];
+      if (is_fluid(type[a])) {
+        const double f = ace[k * n + a];
+        pos[k * n + a] = pos[k * n + a] + dt * vn + 0.5 * dt * dt * f;
+        vel[k * n + a] = mode == 0 ? vel_p[k * n + a] + 2.0 * dt * f : vn + dt * f;
+      }
+      vel_p[k * n + a] = vn;
+    }
+    if ((type[a] & 0x7fu) == ORC_MOVING) {
+      pos[a] = pos[a] + dmove;
+      vel[a] = vmove;
+    }
+    const double rn = rho[a];
+    rho[a] = mode == 0 ? rho_p[a] + 2.0 * dt * arho[a] : rn + dt * arho[a];
+    rho_p[a] = rn;
+  }
+}
+
 /* Marks particles outside the cell grid as excluded (they leave the
  * computation for good, as the GPU path's binning does). */
 static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
@@ -359,5 +395,40 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
   }
   free(ace); free(arho); free(visc); free(nbr);
   free(pos_n); free(vel_n); free(rho_n);
+  return status;
+}
+
+/* nsteps Verlet steps (Section 2.5.1), each: PI at n -> dt (Eq. 35) -> the
+ * update of Eq. 30, or of Eq. 31 on the first step and on every step whose
+ * index is a multiple of ns -> t += dt.  Same outputs and status as orc_run. */
+int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
+                       double* rho, uint8_t* type, int32_t nsteps, int32_t ns, double* t,
+                       double* dt_hist, uint64_t* interactions) {
+  const int dim = p->dim;
+  size_t nd = (size_t)dim * (size_t)(n > 0 ? n : 1);
+  double* ace = (double*)calloc(nd, sizeof(double));
+  double* arho = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* visc = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  uint32_t* nbr = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+  double* vel_p = (double*)calloc(nd, sizeof(double));
+  double* rho_p = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  int32_t status = 0;
+  for (int32_t s = 0; s < nsteps && status == 0; ++s) {
+    mark_excluded(p, n, pos, type);
+    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    uint64_t count = 0;
+    for (int64_t a = 0; a < n; ++a) count += nbr[a];
+    const double dt = orc_time_step(p, n, type, ace, visc);
+    if (dt_hist) dt_hist[s] = dt;
+    if (!(dt > 0.0) || !isfinite(dt)) { status = 2; break; }
+    const int32_t mode = (ns > 0 && s % ns == 0) ? 1 : 0;
+    orc_verlet(p, n, dt, *t, mode, pos, vel, rho, vel_p, rho_p, type, ace, arho);
+    *t += dt;
+    if (interactions) *interactions += count;
+    for (int64_t a = 0; a < n; ++a)
+      if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
+  }
+  free(ace); free(arho); free(visc); free(nbr);
+  free(vel_p); free(rho_p);
   return status;
 }

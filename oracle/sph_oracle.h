@@ -71,6 +71,13 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
                 double* rho, uint8_t* type, int32_t nsteps, double* t,
                 double* dt_hist, uint64_t* interactions);
 
+void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mode,
+                double* pos, double* vel, double* rho, double* vel_p, double* rho_p,
+                const uint8_t* type, const double* ace, const double* arho);
+int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
+                       double* rho, uint8_t* type, int32_t nsteps, int32_t ns, double* t,
+                       double* dt_hist, uint64_t* interactions);
+
 #ifdef __cplusplus
 }
 #endif
