@@ -118,6 +118,28 @@ def cpu_baseline(case, sim, seconds):
                       f"(all {n} as candidate neighbours, brute force FP64), {el:.1f} s"}
 
 
+def verlet_leg(case, steps, warmup):
+    """The same workload advanced with the Verlet scheme (Eq. 30-31, one
+    interaction per step, Eq. 31 every 40 steps): steps/s and interactions/s."""
+    import torch
+    from paper_2104_00537_amd.runner import Simulation
+    sim = Simulation(case, "cuda:0", integrator="verlet", verlet_ns=40)
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    i0 = sim.interaction_count()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if sim.error() != 0:
+        raise SystemExit(f"device error word {sim.error()} in the Verlet leg")
+    pairs = sim.interaction_count() - i0
+    return {"steps": steps, "ms_per_step": el / steps * 1e3, "steps_per_s": steps / el,
+            "interactions_per_s": pairs / el, "ns": 40}
+
+
 def serving(args):
     """The request stream through the batched engine and the plain
     one-case-at-a-time path (same seeded trace, same GPU)."""
@@ -209,6 +231,7 @@ def main():
                     help="step: the benchmark; interact/copy: kernel-only runs for counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-verlet", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -292,6 +315,8 @@ def main():
     }
     print(f"[bench] timed {args.steps} steps: {pairs / el:.4g} interactions/s", file=sys.stderr,
           flush=True)
+    if not args.no_verlet:
+        res["verlet"] = verlet_leg(case, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:

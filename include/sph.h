@@ -12,6 +12,7 @@
  *                        within 2h (Eq. 11, 15, 17-18, 21-22, 28, 36), plus the
  *                        per-particle maxima that set the time step.
  *   sph_reduce_dt        SU: the variable time step of Eq. 35, kept on the GPU.
+ *   sph_verlet_step      SU: the Verlet scheme (Eq. 30-31), one PI per step.
  *   sph_symplectic_step  SU: symplectic predictor / corrector (Eq. 33-34), with
  *                        imposed motion of moving walls (Eq. 37).
  *
@@ -206,6 +207,24 @@ sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase,
                                sph_state* s, const float* ace,
                                const float* arho, void* ws, size_t ws_bytes,
                                void* stream);
+
+/* SU, Section 2.5.1: the Verlet scheme, one interaction per step, on the
+ * sorted state.
+ *   mode 0 (Eq. 30): fluid v = v_prev + 2 dt ace; all rho = rho_prev + 2 dt arho;
+ *   mode 1 (Eq. 31, the intermediate step, also the first step when no
+ *     previous state exists): fluid v += dt ace; all rho += dt arho;
+ *   both: fluid r += dt v^n + dt^2/2 ace (v^n the velocity before the call).
+ *   prev: velocity and density of step n-1 in the current sorted order (carry
+ *     it through sph_bin_cells as the carried state); on return it holds
+ *     those of step n.  prev->pos is not used.
+ *   Moving walls take x = x + D(t + dt) - D(t) and v_x = (A/w) sin(w (t + dt));
+ *   fixed walls keep position and velocity.  Then *t += dt.
+ *   The paper recommends mode 1 every ~40 steps (the caller chooses).
+ * Sets SPH_ERR_NONFINITE for a non-finite velocity or a density not in
+ * (0, inf). */
+sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const double* dt,
+                           double* t, sph_state* prev, sph_state* s, const float* ace,
+                           const float* arho, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batches --
  * Continuous batching: n_slots independent cases packed into one set of

@@ -185,6 +185,19 @@ sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase, co
                                       (hipStream_t)stream));
 }
 
+sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const double* dt,
+                           double* t, sph_state* prev, sph_state* s, const float* ace,
+                           const float* arho, void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !dt || !t || !ws) return SPH_E_ARG;
+  if (mode != 0 && mode != 1) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !prev || !prev->vel || !prev->rho || !ace || !arho))
+    return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state pv = n > 0 ? *prev : sph_state{}, st = n > 0 ? *s : sph_state{};
+  return hip_status(launch_verlet(make_kparams(*p), n, mode, dt, t, pv, st, ace, arho, ws,
+                                  (hipStream_t)stream));
+}
+
 int32_t sph_read_error(const void* ws) {
   if (!ws) return SPH_E_ARG;
   uint32_t v = 0;

@@ -168,4 +168,47 @@ __device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, d
   return bad || !(rf > 0.f) || !isfinite(rf);
 }
 
+// One particle of the Verlet update (Section 2.5.1): MODE 0 is Eq. 30
+// (v^{n+1} = v^{n-1} + 2 dt F, rho^{n+1} = rho^{n-1} + 2 dt R), MODE 1 is
+// Eq. 31 (v^{n+1} = v^n + dt F, rho^{n+1} = rho^n + dt R, the intermediate
+// step); both move fluid particles by r += dt v^n + dt^2/2 F.  `prev` holds
+// the velocity and density of step n-1 and receives those of step n.  Moving
+// walls take their imposed position and velocity (dmove since t, vmove at
+// t + dt).  Returns true if the new state is not finite or the density not
+// positive.
+template <int MODE>
+__device__ inline bool verlet_one(const KParams& kp, int64_t n, int64_t i, double dt,
+                                  double dmove, double vmove, const sph_state& prev,
+                                  const sph_state& s, const float* __restrict__ ace,
+                                  const float* __restrict__ arho) {
+  const uint8_t t = s.type[i];
+  if (is_excluded(t)) return false;
+  bool bad = false;
+  const bool fluid = is_fluid(t);
+  for (int d = 0; d < kp.dim; ++d) {
+    const float vn = s.vel[d * n + i];
+    if (fluid) {
+      const double a = (double)ace[d * n + i];
+      s.pos[d * n + i] = s.pos[d * n + i] + dt * (double)vn + 0.5 * dt * dt * a;
+      const double v1 = MODE == 0 ? (double)prev.vel[d * n + i] + 2.0 * dt * a
+                                  : (double)vn + dt * a;
+      const float v1f = (float)v1;
+      s.vel[d * n + i] = v1f;
+      bad |= !isfinite(v1f);
+    }
+    prev.vel[d * n + i] = vn;
+  }
+  if ((t & 0x7f) == SPH_BOUND_MOVING) {
+    s.pos[i] = s.pos[i] + dmove;
+    s.vel[i] = (float)vmove;
+  }
+  const float rn = s.rho[i];
+  const double r = MODE == 0 ? (double)prev.rho[i] + 2.0 * dt * (double)arho[i]
+                             : (double)rn + dt * (double)arho[i];
+  prev.rho[i] = rn;
+  const float rf = (float)r;
+  s.rho[i] = rf;
+  return bad || !(rf > 0.f) || !isfinite(rf);
+}
+
 }  // namespace sph

@@ -34,6 +34,9 @@ hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* 
 hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const double* dt, double* t,
                              sph_state& saved, sph_state& s, const float* ace, const float* arho,
                              void* ws, hipStream_t st);
+hipError_t launch_verlet(const KParams& kp, int64_t n, int mode, const double* dt, double* t,
+                         sph_state& prev, sph_state& s, const float* ace, const float* arho,
+                         void* ws, hipStream_t st);
 hipError_t launch_clear_error(void* ws, hipStream_t st);
 
 hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_state& out,

@@ -1,6 +1,6 @@
-// System update (Section 5.1): the variable time step of Eq. 35 and the
-// symplectic position-Verlet update of Eq. 33-34, with the imposed motion of
-// moving walls (Eq. 37).
+// System update (Section 5.1): the variable time step of Eq. 35, the
+// symplectic position-Verlet update of Eq. 33-34 and the Verlet update of
+// Eq. 30-31, with the imposed motion of moving walls (Eq. 37).
 #include "sph_dev.h"
 #include "sph_kernels.h"
 
@@ -81,6 +81,26 @@ __global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ d
     set_error(err, SPH_ERR_NONFINITE);
 }
 
+// Verlet update (Eq. 30 for MODE 0, Eq. 31 for MODE 1) of the sorted state.
+template <int MODE>
+__global__ void k_verlet(KParams kp, int64_t n, const double* __restrict__ dtp,
+                         const double* __restrict__ tp, sph_state prev, sph_state s,
+                         const float* __restrict__ ace, const float* __restrict__ arho,
+                         uint32_t* __restrict__ err) {
+  __shared__ double shm[3];
+  if (threadIdx.x == 0) {
+    const double dt = *dtp, t = *tp;
+    shm[0] = dt;
+    shm[1] = motion_disp(kp, t + dt) - motion_disp(kp, t);
+    shm[2] = motion_vel(kp, t + dt);
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (verlet_one<MODE>(kp, n, i, shm[0], shm[1], shm[2], prev, s, ace, arho))
+    set_error(err, SPH_ERR_NONFINITE);
+}
+
 __global__ void k_advance_time(const double* __restrict__ dt, double* __restrict__ t) {
   if (threadIdx.x == 0) *t = *t + *dt;
 }
@@ -113,6 +133,24 @@ hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const doub
                          ace, arho, err);
   }
   if (phase == 1) hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_verlet(const KParams& kp, int64_t n, int mode, const double* dt, double* t,
+                          sph_state& prev, sph_state& s, const float* ace, const float* arho,
+                          void* ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n);
+  uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  if (n > 0) {
+    if (mode == 0)
+      hipLaunchKernelGGL(k_verlet<0>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, prev, s,
+                         ace, arho, err);
+    else
+      hipLaunchKernelGGL(k_verlet<1>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, prev, s,
+                         ace, arho, err);
+  }
+  hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
   return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ from . import sph as S
 
 
 class Simulation:
-    def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0):
+    def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0,
+                 integrator: str = "symplectic", verlet_ns: int = 40):
         cp = case.params
         if cell_div is not None and cell_div != cp.cell_div:
             raise ValueError("cell_div is fixed by the case's grid")
@@ -47,6 +48,14 @@ class Simulation:
         # sph_interact flags: 0 for the production pass, or a precision-study
         # arm (S.SPH_INTERACT_F64 / S.SPH_INTERACT_ABS_F32)
         self.flags = int(flags)
+        # "symplectic" (Eq. 33-34, two interactions per step) or "verlet"
+        # (Eq. 30, with the Eq. 31 step first and every verlet_ns steps)
+        if integrator not in ("symplectic", "verlet"):
+            raise ValueError(f"unknown integrator {integrator}")
+        if integrator == "verlet" and verlet_ns < 1:
+            raise ValueError("verlet_ns must be >= 1")
+        self.integrator = integrator
+        self.verlet_ns = int(verlet_ns)
 
     # ------------------------------------------------------------------ step
     @property
@@ -57,6 +66,8 @@ class Simulation:
         """One symplectic step.  With `timing` (a dict), HIP events are
         recorded on the stream around each call, appended to
         timing[name] as (start, end) pairs."""
+        if self.integrator == "verlet":
+            return self._step_verlet(stream, timing)
         P, n = self.params, self.n
         a, b = self.states
         s0, s1 = self.saved
@@ -93,13 +104,53 @@ class Simulation:
              self.arho, self.ws, stream=stream)
         self.steps_done += 1
 
+    def _step_verlet(self, stream, timing):
+        """One Verlet step: NL (carrying step n-1's velocity and density),
+        PI, dt, update; the result becomes the next step's input."""
+        P, n = self.params, self.n
+        a, b = self.states
+        s0, s1 = self.saved
+
+        def call(name, fn, *args, **kw):
+            if timing is None:
+                fn(*args, **kw)
+                return
+            st = stream if stream is not None else torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn(*args, **kw)
+            e1.record(st)
+            timing.setdefault(name, []).append((e0, e1))
+
+        mode = 1 if self.steps_done % self.verlet_ns == 0 else 0
+        call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
+             self.ws, carry_in=s0, carry_out=s1, stream=stream)
+        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
+             self.ws, flags=self.flags, stream=stream)
+        call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
+             interactions=self.interactions, stream=stream)
+        call("verlet", S.sph_verlet_step, P, n, mode, self.dt, self.t, s1, b, self.ace,
+             self.arho, self.ws, stream=stream)
+        self.states = [b, a]
+        self.saved = [s1, s0]
+        self.steps_done += 1
+
     def run(self, nsteps: int):
         for _ in range(int(nsteps)):
             self.step()
 
     # ----------------------------------------------------------- HIP graphs
     def capture(self, steps_per_graph: int = 1):
-        """Captures `steps_per_graph` steps in one HIP graph (warm up first)."""
+        """Captures `steps_per_graph` steps in one HIP graph (warm up first).
+        With Verlet the graph must start on an Eq. 31 step and span whole
+        periods of verlet_ns steps and an even number of steps (the state
+        buffers alternate every step)."""
+        if self.integrator == "verlet":
+            k = int(steps_per_graph)
+            if self.steps_done % self.verlet_ns or k % self.verlet_ns or k % 2:
+                raise ValueError("a Verlet graph must start at a multiple of verlet_ns and "
+                                 "span an even multiple of it")
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):

@@ -25,7 +25,7 @@ SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
-           "sph_symplectic_step", "sph_read_error", "sph_clear_error", "sph_strerror",
+           "sph_symplectic_step", "sph_verlet_step", "sph_read_error", "sph_clear_error", "sph_strerror",
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
            "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
@@ -81,6 +81,9 @@ def _load() -> C.CDLL:
     L.sph_symplectic_step.restype = C.c_int32
     L.sph_symplectic_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP,
                                       P(SphState), P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_verlet_step.restype = C.c_int32
+    L.sph_verlet_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP,
+                                  P(SphState), P(SphState), VP, VP, VP, C.c_size_t, VP]
     L.sph_read_error.restype = C.c_int32
     L.sph_read_error.argtypes = [VP]
     L.sph_clear_error.restype = C.c_int32
@@ -221,6 +224,14 @@ def sph_symplectic_step(params: SphParams, n: int, phase: int, dt: torch.Tensor,
     _check(lib.sph_symplectic_step(C.byref(params), int(n), int(phase), _ptr(dt), _ptr(t),
                                    C.byref(saved.c()), C.byref(s.c()), _ptr(ace), _ptr(arho),
                                    _ptr(ws), ws.numel(), _stream(stream)), "sph_symplectic_step")
+
+
+def sph_verlet_step(params: SphParams, n: int, mode: int, dt: torch.Tensor, t: torch.Tensor,
+                    prev: DeviceState, s: DeviceState, ace: torch.Tensor, arho: torch.Tensor,
+                    ws: torch.Tensor, stream=None):
+    _check(lib.sph_verlet_step(C.byref(params), int(n), int(mode), _ptr(dt), _ptr(t),
+                               C.byref(prev.c()), C.byref(s.c()), _ptr(ace), _ptr(arho),
+                               _ptr(ws), ws.numel(), _stream(stream)), "sph_verlet_step")
 
 
 def sph_read_error(ws: torch.Tensor) -> int:

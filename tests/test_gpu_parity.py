@@ -369,7 +369,7 @@ def test_one_symplectic_step(maker):
 
 
 def test_dam_break_2d_front_1000_steps():
-    """configs[0]-shaped run: 1000 symplectic steps; the front x_f =
+    """The small 2-D dam break (3,200 fluid particles), 1000 symplectic steps; the front x_f =
     max_{fluid} x stays within 1e-3 of the tank length of the oracle's."""
     _say("2d dam break 1000 steps")
     c = cases.dam_break_2d()
