@@ -46,7 +46,8 @@ class OrcParams(C.Structure):
         ("delta", C.c_double), ("eta2", C.c_double), ("cfl", C.c_double),
         ("mass_fluid", C.c_double), ("mass_bound", C.c_double),
         ("gravity", C.c_double * 3), ("motion_amp", C.c_double),
-        ("motion_omega", C.c_double),
+        ("motion_omega", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
+        ("visc_nu", C.c_double),
     ]
 
 
@@ -63,6 +64,9 @@ def lib():
         L.orc_wendland_w.argtypes = [C.c_double, C.c_double, C.c_int32]
         L.orc_wendland_fab.restype = C.c_double
         L.orc_wendland_fab.argtypes = [C.c_double, C.c_double, C.c_int32]
+        for name in ("orc_cubic_w", "orc_cubic_fab"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double, C.c_double, C.c_int32]
         L.orc_pressure.restype = C.c_double
         L.orc_pressure.argtypes = [P(OrcParams), C.c_double]
         L.orc_cell_keys.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p]
@@ -102,6 +106,9 @@ def params(cp) -> OrcParams:
         p.gravity[k] = float(cp.gravity[k])
     p.inv_cell_size = float(cp.inv_cell_size)
     p.x_sub = int(getattr(cp, "x_sub", 1))
+    p.kernel = int(getattr(cp, "kernel", 0))
+    p.viscosity = int(getattr(cp, "viscosity", 0))
+    p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
     for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
                  "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
         setattr(p, name, float(getattr(cp, name)))
@@ -122,6 +129,14 @@ def wendland_w(r, h, dim):
 
 def wendland_fab(r, h, dim):
     return float(lib().orc_wendland_fab(float(r), float(h), int(dim)))
+
+
+def cubic_w(r, h, dim):
+    return float(lib().orc_cubic_w(float(r), float(h), int(dim)))
+
+
+def cubic_fab(r, h, dim):
+    return float(lib().orc_cubic_fab(float(r), float(h), int(dim)))
 
 
 def pressure(cp, rho):

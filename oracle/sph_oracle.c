@@ -48,6 +48,51 @@ double orc_wendland_fab(double r, double h, int32_t dim) {
   return -5.0 * wendland_alpha(h, dim) * w * w * w / (h * h);
 }
 
+/* Normalisation alpha_D of the cubic spline, Eq. 10: 10/(7 pi h^2) in 2-D and
+ * 1/(pi h^3) in 3-D. */
+static double cubic_alpha(double h, int32_t dim) {
+  if (dim == 2) return 10.0 / (7.0 * M_PI * h * h);
+  return 1.0 / (M_PI * h * h * h);
+}
+
+/* Eq. 10: W = alpha_D (1 - 3/2 q^2 + 3/4 q^3) for q <= 1, alpha_D (2 - q)^3 / 4
+ * for 1 < q <= 2, 0 beyond. */
+double orc_cubic_w(double r, double h, int32_t dim) {
+  double q = r / h;
+  if (q < 0.0 || q > 2.0) return 0.0;
+  if (q <= 1.0) return cubic_alpha(h, dim) * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+  double u = 2.0 - q;
+  return cubic_alpha(h, dim) * 0.25 * u * u * u;
+}
+
+/* Gradient of Eq. 10 as grad_a W_ab = F_ab r_ab: dW/dq = alpha_D (-3q + 9/4 q^2)
+ * for q <= 1 and -3/4 alpha_D (2 - q)^2 beyond, times dq/dr / r = 1/(h r) =
+ * 1/(h^2 q): F_ab = alpha_D/h^2 (-3 + 9/4 q) and -3/4 alpha_D/h^2 (2-q)^2/q. */
+double orc_cubic_fab(double r, double h, int32_t dim) {
+  double q = r / h;
+  if (q < 0.0 || q >= 2.0) return 0.0;
+  double k = cubic_alpha(h, dim) / (h * h);
+  if (q <= 1.0) return k * (-3.0 + 2.25 * q);
+  double u = 2.0 - q;
+  return -0.75 * k * u * u / q;
+}
+
+static double kernel_fab(const orc_params* p, double r) {
+  return p->kernel == 1 ? orc_cubic_fab(r, p->h, p->dim) : orc_wendland_fab(r, p->h, p->dim);
+}
+
+/* Hydrostatic part of the density difference rho_b - rho_a for the DDT of
+ * Fourtakas et al., Eq. 19-20: the hydrostatic pressure difference
+ * P^H_ab = rho0 g z_ab (z_ab = z_a - z_b along the vertical, the last axis;
+ * g the magnitude of gravity along it) turned into a density difference by
+ * the inverse of Eq. 28, rho^H_ab = rho0 [(1 + P^H_ab / B)^(1/gamma) - 1]. */
+static double hydrostatic_drho(const orc_params* p, double z_ab) {
+  const double b = p->c0 * p->c0 * p->rho0 / p->gamma;
+  const double g = fabs(p->gravity[p->dim - 1]);
+  const double ph = p->rho0 * g * z_ab;
+  return p->rho0 * (pow(1.0 + ph / b, 1.0 / p->gamma) - 1.0);
+}
+
 /* Eq. 28: P = (c^2 rho0 / gamma) [(rho/rho0)^gamma - 1], with the constant
  * numerical speed of sound c = c0 (Section 2.4). */
 double orc_pressure(const orc_params* p, double rho) {
@@ -141,6 +186,12 @@ static double particle_mass(const orc_params* p, uint8_t t) {
  * term, so psi_ab . grad_a W_ab = 2 (rho_b - rho_a)(-F_ab) with F_ab < 0;
  * density diffusion acts between fluid particles only.
  *
+ * Options: kernel 1 takes the cubic spline of Eq. 10 for W; viscosity 1
+ * replaces Pi_ab by the laminar term of Eq. 23,
+ *   dv_a/dt += sum_b m_b 4 nu0 (r_ab . grad_a W_ab) / ((rho_a + rho_b)(r_ab^2 + eta^2)) v_ab,
+ * (visc_a and Eq. 35 unchanged); ddt 2 takes psi_ab of Eq. 19, i.e. rho_b -
+ * rho_a above becomes (rho_b - rho_a) - rho^H_ab (hydrostatic_drho).
+ *
  * nbr[a] counts the pairs evaluated for a: all neighbours of a fluid target,
  * the fluid neighbours of a wall target.  Outputs are indexed by target slot;
  * ace is [dim][ntarget].  Excluded particles take no part and get zeros. */
@@ -176,7 +227,7 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
         }
         if (!(r2 < support2)) continue;
         const double r = sqrt(r2);
-        const double fab = orc_wendland_fab(r, h, dim);
+        const double fab = kernel_fab(p, r);
         double vr = 0.0;
         for (int k = 0; k < dim; ++k) vr += (vel[k * n + a] - vel[k * n + b]) * dx[k];
         const double rho_b = rho[b];
@@ -188,12 +239,21 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
           const double p_b = orc_pressure(p, rho_b);
           const double mu = h * vr / (r2 + p->eta2);
           const double rhobar = 0.5 * (rho_a + rho_b);
-          const double pi_ab = vr < 0.0 ? -p->alpha * p->c0 * mu / rhobar : 0.0;
+          double pi_ab = 0.0;
+          if (p->viscosity == 0) {
+            pi_ab = vr < 0.0 ? -p->alpha * p->c0 * mu / rhobar : 0.0;
+          } else {
+            const double lam =
+                m_b * 4.0 * p->visc_nu * (fab * r2) / ((rho_a + rho_b) * (r2 + p->eta2));
+            for (int k = 0; k < dim; ++k) acc[k] += lam * (vel[k * n + a] - vel[k * n + b]);
+          }
           const double coef = m_b * ((p_a + p_b) / (rho_a * rho_b) + pi_ab);
           for (int k = 0; k < dim; ++k) acc[k] -= coef * fab * dx[k];
           if (fabs(mu) > vmax) vmax = fabs(mu);
           if (p->ddt && fb) {
-            const double psi_dot_grad = 2.0 * (rho_b - rho_a) * (-fab);
+            double drho = rho_b - rho_a;
+            if (p->ddt == 2) drho -= hydrostatic_drho(p, dx[dim - 1]);
+            const double psi_dot_grad = 2.0 * drho * (-fab);
             diff += psi_dot_grad * vol_b;
           }
         }

@@ -41,10 +41,15 @@ typedef struct orc_params {
   double mass_fluid, mass_bound;
   double gravity[3];
   double motion_amp, motion_omega;  /* moving walls: x += (A/w^2)(1 - cos wt) */
+  int32_t kernel;          /* 0: Wendland C2 (Eq. 11), 1: cubic spline (Eq. 10) */
+  int32_t viscosity;       /* 0: artificial (Eq. 21), 1: laminar (Eq. 23) */
+  double visc_nu;          /* kinematic viscosity of the laminar term */
 } orc_params;
 
 double orc_wendland_w(double r, double h, int32_t dim);
 double orc_wendland_fab(double r, double h, int32_t dim);
+double orc_cubic_w(double r, double h, int32_t dim);
+double orc_cubic_fab(double r, double h, int32_t dim);
 double orc_pressure(const orc_params* p, double rho);
 
 uint32_t orc_cell_key(const orc_params* p, const double* pos, int64_t n, int64_t i);

@@ -56,7 +56,10 @@ class CaseParams:
     mass_fluid: float = 0.0
     mass_bound: float = 0.0
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
-    ddt: int = 1
+    ddt: int = 1          # 0 none, 1 Molteni-Colagrossi (Eq. 18), 2 Fourtakas (Eq. 19-20)
+    kernel: int = 0       # 0 Wendland C2 (Eq. 11), 1 cubic spline (Eq. 10)
+    viscosity: int = 0    # 0 artificial (Eq. 21), 1 laminar (Eq. 23)
+    visc_nu: float = 1e-6  # kinematic viscosity of the laminar term (water)
     cell_div: int = 1
     x_sub: int = 1
     origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
