@@ -78,7 +78,9 @@ enum {
    * ABS_F32: distances from positions rounded to FP32 as absolute
    * coordinates, the rest FP32 (the scheme that cell-relative positions
    * replace).  Velocities and densities are the stored FP32 values in both;
-   * the outputs and the workspace partials are as in the production pass. */
+   * the outputs and the workspace partials are as in the production pass.
+   * The arms take the default formulation only (Wendland kernel, artificial
+   * viscosity, ddt 0 or 1); other options are rejected with SPH_E_ARG. */
   SPH_INTERACT_F64 = 2u,
   SPH_INTERACT_ABS_F32 = 4u
 };
@@ -89,7 +91,9 @@ typedef struct sph_params {
   int32_t dim;            /* 2 or 3 */
   int32_t cell_div;       /* 1: cells of size 2h, search +-1 cell (Section 5.1);
                              2: cells of size h, search +-2 cells (Section 5.3) */
-  int32_t ddt;            /* 0: no density diffusion; 1: Eq. 17 with Eq. 18 */
+  int32_t ddt;            /* density diffusion: 0 none; 1 Eq. 17 with Eq. 18
+                             (Molteni-Colagrossi); 2 Eq. 17 with Eq. 19-20
+                             (Fourtakas et al., hydrostatic part removed) */
   int32_t ncell[3];       /* key cells per axis; ncell[2] = 1 in 2-D.  Keys are
                              cx + ncell[0]*(cy + ncell[1]*cz) (x fastest); the
                              key of a particle outside the grid is the total
@@ -119,6 +123,11 @@ typedef struct sph_params {
   double motion_amp;      /* moving walls: x(t) = x0 + (A/w^2)(1 - cos wt),   */
   double motion_omega;    /*   A = motion_amp, w = motion_omega (0: no motion) */
   double dt_floor;        /* smallest acceptable dt (error bit below it) */
+  int32_t kernel;         /* 0: Wendland C2 (Eq. 11); 1: cubic spline (Eq. 10) */
+  int32_t viscosity;      /* 0: artificial viscosity (Eq. 21); 1: laminar
+                             viscosity (Eq. 23) with kinematic viscosity
+                             visc_nu, in place of Pi_ab (Eq. 35 unchanged) */
+  double visc_nu;         /* kinematic viscosity of the laminar term (>= 0) */
 } sph_params;
 
 /* Particle state (SoA device arrays of n particles). */
@@ -258,7 +267,9 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * with particle ranges offsets[0..n_slots] (offsets[0] = 0, non-decreasing)
  * to table_host and fills *batch except batch->table.  The caller copies the
  * table to device memory and sets batch->table before the calls below.  The
- * table stays valid while the slots keep their ranges. */
+ * table stays valid while the slots keep their ranges.  Every slot must use
+ * the same cell_div and the default formulation (kernel 0, viscosity 0, ddt
+ * 0 or 1); otherwise SPH_E_ARG. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
                               void* table_host, size_t table_bytes, sph_batch* batch);
 

@@ -39,11 +39,15 @@ KParams make_kparams(const sph_params& p) {
   k.motion_amp = p.motion_amp;
   k.motion_omega = p.motion_omega;
   k.support2 = (2.0 * p.h) * (2.0 * p.h);
-  // Wendland C2 (Eq. 11): alpha_D = 7/(4 pi h^2) in 2-D, 21/(16 pi h^3) in 3-D;
-  // grad_a W_ab = -5 alpha_D (1 - q/2)^3 / h^2 * r_ab.
-  const double alpha_d = p.dim == 2 ? 7.0 / (4.0 * M_PI * p.h * p.h)
-                                    : 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
-  const double kfab = -5.0 * alpha_d / (p.h * p.h);
+  // Kernel gradient grad_a W_ab = kfab g(q) r_ab.  Wendland C2 (Eq. 11):
+  // alpha_D = 7/(4 pi h^2) in 2-D, 21/(16 pi h^3) in 3-D, kfab = -5 alpha_D / h^2,
+  // g = (1 - q/2)^3.  Cubic spline (Eq. 10): alpha_D = 10/(7 pi h^2), 1/(pi h^3),
+  // kfab = alpha_D / h^2, g = -3 + 9q/4 (q <= 1), -3/4 (2 - q)^2 / q (q > 1).
+  const double alpha_d = p.kernel == 1
+      ? (p.dim == 2 ? 10.0 / (7.0 * M_PI * p.h * p.h) : 1.0 / (M_PI * p.h * p.h * p.h))
+      : (p.dim == 2 ? 7.0 / (4.0 * M_PI * p.h * p.h)
+                    : 21.0 / (16.0 * M_PI * p.h * p.h * p.h));
+  const double kfab = p.kernel == 1 ? alpha_d / (p.h * p.h) : -5.0 * alpha_d / (p.h * p.h);
   k.inv_frame = 1.0 / (kFrameCells * p.cell_size);
   k.kfab = kfab;
   k.alpha_c0 = p.alpha * p.c0;
@@ -57,6 +61,23 @@ KParams make_kparams(const sph_params& p) {
   k.kpi_mf_f = (float)(-2.0 * p.alpha * p.c0 * kfab * p.mass_fluid);
   k.kpi_mb_f = (float)(-2.0 * p.alpha * p.c0 * kfab * p.mass_bound);
   k.eta2_f = (float)p.eta2;
+  k.kernel = p.kernel;
+  k.viscosity = p.viscosity;
+  k.inv_h_f = (float)(1.0 / p.h);
+  k.klam_mf_f = (float)(4.0 * p.visc_nu * kfab * p.mass_fluid);
+  k.klam_mb_f = (float)(4.0 * p.visc_nu * kfab * p.mass_bound);
+  {
+    // Eq. 19-20: rho^H_ab = rho0 [(1 + eps)^(1/gamma) - 1], eps = rho0 g z_ab / B,
+    // as its series to eps^3 (|eps| < 0.01 within 2h of any case, so the
+    // remainder is below 1e-8 relative)
+    const double b = p.c0 * p.c0 * p.rho0 / p.gamma;
+    const double g = fabs(p.gravity[p.dim - 1]);
+    const double e = 1.0 / p.gamma;
+    k.fz_f = (float)(p.rho0 * g / b);
+    k.hc1_f = (float)(p.rho0 * e);
+    k.hc2_f = (float)(p.rho0 * e * (e - 1.0) / 2.0);
+    k.hc3_f = (float)(p.rho0 * e * (e - 1.0) * (e - 2.0) / 6.0);
+  }
   k.ddt_coef_f = p.ddt ? (float)(2.0 * p.delta * p.h * p.c0) : 0.f;
   k.cs_f = (float)p.cell_size;
   k.inv_csx_f = (float)(p.inv_cell_size * (double)p.x_sub);
@@ -95,6 +116,10 @@ static bool params_ok(const sph_params* p) {
   if (p->dim != 2 && p->dim != 3) return false;
   if (p->cell_div != 1 && p->cell_div != 2) return false;
   if (p->x_sub != 1 && p->x_sub != 2 && p->x_sub != 4 && p->x_sub != 8) return false;
+  if (p->ddt < 0 || p->ddt > 2) return false;
+  if (p->kernel != 0 && p->kernel != 1) return false;
+  if (p->viscosity != 0 && p->viscosity != 1) return false;
+  if (!(p->visc_nu >= 0) || !isfinite(p->visc_nu)) return false;
   for (int k = 0; k < 3; ++k)
     if (p->ncell[k] < 1) return false;
   if (p->dim == 2 && p->ncell[2] != 1) return false;
@@ -156,6 +181,10 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
   // one of: none, the FP64 diagnostic count, or one precision-study arm
   if (flags != 0 && flags != SPH_DIAG_COUNT_F64 && flags != SPH_INTERACT_F64 &&
       flags != SPH_INTERACT_ABS_F32)
+    return SPH_E_ARG;
+  // the precision-study arms implement the default formulation only
+  if ((flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) &&
+      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   const KParams kp = make_kparams(*p);
@@ -239,6 +268,9 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   for (int s = 0; s < n_slots; ++s) {
     const sph_params* p = &params[s];
     if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
+    // the batched interaction runs the default formulation (Wendland kernel,
+    // artificial viscosity, ddt 0 or 1)
+    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2) return SPH_E_ARG;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};
     e.kp = make_slot_kparams(*p);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
         const int cy = (int)(rest % (uint32_t)kp.ncy);
         const int cz = (int)(rest / (uint32_t)kp.ncy);
         uint32_t c64 = 0;
-        gather_walk<3, R, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
+        gather_walk<3, R, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
                                  acc, c64);
         write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
         cnt = acc.cnt;
@@ -234,14 +234,12 @@ hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
   const unsigned grid = grid_for(n);
-  if (B.cell_div == 1)
-    hipLaunchKernelGGL(k_batch_interact<1>, dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n,
-                       ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key,
-                       cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum));
-  else
-    hipLaunchKernelGGL(k_batch_interact<2>, dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n,
-                       ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key,
-                       cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum));
+#define SPH_BATCH_LAUNCH(RR)                                                                   \
+  hipLaunchKernelGGL((k_batch_interact<RR>), dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n, \
+                     ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key, \
+                     cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum))
+  if (B.cell_div == 1) SPH_BATCH_LAUNCH(1); else SPH_BATCH_LAUNCH(2);
+#undef SPH_BATCH_LAUNCH
   return hipGetLastError();
 }
 

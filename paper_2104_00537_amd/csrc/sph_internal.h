@@ -21,6 +21,7 @@ constexpr uint32_t kXcds = 8;      // accelerator complex dies of the MI355X
 struct KParams {
   int dim, cell_div, ddt, x_sub;   // x_sub: key cells per cell along x
   int lg_xsub, pad2;
+  int kernel, viscosity;           // 0 Wendland / 1 cubic spline; 0 artificial / 1 laminar
   int ncx, ncy, ncz;
   uint32_t ncell_total;          // also the key of particles outside the grid
   double ox, oy, oz;             // grid origin
@@ -36,6 +37,9 @@ struct KParams {
   float h_f, mhalf_inv_h_f, support2_f;      // h, -1/(2h), 4h^2
   float kfab_mf_f, kfab_mb_f;                // kfab m_fluid, kfab m_wall; kfab = -5 alpha_D / h^2
   float kpi_mf_f, kpi_mb_f;                  // -2 alpha c0 kfab m (Eq. 21 with Eq. 22)
+  float inv_h_f;                             // 1/h (cubic spline)
+  float klam_mf_f, klam_mb_f;                // 4 nu0 kfab m (Eq. 23)
+  float fz_f, hc1_f, hc2_f, hc3_f;           // Eq. 19-20: eps = fz z_ab, rho^H = eps(c1 + eps(c2 + eps c3))
   float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
   float cs_f, inv_csx_f, unit_x_f;           // cell size, inverse key-cell size along x, x offset unit
   float gx_f, gy_f, gz_f;

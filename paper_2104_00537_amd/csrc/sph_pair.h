@@ -21,42 +21,74 @@ struct TargetData {
   float vx, vy, vz;
 };
 
-// The pair terms of Eq. 11 (gradient), 15, 17-18, 21-22 and 36 for one pair
-// (a, b) with r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pbw is +rho_b for a
-// fluid particle and -rho_b for a wall; vb.w is P_b.  The caller has already
+// The pair terms of Eq. 15, 17-18, 21-22 and 36 for one pair (a, b) with
+// r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pbw is +rho_b for a fluid
+// particle and -rho_b for a wall; vb.w is P_b.  The caller has already
 // dropped wall-wall pairs (Eq. 36 sums over fluid neighbours only).
-//   F_ab = kfab (1 - q/2)^3, fv = V_b F_ab with V_b = m_b / rho_b;
+//   F_ab = kfab g(q): Wendland C2 (Eq. 11) g = (1 - q/2)^3, or cubic spline
+//     (Eq. 10) g = -3 + 9q/4 (q <= 1), -3/4 (2 - q)^2 / q (q > 1);
+//   fv = V_b F_ab with V_b = m_b / rho_b;
 //   continuity:  fv v_ab.r_ab;
 //   momentum:    -m_b [(P_a + P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
 //              = -[fv (P_a + P_b) / rho_a + m_b Pi_ab F_ab] r_ab,
 //   with Pi_ab = -2 alpha c0 mu_ab / (rho_a + rho_b) for approaching pairs
-//   (mu_ab = h v_ab.r_ab / (r^2 + eta^2) < 0) and 0 otherwise (Eq. 21);
-//   diffusion:   -(rho_b - rho_a) fv over fluid b.
-// EQM: fluid and wall particles have the same mass (no per-pair select).
-template <int DIM, bool EQM>
+//   (mu_ab = h v_ab.r_ab / (r^2 + eta^2) < 0) and 0 otherwise (Eq. 21); or,
+//   with laminar viscosity, no Pi_ab and + m_b 4 nu0 F_ab r^2 v_ab /
+//   ((rho_a + rho_b)(r^2 + eta^2)) (Eq. 23);
+//   diffusion:   -(rho_b - rho_a) fv over fluid b (Eq. 18), or with
+//   rho_b - rho_a less its hydrostatic part rho^H_ab (Eq. 19-20).
+// GEN: any formulation option (read from kp, uniform per slot); otherwise the
+// default one (Wendland C2, artificial viscosity, Eq. 18 or no diffusion),
+// whose code keeps the register budget of the production pass.  EQM: fluid
+// and wall particles have the same mass (no per-pair select).
+template <int DIM, bool EQM, bool GEN>
 __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
                                            float dy, float dz, float r2, float pbw,
                                            const float4& vb, PairAcc& acc) {
   const bool fb = pbw > 0.f;
   const float rhob = fabsf(pbw);
-  const float vr = (a.vx - vb.x) * dx + (a.vy - vb.y) * dy + (DIM == 3 ? (a.vz - vb.z) * dz : 0.f);
-  const float w = fmaf(__builtin_amdgcn_sqrtf(r2), kp.mhalf_inv_h_f, 1.f);  // 1 - q/2
-  const float w3 = w * w * w;
+  const float dvx = a.vx - vb.x, dvy = a.vy - vb.y, dvz = DIM == 3 ? a.vz - vb.z : 0.f;
+  const float vr = dvx * dx + dvy * dy + (DIM == 3 ? dvz * dz : 0.f);
+  const float s = __builtin_amdgcn_sqrtf(r2);
+  float g;
+  if (!GEN || kp.kernel == 0) {
+    const float w = fmaf(s, kp.mhalf_inv_h_f, 1.f);  // 1 - q/2
+    g = w * w * w;
+  } else {
+    const float q = s * kp.inv_h_f, u = 2.f - q;
+    g = q <= 1.f ? fmaf(2.25f, q, -3.f) : -0.75f * u * u * __builtin_amdgcn_rcpf(q);
+  }
   const float irhob = __builtin_amdgcn_rcpf(rhob);
   const float kmb = EQM ? kp.kfab_mf_f : (fb ? kp.kfab_mf_f : kp.kfab_mb_f);  // kfab m_b
-  const float fv = (w3 * irhob) * kmb;
+  const float fv = (g * irhob) * kmb;
   acc.cont = fmaf(fv, vr, acc.cont);
   acc.cnt += 1u;
   if (a.fluid) {
-    const float mu = kp.h_f * vr * __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
+    const float rr = __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
+    const float mu = kp.h_f * vr * rr;
     acc.vmax = fmaxf(acc.vmax, fabsf(mu));
-    const float kpi = EQM ? kp.kpi_mf_f : (fb ? kp.kpi_mf_f : kp.kpi_mb_f);  // -2 alpha c0 kfab m_b
-    const float piw = fminf(mu, 0.f) * __builtin_amdgcn_rcpf(a.rho + rhob) * (w3 * kpi);
-    const float coef = fmaf(fv * (a.p + vb.w), a.irho, piw);
-    acc.ax = fmaf(-coef, dx, acc.ax);
-    acc.ay = fmaf(-coef, dy, acc.ay);
-    if (DIM == 3) acc.az = fmaf(-coef, dz, acc.az);
-    const float drho = fb ? rhob - a.rho : 0.f;
+    const float irs = __builtin_amdgcn_rcpf(a.rho + rhob);
+    if (!GEN || kp.viscosity == 0) {
+      const float kpi = EQM ? kp.kpi_mf_f : (fb ? kp.kpi_mf_f : kp.kpi_mb_f);  // -2 alpha c0 kfab m_b
+      const float piw = fminf(mu, 0.f) * irs * (g * kpi);
+      const float coef = fmaf(fv * (a.p + vb.w), a.irho, piw);
+      acc.ax = fmaf(-coef, dx, acc.ax);
+      acc.ay = fmaf(-coef, dy, acc.ay);
+      if (DIM == 3) acc.az = fmaf(-coef, dz, acc.az);
+    } else {
+      const float klam = EQM ? kp.klam_mf_f : (fb ? kp.klam_mf_f : kp.klam_mb_f);  // 4 nu0 kfab m_b
+      const float coef = fv * (a.p + vb.w) * a.irho;
+      const float lam = (g * klam) * r2 * irs * rr;
+      acc.ax = fmaf(lam, dvx, fmaf(-coef, dx, acc.ax));
+      acc.ay = fmaf(lam, dvy, fmaf(-coef, dy, acc.ay));
+      if (DIM == 3) acc.az = fmaf(lam, dvz, fmaf(-coef, dz, acc.az));
+    }
+    float drho = rhob - a.rho;
+    if (GEN && kp.ddt == 2) {
+      const float e = kp.fz_f * (DIM == 3 ? dz : dy);  // vertical z_ab
+      drho -= e * fmaf(e, fmaf(e, kp.hc3_f, kp.hc2_f), kp.hc1_f);
+    }
+    drho = fb ? drho : 0.f;
     acc.diff = fmaf(-drho, fv, acc.diff);
   }
 }
@@ -145,7 +177,7 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
 // period, which exceeds twice the reach of the stencil.  Along y and z the
 // offsets are cell-relative and (ys, zs) carry the row's cell shift.  Wall
 // targets skip wall candidates (Eq. 36).
-template <int DIM, bool DIAG, bool EQM, bool TAIL>
+template <int DIM, bool DIAG, bool EQM, bool GEN, bool TAIL>
 __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64_t i,
                                              uint32_t xa, float ys, float zs,
                                              const TargetData& T, uint32_t j, uint32_t j1,
@@ -187,7 +219,8 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
     if (hit[u]) vb[u] = qv[u];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
-    if (hit[u]) pair_terms<DIM, EQM>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u].w, vb[u], acc);
+    if (hit[u])
+      pair_terms<DIM, EQM, GEN>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u].w, vb[u], acc);
 }
 
 // The candidate walk of one target lane over the rows of its neighbour cells
@@ -207,7 +240,7 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 // taken off the count here (fluid targets meet themselves; wall targets skip
 // wall candidates).  DIAG also counts neighbours with an FP64 test on the
 // FP64 positions (c64, self excluded).
-template <int DIM, int R, bool DIAG, bool EQM>
+template <int DIM, int R, bool DIAG, bool EQM, bool GEN>
 __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
                                             int64_t i, const float4& pa, const TargetData& T,
                                             int cx, int cy, int cz,
@@ -256,11 +289,11 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
       const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
       uint32_t j = j0;
       for (; j + 4 <= j1; j += 4)
-        gather_group<DIM, DIAG, EQM, false>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64, pos64,
-                                            acc, c64);
+        gather_group<DIM, DIAG, EQM, GEN, false>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64,
+                                                 pos64, acc, c64);
       if (j < j1)
-        gather_group<DIM, DIAG, EQM, true>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64, pos64,
-                                           acc, c64);
+        gather_group<DIM, DIAG, EQM, GEN, true>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64,
+                                                pos64, acc, c64);
     }
   }
   // the self pair (fluid targets only) was counted and added nothing

@@ -43,7 +43,8 @@ class SphParams(C.Structure):
         ("eta2", C.c_double), ("cfl", C.c_double), ("mass_fluid", C.c_double),
         ("mass_bound", C.c_double), ("gravity", C.c_double * 3),
         ("motion_amp", C.c_double), ("motion_omega", C.c_double),
-        ("dt_floor", C.c_double),
+        ("dt_floor", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
+        ("visc_nu", C.c_double),
     ]
 
 
@@ -138,6 +139,9 @@ def make_params(cp) -> SphParams:
     p = SphParams()
     p.dim, p.cell_div, p.ddt = int(cp.dim), int(cp.cell_div), int(cp.ddt)
     p.x_sub = int(getattr(cp, "x_sub", 1))
+    p.kernel = int(getattr(cp, "kernel", 0))
+    p.viscosity = int(getattr(cp, "viscosity", 0))
+    p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
     for k in range(3):
         p.ncell[k] = int(cp.ncell[k])
         p.origin[k] = float(cp.origin[k])

@@ -168,3 +168,15 @@ def test_batch_calls_validate_without_device(S):
     b.n_total = 100
     assert lib.sph_batch_symplectic_step(C.byref(b), 3, d, d, C.byref(st), C.byref(st), d, d, d,
                                          1 << 30, None) == S.SPH_E_ARG
+
+
+def test_batch_rejects_formulation_options(S):
+    """The batched path runs the default formulation only."""
+    import dataclasses
+    from paper_2104_00537_amd import cases
+    base = cases.dam_break_2d(dp=0.05).params
+    for kw in (dict(kernel=1), dict(viscosity=1), dict(ddt=2)):
+        ps = [S.make_params(base), S.make_params(dataclasses.replace(base, **kw))]
+        with pytest.raises(S.SphError):
+            S.sph_batch_describe(ps, [0, 10, 20])
+
