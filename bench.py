@@ -140,6 +140,47 @@ def verlet_leg(case, steps, warmup):
             "interactions_per_s": pairs / el, "ns": 40}
 
 
+VARIANTS = {"default": {}, "cubic_spline": dict(kernel=1),
+            "laminar_viscosity": dict(viscosity=1, visc_nu=1e-6), "fourtakas_ddt": dict(ddt=2),
+            "all_three": dict(kernel=1, viscosity=1, visc_nu=1e-6, ddt=2)}
+
+
+def variants_leg(case, launches=10):
+    """One interaction pass per formulation option on the binned initial
+    state: ms per pass and interactions/s (HIP events on the launch stream)."""
+    import dataclasses
+    import torch
+    from paper_2104_00537_amd import sph as S
+    n, dim = case.n, case.params.dim
+    P0 = S.make_params(case.params)
+    src = S.DeviceState.from_case(case, "cuda:0")
+    dst = S.DeviceState.empty(dim, n, "cuda:0")
+    key = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    perm = torch.empty_like(key)
+    start = torch.empty(case.params.ncell_total() + 1, dtype=torch.int32, device="cuda:0")
+    ws = torch.zeros(S.sph_workspace_bytes(P0, n), dtype=torch.uint8, device="cuda:0")
+    ace = torch.empty((dim, n), dtype=torch.float32, device="cuda:0")
+    arho = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    S.sph_bin_cells(P0, n, src, dst, key, perm, start, ws)
+    out = {}
+    for name, kw in VARIANTS.items():
+        P = S.make_params(dataclasses.replace(case.params, **kw))
+        inter = torch.zeros(2, dtype=torch.int64, device="cuda:0")
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        S.sph_interact(P, n, dst, key, start, ace, arho, ws)  # warm-up
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            S.sph_interact(P, n, dst, key, start, ace, arho, ws)
+        e1.record()
+        S.sph_reduce_dt(P, n, dt, ws, interactions=inter)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / launches
+        out[name] = {"ms_per_pass": ms, "interactions_per_s": int(inter[0].item()) / (ms * 1e-3)}
+    return out
+
+
 def serving(args):
     """The request stream through the batched engine and the plain
     one-case-at-a-time path (same seeded trace, same GPU)."""
@@ -232,6 +273,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -317,6 +359,8 @@ def main():
           flush=True)
     if not args.no_verlet:
         res["verlet"] = verlet_leg(case, args.steps, args.warmup)
+    if not args.no_variants:
+        res["variants"] = variants_leg(case)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:
