@@ -47,7 +47,7 @@ class OrcParams(C.Structure):
         ("mass_fluid", C.c_double), ("mass_bound", C.c_double),
         ("gravity", C.c_double * 3), ("motion_amp", C.c_double),
         ("motion_omega", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
-        ("visc_nu", C.c_double),
+        ("visc_nu", C.c_double), ("boundary", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
@@ -85,12 +85,13 @@ def lib():
                                  C.c_int32] + [C.c_void_p] * 8
         L.orc_run_verlet.restype = C.c_int32
         L.orc_run_verlet.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      P(C.c_double), C.c_void_p, P(C.c_uint64)]
         L.orc_run.restype = C.c_int32
         L.orc_run.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
-                              C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double),
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double),
                               C.c_void_p, P(C.c_uint64)]
+        L.orc_mdbc.argtypes = [P(OrcParams), C.c_int64] + [C.c_void_p] * 7
         _lib = L
     return _lib
 
@@ -109,6 +110,7 @@ def params(cp) -> OrcParams:
     p.kernel = int(getattr(cp, "kernel", 0))
     p.viscosity = int(getattr(cp, "viscosity", 0))
     p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
+    p.boundary = int(getattr(cp, "boundary", 0))
     for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
                  "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
         setattr(p, name, float(getattr(cp, name)))
@@ -222,17 +224,28 @@ def corrector(cp, dt, t, half, saved, ptype, ace, arho):
     return pos, vel, rho
 
 
-def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0):
+def _normal_arg(cp, normal, n):
+    if int(getattr(cp, "boundary", 0)) == 1:
+        if normal is None:
+            raise ValueError("modified DBC needs the wall particles' ghost vectors")
+        return _f64(normal).reshape(int(cp.dim), n)
+    return None
+
+
+def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0, normal=None):
     """nsteps full symplectic steps.  Returns dict with pos, vel, rho, type,
-    t, dt history, interaction count and status."""
+    t, dt history, interaction count and status.  normal: ghost vectors of
+    the wall particles (needed with modified DBC)."""
     pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
     ptype = np.ascontiguousarray(ptype, dtype=np.uint8).copy()
     t = C.c_double(float(t0))
     dts = np.zeros(max(int(nsteps), 1), np.float64)
     inter = C.c_uint64(0)
     p = params(cp)
+    nrm = _normal_arg(cp, normal, rho.shape[0])
     st = lib().orc_run(C.byref(p), rho.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
-                       _ptr(ptype), int(nsteps), C.byref(t), _ptr(dts), C.byref(inter))
+                       _ptr(ptype), _ptr(nrm) if nrm is not None else None, int(nsteps),
+                       C.byref(t), _ptr(dts), C.byref(inter))
     return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
                 dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
 
@@ -251,7 +264,7 @@ def verlet(cp, dt, t, mode, pos, vel, rho, vel_prev, rho_prev, ptype, ace, arho)
     return (pos, vel, rho), (vp, rp)
 
 
-def run_verlet(cp, pos, vel, rho, ptype, nsteps, ns=40, t0=0.0):
+def run_verlet(cp, pos, vel, rho, ptype, nsteps, ns=40, t0=0.0, normal=None):
     """nsteps Verlet steps (Eq. 31 on the first step and every ns-th).
     Returns the same dict as run()."""
     pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
@@ -260,9 +273,24 @@ def run_verlet(cp, pos, vel, rho, ptype, nsteps, ns=40, t0=0.0):
     dts = np.zeros(max(int(nsteps), 1), np.float64)
     inter = C.c_uint64(0)
     p = params(cp)
+    nrm = _normal_arg(cp, normal, rho.shape[0])
     st = lib().orc_run_verlet(C.byref(p), rho.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
-                              _ptr(ptype), int(nsteps), int(ns), C.byref(t), _ptr(dts),
-                              C.byref(inter))
+                              _ptr(ptype), _ptr(nrm) if nrm is not None else None, int(nsteps),
+                              int(ns), C.byref(t), _ptr(dts), C.byref(inter))
     return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
                 dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
+
+
+def mdbc(cp, pos, vel, rho, ptype, normal):
+    """Modified DBC (Section 2.6.2, Eq. 38-39): returns (rho, vel) with the
+    wall particles' density and velocity from their ghost nodes."""
+    pos, vel, rho = _f64(pos), _f64(vel), _f64(rho)
+    n = rho.shape[0]
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    normal = _f64(normal).reshape(int(cp.dim), n)
+    ro, vo = np.zeros_like(rho), np.zeros_like(vel)
+    p = params(cp)
+    lib().orc_mdbc(C.byref(p), n, _ptr(pos), _ptr(vel), _ptr(rho), _ptr(ptype), _ptr(normal),
+                   _ptr(ro), _ptr(vo))
+    return ro, vo
 

@@ -77,6 +77,10 @@ double orc_cubic_fab(double r, double h, int32_t dim) {
   return -0.75 * k * u * u / q;
 }
 
+static double kernel_w(const orc_params* p, double r) {
+  return p->kernel == 1 ? orc_cubic_w(r, p->h, p->dim) : orc_wendland_w(r, p->h, p->dim);
+}
+
 static double kernel_fab(const orc_params* p, double r) {
   return p->kernel == 1 ? orc_cubic_fab(r, p->h, p->dim) : orc_wendland_fab(r, p->h, p->dim);
 }
@@ -210,7 +214,9 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
     double cont = 0.0, diff = 0.0, vmax = 0.0;
     uint32_t count = 0;
     const uint8_t ta = type[a];
-    if (!is_excluded(ta)) {
+    /* with modified DBC the wall density comes from orc_mdbc (Eq. 38), not
+     * from Eq. 36: wall targets get no sums */
+    if (!is_excluded(ta) && (is_fluid(ta) || p->boundary == 0)) {
       const int fa = is_fluid(ta);
       const double rho_a = rho[a];
       const double p_a = orc_pressure(p, rho_a);
@@ -371,6 +377,110 @@ void orc_corrector(const orc_params* p, int64_t n, double dt, double t,
   }
 }
 
+/* Modified dynamic boundary condition, Section 2.6.2.  For every wall
+ * particle B its ghost node G = r_B + normal_B (the mirror image of B across
+ * the wall face, inside the fluid) collects the fluid particles b with
+ * |r_b - r_G| < 2h.  With r = r_b - r_G, w = W(|r|), grad W = F r (the kernel
+ * of the case) and V_b = m_b / rho_b, the first-order corrected SPH
+ * approximation (Liu and Liu) of a field f at G solves
+ *   [ sum V w      sum V w r^T    ] [ f_G      ]   [ sum V f_b w   ]
+ *   [ sum V F r    sum V F r r^T  ] [ grad f_G ] = [ sum V f_b F r ]
+ * which every linear f satisfies exactly (Taylor expansion about G); for
+ * the density V_b rho_b = m_b.  Then rho_B = rho_G + (r_B - r_G).grad rho_G
+ * (Eq. 38).  When |det| of the matrix (dimensionless: about 1 for a full
+ * support) is below 1e-3, the zeroth-order Shepard value sum m w / sum V w
+ * is used with no gradient.  The ghost velocity is the Shepard sum of
+ * Eq. 39, v_G = sum V v_b w / sum V w, and the wall particle takes it
+ * reversed about its own velocity, v_B = 2 v_wall - v_G (no slip; v_B = -v_G
+ * for a fixed wall).  A wall particle with no fluid around its ghost node
+ * gets rho0 and its own velocity.  Fluid and excluded particles are copied
+ * unchanged.  rho_out [n], vel_out [dim][n]. */
+static int solve_small(int m, double* A, double* b, double* det) {
+  /* Gaussian elimination with partial pivoting on the m x m row-major A */
+  double d = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (fabs(A[r * m + c]) > fabs(A[piv * m + c])) piv = r;
+    if (A[piv * m + c] == 0.0) { *det = 0.0; return 0; }
+    if (piv != c) {
+      for (int k = 0; k < m; ++k) {
+        double t = A[c * m + k]; A[c * m + k] = A[piv * m + k]; A[piv * m + k] = t;
+      }
+      double t = b[c]; b[c] = b[piv]; b[piv] = t;
+      d = -d;
+    }
+    d *= A[c * m + c];
+    for (int r = c + 1; r < m; ++r) {
+      const double f = A[r * m + c] / A[c * m + c];
+      for (int k = c; k < m; ++k) A[r * m + k] -= f * A[c * m + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = m - 1; c >= 0; --c) {
+    double s = b[c];
+    for (int k = c + 1; k < m; ++k) s -= A[c * m + k] * b[k];
+    b[c] = s / A[c * m + c];
+  }
+  *det = d;
+  return 1;
+}
+
+void orc_mdbc(const orc_params* p, int64_t n, const double* pos, const double* vel,
+              const double* rho, const uint8_t* type, const double* normal,
+              double* rho_out, double* vel_out) {
+  const int dim = p->dim;
+  const int m = dim + 1;
+  const double support2 = (2.0 * p->h) * (2.0 * p->h);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n; ++a) {
+    rho_out[a] = rho[a];
+    for (int k = 0; k < dim; ++k) vel_out[k * n + a] = vel[k * n + a];
+    if (is_excluded(type[a]) || is_fluid(type[a])) continue;
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) g[k] = pos[k * n + a] + normal[k * n + a];
+    double A[16], B[4], s0 = 0.0, sv[3] = {0.0, 0.0, 0.0};
+    memset(A, 0, sizeof(A));
+    memset(B, 0, sizeof(B));
+    for (int64_t b = 0; b < n; ++b) {
+      if (is_excluded(type[b]) || !is_fluid(type[b])) continue;
+      double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        r[k] = pos[k * n + b] - g[k];
+        r2 += r[k] * r[k];
+      }
+      if (!(r2 < support2)) continue;
+      const double d = sqrt(r2);
+      const double w = kernel_w(p, d), f = kernel_fab(p, d);
+      const double mb = particle_mass(p, type[b]);
+      const double vb = mb / rho[b];
+      double row0[4] = {1.0, r[0], r[1], r[2]};
+      for (int k = 0; k < m; ++k) A[0 * m + k] += vb * w * row0[k];
+      for (int i = 0; i < dim; ++i)
+        for (int k = 0; k < m; ++k) A[(1 + i) * m + k] += vb * f * r[i] * row0[k];
+      B[0] += mb * w;
+      for (int i = 0; i < dim; ++i) B[1 + i] += mb * f * r[i];
+      s0 += vb * w;
+      for (int k = 0; k < dim; ++k) sv[k] += vb * w * vel[k * n + b];
+    }
+    if (!(s0 > 0.0)) {
+      rho_out[a] = p->rho0;
+      continue;
+    }
+    double det = 0.0;
+    double x[4] = {B[0], B[1], B[2], B[3]};
+    double rho_b;
+    if (solve_small(m, A, x, &det) && fabs(det) >= 1e-3) {
+      rho_b = x[0];
+      for (int k = 0; k < dim; ++k) rho_b += (pos[k * n + a] - g[k]) * x[1 + k];
+    } else {
+      rho_b = B[0] / s0;
+    }
+    rho_out[a] = rho_b;
+    for (int k = 0; k < dim; ++k) vel_out[k * n + a] = 2.0 * vel[k * n + a] - sv[k] / s0;
+  }
+}
+
 /* Verlet step, Section 2.5.1, from state n (pos, vel, rho) with the state of
  * step n-1 (vel_p, rho_p) and the rates F^n (ace), R^n (arho):
  *   mode 0 (Eq. 30): v^{n+1} = v^{n-1} + 2 dt F^n, rho^{n+1} = rho^{n-1} + 2 dt R^n;
@@ -422,8 +532,24 @@ static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
  * *interactions accumulates the pair count of every PI (nullable).
  * Returns 0; 1 if a density became non-finite or non-positive; 2 if dt is
  * not a positive finite number (e.g. no fluid particle is left). */
+/* With modified DBC (boundary 1, normal required) each PI is preceded by
+ * orc_mdbc: the wall densities it gives replace the state's, and the
+ * interaction sees its wall velocities. */
+static void mdbc_before_pi(const orc_params* p, int64_t n, const double* pos,
+                           const double* vel, double* rho, const uint8_t* type,
+                           const double* normal, double* vel_pi) {
+  if (p->boundary == 1) {
+    double* rho_new = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    orc_mdbc(p, n, pos, vel, rho, type, normal, rho_new, vel_pi);
+    memcpy(rho, rho_new, sizeof(double) * (size_t)n);
+    free(rho_new);
+  } else {
+    memcpy(vel_pi, vel, sizeof(double) * (size_t)p->dim * (size_t)n);
+  }
+}
+
 int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
-                double* rho, uint8_t* type, int32_t nsteps, double* t,
+                double* rho, uint8_t* type, const double* normal, int32_t nsteps, double* t,
                 double* dt_hist, uint64_t* interactions) {
   const int dim = p->dim;
   size_t nd = (size_t)dim * (size_t)(n > 0 ? n : 1);
@@ -434,10 +560,12 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
   double* pos_n = (double*)calloc(nd, sizeof(double));
   double* vel_n = (double*)calloc(nd, sizeof(double));
   double* rho_n = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* vel_pi = (double*)calloc(nd, sizeof(double));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
     mark_excluded(p, n, pos, type);
-    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
+    orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
     uint64_t count = 0;
     for (int64_t a = 0; a < n; ++a) count += nbr[a];
     const double dt = orc_time_step(p, n, type, ace, visc);
@@ -445,7 +573,8 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
     if (!(dt > 0.0) || !isfinite(dt)) { status = 2; break; }
     orc_predictor(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
     mark_excluded(p, n, pos, type);
-    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
+    orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
     for (int64_t a = 0; a < n; ++a) count += nbr[a];
     orc_corrector(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
     *t += dt;
@@ -454,7 +583,7 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
       if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
   }
   free(ace); free(arho); free(visc); free(nbr);
-  free(pos_n); free(vel_n); free(rho_n);
+  free(pos_n); free(vel_n); free(rho_n); free(vel_pi);
   return status;
 }
 
@@ -462,8 +591,8 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
  * update of Eq. 30, or of Eq. 31 on the first step and on every step whose
  * index is a multiple of ns -> t += dt.  Same outputs and status as orc_run. */
 int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
-                       double* rho, uint8_t* type, int32_t nsteps, int32_t ns, double* t,
-                       double* dt_hist, uint64_t* interactions) {
+                       double* rho, uint8_t* type, const double* normal, int32_t nsteps,
+                       int32_t ns, double* t, double* dt_hist, uint64_t* interactions) {
   const int dim = p->dim;
   size_t nd = (size_t)dim * (size_t)(n > 0 ? n : 1);
   double* ace = (double*)calloc(nd, sizeof(double));
@@ -472,10 +601,12 @@ int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
   uint32_t* nbr = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
   double* vel_p = (double*)calloc(nd, sizeof(double));
   double* rho_p = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* vel_pi = (double*)calloc(nd, sizeof(double));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
     mark_excluded(p, n, pos, type);
-    orc_interact(p, n, pos, vel, rho, type, n, NULL, ace, arho, visc, nbr);
+    mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
+    orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
     uint64_t count = 0;
     for (int64_t a = 0; a < n; ++a) count += nbr[a];
     const double dt = orc_time_step(p, n, type, ace, visc);
@@ -489,6 +620,6 @@ int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
       if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
   }
   free(ace); free(arho); free(visc); free(nbr);
-  free(vel_p); free(rho_p);
+  free(vel_p); free(rho_p); free(vel_pi);
   return status;
 }

@@ -44,6 +44,8 @@ typedef struct orc_params {
   int32_t kernel;          /* 0: Wendland C2 (Eq. 11), 1: cubic spline (Eq. 10) */
   int32_t viscosity;       /* 0: artificial (Eq. 21), 1: laminar (Eq. 23) */
   double visc_nu;          /* kinematic viscosity of the laminar term */
+  int32_t boundary;        /* 0: DBC (Eq. 36); 1: modified DBC (Eq. 38-39) */
+  int32_t pad2;
 } orc_params;
 
 double orc_wendland_w(double r, double h, int32_t dim);
@@ -73,15 +75,18 @@ void orc_corrector(const orc_params* p, int64_t n, double dt, double t,
                    const double* ace, const double* arho, const double* pos_n,
                    const double* vel_n, const double* rho_n);
 int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
-                double* rho, uint8_t* type, int32_t nsteps, double* t,
+                double* rho, uint8_t* type, const double* normal, int32_t nsteps, double* t,
                 double* dt_hist, uint64_t* interactions);
 
 void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mode,
                 double* pos, double* vel, double* rho, double* vel_p, double* rho_p,
                 const uint8_t* type, const double* ace, const double* arho);
+void orc_mdbc(const orc_params* p, int64_t n, const double* pos, const double* vel,
+              const double* rho, const uint8_t* type, const double* normal,
+              double* rho_out, double* vel_out);
 int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
-                       double* rho, uint8_t* type, int32_t nsteps, int32_t ns, double* t,
-                       double* dt_hist, uint64_t* interactions);
+                       double* rho, uint8_t* type, const double* normal, int32_t nsteps,
+                       int32_t ns, double* t, double* dt_hist, uint64_t* interactions);
 
 #ifdef __cplusplus
 }

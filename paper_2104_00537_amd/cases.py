@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, asdict
-from typing import Tuple
+from typing import Optional, Tuple
 
 import numpy as np
 
@@ -58,6 +58,7 @@ class CaseParams:
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     ddt: int = 1          # 0 none, 1 Molteni-Colagrossi (Eq. 18), 2 Fourtakas (Eq. 19-20)
     kernel: int = 0       # 0 Wendland C2 (Eq. 11), 1 cubic spline (Eq. 10)
+    boundary: int = 0     # 0 DBC (Eq. 36), 1 modified DBC (Eq. 38-39)
     viscosity: int = 0    # 0 artificial (Eq. 21), 1 laminar (Eq. 23)
     visc_nu: float = 1e-6  # kinematic viscosity of the laminar term (water)
     cell_div: int = 1
@@ -86,6 +87,10 @@ class Case:
     rho: np.ndarray   # (n,) float32
     type: np.ndarray  # (n,) uint8
     meta: dict = field(default_factory=dict)
+    # (dim, n) float32: for wall particles the vector from the particle to its
+    # ghost node (its mirror image across the wall face, Section 2.6.2);
+    # zero for fluid particles
+    normal: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -131,9 +136,20 @@ def _walls(dim, nx_tank, ny_tank, nz_tank, closed_top):
     return np.concatenate(parts, axis=1)
 
 
+def _ghost_vectors(idx, tank, dp):
+    """Per wall particle (lattice indices idx, tank interior [0, tank[k]) in
+    cells of dp per axis), the vector to its mirror image across the wall
+    faces it lies outside of: 2 (face - centre) along each such axis."""
+    out = np.zeros(idx.shape, np.float64)
+    for k, nk in enumerate(tank):
+        c = idx[k].astype(np.float64) + 0.5
+        out[k] = np.where(idx[k] < 0, -2.0 * c, np.where(idx[k] >= nk, 2.0 * (nk - c), 0.0))
+    return (out * dp).astype(np.float32)
+
+
 def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
             cell_div=1, x_sub=1, wall_type=BOUND_FIXED, motion_amp=0.0,
-            motion_omega=0.0, h_factor=1.0, meta=None) -> Case:
+            motion_omega=0.0, h_factor=1.0, meta=None, tank=None) -> Case:
     rng = np.random.default_rng(seed)
     idx = np.concatenate([fluid_idx, wall_idx], axis=1)
     n = idx.shape[1]
@@ -168,7 +184,10 @@ def _finish(name, dim, dp, fluid_idx, wall_idx, fluid_height, lo, hi, seed,
         cell_div=cell_div, x_sub=x_sub, origin=tuple(origin), cell_size=cs,
         inv_cell_size=1.0 / cs, ncell=tuple(ncell), motion_amp=motion_amp,
         motion_omega=motion_omega, fluid_height=fluid_height)
-    return Case(params=params, pos=np.ascontiguousarray(pos),
+    normal = np.zeros((dim, n), np.float32)
+    if tank is not None and wall_idx.shape[1]:
+        normal[:, fluid_idx.shape[1]:] = _ghost_vectors(wall_idx, tank, dp)
+    return Case(params=params, pos=np.ascontiguousarray(pos), normal=normal,
                 vel=np.zeros((dim, n), np.float32),
                 rho=rho.astype(np.float32), type=ptype, meta=dict(meta or {}))
 
@@ -186,7 +205,8 @@ def dam_break_2d(dp=0.01, tank=(1.6, 1.0), column=(0.4, 0.8), seed=0,
     lo = (-2.0 * dp - 1e-3 * dp, -2.0 * dp - 1e-3 * dp)
     hi = (nxt * dp + 2.0 * dp, max(nzt * dp, 2.5 * nzf * dp) + 2.0 * dp)
     return _finish("dam_break_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
-                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, column=column))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, column=column),
+                   tank=(nxt, nzt))
 
 
 def dam_break_3d(dp=0.6 / 126, tank=(1.6, 0.6, 0.6), block=(0.6, 0.6, 0.3),
@@ -200,7 +220,8 @@ def dam_break_3d(dp=0.6 / 126, tank=(1.6, 0.6, 0.6), block=(0.6, 0.6, 0.3),
     lo = (-m, -m, -m)
     hi = (nxt * dp + m, nyt * dp + m, max(nzt * dp, 2.5 * nzf * dp) + m)
     return _finish("dam_break_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
-                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, block=block))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, block=block),
+                   tank=(nxt, nyt, nzt))
 
 
 def sloshing_3d(dp=0.0025, tank=(2.0, 1.0, 1.0), fill=0.5, seed=0,
@@ -219,7 +240,7 @@ def sloshing_3d(dp=0.0025, tank=(2.0, 1.0, 1.0), fill=0.5, seed=0,
     return _finish("sloshing_3d", 3, dp, fluid, walls, nzf * dp, lo, hi, seed,
                    cell_div=cell_div, x_sub=x_sub, wall_type=BOUND_MOVING,
                    motion_amp=accel, motion_omega=omega,
-                   meta=dict(tank=tank, fill=fill))
+                   meta=dict(tank=tank, fill=fill), tank=(nxt, nyt, nzt))
 
 
 def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
@@ -242,7 +263,8 @@ def block_case(dim, shape, dp=0.01, seed=0, walls=False, cell_div=1,
     lo = tuple(-m for _ in range(dim))
     hi = tuple(s * dp + m for s in shape)
     case = _finish(f"block{dim}d", dim, dp, fluid, wall, height, lo, hi, seed,
-                   cell_div=cell_div, x_sub=x_sub, meta=dict(shape=shape, walls=walls))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(shape=shape, walls=walls),
+                   tank=tuple(shape))
     rng = np.random.default_rng(seed + 7919)
     if vel_scale:
         case.vel[:] = rng.uniform(-vel_scale, vel_scale, case.vel.shape).astype(np.float32)
@@ -304,4 +326,5 @@ def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
     hi = (nxt * dp + m + travel, nzt * dp + m)
     return _finish("sloshing_2d", 2, dp, fluid, walls, nzf * dp, lo, hi, seed,
                    wall_type=BOUND_MOVING, motion_amp=accel, motion_omega=omega,
-                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, fill=fill))
+                   cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, fill=fill),
+                   tank=(nxt, nzt))
