@@ -13,6 +13,8 @@
  *                        per-particle maxima that set the time step.
  *   sph_reduce_dt        SU: the variable time step of Eq. 35, kept on the GPU.
  *   sph_verlet_step      SU: the Verlet scheme (Eq. 30-31), one PI per step.
+ *   sph_mdbc             wall densities and velocities of the modified
+ *                        dynamic boundary condition (Eq. 38-39), before a PI.
  *   sph_symplectic_step  SU: symplectic predictor / corrector (Eq. 33-34), with
  *                        imposed motion of moving walls (Eq. 37).
  *
@@ -102,7 +104,10 @@ typedef struct sph_params {
                              of cs/x_sub along x, cs along y and z); finer x
                              cells let the interaction cut each row of
                              neighbour cells closer to the support sphere */
-  int32_t reserved;       /* 0 */
+  int32_t boundary;       /* 0: dynamic boundary condition, walls evolve their
+                             density by Eq. 36; 1: modified DBC (Eq. 38-39,
+                             sph_mdbc before every sph_interact; the state
+                             then needs the wall ghost vectors, `normal`) */
   double origin[3];       /* grid origin (components beyond dim ignored) */
   double cell_size;       /* cs = 2h / cell_div */
   double inv_cell_size;   /* 1/cs, computed once by the caller; the cell index
@@ -138,6 +143,10 @@ typedef struct sph_state {
   uint8_t* type;    /* [n] particle type, see SPH_FLUID ... */
   uint32_t* id;     /* [n] particle identity, carried through the sort
                        (nullable: then not carried) */
+  float* normal;    /* [dim][n] for wall particles the vector to the ghost
+                       node (mirror image across the wall face), 0 for
+                       fluid; carried through the sort (nullable; needed by
+                       sph_mdbc) */
 } sph_state;
 
 /* Bytes of workspace the calls need for a case of n particles. */
@@ -234,6 +243,24 @@ sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase,
 sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const double* dt,
                            double* t, sph_state* prev, sph_state* s, const float* ace,
                            const float* arho, void* ws, size_t ws_bytes, void* stream);
+
+/* Modified dynamic boundary condition (Section 2.6.2, Eq. 38-39), on the
+ * sorted state and the view left by sph_bin_cells, before sph_interact:
+ * for every wall particle B, the fluid particles within 2h of its ghost node
+ * G = r_B + normal_B give (FP64 sums, positions from s->pos, kernel of the
+ * case, V_b = m_b/rho_b) the first-order corrected approximation of the
+ * density and its gradient at G, i.e. the solution of
+ *   [sum V w, sum V w r^T; sum V F r, sum V F r r^T] [rho_G; grad] =
+ *   [sum m w; sum m F r]   (r = r_b - r_G, w = W, grad W = F r),
+ * and rho_B = rho_G + (r_B - r_G).grad (Eq. 38); with |det| < 1e-3 the
+ * Shepard value sum m w / sum V w and no gradient.  The ghost velocity is the
+ * Shepard sum of Eq. 39 and the wall takes v_B = 2 v_wall - v_G (no slip
+ * about its own velocity).  With no fluid near G: rho0 and v_wall.
+ * Writes rho_B to s->rho and rho_B, v_B, P(rho_B) to the interaction view
+ * (the state velocity keeps the wall's own motion).  p->boundary must be 1
+ * and s->normal set. */
+sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                    const uint32_t* cell_start, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batches --
  * Continuous batching: n_slots independent cases packed into one set of

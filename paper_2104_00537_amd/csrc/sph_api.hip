@@ -62,6 +62,7 @@ KParams make_kparams(const sph_params& p) {
   k.kpi_mb_f = (float)(-2.0 * p.alpha * p.c0 * kfab * p.mass_bound);
   k.eta2_f = (float)p.eta2;
   k.kernel = p.kernel;
+  k.boundary = p.boundary;
   k.viscosity = p.viscosity;
   k.inv_h_f = (float)(1.0 / p.h);
   k.klam_mf_f = (float)(4.0 * p.visc_nu * kfab * p.mass_fluid);
@@ -118,6 +119,7 @@ static bool params_ok(const sph_params* p) {
   if (p->x_sub != 1 && p->x_sub != 2 && p->x_sub != 4 && p->x_sub != 8) return false;
   if (p->ddt < 0 || p->ddt > 2) return false;
   if (p->kernel != 0 && p->kernel != 1) return false;
+  if (p->boundary != 0 && p->boundary != 1) return false;
   if (p->viscosity != 0 && p->viscosity != 1) return false;
   if (!(p->visc_nu >= 0) || !isfinite(p->visc_nu)) return false;
   for (int k = 0; k < 3; ++k)
@@ -227,6 +229,15 @@ sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const d
                                   (hipStream_t)stream));
 }
 
+sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                    const uint32_t* cell_start, void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !cell_start || !ws || p->boundary != 1) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !s->normal || !key)) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  if (n == 0) return SPH_OK;
+  return hip_status(launch_mdbc(make_kparams(*p), n, *s, key, cell_start, ws, (hipStream_t)stream));
+}
+
 int32_t sph_read_error(const void* ws) {
   if (!ws) return SPH_E_ARG;
   uint32_t v = 0;
@@ -270,7 +281,8 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
     if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
     // the batched interaction runs the default formulation (Wendland kernel,
     // artificial viscosity, ddt 0 or 1)
-    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2) return SPH_E_ARG;
+    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->boundary != 0)
+      return SPH_E_ARG;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};
     e.kp = make_slot_kparams(*p);

@@ -75,6 +75,8 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   }
   out.type[i] = t;
   if (in.id && out.id) out.id[i] = in.id[src];
+  if (in.normal && out.normal)
+    for (int d = 0; d < kp.dim; ++d) out.normal[d * n + i] = in.normal[d * n + src];
   if (carry) {
     for (int d = 0; d < kp.dim; ++d) {
       cout.pos[d * n + i] = cin.pos[d * n + src];

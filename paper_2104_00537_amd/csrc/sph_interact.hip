@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
     PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
     TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     uint32_t c64 = 0;
-    if (!is_excluded(type[i])) {
+    // with modified DBC the wall densities come from Eq. 38 (sph_mdbc): wall
+    // targets take no sums
+    if (!is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]))) {
       const float4 pa = pr[i], va = vp[i];
       T.fluid = pa.w > 0.f;
       T.rho = fabsf(pa.w);
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_arm(
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   if (i < n) {
-    if (!is_excluded(type[i])) {
+    if (!is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]))) {
       const float4 pa = pr[i], va = vp[i];
       const bool fa = pa.w > 0.f;
       const T rho_a = (T)fabsf(pa.w);

@@ -22,6 +22,7 @@ struct KParams {
   int dim, cell_div, ddt, x_sub;   // x_sub: key cells per cell along x
   int lg_xsub, pad2;
   int kernel, viscosity;           // 0 Wendland / 1 cubic spline; 0 artificial / 1 laminar
+  int boundary, pad3;              // 0 DBC (Eq. 36) / 1 modified DBC (Eq. 38-39)
   int ncx, ncy, ncz;
   uint32_t ncell_total;          // also the key of particles outside the grid
   double ox, oy, oz;             // grid origin

@@ -1,0 +1,200 @@
+// Modified dynamic boundary condition (Section 2.6.2 of the DualSPHysics
+// v5.0 paper, Eq. 38-39): wall densities and velocities from ghost nodes.
+//
+// One lane per wall particle (sorted order).  Its ghost node G = r_B +
+// normal_B is binned like a particle; the rows of G's neighbour cells are
+// walked as in the interaction (one range per row), with FP64 distances from
+// the FP64 positions and FP64 sums.  The (d+1) x (d+1) corrected system is
+// solved by Gaussian elimination with partial pivoting in registers.  Only
+// wall entries of the state density and of the interaction view are written;
+// the fluid entries that the walk reads are never changed, and the sign of a
+// wall's view density (the only thing read of a wall candidate) stays
+// negative.
+#include "sph_dev.h"
+#include "sph_kernels.h"
+
+namespace sph {
+
+// Kernel value and gradient factor (grad W = F r) in FP64: Wendland C2
+// (Eq. 11) or cubic spline (Eq. 10).
+__device__ inline void kernel_wf64(const KParams& kp, double r, double& w, double& f) {
+  const double q = r / kp.h;
+  if (kp.kernel == 0) {
+    const double a = kp.dim == 2 ? 7.0 / (4.0 * M_PI * kp.h * kp.h)
+                                 : 21.0 / (16.0 * M_PI * kp.h * kp.h * kp.h);
+    const double u = 1.0 - 0.5 * q;
+    w = a * u * u * u * u * (2.0 * q + 1.0);
+    f = -5.0 * a * u * u * u / (kp.h * kp.h);
+  } else {
+    const double a = kp.dim == 2 ? 10.0 / (7.0 * M_PI * kp.h * kp.h)
+                                 : 1.0 / (M_PI * kp.h * kp.h * kp.h);
+    const double k = a / (kp.h * kp.h);
+    if (q <= 1.0) {
+      w = a * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+      f = k * (-3.0 + 2.25 * q);
+    } else {
+      const double u = 2.0 - q;
+      w = a * 0.25 * u * u * u;
+      f = -0.75 * k * u * u / q;
+    }
+  }
+}
+
+// Solves the M x M system A x = b in place (x returned in b); returns the
+// determinant (0 if a pivot vanished).
+template <int M>
+__device__ inline double solve_small(double (&A)[M][M], double (&b)[M]) {
+  double det = 1.0;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+#pragma unroll
+    for (int r = c + 1; r < M; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (A[piv][c] == 0.0) return 0.0;
+    if (piv != c) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double t = A[c][k];
+        A[c][k] = A[piv][k];
+        A[piv][k] = t;
+      }
+      const double t = b[c];
+      b[c] = b[piv];
+      b[piv] = t;
+      det = -det;
+    }
+    det *= A[c][c];
+#pragma unroll
+    for (int r = c + 1; r < M; ++r) {
+      const double f = A[r][c] / A[c][c];
+#pragma unroll
+      for (int k = c; k < M; ++k) A[r][k] -= f * A[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+#pragma unroll
+  for (int c = M - 1; c >= 0; --c) {
+    double s = b[c];
+#pragma unroll
+    for (int k = c + 1; k < M; ++k) s -= A[c][k] * b[k];
+    b[c] = s / A[c][c];
+  }
+  return det;
+}
+
+template <int DIM, int R>
+__global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_state s,
+                                                 const uint32_t* __restrict__ cstart,
+                                                 float4* __restrict__ pr,
+                                                 float4* __restrict__ vp) {
+  constexpr int M = DIM + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t t = s.type[i];
+  if (is_excluded(t) || is_fluid(t)) return;
+  double g[3] = {0.0, 0.0, 0.0}, rb[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < DIM; ++d) {
+    rb[d] = s.pos[d * n + i];
+    g[d] = rb[d] + (double)s.normal[d * n + i];
+  }
+  // key cell of the ghost node, clamped to the grid
+  const double org[3] = {kp.ox, kp.oy, kp.oz};
+  const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
+  int c[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) {
+    const double f = floor((g[d] - org[d]) * (d == 0 ? kp.inv_csx : kp.inv_cs));
+    int v = f < 0.0 ? 0 : (f >= (double)nc[d] ? nc[d] - 1 : (int)f);
+    c[d] = v;
+  }
+  double A[M][M], B[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    B[r] = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) A[r][k] = 0.0;
+  }
+  double s0 = 0.0, sv[3] = {0.0, 0.0, 0.0};
+  const int reach = R * kp.x_sub;
+  const int x0 = c[0] - reach < 0 ? 0 : c[0] - reach;
+  const int x1 = c[0] + reach >= kp.ncx ? kp.ncx - 1 : c[0] + reach;
+  const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = c[2] + dz;
+    if (z < 0 || z >= kp.ncz) continue;
+    for (int dy = -R; dy <= R; ++dy) {
+      const int y = c[1] + dy;
+      if (y < 0 || y >= kp.ncy) continue;
+      const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+      const uint32_t j1 = cstart[row + x1 + 1];
+      for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
+        const float rw = pr[j].w;
+        if (!(rw > 0.f)) continue;  // fluid particles only
+        double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+        for (int d = 0; d < DIM; ++d) {
+          r[d] = s.pos[d * n + j] - g[d];
+          r2 += r[d] * r[d];
+        }
+        if (!(r2 < kp.support2)) continue;
+        double w, f;
+        kernel_wf64(kp, sqrt(r2), w, f);
+        const double mb = kp.mass_f;
+        const double vb = mb / (double)rw;
+        const double row0[4] = {1.0, r[0], r[1], r[2]};
+#pragma unroll
+        for (int k = 0; k < M; ++k) A[0][k] += vb * w * row0[k];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+          for (int k = 0; k < M; ++k) A[1 + a][k] += vb * f * r[a] * row0[k];
+        B[0] += mb * w;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) B[1 + a] += mb * f * r[a];
+        s0 += vb * w;
+        const float4 v = vp[j];
+        const double vv[3] = {(double)v.x, (double)v.y, (double)v.z};
+        for (int d = 0; d < DIM; ++d) sv[d] += vb * w * vv[d];
+      }
+    }
+  }
+  double rho_b = kp.rho0;
+  double vout[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < DIM; ++d) vout[d] = (double)s.vel[d * n + i];
+  if (s0 > 0.0) {
+    const double shepard = B[0] / s0;
+    const double det = solve_small<M>(A, B);
+    if (fabs(det) >= 1e-3) {
+      rho_b = B[0];
+      for (int d = 0; d < DIM; ++d) rho_b += (rb[d] - g[d]) * B[1 + d];
+    } else {
+      rho_b = shepard;
+    }
+    for (int d = 0; d < DIM; ++d) vout[d] = 2.0 * vout[d] - sv[d] / s0;
+  }
+  const float rf = (float)rho_b;
+  s.rho[i] = rf;
+  pr[i].w = -rf;
+  const double pw = tait_ratio(kp, (double)rf);
+  vp[i] = make_float4((float)vout[0], (float)vout[1], DIM == 3 ? (float)vout[2] : 0.f,
+                      (float)(kp.b_tait * pw));
+}
+
+hipError_t launch_mdbc(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
+                       const uint32_t* cell_start, void* ws, hipStream_t st) {
+  (void)key;
+  const WsLayout L = ws_layout(n);
+  float4* pr = ws_ptr<float4>(ws, L.view_pr);
+  float4* vp = ws_ptr<float4>(ws, L.view_vp);
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+#define SPH_MDBC(D, RR) \
+  hipLaunchKernelGGL((k_mdbc<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, s, cell_start, pr, vp)
+  if (kp.dim == 2) {
+    if (kp.cell_div == 1) SPH_MDBC(2, 1); else SPH_MDBC(2, 2);
+  } else {
+    if (kp.cell_div == 1) SPH_MDBC(3, 1); else SPH_MDBC(3, 2);
+  }
+#undef SPH_MDBC
+  return hipGetLastError();
+}
+
+}  // namespace sph

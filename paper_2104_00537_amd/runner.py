@@ -29,8 +29,10 @@ class Simulation:
         self.n = n = case.n
         dev = torch.device(device)
         self.device = dev
-        self.states = [S.DeviceState.from_case(case, dev),
-                       S.DeviceState.empty(self.dim, n, dev)]
+        # modified DBC needs the wall ghost vectors, carried through the sorts
+        self.mdbc = int(getattr(cp, "boundary", 0)) == 1
+        self.states = [S.DeviceState.from_case(case, dev, with_normal=self.mdbc),
+                       S.DeviceState.empty(self.dim, n, dev, with_normal=self.mdbc)]
         self.saved = [S.DeviceState.empty(self.dim, n, dev, with_type=False, with_id=False)
                       for _ in range(2)]
         self.key = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
@@ -86,6 +88,8 @@ class Simulation:
 
         call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
              self.ws, stream=stream)
+        if self.mdbc:
+            call("mdbc", S.sph_mdbc, P, n, b, self.key, self.cell_start, self.ws, stream=stream)
         call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
              self.ws, flags=self.flags, stream=stream)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
@@ -94,6 +98,8 @@ class Simulation:
              self.arho, self.ws, stream=stream)
         call("bin_cells", S.sph_bin_cells, P, n, b, a, self.key, self.perm, self.cell_start,
              self.ws, carry_in=s0, carry_out=s1, stream=stream)
+        if self.mdbc:
+            call("mdbc", S.sph_mdbc, P, n, a, self.key, self.cell_start, self.ws, stream=stream)
         call("interact", S.sph_interact, P, n, a, self.key, self.cell_start, self.ace, self.arho,
              self.ws, flags=self.flags, stream=stream)
         # pair count of the second pass (its dt is not used: Eq. 35 is taken
@@ -126,6 +132,8 @@ class Simulation:
         mode = 1 if self.steps_done % self.verlet_ns == 0 else 0
         call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
              self.ws, carry_in=s0, carry_out=s1, stream=stream)
+        if self.mdbc:
+            call("mdbc", S.sph_mdbc, P, n, b, self.key, self.cell_start, self.ws, stream=stream)
         call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
              self.ws, flags=self.flags, stream=stream)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,

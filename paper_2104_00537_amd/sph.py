@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +26,7 @@ SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
-           "sph_symplectic_step", "sph_verlet_step", "sph_read_error", "sph_clear_error", "sph_strerror",
+           "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_read_error", "sph_clear_error", "sph_strerror",
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
            "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
@@ -35,7 +36,7 @@ SPH_BATCH_MAX_SLOTS = 4096
 class SphParams(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("cell_div", C.c_int32), ("ddt", C.c_int32),
-        ("ncell", C.c_int32 * 3), ("x_sub", C.c_int32), ("reserved", C.c_int32),
+        ("ncell", C.c_int32 * 3), ("x_sub", C.c_int32), ("boundary", C.c_int32),
         ("origin", C.c_double * 3),
         ("cell_size", C.c_double), ("inv_cell_size", C.c_double),
         ("h", C.c_double), ("rho0", C.c_double), ("gamma", C.c_double),
@@ -50,7 +51,7 @@ class SphParams(C.Structure):
 
 class SphState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("rho", C.c_void_p),
-                ("type", C.c_void_p), ("id", C.c_void_p)]
+                ("type", C.c_void_p), ("id", C.c_void_p), ("normal", C.c_void_p)]
 
 
 class SphBatch(C.Structure):
@@ -85,6 +86,8 @@ def _load() -> C.CDLL:
     L.sph_verlet_step.restype = C.c_int32
     L.sph_verlet_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP,
                                   P(SphState), P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_mdbc.restype = C.c_int32
+    L.sph_mdbc.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, C.c_size_t, VP]
     L.sph_read_error.restype = C.c_int32
     L.sph_read_error.argtypes = [VP]
     L.sph_clear_error.restype = C.c_int32
@@ -139,6 +142,7 @@ def make_params(cp) -> SphParams:
     p = SphParams()
     p.dim, p.cell_div, p.ddt = int(cp.dim), int(cp.cell_div), int(cp.ddt)
     p.x_sub = int(getattr(cp, "x_sub", 1))
+    p.boundary = int(getattr(cp, "boundary", 0))
     p.kernel = int(getattr(cp, "kernel", 0))
     p.viscosity = int(getattr(cp, "viscosity", 0))
     p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
@@ -161,30 +165,40 @@ class DeviceState:
     rho: torch.Tensor            # (n,) float32
     type: Optional[torch.Tensor] = None  # (n,) uint8
     id: Optional[torch.Tensor] = None    # (n,) int32 (bit pattern of uint32)
+    normal: Optional[torch.Tensor] = None  # (dim, n) float32 wall ghost vectors
 
     @staticmethod
-    def empty(dim: int, n: int, device, with_type=True, with_id=True) -> "DeviceState":
+    def empty(dim: int, n: int, device, with_type=True, with_id=True,
+              with_normal=False) -> "DeviceState":
         return DeviceState(
             pos=torch.empty((dim, n), dtype=torch.float64, device=device),
             vel=torch.empty((dim, n), dtype=torch.float32, device=device),
             rho=torch.empty((n,), dtype=torch.float32, device=device),
             type=torch.empty((n,), dtype=torch.uint8, device=device) if with_type else None,
-            id=torch.empty((n,), dtype=torch.int32, device=device) if with_id else None)
+            id=torch.empty((n,), dtype=torch.int32, device=device) if with_id else None,
+            normal=(torch.empty((dim, n), dtype=torch.float32, device=device)
+                    if with_normal else None))
 
     @staticmethod
-    def from_case(case, device) -> "DeviceState":
+    def from_case(case, device, with_normal=False) -> "DeviceState":
         n = case.n
+        normal = None
+        if with_normal:
+            if case.normal is None:
+                raise ValueError("the case has no wall ghost vectors")
+            normal = torch.from_numpy(np.ascontiguousarray(case.normal)).to(device)
         return DeviceState(
             pos=torch.from_numpy(case.pos).to(device),
             vel=torch.from_numpy(case.vel).to(device),
             rho=torch.from_numpy(case.rho).to(device),
             type=torch.from_numpy(case.type).to(device),
-            id=torch.arange(n, dtype=torch.int32, device=device))
+            id=torch.arange(n, dtype=torch.int32, device=device), normal=normal)
 
     def c(self) -> SphState:
         return SphState(self.pos.data_ptr(), self.vel.data_ptr(), self.rho.data_ptr(),
                         None if self.type is None else self.type.data_ptr(),
-                        None if self.id is None else self.id.data_ptr())
+                        None if self.id is None else self.id.data_ptr(),
+                        None if self.normal is None else self.normal.data_ptr())
 
     @property
     def n(self) -> int:
@@ -236,6 +250,12 @@ def sph_verlet_step(params: SphParams, n: int, mode: int, dt: torch.Tensor, t: t
     _check(lib.sph_verlet_step(C.byref(params), int(n), int(mode), _ptr(dt), _ptr(t),
                                C.byref(prev.c()), C.byref(s.c()), _ptr(ace), _ptr(arho),
                                _ptr(ws), ws.numel(), _stream(stream)), "sph_verlet_step")
+
+
+def sph_mdbc(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+             cell_start: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib.sph_mdbc(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
+                        _ptr(ws), ws.numel(), _stream(stream)), "sph_mdbc")
 
 
 def sph_read_error(ws: torch.Tensor) -> int:
