@@ -173,7 +173,7 @@ def test_bin_cells_all_same_cell_is_stable():
 def _perturbed(case, seed, vel=0.5, drho=0.003):
     rng = np.random.default_rng(seed)
     c = cases.Case(case.params, case.pos.copy(), case.vel.copy(), case.rho.copy(), case.type.copy(),
-                   dict(case.meta))
+                   dict(case.meta), case.normal)
     c.vel[:] = rng.uniform(-vel, vel, c.vel.shape).astype(np.float32)
     c.rho[:] = (c.rho * (1 + rng.uniform(-drho, drho, c.n))).astype(np.float32)
     return c
