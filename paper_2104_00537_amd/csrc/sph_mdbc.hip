@@ -3,8 +3,10 @@
 //
 // One lane per wall particle (sorted order).  Its ghost node G = r_B +
 // normal_B is binned like a particle; the rows of G's neighbour cells are
-// walked as in the interaction (one range per row), with FP64 distances from
-// the FP64 positions and FP64 sums.  The (d+1) x (d+1) corrected system is
+// walked as in the interaction (one range per row, cut to the support sphere
+// of G), candidates are screened in FP32 on the view's offsets with a margin,
+// and the pairs that pass are tested and summed in FP64 on the FP64
+// positions.  The (d+1) x (d+1) corrected system is
 // solved by Gaussian elimination with partial pivoting in registers.  Only
 // wall entries of the state density and of the interaction view are written;
 // the fluid entries that the walk reads are never changed, and the sign of a
@@ -98,14 +100,16 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
     rb[d] = s.pos[d * n + i];
     g[d] = rb[d] + (double)s.normal[d * n + i];
   }
-  // key cell of the ghost node, clamped to the grid
+  // key cell of the ghost node; a ghost node outside the grid has no fluid
+  // around it (the wall is treated as dry)
   const double org[3] = {kp.ox, kp.oy, kp.oz};
   const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
   int c[3] = {0, 0, 0};
+  bool inside = true;
   for (int d = 0; d < DIM; ++d) {
     const double f = floor((g[d] - org[d]) * (d == 0 ? kp.inv_csx : kp.inv_cs));
-    int v = f < 0.0 ? 0 : (f >= (double)nc[d] ? nc[d] - 1 : (int)f);
-    c[d] = v;
+    inside = inside && f >= 0.0 && f < (double)nc[d];
+    c[d] = inside ? (int)f : 0;
   }
   double A[M][M], B[M];
 #pragma unroll
@@ -115,21 +119,49 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
     for (int k = 0; k < M; ++k) A[r][k] = 0.0;
   }
   double s0 = 0.0, sv[3] = {0.0, 0.0, 0.0};
+  // the ghost node in the view's frame: fixed-point x (as the reorder writes
+  // it), y and z relative to the ghost's cell
+  const double fr = (g[0] - kp.ox) * kp.inv_frame;
+  const uint32_t xg = (uint32_t)(uint64_t)((fr - floor(fr)) * 4294967296.0);
+  const float yg = DIM >= 2 ? (float)(g[1] - (kp.oy + (double)c[1] * kp.cs)) : 0.f;
+  const float zg = DIM == 3 ? (float)(g[2] - (kp.oz + (double)c[2] * kp.cs)) : 0.f;
+  const int fcells = kFrameCells << kp.lg_xsub;
+  const float fx =
+      (float)(int32_t)(xg - ((uint32_t)(c[0] % fcells) << (29 - kp.lg_xsub))) * kp.unit_x_f;
+  const float cs = kp.cs_f;
+  // FP32 pre-test with a margin far above its rounding; the FP64 test on the
+  // FP64 positions decides
+  const float pre2 = kp.support2_f * 1.0002f;
   const int reach = R * kp.x_sub;
-  const int x0 = c[0] - reach < 0 ? 0 : c[0] - reach;
-  const int x1 = c[0] + reach >= kp.ncx ? kp.ncx - 1 : c[0] + reach;
+  const int xlo = c[0] - reach < 0 ? 0 : c[0] - reach;
+  const int xhi = c[0] + reach >= kp.ncx ? kp.ncx - 1 : c[0] + reach;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
+  for (int dz = zlo; dz <= (inside ? zhi : zlo - 1); ++dz) {
     const int z = c[2] + dz;
     if (z < 0 || z >= kp.ncz) continue;
+    const float ez0 = (float)dz * cs - zg;
+    const float ez = DIM == 3 ? (dz > 0 ? ez0 : (dz < 0 ? -(ez0 + cs) : 0.f)) : 0.f;
     for (int dy = -R; dy <= R; ++dy) {
       const int y = c[1] + dy;
       if (y < 0 || y >= kp.ncy) continue;
+      const float ey0 = (float)dy * cs - yg;
+      const float ey = dy > 0 ? ey0 : (dy < 0 ? -(ey0 + cs) : 0.f);
+      const float w2 = pre2 - ey * ey - ez * ez;
+      if (!(w2 > 0.f)) continue;
+      const float wx = sqrtf(w2);
+      int x0 = c[0] + (int)floorf((fx - wx) * kp.inv_csx_f);
+      int x1 = c[0] + (int)floorf((fx + wx) * kp.inv_csx_f);
+      x0 = x0 < xlo ? xlo : x0;
+      x1 = x1 > xhi ? xhi : x1;
       const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const uint32_t j1 = cstart[row + x1 + 1];
+      const float ys = yg - (float)dy * cs, zs = zg - (float)dz * cs;
       for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
-        const float rw = pr[j].w;
-        if (!(rw > 0.f)) continue;  // fluid particles only
+        const float4 pb = pr[j];
+        if (!(pb.w > 0.f)) continue;  // fluid particles only
+        const float ex = (float)(int32_t)(xg - __float_as_uint(pb.x)) * kp.unit_x_f;
+        const float ey1 = ys - pb.y, ez1 = DIM == 3 ? zs - pb.z : 0.f;
+        if (!(ex * ex + ey1 * ey1 + ez1 * ez1 < pre2)) continue;
         double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
         for (int d = 0; d < DIM; ++d) {
           r[d] = s.pos[d * n + j] - g[d];
@@ -139,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
         double w, f;
         kernel_wf64(kp, sqrt(r2), w, f);
         const double mb = kp.mass_f;
-        const double vb = mb / (double)rw;
+        const double vb = mb / (double)pb.w;
         const double row0[4] = {1.0, r[0], r[1], r[2]};
 #pragma unroll
         for (int k = 0; k < M; ++k) A[0][k] += vb * w * row0[k];
