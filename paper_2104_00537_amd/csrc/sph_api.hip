@@ -50,6 +50,9 @@ KParams make_kparams(const sph_params& p) {
   const double kfab = p.kernel == 1 ? alpha_d / (p.h * p.h) : -5.0 * alpha_d / (p.h * p.h);
   k.inv_frame = 1.0 / (kFrameCells * p.cell_size);
   k.kfab = kfab;
+  k.inv_h = 1.0 / p.h;
+  k.w_alpha = alpha_d;
+  k.f_coef = kfab;
   k.alpha_c0 = p.alpha * p.c0;
   k.ddt_coef = p.ddt ? 2.0 * p.delta * p.h * p.c0 : 0.0;
   k.eta2 = p.eta2;

@@ -35,6 +35,7 @@ struct KParams {
   // FP32 copies for the interaction kernel
   double inv_frame;               // 1 / (kFrameCells cs)
   double kfab, alpha_c0, ddt_coef, eta2;  // FP64 copies for the precision-study arms
+  double inv_h, w_alpha, f_coef;          // FP64 kernel: 1/h, alpha_D, gradient factor
   float h_f, mhalf_inv_h_f, support2_f;      // h, -1/(2h), 4h^2
   float kfab_mf_f, kfab_mb_f;                // kfab m_fluid, kfab m_wall; kfab = -5 alpha_D / h^2
   float kpi_mf_f, kpi_mb_f;                  // -2 alpha c0 kfab m (Eq. 21 with Eq. 22)

@@ -18,58 +18,55 @@
 namespace sph {
 
 // Kernel value and gradient factor (grad W = F r) in FP64: Wendland C2
-// (Eq. 11) or cubic spline (Eq. 10).
+// (Eq. 11), W = alpha_D (1 - q/2)^4 (2q + 1), F = kfab (1 - q/2)^3, or cubic
+// spline (Eq. 10), with alpha_D and kfab of the case.
 __device__ inline void kernel_wf64(const KParams& kp, double r, double& w, double& f) {
-  const double q = r / kp.h;
+  const double q = r * kp.inv_h;
   if (kp.kernel == 0) {
-    const double a = kp.dim == 2 ? 7.0 / (4.0 * M_PI * kp.h * kp.h)
-                                 : 21.0 / (16.0 * M_PI * kp.h * kp.h * kp.h);
     const double u = 1.0 - 0.5 * q;
-    w = a * u * u * u * u * (2.0 * q + 1.0);
-    f = -5.0 * a * u * u * u / (kp.h * kp.h);
+    const double u3 = u * u * u;
+    w = kp.w_alpha * u3 * u * (2.0 * q + 1.0);
+    f = kp.f_coef * u3;
+  } else if (q <= 1.0) {
+    w = kp.w_alpha * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+    f = kp.f_coef * (-3.0 + 2.25 * q);
   } else {
-    const double a = kp.dim == 2 ? 10.0 / (7.0 * M_PI * kp.h * kp.h)
-                                 : 1.0 / (M_PI * kp.h * kp.h * kp.h);
-    const double k = a / (kp.h * kp.h);
-    if (q <= 1.0) {
-      w = a * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
-      f = k * (-3.0 + 2.25 * q);
-    } else {
-      const double u = 2.0 - q;
-      w = a * 0.25 * u * u * u;
-      f = -0.75 * k * u * u / q;
-    }
+    const double u = 2.0 - q;
+    w = kp.w_alpha * 0.25 * u * u * u;
+    f = -0.75 * kp.f_coef * u * u / q;
   }
 }
 
-// Solves the M x M system A x = b in place (x returned in b); returns the
+// Solves the M x M system A x = b in place (x returned in b) by Gaussian
+// elimination with partial pivoting; the row exchanges are compare-and-swap
+// steps with fixed indices, so the arrays stay in registers.  Returns the
 // determinant (0 if a pivot vanished).
 template <int M>
 __device__ inline double solve_small(double (&A)[M][M], double (&b)[M]) {
   double det = 1.0;
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    int piv = c;
-#pragma unroll
-    for (int r = c + 1; r < M; ++r)
-      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-    if (A[piv][c] == 0.0) return 0.0;
-    if (piv != c) {
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double t = A[c][k];
-        A[c][k] = A[piv][k];
-        A[piv][k] = t;
-      }
-      const double t = b[c];
-      b[c] = b[piv];
-      b[piv] = t;
-      det = -det;
-    }
-    det *= A[c][c];
 #pragma unroll
     for (int r = c + 1; r < M; ++r) {
-      const double f = A[r][c] / A[c][c];
+      if (fabs(A[r][c]) > fabs(A[c][c])) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const double t = A[c][k];
+          A[c][k] = A[r][k];
+          A[r][k] = t;
+        }
+        const double t = b[c];
+        b[c] = b[r];
+        b[r] = t;
+        det = -det;
+      }
+    }
+    if (A[c][c] == 0.0) return 0.0;
+    det *= A[c][c];
+    const double inv = 1.0 / A[c][c];
+#pragma unroll
+    for (int r = c + 1; r < M; ++r) {
+      const double f = A[r][c] * inv;
 #pragma unroll
       for (int k = c; k < M; ++k) A[r][k] -= f * A[c][k];
       b[r] -= f * b[c];
@@ -96,6 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
   const uint8_t t = s.type[i];
   if (is_excluded(t) || is_fluid(t)) return;
   double g[3] = {0.0, 0.0, 0.0}, rb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
   for (int d = 0; d < DIM; ++d) {
     rb[d] = s.pos[d * n + i];
     g[d] = rb[d] + (double)s.normal[d * n + i];
@@ -106,19 +104,18 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
   const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
   int c[3] = {0, 0, 0};
   bool inside = true;
+#pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const double f = floor((g[d] - org[d]) * (d == 0 ? kp.inv_csx : kp.inv_cs));
     inside = inside && f >= 0.0 && f < (double)nc[d];
     c[d] = inside ? (int)f : 0;
   }
-  double A[M][M], B[M];
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-    B[r] = 0.0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) A[r][k] = 0.0;
-  }
-  double s0 = 0.0, sv[3] = {0.0, 0.0, 0.0};
+  // sums of the corrected system: sw = sum V w, swr = sum V w r,
+  // sfr = sum V F r, sfrr = sum V F r r^T (symmetric, upper part), b0 =
+  // sum m w, bf = sum m F r; and the Shepard velocity sum
+  double sw = 0.0, swr[3] = {0.0, 0.0, 0.0}, sfr[3] = {0.0, 0.0, 0.0};
+  double sfrr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double b0 = 0.0, bf[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0};
   // the ghost node in the view's frame: fixed-point x (as the reorder writes
   // it), y and z relative to the ghost's cell
   const double fr = (g[0] - kp.ox) * kp.inv_frame;
@@ -163,6 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
         const float ey1 = ys - pb.y, ez1 = DIM == 3 ? zs - pb.z : 0.f;
         if (!(ex * ex + ey1 * ey1 + ez1 * ez1 < pre2)) continue;
         double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+#pragma unroll
         for (int d = 0; d < DIM; ++d) {
           r[d] = s.pos[d * n + j] - g[d];
           r2 += r[d] * r[d];
@@ -172,36 +170,57 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
         kernel_wf64(kp, sqrt(r2), w, f);
         const double mb = kp.mass_f;
         const double vb = mb / (double)pb.w;
-        const double row0[4] = {1.0, r[0], r[1], r[2]};
+        const double vw = vb * w, vf = vb * f;
+        sw += vw;
+        b0 += mb * w;
 #pragma unroll
-        for (int k = 0; k < M; ++k) A[0][k] += vb * w * row0[k];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-#pragma unroll
-          for (int k = 0; k < M; ++k) A[1 + a][k] += vb * f * r[a] * row0[k];
-        B[0] += mb * w;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) B[1 + a] += mb * f * r[a];
-        s0 += vb * w;
+        for (int a = 0; a < DIM; ++a) {
+          swr[a] += vw * r[a];
+          sfr[a] += vf * r[a];
+          bf[a] += mb * f * r[a];
+        }
+        sfrr[0] += vf * r[0] * r[0];
+        sfrr[1] += vf * r[0] * r[1];
+        sfrr[3] += vf * r[1] * r[1];
+        if (DIM == 3) {
+          sfrr[2] += vf * r[0] * r[2];
+          sfrr[4] += vf * r[1] * r[2];
+          sfrr[5] += vf * r[2] * r[2];
+        }
         const float4 v = vp[j];
-        const double vv[3] = {(double)v.x, (double)v.y, (double)v.z};
-        for (int d = 0; d < DIM; ++d) sv[d] += vb * w * vv[d];
+        sv[0] += vw * (double)v.x;
+        sv[1] += vw * (double)v.y;
+        if (DIM == 3) sv[2] += vw * (double)v.z;
       }
     }
   }
   double rho_b = kp.rho0;
   double vout[3] = {0.0, 0.0, 0.0};
+#pragma unroll
   for (int d = 0; d < DIM; ++d) vout[d] = (double)s.vel[d * n + i];
-  if (s0 > 0.0) {
-    const double shepard = B[0] / s0;
-    const double det = solve_small<M>(A, B);
-    if (fabs(det) >= 1e-3) {
-      rho_b = B[0];
-      for (int d = 0; d < DIM; ++d) rho_b += (rb[d] - g[d]) * B[1 + d];
-    } else {
-      rho_b = shepard;
+  if (sw > 0.0) {
+    double A[M][M], x[M];
+    A[0][0] = sw;
+    x[0] = b0;
+    const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      A[0][1 + a] = swr[a];
+      A[1 + a][0] = sfr[a];
+      x[1 + a] = bf[a];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) A[1 + a][1 + k] = sfrr[sym[a][k]];
     }
-    for (int d = 0; d < DIM; ++d) vout[d] = 2.0 * vout[d] - sv[d] / s0;
+    const double det = solve_small<M>(A, x);
+    if (fabs(det) >= 1e-3) {
+      rho_b = x[0];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) rho_b += (rb[d] - g[d]) * x[1 + d];
+    } else {
+      rho_b = b0 / sw;
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) vout[d] = 2.0 * vout[d] - sv[d] / sw;
   }
   const float rf = (float)rho_b;
   s.rho[i] = rf;
