@@ -2,11 +2,11 @@
 // v5.0 paper, Eq. 38-39): wall densities and velocities from ghost nodes.
 //
 // One lane per wall particle (sorted order).  Its ghost node G = r_B +
-// normal_B is binned like a particle; the rows of G's neighbour cells are
+// normal_B is binned like a particle and placed in the view's frame
+// (fixed-point x, cell-relative y and z); the rows of G's neighbour cells are
 // walked as in the interaction (one range per row, cut to the support sphere
-// of G), candidates are screened in FP32 on the view's offsets with a margin,
-// and the pairs that pass are tested and summed in FP64 on the FP64
-// positions.  The (d+1) x (d+1) corrected system is
+// of G).  Distances, kernel weights and volumes are FP32 as in the
+// interaction; the moment sums and the solve are FP64.  The (d+1) x (d+1) corrected system is
 // solved by Gaussian elimination with partial pivoting in registers.  Only
 // wall entries of the state density and of the interaction view are written;
 // the fluid entries that the walk reads are never changed, and the sign of a
@@ -17,23 +17,25 @@
 
 namespace sph {
 
-// Kernel value and gradient factor (grad W = F r) in FP64: Wendland C2
+// Kernel value and gradient factor (grad W = F r) in FP32: Wendland C2
 // (Eq. 11), W = alpha_D (1 - q/2)^4 (2q + 1), F = kfab (1 - q/2)^3, or cubic
-// spline (Eq. 10), with alpha_D and kfab of the case.
-__device__ inline void kernel_wf64(const KParams& kp, double r, double& w, double& f) {
-  const double q = r * kp.inv_h;
+// spline (Eq. 10), with alpha_D and kfab of the case.  The weights enter the
+// corrected system both as W and as F; exactness for linear fields holds for
+// any weights, so their FP32 rounding only perturbs the result at ~1e-7.
+__device__ inline void kernel_wf32(const KParams& kp, float r, float& w, float& f) {
+  const float q = r * kp.inv_h_f;
   if (kp.kernel == 0) {
-    const double u = 1.0 - 0.5 * q;
-    const double u3 = u * u * u;
-    w = kp.w_alpha * u3 * u * (2.0 * q + 1.0);
-    f = kp.f_coef * u3;
-  } else if (q <= 1.0) {
-    w = kp.w_alpha * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
-    f = kp.f_coef * (-3.0 + 2.25 * q);
+    const float u = 1.f - 0.5f * q;
+    const float u3 = u * u * u;
+    w = kp.w_alpha_f * u3 * u * (2.f * q + 1.f);
+    f = kp.f_coef_f * u3;
+  } else if (q <= 1.f) {
+    w = kp.w_alpha_f * (1.f - 1.5f * q * q + 0.75f * q * q * q);
+    f = kp.f_coef_f * (-3.f + 2.25f * q);
   } else {
-    const double u = 2.0 - q;
-    w = kp.w_alpha * 0.25 * u * u * u;
-    f = -0.75 * kp.f_coef * u * u / q;
+    const float u = 2.f - q;
+    w = kp.w_alpha_f * 0.25f * u * u * u;
+    f = -0.75f * kp.f_coef_f * u * u / q;
   }
 }
 
@@ -126,9 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
   const float fx =
       (float)(int32_t)(xg - ((uint32_t)(c[0] % fcells) << (29 - kp.lg_xsub))) * kp.unit_x_f;
   const float cs = kp.cs_f;
-  // FP32 pre-test with a margin far above its rounding; the FP64 test on the
-  // FP64 positions decides
+  // rows cut with the support enlarged by 2e-4 (far above the FP32 error)
   const float pre2 = kp.support2_f * 1.0002f;
+  const float mf_f = (float)kp.mass_f;
   const int reach = R * kp.x_sub;
   const int xlo = c[0] - reach < 0 ? 0 : c[0] - reach;
   const int xhi = c[0] + reach >= kp.ncx ? kp.ncx - 1 : c[0] + reach;
@@ -156,28 +158,24 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
       for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
         const float4 pb = pr[j];
         if (!(pb.w > 0.f)) continue;  // fluid particles only
-        const float ex = (float)(int32_t)(xg - __float_as_uint(pb.x)) * kp.unit_x_f;
-        const float ey1 = ys - pb.y, ez1 = DIM == 3 ? zs - pb.z : 0.f;
-        if (!(ex * ex + ey1 * ey1 + ez1 * ez1 < pre2)) continue;
-        double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          r[d] = s.pos[d * n + j] - g[d];
-          r2 += r[d] * r[d];
-        }
-        if (!(r2 < kp.support2)) continue;
-        double w, f;
-        kernel_wf64(kp, sqrt(r2), w, f);
-        const double mb = kp.mass_f;
-        const double vb = mb / (double)pb.w;
-        const double vw = vb * w, vf = vb * f;
+        // r = r_b - r_G from the view's offsets (FP32)
+        const float rx = (float)(int32_t)(__float_as_uint(pb.x) - xg) * kp.unit_x_f;
+        const float ry = pb.y - ys, rz = DIM == 3 ? pb.z - zs : 0.f;
+        const float r2 = rx * rx + ry * ry + rz * rz;
+        if (!(r2 < kp.support2_f)) continue;
+        float w, f;
+        kernel_wf32(kp, sqrtf(r2), w, f);
+        const float vbf = mf_f / pb.w;
+        const double vw = (double)(vbf * w), vf = (double)(vbf * f);
+        const double mw = (double)(mf_f * w), mf = (double)(mf_f * f);
+        const double r[3] = {(double)rx, (double)ry, (double)rz};
         sw += vw;
-        b0 += mb * w;
+        b0 += mw;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           swr[a] += vw * r[a];
           sfr[a] += vf * r[a];
-          bf[a] += mb * f * r[a];
+          bf[a] += mf * r[a];
         }
         sfrr[0] += vf * r[0] * r[0];
         sfrr[1] += vf * r[0] * r[1];
