@@ -68,8 +68,6 @@ KParams make_kparams(const sph_params& p) {
   k.boundary = p.boundary;
   k.viscosity = p.viscosity;
   k.inv_h_f = (float)(1.0 / p.h);
-  k.w_alpha_f = (float)alpha_d;
-  k.f_coef_f = (float)kfab;
   k.klam_mf_f = (float)(4.0 * p.visc_nu * kfab * p.mass_fluid);
   k.klam_mb_f = (float)(4.0 * p.visc_nu * kfab * p.mass_bound);
   {

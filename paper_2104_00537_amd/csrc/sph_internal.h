@@ -40,7 +40,6 @@ struct KParams {
   float kfab_mf_f, kfab_mb_f;                // kfab m_fluid, kfab m_wall; kfab = -5 alpha_D / h^2
   float kpi_mf_f, kpi_mb_f;                  // -2 alpha c0 kfab m (Eq. 21 with Eq. 22)
   float inv_h_f;                             // 1/h (cubic spline)
-  float w_alpha_f, f_coef_f;                 // alpha_D and the gradient factor (mDBC)
   float klam_mf_f, klam_mb_f;                // 4 nu0 kfab m (Eq. 23)
   float fz_f, hc1_f, hc2_f, hc3_f;           // Eq. 19-20: eps = fz z_ab, rho^H = eps(c1 + eps(c2 + eps c3))
   float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
@@ -62,7 +61,8 @@ struct BlockRed {
 struct WsHeader {
   uint32_t err;      // SPH_ERR_* bits
   uint32_t nred;     // BlockRed entries written by the last interaction pass
-  uint32_t pad[62];
+  uint32_t nwall;    // wall particles listed by the last sph_mdbc (its work list)
+  uint32_t pad[61];
 };
 
 // ---------------------------------------------------------------- batches --

@@ -1,12 +1,12 @@
 // Modified dynamic boundary condition (Section 2.6.2 of the DualSPHysics
 // v5.0 paper, Eq. 38-39): wall densities and velocities from ghost nodes.
 //
-// One lane per wall particle (sorted order).  Its ghost node G = r_B +
-// normal_B is binned like a particle and placed in the view's frame
-// (fixed-point x, cell-relative y and z); the rows of G's neighbour cells are
+// A first kernel lists the wall particles; then one lane per listed wall.  Its ghost node G = r_B +
+// normal_B is binned like a particle; the rows of G's neighbour cells are
 // walked as in the interaction (one range per row, cut to the support sphere
-// of G).  Distances, kernel weights and volumes are FP32 as in the
-// interaction; the moment sums and the solve are FP64.  The (d+1) x (d+1) corrected system is
+// of G), candidates are screened in FP32 on the view's offsets with a margin,
+// and the pairs that pass are tested and summed in FP64 on the FP64
+// positions.  The (d+1) x (d+1) corrected system is
 // solved by Gaussian elimination with partial pivoting in registers.  Only
 // wall entries of the state density and of the interaction view are written;
 // the fluid entries that the walk reads are never changed, and the sign of a
@@ -17,25 +17,23 @@
 
 namespace sph {
 
-// Kernel value and gradient factor (grad W = F r) in FP32: Wendland C2
+// Kernel value and gradient factor (grad W = F r) in FP64: Wendland C2
 // (Eq. 11), W = alpha_D (1 - q/2)^4 (2q + 1), F = kfab (1 - q/2)^3, or cubic
-// spline (Eq. 10), with alpha_D and kfab of the case.  The weights enter the
-// corrected system both as W and as F; exactness for linear fields holds for
-// any weights, so their FP32 rounding only perturbs the result at ~1e-7.
-__device__ inline void kernel_wf32(const KParams& kp, float r, float& w, float& f) {
-  const float q = r * kp.inv_h_f;
+// spline (Eq. 10), with alpha_D and kfab of the case.
+__device__ inline void kernel_wf64(const KParams& kp, double r, double& w, double& f) {
+  const double q = r * kp.inv_h;
   if (kp.kernel == 0) {
-    const float u = 1.f - 0.5f * q;
-    const float u3 = u * u * u;
-    w = kp.w_alpha_f * u3 * u * (2.f * q + 1.f);
-    f = kp.f_coef_f * u3;
-  } else if (q <= 1.f) {
-    w = kp.w_alpha_f * (1.f - 1.5f * q * q + 0.75f * q * q * q);
-    f = kp.f_coef_f * (-3.f + 2.25f * q);
+    const double u = 1.0 - 0.5 * q;
+    const double u3 = u * u * u;
+    w = kp.w_alpha * u3 * u * (2.0 * q + 1.0);
+    f = kp.f_coef * u3;
+  } else if (q <= 1.0) {
+    w = kp.w_alpha * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+    f = kp.f_coef * (-3.0 + 2.25 * q);
   } else {
-    const float u = 2.f - q;
-    w = kp.w_alpha_f * 0.25f * u * u * u;
-    f = -0.75f * kp.f_coef_f * u * u / q;
+    const double u = 2.0 - q;
+    w = kp.w_alpha * 0.25 * u * u * u;
+    f = -0.75 * kp.f_coef * u * u / q;
   }
 }
 
@@ -84,16 +82,42 @@ __device__ inline double solve_small(double (&A)[M][M], double (&b)[M]) {
   return det;
 }
 
+__global__ void k_zero_wall_count(WsHeader* __restrict__ hdr) {
+  if (threadIdx.x == 0) hdr->nwall = 0u;
+}
+
+// The wall particles (not excluded) of the sorted state, appended to a work
+// list in any order (one atomic per wave); each wall's result depends only on
+// its own inputs, so the order does not matter.
+__global__ __launch_bounds__(kBlock) void k_wall_list(int64_t n, const uint8_t* __restrict__ type,
+                                                      uint32_t* __restrict__ list,
+                                                      WsHeader* __restrict__ hdr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool wall = i < n && !is_excluded(type[i]) && !is_fluid(type[i]);
+  const uint64_t mask = __ballot(wall);
+  if (mask == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = (int)__builtin_ctzll(mask);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(&hdr->nwall, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (wall) {
+    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (64 - lane)));
+    list[base + (uint32_t)__popcll(below)] = (uint32_t)i;
+  }
+}
+
 template <int DIM, int R>
 __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_state s,
                                                  const uint32_t* __restrict__ cstart,
                                                  float4* __restrict__ pr,
-                                                 float4* __restrict__ vp) {
+                                                 float4* __restrict__ vp,
+                                                 const uint32_t* __restrict__ list,
+                                                 const WsHeader* __restrict__ hdr) {
   constexpr int M = DIM + 1;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint8_t t = s.type[i];
-  if (is_excluded(t) || is_fluid(t)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)hdr->nwall) return;
+  const int64_t i = list[t];
   double g[3] = {0.0, 0.0, 0.0}, rb[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -128,9 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
   const float fx =
       (float)(int32_t)(xg - ((uint32_t)(c[0] % fcells) << (29 - kp.lg_xsub))) * kp.unit_x_f;
   const float cs = kp.cs_f;
-  // rows cut with the support enlarged by 2e-4 (far above the FP32 error)
+  // FP32 pre-test with a margin far above its rounding; the FP64 test on the
+  // FP64 positions decides
   const float pre2 = kp.support2_f * 1.0002f;
-  const float mf_f = (float)kp.mass_f;
   const int reach = R * kp.x_sub;
   const int xlo = c[0] - reach < 0 ? 0 : c[0] - reach;
   const int xhi = c[0] + reach >= kp.ncx ? kp.ncx - 1 : c[0] + reach;
@@ -158,24 +182,28 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
       for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
         const float4 pb = pr[j];
         if (!(pb.w > 0.f)) continue;  // fluid particles only
-        // r = r_b - r_G from the view's offsets (FP32)
-        const float rx = (float)(int32_t)(__float_as_uint(pb.x) - xg) * kp.unit_x_f;
-        const float ry = pb.y - ys, rz = DIM == 3 ? pb.z - zs : 0.f;
-        const float r2 = rx * rx + ry * ry + rz * rz;
-        if (!(r2 < kp.support2_f)) continue;
-        float w, f;
-        kernel_wf32(kp, sqrtf(r2), w, f);
-        const float vbf = mf_f / pb.w;
-        const double vw = (double)(vbf * w), vf = (double)(vbf * f);
-        const double mw = (double)(mf_f * w), mf = (double)(mf_f * f);
-        const double r[3] = {(double)rx, (double)ry, (double)rz};
+        const float ex = (float)(int32_t)(xg - __float_as_uint(pb.x)) * kp.unit_x_f;
+        const float ey1 = ys - pb.y, ez1 = DIM == 3 ? zs - pb.z : 0.f;
+        if (!(ex * ex + ey1 * ey1 + ez1 * ez1 < pre2)) continue;
+        double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          r[d] = s.pos[d * n + j] - g[d];
+          r2 += r[d] * r[d];
+        }
+        if (!(r2 < kp.support2)) continue;
+        double w, f;
+        kernel_wf64(kp, sqrt(r2), w, f);
+        const double mb = kp.mass_f;
+        const double vb = mb / (double)pb.w;
+        const double vw = vb * w, vf = vb * f;
         sw += vw;
-        b0 += mw;
+        b0 += mb * w;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           swr[a] += vw * r[a];
           sfr[a] += vf * r[a];
-          bf[a] += mf * r[a];
+          bf[a] += mb * f * r[a];
         }
         sfrr[0] += vf * r[0] * r[0];
         sfrr[1] += vf * r[0] * r[1];
@@ -234,9 +262,16 @@ hipError_t launch_mdbc(const KParams& kp, int64_t n, const sph_state& s, const u
   const WsLayout L = ws_layout(n);
   float4* pr = ws_ptr<float4>(ws, L.view_pr);
   float4* vp = ws_ptr<float4>(ws, L.view_vp);
+  WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
+  // the work list lives in the sort's key buffer, free once the cells are
+  // binned (sph_bin_cells must not run between this and the next launch)
+  uint32_t* list = ws_ptr<uint32_t>(ws, L.keyA);
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-#define SPH_MDBC(D, RR) \
-  hipLaunchKernelGGL((k_mdbc<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, s, cell_start, pr, vp)
+  hipLaunchKernelGGL(k_zero_wall_count, dim3(1), dim3(64), 0, st, hdr);
+  hipLaunchKernelGGL(k_wall_list, dim3(grid), dim3(kBlock), 0, st, n, s.type, list, hdr);
+#define SPH_MDBC(D, RR)                                                                    \
+  hipLaunchKernelGGL((k_mdbc<D, RR>), dim3(grid), dim3(kBlock), 0, st, kp, n, s, cell_start, \
+                     pr, vp, list, hdr)
   if (kp.dim == 2) {
     if (kp.cell_div == 1) SPH_MDBC(2, 1); else SPH_MDBC(2, 2);
   } else {
