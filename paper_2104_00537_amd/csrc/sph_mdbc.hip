@@ -179,44 +179,65 @@ __global__ __launch_bounds__(kBlock) void k_mdbc(KParams kp, int64_t n, sph_stat
       const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const uint32_t j1 = cstart[row + x1 + 1];
       const float ys = yg - (float)dy * cs, zs = zg - (float)dz * cs;
-      for (uint32_t j = cstart[row + x0]; j < j1; ++j) {
-        const float4 pb = pr[j];
-        if (!(pb.w > 0.f)) continue;  // fluid particles only
-        const float ex = (float)(int32_t)(xg - __float_as_uint(pb.x)) * kp.unit_x_f;
-        const float ey1 = ys - pb.y, ez1 = DIM == 3 ? zs - pb.z : 0.f;
-        if (!(ex * ex + ey1 * ey1 + ez1 * ez1 < pre2)) continue;
-        double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+      // groups of 4 candidates: their views are loaded together (padded), the
+      // screened ones then load their FP64 positions and velocities together
+      for (uint32_t j = cstart[row + x0]; j < j1; j += 4) {
+        const float4* q = pr + j;
+        float4 pb[4];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          r[d] = s.pos[d * n + j] - g[d];
-          r2 += r[d] * r[d];
-        }
-        if (!(r2 < kp.support2)) continue;
-        double w, f;
-        kernel_wf64(kp, sqrt(r2), w, f);
-        const double mb = kp.mass_f;
-        const double vb = mb / (double)pb.w;
-        const double vw = vb * w, vf = vb * f;
-        sw += vw;
-        b0 += mb * w;
+        for (int u = 0; u < 4; ++u) pb[u] = q[u];
+        bool hit[4];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          swr[a] += vw * r[a];
-          sfr[a] += vf * r[a];
-          bf[a] += mb * f * r[a];
+        for (int u = 0; u < 4; ++u) {
+          const float ex = (float)(int32_t)(xg - __float_as_uint(pb[u].x)) * kp.unit_x_f;
+          const float ey1 = ys - pb[u].y, ez1 = DIM == 3 ? zs - pb[u].z : 0.f;
+          hit[u] = j + u < j1 && pb[u].w > 0.f && ex * ex + ey1 * ey1 + ez1 * ez1 < pre2;
         }
-        sfrr[0] += vf * r[0] * r[0];
-        sfrr[1] += vf * r[0] * r[1];
-        sfrr[3] += vf * r[1] * r[1];
-        if (DIM == 3) {
-          sfrr[2] += vf * r[0] * r[2];
-          sfrr[4] += vf * r[1] * r[2];
-          sfrr[5] += vf * r[2] * r[2];
+        double pbx[4][3];
+        float4 vb4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (hit[u]) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) pbx[u][d] = s.pos[d * n + j + u];
+            vb4[u] = vp[j + u];
+          }
         }
-        const float4 v = vp[j];
-        sv[0] += vw * (double)v.x;
-        sv[1] += vw * (double)v.y;
-        if (DIM == 3) sv[2] += vw * (double)v.z;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!hit[u]) continue;
+          double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            r[d] = pbx[u][d] - g[d];
+            r2 += r[d] * r[d];
+          }
+          if (!(r2 < kp.support2)) continue;
+          double w, f;
+          kernel_wf64(kp, sqrt(r2), w, f);
+          const double mb = kp.mass_f;
+          const double vb = mb / (double)pb[u].w;
+          const double vw = vb * w, vf = vb * f;
+          sw += vw;
+          b0 += mb * w;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            swr[a] += vw * r[a];
+            sfr[a] += vf * r[a];
+            bf[a] += mb * f * r[a];
+          }
+          sfrr[0] += vf * r[0] * r[0];
+          sfrr[1] += vf * r[0] * r[1];
+          sfrr[3] += vf * r[1] * r[1];
+          if (DIM == 3) {
+            sfrr[2] += vf * r[0] * r[2];
+            sfrr[4] += vf * r[1] * r[2];
+            sfrr[5] += vf * r[2] * r[2];
+          }
+          sv[0] += vw * (double)vb4[u].x;
+          sv[1] += vw * (double)vb4[u].y;
+          if (DIM == 3) sv[2] += vw * (double)vb4[u].z;
+        }
       }
     }
   }
