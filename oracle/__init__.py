@@ -51,6 +51,13 @@ class OrcParams(C.Structure):
     ]
 
 
+class OrcBody(C.Structure):
+    _fields_ = [
+        ("first", C.c_int64), ("count", C.c_int64), ("mass", C.c_double),
+        ("center", C.c_double * 3), ("vel", C.c_double * 3), ("omega", C.c_double * 3),
+    ]
+
+
 _lib = None
 
 
@@ -90,7 +97,12 @@ def lib():
         L.orc_run.restype = C.c_int32
         L.orc_run.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(C.c_double),
-                              C.c_void_p, P(C.c_uint64)]
+                              C.c_void_p, P(C.c_uint64), C.c_void_p, C.c_int32]
+        L.orc_body_forces.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                      P(OrcBody), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_body_step.restype = C.c_int32
+        L.orc_body_step.argtypes = [P(OrcParams), C.c_int64, C.c_int32, C.c_double,
+                                    P(OrcBody), P(OrcBody)] + [C.c_void_p] * 7
         L.orc_mdbc.argtypes = [P(OrcParams), C.c_int64] + [C.c_void_p] * 7
         _lib = L
     return _lib
@@ -232,10 +244,66 @@ def _normal_arg(cp, normal, n):
     return None
 
 
-def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0, normal=None):
+def body(first, count, mass, center, vel=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0)) -> OrcBody:
+    """A floating body over particles [first, first + count) (Section 3.2)."""
+    b = OrcBody()
+    b.first, b.count, b.mass = int(first), int(count), float(mass)
+    for k in range(3):
+        b.center[k] = float(center[k]) if k < len(center) else 0.0
+        b.vel[k] = float(vel[k]) if k < len(vel) else 0.0
+        b.omega[k] = float(omega[k]) if k < len(omega) else 0.0
+    return b
+
+
+def body_dict(b: OrcBody) -> dict:
+    return dict(first=int(b.first), count=int(b.count), mass=float(b.mass),
+                center=np.array(b.center[:]), vel=np.array(b.vel[:]),
+                omega=np.array(b.omega[:]))
+
+
+def _bodies_arg(bodies):
+    if not bodies:
+        return None, 0
+    arr = (OrcBody * len(bodies))()
+    for k, b in enumerate(bodies):
+        arr[k] = b if isinstance(b, OrcBody) else body(**b)
+    return arr, len(bodies)
+
+
+def body_forces(cp, pos, ace, b):
+    """(force [3], torque [3], inertia [3, 3]) of body b (Eq. 48-49): the
+    fluid force sum_k m_B dv_k/dt, its torque about the centre and the
+    inertia tensor about the centre (2-D: torque[0], inertia[0, 0])."""
+    pos, ace = _f64(pos), _f64(ace)
+    f, tq, inertia = np.zeros(3), np.zeros(3), np.zeros(9)
+    bb = b if isinstance(b, OrcBody) else body(**b)
+    p = params(cp)
+    lib().orc_body_forces(C.byref(p), pos.shape[1], _ptr(pos), _ptr(ace), C.byref(bb),
+                          _ptr(f), _ptr(tq), _ptr(inertia))
+    return f, tq, inertia.reshape(3, 3)
+
+
+def body_step(cp, phase, dt, b, b_n, pos_n, pos, vel, ptype, ace):
+    """One phase of a floating body's symplectic update (orc_body_step).
+    b, b_n: OrcBody (updated in place; phase 0 writes b_n).  Returns
+    (pos, vel, force, torque, status) with the body's particles moved."""
+    pos_n = _f64(pos_n)
+    pos, vel = _f64(pos).copy(), _f64(vel).copy()
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    ace = _f64(ace)
+    f, tq = np.zeros(3), np.zeros(3)
+    p = params(cp)
+    st = lib().orc_body_step(C.byref(p), pos.shape[1], int(phase), float(dt), C.byref(b),
+                             C.byref(b_n), _ptr(pos_n), _ptr(pos), _ptr(vel), _ptr(ptype),
+                             _ptr(ace), _ptr(f), _ptr(tq))
+    return pos, vel, f, tq, int(st)
+
+
+def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0, normal=None, bodies=None):
     """nsteps full symplectic steps.  Returns dict with pos, vel, rho, type,
-    t, dt history, interaction count and status.  normal: ghost vectors of
-    the wall particles (needed with modified DBC)."""
+    t, dt history, interaction count, status and the bodies' final states.
+    normal: ghost vectors of the wall particles (needed with modified DBC);
+    bodies: floating bodies (OrcBody or body() keyword dicts)."""
     pos, vel, rho = _f64(pos).copy(), _f64(vel).copy(), _f64(rho).copy()
     ptype = np.ascontiguousarray(ptype, dtype=np.uint8).copy()
     t = C.c_double(float(t0))
@@ -243,11 +311,14 @@ def run(cp, pos, vel, rho, ptype, nsteps, t0=0.0, normal=None):
     inter = C.c_uint64(0)
     p = params(cp)
     nrm = _normal_arg(cp, normal, rho.shape[0])
+    barr, nb = _bodies_arg(bodies)
     st = lib().orc_run(C.byref(p), rho.shape[0], _ptr(pos), _ptr(vel), _ptr(rho),
                        _ptr(ptype), _ptr(nrm) if nrm is not None else None, int(nsteps),
-                       C.byref(t), _ptr(dts), C.byref(inter))
+                       C.byref(t), _ptr(dts), C.byref(inter),
+                       C.cast(barr, C.c_void_p) if nb else None, nb)
     return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
-                dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
+                dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st),
+                bodies=[body_dict(barr[k]) for k in range(nb)])
 
 
 def verlet(cp, dt, t, mode, pos, vel, rho, vel_prev, rho_prev, ptype, ace, arho):

@@ -17,8 +17,10 @@
 #define ORC_EXCLUDED 0x80u
 #define ORC_FLUID 0u
 #define ORC_MOVING 2u
+#define ORC_FLOATING 3u
 
 static int is_fluid(uint8_t t) { return (t & 0x7fu) == ORC_FLUID; }
+static int is_floating(uint8_t t) { return (t & 0x7fu) == ORC_FLOATING; }
 static int is_excluded(uint8_t t) { return (t & ORC_EXCLUDED) != 0; }
 
 /* Normalisation alpha_D of the Wendland C2 kernel, Eq. 11: 7/(4 pi h^2) in
@@ -184,6 +186,16 @@ static double particle_mass(const orc_params* p, uint8_t t) {
  *  a wall (Eq. 36): drho_a/dt = rho_a sum_{b in F} (m_b/rho_b) v_ab.grad_a W_ab
  *  and no momentum sum (its motion is imposed, Eq. 37).
  *
+ *  a floating particle (type 3, Section 3.2): the density of a wall (Eq. 36)
+ *  and, by Eq. 47, the momentum sum of a fluid target taken over its fluid
+ *  neighbours only and without gravity (which acts on the whole body, see
+ *  orc_body_step):
+ *    dv_a/dt = - sum_{b in F} m_b [(P_a + P_b)/(rho_a rho_b) + Pi_ab] grad_a W_ab.
+ *  In every sum a floating particle b is a boundary particle of mass
+ *  mass_bound (K is a subset of B); then the force m_B dv_a/dt on a floating
+ *  particle is exactly opposite to the force its fluid neighbours receive
+ *  from it.  visc_a stays 0 (Eq. 35 runs over fluid only).
+ *
  * Readings: the mean in Eq. 21 is (x_a + x_b)/2; eta^2 = eta2 (the case uses
  * 0.001 h^2); c_a and cbar_ab are the constant c0; psi_ab of Eq. 18 is taken
  * along r_ba = r_b - r_a, the diffusive direction of the Molteni-Colagrossi
@@ -218,6 +230,7 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
      * from Eq. 36: wall targets get no sums */
     if (!is_excluded(ta) && (is_fluid(ta) || p->boundary == 0)) {
       const int fa = is_fluid(ta);
+      const int ka = is_floating(ta);
       const double rho_a = rho[a];
       const double p_a = orc_pressure(p, rho_a);
       for (int64_t b = 0; b < n; ++b) {
@@ -241,7 +254,7 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
         const double vol_b = m_b / rho_b;
         cont += vol_b * vr * fab;  /* (m_b/rho_b) v_ab . grad_a W_ab */
         count++;
-        if (fa) {
+        if (fa || ka) {
           const double p_b = orc_pressure(p, rho_b);
           const double mu = h * vr / (r2 + p->eta2);
           const double rhobar = 0.5 * (rho_a + rho_b);
@@ -255,8 +268,8 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
           }
           const double coef = m_b * ((p_a + p_b) / (rho_a * rho_b) + pi_ab);
           for (int k = 0; k < dim; ++k) acc[k] -= coef * fab * dx[k];
-          if (fabs(mu) > vmax) vmax = fabs(mu);
-          if (p->ddt && fb) {
+          if (fa && fabs(mu) > vmax) vmax = fabs(mu);
+          if (fa && p->ddt && fb) {
             double drho = rho_b - rho_a;
             if (p->ddt == 2) drho -= hydrostatic_drho(p, dx[dim - 1]);
             const double psi_dot_grad = 2.0 * drho * (-fab);
@@ -517,6 +530,162 @@ void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mod
   }
 }
 
+/* Floating bodies, Section 3.2.  A body is a set of floating particles
+ * (type 3), here particles [first, first + count) of the arrays, moving as
+ * one rigid object of total mass M, centre R0, velocity V and angular
+ * velocity Omega.
+ *
+ * Force, torque and inertia (Eq. 48-49).  Each particle k contributes the
+ * force m_B dv_k/dt, with dv_k/dt from orc_interact (Eq. 47) and m_B the
+ * boundary particle mass it carries in the SPH sums, so the fluid part of
+ * the force is F = sum_k m_B dv_k/dt and its torque about R0 is
+ * T = sum_k m_B (r_k - R0) x dv_k/dt.  The body's own mass M sets its
+ * inertia: it is shared equally by its particles, so the inertia tensor
+ * about R0 is I = sum_k (M/count) (|r'|^2 1 - r' r'^T) with r' = r_k - R0.
+ * In 2-D the rotation is about the axis normal to the plane of the two
+ * components: Omega, T and I are scalars (stored in [0]), T = sum m_B
+ * (r'_0 a_1 - r'_1 a_0) and I = sum (M/count)|r'|^2, so that a positive
+ * Omega turns the first axis towards the second.
+ * force [dim], torque [3] (2-D: [0]), inertia [9] row-major (2-D: [0]).
+ * Excluded particles are left out. */
+void orc_body_forces(const orc_params* p, int64_t n, const double* pos, const double* ace,
+                     const orc_body* b, double* force, double* torque, double* inertia) {
+  const int dim = p->dim;
+  const double mb = p->mass_bound;
+  const double mi = b->count > 0 ? b->mass / (double)b->count : 0.0;
+  for (int k = 0; k < 3; ++k) { force[k] = 0.0; torque[k] = 0.0; }
+  for (int k = 0; k < 9; ++k) inertia[k] = 0.0;
+  for (int64_t j = b->first; j < b->first + b->count; ++j) {
+    double r[3] = {0.0, 0.0, 0.0}, a[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) {
+      r[k] = pos[k * n + j] - b->center[k];
+      a[k] = ace[k * n + j];
+      force[k] += mb * a[k];
+    }
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    if (dim == 2) {
+      torque[0] += mb * (r[0] * a[1] - r[1] * a[0]);
+      inertia[0] += mi * r2;
+    } else {
+      torque[0] += mb * (r[1] * a[2] - r[2] * a[1]);
+      torque[1] += mb * (r[2] * a[0] - r[0] * a[2]);
+      torque[2] += mb * (r[0] * a[1] - r[1] * a[0]);
+      for (int u = 0; u < 3; ++u)
+        for (int v = 0; v < 3; ++v)
+          inertia[u * 3 + v] += mi * ((u == v ? r2 : 0.0) - r[u] * r[v]);
+    }
+  }
+}
+
+/* Rotation by the rotation vector th (3-D: axis th/|th|, angle |th|,
+ * right-handed) of the vector x, by Rodrigues' formula
+ * x' = x cos(phi) + (e x x) sin(phi) + e (e.x)(1 - cos(phi)), e the unit
+ * axis; in 2-D the rotation by the angle th[0] in the plane. */
+static void rotate(int dim, const double* th, const double* x, double* out) {
+  if (dim == 2) {
+    const double c = cos(th[0]), s = sin(th[0]);
+    out[0] = c * x[0] - s * x[1];
+    out[1] = s * x[0] + c * x[1];
+    return;
+  }
+  const double phi = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+  if (phi == 0.0) {
+    for (int k = 0; k < 3; ++k) out[k] = x[k];
+    return;
+  }
+  const double e[3] = {th[0] / phi, th[1] / phi, th[2] / phi};
+  const double c = cos(phi), s = sin(phi);
+  const double ex[3] = {e[1] * x[2] - e[2] * x[1], e[2] * x[0] - e[0] * x[2],
+                        e[0] * x[1] - e[1] * x[0]};
+  const double ed = e[0] * x[0] + e[1] * x[1] + e[2] * x[2];
+  for (int k = 0; k < 3; ++k) out[k] = x[k] * c + ex[k] * s + e[k] * ed * (1.0 - c);
+}
+
+/* Omega x r (Eq. 50); 2-D: omega[0] (-r_1, r_0). */
+static void omega_cross(int dim, const double* om, const double* r, double* out) {
+  if (dim == 2) {
+    out[0] = -om[0] * r[1];
+    out[1] = om[0] * r[0];
+    return;
+  }
+  out[0] = om[1] * r[2] - om[2] * r[1];
+  out[1] = om[2] * r[0] - om[0] * r[2];
+  out[2] = om[0] * r[1] - om[1] * r[0];
+}
+
+/* One phase of the symplectic update of a floating body (Section 2.5.2
+ * applied to Eq. 48-50), after orc_predictor / orc_corrector of the same
+ * phase (which leave floating particles in place and update their density
+ * as walls).  pos holds the current positions (state n in the predictor,
+ * n+1/2 in the corrector) and b the current body state; pos_n and b_n hold
+ * state n (phase 0 writes b_n).  With the linear and angular accelerations
+ *   A = F/M + g (gravity acts on the body as a whole),
+ *   alpha = I^-1 T (Eq. 49 as printed, I of the current configuration),
+ * evaluated from the current state:
+ *   phase 0: V = V^n + dt/2 A, Omega = Omega^n + dt/2 alpha,
+ *            R0 = R0^n + dt/2 V^n, rotation by dt/2 Omega^n;
+ *   phase 1: V = V^n + dt A, Omega = Omega^n + dt alpha,
+ *            R0 = R0^n + dt (V + V^n)/2, rotation by dt (Omega + Omega^n)/2,
+ * the position and velocity updates of Eq. 33 for the centre and the
+ * orientation.  Every particle then takes the rigid motion from state n,
+ *   r_k = R0 + Rot (r_k^n - R0^n),   v_k = V + Omega x (r_k - R0)  (Eq. 50).
+ * force / torque (nullable) receive F and T.  Returns 0, or 1 if the
+ * inertia tensor is singular. */
+int32_t orc_body_step(const orc_params* p, int64_t n, int32_t phase, double dt, orc_body* b,
+                      orc_body* b_n, const double* pos_n, double* pos, double* vel,
+                      const uint8_t* type, const double* ace, double* force, double* torque) {
+  const int dim = p->dim;
+  double F[3], T[3], I[9];
+  orc_body_forces(p, n, pos, ace, b, F, T, I);
+  if (force) for (int k = 0; k < 3; ++k) force[k] = F[k];
+  if (torque) for (int k = 0; k < 3; ++k) torque[k] = T[k];
+  double A[3] = {0.0, 0.0, 0.0}, al[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) A[k] = F[k] / b->mass + p->gravity[k];
+  if (dim == 2) {
+    if (!(I[0] > 0.0)) return 1;
+    al[0] = T[0] / I[0];
+  } else {
+    double M[9], det = 0.0;
+    for (int k = 0; k < 9; ++k) M[k] = I[k];
+    for (int k = 0; k < 3; ++k) al[k] = T[k];
+    if (!solve_small(3, M, al, &det) || !(fabs(det) > 0.0)) return 1;
+  }
+  const int nw = dim == 2 ? 1 : 3;
+  double th[3] = {0.0, 0.0, 0.0};
+  if (phase == 0) {
+    *b_n = *b;
+    for (int k = 0; k < dim; ++k) {
+      b->vel[k] = b_n->vel[k] + 0.5 * dt * A[k];
+      b->center[k] = b_n->center[k] + 0.5 * dt * b_n->vel[k];
+    }
+    for (int k = 0; k < nw; ++k) {
+      b->omega[k] = b_n->omega[k] + 0.5 * dt * al[k];
+      th[k] = 0.5 * dt * b_n->omega[k];
+    }
+  } else {
+    for (int k = 0; k < dim; ++k) {
+      b->vel[k] = b_n->vel[k] + dt * A[k];
+      b->center[k] = b_n->center[k] + dt * 0.5 * (b->vel[k] + b_n->vel[k]);
+    }
+    for (int k = 0; k < nw; ++k) {
+      b->omega[k] = b_n->omega[k] + dt * al[k];
+      th[k] = dt * 0.5 * (b->omega[k] + b_n->omega[k]);
+    }
+  }
+  for (int64_t j = b->first; j < b->first + b->count; ++j) {
+    if (is_excluded(type[j])) continue;
+    double r[3] = {0.0, 0.0, 0.0}, q[3], w[3];
+    for (int k = 0; k < dim; ++k) r[k] = pos_n[k * n + j] - b_n->center[k];
+    rotate(dim, th, r, q);
+    omega_cross(dim, b->omega, q, w);
+    for (int k = 0; k < dim; ++k) {
+      pos[k * n + j] = b->center[k] + q[k];
+      vel[k * n + j] = b->vel[k] + w[k];
+    }
+  }
+  return 0;
+}
+
 /* Marks particles outside the cell grid as excluded (they leave the
  * computation for good, as the GPU path's binning does). */
 static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
@@ -531,7 +700,9 @@ static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
  * corrector -> t += dt.  dt_hist[s] receives each step's dt (nullable);
  * *interactions accumulates the pair count of every PI (nullable).
  * Returns 0; 1 if a density became non-finite or non-positive; 2 if dt is
- * not a positive finite number (e.g. no fluid particle is left). */
+ * not a positive finite number (e.g. no fluid particle is left); 3 if a
+ * floating body's inertia is singular.  bodies[n_bodies] (nullable): the
+ * floating bodies, advanced by orc_body_step after each update phase. */
 /* With modified DBC (boundary 1, normal required) each PI is preceded by
  * orc_mdbc: the wall densities it gives replace the state's, and the
  * interaction sees its wall velocities. */
@@ -550,7 +721,7 @@ static void mdbc_before_pi(const orc_params* p, int64_t n, const double* pos,
 
 int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
                 double* rho, uint8_t* type, const double* normal, int32_t nsteps, double* t,
-                double* dt_hist, uint64_t* interactions) {
+                double* dt_hist, uint64_t* interactions, orc_body* bodies, int32_t n_bodies) {
   const int dim = p->dim;
   size_t nd = (size_t)dim * (size_t)(n > 0 ? n : 1);
   double* ace = (double*)calloc(nd, sizeof(double));
@@ -561,6 +732,8 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
   double* vel_n = (double*)calloc(nd, sizeof(double));
   double* rho_n = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* vel_pi = (double*)calloc(nd, sizeof(double));
+  orc_body* bodies_n =
+      (orc_body*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(orc_body));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
     mark_excluded(p, n, pos, type);
@@ -572,18 +745,26 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
     if (dt_hist) dt_hist[s] = dt;
     if (!(dt > 0.0) || !isfinite(dt)) { status = 2; break; }
     orc_predictor(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
+    for (int32_t k = 0; k < n_bodies; ++k)
+      if (orc_body_step(p, n, 0, dt, &bodies[k], &bodies_n[k], pos_n, pos, vel, type, ace,
+                        NULL, NULL))
+        status = 3;
     mark_excluded(p, n, pos, type);
     mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
     orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
     for (int64_t a = 0; a < n; ++a) count += nbr[a];
     orc_corrector(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
+    for (int32_t k = 0; k < n_bodies; ++k)
+      if (orc_body_step(p, n, 1, dt, &bodies[k], &bodies_n[k], pos_n, pos, vel, type, ace,
+                        NULL, NULL))
+        status = 3;
     *t += dt;
     if (interactions) *interactions += count;
     for (int64_t a = 0; a < n; ++a)
       if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
   }
   free(ace); free(arho); free(visc); free(nbr);
-  free(pos_n); free(vel_n); free(rho_n); free(vel_pi);
+  free(pos_n); free(vel_n); free(rho_n); free(vel_pi); free(bodies_n);
   return status;
 }
 

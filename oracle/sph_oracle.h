@@ -7,7 +7,10 @@
  * 17, 18), momentum with artificial viscosity (Eq. 21, 22), Tait equation of
  * state (Eq. 28), symplectic position-Verlet update (Eq. 33, 34), variable
  * time step (Eq. 35), dynamic boundary particles (Eq. 36, 37), and the
- * cell-linked list of Section 5.1 (cell keys, stable sort, cell ranges).
+ * cell-linked list of Section 5.1 (cell keys, stable sort, cell ranges),
+ * and the variants: cubic spline (Eq. 10), laminar viscosity (Eq. 23),
+ * Fourtakas diffusion (Eq. 19-20), Verlet (Eq. 30-31), modified DBC
+ * (Eq. 38-39) and rigid floating bodies (Eq. 47-50).
  *
  * Neighbours are found by brute force over all particle pairs.  Only the test
  * suite, the smoke check and the CPU-baseline leg of the benchmark use this
@@ -16,8 +19,8 @@
  * Conventions shared with the inputs (not with any GPU code):
  *  - arrays are component-major: component k of particle i is x[k*n + i];
  *    2-D cases store (x, z), the vertical axis last;
- *  - particle type: 0 fluid, 1 fixed wall, 2 moving wall; bit 0x80 marks a
- *    particle excluded from the domain (outside the cell grid);
+ *  - particle type: 0 fluid, 1 fixed wall, 2 moving wall, 3 floating; bit
+ *    0x80 marks a particle excluded from the domain (outside the cell grid);
  *  - the key of a particle outside the grid is ncell_total.
  */
 #ifndef SPH_ORACLE_H
@@ -48,6 +51,17 @@ typedef struct orc_params {
   int32_t pad2;
 } orc_params;
 
+/* A rigid floating body (Section 3.2): particles [first, first + count) of
+ * the arrays, all of type 3.  2-D: omega[0] is the angular velocity in the
+ * plane (positive turns the first axis towards the second). */
+typedef struct orc_body {
+  int64_t first, count;
+  double mass;             /* M, the body's total mass */
+  double center[3];        /* R0, its centre of mass */
+  double vel[3];           /* V, the velocity of R0 */
+  double omega[3];         /* Omega, the angular velocity */
+} orc_body;
+
 double orc_wendland_w(double r, double h, int32_t dim);
 double orc_wendland_fab(double r, double h, int32_t dim);
 double orc_cubic_w(double r, double h, int32_t dim);
@@ -76,7 +90,12 @@ void orc_corrector(const orc_params* p, int64_t n, double dt, double t,
                    const double* vel_n, const double* rho_n);
 int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
                 double* rho, uint8_t* type, const double* normal, int32_t nsteps, double* t,
-                double* dt_hist, uint64_t* interactions);
+                double* dt_hist, uint64_t* interactions, orc_body* bodies, int32_t n_bodies);
+void orc_body_forces(const orc_params* p, int64_t n, const double* pos, const double* ace,
+                     const orc_body* b, double* force, double* torque, double* inertia);
+int32_t orc_body_step(const orc_params* p, int64_t n, int32_t phase, double dt, orc_body* b,
+                      orc_body* b_n, const double* pos_n, double* pos, double* vel,
+                      const uint8_t* type, const double* ace, double* force, double* torque);
 
 void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mode,
                 double* pos, double* vel, double* rho, double* vel_p, double* rho_p,

@@ -30,13 +30,13 @@ from typing import Optional, Tuple
 
 import numpy as np
 
-FLUID, BOUND_FIXED, BOUND_MOVING = 0, 1, 2
+FLUID, BOUND_FIXED, BOUND_MOVING, FLOATING = 0, 1, 2, 3
 EXCLUDED = 0x80
 GRAVITY = 9.81
 
 __all__ = ["CaseParams", "Case", "dam_break_2d", "dam_break_3d", "sloshing_3d",
-           "block_case", "random_serving_case", "FLUID", "BOUND_FIXED",
-           "BOUND_MOVING", "EXCLUDED", "GRAVITY"]
+           "block_case", "random_serving_case", "floating_box", "FLUID", "BOUND_FIXED",
+           "BOUND_MOVING", "FLOATING", "EXCLUDED", "GRAVITY"]
 
 
 @dataclass
@@ -91,6 +91,10 @@ class Case:
     # ghost node (its mirror image across the wall face, Section 2.6.2);
     # zero for fluid particles
     normal: Optional[np.ndarray] = None
+    # floating bodies (Section 3.2): dicts with id_first, count (the body owns
+    # particles [id_first, id_first + count), of type FLOATING), mass, center,
+    # vel, omega (3 components each; 2-D uses omega[0])
+    bodies: Optional[list] = None
 
     @property
     def n(self) -> int:
@@ -328,3 +332,78 @@ def _sloshing_2d(dp, fill, seed, tank=(2.0, 1.0), accel=0.05 * GRAVITY,
                    wall_type=BOUND_MOVING, motion_amp=accel, motion_omega=omega,
                    cell_div=cell_div, x_sub=x_sub, meta=dict(tank=tank, fill=fill),
                    tank=(nxt, nzt))
+
+
+def floating_box(dim=2, dp=0.02, tank=None, column=None, layer=0.15, box=None,
+                 box_x=0.9, box_density=500.0, seed=0, cell_div=1, x_sub=1) -> Case:
+    """A dam-break column released into a tank that holds a still water
+    layer, with a rigid box floating on the layer (Section 3.2: a
+    fluid-driven object).
+
+    The box is a solid block of lattice cells (its particles are FLOATING,
+    ids right after the fluid) of density ``box_density``, centred at
+    x = box_x (and mid-width in 3-D) with its bottom at its equilibrium draft
+    box_density / rho0 times its height below the layer surface; fluid cells
+    it covers are removed.  Fluid and box particles start at the hydrostatic
+    density below their own free surface (column or layer); the speed of
+    sound is set by the column height.  The box stays clear of the walls
+    for the first second or so; contact with walls is not modelled."""
+    if tank is None:
+        tank = (1.6, 0.8) if dim == 2 else (1.6, 0.6, 0.6)
+    if column is None:
+        column = (0.4, 0.5) if dim == 2 else (0.4, 0.6, 0.4)
+    if box is None:
+        box = (0.16, 0.10) if dim == 2 else (0.16, 0.16, 0.12)
+    nt = [int(round(v / dp)) for v in tank]
+    nc = [int(round(v / dp)) for v in column]
+    nb = [int(round(v / dp)) for v in box]
+    nzl = int(round(layer / dp))
+    # lattice ranges: x, (y), z
+    if dim == 2:
+        col = _grid((0, nc[0]), (0, nc[1]))
+        lay = _grid((nc[0], nt[0]), (0, nzl))
+    else:
+        col = _grid((0, nc[0]), (0, nt[1]), (0, nc[2]))
+        lay = _grid((nc[0], nt[0]), (0, nt[1]), (0, nzl))
+    draft = int(round(box_density / 1000.0 * nb[-1]))
+    bx0 = int(round(box_x / dp)) - nb[0] // 2
+    bz0 = nzl - draft
+    if dim == 2:
+        bidx = _grid((bx0, bx0 + nb[0]), (bz0, bz0 + nb[1]))
+    else:
+        by0 = nt[1] // 2 - nb[1] // 2
+        bidx = _grid((bx0, bx0 + nb[0]), (by0, by0 + nb[1]), (bz0, bz0 + nb[2]))
+    lo_b = bidx.min(axis=1)
+    hi_b = bidx.max(axis=1)
+    inside = np.all((lay >= lo_b[:, None]) & (lay <= hi_b[:, None]), axis=0)
+    lay = lay[:, ~inside]
+    fluid = np.concatenate([col, lay], axis=1)
+    walls = _walls(dim, nt[0], nt[1] if dim == 3 else 1, nt[-1], closed_top=False)
+    m = 2.0 * dp + 1e-3 * dp
+    lo = tuple(-m for _ in range(dim))
+    top = max(nt[-1] * dp, 2.5 * nc[-1] * dp) + m
+    hi = tuple([nt[k] * dp + m for k in range(dim - 1)] + [top])
+    tank_cells = tuple(nt)
+    case = _finish(f"floating_box_{dim}d", dim, dp, fluid, np.concatenate([bidx, walls], axis=1),
+                   nc[-1] * dp, lo, hi, seed, cell_div=cell_div, x_sub=x_sub,
+                   meta=dict(tank=tank, column=column, layer=layer, box=box,
+                             box_density=box_density), tank=tank_cells)
+    nf = fluid.shape[1]
+    nbox = bidx.shape[1]
+    case.type[nf: nf + nbox] = FLOATING
+    case.normal[:, nf: nf + nbox] = 0.0
+    # hydrostatic density below each particle's own free surface: the layer
+    # surface for the layer and the box, the column top for the column
+    rho0 = case.params.rho0
+    b_tait = case.params.c0 ** 2 * rho0 / case.params.gamma
+    z = case.pos[dim - 1]
+    in_layer = np.zeros(case.n, bool)
+    in_layer[col.shape[1]: nf + nbox] = True
+    depth = np.maximum(nzl * dp - z, 0.0)
+    rho_layer = rho0 * np.power(1.0 + rho0 * GRAVITY * depth / b_tait, 1.0 / case.params.gamma)
+    case.rho[in_layer] = rho_layer[in_layer].astype(np.float32)
+    center = case.pos[:, nf: nf + nbox].mean(axis=1)
+    c3 = [float(v) for v in center] + [0.0] * (3 - dim)
+    case.bodies = [dict(id_first=nf, count=nbox, mass=box_density * nbox * dp ** dim,
+                        center=tuple(c3), vel=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0))]
+    return case
