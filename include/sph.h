@@ -17,6 +17,8 @@
  *                        dynamic boundary condition (Eq. 38-39), before a PI.
  *   sph_symplectic_step  SU: symplectic predictor / corrector (Eq. 33-34), with
  *                        imposed motion of moving walls (Eq. 37).
+ *   sph_floating_step    SU of rigid floating bodies (Section 3.2, Eq. 47-50),
+ *                        after each phase of sph_symplectic_step.
  *
  * A full step is: bin, interact, reduce_dt, predictor, bin (carrying the saved
  * state along), interact, corrector.
@@ -27,9 +29,10 @@
  *  - Arrays are structure-of-arrays and component-major: component k of
  *    particle i is x[k*n + i].  Positions are FP64, velocity and density FP32.
  *    2-D cases store (x, z) -- the vertical axis is always the last component.
- *  - Particle type (uint8): 0 fluid, 1 fixed wall, 2 moving wall; bit 0x80 is
- *    set by sph_bin_cells on particles outside the cell grid, which then take
- *    no part in the interaction or the update ("excluded").
+ *  - Particle type (uint8): 0 fluid, 1 fixed wall, 2 moving wall, 3 floating
+ *    (a particle of a rigid body, see sph_body); bit 0x80 is set by
+ *    sph_bin_cells on particles outside the cell grid, which then take no
+ *    part in the interaction or the update ("excluded").
  *  - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL means
  *    the default stream).  Calls on distinct workspaces are independent.
  *  - Every call returns an sph_status synchronously for argument and launch
@@ -59,6 +62,7 @@ enum {
   SPH_FLUID = 0,
   SPH_BOUND_FIXED = 1,
   SPH_BOUND_MOVING = 2,
+  SPH_FLOATING = 3,
   SPH_EXCLUDED = 0x80
 };
 
@@ -66,7 +70,11 @@ enum {
 enum {
   SPH_ERR_NONFINITE = 1u,   /* non-finite velocity, or density not in (0, inf) */
   SPH_ERR_EXCLUDED = 2u,    /* a particle left the cell grid and was excluded */
-  SPH_ERR_DT_FLOOR = 4u     /* dt fell below dt_floor, or is not finite */
+  SPH_ERR_DT_FLOOR = 4u,    /* dt fell below dt_floor, or is not finite */
+  SPH_ERR_FLOATING = 8u     /* sph_floating_step: a floating particle whose id is
+                               in no body's range, a body whose particles are
+                               not all present, body counts summing above n,
+                               or a singular inertia */
 };
 
 /* flags of sph_interact */
@@ -82,7 +90,8 @@ enum {
    * replace).  Velocities and densities are the stored FP32 values in both;
    * the outputs and the workspace partials are as in the production pass.
    * The arms take the default formulation only (Wendland kernel, artificial
-   * viscosity, ddt 0 or 1); other options are rejected with SPH_E_ARG. */
+   * viscosity, ddt 0 or 1, no floating bodies); other options are rejected
+   * with SPH_E_ARG. */
   SPH_INTERACT_F64 = 2u,
   SPH_INTERACT_ABS_F32 = 4u
 };
@@ -133,6 +142,11 @@ typedef struct sph_params {
                              viscosity (Eq. 23) with kinematic viscosity
                              visc_nu, in place of Pi_ab (Eq. 35 unchanged) */
   double visc_nu;         /* kinematic viscosity of the laminar term (>= 0) */
+  int32_t floating;       /* 1: the state holds floating particles (type 3);
+                             sph_interact then gives them the momentum sum of
+                             Eq. 47.  Needs boundary 0; with 0, particles of
+                             type 3 take the fixed-wall path. */
+  int32_t pad0;
 } sph_params;
 
 /* Particle state (SoA device arrays of n particles). */
@@ -184,7 +198,10 @@ sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in,
  *             arho[a] = rho_a sum_b (m_b/rho_b) v_ab.grad_a W_ab + D_a
  *             with D_a = 2 delta h c0 sum_{b fluid} (rho_b - rho_a)|F_ab| m_b/rho_b
  *             (the diffusive reading of Eq. 18) and P from Eq. 28;
- *   wall a:   arho[a] = rho_a sum_{b fluid} (m_b/rho_b) v_ab.grad_a W_ab, ace = 0.
+ *   wall a:   arho[a] = rho_a sum_{b fluid} (m_b/rho_b) v_ab.grad_a W_ab, ace = 0;
+ *   floating a (p->floating = 1): arho as a wall, and (Eq. 47)
+ *             ace[a] = - sum_{b fluid} m_b [(P_a+P_b)/(rho_a rho_b) + Pi_ab] grad_a W_ab
+ *             (no gravity; visc[a] = 0).
  *   ace[dim][n], arho[n]   out (FP32, sorted order; excluded particles get 0)
  *   visc[n]                out, nullable: max_b |h v_ab.r_ab|/(r_ab^2+eta^2)
  *   nbr_count[n]           out, nullable: pairs evaluated for a (all neighbours
@@ -262,6 +279,61 @@ sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const d
 sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                     const uint32_t* cell_start, void* ws, size_t ws_bytes, void* stream);
 
+/* Floating bodies (Section 3.2).  A body is a rigid object whose particles
+ * are the particles of type SPH_FLOATING with id in [id_first, id_first +
+ * count) (sph_state.id is required).  In every SPH sum its particles are
+ * boundary particles of mass mass_bound (Eq. 36 gives their density); each
+ * gets from sph_interact the momentum sum of a fluid particle over its fluid
+ * neighbours only, without gravity (Eq. 47), so that m_B dv_k/dt is exactly
+ * the reaction of the fluid to it.  The body moves as one rigid object
+ * (Eq. 48-50): its own mass M sets its inertia, gravity acts on it as a
+ * whole, and contact with walls or other bodies is not modelled.
+ * The table is an array of sph_body in DEVICE memory owned by the caller;
+ * sph_floating_step reads and advances it.  FP64 throughout; 2-D cases use
+ * components (x, z) in [0], [1] and the rotation in the plane is the scalar
+ * in [0] of omega and torque (positive turns the first axis towards the
+ * second). */
+#define SPH_MAX_BODIES 64
+
+typedef struct sph_body {
+  int64_t id_first;     /* first particle id of the body */
+  int64_t count;        /* its particle count (> 0) */
+  double mass;          /* M, the total mass of the body (> 0) */
+  double center[3];     /* R0, centre of mass */
+  double vel[3];        /* V, velocity of R0 */
+  double omega[3];      /* Omega, angular velocity */
+  double center_n[3];   /* state n, written by the predictor (phase 0) */
+  double vel_n[3];
+  double omega_n[3];
+  double force[3];      /* out: sum_k m_B dv_k/dt, the fluid force (Eq. 48) */
+  double torque[3];     /* out: sum_k m_B (r_k - R0) x dv_k/dt (Eq. 49) */
+} sph_body;
+
+/* One phase of the rigid-body update of n_bodies floating bodies, called
+ * right after sph_symplectic_step of the same phase on the same state (that
+ * call saved state n and advanced the floating particles' density as walls'
+ * but left their position and velocity).  ace is the interaction's output
+ * that the symplectic phase used.  Per body, from its particles in the
+ * current (sorted) state:
+ *   F = sum_k m_B ace_k, T = sum_k m_B (r_k - R0) x ace_k, and the inertia
+ *   tensor about R0, I = sum_k (M/count)(|r'|^2 1 - r' r'^T), r' = r_k - R0;
+ *   A = F/M + g, alpha = I^-1 T (Eq. 48-49);
+ *   phase 0: saves (R0, V, Omega) as state n, then V += dt/2 A,
+ *     Omega += dt/2 alpha, R0 += dt/2 V^n, rotation by dt/2 Omega^n;
+ *   phase 1: V = V^n + dt A, Omega = Omega^n + dt alpha,
+ *     R0 = R0^n + dt (V + V^n)/2, rotation by dt (Omega + Omega^n)/2;
+ *   each particle: r_k = R0 + Rot (r_k^n - R0^n) from saved->pos (state n),
+ *     v_k = V + Omega x (r_k - R0) (Eq. 50).
+ * Sums are taken in a fixed order (by particle id), so results do not
+ * depend on the particle order.  Sets SPH_ERR_FLOATING on the conditions
+ * listed with it.  The workspace's sort buffers hold the id map between the
+ * kernels of one call.  p->floating must be 1 and p->boundary 0;
+ * 1 <= n_bodies <= SPH_MAX_BODIES. */
+sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, const double* dt,
+                             sph_body* bodies, int32_t n_bodies, const sph_state* saved,
+                             sph_state* s, const float* ace, void* ws, size_t ws_bytes,
+                             void* stream);
+
 /* ---------------------------------------------------------------- batches --
  * Continuous batching: n_slots independent cases packed into one set of
  * arrays advance together through the calls below, each case ("slot") with
@@ -296,7 +368,7 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * table to device memory and sets batch->table before the calls below.  The
  * table stays valid while the slots keep their ranges.  Every slot must use
  * the same cell_div and the default formulation (kernel 0, viscosity 0, ddt
- * 0 or 1); otherwise SPH_E_ARG. */
+ * 0 or 1, boundary 0, no floating bodies); otherwise SPH_E_ARG. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
                               void* table_host, size_t table_bytes, sph_batch* batch);
 

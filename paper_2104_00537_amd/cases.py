@@ -59,6 +59,7 @@ class CaseParams:
     ddt: int = 1          # 0 none, 1 Molteni-Colagrossi (Eq. 18), 2 Fourtakas (Eq. 19-20)
     kernel: int = 0       # 0 Wendland C2 (Eq. 11), 1 cubic spline (Eq. 10)
     boundary: int = 0     # 0 DBC (Eq. 36), 1 modified DBC (Eq. 38-39)
+    floating: int = 0     # 1: the case has floating bodies (Section 3.2)
     viscosity: int = 0    # 0 artificial (Eq. 21), 1 laminar (Eq. 23)
     visc_nu: float = 1e-6  # kinematic viscosity of the laminar term (water)
     cell_div: int = 1
@@ -406,4 +407,5 @@ def floating_box(dim=2, dp=0.02, tank=None, column=None, layer=0.15, box=None,
     c3 = [float(v) for v in center] + [0.0] * (3 - dim)
     case.bodies = [dict(id_first=nf, count=nbox, mass=box_density * nbox * dp ** dim,
                         center=tuple(c3), vel=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0))]
+    case.params.floating = 1
     return case

@@ -66,6 +66,7 @@ KParams make_kparams(const sph_params& p) {
   k.eta2_f = (float)p.eta2;
   k.kernel = p.kernel;
   k.boundary = p.boundary;
+  k.floating = p.floating;
   k.viscosity = p.viscosity;
   k.inv_h_f = (float)(1.0 / p.h);
   k.klam_mf_f = (float)(4.0 * p.visc_nu * kfab * p.mass_fluid);
@@ -123,6 +124,8 @@ static bool params_ok(const sph_params* p) {
   if (p->ddt < 0 || p->ddt > 2) return false;
   if (p->kernel != 0 && p->kernel != 1) return false;
   if (p->boundary != 0 && p->boundary != 1) return false;
+  if (p->floating != 0 && p->floating != 1) return false;
+  if (p->floating == 1 && p->boundary != 0) return false;
   if (p->viscosity != 0 && p->viscosity != 1) return false;
   if (!(p->visc_nu >= 0) || !isfinite(p->visc_nu)) return false;
   for (int k = 0; k < 3; ++k)
@@ -189,7 +192,7 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
   if ((flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) &&
-      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2))
+      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   const KParams kp = make_kparams(*p);
@@ -241,6 +244,21 @@ sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t
   return hip_status(launch_mdbc(make_kparams(*p), n, *s, key, cell_start, ws, (hipStream_t)stream));
 }
 
+sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, const double* dt,
+                             sph_body* bodies, int32_t n_bodies, const sph_state* saved,
+                             sph_state* s, const float* ace, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !dt || !ws || !bodies || p->floating != 1) return SPH_E_ARG;
+  if (phase != 0 && phase != 1) return SPH_E_ARG;
+  if (n_bodies < 1 || n_bodies > SPH_MAX_BODIES) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !s->id || !saved || !saved->pos || !ace))
+    return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state sv = n > 0 ? *saved : sph_state{}, st = n > 0 ? *s : sph_state{};
+  return hip_status(launch_floating(make_kparams(*p), n, phase, dt, bodies, n_bodies, sv, st, ace,
+                                    ws, (hipStream_t)stream));
+}
+
 int32_t sph_read_error(const void* ws) {
   if (!ws) return SPH_E_ARG;
   uint32_t v = 0;
@@ -284,7 +302,8 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
     if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
     // the batched interaction runs the default formulation (Wendland kernel,
     // artificial viscosity, ddt 0 or 1)
-    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->boundary != 0)
+    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->boundary != 0 ||
+        p->floating != 0)
       return SPH_E_ARG;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   if (i < n) {
     PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
     uint32_t c64 = 0;
     // with modified DBC the wall densities come from Eq. 38 (sph_mdbc): wall
     // targets take no sums
@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
       T.vx = va.x;
       T.vy = va.y;
       T.vz = va.z;
+      T.flt = GEN && kp.floating && is_floating(type[i]);
       const uint32_t k = key[i];
       const int cx = (int)(k % (uint32_t)kp.ncx);
       const uint32_t rest = k / (uint32_t)kp.ncx;
@@ -203,7 +204,7 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   }
   const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
   const bool eqm = kp.mass_f == kp.mass_b;
-  const bool gen = kp.kernel != 0 || kp.viscosity != 0 || kp.ddt == 2;
+  const bool gen = kp.kernel != 0 || kp.viscosity != 0 || kp.ddt == 2 || kp.floating != 0;
 #define SPH_LAUNCH(D, RR, G, PP, GG)                                                         \
   hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG>), dim3(grid), dim3(kBlock), 0, st, \
                      kp, n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, \

@@ -16,13 +16,17 @@ constexpr int kScanTile = kBlock * 8;
 constexpr int kViewPad = 8;        // spare float4 entries after each interaction view
 constexpr int kFrameCells = 8;     // x offsets in the views are taken per block of 8 cells
 constexpr uint32_t kXcds = 8;      // accelerator complex dies of the MI355X
+constexpr int kFloatParts = 32;    // blocks per floating body in its reductions
+constexpr int kFloatSums = 16;     // FP64 partial sums per block (force, torque, inertia, count)
+constexpr int kFloatMotion = 24;   // FP64 words of a body's rigid motion of one phase
 
 // Per-launch constants derived once on the host from sph_params.
 struct KParams {
   int dim, cell_div, ddt, x_sub;   // x_sub: key cells per cell along x
   int lg_xsub, pad2;
   int kernel, viscosity;           // 0 Wendland / 1 cubic spline; 0 artificial / 1 laminar
-  int boundary, pad3;              // 0 DBC (Eq. 36) / 1 modified DBC (Eq. 38-39)
+  int boundary;                    // 0 DBC (Eq. 36) / 1 modified DBC (Eq. 38-39)
+  int floating;                    // 1: floating particles (type 3) get Eq. 47
   int ncx, ncy, ncz;
   uint32_t ncell_total;          // also the key of particles outside the grid
   double ox, oy, oz;             // grid origin
@@ -98,6 +102,8 @@ struct WsLayout {
   size_t view_pr;    // float4 [n]: cell-relative position, signed density
   size_t view_vp;    // float4 [n]: velocity, pressure
   size_t red;        // BlockRed [nblk_interact]
+  size_t fpart;      // double [SPH_MAX_BODIES][kFloatParts][kFloatSums]: body partial sums
+  size_t fmotion;    // double [SPH_MAX_BODIES][kFloatMotion]: rigid motion of each body
   size_t total;
   int64_t nblk_sort, nblk_interact, hist_len, scan_parts;
 };
@@ -127,6 +133,9 @@ inline WsLayout ws_layout(int64_t n) {
   L.view_pr = off; off = align_up(off + 16 * (nn + kViewPad));
   L.view_vp = off; off = align_up(off + 16 * (nn + kViewPad));
   L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
+  L.fpart = off;
+  off = align_up(off + sizeof(double) * SPH_MAX_BODIES * kFloatParts * kFloatSums);
+  L.fmotion = off; off = align_up(off + sizeof(double) * SPH_MAX_BODIES * kFloatMotion);
   L.total = off;
   return L;
 }
@@ -158,6 +167,7 @@ inline T* ws_ptr(void* ws, size_t off) {
 // ---------------------------------------------------------------- device ----
 __device__ inline bool is_excluded(uint8_t t) { return (t & SPH_EXCLUDED) != 0; }
 __device__ inline bool is_fluid(uint8_t t) { return (t & 0x7f) == SPH_FLUID; }
+__device__ inline bool is_floating(uint8_t t) { return (t & 0x7f) == SPH_FLOATING; }
 
 __device__ inline void set_error(uint32_t* err, uint32_t bits) {
   atomicOr(err, bits);

@@ -19,6 +19,7 @@ struct TargetData {
   bool fluid;
   float rho, irho, p;
   float vx, vy, vz;
+  bool flt;  // a floating particle (general kernels only): Eq. 47
 };
 
 // The pair terms of Eq. 15, 17-18, 21-22 and 36 for one pair (a, b) with
@@ -37,10 +38,12 @@ struct TargetData {
 //   ((rho_a + rho_b)(r^2 + eta^2)) (Eq. 23);
 //   diffusion:   -(rho_b - rho_a) fv over fluid b (Eq. 18), or with
 //   rho_b - rho_a less its hydrostatic part rho^H_ab (Eq. 19-20).
-// GEN: any formulation option (read from kp, uniform per slot); otherwise the
-// default one (Wendland C2, artificial viscosity, Eq. 18 or no diffusion),
-// whose code keeps the register budget of the production pass.  EQM: fluid
-// and wall particles have the same mass (no per-pair select).
+// GEN: any formulation option (read from kp, uniform per slot) and floating
+// targets, which take the momentum terms of a fluid target from their fluid
+// neighbours (Eq. 47; no viscosity maximum, no diffusion); otherwise the
+// default formulation (Wendland C2, artificial viscosity, Eq. 18 or no
+// diffusion), whose code keeps the register budget of the production pass.
+// EQM: fluid and wall particles have the same mass (no per-pair select).
 template <int DIM, bool EQM, bool GEN>
 __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
                                            float dy, float dz, float r2, float pbw,
@@ -63,10 +66,10 @@ __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& 
   const float fv = (g * irhob) * kmb;
   acc.cont = fmaf(fv, vr, acc.cont);
   acc.cnt += 1u;
-  if (a.fluid) {
+  if (a.fluid || (GEN && a.flt)) {
     const float rr = __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
     const float mu = kp.h_f * vr * rr;
-    acc.vmax = fmaxf(acc.vmax, fabsf(mu));
+    if (!GEN || !a.flt) acc.vmax = fmaxf(acc.vmax, fabsf(mu));
     const float irs = __builtin_amdgcn_rcpf(a.rho + rhob);
     if (!GEN || kp.viscosity == 0) {
       const float kpi = EQM ? kp.kpi_mf_f : (fb ? kp.kpi_mf_f : kp.kpi_mb_f);  // -2 alpha c0 kfab m_b
@@ -127,9 +130,10 @@ __device__ inline void write_block_red(float fmag, float vmax, uint32_t cnt, uin
   }
 }
 
-// Per-target outputs: dv/dt (with gravity) for fluid targets, drho/dt, visc
-// and the pair count; returns |dv/dt|, visc and the fluid flag for the block
-// partial results.
+// Per-target outputs: dv/dt (with gravity) for fluid targets, dv/dt of
+// Eq. 47 (without gravity) for floating ones, drho/dt, visc and the pair
+// count; returns |dv/dt|, visc and the fluid flag for the block partial
+// results.
 template <int DIM>
 __device__ __forceinline__ void write_target(const KParams& kp, int64_t n, int64_t a,
                                              const TargetData& t, const PairAcc& acc,
@@ -146,6 +150,10 @@ __device__ __forceinline__ void write_target(const KParams& kp, int64_t n, int64
     fmag = sqrtf(ax * ax + ay * ay + az * az);
     vmax_out = acc.vmax;
     nfl = 1;
+  } else if (t.flt) {
+    ax = acc.ax;
+    ay = acc.ay;
+    az = DIM == 3 ? acc.az : 0.f;
   }
   ace[a] = ax;
   ace[n + a] = ay;

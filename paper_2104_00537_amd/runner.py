@@ -58,6 +58,15 @@ class Simulation:
             raise ValueError("verlet_ns must be >= 1")
         self.integrator = integrator
         self.verlet_ns = int(verlet_ns)
+        # floating bodies (Section 3.2): the device body table, advanced by
+        # sph_floating_step after each symplectic phase
+        self.bodies = None
+        if getattr(case, "bodies", None):
+            if integrator != "symplectic":
+                raise ValueError("floating bodies take the symplectic integrator")
+            if int(getattr(cp, "floating", 0)) != 1:
+                raise ValueError("a case with bodies needs params.floating = 1")
+            self.bodies = S.bodies_to_device(case.bodies, dev)
 
     # ------------------------------------------------------------------ step
     @property
@@ -96,6 +105,9 @@ class Simulation:
              interactions=self.interactions, stream=stream)
         call("symplectic", S.sph_symplectic_step, P, n, 0, self.dt, self.t, s0, b, self.ace,
              self.arho, self.ws, stream=stream)
+        if self.bodies is not None:
+            call("floating", S.sph_floating_step, P, n, 0, self.dt, self.bodies, s0, b, self.ace,
+                 self.ws, stream=stream)
         call("bin_cells", S.sph_bin_cells, P, n, b, a, self.key, self.perm, self.cell_start,
              self.ws, carry_in=s0, carry_out=s1, stream=stream)
         if self.mdbc:
@@ -108,6 +120,9 @@ class Simulation:
              interactions=self.interactions, stream=stream)
         call("symplectic", S.sph_symplectic_step, P, n, 1, self.dt, self.t, s1, a, self.ace,
              self.arho, self.ws, stream=stream)
+        if self.bodies is not None:
+            call("floating", S.sph_floating_step, P, n, 1, self.dt, self.bodies, s1, a, self.ace,
+                 self.ws, stream=stream)
         self.steps_done += 1
 
     def _step_verlet(self, stream, timing):
@@ -190,6 +205,10 @@ class Simulation:
         return dict(pos=st.pos.cpu().numpy()[:, inv], vel=st.vel.cpu().numpy()[:, inv],
                     rho=st.rho.cpu().numpy()[inv], type=st.type.cpu().numpy()[inv],
                     t=self.time())
+
+    def body_state(self) -> list:
+        """The floating bodies' current state (host dicts)."""
+        return [] if self.bodies is None else S.bodies_from_device(self.bodies)
 
     def interaction_count(self) -> int:
         return int(self.interactions[0].item())

@@ -19,14 +19,16 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsph.so")
 
 SPH_OK, SPH_E_ARG, SPH_E_WORKSPACE, SPH_E_HIP = 0, -1, -2, -3
-SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_EXCLUDED = 0, 1, 2, 0x80
-SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR = 1, 2, 4
+SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_FLOATING, SPH_EXCLUDED = 0, 1, 2, 3, 0x80
+SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR, SPH_ERR_FLOATING = 1, 2, 4, 8
+SPH_MAX_BODIES = 64
 SPH_DIAG_COUNT_F64 = 1
 SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
-           "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_read_error", "sph_clear_error", "sph_strerror",
+           "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_floating_step",
+           "sph_read_error", "sph_clear_error", "sph_strerror",
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
            "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
@@ -45,8 +47,16 @@ class SphParams(C.Structure):
         ("mass_bound", C.c_double), ("gravity", C.c_double * 3),
         ("motion_amp", C.c_double), ("motion_omega", C.c_double),
         ("dt_floor", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
-        ("visc_nu", C.c_double),
+        ("visc_nu", C.c_double), ("floating", C.c_int32), ("pad0", C.c_int32),
     ]
+
+
+class SphBody(C.Structure):
+    _fields_ = [("id_first", C.c_int64), ("count", C.c_int64), ("mass", C.c_double),
+                ("center", C.c_double * 3), ("vel", C.c_double * 3), ("omega", C.c_double * 3),
+                ("center_n", C.c_double * 3), ("vel_n", C.c_double * 3),
+                ("omega_n", C.c_double * 3), ("force", C.c_double * 3),
+                ("torque", C.c_double * 3)]
 
 
 class SphState(C.Structure):
@@ -88,6 +98,9 @@ def _load() -> C.CDLL:
                                   P(SphState), P(SphState), VP, VP, VP, C.c_size_t, VP]
     L.sph_mdbc.restype = C.c_int32
     L.sph_mdbc.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_floating_step.restype = C.c_int32
+    L.sph_floating_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP, C.c_int32,
+                                    P(SphState), P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_read_error.restype = C.c_int32
     L.sph_read_error.argtypes = [VP]
     L.sph_clear_error.restype = C.c_int32
@@ -146,6 +159,7 @@ def make_params(cp) -> SphParams:
     p.kernel = int(getattr(cp, "kernel", 0))
     p.viscosity = int(getattr(cp, "viscosity", 0))
     p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
+    p.floating = int(getattr(cp, "floating", 0))
     for k in range(3):
         p.ncell[k] = int(cp.ncell[k])
         p.origin[k] = float(cp.origin[k])
@@ -256,6 +270,45 @@ def sph_mdbc(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
              cell_start: torch.Tensor, ws: torch.Tensor, stream=None):
     _check(lib.sph_mdbc(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
                         _ptr(ws), ws.numel(), _stream(stream)), "sph_mdbc")
+
+
+def bodies_to_device(bodies, device) -> torch.Tensor:
+    """The sph_body table of `bodies` (dicts with id_first, count, mass,
+    center, vel, omega) as a uint8 device tensor."""
+    arr = (SphBody * len(bodies))()
+    for k, b in enumerate(bodies):
+        arr[k].id_first, arr[k].count, arr[k].mass = int(b["id_first"]), int(b["count"]), \
+            float(b["mass"])
+        for d in range(3):
+            arr[k].center[d] = float(b["center"][d])
+            arr[k].vel[d] = float(b.get("vel", (0.0,) * 3)[d])
+            arr[k].omega[d] = float(b.get("omega", (0.0,) * 3)[d])
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def bodies_from_device(table: torch.Tensor) -> list:
+    """The body table read back as dicts (numpy arrays of 3 components)."""
+    raw = table.cpu().numpy().tobytes()
+    nb = len(raw) // C.sizeof(SphBody)
+    arr = (SphBody * nb).from_buffer_copy(raw)
+    out = []
+    for b in arr:
+        d = dict(id_first=int(b.id_first), count=int(b.count), mass=float(b.mass))
+        for name in ("center", "vel", "omega", "center_n", "vel_n", "omega_n", "force",
+                     "torque"):
+            d[name] = np.array(getattr(b, name)[:])
+        out.append(d)
+    return out
+
+
+def sph_floating_step(params: SphParams, n: int, phase: int, dt: torch.Tensor,
+                      bodies: torch.Tensor, saved: DeviceState, s: DeviceState,
+                      ace: torch.Tensor, ws: torch.Tensor, stream=None):
+    nb = bodies.numel() // C.sizeof(SphBody)
+    _check(lib.sph_floating_step(C.byref(params), int(n), int(phase), _ptr(dt), _ptr(bodies),
+                                 int(nb), C.byref(saved.c()), C.byref(s.c()), _ptr(ace),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "sph_floating_step")
 
 
 def sph_read_error(ws: torch.Tensor) -> int:

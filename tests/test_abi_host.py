@@ -53,6 +53,62 @@ def test_struct_layout_matches_header(S, tmp_path):
     assert vals[2 + len(fields):] == [getattr(S.SphState, f).offset for f in sfields]
 
 
+def test_body_layout_matches_header(S, tmp_path):
+    """The ctypes mirror of sph_body has the C size and field offsets."""
+    fields = [f for f, _ in S.SphBody._fields_]
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "sph.h"', "int main(void){",
+            'printf("%zu %d\\n", sizeof(sph_body), SPH_MAX_BODIES);']
+    prog += [f'printf("%zu\\n", offsetof(sph_body, {f}));' for f in fields]
+    prog += ["return 0;}"]
+    src = tmp_path / "body.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "body"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    vals = [int(v) for v in
+            subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == C.sizeof(S.SphBody) and vals[1] == S.SPH_MAX_BODIES
+    assert vals[2:] == [getattr(S.SphBody, f).offset for f in fields]
+
+
+def test_floating_step_validates_without_device(S):
+    """sph_floating_step rejects a case without floating = 1, a body count
+    outside [1, SPH_MAX_BODIES], a missing table or particle ids, and a bad
+    phase; floating bodies cannot be combined with modified DBC, the
+    precision-study arms or the batched path."""
+    from paper_2104_00537_amd import cases
+    c = cases.floating_box(2, dp=0.04)
+    P = S.make_params(c.params)
+    assert P.floating == 1
+    lib = S.lib
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, 16, None)
+    noid = S.SphState(16, 16, 16, 16, None, None)
+    need = S.sph_workspace_bytes(P, 1000)
+
+    def call(p=P, phase=0, bodies=d, nb=1, s=st, ws=need):
+        return lib.sph_floating_step(C.byref(p), 1000, phase, d, bodies, nb, C.byref(st),
+                                     C.byref(s), d, d, ws, None)
+
+    assert call(nb=0) == S.SPH_E_ARG
+    assert call(nb=S.SPH_MAX_BODIES + 1) == S.SPH_E_ARG
+    assert call(bodies=None) == S.SPH_E_ARG
+    assert call(s=noid) == S.SPH_E_ARG
+    assert call(phase=2) == S.SPH_E_ARG
+    assert call(ws=need - 1) == S.SPH_E_WORKSPACE
+    P0 = S.make_params(c.params)
+    P0.floating = 0
+    assert call(p=P0) == S.SPH_E_ARG
+    P1 = S.make_params(c.params)
+    P1.boundary = 1
+    assert call(p=P1) == S.SPH_E_ARG
+    for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32):
+        assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, flags, d,
+                                need, None) == S.SPH_E_ARG
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe([S.make_params(cases.dam_break_2d(dp=0.05).params), P],
+                             [0, 10, 20])
+
+
 def test_workspace_bytes_monotone(S):
     from paper_2104_00537_amd import cases
     P = S.make_params(cases.dam_break_2d().params)
