@@ -140,6 +140,46 @@ def verlet_leg(case, steps, warmup):
             "interactions_per_s": pairs / el, "ns": 40}
 
 
+def floating_leg(args, steps=20, warmup=5):
+    """A floating box (Section 3.2) at the workload's resolution: the 3-D
+    dam-break block released into a tank holding a 0.06 m water layer, with
+    a 0.12 x 0.12 x 0.08 m box of density 500 kg/m^3 floating on the layer
+    at x = 1.0 m.  Steps/s, interactions/s and the cost of the rigid-body
+    calls (HIP events on the launch stream)."""
+    import numpy as np
+    import torch
+    from paper_2104_00537_amd import cases
+    from paper_2104_00537_amd.runner import Simulation
+    case = cases.floating_box(3, dp=0.6 / 126, tank=(1.6, 0.6, 0.6), column=(0.6, 0.6, 0.3),
+                              layer=0.06, box=(0.12, 0.12, 0.08), box_x=1.0,
+                              cell_div=args.cell_div, x_sub=args.x_sub)
+    sim = Simulation(case, "cuda:0")
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    i0 = sim.interaction_count()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timing = {}
+    for _ in range(3):
+        sim.step(timing=timing)
+    torch.cuda.synchronize()
+    if sim.error() != 0:
+        raise SystemExit(f"device error word {sim.error()} in the floating-body leg")
+    pairs = sim.interaction_count() - i0
+    steps_all = steps + 3
+    phase_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in timing.items()}
+    b = sim.body_state()[0]
+    return {"workload": "floating_box_3d", "n_particles": case.n,
+            "n_floating": case.bodies[0]["count"], "steps": steps,
+            "ms_per_step": el / steps * 1e3, "interactions_per_s": pairs / (el * steps_all / steps),
+            "ms_floating_call": phase_ms["floating"], "ms_interact": phase_ms["interact"],
+            "body_velocity": [float(v) for v in b["vel"]]}
+
+
 VARIANTS = {"default": {}, "cubic_spline": dict(kernel=1),
             "laminar_viscosity": dict(viscosity=1, visc_nu=1e-6), "fourtakas_ddt": dict(ddt=2),
             "all_three": dict(kernel=1, viscosity=1, visc_nu=1e-6, ddt=2)}
@@ -294,6 +334,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-floating", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -381,6 +422,8 @@ def main():
         res["verlet"] = verlet_leg(case, args.steps, args.warmup)
     if not args.no_variants:
         res["variants"] = variants_leg(case)
+    if not args.no_floating:
+        res["floating"] = floating_leg(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:
