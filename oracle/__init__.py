@@ -48,6 +48,7 @@ class OrcParams(C.Structure):
         ("gravity", C.c_double * 3), ("motion_amp", C.c_double),
         ("motion_omega", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
         ("visc_nu", C.c_double), ("boundary", C.c_int32), ("pad2", C.c_int32),
+        ("period", C.c_double * 3),
     ]
 
 
@@ -77,6 +78,7 @@ def lib():
         L.orc_pressure.restype = C.c_double
         L.orc_pressure.argtypes = [P(OrcParams), C.c_double]
         L.orc_cell_keys.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_wrap.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p]
         L.orc_sort_perm.argtypes = [C.c_int64, C.c_void_p, C.c_void_p]
         L.orc_cell_start.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         L.orc_interact.argtypes = [P(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
@@ -123,6 +125,9 @@ def params(cp) -> OrcParams:
     p.viscosity = int(getattr(cp, "viscosity", 0))
     p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
     p.boundary = int(getattr(cp, "boundary", 0))
+    period = getattr(cp, "period", (0.0, 0.0, 0.0))
+    for k in range(3):
+        p.period[k] = float(period[k])
     for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
                  "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
         setattr(p, name, float(getattr(cp, name)))
@@ -165,6 +170,16 @@ def cell_keys(cp, pos):
     p = params(cp)
     lib().orc_cell_keys(C.byref(p), n, _ptr(pos), _ptr(key))
     return key
+
+
+def wrap(cp, pos, ptype=None):
+    """Positions brought back into [origin, origin + period) along periodic
+    components (Section 2.7)."""
+    pos = _f64(pos).copy()
+    p = params(cp)
+    tp = None if ptype is None else np.ascontiguousarray(ptype, dtype=np.uint8)
+    lib().orc_wrap(C.byref(p), pos.shape[1], _ptr(pos), None if tp is None else _ptr(tp))
+    return pos
 
 
 def sort_perm(key):

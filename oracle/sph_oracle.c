@@ -106,6 +106,41 @@ double orc_pressure(const orc_params* p, double rho) {
   return b * (pow(rho / p->rho0, p->gamma) - 1.0);
 }
 
+/* Periodic boundaries, Section 2.7: along a periodic component k the domain
+ * is [origin_k, origin_k + L_k) and repeats with period L_k, so that a
+ * particle near one end sees those near the other end as neighbours.
+ * Distances take the nearest image: d - L if d > L/2, d + L if d < -L/2
+ * (one image suffices while L exceeds twice the support 2h). */
+static double min_image(const orc_params* p, int k, double d) {
+  const double L = p->period[k];
+  if (L > 0.0) {
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+  }
+  return d;
+}
+
+/* A particle that left [origin, origin + L) along a periodic component
+ * re-enters at the other end: x - L, or x + L (and origin if x + L rounds
+ * to the end itself).  Excluded particles are left alone. */
+void orc_wrap(const orc_params* p, int64_t n, double* pos, const uint8_t* type) {
+  for (int k = 0; k < p->dim; ++k) {
+    const double L = p->period[k], o = p->origin[k];
+    if (!(L > 0.0)) continue;
+    for (int64_t a = 0; a < n; ++a) {
+      if (type && is_excluded(type[a])) continue;
+      double x = pos[k * n + a];
+      if (x >= o + L) {
+        x = x - L;
+      } else if (x < o) {
+        x = x + L;
+        if (x >= o + L) x = o;
+      }
+      pos[k * n + a] = x;
+    }
+  }
+}
+
 /* Cell key of Section 5.1's cell-linked list: the cell index along each axis
  * is floor((x - origin) * inv) (an FP64 subtraction, then an FP64
  * multiplication) with inv the inverse cell size of that axis
@@ -119,6 +154,9 @@ uint32_t orc_cell_key(const orc_params* p, const double* pos, int64_t n, int64_t
     double inv = p->inv_cell_size * (k == 0 && p->x_sub > 1 ? (double)p->x_sub : 1.0);
     double s = d * inv;
     double f = floor(s);
+    /* a wrapped coordinate lies in [origin, origin + L): a product that
+     * rounds up to the end is the last cell */
+    if (p->period[k] > 0.0 && f == (double)p->ncell[k]) f -= 1.0;
     if (!(f >= 0.0) || !(f < (double)p->ncell[k]))
       return (uint32_t)((int64_t)p->ncell[0] * p->ncell[1] * p->ncell[2]);
     c[k] = (int64_t)f;
@@ -196,6 +234,9 @@ static double particle_mass(const orc_params* p, uint8_t t) {
  *  particle is exactly opposite to the force its fluid neighbours receive
  *  from it.  visc_a stays 0 (Eq. 35 runs over fluid only).
  *
+ * Distances along periodic components take the nearest image (Section
+ * 2.7, min_image).
+ *
  * Readings: the mean in Eq. 21 is (x_a + x_b)/2; eta^2 = eta2 (the case uses
  * 0.001 h^2); c_a and cbar_ab are the constant c0; psi_ab of Eq. 18 is taken
  * along r_ba = r_b - r_a, the diffusive direction of the Molteni-Colagrossi
@@ -241,7 +282,7 @@ void orc_interact(const orc_params* p, int64_t n, const double* pos,
         if (!fa && !fb) continue;  /* Eq. 36 sums over fluid b only */
         double dx[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
         for (int k = 0; k < dim; ++k) {
-          dx[k] = pos[k * n + a] - pos[k * n + b];
+          dx[k] = min_image(p, k, pos[k * n + a] - pos[k * n + b]);
           r2 += dx[k] * dx[k];
         }
         if (!(r2 < support2)) continue;
@@ -459,7 +500,7 @@ void orc_mdbc(const orc_params* p, int64_t n, const double* pos, const double* v
       if (is_excluded(type[b]) || !is_fluid(type[b])) continue;
       double r[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
       for (int k = 0; k < dim; ++k) {
-        r[k] = pos[k * n + b] - g[k];
+        r[k] = min_image(p, k, pos[k * n + b] - g[k]);
         r2 += r[k] * r[k];
       }
       if (!(r2 < support2)) continue;
@@ -736,6 +777,7 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
       (orc_body*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(orc_body));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
+    orc_wrap(p, n, pos, type);
     mark_excluded(p, n, pos, type);
     mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
     orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
@@ -749,6 +791,7 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
       if (orc_body_step(p, n, 0, dt, &bodies[k], &bodies_n[k], pos_n, pos, vel, type, ace,
                         NULL, NULL))
         status = 3;
+    orc_wrap(p, n, pos, type);
     mark_excluded(p, n, pos, type);
     mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
     orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
@@ -785,6 +828,7 @@ int32_t orc_run_verlet(const orc_params* p, int64_t n, double* pos, double* vel,
   double* vel_pi = (double*)calloc(nd, sizeof(double));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
+    orc_wrap(p, n, pos, type);
     mark_excluded(p, n, pos, type);
     mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
     orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);

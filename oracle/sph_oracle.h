@@ -49,6 +49,9 @@ typedef struct orc_params {
   double visc_nu;          /* kinematic viscosity of the laminar term */
   int32_t boundary;        /* 0: DBC (Eq. 36); 1: modified DBC (Eq. 38-39) */
   int32_t pad2;
+  double period[3];        /* > 0: the domain is periodic along that component
+                              with this length, starting at origin (Section
+                              2.7); 0: open */
 } orc_params;
 
 /* A rigid floating body (Section 3.2): particles [first, first + count) of
@@ -70,6 +73,7 @@ double orc_pressure(const orc_params* p, double rho);
 
 uint32_t orc_cell_key(const orc_params* p, const double* pos, int64_t n, int64_t i);
 void orc_cell_keys(const orc_params* p, int64_t n, const double* pos, uint32_t* key);
+void orc_wrap(const orc_params* p, int64_t n, double* pos, const uint8_t* type);
 void orc_sort_perm(int64_t n, const uint32_t* key, uint32_t* perm);
 void orc_cell_start(int64_t n, const uint32_t* sorted_key, int64_t ncell_total,
                     uint32_t* start);

@@ -35,7 +35,8 @@ EXCLUDED = 0x80
 GRAVITY = 9.81
 
 __all__ = ["CaseParams", "Case", "dam_break_2d", "dam_break_3d", "sloshing_3d",
-           "block_case", "random_serving_case", "floating_box", "FLUID", "BOUND_FIXED",
+           "block_case", "random_serving_case", "floating_box", "periodic_box", "FLUID",
+           "BOUND_FIXED",
            "BOUND_MOVING", "FLOATING", "EXCLUDED", "GRAVITY"]
 
 
@@ -60,6 +61,9 @@ class CaseParams:
     kernel: int = 0       # 0 Wendland C2 (Eq. 11), 1 cubic spline (Eq. 10)
     boundary: int = 0     # 0 DBC (Eq. 36), 1 modified DBC (Eq. 38-39)
     floating: int = 0     # 1: the case has floating bodies (Section 3.2)
+    # periodic length per component (Section 2.7), 0 = open; a periodic
+    # component's grid starts at the periodic boundary and spans the period
+    period: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     viscosity: int = 0    # 0 artificial (Eq. 21), 1 laminar (Eq. 23)
     visc_nu: float = 1e-6  # kinematic viscosity of the laminar term (water)
     cell_div: int = 1
@@ -408,4 +412,101 @@ def floating_box(dim=2, dp=0.02, tank=None, column=None, layer=0.15, box=None,
     case.bodies = [dict(id_first=nf, count=nbox, mass=box_density * nbox * dp ** dim,
                         center=tuple(c3), vel=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0))]
     case.params.floating = 1
+    return case
+
+
+def periodic_box(dim=2, shape=None, dp=0.01, periodic=(0,), walls=True, gravity=None,
+                 seed=0, cell_div=1, x_sub=1, vel_scale=0.0, rho_jitter=0.0) -> Case:
+    """A block of fluid of ``shape`` lattice cells that repeats along the
+    components listed in ``periodic`` (Section 2.7), e.g. a channel periodic
+    along x between a bottom and a top wall (``walls``: two layers on each
+    open side of every non-periodic component; none if False).
+
+    Along a periodic component the grid starts at the periodic boundary
+    (x = 0) and spans the period exactly, so the cell size is a whole number
+    of lattice spacings (the smallest one >= 2h / cell_div) and the period a
+    whole number of cells (``shape`` is rounded up to one).  ``gravity``
+    defaults to -g along the last component; the initial density is
+    hydrostatic below the top of the fluid when gravity has a vertical part.
+    Optional seeded random velocities and density jitter as in block_case."""
+    if shape is None:
+        shape = (40, 12) if dim == 2 else (16, 12, 10)
+    periodic = tuple(sorted(set(int(k) for k in periodic)))
+    h = math.sqrt(dim) * dp
+    k_cs = int(math.ceil(2.0 * h / (cell_div * dp) - 1e-9))
+    cs = k_cs * dp
+    shape = [int(math.ceil(s / k_cs) * k_cs) if k in periodic else int(s)
+             for k, s in enumerate(shape)]
+    fluid = _grid(*[(0, s) for s in shape])
+    parts = []
+    if walls:
+        for k in range(dim):
+            if k in periodic:
+                continue
+            for side in (0, 1):
+                rng_k = [(0, s) for s in shape]
+                # the wall layers span the other non-periodic components'
+                # wall thickness too (corners), the periodic ones as they are
+                for j in range(dim):
+                    if j != k and j not in periodic:
+                        rng_k[j] = (-2, shape[j] + 2)
+                rng_k[k] = (-2, 0) if side == 0 else (shape[k], shape[k] + 2)
+                parts.append(_grid(*rng_k))
+        # corners counted once: keep unique lattice points
+        if parts:
+            wall = np.unique(np.concatenate(parts, axis=1), axis=1)
+        else:
+            wall = np.zeros((dim, 0), np.int64)
+    else:
+        wall = np.zeros((dim, 0), np.int64)
+    idx = np.concatenate([fluid, wall], axis=1)
+    n = idx.shape[1]
+    rng = np.random.default_rng(seed)
+    pos = (idx.astype(np.float64) + 0.5) * dp
+    pos += rng.uniform(-1e-4 * dp, 1e-4 * dp, size=pos.shape)
+    ptype = np.full(n, FLUID, np.uint8)
+    ptype[fluid.shape[1]:] = BOUND_FIXED
+    g = [0.0, 0.0, 0.0]
+    if gravity is None:
+        g[dim - 1] = -GRAVITY
+    else:
+        g = [float(v) for v in gravity] + [0.0] * (3 - len(gravity))
+    height = shape[dim - 1] * dp
+    rho0, gamma = 1000.0, 7.0
+    c0 = 10.0 * math.sqrt(GRAVITY * height)
+    b_tait = c0 * c0 * rho0 / gamma
+    gz = abs(g[dim - 1])
+    depth = np.maximum(height - pos[dim - 1], 0.0)
+    rho = rho0 * np.power(1.0 + rho0 * gz * depth / b_tait, 1.0 / gamma)
+    origin, ncell, period = [0.0] * 3, [1, 1, 1], [0.0] * 3
+    for k in range(dim):
+        if k in periodic:
+            origin[k] = 0.0
+            ncell[k] = shape[k] // k_cs
+            period[k] = shape[k] * dp
+        else:
+            m = 2.0 * dp + 1e-3 * dp + 2 * cs
+            origin[k] = -m
+            ncell[k] = int(math.ceil((shape[k] * dp + 2 * m) / cs))
+    ncell[0] *= x_sub
+    mass = rho0 * dp ** dim
+    params = CaseParams(
+        name=f"periodic_box_{dim}d", dim=dim, dp=dp, h=h, rho0=rho0, gamma=gamma, c0=c0,
+        alpha=0.01, delta=0.1, eta2=0.001 * h * h, cfl=0.2, mass_fluid=mass, mass_bound=mass,
+        gravity=tuple(g), ddt=1, cell_div=cell_div, x_sub=x_sub, origin=tuple(origin),
+        cell_size=cs, inv_cell_size=1.0 / cs, ncell=tuple(ncell), fluid_height=height,
+        period=tuple(period))
+    normal = np.zeros((dim, n), np.float32)
+    if wall.shape[1]:
+        # walls lie outside the fluid only along non-periodic components
+        normal[:, fluid.shape[1]:] = _ghost_vectors(wall, tuple(shape), dp)
+    case = Case(params=params, pos=np.ascontiguousarray(pos),
+                vel=np.zeros((dim, n), np.float32), rho=rho.astype(np.float32), type=ptype,
+                meta=dict(shape=tuple(shape), periodic=periodic, walls=walls), normal=normal)
+    rng2 = np.random.default_rng(seed + 7919)
+    if vel_scale:
+        case.vel[:] = rng2.uniform(-vel_scale, vel_scale, case.vel.shape).astype(np.float32)
+    if rho_jitter:
+        case.rho[:] = (case.rho * (1.0 + rng2.uniform(-rho_jitter, rho_jitter,
+                                                      case.n))).astype(np.float32)
     return case
