@@ -90,8 +90,8 @@ enum {
    * replace).  Velocities and densities are the stored FP32 values in both;
    * the outputs and the workspace partials are as in the production pass.
    * The arms take the default formulation only (Wendland kernel, artificial
-   * viscosity, ddt 0 or 1, no floating bodies); other options are rejected
-   * with SPH_E_ARG. */
+   * viscosity, ddt 0 or 1, no floating bodies, no periodic components);
+   * other options are rejected with SPH_E_ARG. */
   SPH_INTERACT_F64 = 2u,
   SPH_INTERACT_ABS_F32 = 4u
 };
@@ -147,6 +147,18 @@ typedef struct sph_params {
                              Eq. 47.  Needs boundary 0; with 0, particles of
                              type 3 take the fixed-wall path. */
   int32_t pad0;
+  double period[3];       /* periodic boundaries (Section 2.7): period[k] > 0
+                             makes component k periodic with this length; the
+                             grid along k must start at the periodic boundary
+                             (origin[k]) and span exactly the period: period
+                             = cells * cell_size within 1e-9 relative, cells
+                             = ncell[k] (ncell[0] / x_sub along x, which must
+                             divide), and at least 2 cell_div + 1 cells.
+                             Particles leaving [origin, origin + period) along
+                             k re-enter at the other end (sph_bin_cells wraps
+                             the positions it writes) and pairs take the
+                             nearest image.  0: open.  Needs boundary 0 and
+                             no floating bodies. */
 } sph_params;
 
 /* Particle state (SoA device arrays of n particles). */
@@ -177,7 +189,10 @@ size_t sph_workspace_bytes(const sph_params* p, int64_t n);
  *                     [cell_start[c], cell_start[c+1]); cell_start[C] is the
  *                     number of particles inside the grid
  *   out               out: `in` gathered by perm (pos, vel, rho, type, id);
- *                     newly excluded particles get the 0x80 type bit
+ *                     newly excluded particles get the 0x80 type bit; along
+ *                     periodic components positions are first brought back
+ *                     into [origin, origin + period): x - period if beyond,
+ *                     x + period if below (origin if that rounds to the end)
  *   carry_in/out      nullable pair: a second state (pos, vel, rho only)
  *                     gathered by the same perm -- the saved state n during
  *                     the corrector's NL.
@@ -206,6 +221,7 @@ sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in,
  *   visc[n]                out, nullable: max_b |h v_ab.r_ab|/(r_ab^2+eta^2)
  *   nbr_count[n]           out, nullable: pairs evaluated for a (all neighbours
  *                          of a fluid target, fluid neighbours of a wall)
+ * Along periodic components (p->period) pairs take the nearest image.
  * Arithmetic is FP32 on cell-relative FP32 positions (Section 5.1, precision
  * paragraph).  Per-block maxima of |ace| and visc over fluid targets and the
  * interaction count go to the workspace for sph_reduce_dt. */
@@ -368,7 +384,8 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * table to device memory and sets batch->table before the calls below.  The
  * table stays valid while the slots keep their ranges.  Every slot must use
  * the same cell_div and the default formulation (kernel 0, viscosity 0, ddt
- * 0 or 1, boundary 0, no floating bodies); otherwise SPH_E_ARG. */
+ * 0 or 1, boundary 0, no floating bodies, no periodic components);
+ * otherwise SPH_E_ARG. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
                               void* table_host, size_t table_bytes, sph_batch* batch);
 

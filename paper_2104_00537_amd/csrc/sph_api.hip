@@ -67,6 +67,17 @@ KParams make_kparams(const sph_params& p) {
   k.kernel = p.kernel;
   k.boundary = p.boundary;
   k.floating = p.floating;
+  k.periodic = 0;
+  for (int d = 0; d < p.dim; ++d)
+    if (p.period[d] > 0.0) k.periodic |= 1 << d;
+  k.px = p.period[0] > 0.0 ? p.period[0] : 0.0;
+  k.py = p.dim > 1 && p.period[1] > 0.0 ? p.period[1] : 0.0;
+  k.pz = p.dim > 2 && p.period[2] > 0.0 ? p.period[2] : 0.0;
+  // the x period in fixed-point x units (kFrameCells cells = 2^32), mod 2^32
+  {
+    const double fr = k.px / (kFrameCells * p.cell_size);
+    k.lu = (uint32_t)(uint64_t)llround((fr - floor(fr)) * 4294967296.0);
+  }
   k.viscosity = p.viscosity;
   k.inv_h_f = (float)(1.0 / p.h);
   k.klam_mf_f = (float)(4.0 * p.visc_nu * kfab * p.mass_fluid);
@@ -126,6 +137,18 @@ static bool params_ok(const sph_params* p) {
   if (p->boundary != 0 && p->boundary != 1) return false;
   if (p->floating != 0 && p->floating != 1) return false;
   if (p->floating == 1 && p->boundary != 0) return false;
+  // periodic components: the grid spans exactly the period, in whole cells,
+  // at least 2 cell_div + 1 of them (so no neighbour cell is reached twice)
+  for (int k = 0; k < 3; ++k) {
+    const double L = p->period[k];
+    if (!(L >= 0.0) || !isfinite(L)) return false;
+    if (L == 0.0) continue;
+    if (k >= p->dim || p->boundary != 0 || p->floating != 0) return false;
+    if (k == 0 && p->ncell[0] % p->x_sub != 0) return false;
+    const int cells = k == 0 ? p->ncell[0] / p->x_sub : p->ncell[k];
+    if (cells < 2 * p->cell_div + 1) return false;
+    if (fabs(L - cells * p->cell_size) > 1e-9 * L) return false;
+  }
   if (p->viscosity != 0 && p->viscosity != 1) return false;
   if (!(p->visc_nu >= 0) || !isfinite(p->visc_nu)) return false;
   for (int k = 0; k < 3; ++k)
@@ -192,7 +215,8 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
   if ((flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) &&
-      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0))
+      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0 ||
+       p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   const KParams kp = make_kparams(*p);
@@ -303,7 +327,7 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
     // the batched interaction runs the default formulation (Wendland kernel,
     // artificial viscosity, ddt 0 or 1)
     if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->boundary != 0 ||
-        p->floating != 0)
+        p->floating != 0 || p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0)
       return SPH_E_ARG;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
         const int cy = (int)(rest % (uint32_t)kp.ncy);
         const int cz = (int)(rest / (uint32_t)kp.ncy);
         uint32_t c64 = 0;
-        gather_walk<3, R, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
+        gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
                                  acc, c64);
         write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
         cnt = acc.cnt;

@@ -8,11 +8,28 @@
 
 namespace sph {
 
+// Along a periodic component k (period L > 0, Section 2.7) a coordinate that
+// left [o, o + L) re-enters at the other end: x - L, or x + L (o if that
+// rounds to o + L).
+__device__ inline double wrap_coord(const KParams& kp, int k, double x) {
+  const double L = k == 0 ? kp.px : (k == 1 ? kp.py : kp.pz);
+  if (!(L > 0.0)) return x;
+  const double o = k == 0 ? kp.ox : (k == 1 ? kp.oy : kp.oz);
+  if (x >= o + L) return __dsub_rn(x, L);
+  if (x < o) {
+    x = __dadd_rn(x, L);
+    if (x >= o + L) x = o;
+  }
+  return x;
+}
+
 // Cell index per axis = floor((x - origin) * inv): one FP64 subtraction and
 // one FP64 multiplication (no contraction is possible), x fastest; inv is the
 // inverse cell size, times x_sub along x.  Outside
 // the grid, and for particles excluded earlier, the key is ncell_total, so
-// they sort last and lie in no cell range.
+// they sort last and lie in no cell range.  Periodic components take the
+// wrapped coordinate (and its last cell if the product rounds up to the
+// end).
 __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __restrict__ pos,
                                           const uint8_t* __restrict__ type, int64_t n,
                                           int64_t i) {
@@ -21,9 +38,10 @@ __device__ inline uint32_t cell_key_local(const KParams& kp, const double* __res
   const int nc[3] = {kp.ncx, kp.ncy, kp.ncz};
   int c[3] = {0, 0, 0};
   for (int k = 0; k < kp.dim; ++k) {
-    const double d = __dsub_rn(pos[k * n + i], org[k]);
+    const double d = __dsub_rn(wrap_coord(kp, k, pos[k * n + i]), org[k]);
     const double s = __dmul_rn(d, k == 0 ? kp.inv_csx : kp.inv_cs);
-    const double f = floor(s);
+    double f = floor(s);
+    if (((kp.periodic >> k) & 1) && f == (double)nc[k]) f -= 1.0;
     if (!(f >= 0.0) || !(f < (double)nc[k])) return kp.ncell_total;
     c[k] = (int)f;
   }
@@ -59,8 +77,10 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
                                    float4* __restrict__ pr, float4* __restrict__ vp) {
   double x[3] = {0.0, 0.0, 0.0};
   float v[3] = {0.f, 0.f, 0.f};
+  const bool live = !(in.type[src] & SPH_EXCLUDED);
   for (int d = 0; d < kp.dim; ++d) {
     x[d] = in.pos[d * n + src];
+    if (live) x[d] = wrap_coord(kp, d, x[d]);
     v[d] = in.vel[d * n + src];
     out.pos[d * n + i] = x[d];
     out.vel[d * n + i] = v[d];

@@ -15,7 +15,7 @@ namespace sph {
 
 // ------------------------------------------------- interaction: gather --
 // One lane per target particle (sorted order): the production kernel.
-template <int DIM, int R, bool DIAG, bool EQM, bool GEN>
+template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER>
 __global__ __launch_bounds__(kBlock) void k_interact_gather(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
       const uint32_t rest = k / (uint32_t)kp.ncx;
       const int cy = (int)(rest % (uint32_t)kp.ncy);
       const int cz = (int)(rest / (uint32_t)kp.ncy);
-      gather_walk<DIM, R, DIAG, EQM, GEN>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart, pos64, acc, c64);
+      gather_walk<DIM, R, DIAG, EQM, GEN, PER>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart,
+                                              pos64, acc, c64);
       const uint32_t c = DIAG ? c64 : acc.cnt;
       write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
       cnt_out = acc.cnt;
@@ -205,12 +206,15 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
   const bool eqm = kp.mass_f == kp.mass_b;
   const bool gen = kp.kernel != 0 || kp.viscosity != 0 || kp.ddt == 2 || kp.floating != 0;
-#define SPH_LAUNCH(D, RR, G, PP, GG)                                                         \
-  hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG>), dim3(grid), dim3(kBlock), 0, st, \
-                     kp, n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, \
-                     hdr)
-#define SPH_LAUNCH_G(D, RR, G, PP) \
-  if (gen) SPH_LAUNCH(D, RR, G, PP, true); else SPH_LAUNCH(D, RR, G, PP, false)
+  const bool per = kp.periodic != 0;  // periodic cases run the general kernel with PER
+#define SPH_LAUNCH(D, RR, G, PP, GG, PE)                                                   \
+  hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG, PE>), dim3(grid), dim3(kBlock), 0, \
+                     st, kp, n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, \
+                     red, hdr)
+#define SPH_LAUNCH_G(D, RR, G, PP)                                       \
+  if (per) SPH_LAUNCH(D, RR, G, PP, true, true);                         \
+  else if (gen) SPH_LAUNCH(D, RR, G, PP, true, false);                   \
+  else SPH_LAUNCH(D, RR, G, PP, false, false)
 #define SPH_LAUNCH_P(D, RR, G) \
   if (eqm) SPH_LAUNCH_G(D, RR, G, true); else SPH_LAUNCH_G(D, RR, G, false)
   if (kp.dim == 2) {

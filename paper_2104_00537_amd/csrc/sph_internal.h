@@ -23,7 +23,8 @@ constexpr int kFloatMotion = 24;   // FP64 words of a body's rigid motion of one
 // Per-launch constants derived once on the host from sph_params.
 struct KParams {
   int dim, cell_div, ddt, x_sub;   // x_sub: key cells per cell along x
-  int lg_xsub, pad2;
+  int lg_xsub;
+  int periodic;                    // bit k: component k is periodic (Section 2.7)
   int kernel, viscosity;           // 0 Wendland / 1 cubic spline; 0 artificial / 1 laminar
   int boundary;                    // 0 DBC (Eq. 36) / 1 modified DBC (Eq. 38-39)
   int floating;                    // 1: floating particles (type 3) get Eq. 47
@@ -35,6 +36,7 @@ struct KParams {
   double mass_f, mass_b;
   double gx, gy, gz;
   double motion_amp, motion_omega;
+  double px, py, pz;             // periods (0: open)
   double support2;               // (2h)^2 in FP64, for the diagnostic count
   // FP32 copies for the interaction kernel
   double inv_frame;               // 1 / (kFrameCells cs)
@@ -49,6 +51,7 @@ struct KParams {
   float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
   float cs_f, inv_csx_f, unit_x_f;           // cell size, inverse key-cell size along x, x offset unit
   float gx_f, gy_f, gz_f;
+  uint32_t lu;                   // the x period in x-offset units, modulo 2^32
 };
 
 // Per-block partial results of the interaction (reduced by sph_reduce_dt).

@@ -185,7 +185,7 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
 // period, which exceeds twice the reach of the stencil.  Along y and z the
 // offsets are cell-relative and (ys, zs) carry the row's cell shift.  Wall
 // targets skip wall candidates (Eq. 36).
-template <int DIM, bool DIAG, bool EQM, bool GEN, bool TAIL>
+template <int DIM, bool DIAG, bool EQM, bool GEN, bool PER, bool TAIL>
 __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64_t i,
                                              uint32_t xa, float ys, float zs,
                                              const TargetData& T, uint32_t j, uint32_t j1,
@@ -213,7 +213,12 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
       if (jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
         double r2d = 0.0;
         for (int d = 0; d < DIM; ++d) {
-          const double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
+          double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
+          if (PER && ((kp.periodic >> d) & 1)) {  // nearest image
+            const double L = d == 0 ? kp.px : (d == 1 ? kp.py : kp.pz);
+            if (e > 0.5 * L) e = __dsub_rn(e, L);
+            else if (e < -0.5 * L) e = __dadd_rn(e, L);
+          }
           r2d = __dadd_rn(r2d, __dmul_rn(e, e));
         }
         c64 += (r2d < kp.support2) ? 1u : 0u;
@@ -243,12 +248,21 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 // 2h is ever cut.  Each range runs as whole groups of 4 and one masked tail
 // group.
 //
+// Periodic components (PER kernels only, Section 2.7): a row index along
+// y or z past either end wraps to the other end (the row's shift (ys, zs)
+// stays that of the unwrapped cell, which is the nearest image since the
+// offsets are cell-relative); along x the cut window may run past either
+// end, and the part beyond is walked as a second range of cells at the
+// other end, with the target's fixed-point x moved by one period so that
+// the 32-bit differences give the nearest image.  Validation keeps every
+// periodic component at least 2R+1 cells long, so no cell is walked twice.
+//
 // The target is not excluded from its own candidates: its self pair adds
 // exactly zero to every sum (v_aa = 0, r_aa = 0 and rho_a - rho_a = 0) and is
 // taken off the count here (fluid targets meet themselves; wall targets skip
 // wall candidates).  DIAG also counts neighbours with an FP64 test on the
 // FP64 positions (c64, self excluded).
-template <int DIM, int R, bool DIAG, bool EQM, bool GEN>
+template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER>
 __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
                                             int64_t i, const float4& pa, const TargetData& T,
                                             int cx, int cy, int cz,
@@ -271,17 +285,26 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
   const float fx =
       (float)(int32_t)(xa - ((uint32_t)(cx % fcells) << (29 - kp.lg_xsub))) * kp.unit_x_f;
   const int reach = R * kp.x_sub;  // the stencil's reach in key cells along x
-  const int xlo = cx - reach < 0 ? 0 : cx - reach;
-  const int xhi = cx + reach >= kp.ncx ? kp.ncx - 1 : cx + reach;
+  const bool perx = PER && (kp.periodic & 1);
+  const bool pery = PER && (kp.periodic & 2);
+  const bool perz = PER && DIM == 3 && (kp.periodic & 4);
+  const int xlo = cx - reach < 0 && !perx ? 0 : cx - reach;
+  const int xhi = cx + reach >= kp.ncx && !perx ? kp.ncx - 1 : cx + reach;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
-    const int z = cz + dz;
-    if (z < 0 || z >= kp.ncz) continue;
+    int z = cz + dz;
+    if (z < 0 || z >= kp.ncz) {
+      if (!perz) continue;
+      z += z < 0 ? kp.ncz : -kp.ncz;
+    }
     const float ez0 = (float)dz * cs - pa.z;  // lower edge of the row's z extent
     const float ez = dz > 0 ? ez0 : (dz < 0 ? -(ez0 + cs) : 0.f);
     for (int dy = -R; dy <= R; ++dy) {
-      const int y = cy + dy;
-      if (y < 0 || y >= kp.ncy) continue;
+      int y = cy + dy;
+      if (y < 0 || y >= kp.ncy) {
+        if (!pery) continue;
+        y += y < 0 ? kp.ncy : -kp.ncy;
+      }
       const float ey0 = (float)dy * cs - pa.y;
       const float ey = dy > 0 ? ey0 : (dy < 0 ? -(ey0 + cs) : 0.f);
       const float w2 = cull2 - ey * ey - ez * ez;
@@ -293,15 +316,29 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
       x1 = x1 > xhi ? xhi : x1;
       const uint32_t row =
           cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-      const uint32_t j0 = cstart[row + x0], j1 = cstart[row + x1 + 1];
       const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
-      uint32_t j = j0;
-      for (; j + 4 <= j1; j += 4)
-        gather_group<DIM, DIAG, EQM, GEN, false>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64,
-                                                 pos64, acc, c64);
-      if (j < j1)
-        gather_group<DIM, DIAG, EQM, GEN, true>(kp, n, i, xa, ys, zs, T, j, j1, pr, vp, pa64,
-                                                pos64, acc, c64);
+      // the candidates of key cells [c0, c1] of the row, with target x bits xv
+      auto walk = [&](int c0, int c1, uint32_t xv) {
+        const uint32_t j0 = cstart[row + c0], j1 = cstart[row + c1 + 1];
+        uint32_t j = j0;
+        for (; j + 4 <= j1; j += 4)
+          gather_group<DIM, DIAG, EQM, GEN, PER, false>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
+                                                        pa64, pos64, acc, c64);
+        if (j < j1)
+          gather_group<DIM, DIAG, EQM, GEN, PER, true>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
+                                                       pa64, pos64, acc, c64);
+      };
+      if (perx) {
+        if (x0 < 0) {  // cells at the far end, one period below
+          walk(kp.ncx + x0, kp.ncx - 1, xa + kp.lu);
+          x0 = 0;
+        }
+        if (x1 >= kp.ncx) {  // cells at the near end, one period above
+          walk(0, x1 - kp.ncx, xa - kp.lu);
+          x1 = kp.ncx - 1;
+        }
+      }
+      walk(x0, x1, xa);
     }
   }
   // the self pair (fluid targets only) was counted and added nothing

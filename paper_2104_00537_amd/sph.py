@@ -48,6 +48,7 @@ class SphParams(C.Structure):
         ("motion_amp", C.c_double), ("motion_omega", C.c_double),
         ("dt_floor", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
         ("visc_nu", C.c_double), ("floating", C.c_int32), ("pad0", C.c_int32),
+        ("period", C.c_double * 3),
     ]
 
 
@@ -160,6 +161,9 @@ def make_params(cp) -> SphParams:
     p.viscosity = int(getattr(cp, "viscosity", 0))
     p.visc_nu = float(getattr(cp, "visc_nu", 0.0))
     p.floating = int(getattr(cp, "floating", 0))
+    period = getattr(cp, "period", (0.0, 0.0, 0.0))
+    for k in range(3):
+        p.period[k] = float(period[k])
     for k in range(3):
         p.ncell[k] = int(cp.ncell[k])
         p.origin[k] = float(cp.origin[k])

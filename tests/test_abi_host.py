@@ -236,3 +236,42 @@ def test_batch_rejects_formulation_options(S):
         with pytest.raises(S.SphError):
             S.sph_batch_describe(ps, [0, 10, 20])
 
+
+
+def test_periodic_params_validate_without_device(S):
+    """A periodic component must span exactly its period in whole cells, at
+    least 2 cell_div + 1 of them (x: ncell[0] divisible by x_sub); periodic
+    cases reject modified DBC, floating bodies, the precision-study arms and
+    the batched path."""
+    import dataclasses
+    from paper_2104_00537_amd import cases
+    c = cases.periodic_box(3, periodic=(0, 1), cell_div=2, x_sub=4)
+    cp = c.params
+    lib = S.lib
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, 16, None)
+    need = S.sph_workspace_bytes(S.make_params(cp), 1000)
+
+    def interact(p, flags=0):
+        return lib.sph_interact(C.byref(p), 1000, C.byref(st), d, d, d, d, None, None, flags, d,
+                                need, None)
+
+    P = S.make_params(cp)
+    assert P.period[0] > 0 and P.period[1] > 0 and P.period[2] == 0
+    # (only calls that are rejected before any device work are made here)
+    bad = [dict(period=(cp.period[0] * 1.001, cp.period[1], 0.0)),      # not the grid extent
+           dict(period=(cp.period[0], cp.period[1], 0.05)),             # not z's grid extent
+           dict(boundary=1), dict(floating=1),
+           dict(ncell=(cp.ncell[0] + 1, cp.ncell[1], cp.ncell[2])),     # not divisible by x_sub
+           ]
+    for kw in bad:
+        assert interact(S.make_params(dataclasses.replace(cp, **kw))) == S.SPH_E_ARG, kw
+    small = cases.periodic_box(2, shape=(8, 10), periodic=(0,), cell_div=2)
+    assert small.params.ncell[0] < 5
+    assert interact(S.make_params(small.params)) == S.SPH_E_ARG
+    for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32):
+        assert interact(P, flags) == S.SPH_E_ARG
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe([S.make_params(cases.dam_break_2d(dp=0.05).params),
+                              S.make_params(cases.periodic_box(2, periodic=(0,)).params)],
+                             [0, 10, 20])
