@@ -140,6 +140,52 @@ def verlet_leg(case, steps, warmup):
             "interactions_per_s": pairs / el, "ns": 40}
 
 
+def case_leg(case, steps=20, warmup=5):
+    """Whole symplectic steps of another case: ms per step, interactions/s
+    and the mean time of each call (HIP events on the launch stream, 3 extra
+    steps)."""
+    import numpy as np
+    import torch
+    from paper_2104_00537_amd.runner import Simulation
+    sim = Simulation(case, "cuda:0")
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    i0 = sim.interaction_count()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pairs = sim.interaction_count() - i0
+    timing = {}
+    for _ in range(3):
+        sim.step(timing=timing)
+    torch.cuda.synchronize()
+    if sim.error() != 0:
+        raise SystemExit(f"device error word {sim.error()} in the {case.params.name} leg")
+    phase_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in timing.items()}
+    return sim, {"n_particles": case.n, "steps": steps, "ms_per_step": el / steps * 1e3,
+                 "interactions_per_s": pairs / el, "phase_ms_per_call": phase_ms}
+
+
+def periodic_leg(args):
+    """A 3-D channel periodic along x and y (Section 2.7): 1.6 x 0.6 m in
+    plan, 0.3 m deep between a bottom and a top wall, at the workload's
+    resolution (cells of a whole number of particle spacings), with a mean
+    flow of 1 m/s along x driven by a body force of 2 m/s^2."""
+    from paper_2104_00537_amd import cases
+    dp = 0.6 / 126
+    g = (2.0, 0.0, -cases.GRAVITY)
+    case = cases.periodic_box(3, shape=(336, 126, 63), dp=dp, periodic=(0, 1), walls=True,
+                              gravity=g, cell_div=args.cell_div, x_sub=args.x_sub)
+    case.vel[0, case.type == cases.FLUID] = 1.0
+    _, res = case_leg(case)
+    res["workload"] = "periodic_channel_3d"
+    res["n_fluid"] = case.n_fluid
+    return res
+
+
 def floating_leg(args, steps=20, warmup=5):
     """A floating box (Section 3.2) at the workload's resolution: the 3-D
     dam-break block released into a tank holding a 0.06 m water layer, with
@@ -335,6 +381,7 @@ def main():
     ap.add_argument("--no-verlet", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-floating", action="store_true")
+    ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -424,6 +471,8 @@ def main():
         res["variants"] = variants_leg(case)
     if not args.no_floating:
         res["floating"] = floating_leg(args)
+    if not args.no_periodic:
+        res["periodic"] = periodic_leg(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:
