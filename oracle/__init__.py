@@ -48,7 +48,7 @@ class OrcParams(C.Structure):
         ("gravity", C.c_double * 3), ("motion_amp", C.c_double),
         ("motion_omega", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
         ("visc_nu", C.c_double), ("boundary", C.c_int32), ("pad2", C.c_int32),
-        ("period", C.c_double * 3),
+        ("period", C.c_double * 3), ("shift_coef", C.c_double), ("shift_fs", C.c_double),
     ]
 
 
@@ -106,6 +106,8 @@ def lib():
         L.orc_body_step.argtypes = [P(OrcParams), C.c_int64, C.c_int32, C.c_double,
                                     P(OrcBody), P(OrcBody)] + [C.c_void_p] * 7
         L.orc_mdbc.argtypes = [P(OrcParams), C.c_int64] + [C.c_void_p] * 7
+        L.orc_shift.argtypes = [P(OrcParams), C.c_int64] + [C.c_void_p] * 4 + \
+            [C.c_double] + [C.c_void_p] * 3
         _lib = L
     return _lib
 
@@ -128,6 +130,8 @@ def params(cp) -> OrcParams:
     period = getattr(cp, "period", (0.0, 0.0, 0.0))
     for k in range(3):
         p.period[k] = float(period[k])
+    p.shift_coef = float(getattr(cp, "shift_coef", 0.0))
+    p.shift_fs = float(getattr(cp, "shift_fs", 0.0))
     for name in ("h", "rho0", "gamma", "c0", "alpha", "delta", "eta2", "cfl",
                  "mass_fluid", "mass_bound", "motion_amp", "motion_omega"):
         setattr(p, name, float(getattr(cp, name)))
@@ -365,6 +369,20 @@ def run_verlet(cp, pos, vel, rho, ptype, nsteps, ns=40, t0=0.0, normal=None):
                               int(ns), C.byref(t), _ptr(dts), C.byref(inter))
     return dict(pos=pos, vel=vel, rho=rho, type=ptype, t=t.value,
                 dt=dts[: int(nsteps)], interactions=int(inter.value), status=int(st))
+
+
+def shift(cp, pos, vel, rho, ptype, dt):
+    """Particle shifting (Section 2.8, Eq. 40-41, 53): returns (C [n],
+    grad C [dim, n], dr [dim, n]) for the given state and time step."""
+    pos, vel, rho = _f64(pos), _f64(vel), _f64(rho)
+    n = rho.shape[0]
+    ptype = np.ascontiguousarray(ptype, dtype=np.uint8)
+    dim = int(cp.dim)
+    conc, grad, dr = np.zeros(n), np.zeros((dim, n)), np.zeros((dim, n))
+    p = params(cp)
+    lib().orc_shift(C.byref(p), n, _ptr(pos), _ptr(vel), _ptr(rho), _ptr(ptype), float(dt),
+                    _ptr(conc), _ptr(grad), _ptr(dr))
+    return conc, grad, dr
 
 
 def mdbc(cp, pos, vel, rho, ptype, normal):

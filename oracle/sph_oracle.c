@@ -727,6 +727,81 @@ int32_t orc_body_step(const orc_params* p, int64_t n, int32_t phase, double dt, 
   return 0;
 }
 
+/* Particle shifting, Section 2.8: Eq. 40-41 with the concentration and its
+ * gradient of Eq. 53, for fluid particles:
+ *   C_a      = sum_{b in P} V_b W_ab, b = a included (the kernel sum of the
+ *              particle distribution: about 1 inside the fluid, lower where
+ *              the support is truncated),
+ *   grad C_a = sum_{b in P} V_b (C_b - C_a) grad_a W_ab,
+ *   dr_a     = -D_s grad C_a,  D_s = A_s h |v_a| dt  (A_s = shift_coef),
+ * with V_b = m_b / rho_b over every non-excluded particle (fluid, walls,
+ * floating).  Particles move from crowded to sparse regions.  With
+ * shift_fs > 0 a particle whose C_a < shift_fs (a support truncated by the
+ * free surface) keeps only the tangential part of dr_a: its component along
+ * n = grad C_a / |grad C_a| is removed (Eq. 54 with a_n = 0, the setting
+ * the paper gives for violent flows).  Non-fluid and excluded
+ * particles get dr = 0 (their C is still computed).
+ * conc [n], grad [dim][n], dr [dim][n]: outputs, each nullable. */
+void orc_shift(const orc_params* p, int64_t n, const double* pos, const double* vel,
+               const double* rho, const uint8_t* type, double dt, double* conc, double* grad,
+               double* dr) {
+  const int dim = p->dim;
+  const double support2 = (2.0 * p->h) * (2.0 * p->h);
+  double* c = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n; ++a) {
+    if (is_excluded(type[a])) continue;
+    double s = 0.0;
+    for (int64_t b = 0; b < n; ++b) {
+      if (is_excluded(type[b])) continue;
+      double r2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        const double d = min_image(p, k, pos[k * n + a] - pos[k * n + b]);
+        r2 += d * d;
+      }
+      if (!(r2 < support2)) continue;
+      s += particle_mass(p, type[b]) / rho[b] * kernel_w(p, sqrt(r2));
+    }
+    c[a] = s;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n; ++a) {
+    double g[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+    if (!is_excluded(type[a]) && is_fluid(type[a])) {
+      for (int64_t b = 0; b < n; ++b) {
+        if (b == a || is_excluded(type[b])) continue;
+        double dx[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+        for (int k = 0; k < dim; ++k) {
+          dx[k] = min_image(p, k, pos[k * n + a] - pos[k * n + b]);
+          r2 += dx[k] * dx[k];
+        }
+        if (!(r2 < support2)) continue;
+        const double f = kernel_fab(p, sqrt(r2));
+        const double w = particle_mass(p, type[b]) / rho[b] * (c[b] - c[a]) * f;
+        for (int k = 0; k < dim; ++k) g[k] += w * dx[k];
+      }
+      double v2 = 0.0;
+      for (int k = 0; k < dim; ++k) v2 += vel[k * n + a] * vel[k * n + a];
+      const double ds = p->shift_coef * p->h * sqrt(v2) * dt;
+      for (int k = 0; k < dim; ++k) d[k] = -ds * g[k];
+      if (p->shift_fs > 0.0 && c[a] < p->shift_fs) {
+        double g2 = 0.0, dn = 0.0;
+        for (int k = 0; k < dim; ++k) g2 += g[k] * g[k];
+        if (g2 > 0.0) {
+          for (int k = 0; k < dim; ++k) dn += d[k] * g[k];
+          for (int k = 0; k < dim; ++k) d[k] -= dn / g2 * g[k];
+        }
+      }
+    }
+    for (int k = 0; k < dim; ++k) {
+      if (grad) grad[k * n + a] = g[k];
+      if (dr) dr[k * n + a] = d[k];
+    }
+    if (conc) conc[a] = c[a];
+  }
+  free(c);
+}
+
 /* Marks particles outside the cell grid as excluded (they leave the
  * computation for good, as the GPU path's binning does). */
 static void mark_excluded(const orc_params* p, int64_t n, const double* pos,
@@ -775,6 +850,7 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
   double* vel_pi = (double*)calloc(nd, sizeof(double));
   orc_body* bodies_n =
       (orc_body*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(orc_body));
+  double* shift = (double*)calloc(nd, sizeof(double));
   int32_t status = 0;
   for (int32_t s = 0; s < nsteps && status == 0; ++s) {
     orc_wrap(p, n, pos, type);
@@ -796,7 +872,13 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
     mdbc_before_pi(p, n, pos, vel, rho, type, normal, vel_pi);
     orc_interact(p, n, pos, vel_pi, rho, type, n, NULL, ace, arho, visc, nbr);
     for (int64_t a = 0; a < n; ++a) count += nbr[a];
+    /* shifting (Section 2.8): computed on the state of the corrector's PI,
+     * added to the corrected positions */
+    if (p->shift_coef > 0.0) orc_shift(p, n, pos, vel_pi, rho, type, dt, NULL, NULL, shift);
     orc_corrector(p, n, dt, *t, pos, vel, rho, type, ace, arho, pos_n, vel_n, rho_n);
+    if (p->shift_coef > 0.0)
+      for (int64_t a = 0; a < n; ++a)
+        for (int k = 0; k < dim; ++k) pos[k * n + a] += shift[k * n + a];
     for (int32_t k = 0; k < n_bodies; ++k)
       if (orc_body_step(p, n, 1, dt, &bodies[k], &bodies_n[k], pos_n, pos, vel, type, ace,
                         NULL, NULL))
@@ -807,7 +889,7 @@ int32_t orc_run(const orc_params* p, int64_t n, double* pos, double* vel,
       if (!is_excluded(type[a]) && !(rho[a] > 0.0 && isfinite(rho[a]))) status = 1;
   }
   free(ace); free(arho); free(visc); free(nbr);
-  free(pos_n); free(vel_n); free(rho_n); free(vel_pi); free(bodies_n);
+  free(pos_n); free(vel_n); free(rho_n); free(vel_pi); free(bodies_n); free(shift);
   return status;
 }
 

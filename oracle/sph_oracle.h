@@ -52,6 +52,9 @@ typedef struct orc_params {
   double period[3];        /* > 0: the domain is periodic along that component
                               with this length, starting at origin (Section
                               2.7); 0: open */
+  double shift_coef;       /* A_s of Eq. 41 (> 0: particle shifting on, 2.8) */
+  double shift_fs;         /* > 0: particles with C < shift_fs keep only the
+                              tangential part of their shift (Eq. 54, a_n = 0) */
 } orc_params;
 
 /* A rigid floating body (Section 3.2): particles [first, first + count) of
@@ -104,6 +107,9 @@ int32_t orc_body_step(const orc_params* p, int64_t n, int32_t phase, double dt, 
 void orc_verlet(const orc_params* p, int64_t n, double dt, double t, int32_t mode,
                 double* pos, double* vel, double* rho, double* vel_p, double* rho_p,
                 const uint8_t* type, const double* ace, const double* arho);
+void orc_shift(const orc_params* p, int64_t n, const double* pos, const double* vel,
+               const double* rho, const uint8_t* type, double dt, double* conc, double* grad,
+               double* dr);
 void orc_mdbc(const orc_params* p, int64_t n, const double* pos, const double* vel,
               const double* rho, const uint8_t* type, const double* normal,
               double* rho_out, double* vel_out);

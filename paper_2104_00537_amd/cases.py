@@ -64,6 +64,10 @@ class CaseParams:
     # periodic length per component (Section 2.7), 0 = open; a periodic
     # component's grid starts at the periodic boundary and spans the period
     period: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    # particle shifting (Section 2.8): A_s of Eq. 41 (0 = off) and the
+    # concentration below which only the tangential shift is kept (0 = none)
+    shift_coef: float = 0.0
+    shift_fs: float = 0.0
     viscosity: int = 0    # 0 artificial (Eq. 21), 1 laminar (Eq. 23)
     visc_nu: float = 1e-6  # kinematic viscosity of the laminar term (water)
     cell_div: int = 1
