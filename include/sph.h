@@ -19,6 +19,8 @@
  *                        imposed motion of moving walls (Eq. 37).
  *   sph_floating_step    SU of rigid floating bodies (Section 3.2, Eq. 47-50),
  *                        after each phase of sph_symplectic_step.
+ *   sph_shifting         particle shifting (Section 2.8, Eq. 40-41, 53) after
+ *                        the corrector.
  *
  * A full step is: bin, interact, reduce_dt, predictor, bin (carrying the saved
  * state along), interact, corrector.
@@ -159,6 +161,11 @@ typedef struct sph_params {
                              the positions it writes) and pairs take the
                              nearest image.  0: open.  Needs boundary 0 and
                              no floating bodies. */
+  double shift_coef;      /* A_s of Eq. 41 (>= 0; see sph_shifting) */
+  double shift_fs;        /* >= 0: fluid particles whose concentration C is
+                             below it (a support truncated by the free
+                             surface) keep only the tangential part of their
+                             shift (Eq. 54 with a_n = 0); 0: none */
 } sph_params;
 
 /* Particle state (SoA device arrays of n particles). */
@@ -294,6 +301,30 @@ sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const d
  * and s->normal set. */
 sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                     const uint32_t* cell_start, void* ws, size_t ws_bytes, void* stream);
+
+/* Particle shifting (Section 2.8: Eq. 40-41 with the concentration and its
+ * gradient of Eq. 53), called right after the corrector (sph_symplectic_step
+ * phase 1) on the same state, before the next sph_bin_cells.  It reads the
+ * interaction view that the last sph_bin_cells / sph_interact pair left in
+ * the workspace (state n+1/2; with modified DBC, its wall densities):
+ *   C_a      = sum_b V_b W_ab over every non-excluded b within 2h, b = a
+ *              included (V_b = m_b / rho_b, the kernel of the case),
+ *   grad C_a = sum_b V_b (C_b - C_a) grad_a W_ab,
+ *   dr_a     = -A_s h |v_a| dt grad C_a   (A_s = p->shift_coef, |v_a| at
+ *              n+1/2, dt the step's),
+ * for every fluid particle a; if p->shift_fs > 0 and C_a < shift_fs, the
+ * component of dr_a along grad C_a is removed (Eq. 54 with a_n = 0).  dr_a
+ * is added to s->pos (the corrected positions, FP64).  Along periodic
+ * components distances take the nearest image.
+ *   conc[n]       out, nullable: C of every particle (FP32, sorted order;
+ *                 0 for excluded particles)
+ *   shift[dim][n] out, nullable: the dr applied (FP32; 0 for non-fluid)
+ * Arithmetic is FP32 on the view's offsets, as in sph_interact.  Needs
+ * p->shift_coef > 0.  Without conc the concentrations live in the
+ * workspace's sort buffers during the call. */
+sph_status sph_shifting(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                        const uint32_t* cell_start, const double* dt, float* conc,
+                        float* shift, void* ws, size_t ws_bytes, void* stream);
 
 /* Floating bodies (Section 3.2).  A body is a rigid object whose particles
  * are the particles of type SPH_FLOATING with id in [id_first, id_first +

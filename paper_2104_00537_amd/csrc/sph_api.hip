@@ -98,6 +98,9 @@ KParams make_kparams(const sph_params& p) {
   k.cs_f = (float)p.cell_size;
   k.inv_csx_f = (float)(p.inv_cell_size * (double)p.x_sub);
   k.unit_x_f = (float)(kFrameCells * p.cell_size / 4294967296.0);
+  k.w_alpha_f = (float)alpha_d;
+  k.shift_k_f = (float)(p.shift_coef * p.h);
+  k.shift_fs_f = (float)p.shift_fs;
   k.gx_f = (float)p.gravity[0];
   k.gy_f = (float)p.gravity[1];
   k.gz_f = (float)p.gravity[2];
@@ -136,6 +139,8 @@ static bool params_ok(const sph_params* p) {
   if (p->kernel != 0 && p->kernel != 1) return false;
   if (p->boundary != 0 && p->boundary != 1) return false;
   if (p->floating != 0 && p->floating != 1) return false;
+  if (!(p->shift_coef >= 0.0) || !isfinite(p->shift_coef)) return false;
+  if (!(p->shift_fs >= 0.0) || !isfinite(p->shift_fs)) return false;
   if (p->floating == 1 && p->boundary != 0) return false;
   // periodic components: the grid spans exactly the period, in whole cells,
   // at least 2 cell_div + 1 of them (so no neighbour cell is reached twice)
@@ -281,6 +286,18 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
   sph_state sv = n > 0 ? *saved : sph_state{}, st = n > 0 ? *s : sph_state{};
   return hip_status(launch_floating(make_kparams(*p), n, phase, dt, bodies, n_bodies, sv, st, ace,
                                     ws, (hipStream_t)stream));
+}
+
+sph_status sph_shifting(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                        const uint32_t* cell_start, const double* dt, float* conc,
+                        float* shift, void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !cell_start || !dt || !ws) return SPH_E_ARG;
+  if (!(p->shift_coef > 0.0)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  if (n == 0) return SPH_OK;
+  return hip_status(launch_shifting(make_kparams(*p), n, *s, key, cell_start, dt, conc, shift, ws,
+                                    (hipStream_t)stream));
 }
 
 int32_t sph_read_error(const void* ws) {

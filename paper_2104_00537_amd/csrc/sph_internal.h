@@ -52,6 +52,8 @@ struct KParams {
   float cs_f, inv_csx_f, unit_x_f;           // cell size, inverse key-cell size along x, x offset unit
   float gx_f, gy_f, gz_f;
   uint32_t lu;                   // the x period in x-offset units, modulo 2^32
+  float w_alpha_f;               // alpha_D of the kernel (shifting's W)
+  float shift_k_f, shift_fs_f;   // A_s h (Eq. 41); surface threshold on C
 };
 
 // Per-block partial results of the interaction (reduced by sph_reduce_dt).

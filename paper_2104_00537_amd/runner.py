@@ -60,6 +60,10 @@ class Simulation:
         self.verlet_ns = int(verlet_ns)
         # floating bodies (Section 3.2): the device body table, advanced by
         # sph_floating_step after each symplectic phase
+        # particle shifting (Section 2.8) after each corrector
+        self.shifting = float(getattr(cp, "shift_coef", 0.0)) > 0.0
+        if self.shifting and integrator != "symplectic":
+            raise ValueError("particle shifting takes the symplectic integrator")
         self.bodies = None
         if getattr(case, "bodies", None):
             if integrator != "symplectic":
@@ -123,6 +127,9 @@ class Simulation:
         if self.bodies is not None:
             call("floating", S.sph_floating_step, P, n, 1, self.dt, self.bodies, s1, a, self.ace,
                  self.ws, stream=stream)
+        if self.shifting:
+            call("shifting", S.sph_shifting, P, n, a, self.key, self.cell_start, self.dt, self.ws,
+                 stream=stream)
         self.steps_done += 1
 
     def _step_verlet(self, stream, timing):

@@ -28,6 +28,7 @@ SPH_INTERACT_ABS_F32 = 4
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
            "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_floating_step",
+           "sph_shifting",
            "sph_read_error", "sph_clear_error", "sph_strerror",
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
            "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
@@ -48,7 +49,7 @@ class SphParams(C.Structure):
         ("motion_amp", C.c_double), ("motion_omega", C.c_double),
         ("dt_floor", C.c_double), ("kernel", C.c_int32), ("viscosity", C.c_int32),
         ("visc_nu", C.c_double), ("floating", C.c_int32), ("pad0", C.c_int32),
-        ("period", C.c_double * 3),
+        ("period", C.c_double * 3), ("shift_coef", C.c_double), ("shift_fs", C.c_double),
     ]
 
 
@@ -102,6 +103,9 @@ def _load() -> C.CDLL:
     L.sph_floating_step.restype = C.c_int32
     L.sph_floating_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP, C.c_int32,
                                     P(SphState), P(SphState), VP, VP, C.c_size_t, VP]
+    L.sph_shifting.restype = C.c_int32
+    L.sph_shifting.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP, VP,
+                               C.c_size_t, VP]
     L.sph_read_error.restype = C.c_int32
     L.sph_read_error.argtypes = [VP]
     L.sph_clear_error.restype = C.c_int32
@@ -164,6 +168,8 @@ def make_params(cp) -> SphParams:
     period = getattr(cp, "period", (0.0, 0.0, 0.0))
     for k in range(3):
         p.period[k] = float(period[k])
+    p.shift_coef = float(getattr(cp, "shift_coef", 0.0))
+    p.shift_fs = float(getattr(cp, "shift_fs", 0.0))
     for k in range(3):
         p.ncell[k] = int(cp.ncell[k])
         p.origin[k] = float(cp.origin[k])
@@ -313,6 +319,15 @@ def sph_floating_step(params: SphParams, n: int, phase: int, dt: torch.Tensor,
     _check(lib.sph_floating_step(C.byref(params), int(n), int(phase), _ptr(dt), _ptr(bodies),
                                  int(nb), C.byref(saved.c()), C.byref(s.c()), _ptr(ace),
                                  _ptr(ws), ws.numel(), _stream(stream)), "sph_floating_step")
+
+
+def sph_shifting(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                 cell_start: torch.Tensor, dt: torch.Tensor, ws: torch.Tensor,
+                 conc: Optional[torch.Tensor] = None, shift: Optional[torch.Tensor] = None,
+                 stream=None):
+    _check(lib.sph_shifting(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
+                            _ptr(dt), _ptr(conc), _ptr(shift), _ptr(ws), ws.numel(),
+                            _stream(stream)), "sph_shifting")
 
 
 def sph_read_error(ws: torch.Tensor) -> int:

@@ -275,3 +275,28 @@ def test_periodic_params_validate_without_device(S):
         S.sph_batch_describe([S.make_params(cases.dam_break_2d(dp=0.05).params),
                               S.make_params(cases.periodic_box(2, periodic=(0,)).params)],
                              [0, 10, 20])
+
+
+def test_shifting_validates_without_device(S):
+    """sph_shifting needs shift_coef > 0; negative or non-finite shifting
+    parameters are rejected by every call."""
+    import dataclasses
+    from paper_2104_00537_amd import cases
+    cp = cases.dam_break_2d(dp=0.05).params
+    lib = S.lib
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, 16, None)
+    need = S.sph_workspace_bytes(S.make_params(cp), 1000)
+
+    def shifting(p, ws=need):
+        return lib.sph_shifting(C.byref(p), 1000, C.byref(st), d, d, d, None, None, d, ws, None)
+
+    assert shifting(S.make_params(cp)) == S.SPH_E_ARG                 # shift_coef = 0
+    ok = dataclasses.replace(cp, shift_coef=2.0)
+    assert shifting(S.make_params(ok), ws=need - 1) == S.SPH_E_WORKSPACE
+    for kw in (dict(shift_coef=-1.0), dict(shift_coef=2.0, shift_fs=-0.5),
+               dict(shift_coef=float("inf"))):
+        P = S.make_params(dataclasses.replace(cp, **kw))
+        assert shifting(P) == S.SPH_E_ARG
+        assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, 0, d,
+                                need, None) == S.SPH_E_ARG
