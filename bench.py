@@ -186,6 +186,19 @@ def periodic_leg(args):
     return res
 
 
+def shifting_leg(args):
+    """The workload itself with particle shifting (Section 2.8: A_s = 2,
+    tangential shift where C < 0.9) after every corrector."""
+    import dataclasses
+    from paper_2104_00537_amd import cases
+    case = workload(args.workload, args.cell_div, args.x_sub)
+    case = cases.Case(dataclasses.replace(case.params, shift_coef=2.0, shift_fs=0.9), case.pos,
+                      case.vel, case.rho, case.type, dict(case.meta), case.normal)
+    _, res = case_leg(case)
+    res["workload"] = args.workload + "+shifting"
+    return res
+
+
 def floating_leg(args, steps=20, warmup=5):
     """A floating box (Section 3.2) at the workload's resolution: the 3-D
     dam-break block released into a tank holding a 0.06 m water layer, with
@@ -382,6 +395,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-floating", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
+    ap.add_argument("--no-shifting", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -473,6 +487,8 @@ def main():
         res["floating"] = floating_leg(args)
     if not args.no_periodic:
         res["periodic"] = periodic_leg(args)
+    if not args.no_shifting:
+        res["shifting"] = shifting_leg(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(case, sim, args.cpu_seconds)
     if not args.no_serve:
