@@ -13,7 +13,7 @@ namespace sph {
 // Visits every candidate b within 2h of a target (view position pa, key
 // cell (cx, cy, cz)): the rows of the neighbour cells, each cut to the key
 // cells the support sphere reaches, as in the interaction's walk (periodic
-// components wrapped the same way when PER), one candidate at a time.
+// components wrapped the same way when PER), in groups of 4 candidates.
 // Calls f(j, dx, dy, dz, r2, pb) with r_ab = (dx, dy, dz) and |r_ab|^2 < 4h^2.
 template <int DIM, int R, bool PER, typename F>
 __device__ inline void visit_neighbours(const KParams& kp, const float4& pa, int cx, int cy,
@@ -57,15 +57,23 @@ __device__ inline void visit_neighbours(const KParams& kp, const float4& pa, int
       x1 = x1 > xhi ? xhi : x1;
       const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
+      // candidates 4 at a time, all loads in flight (the view is padded by
+      // kViewPad entries, so a group may read past the last particle;
+      // those candidates are masked)
       auto range = [&](int c0, int c1, uint32_t xv) {
         const uint32_t j1 = cstart[row + c1 + 1];
-        for (uint32_t j = cstart[row + c0]; j < j1; ++j) {
-          const float4 pb = pr[j];
-          const float dx = (float)(int32_t)(xv - __float_as_uint(pb.x)) * kp.unit_x_f;
-          const float ddy = ys - pb.y;
-          const float ddz = DIM == 3 ? zs - pb.z : 0.f;
-          const float r2 = dx * dx + ddy * ddy + ddz * ddz;
-          if (r2 < kp.support2_f) f(j, dx, ddy, ddz, r2, pb);
+        for (uint32_t j = cstart[row + c0]; j < j1; j += 4) {
+          float4 pb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pb[u] = pr[j + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float dx = (float)(int32_t)(xv - __float_as_uint(pb[u].x)) * kp.unit_x_f;
+            const float ddy = ys - pb[u].y;
+            const float ddz = DIM == 3 ? zs - pb[u].z : 0.f;
+            const float r2 = dx * dx + ddy * ddy + ddz * ddz;
+            if (j + u < j1 && r2 < kp.support2_f) f(j + u, dx, ddy, ddz, r2, pb[u]);
+          }
         }
       };
       if (perx) {
