@@ -396,6 +396,10 @@ def main():
     ap.add_argument("--no-floating", action="store_true")
     ap.add_argument("--no-periodic", action="store_true")
     ap.add_argument("--no-shifting", action="store_true")
+    ap.add_argument("--timing", choices=["all", "interact", "none"], default="interact",
+                    help="calls bracketed by HIP events inside the timed steps")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="> 0: replay the timed steps as HIP graphs of this many steps")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
@@ -428,10 +432,19 @@ def main():
         raise SystemExit(f"device error word {sim.error()} after warm-up")
     inter0 = sim.interactions.clone()
     timing = {}
+    if args.timing == "interact":
+        sim.timed_calls = ("interact",)
+    if args.graph_steps > 0:
+        if args.steps % args.graph_steps:
+            raise SystemExit("--steps must be a multiple of --graph-steps")
+        sim.capture(args.graph_steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sim.step(timing=timing)
+    if args.graph_steps > 0:
+        sim.replay(args.steps // args.graph_steps)
+    else:
+        for _ in range(args.steps):
+            sim.step(timing=None if args.timing == "none" else timing)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     err = sim.error()
@@ -439,8 +452,23 @@ def main():
         raise SystemExit(f"device error word {err} during the timed steps")
     d_inter = (sim.interactions - inter0).cpu().numpy().astype(np.int64)
     pairs, wall_pairs = int(d_inter[0]), int(d_inter[1])
+    launches = 2 * args.steps  # two interaction passes per symplectic step
+    phase_src = "timed steps"
+    if not timing or set(timing) == {"interact"}:
+        # the other calls' durations from 5 extra steps after the timed region
+        extra = {}
+        sim.timed_calls = None
+        for _ in range(5):
+            sim.step(timing=extra)
+        torch.cuda.synchronize()
+        for k, v in extra.items():
+            if k not in timing:
+                timing[k] = v
+        phase_src = "timed steps (interact)" if "interact" in timing and \
+            len(timing["interact"]) == launches else "5 steps after the timed region"
+        if not args.graph_steps and args.timing == "none":
+            phase_src = "5 steps after the timed region"
     phase_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in timing.items()}
-    launches = len(timing["interact"])
     t_int = phase_ms["interact"] * 1e-3
     flops = (FLOPS_FLUID_PAIR * (pairs - wall_pairs) + FLOPS_WALL_PAIR * wall_pairs) / launches
     achieved = flops / t_int / 1e12
@@ -470,6 +498,8 @@ def main():
         "steps_per_s": args.steps / el,
         "interactions_per_step": pairs / args.steps,
         "phase_ms_per_call": phase_ms,
+        "phase_ms_source": phase_src,
+        "timing_mode": {"events": args.timing, "graph_steps": args.graph_steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "traffic_unit": "bytes/launch", "kernel": kernel,

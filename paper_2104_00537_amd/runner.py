@@ -47,6 +47,8 @@ class Simulation:
         self.interactions = torch.zeros(2, dtype=torch.int64, device=dev)
         self.steps_done = 0
         self.graph = None
+        # with `timing`, record events around these calls only (None: all)
+        self.timed_calls = None
         # sph_interact flags: 0 for the production pass, or a precision-study
         # arm (S.SPH_INTERACT_F64 / S.SPH_INTERACT_ABS_F32)
         self.flags = int(flags)
@@ -88,7 +90,7 @@ class Simulation:
         s0, s1 = self.saved
 
         def call(name, fn, *args, **kw):
-            if timing is None:
+            if timing is None or (self.timed_calls and name not in self.timed_calls):
                 fn(*args, **kw)
                 return
             st = stream if stream is not None else torch.cuda.current_stream()
@@ -140,7 +142,7 @@ class Simulation:
         s0, s1 = self.saved
 
         def call(name, fn, *args, **kw):
-            if timing is None:
+            if timing is None or (self.timed_calls and name not in self.timed_calls):
                 fn(*args, **kw)
                 return
             st = stream if stream is not None else torch.cuda.current_stream()
