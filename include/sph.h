@@ -73,10 +73,13 @@ enum {
   SPH_ERR_NONFINITE = 1u,   /* non-finite velocity, or density not in (0, inf) */
   SPH_ERR_EXCLUDED = 2u,    /* a particle left the cell grid and was excluded */
   SPH_ERR_DT_FLOOR = 4u,    /* dt fell below dt_floor, or is not finite */
-  SPH_ERR_FLOATING = 8u     /* sph_floating_step: a floating particle whose id is
+  SPH_ERR_FLOATING = 8u,    /* sph_floating_step: a floating particle whose id is
                                in no body's range, a body whose particles are
                                not all present, body counts summing above n,
                                or a singular inertia */
+  SPH_ERR_MARGIN = 16u      /* an interaction with SPH_INTERACT_REUSE_CELLS after
+                               particles moved half a cell or more since the
+                               binning: neighbours may have been missed */
 };
 
 /* flags of sph_interact */
@@ -95,7 +98,17 @@ enum {
    * viscosity, ddt 0 or 1, no floating bodies, no periodic components);
    * other options are rejected with SPH_E_ARG. */
   SPH_INTERACT_F64 = 2u,
-  SPH_INTERACT_ABS_F32 = 4u
+  SPH_INTERACT_ABS_F32 = 4u,
+  /* The cells of the last sph_bin_cells are reused for a state whose
+   * particles have moved since (the second interaction of a symplectic
+   * step, after sph_refresh_view): the search reaches one cell further and
+   * widens its cut by the largest distance a particle moved since the
+   * binning, which sph_symplectic_step's predictor and sph_floating_step's
+   * predictor phase record in the workspace.  The same pairs within 2h are
+   * found as after a new binning (only the summation order differs).  Sets
+   * SPH_ERR_MARGIN if a particle moved half a cell or more.  Combines with
+   * SPH_DIAG_COUNT_F64; not with the precision-study arms or modified DBC. */
+  SPH_INTERACT_REUSE_CELLS = 8u
 };
 
 /* Case constants, passed by pointer to host memory and copied by value into
@@ -237,6 +250,19 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s,
                         float* ace, float* arho, float* visc,
                         uint32_t* nbr_count, uint32_t flags, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* Rewrites the interaction view that sph_bin_cells left in the workspace
+ * from the state's current positions, velocities and densities, keeping the
+ * sorted order and the cells of that binning (key, cell_start unchanged),
+ * for an interaction with SPH_INTERACT_REUSE_CELLS: the second interaction
+ * of a symplectic step, whose particles moved by dt/2 v since the binning,
+ * without sorting again.  Positions are not wrapped along periodic
+ * components (they stay relative to their binned cells; the next
+ * sph_bin_cells wraps them).  A particle now outside the grid along an open
+ * component is excluded as sph_bin_cells would exclude it (type bit,
+ * SPH_ERR_EXCLUDED); it stays in its slot but meets no target. */
+sph_status sph_refresh_view(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* SU, Eq. 35: dt = cfl * min(sqrt(h / max_a |f_a|), h / (c0 + max_a visc_a))
  * over fluid particles, reduced from the last sph_interact on this workspace.

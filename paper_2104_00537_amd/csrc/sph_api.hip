@@ -214,9 +214,14 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
                         void* stream) {
   if (!params_ok(p) || !n_ok(n) || !cell_start || !ws) return SPH_E_ARG;
   if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
-  // one of: none, the FP64 diagnostic count, or one precision-study arm
-  if (flags != 0 && flags != SPH_DIAG_COUNT_F64 && flags != SPH_INTERACT_F64 &&
-      flags != SPH_INTERACT_ABS_F32)
+  // none, the FP64 diagnostic count and/or reused cells, or one
+  // precision-study arm alone
+  const uint32_t reuse = flags & SPH_INTERACT_REUSE_CELLS;
+  const uint32_t base = flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS;
+  if (base != 0 && base != SPH_DIAG_COUNT_F64 && base != SPH_INTERACT_F64 &&
+      base != SPH_INTERACT_ABS_F32)
+    return SPH_E_ARG;
+  if (reuse && (base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 || p->boundary != 0))
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
   if ((flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) &&
@@ -228,6 +233,15 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
   sph_state s0 = n > 0 ? *s : sph_state{};
   return hip_status(launch_interact(kp, n, s0, key, cell_start, ace, arho, visc, nbr_count, flags,
                                     ws, (hipStream_t)stream));
+}
+
+sph_status sph_refresh_view(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
+                            void* ws, size_t ws_bytes, void* stream) {
+  if (!params_ok(p) || !n_ok(n) || !ws) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state s0 = n > 0 ? *s : sph_state{};
+  return hip_status(launch_refresh_view(make_kparams(*p), n, s0, key, ws, (hipStream_t)stream));
 }
 
 sph_status sph_reduce_dt(const sph_params* p, int64_t n, double* dt, uint64_t* interactions,

@@ -88,8 +88,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
         const int cy = (int)(rest % (uint32_t)kp.ncy);
         const int cz = (int)(rest / (uint32_t)kp.ncy);
         uint32_t c64 = 0;
-        gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp, cstart, nullptr,
-                                 acc, c64);
+        gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
+                                                      cstart, nullptr, acc, c64,
+                                                      kp.support2_f * 1.0002f);
         write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
         cnt = acc.cnt;
         cntw = T.fluid ? 0u : acc.cnt;
@@ -174,7 +175,9 @@ __global__ void k_batch_symplectic(const SlotEntry* __restrict__ tab, int ns, in
   if (i >= n) return;
   const int sl = find_slot(tab, ns, i);
   const SlotMotion M = mot[sl];
-  if (symplectic_one<PHASE>(tab[sl].kp, n, i, M.dt, M.dmove, M.vmove, saved, s, ace, arho)) {
+  double disp2 = 0.0;  // (the batched path always rebins)
+  if (symplectic_one<PHASE>(tab[sl].kp, n, i, M.dt, M.dmove, M.vmove, saved, s, ace, arho,
+                            disp2)) {
     set_error(err, SPH_ERR_NONFINITE);
     set_error(&slot_err[sl], SPH_ERR_NONFINITE);
   }

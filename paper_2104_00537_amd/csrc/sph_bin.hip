@@ -7,10 +7,13 @@
 namespace sph {
 
 // -------------------------------------------------------------- cell keys --
+// (a new binning also restarts the record of the largest displacement)
 __global__ void k_cell_keys(KParams kp, int64_t n, const double* __restrict__ pos,
-                            const uint8_t* __restrict__ type, uint32_t* __restrict__ key) {
+                            const uint8_t* __restrict__ type, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ disp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (i == 0) *disp = 0u;
   key[i] = cell_key_local(kp, pos, type, n, i);
 }
 
@@ -291,6 +294,47 @@ __global__ void k_reorder(KParams kp, int64_t n, const uint32_t* __restrict__ pe
     set_error(err, SPH_ERR_EXCLUDED);
 }
 
+// ------------------------------------------------------------ view refresh --
+// Rewrites the view of sorted slot i from the state's current position,
+// velocity and density, relative to the cell its key (from the last
+// binning) names; positions are not wrapped (they stay relative to that
+// cell).  A particle that is now outside the grid along an open component
+// is excluded, as a binning would; its view entry gets NaN offsets and zero
+// density, so it meets no target in the cell range it still sits in.
+__global__ void k_refresh_view(KParams kp, int64_t n, const uint32_t* __restrict__ key,
+                               sph_state s, float4* __restrict__ pr, float4* __restrict__ vp,
+                               uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint8_t t = s.type[i];
+  if (t & SPH_EXCLUDED) return;  // its entry was written by the binning
+  if (cell_key_local(kp, s.pos, s.type, n, i) == kp.ncell_total) {
+    s.type[i] = t | SPH_EXCLUDED;
+    set_error(err, SPH_ERR_EXCLUDED);
+    const float nan = __builtin_nanf("");
+    pr[i] = make_float4(0.f, nan, nan, 0.f);
+    vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  double x[3] = {0.0, 0.0, 0.0};
+  float v[3] = {0.f, 0.f, 0.f};
+  for (int d = 0; d < kp.dim; ++d) {
+    x[d] = s.pos[d * n + i];
+    v[d] = s.vel[d * n + i];
+  }
+  write_view(kp, i, x, v, s.rho[i], t, key[i], pr, vp);
+}
+
+hipError_t launch_refresh_view(const KParams& kp, int64_t n, const sph_state& s,
+                               const uint32_t* key, void* ws, hipStream_t st) {
+  const WsLayout L = ws_layout(n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_refresh_view, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, st, kp, n, key, s, ws_ptr<float4>(ws, L.view_pr),
+                       ws_ptr<float4>(ws, L.view_vp), ws_ptr<uint32_t>(ws, L.err));
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host --
 int key_bits(uint32_t ncell_total) {
   int bits = 1;
@@ -359,7 +403,7 @@ hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, s
   const unsigned gridn = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
     hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type,
-                       ws_ptr<uint32_t>(ws, L.keyA));
+                       ws_ptr<uint32_t>(ws, L.keyA), &ws_ptr<WsHeader>(ws, L.err)->disp);
     const hipError_t e = radix_sort(n, kp.ncell_total, key, perm, ws, st);
     if (e != hipSuccess) return e;
   }

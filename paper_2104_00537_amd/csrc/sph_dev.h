@@ -59,6 +59,10 @@ __device__ inline double tait_ratio(const KParams& kp, double r) {
   return pow(r / kp.rho0, kp.gamma) - 1.0;
 }
 
+__device__ inline void write_view(const KParams& kp, int64_t i, const double* x, const float* v,
+                                  float rho, uint8_t t, uint32_t lkey, float4* __restrict__ pr,
+                                  float4* __restrict__ vp);
+
 // Gathers particle src into sorted slot i and writes the two float4 the
 // interaction reads (the "view"):
 //   pr = {local position (dim components), 0, +rho fluid / -rho wall}
@@ -109,6 +113,18 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
     vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     return newly;
   }
+  write_view(kp, i, x, v, rho, t, lkey, pr, vp);
+  return newly;
+}
+
+// The view entry of sorted slot i (a live particle) from its position x
+// (FP64), velocity v, density rho and type t, relative to the cell of key
+// lkey (see reorder_one).  The position may lie slightly outside that cell
+// (a view refreshed after the particle moved): the offsets then fall
+// outside [0, cs), which the interaction handles like any other.
+__device__ inline void write_view(const KParams& kp, int64_t i, const double* x, const float* v,
+                                  float rho, uint8_t t, uint32_t lkey, float4* __restrict__ pr,
+                                  float4* __restrict__ vp) {
   const int c0 = (int)(lkey % (uint32_t)kp.ncx);
   const uint32_t rest = lkey / (uint32_t)kp.ncx;
   const int c[3] = {c0, (int)(rest % (uint32_t)kp.ncy), (int)(rest / (uint32_t)kp.ncy)};
@@ -122,7 +138,6 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   const double pw = tait_ratio(kp, (double)rho);
   pr[i] = make_float4(o[0], o[1], o[2], is_fluid(t) ? rho : -rho);
   vp[i] = make_float4(v[0], v[1], v[2], (float)(kp.b_tait * pw));
-  return newly;
 }
 
 // Imposed wall motion along x: D(t) = (A/w^2)(1 - cos wt), v(t) = (A/w) sin wt.
@@ -141,11 +156,12 @@ __device__ inline double motion_vel(const KParams& kp, double t) {
 // lines 3-4, Eq. 34 line 2) from the saved state.  dmove / vmove are the
 // imposed wall displacement since t and velocity at the phase's end time.
 // Returns true if the new state is not finite or the density not positive.
+// disp2 (PHASE 0) receives the squared distance the particle moved.
 template <int PHASE>
 __device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, double dt,
                                       double dmove, double vmove, const sph_state& saved,
                                       const sph_state& s, const float* __restrict__ ace,
-                                      const float* __restrict__ arho) {
+                                      const float* __restrict__ arho, double& disp2) {
   const uint8_t t = s.type[i];
   if (PHASE == 0) {
     for (int d = 0; d < kp.dim; ++d) {
@@ -161,7 +177,9 @@ __device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, d
       const double a = (double)ace[d * n + i];
       if (PHASE == 0) {
         const double v = (double)s.vel[d * n + i];
-        s.pos[d * n + i] = s.pos[d * n + i] + 0.5 * dt * v;
+        const double x0 = s.pos[d * n + i], x1 = x0 + 0.5 * dt * v;
+        s.pos[d * n + i] = x1;
+        disp2 += (x1 - x0) * (x1 - x0);
         const float v1 = (float)(v + 0.5 * dt * a);
         s.vel[d * n + i] = v1;
         bad |= !isfinite(v1);
@@ -177,6 +195,7 @@ __device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, d
   } else if ((t & 0x7f) == SPH_BOUND_MOVING) {
     s.pos[i] = saved.pos[i] + dmove;
     s.vel[i] = (float)vmove;
+    if (PHASE == 0) disp2 += dmove * dmove;
   }
   double r;
   if (PHASE == 0) {

@@ -268,16 +268,18 @@ __global__ void k_float_finish(KParams kp, const double* __restrict__ dtp,
 // ------------------------------------------------------ particle motion --
 // r_k = R0 + Q (r_k^n - R0^n), v_k = V + Omega x (r_k - R0) (Eq. 50), from
 // the saved state n.
+// With disp (the predictor), also records the largest distance moved.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_float_move(
     int64_t n, const sph_body* __restrict__ bodies, const uint32_t* __restrict__ map,
     const uint8_t* __restrict__ type, const uint32_t* __restrict__ id,
     const BodyMotion* __restrict__ motion, const double* __restrict__ pos_n,
-    double* __restrict__ pos, float* __restrict__ vel) {
+    double* __restrict__ pos, float* __restrict__ vel, uint32_t* __restrict__ disp) {
   const int b = blockIdx.y, p = blockIdx.x;
   const int64_t base = body_base(bodies, b);
   const int64_t first = bodies[b].id_first, count = bodies[b].count;
   const BodyMotion& m = motion[b];
+  double dmax2 = 0.0;
   for (int64_t k = (int64_t)p * kBlock + threadIdx.x; k < count;
        k += (int64_t)kFloatParts * kBlock) {
     const int64_t i = slot_particle(n, map, type, id, base + k, first + k);
@@ -298,11 +300,16 @@ __global__ __launch_bounds__(kBlock) void k_float_move(
       w[1] = m.omega[2] * r[0] - m.omega[0] * r[2];
       w[2] = m.omega[0] * r[1] - m.omega[1] * r[0];
     }
+    double d2 = 0.0;
     for (int d = 0; d < DIM; ++d) {
-      pos[d * n + i] = m.to[d] + r[d];
+      const double x1 = m.to[d] + r[d];
+      d2 += (x1 - pos[d * n + i]) * (x1 - pos[d * n + i]);
+      pos[d * n + i] = x1;
       vel[d * n + i] = (float)(m.vel[d] + w[d]);
     }
+    dmax2 = d2 > dmax2 ? d2 : dmax2;
   }
+  if (disp) record_displacement(sqrt(dmax2), disp);
 }
 
 hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double* dt,
@@ -313,6 +320,8 @@ hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double
   uint32_t* map = ws_ptr<uint32_t>(ws, L.keyB);
   double* part = ws_ptr<double>(ws, L.fpart);
   BodyMotion* motion = ws_ptr<BodyMotion>(ws, L.fmotion);
+  // the predictor's moves count towards the displacement since the binning
+  uint32_t* disp = phase == 0 ? &ws_ptr<WsHeader>(ws, L.err)->disp : nullptr;
   if (n > 0) {
     const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_float_map, dim3(grid), dim3(kBlock), 0, st, n, s.type, s.id, bodies, nb,
@@ -329,7 +338,7 @@ hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double
       hipLaunchKernelGGL((k_float_finish<2, 1>), dim3(1), dim3(64), 0, st, kp, dt, bodies, nb,
                          part, motion, err);
     hipLaunchKernelGGL(k_float_move<2>, g2, dim3(kBlock), 0, st, n, bodies, map, s.type, s.id,
-                       motion, saved.pos, s.pos, s.vel);
+                       motion, saved.pos, s.pos, s.vel, disp);
   } else {
     hipLaunchKernelGGL(k_float_reduce<3>, g2, dim3(kBlock), 0, st, n, bodies, map, s.type, s.id,
                        s.pos, ace, part);
@@ -340,7 +349,7 @@ hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double
       hipLaunchKernelGGL((k_float_finish<3, 1>), dim3(1), dim3(64), 0, st, kp, dt, bodies, nb,
                          part, motion, err);
     hipLaunchKernelGGL(k_float_move<3>, g2, dim3(kBlock), 0, st, n, bodies, map, s.type, s.id,
-                       motion, saved.pos, s.pos, s.vel);
+                       motion, saved.pos, s.pos, s.vel, disp);
   }
   return hipGetLastError();
 }

@@ -25,6 +25,16 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
+  // cells reused after a view refresh (R above the cells' own stencil): cull
+  // with the support widened by the largest displacement since the binning
+  float cull2 = kp.support2_f * 1.0002f;
+  if (R > kp.cell_div) {
+    const float delta = __uint_as_float(hdr->disp);
+    const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
+    cull2 = rc * rc;
+    if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)
+      set_error(&hdr->err, SPH_ERR_MARGIN);
+  }
   if (i < n) {
     PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
     TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
@@ -47,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
       const int cy = (int)(rest % (uint32_t)kp.ncy);
       const int cz = (int)(rest / (uint32_t)kp.ncy);
       gather_walk<DIM, R, DIAG, EQM, GEN, PER>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart,
-                                              pos64, acc, c64);
+                                              pos64, acc, c64, cull2);
       const uint32_t c = DIAG ? c64 : acc.cnt;
       write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
       cnt_out = acc.cnt;
@@ -204,6 +214,8 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
     return hipGetLastError();
   }
   const bool diag = (flags & SPH_DIAG_COUNT_F64) != 0;
+  // reused cells: one more cell of reach (the kernels read the displacement)
+  const int reach = kp.cell_div + ((flags & SPH_INTERACT_REUSE_CELLS) ? 1 : 0);
   const bool eqm = kp.mass_f == kp.mass_b;
   const bool gen = kp.kernel != 0 || kp.viscosity != 0 || kp.ddt == 2 || kp.floating != 0;
   const bool per = kp.periodic != 0;  // periodic cases run the general kernel with PER
@@ -217,19 +229,18 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   else SPH_LAUNCH(D, RR, G, PP, false, false)
 #define SPH_LAUNCH_P(D, RR, G) \
   if (eqm) SPH_LAUNCH_G(D, RR, G, true); else SPH_LAUNCH_G(D, RR, G, false)
+#define SPH_LAUNCH_R(D, RR) \
+  if (diag) SPH_LAUNCH_P(D, RR, true); else SPH_LAUNCH_P(D, RR, false)
   if (kp.dim == 2) {
-    if (kp.cell_div == 1) {
-      if (diag) SPH_LAUNCH_P(2, 1, true); else SPH_LAUNCH_P(2, 1, false);
-    } else {
-      if (diag) SPH_LAUNCH_P(2, 2, true); else SPH_LAUNCH_P(2, 2, false);
-    }
+    if (reach == 1) { SPH_LAUNCH_R(2, 1); }
+    else if (reach == 2) { SPH_LAUNCH_R(2, 2); }
+    else { SPH_LAUNCH_R(2, 3); }
   } else {
-    if (kp.cell_div == 1) {
-      if (diag) SPH_LAUNCH_P(3, 1, true); else SPH_LAUNCH_P(3, 1, false);
-    } else {
-      if (diag) SPH_LAUNCH_P(3, 2, true); else SPH_LAUNCH_P(3, 2, false);
-    }
+    if (reach == 1) { SPH_LAUNCH_R(3, 1); }
+    else if (reach == 2) { SPH_LAUNCH_R(3, 2); }
+    else { SPH_LAUNCH_R(3, 3); }
   }
+#undef SPH_LAUNCH_R
 #undef SPH_LAUNCH_G
 #undef SPH_LAUNCH_P
 #undef SPH_LAUNCH

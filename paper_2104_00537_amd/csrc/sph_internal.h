@@ -71,7 +71,9 @@ struct WsHeader {
   uint32_t err;      // SPH_ERR_* bits
   uint32_t nred;     // BlockRed entries written by the last interaction pass
   uint32_t nwall;    // wall particles listed by the last sph_mdbc (its work list)
-  uint32_t pad[61];
+  uint32_t disp;     // bits of the largest displacement since the last binning
+                     // (a non-negative float; set to 0 by the binning)
+  uint32_t pad[60];
 };
 
 // ---------------------------------------------------------------- batches --
@@ -193,6 +195,29 @@ __device__ inline float wave_max(float v) {
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
   return v;
 }
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off, 64));
+  return v;
+}
+
+// Raises the recorded largest displacement since the binning to cover d
+// (>= 0, FP64) for the calling block: one atomic per block.  Every thread
+// of the block calls this (threads without a displacement pass 0).
+__device__ inline void record_displacement(double d, uint32_t* disp) {
+  __shared__ uint32_t wmax[kBlock / 64];
+  // rounded up, so the recorded float is never below the FP64 value
+  uint32_t b = __float_as_uint(__double2float_ru(d));
+  b = wave_max_u32(b);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wmax[wave] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
+    if (m) atomicMax(disp, m);
+  }
+}
+
 __device__ inline uint32_t wave_sum(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

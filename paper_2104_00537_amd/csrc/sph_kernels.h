@@ -26,6 +26,8 @@ void launch_cell_start(const uint32_t* key, int64_t n, uint32_t last_key, uint32
 hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, sph_state& out,
                             const sph_state* cin, sph_state* cout, uint32_t* key,
                             uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st);
+hipError_t launch_refresh_view(const KParams& kp, int64_t n, const sph_state& s,
+                               const uint32_t* key, void* ws, hipStream_t st);
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, float* ace, float* arho, float* visc,
                            uint32_t* nbr, uint32_t flags, void* ws, hipStream_t st);

@@ -210,7 +210,8 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
     if (TAIL) hit[u] = hit[u] && j + u < j1;
     if (DIAG) {
       const uint32_t jj = j + u;
-      if (jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f)) {
+      // (pb.w == 0: a particle excluded by a view refresh, no neighbour)
+      if (jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f) && pb[u].w != 0.f) {
         double r2d = 0.0;
         for (int d = 0; d < DIM; ++d) {
           double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
@@ -257,6 +258,17 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 // the 32-bit differences give the nearest image.  Validation keeps every
 // periodic component at least 2R+1 cells long, so no cell is walked twice.
 //
+// Reused cells (an interaction after a view refresh, R one above the
+// stencil of the cells): the particles have moved by up to delta since the
+// binning, so a neighbour within 2h of the target's current position lies
+// in a cell whose binned extent is within 2h + delta of it.  The caller
+// passes the culling radius squared accordingly (cull2), and one more cell
+// of reach covers the target's own drift out of its cell while 2 delta
+// stays below a cell.  Along x the visited candidates then lie within 4
+// cells plus delta of the target; one that aliases across the 8-cell
+// fixed-point period is at least 4 cells away either way, beyond 2h, so it
+// is never a neighbour.
+//
 // The target is not excluded from its own candidates: its self pair adds
 // exactly zero to every sum (v_aa = 0, r_aa = 0 and rho_a - rho_a = 0) and is
 // taken off the count here (fluid targets meet themselves; wall targets skip
@@ -270,14 +282,13 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
                                             const float4* __restrict__ vp,
                                             const uint32_t* __restrict__ cstart,
                                             const double* __restrict__ pos64, PairAcc& acc,
-                                            uint32_t& c64) {
-  static_assert(2 * (R + 1) < kFrameCells, "the x period must exceed twice the stencil reach");
+                                            uint32_t& c64, float cull2) {
+  static_assert(R <= 3, "the x period (8 cells) must exceed twice the stencil reach");
   static_assert(kFrameCells == 8, "x offsets use 2^29 units per cell");
   double pa64[3] = {0.0, 0.0, 0.0};
   if (DIAG)
     for (int d = 0; d < DIM; ++d) pa64[d] = pos64[d * n + i];
   const float cs = kp.cs_f;
-  const float cull2 = kp.support2_f * 1.0002f;
   const uint32_t xa = __float_as_uint(pa.x);
   // the target's offset inside its own key cell along x (key cells of
   // cs/x_sub: 2^(29 - lg x_sub) fixed-point units each)

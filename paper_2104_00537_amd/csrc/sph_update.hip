@@ -61,11 +61,17 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_dt(KParams kp, const Blo
 }
 
 // phase 0: predictor, saving state n; phase 1: corrector from the saved state.
+// The predictor also records the largest distance a particle moved (for an
+// interaction that reuses the cells of the last binning).
 template <int PHASE>
-__global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ dtp,
-                             const double* __restrict__ tp, sph_state saved, sph_state s,
-                             const float* __restrict__ ace, const float* __restrict__ arho,
-                             uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(kBlock) void k_symplectic(KParams kp, int64_t n,
+                                                       const double* __restrict__ dtp,
+                                                       const double* __restrict__ tp,
+                                                       sph_state saved, sph_state s,
+                                                       const float* __restrict__ ace,
+                                                       const float* __restrict__ arho,
+                                                       uint32_t* __restrict__ err,
+                                                       uint32_t* __restrict__ disp) {
   __shared__ double shm[3];
   if (threadIdx.x == 0) {
     const double dt = *dtp, t = *tp;
@@ -76,9 +82,11 @@ __global__ void k_symplectic(KParams kp, int64_t n, const double* __restrict__ d
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s, ace, arho))
+  double disp2 = 0.0;
+  if (i < n && symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s, ace, arho,
+                                     disp2))
     set_error(err, SPH_ERR_NONFINITE);
+  if (PHASE == 0) record_displacement(sqrt(disp2), disp);
 }
 
 // Verlet update (Eq. 30 for MODE 0, Eq. 31 for MODE 1) of the sorted state.
@@ -122,15 +130,15 @@ hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const doub
                              sph_state& saved, sph_state& s, const float* ace, const float* arho,
                              void* ws, hipStream_t st) {
   const WsLayout L = ws_layout(n);
-  uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
+  WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
     if (phase == 0)
       hipLaunchKernelGGL(k_symplectic<0>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, err);
+                         ace, arho, &hdr->err, &hdr->disp);
     else
       hipLaunchKernelGGL(k_symplectic<1>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, err);
+                         ace, arho, &hdr->err, &hdr->disp);
   }
   if (phase == 1) hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
   return hipGetLastError();

@@ -4,7 +4,12 @@ A symplectic step (Section 2.5.2) is
     bin(n) -> interact(n) -> reduce_dt -> predictor -> bin(n+1/2, carrying the
     saved state n) -> interact(n+1/2) -> corrector (t += dt)
 with dt and t kept in device memory, so a step enqueues no host work and can
-be captured once in a HIP graph and replayed.
+be captured once in a HIP graph and replayed.  With reuse_cells (the default
+where it applies) the second binning is replaced by a refresh of the
+interaction view on the cells of the first, and the second interaction
+searches one cell further with the cut widened by the largest displacement
+since the binning: the same pairs, one sort and one reorder fewer per step;
+the state then alternates between the two buffers from step to step.
 """
 from __future__ import annotations
 
@@ -18,7 +23,8 @@ from . import sph as S
 
 class Simulation:
     def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0,
-                 integrator: str = "symplectic", verlet_ns: int = 40):
+                 integrator: str = "symplectic", verlet_ns: int = 40,
+                 reuse_cells: Optional[bool] = None):
         cp = case.params
         if cell_div is not None and cell_div != cp.cell_div:
             raise ValueError("cell_div is fixed by the case's grid")
@@ -66,6 +72,15 @@ class Simulation:
         self.shifting = float(getattr(cp, "shift_coef", 0.0)) > 0.0
         if self.shifting and integrator != "symplectic":
             raise ValueError("particle shifting takes the symplectic integrator")
+        # the second interaction of a step on the cells of the first (not
+        # with modified DBC, shifting or a precision-study arm, whose passes
+        # search the cells without a displacement margin)
+        can_reuse = (integrator == "symplectic" and not self.mdbc and not self.shifting
+                     and self.flags in (0, S.SPH_DIAG_COUNT_F64))
+        if reuse_cells and not can_reuse:
+            raise ValueError("reuse_cells needs the symplectic integrator, DBC walls, no "
+                             "shifting and no precision-study arm")
+        self.reuse_cells = can_reuse if reuse_cells is None else bool(reuse_cells)
         self.bodies = None
         if getattr(case, "bodies", None):
             if integrator != "symplectic":
@@ -85,6 +100,8 @@ class Simulation:
         timing[name] as (start, end) pairs."""
         if self.integrator == "verlet":
             return self._step_verlet(stream, timing)
+        if self.reuse_cells:
+            return self._step_reuse(stream, timing)
         P, n = self.params, self.n
         a, b = self.states
         s0, s1 = self.saved
@@ -132,6 +149,53 @@ class Simulation:
         if self.shifting:
             call("shifting", S.sph_shifting, P, n, a, self.key, self.cell_start, self.dt, self.ws,
                  stream=stream)
+        self.steps_done += 1
+
+    def _call(self, stream, timing):
+        def call(name, fn, *args, **kw):
+            if timing is None or (self.timed_calls and name not in self.timed_calls):
+                fn(*args, **kw)
+                return
+            st = stream if stream is not None else torch.cuda.current_stream()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn(*args, **kw)
+            e1.record(st)
+            timing.setdefault(name, []).append((e0, e1))
+        return call
+
+    def _step_reuse(self, stream, timing):
+        """A symplectic step with one binning: the n+1/2 interaction reuses
+        the cells of state n (sph_refresh_view, SPH_INTERACT_REUSE_CELLS);
+        the saved state n needs no carrying, and the result stays in the
+        other buffer (the two swap roles every step)."""
+        P, n = self.params, self.n
+        a, b = self.states
+        s0 = self.saved[0]
+        call = self._call(stream, timing)
+        call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
+             self.ws, stream=stream)
+        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
+             self.ws, flags=self.flags, stream=stream)
+        call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
+             interactions=self.interactions, stream=stream)
+        call("symplectic", S.sph_symplectic_step, P, n, 0, self.dt, self.t, s0, b, self.ace,
+             self.arho, self.ws, stream=stream)
+        if self.bodies is not None:
+            call("floating", S.sph_floating_step, P, n, 0, self.dt, self.bodies, s0, b, self.ace,
+                 self.ws, stream=stream)
+        call("refresh_view", S.sph_refresh_view, P, n, b, self.key, self.ws, stream=stream)
+        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
+             self.ws, flags=self.flags | S.SPH_INTERACT_REUSE_CELLS, stream=stream)
+        call("reduce_dt", S.sph_reduce_dt, P, n, self.dt_half, self.ws,
+             interactions=self.interactions, stream=stream)
+        call("symplectic", S.sph_symplectic_step, P, n, 1, self.dt, self.t, s0, b, self.ace,
+             self.arho, self.ws, stream=stream)
+        if self.bodies is not None:
+            call("floating", S.sph_floating_step, P, n, 1, self.dt, self.bodies, s0, b, self.ace,
+                 self.ws, stream=stream)
+        self.states = [b, a]
         self.steps_done += 1
 
     def _step_verlet(self, stream, timing):
@@ -183,6 +247,9 @@ class Simulation:
             if self.steps_done % self.verlet_ns or k % self.verlet_ns or k % 2:
                 raise ValueError("a Verlet graph must start at a multiple of verlet_ns and "
                                  "span an even multiple of it")
+        if self.reuse_cells and int(steps_per_graph) % 2:
+            raise ValueError("with reuse_cells the state buffers alternate every step: a graph "
+                             "must span an even number of steps")
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):

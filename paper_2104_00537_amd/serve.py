@@ -351,10 +351,13 @@ def serve_plain(reqs: List[Request], device="cuda", use_graph: bool = True,
             time.sleep(r.arrival - now)
         r.start = time.perf_counter() - t0
         sim = Simulation(r.case, device)
-        if use_graph and r.steps > 1:
+        if use_graph and r.steps > 2:
             sim.step()
-            sim.capture(1)
-            sim.replay(r.steps - 1)
+            k = 2 if sim.reuse_cells else 1  # (the buffers alternate per step)
+            sim.capture(k)
+            reps = (r.steps - 1) // k
+            sim.replay(reps)
+            sim.run(r.steps - 1 - reps * k)
         else:
             sim.run(r.steps)
         torch.cuda.synchronize()

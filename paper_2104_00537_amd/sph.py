@@ -21,12 +21,15 @@ LIB_PATH = os.path.join(_PKG, "libsph.so")
 SPH_OK, SPH_E_ARG, SPH_E_WORKSPACE, SPH_E_HIP = 0, -1, -2, -3
 SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_FLOATING, SPH_EXCLUDED = 0, 1, 2, 3, 0x80
 SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR, SPH_ERR_FLOATING = 1, 2, 4, 8
+SPH_ERR_MARGIN = 16
 SPH_MAX_BODIES = 64
 SPH_DIAG_COUNT_F64 = 1
 SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
+SPH_INTERACT_REUSE_CELLS = 8
 
-EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_interact", "sph_reduce_dt",
+EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_interact",
+           "sph_reduce_dt",
            "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_floating_step",
            "sph_shifting",
            "sph_read_error", "sph_clear_error", "sph_strerror",
@@ -90,6 +93,8 @@ def _load() -> C.CDLL:
     L.sph_interact.restype = C.c_int32
     L.sph_interact.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP, VP,
                                C.c_uint32, VP, C.c_size_t, VP]
+    L.sph_refresh_view.restype = C.c_int32
+    L.sph_refresh_view.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_reduce_dt.restype = C.c_int32
     L.sph_reduce_dt.argtypes = [P(SphParams), C.c_int64, VP, VP, VP, VP, C.c_size_t, VP]
     L.sph_symplectic_step.restype = C.c_int32
@@ -251,6 +256,12 @@ def sph_interact(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
     _check(lib.sph_interact(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
                             _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), int(flags), _ptr(ws),
                             ws.numel(), _stream(stream)), "sph_interact")
+
+
+def sph_refresh_view(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                     ws: torch.Tensor, stream=None):
+    _check(lib.sph_refresh_view(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(ws),
+                                ws.numel(), _stream(stream)), "sph_refresh_view")
 
 
 def sph_reduce_dt(params: SphParams, n: int, dt: torch.Tensor, ws: torch.Tensor,

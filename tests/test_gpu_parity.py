@@ -336,8 +336,9 @@ def _oracle_step(cp, st, dt=None, t=0.0):
     return out, dt_n, amax, rmax
 
 
+@pytest.mark.parametrize("reuse", [True, False])
 @pytest.mark.parametrize("maker", ["dam2d", "slosh3d"])
-def test_one_symplectic_step(maker):
+def test_one_symplectic_step(maker, reuse):
     """One full step (NL, PI, dt, predictor, NL with carry, PI, corrector)
     against the oracle's step from the same state, with the GPU's dt.  The
     bound: the 1e-4 force/density-rate tolerance times dt, plus FP32 storage
@@ -347,7 +348,7 @@ def test_one_symplectic_step(maker):
         c = _perturbed(cases.dam_break_2d(), 13, vel=0.5)
     else:
         c = _perturbed(cases.sloshing_3d(dp=0.04, seed=1), 14, vel=0.2)
-    sim = Simulation(c, DEV)
+    sim = Simulation(c, DEV, reuse_cells=reuse)
     sim.t.fill_(0.3)  # moving walls away from t = 0
     sim.step()
     torch.cuda.synchronize()
@@ -394,13 +395,15 @@ def test_dam_break_2d_front_1000_steps():
     assert fronts_o[-1] > 0.4 + 0.005
 
 
-def test_determinism_and_graph_replay():
+@pytest.mark.parametrize("reuse", [True, False])
+def test_determinism_and_graph_replay(reuse):
     c = _perturbed(cases.dam_break_2d(dp=0.015), 21, vel=0.3)
-    a = Simulation(c, DEV)
-    b = Simulation(c, DEV)
-    a.run(5)
+    a = Simulation(c, DEV, reuse_cells=reuse)
+    b = Simulation(c, DEV, reuse_cells=reuse)
+    k = 2 if reuse else 1  # with reused cells the buffers alternate per step
+    a.run(2 + 3 * k)
     b.run(2)
-    b.capture(1)
+    b.capture(k)
     for _ in range(3):
         b.replay(1)
         torch.cuda.synchronize()
