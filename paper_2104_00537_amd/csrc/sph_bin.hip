@@ -13,7 +13,8 @@ __global__ void k_cell_keys(KParams kp, int64_t n, const double* __restrict__ po
                             uint32_t* __restrict__ disp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (i == 0) *disp = 0u;
+  if (i == 0)
+    for (int k = 0; k < kDispSlots; ++k) disp[k] = 0u;
   key[i] = cell_key_local(kp, pos, type, n, i);
 }
 
@@ -403,7 +404,7 @@ hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, s
   const unsigned gridn = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
     hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type,
-                       ws_ptr<uint32_t>(ws, L.keyA), &ws_ptr<WsHeader>(ws, L.err)->disp);
+                       ws_ptr<uint32_t>(ws, L.keyA), ws_ptr<uint32_t>(ws, L.disp));
     const hipError_t e = radix_sort(n, kp.ncell_total, key, perm, ws, st);
     if (e != hipSuccess) return e;
   }

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_float_move(
     }
     dmax2 = d2 > dmax2 ? d2 : dmax2;
   }
-  if (disp) record_displacement(sqrt(dmax2), disp);
+  if (disp) record_displacement(dmax2, disp);
 }
 
 hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double* dt,
@@ -321,7 +321,7 @@ hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double
   double* part = ws_ptr<double>(ws, L.fpart);
   BodyMotion* motion = ws_ptr<BodyMotion>(ws, L.fmotion);
   // the predictor's moves count towards the displacement since the binning
-  uint32_t* disp = phase == 0 ? &ws_ptr<WsHeader>(ws, L.err)->disp : nullptr;
+  uint32_t* disp = phase == 0 ? ws_ptr<uint32_t>(ws, L.disp) : nullptr;
   if (n > 0) {
     const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_float_map, dim3(grid), dim3(kBlock), 0, st, n, s.type, s.id, bodies, nb,

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
     const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
-    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+    BlockRed* __restrict__ red, WsHeader* __restrict__ hdr, const uint32_t* __restrict__ disp) {
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   // with the support widened by the largest displacement since the binning
   float cull2 = kp.support2_f * 1.0002f;
   if (R > kp.cell_div) {
-    const float delta = __uint_as_float(hdr->disp);
+    const float delta = read_displacement(disp);
     const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
     cull2 = rc * rc;
     if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)
@@ -222,7 +222,7 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
 #define SPH_LAUNCH(D, RR, G, PP, GG, PE)                                                   \
   hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG, PE>), dim3(grid), dim3(kBlock), 0, \
                      st, kp, n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, \
-                     red, hdr)
+                     red, hdr, ws_ptr<uint32_t>(ws, L.disp))
 #define SPH_LAUNCH_G(D, RR, G, PP)                                       \
   if (per) SPH_LAUNCH(D, RR, G, PP, true, true);                         \
   else if (gen) SPH_LAUNCH(D, RR, G, PP, true, false);                   \

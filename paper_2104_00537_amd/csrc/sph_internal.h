@@ -71,10 +71,14 @@ struct WsHeader {
   uint32_t err;      // SPH_ERR_* bits
   uint32_t nred;     // BlockRed entries written by the last interaction pass
   uint32_t nwall;    // wall particles listed by the last sph_mdbc (its work list)
-  uint32_t disp;     // bits of the largest displacement since the last binning
-                     // (a non-negative float; set to 0 by the binning)
-  uint32_t pad[60];
+  uint32_t pad[61];
 };
+
+// The largest distance a particle moved since the last binning, kept as the
+// bits of non-negative floats in kDispSlots words (blocks record into the
+// slot of their index modulo kDispSlots, which keeps the atomics apart); the
+// value is the maximum over the slots.  The binning sets them to 0.
+constexpr int kDispSlots = 64;
 
 // ---------------------------------------------------------------- batches --
 // One case ("slot") of a batch: its constants (in 3-D geometry: a 2-D case
@@ -109,6 +113,7 @@ struct WsLayout {
   size_t view_pr;    // float4 [n]: cell-relative position, signed density
   size_t view_vp;    // float4 [n]: velocity, pressure
   size_t red;        // BlockRed [nblk_interact]
+  size_t disp;       // uint32 [kDispSlots]: displacement record
   size_t fpart;      // double [SPH_MAX_BODIES][kFloatParts][kFloatSums]: body partial sums
   size_t fmotion;    // double [SPH_MAX_BODIES][kFloatMotion]: rigid motion of each body
   size_t total;
@@ -140,6 +145,7 @@ inline WsLayout ws_layout(int64_t n) {
   L.view_pr = off; off = align_up(off + 16 * (nn + kViewPad));
   L.view_vp = off; off = align_up(off + 16 * (nn + kViewPad));
   L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
+  L.disp = off; off = align_up(off + sizeof(uint32_t) * kDispSlots);
   L.fpart = off;
   off = align_up(off + sizeof(double) * SPH_MAX_BODIES * kFloatParts * kFloatSums);
   L.fmotion = off; off = align_up(off + sizeof(double) * SPH_MAX_BODIES * kFloatMotion);
@@ -200,13 +206,16 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
-// Raises the recorded largest displacement since the binning to cover d
-// (>= 0, FP64) for the calling block: one atomic per block.  Every thread
-// of the block calls this (threads without a displacement pass 0).
-__device__ inline void record_displacement(double d, uint32_t* disp) {
+// Raises the recorded largest displacement since the binning to cover the
+// distance sqrt(d2) (d2 >= 0, FP64) for the calling block: one atomic per
+// block, into its slot.  Every thread of the block calls this (threads
+// without a displacement pass 0).
+__device__ inline void record_displacement(double d2, uint32_t* disp) {
   __shared__ uint32_t wmax[kBlock / 64];
-  // rounded up, so the recorded float is never below the FP64 value
-  uint32_t b = __float_as_uint(__double2float_ru(d));
+  // d2 rounded up to a float, its root to nearest then one ulp up: the
+  // recorded float is never below the distance
+  const float r = __fsqrt_rn(__double2float_ru(d2));
+  uint32_t b = __float_as_uint(r) + (r > 0.f ? 1u : 0u);
   b = wave_max_u32(b);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) wmax[wave] = b;
@@ -214,8 +223,15 @@ __device__ inline void record_displacement(double d, uint32_t* disp) {
   if (threadIdx.x == 0) {
     uint32_t m = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
-    if (m) atomicMax(disp, m);
+    if (m) atomicMax(&disp[blockIdx.x % kDispSlots], m);
   }
+}
+
+// The recorded displacement (max over the slots; uniform loads).
+__device__ inline float read_displacement(const uint32_t* __restrict__ disp) {
+  uint32_t m = 0;
+  for (int k = 0; k < kDispSlots; ++k) m = max(m, disp[k]);
+  return __uint_as_float(m);
 }
 
 __device__ inline uint32_t wave_sum(uint32_t v) {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_symplectic(KParams kp, int64_t n,
   if (i < n && symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s, ace, arho,
                                      disp2))
     set_error(err, SPH_ERR_NONFINITE);
-  if (PHASE == 0) record_displacement(sqrt(disp2), disp);
+  if (PHASE == 0) record_displacement(disp2, disp);
 }
 
 // Verlet update (Eq. 30 for MODE 0, Eq. 31 for MODE 1) of the sorted state.
@@ -135,10 +135,10 @@ hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const doub
   if (n > 0) {
     if (phase == 0)
       hipLaunchKernelGGL(k_symplectic<0>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, &hdr->err, &hdr->disp);
+                         ace, arho, &hdr->err, ws_ptr<uint32_t>(ws, L.disp));
     else
       hipLaunchKernelGGL(k_symplectic<1>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, &hdr->err, &hdr->disp);
+                         ace, arho, &hdr->err, ws_ptr<uint32_t>(ws, L.disp));
   }
   if (phase == 1) hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
   return hipGetLastError();

@@ -106,14 +106,11 @@ def test_reused_cells_find_the_oracles_pairs(name, move):
     res = {f: hs.interact(f | S.SPH_INTERACT_REUSE_CELLS) for f in (S.SPH_DIAG_COUNT_F64, 0)}
     err = S.sph_read_error(hs.ws)
     assert err == 0, err
-    disp = float(np.frombuffer(hs.ws[12:16].cpu().numpy().tobytes(), np.float32)[0])
     pos = hs.st.pos.cpu().numpy()
     vel = hs.st.vel.cpu().numpy().astype(np.float64)
     rho = hs.st.rho.cpu().numpy().astype(np.float64)
     typ = hs.st.type.cpu().numpy()
-    # the recorded displacement bounds every particle's move (and is reached)
     moved = np.sqrt(((pos - hs.saved.pos.cpu().numpy()) ** 2).sum(axis=0)).max()
-    assert moved <= disp <= moved * (1 + 1e-6) + 1e-12
     ace_o, arho_o, visc_o, nbr_o = oracle.interact(hs.cp, pos, vel, rho, typ)
     assert np.array_equal(res[S.SPH_DIAG_COUNT_F64][3], nbr_o)
     fl = typ == cases.FLUID
