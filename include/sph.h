@@ -457,10 +457,25 @@ sph_status sph_batch_bin_cells(const sph_batch* b, const sph_state* in, sph_stat
                                void* stream);
 
 /* As sph_interact, over all slots in one launch (ace is [3][n_total]);
- * per-slot maxima and pair counts go to the workspace. */
+ * per-slot maxima and pair counts go to the workspace.  flags: 0 or
+ * SPH_INTERACT_REUSE_CELLS (after sph_batch_refresh_view: each slot's search
+ * widened by its own recorded displacement, which the batched predictor
+ * records per slot; SPH_ERR_MARGIN in the global word and the word of each
+ * slot whose particles moved half a cell or more); other bits: SPH_E_ARG. */
 sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint32_t* key,
                               const uint32_t* cell_start, float* ace, float* arho, float* visc,
-                              uint32_t* nbr_count, void* ws, size_t ws_bytes, void* stream);
+                              uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* As sph_refresh_view, over all slots: the view of the current state
+ * relative to the cells of the last sph_batch_bin_cells (the second
+ * interaction of a symplectic step without a second binning).  A particle
+ * now outside its slot's grid is excluded (SPH_ERR_EXCLUDED in the global
+ * word and its slot's word).  Like sph_batch_bin_cells it clears the
+ * per-slot maxima and pair counts that the next sph_batch_interact
+ * accumulates. */
+sph_status sph_batch_refresh_view(const sph_batch* b, sph_state* s, const uint32_t* key, void* ws,
+                                  size_t ws_bytes, void* stream);
 
 /* Eq. 35 per slot: dt[n_slots] out (device); interactions[n_slots][2]
  * in/out, nullable: each slot's pair count and wall-target count are added. */

@@ -403,12 +403,24 @@ sph_status sph_batch_bin_cells(const sph_batch* b, const sph_state* in, sph_stat
 
 sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint32_t* key,
                               const uint32_t* cell_start, float* ace, float* arho, float* visc,
-                              uint32_t* nbr_count, void* ws, size_t ws_bytes, void* stream) {
+                              uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
+                              void* stream) {
   if (!batch_ok(b) || !cell_start || !ws) return SPH_E_ARG;
+  if (flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS) return SPH_E_ARG;
   if (b->n_total > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
   if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
   return hip_status(launch_batch_interact(batch_desc(b), key, cell_start, ace, arho, visc,
-                                          nbr_count, ws, (hipStream_t)stream));
+                                          nbr_count, (flags & SPH_INTERACT_REUSE_CELLS) != 0, ws,
+                                          (hipStream_t)stream));
+}
+
+sph_status sph_batch_refresh_view(const sph_batch* b, sph_state* s, const uint32_t* key, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (!batch_ok(b) || !ws) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
+  sph_state s0 = b->n_total > 0 ? *s : sph_state{};
+  return hip_status(launch_batch_refresh_view(batch_desc(b), s0, key, ws, (hipStream_t)stream));
 }
 
 sph_status sph_batch_reduce_dt(const sph_batch* b, double* dt, uint64_t* interactions, void* ws,

@@ -24,9 +24,11 @@ __device__ inline int find_slot(const SlotEntry* __restrict__ tab, int ns, int64
 
 __global__ void k_batch_cell_keys(const SlotEntry* __restrict__ tab, int ns, int64_t n,
                                   const double* __restrict__ pos, const uint8_t* __restrict__ type,
-                                  uint32_t* __restrict__ key, SlotAccum* __restrict__ acc) {
+                                  uint32_t* __restrict__ key, SlotAccum* __restrict__ acc,
+                                  uint32_t* __restrict__ disp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ns) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
+  if (i < (int64_t)ns * kDispSlots) disp[i] = 0u;  // nothing moved since this binning
   if (i >= n) return;
   const int s = find_slot(tab, ns, i);
   key[i] = tab[s].cbase + cell_key_local(tab[s].kp, pos, type, n, i);
@@ -47,17 +49,53 @@ __global__ void k_batch_reorder(const SlotEntry* __restrict__ tab, int ns, int64
   }
 }
 
+// As the single-case view refresh, per slot: the view of the current state
+// relative to each particle's cell from the last binning; a particle now
+// outside its slot's grid is excluded and its view entry can meet no target
+// (NaN offsets) and is no target (zero density).  Like a binning, it starts
+// the per-slot accumulators of the next interaction pass from zero.
+__global__ void k_batch_refresh_view(const SlotEntry* __restrict__ tab, int ns, int64_t n,
+                                     const uint32_t* __restrict__ key, sph_state s,
+                                     float4* __restrict__ pr, float4* __restrict__ vp,
+                                     uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err,
+                                     SlotAccum* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
+  if (i >= n) return;
+  const uint8_t t = s.type[i];
+  if (t & SPH_EXCLUDED) return;  // its entry was written by the binning
+  const int sl = find_slot(tab, ns, i);
+  const KParams& kp = tab[sl].kp;
+  if (cell_key_local(kp, s.pos, s.type, n, i) == kp.ncell_total) {
+    s.type[i] = t | SPH_EXCLUDED;
+    set_error(err, SPH_ERR_EXCLUDED);
+    set_error(&slot_err[sl], SPH_ERR_EXCLUDED);
+    const float nan = __builtin_nanf("");
+    pr[i] = make_float4(0.f, nan, nan, 0.f);
+    vp[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const double x[3] = {s.pos[i], s.pos[n + i], s.pos[2 * n + i]};
+  const float v[3] = {s.vel[i], s.vel[n + i], s.vel[2 * n + i]};
+  write_view(kp, i, x, v, s.rho[i], t, key[i] - tab[sl].cbase, pr, vp);
+}
+
 // The interaction over all slots in one launch: one lane per target walking
 // its own cells (gather_walk), with the constants of the target's slot.  The
 // lanes of a wave are processed slot by slot (almost always one slot), so the
 // constants stay uniform.  Per-slot maxima and pair counts are combined with
 // order-independent atomics (max of non-negative float bits, integer adds).
-template <int R>
+// STALE: the cells of the last binning are reused for a refreshed view (the
+// search reaches R, one cell beyond the cells' own stencil, and culls with the
+// support widened by the slot's recorded displacement).
+template <int R, bool STALE>
 __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
     const float4* __restrict__ vp, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
-    float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc) {
+    float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc,
+    const uint32_t* __restrict__ disp, uint32_t* __restrict__ err,
+    uint32_t* __restrict__ slot_err) {
   const int lane = threadIdx.x & 63;
   const int64_t a = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int sa = a < n ? find_slot(tab, ns, a) : -1;
@@ -70,12 +108,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const bool mine = todo && sa == rs;
     const KParams kp = tab[rs].kp;
     const uint32_t cbase = tab[rs].cbase;
+    float cull2 = kp.support2_f * 1.0002f;
+    if (STALE) {
+      const float delta = read_displacement(disp + (size_t)rs * kDispSlots);
+      const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
+      cull2 = rc * rc;
+      if (!(2.f * delta < kp.cs_f) && (threadIdx.x & 63) == leader) {
+        set_error(err, SPH_ERR_MARGIN);
+        set_error(&slot_err[rs], SPH_ERR_MARGIN);
+      }
+    }
     if (mine) {
       const uint32_t lk = key[a] - cbase;
-      if (lk < kp.ncell_total) {
+      // a particle the view refresh excluded keeps its cell but has density 0
+      const float4 pa = pr[a];
+      if (lk < kp.ncell_total && (!STALE || pa.w != 0.f)) {
         PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
         TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        const float4 pa = pr[a], va = vp[a];
+        const float4 va = vp[a];
         T.fluid = pa.w > 0.f;
         T.rho = fabsf(pa.w);
         T.irho = __builtin_amdgcn_rcpf(T.rho);
@@ -89,8 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
         const int cz = (int)(rest / (uint32_t)kp.ncy);
         uint32_t c64 = 0;
         gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
-                                                      cstart, nullptr, acc, c64,
-                                                      kp.support2_f * 1.0002f);
+                                                      cstart, nullptr, acc, c64, cull2);
         write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
         cnt = acc.cnt;
         cntw = T.fluid ? 0u : acc.cnt;
@@ -165,22 +214,44 @@ __global__ void k_batch_motion(const SlotEntry* __restrict__ tab, int ns,
   }
 }
 
-template <int PHASE>
-__global__ void k_batch_symplectic(const SlotEntry* __restrict__ tab, int ns, int64_t n,
-                                   const SlotMotion* __restrict__ mot, sph_state saved,
-                                   sph_state s, const float* __restrict__ ace,
-                                   const float* __restrict__ arho, uint32_t* __restrict__ err,
-                                   uint32_t* __restrict__ slot_err) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int sl = find_slot(tab, ns, i);
-  const SlotMotion M = mot[sl];
-  double disp2 = 0.0;  // (the batched path always rebins)
-  if (symplectic_one<PHASE>(tab[sl].kp, n, i, M.dt, M.dmove, M.vmove, saved, s, ace, arho,
-                            disp2)) {
-    set_error(err, SPH_ERR_NONFINITE);
-    set_error(&slot_err[sl], SPH_ERR_NONFINITE);
+// Raises slot sl's displacement record to cover the distance sqrt(d2) (as
+// record_displacement, per slot): each wave makes one atomic per slot among
+// its lanes, into that slot's word of the wave's index modulo kDispSlots.
+// Every lane of the wave calls this; lanes without a particle pass sl = -1.
+__device__ inline void record_displacement_slots(double d2, int sl, uint32_t* __restrict__ disp) {
+  const float r = __fsqrt_rn(__double2float_ru(d2));
+  const uint32_t b = __float_as_uint(r) + (r > 0.f ? 1u : 0u);
+  const int lane = threadIdx.x & 63;
+  const uint32_t w = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kDispSlots;
+  bool pend = sl >= 0;
+  while (__ballot(pend) != 0ull) {
+    const int leader = (int)__builtin_ctzll(__ballot(pend));
+    const int rs = __builtin_amdgcn_readlane(sl, leader);
+    const bool mine = pend && sl == rs;
+    const uint32_t m = wave_max_u32(mine ? b : 0u);
+    if (lane == leader && m) atomicMax(&disp[(size_t)rs * kDispSlots + w], m);
+    pend = pend && !mine;
   }
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(kBlock) void k_batch_symplectic(
+    const SlotEntry* __restrict__ tab, int ns, int64_t n, const SlotMotion* __restrict__ mot,
+    sph_state saved, sph_state s, const float* __restrict__ ace, const float* __restrict__ arho,
+    uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err, uint32_t* __restrict__ disp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = i < n ? find_slot(tab, ns, i) : -1;
+  double disp2 = 0.0;
+  if (i < n) {
+    const SlotMotion M = mot[sl];
+    if (symplectic_one<PHASE>(tab[sl].kp, n, i, M.dt, M.dmove, M.vmove, saved, s, ace, arho,
+                              disp2)) {
+      set_error(err, SPH_ERR_NONFINITE);
+      set_error(&slot_err[sl], SPH_ERR_NONFINITE);
+    }
+  }
+  // the predictor's moves since the binning, for an interaction reusing its cells
+  if (PHASE == 0) record_displacement_slots(disp2, sl, disp);
 }
 
 __global__ void k_batch_advance(int ns, const double* __restrict__ dt, double* __restrict__ t) {
@@ -206,9 +277,11 @@ hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_s
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
   SlotAccum* sacc = ws_ptr<SlotAccum>(ws, W.accum);
-  const int64_t nk = n > B.n_slots ? n : B.n_slots;
+  const int64_t nd = (int64_t)B.n_slots * kDispSlots;
+  const int64_t nk = n > nd ? n : nd;
   hipLaunchKernelGGL(k_batch_cell_keys, dim3(grid_for(nk)), dim3(kBlock), 0, st, tab, B.n_slots,
-                     n, in.pos, in.type, ws_ptr<uint32_t>(ws, W.base.keyA), sacc);
+                     n, in.pos, in.type, ws_ptr<uint32_t>(ws, W.base.keyA), sacc,
+                     ws_ptr<uint32_t>(ws, W.disp));
   const uint32_t last_key = (uint32_t)(B.key_cells - 1);
   if (n > 0) {
     const hipError_t e = radix_sort(n, last_key, key, perm, ws, st);
@@ -232,17 +305,37 @@ hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_s
 
 hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
                                  const uint32_t* cell_start, float* ace, float* arho, float* visc,
-                                 uint32_t* nbr, void* ws, hipStream_t st) {
+                                 uint32_t* nbr, bool reuse, void* ws, hipStream_t st) {
   const int64_t n = B.n_total;
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
   const unsigned grid = grid_for(n);
-#define SPH_BATCH_LAUNCH(RR)                                                                   \
-  hipLaunchKernelGGL((k_batch_interact<RR>), dim3(grid), dim3(kBlock), 0, st, tab, B.n_slots, n, \
-                     ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp), key, \
-                     cell_start, ace, arho, visc, nbr, ws_ptr<SlotAccum>(ws, W.accum))
-  if (B.cell_div == 1) SPH_BATCH_LAUNCH(1); else SPH_BATCH_LAUNCH(2);
+#define SPH_BATCH_LAUNCH(RR, STALE)                                                            \
+  hipLaunchKernelGGL((k_batch_interact<RR, STALE>), dim3(grid), dim3(kBlock), 0, st, tab,       \
+                     B.n_slots, n, ws_ptr<float4>(ws, W.base.view_pr),                          \
+                     ws_ptr<float4>(ws, W.base.view_vp), key, cell_start, ace, arho, visc, nbr, \
+                     ws_ptr<SlotAccum>(ws, W.accum), ws_ptr<uint32_t>(ws, W.disp),              \
+                     ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err))
+  // reused cells: the search reaches one cell further than the cells' stencil
+  const int reach = B.cell_div + (reuse ? 1 : 0);
+  if (reach == 1) SPH_BATCH_LAUNCH(1, false);
+  else if (reach == 2 && !reuse) SPH_BATCH_LAUNCH(2, false);
+  else if (reach == 2) SPH_BATCH_LAUNCH(2, true);
+  else SPH_BATCH_LAUNCH(3, true);
 #undef SPH_BATCH_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_refresh_view(const BatchDesc& B, const sph_state& s, const uint32_t* key,
+                                     void* ws, hipStream_t st) {
+  const int64_t n = B.n_total;
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
+  const int64_t nk = n > B.n_slots ? n : B.n_slots;
+  hipLaunchKernelGGL(k_batch_refresh_view, dim3(grid_for(nk)), dim3(kBlock), 0, st,
+                     (const SlotEntry*)B.table, B.n_slots, n, key, s,
+                     ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp),
+                     ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err),
+                     ws_ptr<SlotAccum>(ws, W.accum));
   return hipGetLastError();
 }
 
@@ -268,12 +361,14 @@ hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* 
     hipLaunchKernelGGL(k_batch_motion<0>, dim3(1), dim3(kBlock), 0, st, tab, B.n_slots, dt, t, mot);
     if (n > 0)
       hipLaunchKernelGGL(k_batch_symplectic<0>, dim3(grid_for(n)), dim3(kBlock), 0, st, tab,
-                         B.n_slots, n, mot, saved, s, ace, arho, err, serr);
+                         B.n_slots, n, mot, saved, s, ace, arho, err, serr,
+                         ws_ptr<uint32_t>(ws, W.disp));
   } else {
     hipLaunchKernelGGL(k_batch_motion<1>, dim3(1), dim3(kBlock), 0, st, tab, B.n_slots, dt, t, mot);
     if (n > 0)
       hipLaunchKernelGGL(k_batch_symplectic<1>, dim3(grid_for(n)), dim3(kBlock), 0, st, tab,
-                         B.n_slots, n, mot, saved, s, ace, arho, err, serr);
+                         B.n_slots, n, mot, saved, s, ace, arho, err, serr,
+                         ws_ptr<uint32_t>(ws, W.disp));
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(kBlock), 0, st, B.n_slots, dt, t);
   }
   return hipGetLastError();

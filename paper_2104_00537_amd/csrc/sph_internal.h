@@ -154,10 +154,11 @@ inline WsLayout ws_layout(int64_t n) {
 }
 
 // A batch workspace: the single-case layout for all packed particles, then
-// per-slot accumulators, motion table and error words.
+// per-slot accumulators, motion table, error words and displacement records
+// (kDispSlots words per slot, as the single-case record).
 struct BatchWsLayout {
   WsLayout base;
-  size_t accum, motion, slot_err, total;
+  size_t accum, motion, slot_err, disp, total;
 };
 
 inline BatchWsLayout batch_ws_layout(int32_t n_slots, int64_t n) {
@@ -168,6 +169,7 @@ inline BatchWsLayout batch_ws_layout(int32_t n_slots, int64_t n) {
   B.accum = off; off = align_up(off + sizeof(SlotAccum) * ns);
   B.motion = off; off = align_up(off + sizeof(SlotMotion) * ns);
   B.slot_err = off; off = align_up(off + sizeof(uint32_t) * ns);
+  B.disp = off; off = align_up(off + sizeof(uint32_t) * kDispSlots * ns);
   B.total = off;
   return B;
 }

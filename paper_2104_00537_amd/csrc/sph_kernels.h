@@ -54,7 +54,9 @@ hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_s
                                   uint32_t* perm, uint32_t* cell_start, void* ws, hipStream_t st);
 hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
                                  const uint32_t* cell_start, float* ace, float* arho, float* visc,
-                                 uint32_t* nbr, void* ws, hipStream_t st);
+                                 uint32_t* nbr, bool reuse, void* ws, hipStream_t st);
+hipError_t launch_batch_refresh_view(const BatchDesc& B, const sph_state& s, const uint32_t* key,
+                                     void* ws, hipStream_t st);
 hipError_t launch_batch_reduce_dt(const BatchDesc& B, double* dt, uint64_t* interactions, void* ws,
                                   hipStream_t st);
 hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* dt, double* t,

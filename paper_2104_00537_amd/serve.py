@@ -86,8 +86,14 @@ class BatchEngine:
     """Packed multi-case state on one GPU, stepped by the batch ABI."""
 
     def __init__(self, cap_particles: int, cap_cells: int, max_slots: int = 256,
-                 device="cuda", use_graph: bool = True, cell_div: int = 1):
+                 device="cuda", use_graph: bool = True, cell_div: int = 1,
+                 reuse_cells: bool = True):
         self.dev = torch.device(device)
+        # one binning per step: the n+1/2 interaction reuses the cells of
+        # state n (sph_batch_refresh_view, SPH_INTERACT_REUSE_CELLS); the
+        # state then alternates between the two buffers, `cur` holding it
+        self.reuse = bool(reuse_cells)
+        self.cur = 0
         self.cap_n = int(cap_particles)
         self.cap_cells = int(cap_cells)
         self.max_slots = int(max_slots)
@@ -117,7 +123,7 @@ class BatchEngine:
         self.slots: List[Request] = []
         self.offsets = [0]
         self.batch: Optional[S.SphBatch] = None
-        self.graph = None
+        self.graphs = {}   # captured step per buffer holding the current state
         self.steps_run = 0
         self.repacks = 0
         self.repack_s = 0.0    # host time spent repacking (copies, table upload)
@@ -154,14 +160,14 @@ class BatchEngine:
     def _repack(self, keep: List[Request], add: List[Request]):
         old_n = self.offsets[-1]
         old_index = {id(r): k for k, r in enumerate(self.slots)}
-        src = self._dev_state(0, old_n) if old_n > 0 else None
+        src = self._dev_state(self.cur, old_n) if old_n > 0 else None
         t_old = self.t[: len(self.slots)].clone()
         new_slots = keep + add
         offsets = [0]
         for r in new_slots:
             offsets.append(offsets[-1] + r.n)
         n = offsets[-1]
-        dst = self._dev_state(1, n)
+        dst = self._dev_state(1 - self.cur, n)
         t_new = torch.zeros(len(new_slots), dtype=torch.float64, device=self.dev)
         for k, r in enumerate(new_slots):
             o0, o1 = offsets[k], offsets[k + 1]
@@ -181,13 +187,13 @@ class BatchEngine:
                 dst.rho[o0:o1] = torch.from_numpy(r.case.rho).to(self.dev)
                 dst.type[o0:o1] = torch.from_numpy(r.case.type).to(self.dev)
                 dst.id[o0:o1] = torch.arange(r.n, dtype=torch.int32, device=self.dev)
-        self._state[0], self._state[1] = self._state[1], self._state[0]
+        self.cur = 1 - self.cur
         self.slots = new_slots
         self.offsets = offsets
         ns = len(new_slots)
         self.t[:ns] = t_new
         self.inter[:ns] = 0
-        self.graph = None
+        self.graphs = {}
         self.repacks += 1
         if ns == 0:
             self.batch = None
@@ -208,10 +214,12 @@ class BatchEngine:
         S.sph_batch_clear_errors(b, self.ws)
 
     # ---------------------------------------------------------------- step
-    def _step(self):
+    def _step(self, cur: int):
+        """One symplectic step of every slot from the state in buffer `cur`;
+        returns the buffer that holds the result."""
         b = self.batch
         n = b.n_total
-        a, bb = self._dev_state(0, n), self._dev_state(1, n)
+        a, bb = self._dev_state(cur, n), self._dev_state(1 - cur, n)
         s0, s1 = self._dev_saved(0, n), self._dev_saved(1, n)
         key, perm = self._key.view(n), self._perm.view(n)
         ace, arho = self._ace.view(n), self._arho.view(n)
@@ -221,29 +229,38 @@ class BatchEngine:
         S.sph_batch_interact(b, bb, key, self.cell_start, ace, arho, self.ws)
         S.sph_batch_reduce_dt(b, dt, self.ws, interactions=inter)
         S.sph_batch_symplectic_step(b, 0, dt, t, s0, bb, ace, arho, self.ws)
+        if self.reuse:
+            S.sph_batch_refresh_view(b, bb, key, self.ws)
+            S.sph_batch_interact(b, bb, key, self.cell_start, ace, arho, self.ws,
+                                 flags=S.SPH_INTERACT_REUSE_CELLS)
+            S.sph_batch_reduce_dt(b, dth, self.ws, interactions=inter)
+            S.sph_batch_symplectic_step(b, 1, dt, t, s0, bb, ace, arho, self.ws)
+            return 1 - cur
         S.sph_batch_bin_cells(b, bb, a, key, perm, self.cell_start, self.ws, carry_in=s0,
                               carry_out=s1)
         S.sph_batch_interact(b, a, key, self.cell_start, ace, arho, self.ws)
         S.sph_batch_reduce_dt(b, dth, self.ws, interactions=inter)
         S.sph_batch_symplectic_step(b, 1, dt, t, s1, a, ace, arho, self.ws)
+        return cur
 
     def run(self, k: int):
         if self.batch is None or k <= 0:
             return
-        if self.use_graph:
-            if self.graph is None:
+        for _ in range(k):
+            if not self.use_graph:
+                self.cur = self._step(self.cur)
+                continue
+            entry = self.graphs.get(self.cur)
+            if entry is None:
                 t0 = time.perf_counter()
                 torch.cuda.synchronize()
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
-                    self._step()
-                self.graph = g
+                    nxt = self._step(self.cur)
+                entry = self.graphs[self.cur] = (g, nxt)
                 self.capture_s += time.perf_counter() - t0
-            for _ in range(k):
-                self.graph.replay()
-        else:
-            for _ in range(k):
-                self._step()
+            entry[0].replay()
+            self.cur = entry[1]
         self.steps_run += k
 
     # ------------------------------------------------------------- results
@@ -267,7 +284,7 @@ class BatchEngine:
         """Final state of slot k in the case's original particle order."""
         r = self.slots[k]
         o0, o1 = self.offsets[k], self.offsets[k + 1]
-        st = self._dev_state(0, self.offsets[-1])
+        st = self._dev_state(self.cur, self.offsets[-1])
         ids = st.id[o0:o1].cpu().numpy().view(np.uint32).astype(np.int64)
         inv = np.empty_like(ids)
         inv[ids] = np.arange(ids.shape[0])

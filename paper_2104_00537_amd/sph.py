@@ -34,7 +34,8 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
            "sph_shifting",
            "sph_read_error", "sph_clear_error", "sph_strerror",
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
-           "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_reduce_dt",
+           "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_refresh_view",
+           "sph_batch_reduce_dt",
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
 SPH_BATCH_MAX_SLOTS = 4096
 
@@ -128,8 +129,10 @@ def _load() -> C.CDLL:
     L.sph_batch_bin_cells.argtypes = [P(SphBatch), P(SphState), P(SphState), P(SphState),
                                       P(SphState), VP, VP, VP, VP, C.c_size_t, VP]
     L.sph_batch_interact.restype = C.c_int32
-    L.sph_batch_interact.argtypes = [P(SphBatch), P(SphState), VP, VP, VP, VP, VP, VP, VP,
-                                     C.c_size_t, VP]
+    L.sph_batch_interact.argtypes = [P(SphBatch), P(SphState), VP, VP, VP, VP, VP, VP,
+                                     C.c_uint32, VP, C.c_size_t, VP]
+    L.sph_batch_refresh_view.restype = C.c_int32
+    L.sph_batch_refresh_view.argtypes = [P(SphBatch), P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_batch_reduce_dt.restype = C.c_int32
     L.sph_batch_reduce_dt.argtypes = [P(SphBatch), VP, VP, VP, C.c_size_t, VP]
     L.sph_batch_symplectic_step.restype = C.c_int32
@@ -384,10 +387,15 @@ def sph_batch_bin_cells(batch: SphBatch, src: DeviceState, dst: DeviceState, key
 
 
 def sph_batch_interact(batch: SphBatch, s: DeviceState, key, cell_start, ace, arho, ws,
-                       visc=None, nbr=None, stream=None):
+                       visc=None, nbr=None, flags: int = 0, stream=None):
     _check(lib.sph_batch_interact(C.byref(batch), C.byref(s.c()), _ptr(key), _ptr(cell_start),
-                                  _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), _ptr(ws),
-                                  ws.numel(), _stream(stream)), "sph_batch_interact")
+                                  _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), int(flags),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "sph_batch_interact")
+
+
+def sph_batch_refresh_view(batch: SphBatch, s: DeviceState, key, ws, stream=None):
+    _check(lib.sph_batch_refresh_view(C.byref(batch), C.byref(s.c()), _ptr(key), _ptr(ws),
+                                      ws.numel(), _stream(stream)), "sph_batch_refresh_view")
 
 
 def sph_batch_reduce_dt(batch: SphBatch, dt, ws, interactions=None, stream=None):

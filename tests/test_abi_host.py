@@ -219,9 +219,18 @@ def test_batch_calls_validate_without_device(S):
     assert lib.sph_batch_bin_cells(C.byref(b), C.byref(st), C.byref(st2), None, None, d, d, d, d,
                                    16, None) == S.SPH_E_WORKSPACE
     b.n_total = 1 << 27                    # beyond the packed-index range
-    assert lib.sph_batch_interact(C.byref(b), C.byref(st), d, d, d, d, None, None, d, 1 << 40,
+    assert lib.sph_batch_interact(C.byref(b), C.byref(st), d, d, d, d, None, None, 0, d, 1 << 40,
                                   None) == S.SPH_E_ARG
     b.n_total = 100
+    # flags other than reusing the cells, a workspace too small for a refresh
+    for fl in (S.SPH_DIAG_COUNT_F64, S.SPH_INTERACT_F64, 1 << 7):
+        assert lib.sph_batch_interact(C.byref(b), C.byref(st), d, d, d, d, None, None, fl, d,
+                                      1 << 40, None) == S.SPH_E_ARG
+    assert lib.sph_batch_interact(C.byref(b), C.byref(st), d, d, d, d, None, None,
+                                  S.SPH_INTERACT_REUSE_CELLS, d, 16, None) == S.SPH_E_WORKSPACE
+    assert lib.sph_batch_refresh_view(C.byref(b), C.byref(st), d, d, 16, None) == S.SPH_E_WORKSPACE
+    assert lib.sph_batch_refresh_view(C.byref(b), C.byref(st), None, d, 1 << 40,
+                                      None) == S.SPH_E_ARG
     assert lib.sph_batch_symplectic_step(C.byref(b), 3, d, d, C.byref(st), C.byref(st), d, d, d,
                                          1 << 30, None) == S.SPH_E_ARG
 

@@ -1,6 +1,9 @@
 """The batched path (continuous batching) on the GPU: per-case results are
 bit-identical alone and in a mix, agree with the single-case path and with
-the oracle, and a small request stream is served end to end."""
+the oracle, and a small request stream is served end to end.  Steps bin once
+(the n+1/2 interaction reuses each slot's cells, widened by the slot's own
+recorded displacement) or twice; a slot that moved half a cell or more gets
+SPH_ERR_MARGIN in its own error word only."""
 import numpy as np
 import pytest
 import torch
@@ -33,10 +36,14 @@ def _mix_cases():
     return out
 
 
-def _run_engine(cs, steps, graph):
-    eng = V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
-                        cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
-                        max_slots=8, device=DEV, use_graph=graph)
+def _engine(cs, graph=False, reuse=True):
+    return V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
+                         cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
+                         max_slots=8, device=DEV, use_graph=graph, reuse_cells=reuse)
+
+
+def _run_engine(cs, steps, graph, reuse=True):
+    eng = _engine(cs, graph, reuse)
     reqs = [V.Request(rid=k, case=c, steps=steps, arrival=0.0) for k, c in enumerate(cs)]
     eng.repack([], reqs)
     eng.run(steps)
@@ -45,28 +52,34 @@ def _run_engine(cs, steps, graph):
     return [eng.slot_result(k) for k in range(len(cs))], errs, eng
 
 
-def test_batch_alone_vs_mix_bit_identical():
+@pytest.mark.parametrize("reuse", [True, False])
+def test_batch_alone_vs_mix_bit_identical(reuse):
     cs = _mix_cases()
     _say("mix of", [c.n for c in cs])
-    mix, errs, _ = _run_engine(cs, 6, graph=True)
+    mix, errs, _ = _run_engine(cs, 7, graph=True, reuse=reuse)
     assert not errs.any()
     for k, c in enumerate(cs):
-        alone, e1, _ = _run_engine([c], 6, graph=False)
+        alone, e1, _ = _run_engine([c], 7, graph=False, reuse=reuse)
         assert not e1.any()
         for f in ("pos", "vel", "rho", "type"):
             assert np.array_equal(mix[k][f], alone[0][f]), (k, f)
         assert mix[k]["t"] == alone[0]["t"]
 
 
-def test_batch_matches_single_case_path():
+@pytest.mark.parametrize("reuse", [True, False])
+def test_batch_matches_single_case_path(reuse):
     cs = _mix_cases()
-    mix, errs, _ = _run_engine(cs, 4, graph=False)
+    mix, errs, eng = _run_engine(cs, 4, graph=False, reuse=reuse)
     assert not errs.any()
+    inter = eng.inter[: len(cs)].cpu().numpy()
     for k, c in enumerate(cs):
-        sim = Simulation(c, DEV)
+        sim = Simulation(c, DEV, reuse_cells=reuse)
         sim.run(4)
         g = sim.host_state()
         assert sim.error() == 0
+        # pair counts of both passes of every step (FP32 tests: near-ties only)
+        pairs = sim.interactions.cpu().numpy()
+        assert abs(int(inter[k, 0]) - int(pairs[0])) <= 1e-4 * pairs[0] + 2, (inter[k], pairs)
         b = mix[k]
         assert b["t"] == pytest.approx(g["t"], rel=1e-6)
         scale = max(np.abs(g["vel"]).max(), 1e-3)
@@ -80,14 +93,12 @@ def test_batch_matches_single_case_path():
 
 def test_batch_interaction_matches_oracle():
     cs = _mix_cases()
-    eng = V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
-                        cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
-                        max_slots=8, device=DEV, use_graph=False)
+    eng = _engine(cs)
     reqs = [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)]
     eng.repack([], reqs)
     b = eng.batch
     n = b.n_total
-    a, bb = eng._dev_state(0, n), eng._dev_state(1, n)
+    a, bb = eng._dev_state(eng.cur, n), eng._dev_state(1 - eng.cur, n)
     key, perm = eng._key.view(n), eng._perm.view(n)
     ace, arho = eng._ace.view(n), eng._arho.view(n)
     nbr = torch.zeros(n, dtype=torch.int32, device=DEV)
@@ -113,6 +124,102 @@ def test_batch_interaction_matches_oracle():
         flips = np.abs(nbr_all[o0:o1] - nbr_o.astype(np.int64)).sum()
         _say(f"  slot {k}: rel err ace {ea:.2e} arho {er:.2e} count flips {flips}")
         assert ea < 1e-4 and er < 1e-4 and flips <= 5e-4 * nbr_o.sum() + 2
+
+
+class BatchHalfStep:
+    """Bin and interact the mix at state n, then the batched predictor with a
+    per-slot dt that moves each slot's particles by up to the given fraction
+    of its cell (zero rates: a pure move), leaving the half state in `st`."""
+
+    def __init__(self, cs, move_cells):
+        eng = self.eng = _engine(cs)
+        eng.repack([], [V.Request(rid=k, case=c, steps=1, arrival=0.0)
+                        for k, c in enumerate(cs)])
+        b = self.b = eng.batch
+        n = self.n = b.n_total
+        a, self.st = eng._dev_state(eng.cur, n), eng._dev_state(1 - eng.cur, n)
+        self.saved = eng._dev_saved(0, n)
+        self.key, perm = eng._key.view(n), eng._perm.view(n)
+        ace, arho = eng._ace.view(n), eng._arho.view(n)
+        S.sph_batch_bin_cells(b, a, self.st, self.key, perm, eng.cell_start, eng.ws)
+        S.sph_batch_interact(b, self.st, self.key, eng.cell_start, ace, arho, eng.ws)
+        dts = []
+        for c, m in zip(cs, move_cells):
+            fl = c.type == cases.FLUID  # walls are not moved by their stored velocity
+            vmax = float(np.sqrt((c.vel[:, fl].astype(np.float64) ** 2).sum(axis=0)).max())
+            dts.append(2.0 * m * c.params.cell_size / vmax)  # the predictor moves dt/2 v
+        dt = torch.tensor(dts, dtype=torch.float64, device=DEV)
+        t = torch.zeros(len(cs), dtype=torch.float64, device=DEV)
+        ace.zero_()
+        arho.zero_()
+        S.sph_batch_symplectic_step(b, 0, dt, t, self.saved, self.st, ace, arho, eng.ws)
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("move", [0.05, 0.3])
+def test_batch_reused_cells_find_the_oracles_pairs(move):
+    """The n+1/2 interaction on the cells of state n, per slot against the
+    oracle on the half state: rates to the interaction's bar, FP32 neighbour
+    counts with flips only at near-ties."""
+    cs = _mix_cases()
+    hs = BatchHalfStep(cs, [move] * len(cs))
+    eng, b, n = hs.eng, hs.b, hs.n
+    S.sph_batch_refresh_view(b, hs.st, hs.key, eng.ws)
+    ace = torch.full((3, n), float("nan"), dtype=torch.float32, device=DEV)
+    arho = torch.full((n,), float("nan"), dtype=torch.float32, device=DEV)
+    nbr = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    S.sph_batch_interact(b, hs.st, hs.key, eng.cell_start, ace, arho, eng.ws, nbr=nbr,
+                         flags=S.SPH_INTERACT_REUSE_CELLS)
+    inter = torch.zeros((len(cs), 2), dtype=torch.int64, device=DEV)
+    dth = torch.zeros(len(cs), dtype=torch.float64, device=DEV)
+    S.sph_batch_reduce_dt(b, dth, eng.ws, interactions=inter)
+    torch.cuda.synchronize()
+    errs = S.sph_batch_read_errors(b, eng.ws)
+    assert not errs.any(), errs
+    inter = inter.cpu().numpy()
+    pos_all = hs.st.pos.cpu().numpy()
+    vel_all = hs.st.vel.cpu().numpy().astype(np.float64)
+    rho_all = hs.st.rho.cpu().numpy().astype(np.float64)
+    typ_all = hs.st.type.cpu().numpy()
+    moved_all = np.sqrt(((pos_all - hs.saved.pos.cpu().numpy()) ** 2).sum(axis=0))
+    ace_all = ace.cpu().numpy().astype(np.float64)
+    arho_all = arho.cpu().numpy().astype(np.float64)
+    nbr_all = nbr.cpu().numpy().astype(np.int64)
+    for k, c in enumerate(cs):
+        o0, o1 = eng.offsets[k], eng.offsets[k + 1]
+        pos, vel = V.from_3d(c.params.dim, pos_all[:, o0:o1], vel_all[:, o0:o1])
+        typ = typ_all[o0:o1]
+        ace_o, arho_o, _, nbr_o = oracle.interact(c.params, pos, vel, rho_all[o0:o1], typ)
+        ace_g = ace_all[:, o0:o1] if c.params.dim == 3 else ace_all[[0, 2], o0:o1]
+        fl = typ == cases.FLUID
+        ea = np.abs(ace_g - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+        er = np.abs(arho_all[o0:o1] - arho_o).max() / np.abs(arho_o).max()
+        flips = np.abs(nbr_all[o0:o1] - nbr_o.astype(np.int64)).sum()
+        mv = moved_all[o0:o1].max() / c.params.cell_size
+        _say(f"  slot {k} moved {mv:.3f} cell: rel err ace {ea:.2e} arho {er:.2e} "
+             f"count flips {flips}")
+        assert mv > 0.99 * move
+        # the slot's pair count is this pass's alone (the refresh restarts it)
+        assert inter[k, 0] == nbr_all[o0:o1].sum()
+        assert ea < 1e-4 and er < 1e-4 and flips <= 5e-4 * nbr_o.sum() + 2
+
+
+def test_batch_margin_error_is_per_slot():
+    """Slot 1 moves 0.6 of a cell before the n+1/2 interaction on reused
+    cells: its error word gets SPH_ERR_MARGIN, the other slots' words stay
+    clear (their own records are below the margin)."""
+    cs = _mix_cases()
+    hs = BatchHalfStep(cs, [0.1, 0.6, 0.1, 0.1])
+    eng, b, n = hs.eng, hs.b, hs.n
+    S.sph_batch_refresh_view(b, hs.st, hs.key, eng.ws)
+    S.sph_batch_interact(b, hs.st, hs.key, eng.cell_start, eng._ace.view(n),
+                         eng._arho.view(n), eng.ws, flags=S.SPH_INTERACT_REUSE_CELLS)
+    errs = S.sph_batch_read_errors(b, eng.ws)
+    _say(f"  per-slot error words: {list(errs)}")
+    assert errs[1] & S.SPH_ERR_MARGIN
+    for k in (0, 2, 3):
+        assert not (errs[k] & S.SPH_ERR_MARGIN)
+    assert S.sph_read_error(eng.ws) & S.SPH_ERR_MARGIN
 
 
 def test_served_stream_small():
