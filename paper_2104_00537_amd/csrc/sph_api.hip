@@ -95,6 +95,11 @@ KParams make_kparams(const sph_params& p) {
     k.hc3_f = (float)(p.rho0 * e * (e - 1.0) * (e - 2.0) / 6.0);
   }
   k.ddt_coef_f = p.ddt ? (float)(2.0 * p.delta * p.h * p.c0) : 0.f;
+  // the viscous term's constant in the pair loop's scaling (infinite when
+  // the viscosity is zero: the term is then exactly zero)
+  k.kvc_f = p.viscosity == 0 ? (float)(-1.0 / (2.0 * p.alpha * p.c0 * p.h))
+                             : (float)(1.0 / (4.0 * p.visc_nu));
+  k.mass_ratio_f = (float)(p.mass_bound / p.mass_fluid);
   k.cs_f = (float)p.cell_size;
   k.inv_csx_f = (float)(p.inv_cell_size * (double)p.x_sub);
   k.unit_x_f = (float)(kFrameCells * p.cell_size / 4294967296.0);

@@ -124,11 +124,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
       const float4 pa = pr[a];
       if (lk < kp.ncell_total && (!STALE || pa.w != 0.f)) {
         PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-        TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
         const float4 va = vp[a];
         T.fluid = pa.w > 0.f;
         T.rho = fabsf(pa.w);
         T.irho = __builtin_amdgcn_rcpf(T.rho);
+        T.ik = kp.kvc_f * T.irho;
         T.p = va.w;
         T.vx = va.x;
         T.vy = va.y;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
   }
   if (i < n) {
     PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
     uint32_t c64 = 0;
     // with modified DBC the wall densities come from Eq. 38 (sph_mdbc): wall
     // targets take no sums
@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
       T.fluid = pa.w > 0.f;
       T.rho = fabsf(pa.w);
       T.irho = __builtin_amdgcn_rcpf(T.rho);
+      T.ik = kp.kvc_f * T.irho;
       T.p = va.w;
       T.vx = va.x;
       T.vy = va.y;

@@ -49,6 +49,8 @@ struct KParams {
   float klam_mf_f, klam_mb_f;                // 4 nu0 kfab m (Eq. 23)
   float fz_f, hc1_f, hc2_f, hc3_f;           // Eq. 19-20: eps = fz z_ab, rho^H = eps(c1 + eps(c2 + eps c3))
   float eta2_f, ddt_coef_f;                  // eta^2 ; 2 delta h c0
+  float kvc_f;                               // -1/(2 alpha c0 h) (Eq. 21), or 1/(4 nu0) (Eq. 23)
+  float mass_ratio_f;                        // m_wall / m_fluid
   float cs_f, inv_csx_f, unit_x_f;           // cell size, inverse key-cell size along x, x offset unit
   float gx_f, gy_f, gz_f;
   uint32_t lu;                   // the x period in x-offset units, modulo 2^32

@@ -7,11 +7,15 @@
 
 namespace sph {
 
+// Per-target sums of the pair loop, each without the factors that are the
+// same for every pair of the target (applied once in write_target):
+// kfab m_f (the fluid particle's mass with the kernel gradient's constant),
+// 1/rho_a and h.
 struct PairAcc {
-  float ax, ay, az;  // sum of -m_b [(P_a+P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
-  float cont;        // sum of (m_b/rho_b) F_ab v_ab.r_ab
-  float diff;        // sum over fluid b of (rho_b - rho_a)|F_ab| m_b/rho_b
-  float vmax;        // max of |h v_ab.r_ab/(r^2+eta^2)|
+  float ax, ay, az;  // dv/dt = kfab m_f / rho_a * (ax, ay, az)
+  float cont;        // drho/dt continuity part = rho_a kfab m_f * cont
+  float diff;        // density diffusion sum = kfab m_f * diff
+  float vmax;        // visc = h * vmax
   uint32_t cnt;      // pairs evaluated
 };
 
@@ -20,7 +24,17 @@ struct TargetData {
   float rho, irho, p;
   float vx, vy, vz;
   bool flt;  // a floating particle (general kernels only): Eq. 47
+  float ik;  // kvc / rho_a: the viscosity constant's share of the target (see pair_terms)
 };
+
+// max(m, |t|) for a running maximum m >= 0 as one instruction: the compiler's
+// own maximum first quiets a possible signalling NaN in m (an extra
+// instruction per pair), which the values here (finite or quiet) never need.
+__device__ __forceinline__ float max_abs(float m, float t) {
+  float r;
+  asm("v_max_f32_e64 %0, %1, |%2|" : "=v"(r) : "v"(m), "v"(t));
+  return r;
+}
 
 // The pair terms of Eq. 15, 17-18, 21-22 and 36 for one pair (a, b) with
 // r_ab = (dx, dy, dz), |r_ab|^2 = r2 < 4h^2.  pbw is +rho_b for a fluid
@@ -28,22 +42,29 @@ struct TargetData {
 // dropped wall-wall pairs (Eq. 36 sums over fluid neighbours only).
 //   F_ab = kfab g(q): Wendland C2 (Eq. 11) g = (1 - q/2)^3, or cubic spline
 //     (Eq. 10) g = -3 + 9q/4 (q <= 1), -3/4 (2 - q)^2 / q (q > 1);
-//   fv = V_b F_ab with V_b = m_b / rho_b;
-//   continuity:  fv v_ab.r_ab;
+//   with m_b = mr m_f (mr = 1 for fluid neighbours and with equal masses)
+//   and fv = mr g / rho_b, so that V_b F_ab = kfab m_f fv:
+//   continuity:  V_b F_ab v_ab.r_ab = kfab m_f fv v_ab.r_ab;
 //   momentum:    -m_b [(P_a + P_b)/(rho_a rho_b) + Pi_ab] F_ab r_ab
-//              = -[fv (P_a + P_b) / rho_a + m_b Pi_ab F_ab] r_ab,
+//              = -(kfab m_f / rho_a) [fv (P_a + P_b) + mr g pi_ab] r_ab,
 //   with Pi_ab = -2 alpha c0 mu_ab / (rho_a + rho_b) for approaching pairs
-//   (mu_ab = h v_ab.r_ab / (r^2 + eta^2) < 0) and 0 otherwise (Eq. 21); or,
-//   with laminar viscosity, no Pi_ab and + m_b 4 nu0 F_ab r^2 v_ab /
-//   ((rho_a + rho_b)(r^2 + eta^2)) (Eq. 23);
-//   diffusion:   -(rho_b - rho_a) fv over fluid b (Eq. 18), or with
+//   (mu_ab = h t, t = v_ab.r_ab / (r^2 + eta^2) < 0) and 0 otherwise (Eq. 21),
+//   so pi_ab = rho_a Pi_ab / m_f = min(t, 0) / (rho_b kvc/rho_a + kvc) with
+//   kvc = -1 / (2 alpha c0 h) (per case) and kvc/rho_a = T.ik (per target);
+//   or, with laminar viscosity (Eq. 23), no Pi_ab and
+//     + (kfab m_f / rho_a) mr g r^2 v_ab / ((r^2 + eta^2)(rho_b kvc/rho_a + kvc)),
+//   kvc = 1 / (4 nu0);
+//   diffusion:   -(rho_b - rho_a) V_b F_ab over fluid b (Eq. 18), or with
 //   rho_b - rho_a less its hydrostatic part rho^H_ab (Eq. 19-20).
+// The per-target factors kfab m_f, 1/rho_a (and h in visc = max |mu|) are
+// applied once in write_target.  With alpha (or nu0) zero kvc is infinite
+// and the viscous term is exactly zero (the reciprocal of infinity).
 // GEN: any formulation option (read from kp, uniform per slot) and floating
 // targets, which take the momentum terms of a fluid target from their fluid
 // neighbours (Eq. 47; no viscosity maximum, no diffusion); otherwise the
 // default formulation (Wendland C2, artificial viscosity, Eq. 18 or no
 // diffusion), whose code keeps the register budget of the production pass.
-// EQM: fluid and wall particles have the same mass (no per-pair select).
+// EQM: fluid and wall particles have the same mass (mr = 1 for every pair).
 template <int DIM, bool EQM, bool GEN>
 __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& a, float dx,
                                            float dy, float dz, float r2, float pbw,
@@ -61,27 +82,24 @@ __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& 
     const float q = s * kp.inv_h_f, u = 2.f - q;
     g = q <= 1.f ? fmaf(2.25f, q, -3.f) : -0.75f * u * u * __builtin_amdgcn_rcpf(q);
   }
-  const float irhob = __builtin_amdgcn_rcpf(rhob);
-  const float kmb = EQM ? kp.kfab_mf_f : (fb ? kp.kfab_mf_f : kp.kfab_mb_f);  // kfab m_b
-  const float fv = (g * irhob) * kmb;
+  if (!EQM && !fb) g *= kp.mass_ratio_f;  // m_b / m_f for a wall neighbour
+  const float fv = g * __builtin_amdgcn_rcpf(rhob);
   acc.cont = fmaf(fv, vr, acc.cont);
   acc.cnt += 1u;
   if (a.fluid || (GEN && a.flt)) {
     const float rr = __builtin_amdgcn_rcpf(r2 + kp.eta2_f);
-    const float mu = kp.h_f * vr * rr;
-    if (!GEN || !a.flt) acc.vmax = fmaxf(acc.vmax, fabsf(mu));
-    const float irs = __builtin_amdgcn_rcpf(a.rho + rhob);
+    const float t = vr * rr;
+    if (!GEN || !a.flt) acc.vmax = max_abs(acc.vmax, t);
+    const float ivs = __builtin_amdgcn_rcpf(fmaf(rhob, a.ik, kp.kvc_f));
+    const float pab = a.p + vb.w;
     if (!GEN || kp.viscosity == 0) {
-      const float kpi = EQM ? kp.kpi_mf_f : (fb ? kp.kpi_mf_f : kp.kpi_mb_f);  // -2 alpha c0 kfab m_b
-      const float piw = fminf(mu, 0.f) * irs * (g * kpi);
-      const float coef = fmaf(fv * (a.p + vb.w), a.irho, piw);
+      const float coef = fmaf(fv, pab, (fminf(t, 0.f) * ivs) * g);
       acc.ax = fmaf(-coef, dx, acc.ax);
       acc.ay = fmaf(-coef, dy, acc.ay);
       if (DIM == 3) acc.az = fmaf(-coef, dz, acc.az);
     } else {
-      const float klam = EQM ? kp.klam_mf_f : (fb ? kp.klam_mf_f : kp.klam_mb_f);  // 4 nu0 kfab m_b
-      const float coef = fv * (a.p + vb.w) * a.irho;
-      const float lam = (g * klam) * r2 * irs * rr;
+      const float coef = fv * pab;
+      const float lam = (rr * ivs) * (g * r2);
       acc.ax = fmaf(lam, dvx, fmaf(-coef, dx, acc.ax));
       acc.ay = fmaf(lam, dvy, fmaf(-coef, dy, acc.ay));
       if (DIM == 3) acc.az = fmaf(lam, dvz, fmaf(-coef, dz, acc.az));
@@ -141,25 +159,28 @@ __device__ __forceinline__ void write_target(const KParams& kp, int64_t n, int64
                                              float* visc, uint32_t* nbr, float& fmag,
                                              float& vmax_out, uint32_t& nfl) {
   float ax = 0.f, ay = 0.f, az = 0.f;
-  float ar = t.rho * acc.cont;
+  // the factors the pair sums leave out (see PairAcc)
+  const float km = kp.kfab_mf_f, kma = km * t.irho;
+  float ar = (t.rho * km) * acc.cont;
+  const float vm = kp.h_f * acc.vmax;
   if (t.fluid) {
-    ax = acc.ax + kp.gx_f;
-    ay = acc.ay + kp.gy_f;
-    az = DIM == 3 ? acc.az + kp.gz_f : 0.f;
-    ar += kp.ddt_coef_f * acc.diff;
+    ax = fmaf(kma, acc.ax, kp.gx_f);
+    ay = fmaf(kma, acc.ay, kp.gy_f);
+    az = DIM == 3 ? fmaf(kma, acc.az, kp.gz_f) : 0.f;
+    ar += (kp.ddt_coef_f * km) * acc.diff;
     fmag = sqrtf(ax * ax + ay * ay + az * az);
-    vmax_out = acc.vmax;
+    vmax_out = vm;
     nfl = 1;
   } else if (t.flt) {
-    ax = acc.ax;
-    ay = acc.ay;
-    az = DIM == 3 ? acc.az : 0.f;
+    ax = kma * acc.ax;
+    ay = kma * acc.ay;
+    az = DIM == 3 ? kma * acc.az : 0.f;
   }
   ace[a] = ax;
   ace[n + a] = ay;
   if (DIM == 3) ace[2 * n + a] = az;
   arho[a] = ar;
-  if (visc) visc[a] = acc.vmax;
+  if (visc) visc[a] = vm;
   if (nbr) nbr[a] = count_out;
 }
 
