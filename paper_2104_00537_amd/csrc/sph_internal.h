@@ -191,13 +191,19 @@ __device__ inline void set_error(uint32_t* err, uint32_t bits) {
 }
 
 // The dispatcher hands workgroup b to XCD b % kXcds.  Returns the logical
-// block index that gives each XCD one contiguous share of the nb blocks (XCD
-// x runs shares x in order), so that blocks working on neighbouring data
-// share one L2.  A bijection of [0, nb).
+// block index that deals chunks of kXcdChunk consecutive blocks to the XCDs
+// in turn (XCD x runs chunks x, x + kXcds, ...; a last incomplete round keeps
+// the identity), so that blocks working on neighbouring data mostly share
+// one L2 while every XCD gets a share of every part of the domain: the work
+// per target varies across the domain (walls, free surface), and one
+// contiguous share per XCD leaves some XCDs idle at the end.  A bijection of
+// [0, nb).
+constexpr uint32_t kXcdChunk = 16;
 __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t full = nb / (kXcds * kXcdChunk) * (kXcds * kXcdChunk);
+  if (b >= full) return b;
   const uint32_t x = b % kXcds, k = b / kXcds;
-  const uint32_t q = nb / kXcds, r = nb % kXcds;
-  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+  return ((k / kXcdChunk) * kXcds + x) * kXcdChunk + k % kXcdChunk;
 }
 
 // Wave-wide reductions over the 64 lanes of a wavefront.
