@@ -22,12 +22,23 @@ __device__ inline int find_slot(const SlotEntry* __restrict__ tab, int ns, int64
   return lo;
 }
 
+// The slots of the block's first and last particle (uniform over the block;
+// -1, -1 for a block wholly past n).  Slots are in particle order, so equal
+// values mean the whole block lies in one slot.
+__device__ inline int2 block_slots(const SlotEntry* __restrict__ tab, int ns, int64_t n,
+                                   int64_t first) {
+  if (first >= n) return make_int2(-1, -1);
+  const int64_t last = first + kBlock - 1 < n ? first + kBlock - 1 : n - 1;
+  return make_int2(__builtin_amdgcn_readfirstlane(find_slot(tab, ns, first)),
+                   __builtin_amdgcn_readfirstlane(find_slot(tab, ns, last)));
+}
+
 __global__ void k_batch_cell_keys(const SlotEntry* __restrict__ tab, int ns, int64_t n,
                                   const double* __restrict__ pos, const uint8_t* __restrict__ type,
                                   uint32_t* __restrict__ key, SlotAccum* __restrict__ acc,
                                   uint32_t* __restrict__ disp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ns) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
+  if (i < (int64_t)ns * kAccCopies) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
   if (i < (int64_t)ns * kDispSlots) disp[i] = 0u;  // nothing moved since this binning
   if (i >= n) return;
   const int s = find_slot(tab, ns, i);
@@ -60,7 +71,7 @@ __global__ void k_batch_refresh_view(const SlotEntry* __restrict__ tab, int ns, 
                                      uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err,
                                      SlotAccum* __restrict__ acc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ns) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
+  if (i < (int64_t)ns * kAccCopies) acc[i] = SlotAccum{0u, 0u, 0u, 0u, 0ull, 0ull};
   if (i >= n) return;
   const uint8_t t = s.type[i];
   if (t & SPH_EXCLUDED) return;  // its entry was written by the binning
@@ -97,7 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const uint32_t* __restrict__ disp, uint32_t* __restrict__ err,
     uint32_t* __restrict__ slot_err) {
   const int lane = threadIdx.x & 63;
-  const int64_t a = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t a = (int64_t)lb * kBlock + threadIdx.x;
   const int sa = a < n ? find_slot(tab, ns, a) : -1;
   float fmag = 0.f, vmx = 0.f;
   uint32_t cnt = 0, cntw = 0, nfl = 0;
@@ -150,7 +162,44 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     }
     todo = todo && !mine;
   }
-  // per-slot combination: one pass per distinct slot among the wave's lanes
+  // per-slot combination into copy lb % kAccCopies of the slot's sums: the
+  // block's waves combined in LDS when the block lies in one slot (one set
+  // of atomics per block), else one set per wave and slot
+  const int2 bs = block_slots(tab, ns, n, (int64_t)lb * kBlock);
+  if (bs.x >= 0 && bs.x == bs.y) {
+    __shared__ float sf[kBlock / 64], sv[kBlock / 64];
+    __shared__ uint32_t sc[kBlock / 64], sw[kBlock / 64], sk[kBlock / 64];
+    const float f = wave_max(fmag), v = wave_max(vmx);
+    const uint32_t c = wave_sum(cnt), w = wave_sum(cntw), k = wave_sum(nfl);
+    const int wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      sf[wave] = f;
+      sv[wave] = v;
+      sc[wave] = c;
+      sw[wave] = w;
+      sk[wave] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float bf = 0.f, bv = 0.f;
+      unsigned long long bc = 0, bw = 0;
+      uint32_t bk = 0;
+      for (int q = 0; q < kBlock / 64; ++q) {
+        bf = fmaxf(bf, sf[q]);
+        bv = fmaxf(bv, sv[q]);
+        bc += sc[q];
+        bw += sw[q];
+        bk += sk[q];
+      }
+      SlotAccum* A = &sacc[(size_t)bs.x * kAccCopies + lb % kAccCopies];
+      atomicMax(&A->fmax_bits, __float_as_uint(bf));
+      atomicMax(&A->vmax_bits, __float_as_uint(bv));
+      atomicAdd(&A->nfluid, bk);
+      atomicAdd(&A->count, bc);
+      atomicAdd(&A->count_wall, bw);
+    }
+    return;
+  }
   bool pend = a < n;
   while (__ballot(pend) != 0ull) {
     const int leader = (int)__builtin_ctzll(__ballot(pend));
@@ -164,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     w = wave_sum(w);
     k = wave_sum(k);
     if (lane == leader) {
-      SlotAccum* A = &sacc[rs];
+      SlotAccum* A = &sacc[(size_t)rs * kAccCopies + lb % kAccCopies];
       atomicMax(&A->fmax_bits, __float_as_uint(f));
       atomicMax(&A->vmax_bits, __float_as_uint(v));
       atomicAdd(&A->nfluid, k);
@@ -182,7 +231,15 @@ __global__ void k_batch_reduce_dt(const SlotEntry* __restrict__ tab, int ns,
                                   uint32_t* __restrict__ slot_err) {
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     const KParams& kp = tab[s].kp;
-    const SlotAccum A = sacc[s];
+    SlotAccum A{0u, 0u, 0u, 0u, 0ull, 0ull};
+    for (int q = 0; q < kAccCopies; ++q) {
+      const SlotAccum B = sacc[(size_t)s * kAccCopies + q];
+      A.fmax_bits = max(A.fmax_bits, B.fmax_bits);
+      A.vmax_bits = max(A.vmax_bits, B.vmax_bits);
+      A.nfluid += B.nfluid;
+      A.count += B.count;
+      A.count_wall += B.count_wall;
+    }
     const double f = (double)__uint_as_float(A.fmax_bits);
     const double v = (double)__uint_as_float(A.vmax_bits);
     double d = INFINITY;
@@ -251,8 +308,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_symplectic(
       set_error(&slot_err[sl], SPH_ERR_NONFINITE);
     }
   }
-  // the predictor's moves since the binning, for an interaction reusing its cells
-  if (PHASE == 0) record_displacement_slots(disp2, sl, disp);
+  // the predictor's moves since the binning, for an interaction reusing its
+  // cells: one atomic per block when the block lies in one slot
+  if (PHASE == 0) {
+    const int2 bs = block_slots(tab, ns, n, (int64_t)blockIdx.x * kBlock);
+    if (bs.x >= 0 && bs.x == bs.y)
+      record_displacement(disp2, disp + (size_t)bs.x * kDispSlots);
+    else
+      record_displacement_slots(disp2, sl, disp);
+  }
 }
 
 __global__ void k_batch_advance(int ns, const double* __restrict__ dt, double* __restrict__ t) {
@@ -278,7 +342,7 @@ hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_s
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
   SlotAccum* sacc = ws_ptr<SlotAccum>(ws, W.accum);
-  const int64_t nd = (int64_t)B.n_slots * kDispSlots;
+  const int64_t nd = (int64_t)B.n_slots * (kDispSlots > kAccCopies ? kDispSlots : kAccCopies);
   const int64_t nk = n > nd ? n : nd;
   hipLaunchKernelGGL(k_batch_cell_keys, dim3(grid_for(nk)), dim3(kBlock), 0, st, tab, B.n_slots,
                      n, in.pos, in.type, ws_ptr<uint32_t>(ws, W.base.keyA), sacc,
@@ -331,7 +395,8 @@ hipError_t launch_batch_refresh_view(const BatchDesc& B, const sph_state& s, con
                                      void* ws, hipStream_t st) {
   const int64_t n = B.n_total;
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
-  const int64_t nk = n > B.n_slots ? n : B.n_slots;
+  const int64_t na = (int64_t)B.n_slots * kAccCopies;
+  const int64_t nk = n > na ? n : na;
   hipLaunchKernelGGL(k_batch_refresh_view, dim3(grid_for(nk)), dim3(kBlock), 0, st,
                      (const SlotEntry*)B.table, B.n_slots, n, key, s,
                      ws_ptr<float4>(ws, W.base.view_pr), ws_ptr<float4>(ws, W.base.view_vp),

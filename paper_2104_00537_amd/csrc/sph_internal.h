@@ -95,7 +95,11 @@ struct SlotEntry {
 };
 
 // Per-slot results of one interaction pass (cleared by each binning);
-// maxima of non-negative floats are kept as their bit patterns.
+// maxima of non-negative floats are kept as their bit patterns.  Each slot
+// has kAccCopies copies (blocks add into the copy of their index modulo
+// kAccCopies, which keeps the atomics of a large slot apart); the slot's
+// value combines the copies.
+constexpr int kAccCopies = 64;
 struct SlotAccum {
   uint32_t fmax_bits, vmax_bits, nfluid, pad;
   unsigned long long count, count_wall;
@@ -168,7 +172,7 @@ inline BatchWsLayout batch_ws_layout(int32_t n_slots, int64_t n) {
   B.base = ws_layout(n);
   const size_t ns = (size_t)(n_slots > 0 ? n_slots : 1);
   size_t off = B.base.total;
-  B.accum = off; off = align_up(off + sizeof(SlotAccum) * ns);
+  B.accum = off; off = align_up(off + sizeof(SlotAccum) * kAccCopies * ns);
   B.motion = off; off = align_up(off + sizeof(SlotMotion) * ns);
   B.slot_err = off; off = align_up(off + sizeof(uint32_t) * ns);
   B.disp = off; off = align_up(off + sizeof(uint32_t) * kDispSlots * ns);

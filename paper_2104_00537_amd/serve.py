@@ -82,6 +82,15 @@ class _Flat:
         return v.view(self.comps, n) if self.comps > 1 else v
 
 
+# Each slot's particle range is padded to a whole number of wavefronts with
+# excluded particles, so that no wavefront holds targets of two slots.
+WAVE = 64
+
+
+def padded(n: int) -> int:
+    return -(-n // WAVE) * WAVE
+
+
 class BatchEngine:
     """Packed multi-case state on one GPU, stepped by the batch ABI."""
 
@@ -133,7 +142,7 @@ class BatchEngine:
     def fits(self, slots: List[Request], req: Request) -> bool:
         """Footprint admission: a free slot, particle capacity (HBM) and cell
         capacity for `slots` plus `req`."""
-        n_after = sum(r.n for r in slots) + req.n
+        n_after = sum(padded(r.n) for r in slots) + padded(req.n)
         cells_after = sum(r.case.params.ncell_total() + 1 for r in slots + [req])
         return (len(slots) + 1 <= self.max_slots and n_after <= self.cap_n
                 and cells_after <= self.cap_cells)
@@ -165,8 +174,11 @@ class BatchEngine:
         new_slots = keep + add
         offsets = [0]
         for r in new_slots:
-            offsets.append(offsets[-1] + r.n)
+            offsets.append(offsets[-1] + padded(r.n))
         n = offsets[-1]
+        if n > self.cap_n:
+            raise S.SphError(f"batch of {n} particles (slots padded to whole wavefronts) "
+                             f"exceeds the particle capacity {self.cap_n}")
         dst = self._dev_state(1 - self.cur, n)
         t_new = torch.zeros(len(new_slots), dtype=torch.float64, device=self.dev)
         for k, r in enumerate(new_slots):
@@ -182,11 +194,16 @@ class BatchEngine:
                 t_new[k] = t_old[j]
             else:
                 pos, vel = to_3d(r.case)
-                dst.pos[:, o0:o1] = torch.from_numpy(pos).to(self.dev)
-                dst.vel[:, o0:o1] = torch.from_numpy(vel).to(self.dev)
-                dst.rho[o0:o1] = torch.from_numpy(r.case.rho).to(self.dev)
-                dst.type[o0:o1] = torch.from_numpy(r.case.type).to(self.dev)
-                dst.id[o0:o1] = torch.arange(r.n, dtype=torch.int32, device=self.dev)
+                o2 = o0 + r.n  # the case's particles, then excluded padding
+                dst.pos[:, o0:o2] = torch.from_numpy(pos).to(self.dev)
+                dst.vel[:, o0:o2] = torch.from_numpy(vel).to(self.dev)
+                dst.rho[o0:o2] = torch.from_numpy(r.case.rho).to(self.dev)
+                dst.type[o0:o2] = torch.from_numpy(r.case.type).to(self.dev)
+                dst.pos[:, o2:o1] = 0.0
+                dst.vel[:, o2:o1] = 0.0
+                dst.rho[o2:o1] = float(r.case.params.rho0)
+                dst.type[o2:o1] = K.EXCLUDED
+                dst.id[o0:o1] = torch.arange(o1 - o0, dtype=torch.int32, device=self.dev)
         self.cur = 1 - self.cur
         self.slots = new_slots
         self.offsets = offsets
@@ -288,6 +305,7 @@ class BatchEngine:
         ids = st.id[o0:o1].cpu().numpy().view(np.uint32).astype(np.int64)
         inv = np.empty_like(ids)
         inv[ids] = np.arange(ids.shape[0])
+        inv = inv[: r.n]  # the padding's ids follow the case's
         pos = st.pos[:, o0:o1].cpu().numpy()[:, inv]
         vel = st.vel[:, o0:o1].cpu().numpy()[:, inv]
         pos, vel = from_3d(r.case.params.dim, pos, vel)

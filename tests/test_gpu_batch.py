@@ -37,7 +37,7 @@ def _mix_cases():
 
 
 def _engine(cs, graph=False, reuse=True):
-    return V.BatchEngine(cap_particles=sum(c.n for c in cs) + 16,
+    return V.BatchEngine(cap_particles=sum(V.padded(c.n) for c in cs) + 16,
                          cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
                          max_slots=8, device=DEV, use_graph=graph, reuse_cells=reuse)
 
