@@ -423,6 +423,15 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
  */
 #define SPH_BATCH_MAX_SLOTS 4096
 
+/* sph_batch.flags, set by sph_batch_describe (callers do not change them) */
+enum {
+  /* every slot's particle range starts and ends at a multiple of 64 (whole
+   * wavefronts): the interaction then runs a leaner kernel in which each
+   * wavefront lies in one slot.  Pad a case's range with excluded particles
+   * (type SPH_EXCLUDED) to get it. */
+  SPH_BATCH_WAVE_ALIGNED = 1u
+};
+
 typedef struct sph_batch {
   int32_t n_slots;
   int32_t cell_div;
@@ -430,6 +439,8 @@ typedef struct sph_batch {
   int64_t key_cells;    /* sum over slots of (cells + 1): cell_start has
                            key_cells + 1 entries */
   const void* table;    /* DEVICE copy of the slot table (see below) */
+  uint32_t flags;       /* SPH_BATCH_* flags */
+  uint32_t pad;
 } sph_batch;
 
 /* Bytes of the slot table for n_slots cases. */

@@ -341,7 +341,7 @@ static bool batch_ok(const sph_batch* b) {
 }
 
 static BatchDesc batch_desc(const sph_batch* b) {
-  return BatchDesc{b->n_slots, b->cell_div, b->n_total, b->key_cells, b->table};
+  return BatchDesc{b->n_slots, b->cell_div, b->n_total, b->key_cells, b->table, b->flags};
 }
 
 size_t sph_batch_table_bytes(int32_t n_slots) {
@@ -376,7 +376,11 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
     if (cbase >= 0xfffffff0ull) return SPH_E_ARG;
   }
   if (offsets[n_slots] >= ((int64_t)1 << 27)) return SPH_E_ARG;
+  bool aligned = true;
+  for (int s = 0; s <= n_slots; ++s) aligned = aligned && offsets[s] % 64 == 0;
   batch->n_slots = n_slots;
+  batch->flags = aligned ? SPH_BATCH_WAVE_ALIGNED : 0u;
+  batch->pad = 0;
   batch->cell_div = params[0].cell_div;
   batch->n_total = offsets[n_slots];
   batch->key_cells = (int64_t)cbase;

@@ -91,15 +91,74 @@ __global__ void k_batch_refresh_view(const SlotEntry* __restrict__ tab, int ns, 
   write_view(kp, i, x, v, s.rho[i], t, key[i] - tab[sl].cbase, pr, vp);
 }
 
-// The interaction over all slots in one launch: one lane per target walking
-// its own cells (gather_walk), with the constants of the target's slot.  The
-// lanes of a wave are processed slot by slot (almost always one slot), so the
-// constants stay uniform.  Per-slot maxima and pair counts are combined with
-// order-independent atomics (max of non-negative float bits, integer adds).
-// STALE: the cells of the last binning are reused for a refreshed view (the
-// search reaches R, one cell beyond the cells' own stencil, and culls with the
-// support widened by the slot's recorded displacement).
+// One slot's targets among the wave's lanes (`mine`), with that slot's
+// constants: each lane walks its own cells (gather_walk) and writes its
+// target; returns the lane's contributions to the slot's sums.  The slot's
+// error words get SPH_ERR_MARGIN (STALE: cells reused after particles moved
+// half a cell or more) from lane `leader`.
 template <int R, bool STALE>
+__device__ __forceinline__ void batch_slot_pass(
+    const SlotEntry* __restrict__ tab, int rs, int leader, bool mine, int64_t n, int64_t a,
+    const float4* __restrict__ pr, const float4* __restrict__ vp, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
+    float* __restrict__ visc, uint32_t* __restrict__ nbr, const uint32_t* __restrict__ disp,
+    uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err, float& fmag, float& vmx,
+    uint32_t& cnt, uint32_t& cntw, uint32_t& nfl) {
+  const KParams kp = tab[rs].kp;
+  const uint32_t cbase = tab[rs].cbase;
+  float cull2 = kp.support2_f * 1.0002f;
+  if (STALE) {
+    const float delta = read_displacement(disp + (size_t)rs * kDispSlots);
+    const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
+    cull2 = rc * rc;
+    if (!(2.f * delta < kp.cs_f) && (threadIdx.x & 63) == leader) {
+      set_error(err, SPH_ERR_MARGIN);
+      set_error(&slot_err[rs], SPH_ERR_MARGIN);
+    }
+  }
+  if (!mine) return;
+  const uint32_t lk = key[a] - cbase;
+  // a particle the view refresh excluded keeps its cell but has density 0
+  const float4 pa = pr[a];
+  if (lk < kp.ncell_total && (!STALE || pa.w != 0.f)) {
+    PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
+    const float4 va = vp[a];
+    T.fluid = pa.w > 0.f;
+    T.rho = fabsf(pa.w);
+    T.irho = __builtin_amdgcn_rcpf(T.rho);
+    T.ik = kp.kvc_f * T.irho;
+    T.p = va.w;
+    T.vx = va.x;
+    T.vy = va.y;
+    T.vz = va.z;
+    const int cx = (int)(lk % (uint32_t)kp.ncx);
+    const uint32_t rest = lk / (uint32_t)kp.ncx;
+    const int cy = (int)(rest % (uint32_t)kp.ncy);
+    const int cz = (int)(rest / (uint32_t)kp.ncy);
+    uint32_t c64 = 0;
+    gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
+                                                  cstart, nullptr, acc, c64, cull2);
+    write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
+    cnt = acc.cnt;
+    cntw = T.fluid ? 0u : acc.cnt;
+  } else {
+    write_zero<3>(n, a, ace, arho, visc, nbr);
+  }
+}
+
+// The interaction over all slots in one launch: one lane per target, with
+// the constants of the target's slot.  ALIGNED: every slot's particle range
+// is a whole number of wavefronts (sph_batch_describe's flag), so each wave
+// lies in one slot and makes one pass; otherwise the lanes of a wave are
+// processed slot by slot (almost always one slot), keeping the constants
+// uniform, which costs registers.  Per-slot maxima and pair counts are
+// combined with order-independent atomics (max of non-negative float bits,
+// integer adds).  STALE: the cells of the last binning are reused for a
+// refreshed view (the search reaches R, one cell beyond the cells' own
+// stencil, and culls with the support widened by the slot's recorded
+// displacement).
+template <int R, bool STALE, bool ALIGNED>
 __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
     const float4* __restrict__ vp, const uint32_t* __restrict__ key,
@@ -113,54 +172,22 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
   const int sa = a < n ? find_slot(tab, ns, a) : -1;
   float fmag = 0.f, vmx = 0.f;
   uint32_t cnt = 0, cntw = 0, nfl = 0;
-  bool todo = a < n;
-  while (__ballot(todo) != 0ull) {
-    const int leader = (int)__builtin_ctzll(__ballot(todo));
-    const int rs = __builtin_amdgcn_readlane(sa, leader);
-    const bool mine = todo && sa == rs;
-    const KParams kp = tab[rs].kp;
-    const uint32_t cbase = tab[rs].cbase;
-    float cull2 = kp.support2_f * 1.0002f;
-    if (STALE) {
-      const float delta = read_displacement(disp + (size_t)rs * kDispSlots);
-      const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
-      cull2 = rc * rc;
-      if (!(2.f * delta < kp.cs_f) && (threadIdx.x & 63) == leader) {
-        set_error(err, SPH_ERR_MARGIN);
-        set_error(&slot_err[rs], SPH_ERR_MARGIN);
-      }
+  if (ALIGNED) {
+    // one slot for the whole wave, or a wave wholly past n (sa = -1)
+    const int rs = __builtin_amdgcn_readfirstlane(sa);
+    if (rs >= 0)
+      batch_slot_pass<R, STALE>(tab, rs, 0, a < n, n, a, pr, vp, key, cstart, ace, arho, visc,
+                                nbr, disp, err, slot_err, fmag, vmx, cnt, cntw, nfl);
+  } else {
+    bool todo = a < n;
+    while (__ballot(todo) != 0ull) {
+      const int leader = (int)__builtin_ctzll(__ballot(todo));
+      const int rs = __builtin_amdgcn_readlane(sa, leader);
+      const bool mine = todo && sa == rs;
+      batch_slot_pass<R, STALE>(tab, rs, leader, mine, n, a, pr, vp, key, cstart, ace, arho,
+                                visc, nbr, disp, err, slot_err, fmag, vmx, cnt, cntw, nfl);
+      todo = todo && !mine;
     }
-    if (mine) {
-      const uint32_t lk = key[a] - cbase;
-      // a particle the view refresh excluded keeps its cell but has density 0
-      const float4 pa = pr[a];
-      if (lk < kp.ncell_total && (!STALE || pa.w != 0.f)) {
-        PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-        TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
-        const float4 va = vp[a];
-        T.fluid = pa.w > 0.f;
-        T.rho = fabsf(pa.w);
-        T.irho = __builtin_amdgcn_rcpf(T.rho);
-        T.ik = kp.kvc_f * T.irho;
-        T.p = va.w;
-        T.vx = va.x;
-        T.vy = va.y;
-        T.vz = va.z;
-        const int cx = (int)(lk % (uint32_t)kp.ncx);
-        const uint32_t rest = lk / (uint32_t)kp.ncx;
-        const int cy = (int)(rest % (uint32_t)kp.ncy);
-        const int cz = (int)(rest / (uint32_t)kp.ncy);
-        uint32_t c64 = 0;
-        gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
-                                                      cstart, nullptr, acc, c64, cull2);
-        write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
-        cnt = acc.cnt;
-        cntw = T.fluid ? 0u : acc.cnt;
-      } else {
-        write_zero<3>(n, a, ace, arho, visc, nbr);
-      }
-    }
-    todo = todo && !mine;
   }
   // per-slot combination into copy lb % kAccCopies of the slot's sums: the
   // block's waves combined in LDS when the block lies in one slot (one set
@@ -375,18 +402,27 @@ hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
   const unsigned grid = grid_for(n);
-#define SPH_BATCH_LAUNCH(RR, STALE)                                                            \
-  hipLaunchKernelGGL((k_batch_interact<RR, STALE>), dim3(grid), dim3(kBlock), 0, st, tab,       \
+#define SPH_BATCH_LAUNCH(RR, STALE, AL)                                                        \
+  hipLaunchKernelGGL((k_batch_interact<RR, STALE, AL>), dim3(grid), dim3(kBlock), 0, st, tab,   \
                      B.n_slots, n, ws_ptr<float4>(ws, W.base.view_pr),                          \
                      ws_ptr<float4>(ws, W.base.view_vp), key, cell_start, ace, arho, visc, nbr, \
                      ws_ptr<SlotAccum>(ws, W.accum), ws_ptr<uint32_t>(ws, W.disp),              \
                      ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err))
+#define SPH_BATCH_LAUNCH_R(RR, STALE)                                                          \
+  if (aligned) SPH_BATCH_LAUNCH(RR, STALE, true); else SPH_BATCH_LAUNCH(RR, STALE, false)
+  const bool aligned = (B.flags & SPH_BATCH_WAVE_ALIGNED) != 0;
   // reused cells: the search reaches one cell further than the cells' stencil
   const int reach = B.cell_div + (reuse ? 1 : 0);
-  if (reach == 1) SPH_BATCH_LAUNCH(1, false);
-  else if (reach == 2 && !reuse) SPH_BATCH_LAUNCH(2, false);
-  else if (reach == 2) SPH_BATCH_LAUNCH(2, true);
-  else SPH_BATCH_LAUNCH(3, true);
+  if (reach == 1) {
+    SPH_BATCH_LAUNCH_R(1, false);
+  } else if (reach == 2 && !reuse) {
+    SPH_BATCH_LAUNCH_R(2, false);
+  } else if (reach == 2) {
+    SPH_BATCH_LAUNCH_R(2, true);
+  } else {
+    SPH_BATCH_LAUNCH_R(3, true);
+  }
+#undef SPH_BATCH_LAUNCH_R
 #undef SPH_BATCH_LAUNCH
   return hipGetLastError();
 }

@@ -15,6 +15,7 @@ struct BatchDesc {
   int64_t n_total;
   int64_t key_cells;
   const void* table;  // device SlotEntry[n_slots]
+  uint32_t flags;     // SPH_BATCH_* flags of sph_batch_describe
 };
 int key_bits(uint32_t ncell_total);
 void exclusive_scan(uint32_t* data, int64_t len, uint32_t* part, hipStream_t st);

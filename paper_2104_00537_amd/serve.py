@@ -83,12 +83,13 @@ class _Flat:
 
 
 # Each slot's particle range is padded to a whole number of wavefronts with
-# excluded particles, so that no wavefront holds targets of two slots.
+# excluded particles, so that no wavefront holds targets of two slots (the
+# batch's SPH_BATCH_WAVE_ALIGNED kernels).
 WAVE = 64
 
 
-def padded(n: int) -> int:
-    return -(-n // WAVE) * WAVE
+def padded(n: int, pad: bool = True) -> int:
+    return -(-n // WAVE) * WAVE if pad else n
 
 
 class BatchEngine:
@@ -96,12 +97,13 @@ class BatchEngine:
 
     def __init__(self, cap_particles: int, cap_cells: int, max_slots: int = 256,
                  device="cuda", use_graph: bool = True, cell_div: int = 1,
-                 reuse_cells: bool = True):
+                 reuse_cells: bool = True, pad_slots: bool = True):
         self.dev = torch.device(device)
         # one binning per step: the n+1/2 interaction reuses the cells of
         # state n (sph_batch_refresh_view, SPH_INTERACT_REUSE_CELLS); the
         # state then alternates between the two buffers, `cur` holding it
         self.reuse = bool(reuse_cells)
+        self.pad = bool(pad_slots)
         self.cur = 0
         self.cap_n = int(cap_particles)
         self.cap_cells = int(cap_cells)
@@ -142,7 +144,7 @@ class BatchEngine:
     def fits(self, slots: List[Request], req: Request) -> bool:
         """Footprint admission: a free slot, particle capacity (HBM) and cell
         capacity for `slots` plus `req`."""
-        n_after = sum(padded(r.n) for r in slots) + padded(req.n)
+        n_after = sum(padded(r.n, self.pad) for r in slots) + padded(req.n, self.pad)
         cells_after = sum(r.case.params.ncell_total() + 1 for r in slots + [req])
         return (len(slots) + 1 <= self.max_slots and n_after <= self.cap_n
                 and cells_after <= self.cap_cells)
@@ -174,7 +176,7 @@ class BatchEngine:
         new_slots = keep + add
         offsets = [0]
         for r in new_slots:
-            offsets.append(offsets[-1] + padded(r.n))
+            offsets.append(offsets[-1] + padded(r.n, self.pad))
         n = offsets[-1]
         if n > self.cap_n:
             raise S.SphError(f"batch of {n} particles (slots padded to whole wavefronts) "

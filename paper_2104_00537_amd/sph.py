@@ -38,6 +38,7 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
            "sph_batch_reduce_dt",
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
 SPH_BATCH_MAX_SLOTS = 4096
+SPH_BATCH_WAVE_ALIGNED = 1
 
 
 class SphParams(C.Structure):
@@ -72,7 +73,8 @@ class SphState(C.Structure):
 
 class SphBatch(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("cell_div", C.c_int32), ("n_total", C.c_int64),
-                ("key_cells", C.c_int64), ("table", C.c_void_p)]
+                ("key_cells", C.c_int64), ("table", C.c_void_p), ("flags", C.c_uint32),
+                ("pad", C.c_uint32)]
 
 
 class SphError(RuntimeError):

@@ -235,6 +235,16 @@ def test_batch_calls_validate_without_device(S):
                                          1 << 30, None) == S.SPH_E_ARG
 
 
+def test_batch_describe_sets_the_wave_alignment_flag(S):
+    """SPH_BATCH_WAVE_ALIGNED iff every slot offset is a multiple of 64."""
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d(dp=0.02).params)
+    for offs, want in (([0, 64, 192], True), ([0, 64, 190], False), ([0, 60, 128], False),
+                       ([0, 0, 128], True)):
+        b, _ = S.sph_batch_describe([P, P], offs)
+        assert bool(b.flags & S.SPH_BATCH_WAVE_ALIGNED) == want, offs
+
+
 def test_batch_rejects_formulation_options(S):
     """The batched path runs the default formulation only."""
     import dataclasses
