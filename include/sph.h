@@ -108,7 +108,15 @@ enum {
    * found as after a new binning (only the summation order differs).  Sets
    * SPH_ERR_MARGIN if a particle moved half a cell or more.  Combines with
    * SPH_DIAG_COUNT_F64; not with the precision-study arms or modified DBC. */
-  SPH_INTERACT_REUSE_CELLS = 8u
+  SPH_INTERACT_REUSE_CELLS = 8u,
+  /* One lane per target particle.  By default a case too small to fill the
+   * GPU (at most 262,144 particles) with the default formulation (Wendland
+   * kernel, artificial viscosity, ddt 0 or 1, no floating bodies or periodic
+   * components) deals each target's neighbour rows to four lanes and sums
+   * their results, which shortens each lane's chain of dependent loads;
+   * results agree up to the order of the FP32 sums (FP64 counts are
+   * identical).  Combines with every other flag. */
+  SPH_INTERACT_ONE_LANE = 16u
 };
 
 /* Case constants, passed by pointer to host memory and copied by value into

@@ -222,14 +222,15 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
   // none, the FP64 diagnostic count and/or reused cells, or one
   // precision-study arm alone
   const uint32_t reuse = flags & SPH_INTERACT_REUSE_CELLS;
-  const uint32_t base = flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS;
+  const uint32_t base =
+      flags & ~(uint32_t)(SPH_INTERACT_REUSE_CELLS | SPH_INTERACT_ONE_LANE);
   if (base != 0 && base != SPH_DIAG_COUNT_F64 && base != SPH_INTERACT_F64 &&
       base != SPH_INTERACT_ABS_F32)
     return SPH_E_ARG;
   if (reuse && (base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 || p->boundary != 0))
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
-  if ((flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) &&
+  if ((base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32) &&
       (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0 ||
        p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0))
     return SPH_E_ARG;

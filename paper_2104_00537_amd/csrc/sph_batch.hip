@@ -139,6 +139,7 @@ __device__ __forceinline__ void batch_slot_pass(
     uint32_t c64 = 0;
     gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
                                                   cstart, nullptr, acc, c64, cull2);
+    if (T.fluid) acc.cnt -= 1u;  // the self pair: counted, added nothing
     write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
     cnt = acc.cnt;
     cntw = T.fluid ? 0u : acc.cnt;

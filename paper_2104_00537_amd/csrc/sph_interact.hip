@@ -14,15 +14,47 @@
 namespace sph {
 
 // ------------------------------------------------- interaction: gather --
-// One lane per target particle (sorted order): the production kernel.
-template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER>
+// The target's own terms from its view entry (sorted slot i).
+template <bool GEN>
+__device__ __forceinline__ void target_data(const KParams& kp, int64_t i,
+                                            const float4* __restrict__ pr,
+                                            const float4* __restrict__ vp,
+                                            const uint8_t* __restrict__ type, TargetData& T) {
+  const float4 pa = pr[i], va = vp[i];
+  T.fluid = pa.w > 0.f;
+  T.rho = fabsf(pa.w);
+  T.irho = __builtin_amdgcn_rcpf(T.rho);
+  T.ik = kp.kvc_f * T.irho;
+  T.p = va.w;
+  T.vx = va.x;
+  T.vy = va.y;
+  T.vz = va.z;
+  T.flt = GEN && kp.floating && is_floating(type[i]);
+}
+
+// Cell coordinates (in key cells) of key k.
+__device__ __forceinline__ void key_cell(const KParams& kp, uint32_t k, int& cx, int& cy,
+                                         int& cz) {
+  cx = (int)(k % (uint32_t)kp.ncx);
+  const uint32_t rest = k / (uint32_t)kp.ncx;
+  cy = (int)(rest % (uint32_t)kp.ncy);
+  cz = (int)(rest / (uint32_t)kp.ncy);
+}
+
+// LPT lanes per target particle (sorted order); LPT = 1 is the production
+// kernel of large cases, LPT = 4 deals each target's rows to four lanes for
+// cases too small to fill the GPU.
+template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER, int LPT>
 __global__ __launch_bounds__(kBlock) void k_interact_gather(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
     const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
     BlockRed* __restrict__ red, WsHeader* __restrict__ hdr, const uint32_t* __restrict__ disp) {
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  static_assert(LPT == 1 || LPT == 2 || LPT == 4, "lanes per target: 1, 2 or 4");
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int64_t i = t / LPT;
+  const int sub = (int)(t % LPT);
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   // cells reused after a view refresh (R above the cells' own stencil): cull
@@ -35,36 +67,64 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
     if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)
       set_error(&hdr->err, SPH_ERR_MARGIN);
   }
-  if (i < n) {
+  if constexpr (LPT == 1) {
+    if (i < n) {
+      PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+      TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
+      uint32_t c64 = 0;
+      // with modified DBC the wall densities come from Eq. 38 (sph_mdbc): wall
+      // targets take no sums
+      if (!is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]))) {
+        const float4 pa = pr[i], va = vp[i];
+        T.fluid = pa.w > 0.f;
+        T.rho = fabsf(pa.w);
+        T.irho = __builtin_amdgcn_rcpf(T.rho);
+        T.ik = kp.kvc_f * T.irho;
+        T.p = va.w;
+        T.vx = va.x;
+        T.vy = va.y;
+        T.vz = va.z;
+        T.flt = GEN && kp.floating && is_floating(type[i]);
+        const uint32_t k = key[i];
+        const int cx = (int)(k % (uint32_t)kp.ncx);
+        const uint32_t rest = k / (uint32_t)kp.ncx;
+        const int cy = (int)(rest % (uint32_t)kp.ncy);
+        const int cz = (int)(rest / (uint32_t)kp.ncy);
+        gather_walk<DIM, R, DIAG, EQM, GEN, PER>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart,
+                                                pos64, acc, c64, cull2);
+        if (T.fluid) acc.cnt -= 1u;  // the self pair: counted, added nothing
+        const uint32_t c = DIAG ? c64 : acc.cnt;
+        write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+        cnt_out = acc.cnt;
+        cnt_wall = T.fluid ? 0u : acc.cnt;
+      } else {
+        write_zero<DIM>(n, i, ace, arho, visc, nbr);
+      }
+    }
+  } else {
     PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
     TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
     uint32_t c64 = 0;
-    // with modified DBC the wall densities come from Eq. 38 (sph_mdbc): wall
-    // targets take no sums
-    if (!is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]))) {
-      const float4 pa = pr[i], va = vp[i];
-      T.fluid = pa.w > 0.f;
-      T.rho = fabsf(pa.w);
-      T.irho = __builtin_amdgcn_rcpf(T.rho);
-      T.ik = kp.kvc_f * T.irho;
-      T.p = va.w;
-      T.vx = va.x;
-      T.vy = va.y;
-      T.vz = va.z;
-      T.flt = GEN && kp.floating && is_floating(type[i]);
-      const uint32_t k = key[i];
-      const int cx = (int)(k % (uint32_t)kp.ncx);
-      const uint32_t rest = k / (uint32_t)kp.ncx;
-      const int cy = (int)(rest % (uint32_t)kp.ncy);
-      const int cz = (int)(rest / (uint32_t)kp.ncy);
-      gather_walk<DIM, R, DIAG, EQM, GEN, PER>(kp, 0u, n, i, pa, T, cx, cy, cz, pr, vp, cstart,
-                                              pos64, acc, c64, cull2);
-      const uint32_t c = DIAG ? c64 : acc.cnt;
-      write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
-      cnt_out = acc.cnt;
-      cnt_wall = T.fluid ? 0u : acc.cnt;
-    } else {
-      write_zero<DIM>(n, i, ace, arho, visc, nbr);
+    const bool active =
+        i < n && !is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]));
+    if (active) {
+      target_data<GEN>(kp, i, pr, vp, type, T);
+      int cx, cy, cz;
+      key_cell(kp, key[i], cx, cy, cz);
+      gather_walk<DIM, R, DIAG, EQM, GEN, PER, LPT>(kp, 0u, n, i, pr[i], T, cx, cy, cz, pr, vp,
+                                                    cstart, pos64, acc, c64, cull2, sub);
+    }
+    combine_lanes<LPT>(acc, c64);  // every lane: the sums of its target's lanes
+    if (i < n && sub == 0) {
+      if (active) {
+        if (T.fluid) acc.cnt -= 1u;  // the self pair: counted, added nothing
+        const uint32_t c = DIAG ? c64 : acc.cnt;
+        write_target<DIM>(kp, n, i, T, acc, c, ace, arho, visc, nbr, fmag, vmax_out, nfl);
+        cnt_out = acc.cnt;
+        cnt_wall = T.fluid ? 0u : acc.cnt;
+      } else {
+        write_zero<DIM>(n, i, ace, arho, visc, nbr);
+      }
     }
   }
   write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
@@ -198,8 +258,9 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   BlockRed* red = ws_ptr<BlockRed>(ws, L.red);
   WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
   const unsigned grid = (unsigned)L.nblk_interact;
-  if (flags == SPH_INTERACT_F64 || flags == SPH_INTERACT_ABS_F32) {
-    const bool f64 = flags == SPH_INTERACT_F64;
+  const uint32_t arm = flags & ~(uint32_t)SPH_INTERACT_ONE_LANE;  // the arms take one lane
+  if (arm == SPH_INTERACT_F64 || arm == SPH_INTERACT_ABS_F32) {
+    const bool f64 = arm == SPH_INTERACT_F64;
 #define SPH_ARM(D, RR, T)                                                                  \
   hipLaunchKernelGGL((k_interact_arm<D, RR, T>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
                      vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr)
@@ -220,14 +281,19 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   const bool eqm = kp.mass_f == kp.mass_b;
   const bool gen = kp.kernel != 0 || kp.viscosity != 0 || kp.ddt == 2 || kp.floating != 0;
   const bool per = kp.periodic != 0;  // periodic cases run the general kernel with PER
-#define SPH_LAUNCH(D, RR, G, PP, GG, PE)                                                   \
-  hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG, PE>), dim3(grid), dim3(kBlock), 0, \
-                     st, kp, n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, \
-                     red, hdr, ws_ptr<uint32_t>(ws, L.disp))
+  // small cases of the default formulation: four lanes per target
+  const bool lanes4 = !gen && !per && !(flags & SPH_INTERACT_ONE_LANE) && n <= kLanesMaxN;
+  const unsigned grid4 = (unsigned)((n * kMaxLanes + kBlock - 1) / kBlock);
+#define SPH_LAUNCH(D, RR, G, PP, GG, PE, LP)                                                 \
+  hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG, PE, LP>),                          \
+                     dim3(LP == 1 ? grid : (grid4 > 0 ? grid4 : 1)), dim3(kBlock), 0, st, kp, n, \
+                     pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr,   \
+                     ws_ptr<uint32_t>(ws, L.disp))
 #define SPH_LAUNCH_G(D, RR, G, PP)                                       \
-  if (per) SPH_LAUNCH(D, RR, G, PP, true, true);                         \
-  else if (gen) SPH_LAUNCH(D, RR, G, PP, true, false);                   \
-  else SPH_LAUNCH(D, RR, G, PP, false, false)
+  if (per) SPH_LAUNCH(D, RR, G, PP, true, true, 1);                      \
+  else if (gen) SPH_LAUNCH(D, RR, G, PP, true, false, 1);                \
+  else if (lanes4) SPH_LAUNCH(D, RR, G, PP, false, false, kMaxLanes);    \
+  else SPH_LAUNCH(D, RR, G, PP, false, false, 1)
 #define SPH_LAUNCH_P(D, RR, G) \
   if (eqm) SPH_LAUNCH_G(D, RR, G, true); else SPH_LAUNCH_G(D, RR, G, false)
 #define SPH_LAUNCH_R(D, RR) \

@@ -110,6 +110,11 @@ struct SlotMotion {
   double dt, dmove, vmove, pad;
 };
 
+// Most lanes that share one target particle in the interaction, and the
+// largest case that gets them (n * kMaxLanes / 64 wavefronts at most).
+constexpr int kMaxLanes = 4;
+constexpr int64_t kLanesMaxN = 262144;
+
 // Workspace layout (offsets in bytes, each region 256-aligned).
 struct WsLayout {
   size_t err;        // the WsHeader (offset 0)
@@ -150,7 +155,8 @@ inline WsLayout ws_layout(int64_t n) {
   // in groups of 4 with scalar loads that may run past the last particle
   L.view_pr = off; off = align_up(off + 16 * (nn + kViewPad));
   L.view_vp = off; off = align_up(off + 16 * (nn + kViewPad));
-  L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact);
+  // (room for the blocks of kMaxLanes lanes per target)
+  L.red = off; off = align_up(off + sizeof(BlockRed) * (size_t)L.nblk_interact * kMaxLanes);
   L.disp = off; off = align_up(off + sizeof(uint32_t) * kDispSlots);
   L.fpart = off;
   off = align_up(off + sizeof(double) * SPH_MAX_BODIES * kFloatParts * kFloatSums);

@@ -291,11 +291,16 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 // is never a neighbour.
 //
 // The target is not excluded from its own candidates: its self pair adds
-// exactly zero to every sum (v_aa = 0, r_aa = 0 and rho_a - rho_a = 0) and is
-// taken off the count here (fluid targets meet themselves; wall targets skip
-// wall candidates).  DIAG also counts neighbours with an FP64 test on the
-// FP64 positions (c64, self excluded).
-template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER>
+// exactly zero to every sum (v_aa = 0, r_aa = 0 and rho_a - rho_a = 0) and
+// the caller takes it off the count (fluid targets meet themselves; wall
+// targets skip wall candidates).  DIAG also counts neighbours with an FP64
+// test on the FP64 positions (c64, self excluded).
+//
+// LPT > 1: the rows of the stencil are dealt to LPT lanes (by position in
+// the stencil, lane `sub` taking every LPT-th), which shortens each lane's
+// chain of dependent loads for cases too small to fill the GPU; the caller
+// sums the lanes' partial results (combine_lanes).
+template <int DIM, int R, bool DIAG, bool EQM, bool GEN, bool PER, int LPT = 1>
 __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, int64_t n,
                                             int64_t i, const float4& pa, const TargetData& T,
                                             int cx, int cy, int cz,
@@ -303,7 +308,7 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
                                             const float4* __restrict__ vp,
                                             const uint32_t* __restrict__ cstart,
                                             const double* __restrict__ pos64, PairAcc& acc,
-                                            uint32_t& c64, float cull2) {
+                                            uint32_t& c64, float cull2, int sub = 0) {
   static_assert(R <= 3, "the x period (8 cells) must exceed twice the stencil reach");
   static_assert(kFrameCells == 8, "x offsets use 2^29 units per cell");
   double pa64[3] = {0.0, 0.0, 0.0};
@@ -323,58 +328,86 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
   const int xlo = cx - reach < 0 && !perx ? 0 : cx - reach;
   const int xhi = cx + reach >= kp.ncx && !perx ? kp.ncx - 1 : cx + reach;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
+  // one row of the stencil: the key cells (dy, dz) away, cut to the window
+  // the support sphere reaches
+  auto visit = [&](int dz, int dy) {
     int z = cz + dz;
     if (z < 0 || z >= kp.ncz) {
-      if (!perz) continue;
+      if (!perz) return;
       z += z < 0 ? kp.ncz : -kp.ncz;
     }
     const float ez0 = (float)dz * cs - pa.z;  // lower edge of the row's z extent
     const float ez = dz > 0 ? ez0 : (dz < 0 ? -(ez0 + cs) : 0.f);
-    for (int dy = -R; dy <= R; ++dy) {
-      int y = cy + dy;
-      if (y < 0 || y >= kp.ncy) {
-        if (!pery) continue;
-        y += y < 0 ? kp.ncy : -kp.ncy;
+    int y = cy + dy;
+    if (y < 0 || y >= kp.ncy) {
+      if (!pery) return;
+      y += y < 0 ? kp.ncy : -kp.ncy;
+    }
+    const float ey0 = (float)dy * cs - pa.y;
+    const float ey = dy > 0 ? ey0 : (dy < 0 ? -(ey0 + cs) : 0.f);
+    const float w2 = cull2 - ey * ey - ez * ez;
+    if (!(w2 > 0.f)) return;
+    const float w = __builtin_amdgcn_sqrtf(w2);
+    int x0 = cx + (int)floorf((fx - w) * kp.inv_csx_f);
+    int x1 = cx + (int)floorf((fx + w) * kp.inv_csx_f);
+    x0 = x0 < xlo ? xlo : x0;
+    x1 = x1 > xhi ? xhi : x1;
+    const uint32_t row =
+        cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+    const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
+    // the candidates of key cells [c0, c1] of the row, with target x bits xv
+    auto walk = [&](int c0, int c1, uint32_t xv) {
+      const uint32_t j0 = cstart[row + c0], j1 = cstart[row + c1 + 1];
+      uint32_t j = j0;
+      for (; j + 4 <= j1; j += 4)
+        gather_group<DIM, DIAG, EQM, GEN, PER, false>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
+                                                      pa64, pos64, acc, c64);
+      if (j < j1)
+        gather_group<DIM, DIAG, EQM, GEN, PER, true>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
+                                                     pa64, pos64, acc, c64);
+    };
+    if (perx) {
+      if (x0 < 0) {  // cells at the far end, one period below
+        walk(kp.ncx + x0, kp.ncx - 1, xa + kp.lu);
+        x0 = 0;
       }
-      const float ey0 = (float)dy * cs - pa.y;
-      const float ey = dy > 0 ? ey0 : (dy < 0 ? -(ey0 + cs) : 0.f);
-      const float w2 = cull2 - ey * ey - ez * ez;
-      if (!(w2 > 0.f)) continue;
-      const float w = __builtin_amdgcn_sqrtf(w2);
-      int x0 = cx + (int)floorf((fx - w) * kp.inv_csx_f);
-      int x1 = cx + (int)floorf((fx + w) * kp.inv_csx_f);
-      x0 = x0 < xlo ? xlo : x0;
-      x1 = x1 > xhi ? xhi : x1;
-      const uint32_t row =
-          cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-      const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
-      // the candidates of key cells [c0, c1] of the row, with target x bits xv
-      auto walk = [&](int c0, int c1, uint32_t xv) {
-        const uint32_t j0 = cstart[row + c0], j1 = cstart[row + c1 + 1];
-        uint32_t j = j0;
-        for (; j + 4 <= j1; j += 4)
-          gather_group<DIM, DIAG, EQM, GEN, PER, false>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
-                                                        pa64, pos64, acc, c64);
-        if (j < j1)
-          gather_group<DIM, DIAG, EQM, GEN, PER, true>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
-                                                       pa64, pos64, acc, c64);
-      };
-      if (perx) {
-        if (x0 < 0) {  // cells at the far end, one period below
-          walk(kp.ncx + x0, kp.ncx - 1, xa + kp.lu);
-          x0 = 0;
-        }
-        if (x1 >= kp.ncx) {  // cells at the near end, one period above
-          walk(0, x1 - kp.ncx, xa - kp.lu);
-          x1 = kp.ncx - 1;
-        }
+      if (x1 >= kp.ncx) {  // cells at the near end, one period above
+        walk(0, x1 - kp.ncx, xa - kp.lu);
+        x1 = kp.ncx - 1;
       }
-      walk(x0, x1, xa);
+    }
+    walk(x0, x1, xa);
+  };
+  if constexpr (LPT == 1) {
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = -R; dy <= R; ++dy) visit(dz, dy);
+  } else {
+    // the LPT lanes of a target walk different rows at the same time: in
+    // round q, lane `sub` takes row q LPT + sub of the stencil
+    constexpr int kRowsY = 2 * R + 1;
+    constexpr int kRows = kRowsY * (DIM == 3 ? 2 * R + 1 : 1);
+    for (int q = 0; q < (kRows + LPT - 1) / LPT; ++q) {
+      const int r = q * LPT + sub;
+      if (r < kRows) visit(zlo + r / kRowsY, r % kRowsY - R);
     }
   }
-  // the self pair (fluid targets only) was counted and added nothing
-  if (T.fluid) acc.cnt -= 1u;
+}
+
+// Sums the walks of the LPT lanes of each target (adjacent lanes, LPT a
+// power of two); every lane of the wave calls this, and every lane of a
+// group ends with the group's sums.  Maxima take the maximum.
+template <int LPT>
+__device__ __forceinline__ void combine_lanes(PairAcc& acc, uint32_t& c64) {
+  for (int off = 1; off < LPT; off <<= 1) {
+    acc.ax += __shfl_xor(acc.ax, off, 64);
+    acc.ay += __shfl_xor(acc.ay, off, 64);
+    acc.az += __shfl_xor(acc.az, off, 64);
+    acc.cont += __shfl_xor(acc.cont, off, 64);
+    acc.diff += __shfl_xor(acc.diff, off, 64);
+    acc.vmax = fmaxf(acc.vmax, __shfl_xor(acc.vmax, off, 64));
+    acc.cnt += (uint32_t)__shfl_xor((int)acc.cnt, off, 64);
+    c64 += (uint32_t)__shfl_xor((int)c64, off, 64);
+  }
 }
 
 }  // namespace sph

@@ -76,7 +76,7 @@ class Simulation:
         # with modified DBC, shifting or a precision-study arm, whose passes
         # search the cells without a displacement margin)
         can_reuse = (integrator == "symplectic" and not self.mdbc and not self.shifting
-                     and self.flags in (0, S.SPH_DIAG_COUNT_F64))
+                     and (self.flags & ~S.SPH_INTERACT_ONE_LANE) in (0, S.SPH_DIAG_COUNT_F64))
         if reuse_cells and not can_reuse:
             raise ValueError("reuse_cells needs the symplectic integrator, DBC walls, no "
                              "shifting and no precision-study arm")

@@ -27,6 +27,7 @@ SPH_DIAG_COUNT_F64 = 1
 SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
 SPH_INTERACT_REUSE_CELLS = 8
+SPH_INTERACT_ONE_LANE = 16
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_interact",
            "sph_reduce_dt",

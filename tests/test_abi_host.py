@@ -101,7 +101,11 @@ def test_floating_step_validates_without_device(S):
     P1 = S.make_params(c.params)
     P1.boundary = 1
     assert call(p=P1) == S.SPH_E_ARG
-    for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32):
+    # the precision-study arms take the default formulation only, with or
+    # without the one-lane flag
+    for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32,
+                  S.SPH_INTERACT_F64 | S.SPH_INTERACT_ONE_LANE,
+                  S.SPH_INTERACT_ABS_F32 | S.SPH_INTERACT_ONE_LANE):
         assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, flags, d,
                                 need, None) == S.SPH_E_ARG
     with pytest.raises(S.SphError):
@@ -173,8 +177,10 @@ def test_workspace_and_pointer_checks_without_device(S):
     # null outputs
     assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, None, d, None, None, 0, d, need,
                             None) == S.SPH_E_ARG
-    assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, 0x10, d, need,
-                            None) == S.SPH_E_ARG
+    # an unknown flag bit (0x20), and unknown bits with the known ones
+    for fl in (0x20, 0x20 | S.SPH_INTERACT_ONE_LANE, 0x40 | S.SPH_DIAG_COUNT_F64):
+        assert lib.sph_interact(C.byref(P), 1000, C.byref(st), d, d, d, d, None, None, fl, d,
+                                need, None) == S.SPH_E_ARG
     assert lib.sph_symplectic_step(C.byref(P), 1000, 2, d, d, C.byref(st), C.byref(st), d, d, d,
                                    need, None) == S.SPH_E_ARG
     assert lib.sph_read_error(None) == S.SPH_E_ARG

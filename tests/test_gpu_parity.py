@@ -247,6 +247,36 @@ def test_interaction_stencils_agree():
             assert np.abs(t[i] - g[i]).max() <= 2e-5 * scale
 
 
+@pytest.mark.parametrize("dim,grid", [(2, (1, 1)), (2, (2, 4)), (3, (1, 2)), (3, (2, 4))])
+def test_four_lanes_per_target_agree_with_one(dim, grid):
+    """A case small enough for four lanes per target (the default for such
+    cases): the same FP64 counts and FP32 pair decisions as one lane per
+    target (SPH_INTERACT_ONE_LANE), sums equal up to their order, and both
+    within the interaction's bar of the oracle."""
+    shape = (40, 24) if dim == 2 else (17, 13, 11)
+    c = _perturbed(cases.block_case(dim, shape, walls=True, seed=41 + dim, cell_div=grid[0],
+                                    x_sub=grid[1]), 42, vel=0.4)
+    assert c.n <= 262144
+    b = Binned(c)
+    pos, vel, rho, typ = b.sorted_host()
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ)
+    fl = typ == cases.FLUID
+    out = {}
+    for one in (0, S.SPH_INTERACT_ONE_LANE):
+        d = b.interact(flags=S.SPH_DIAG_COUNT_F64 | one)
+        assert np.array_equal(d[3], nbr_o)
+        out[one] = b.interact(flags=one)
+        ea, er, ev = _rel_errors(out[one][:3], (ace_o, arho_o, visc_o), fl)
+        _say(f"  {dim}d {grid} one_lane={bool(one)}: rel err ace {ea:.2e} arho {er:.2e} "
+             f"visc {ev:.2e}")
+        assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
+    four, single = out[0], out[S.SPH_INTERACT_ONE_LANE]
+    assert np.array_equal(four[3], single[3])  # the same FP32 pair tests
+    for k in range(3):
+        scale = max(np.abs(single[k]).max(), 1e-30)
+        assert np.abs(four[k] - single[k]).max() <= 1e-5 * scale
+
+
 @pytest.mark.parametrize("grid", [(1, 1), (2, 1), (2, 4)])
 def test_interact_long_x_frame_blocks(grid):
     """A block long along x spans many periods (8 cells) of the fixed-point x
