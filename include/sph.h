@@ -110,7 +110,7 @@ enum {
    * SPH_DIAG_COUNT_F64; not with the precision-study arms or modified DBC. */
   SPH_INTERACT_REUSE_CELLS = 8u,
   /* One lane per target particle.  By default a case too small to fill the
-   * GPU (at most 262,144 particles) with the default formulation (Wendland
+   * GPU (at most 131,072 particles) with the default formulation (Wendland
    * kernel, artificial viscosity, ddt 0 or 1, no floating bodies or periodic
    * components) deals each target's neighbour rows to four lanes and sums
    * their results, which shortens each lane's chain of dependent loads;

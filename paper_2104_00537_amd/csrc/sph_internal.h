@@ -113,7 +113,7 @@ struct SlotMotion {
 // Most lanes that share one target particle in the interaction, and the
 // largest case that gets them (n * kMaxLanes / 64 wavefronts at most).
 constexpr int kMaxLanes = 4;
-constexpr int64_t kLanesMaxN = 262144;
+constexpr int64_t kLanesMaxN = 131072;
 
 // Workspace layout (offsets in bytes, each region 256-aligned).
 struct WsLayout {

@@ -256,7 +256,7 @@ def test_four_lanes_per_target_agree_with_one(dim, grid):
     shape = (40, 24) if dim == 2 else (17, 13, 11)
     c = _perturbed(cases.block_case(dim, shape, walls=True, seed=41 + dim, cell_div=grid[0],
                                     x_sub=grid[1]), 42, vel=0.4)
-    assert c.n <= 262144
+    assert c.n <= 131072
     b = Binned(c)
     pos, vel, rho, typ = b.sorted_host()
     ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ)
