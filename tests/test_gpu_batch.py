@@ -227,6 +227,29 @@ def test_batch_margin_error_is_per_slot():
     assert S.sph_read_error(eng.ws) & S.SPH_ERR_MARGIN
 
 
+def test_engine_capacity_counts_the_padding():
+    """Slots are padded to whole wavefronts: a case that fits the particle
+    capacity only unpadded is refused with a clear error (before any copy),
+    and admission (fits) counts the padded size."""
+    c = cases.dam_break_2d(dp=0.02, seed=1)
+    assert c.n % V.WAVE != 0
+    eng = V.BatchEngine(cap_particles=c.n, cap_cells=c.params.ncell_total() + 16, max_slots=2,
+                        device=DEV)
+    req = V.Request(rid=0, case=c, steps=1, arrival=0.0)
+    assert not eng.fits([], req)
+    with pytest.raises(S.SphError, match="capacity"):
+        eng.repack([], [req])
+    eng2 = V.BatchEngine(cap_particles=V.padded(c.n), cap_cells=c.params.ncell_total() + 16,
+                         max_slots=2, device=DEV)
+    assert eng2.fits([], req)
+    eng2.repack([], [req])
+    eng2.run(2)
+    torch.cuda.synchronize()
+    assert not S.sph_batch_read_errors(eng2.batch, eng2.ws).any()
+    r = eng2.slot_result(0)
+    assert r["pos"].shape == c.pos.shape and np.all(r["type"] == c.type)
+
+
 def test_served_stream_small():
     """A short stream through the batched and the plain path: every request
     completes without error and gets the same answer either way."""
