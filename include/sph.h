@@ -107,7 +107,9 @@ enum {
    * predictor phase record in the workspace.  The same pairs within 2h are
    * found as after a new binning (only the summation order differs).  Sets
    * SPH_ERR_MARGIN if a particle moved half a cell or more.  Combines with
-   * SPH_DIAG_COUNT_F64; not with the precision-study arms or modified DBC. */
+   * SPH_DIAG_COUNT_F64; not with the precision-study arms or modified DBC;
+   * a periodic component must then span at least 2 (cell_div + 1) + 1 cells
+   * (else SPH_E_ARG), so that the longer walk meets no cell twice. */
   SPH_INTERACT_REUSE_CELLS = 8u,
   /* One lane per target particle.  By default a case too small to fill the
    * GPU (at most 131,072 particles) with the default formulation (Wendland
@@ -355,10 +357,15 @@ sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t
  *   shift[dim][n] out, nullable: the dr applied (FP32; 0 for non-fluid)
  * Arithmetic is FP32 on the view's offsets, as in sph_interact.  Needs
  * p->shift_coef > 0.  Without conc the concentrations live in the
- * workspace's sort buffers during the call. */
+ * workspace's sort buffers during the call.  flags: 0, or
+ * SPH_INTERACT_REUSE_CELLS when the view is a refreshed one on the cells of
+ * an earlier binning (after sph_refresh_view and an interaction with that
+ * flag): the search then reaches one cell further and widens its cut by the
+ * recorded displacement, as in sph_interact (SPH_ERR_MARGIN past half a
+ * cell; not with modified DBC).  Other bits: SPH_E_ARG. */
 sph_status sph_shifting(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                         const uint32_t* cell_start, const double* dt, float* conc,
-                        float* shift, void* ws, size_t ws_bytes, void* stream);
+                        float* shift, uint32_t flags, void* ws, size_t ws_bytes, void* stream);
 
 /* Floating bodies (Section 3.2).  A body is a rigid object whose particles
  * are the particles of type SPH_FLOATING with id in [id_first, id_first +

@@ -135,6 +135,18 @@ KParams make_slot_kparams(const sph_params& p) {
   return k;
 }
 
+// Every periodic component spans at least 2 reach + 1 cells, so that a walk
+// of that reach meets no cell twice (params_ok checks the cells' own reach;
+// a walk on reused cells reaches one cell further).
+static bool periodic_reach_ok(const sph_params* p, int reach) {
+  for (int k = 0; k < p->dim; ++k) {
+    if (!(p->period[k] > 0.0)) continue;
+    const int cells = k == 0 ? p->ncell[0] / p->x_sub : p->ncell[k];
+    if (cells < 2 * reach + 1) return false;
+  }
+  return true;
+}
+
 static bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
@@ -227,7 +239,8 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
   if (base != 0 && base != SPH_DIAG_COUNT_F64 && base != SPH_INTERACT_F64 &&
       base != SPH_INTERACT_ABS_F32)
     return SPH_E_ARG;
-  if (reuse && (base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 || p->boundary != 0))
+  if (reuse && (base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 || p->boundary != 0 ||
+                !periodic_reach_ok(p, p->cell_div + 1)))
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
   if ((base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32) &&
@@ -310,13 +323,18 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
 
 sph_status sph_shifting(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                         const uint32_t* cell_start, const double* dt, float* conc,
-                        float* shift, void* ws, size_t ws_bytes, void* stream) {
+                        float* shift, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
   if (!params_ok(p) || !n_ok(n) || !cell_start || !dt || !ws) return SPH_E_ARG;
   if (!(p->shift_coef > 0.0)) return SPH_E_ARG;
+  if (flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS) return SPH_E_ARG;
+  if ((flags & SPH_INTERACT_REUSE_CELLS) &&
+      (p->boundary != 0 || !periodic_reach_ok(p, p->cell_div + 1)))
+    return SPH_E_ARG;
   if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   if (n == 0) return SPH_OK;
-  return hip_status(launch_shifting(make_kparams(*p), n, *s, key, cell_start, dt, conc, shift, ws,
+  return hip_status(launch_shifting(make_kparams(*p), n, *s, key, cell_start, dt, conc, shift,
+                                    (flags & SPH_INTERACT_REUSE_CELLS) != 0, ws,
                                     (hipStream_t)stream));
 }
 

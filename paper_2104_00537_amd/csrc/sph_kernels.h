@@ -47,7 +47,7 @@ hipError_t launch_floating(const KParams& kp, int64_t n, int phase, const double
                            const float* ace, void* ws, hipStream_t st);
 hipError_t launch_shifting(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, const double* dt, float* conc,
-                           float* shift, void* ws, hipStream_t st);
+                           float* shift, bool reuse, void* ws, hipStream_t st);
 hipError_t launch_clear_error(void* ws, hipStream_t st);
 
 hipError_t launch_batch_bin_cells(const BatchDesc& B, const sph_state& in, sph_state& out,

@@ -18,9 +18,9 @@ namespace sph {
 template <int DIM, int R, bool PER, typename F>
 __device__ inline void visit_neighbours(const KParams& kp, const float4& pa, int cx, int cy,
                                         int cz, const float4* __restrict__ pr,
-                                        const uint32_t* __restrict__ cstart, F&& f) {
+                                        const uint32_t* __restrict__ cstart, float cull2,
+                                        F&& f) {
   const float cs = kp.cs_f;
-  const float cull2 = kp.support2_f * 1.0002f;
   const uint32_t xa = __float_as_uint(pa.x);
   const int fcells = kFrameCells << kp.lg_xsub;
   const float fx =
@@ -123,14 +123,32 @@ __device__ inline void target_cell(const KParams& kp, uint32_t k, int& cx, int& 
 }
 
 // C_a = sum_b V_b W_ab (Eq. 53), every non-excluded particle, a included.
+// The culling radius squared of a walk: the support (with a margin above the
+// FP32 error of the offsets) when the cells are those of the view's own
+// binning; widened by the largest recorded displacement when they are reused
+// (R above the cells' stencil), with SPH_ERR_MARGIN past half a cell.
+template <int R>
+__device__ inline float shift_cull2(const KParams& kp, const uint32_t* __restrict__ disp,
+                                    uint32_t* __restrict__ err) {
+  if (R <= kp.cell_div) return kp.support2_f * 1.0002f;
+  const float delta = read_displacement(disp);
+  const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
+  if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)
+    set_error(err, SPH_ERR_MARGIN);
+  return rc * rc;
+}
+
 template <int DIM, int R, bool PER>
 __global__ __launch_bounds__(kBlock) void k_shift_conc(KParams kp, int64_t n,
                                                        const float4* __restrict__ pr,
                                                        const uint32_t* __restrict__ key,
                                                        const uint32_t* __restrict__ cstart,
                                                        const uint8_t* __restrict__ type,
-                                                       float* __restrict__ conc) {
+                                                       float* __restrict__ conc,
+                                                       const uint32_t* __restrict__ disp,
+                                                       uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const float cull2 = shift_cull2<R>(kp, disp, err);
   if (i >= n) return;
   if (is_excluded(type[i])) {
     conc[i] = 0.f;
@@ -141,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_conc(KParams kp, int64_t n,
   int cx, cy, cz;
   target_cell(kp, key[i], cx, cy, cz);
   float c = 0.f;
-  visit_neighbours<DIM, R, PER>(kp, pa, cx, cy, cz, pr, cstart,
+  visit_neighbours<DIM, R, PER>(kp, pa, cx, cy, cz, pr, cstart, cull2,
                                 [&](uint32_t, float, float, float, float r2, const float4& pb) {
                                   const float vb = (pb.w > 0.f ? mf : mw) *
                                                    __builtin_amdgcn_rcpf(fabsf(pb.w));
@@ -158,8 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_apply(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
     const uint8_t* __restrict__ type, const float* __restrict__ conc,
-    const double* __restrict__ dtp, double* __restrict__ pos, float* __restrict__ shift) {
+    const double* __restrict__ dtp, double* __restrict__ pos, float* __restrict__ shift,
+    const uint32_t* __restrict__ disp, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const float cull2 = shift_cull2<R>(kp, disp, err);
   if (i >= n) return;
   const uint8_t t = type[i];
   if (!is_fluid(t) || is_excluded(t)) {
@@ -174,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_apply(
   target_cell(kp, key[i], cx, cy, cz);
   float g0 = 0.f, g1 = 0.f, g2 = 0.f;
   visit_neighbours<DIM, R, PER>(
-      kp, pa, cx, cy, cz, pr, cstart,
+      kp, pa, cx, cy, cz, pr, cstart, cull2,
       [&](uint32_t j, float dx, float dy, float dz, float r2, const float4& pb) {
         const float vb = (pb.w > 0.f ? mf : mw) * __builtin_amdgcn_rcpf(fabsf(pb.w));
         const float w = vb * (conc[j] - ca) * kernel_f_f(kp, kfab, r2);
@@ -202,27 +222,36 @@ __global__ __launch_bounds__(kBlock) void k_shift_apply(
 
 hipError_t launch_shifting(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, const double* dt, float* conc,
-                           float* shift, void* ws, hipStream_t st) {
+                           float* shift, bool reuse, void* ws, hipStream_t st) {
   const WsLayout L = ws_layout(n);
   const float4* pr = ws_ptr<float4>(ws, L.view_pr);
   const float4* vp = ws_ptr<float4>(ws, L.view_vp);
   float* c = conc ? conc : ws_ptr<float>(ws, L.keyA);
+  const uint32_t* disp = ws_ptr<uint32_t>(ws, L.disp);
+  uint32_t* err = ws_ptr<uint32_t>(ws, L.err);
   const unsigned grid = (unsigned)L.nblk_interact;
   const bool per = kp.periodic != 0;
+  // reused cells: one more cell of reach, cut widened by the displacement
+  const int reach = kp.cell_div + (reuse ? 1 : 0);
 #define SPH_SHIFT(D, RR, PE)                                                                  \
   do {                                                                                        \
     hipLaunchKernelGGL((k_shift_conc<D, RR, PE>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
-                       key, cell_start, s.type, c);                                          \
+                       key, cell_start, s.type, c, disp, err);                                \
     hipLaunchKernelGGL((k_shift_apply<D, RR, PE>), dim3(grid), dim3(kBlock), 0, st, kp, n,    \
-                       pr, vp, key, cell_start, s.type, c, dt, s.pos, shift);                 \
+                       pr, vp, key, cell_start, s.type, c, dt, s.pos, shift, disp, err);      \
   } while (0)
 #define SPH_SHIFT_P(D, RR) \
   if (per) SPH_SHIFT(D, RR, true); else SPH_SHIFT(D, RR, false)
+#define SPH_SHIFT_R(D)                      \
+  if (reach == 1) SPH_SHIFT_P(D, 1);        \
+  else if (reach == 2) SPH_SHIFT_P(D, 2);   \
+  else SPH_SHIFT_P(D, 3)
   if (kp.dim == 2) {
-    if (kp.cell_div == 1) SPH_SHIFT_P(2, 1); else SPH_SHIFT_P(2, 2);
+    SPH_SHIFT_R(2);
   } else {
-    if (kp.cell_div == 1) SPH_SHIFT_P(3, 1); else SPH_SHIFT_P(3, 2);
+    SPH_SHIFT_R(3);
   }
+#undef SPH_SHIFT_R
 #undef SPH_SHIFT_P
 #undef SPH_SHIFT
   return hipGetLastError();

@@ -72,14 +72,20 @@ class Simulation:
         self.shifting = float(getattr(cp, "shift_coef", 0.0)) > 0.0
         if self.shifting and integrator != "symplectic":
             raise ValueError("particle shifting takes the symplectic integrator")
-        # the second interaction of a step on the cells of the first (not
-        # with modified DBC, shifting or a precision-study arm, whose passes
+        # the second interaction of a step (and shifting) on the cells of the
+        # first (not with modified DBC or a precision-study arm, whose passes
         # search the cells without a displacement margin)
-        can_reuse = (integrator == "symplectic" and not self.mdbc and not self.shifting
-                     and (self.flags & ~S.SPH_INTERACT_ONE_LANE) in (0, S.SPH_DIAG_COUNT_F64))
+        # (a periodic component needs 2 (cell_div + 1) + 1 cells for the
+        # longer walk on reused cells)
+        per_cells = [cp.ncell[k] // (cp.x_sub if k == 0 else 1) for k in range(cp.dim)
+                     if cp.period[k] > 0]
+        can_reuse = (integrator == "symplectic" and not self.mdbc
+                     and (self.flags & ~S.SPH_INTERACT_ONE_LANE) in (0, S.SPH_DIAG_COUNT_F64)
+                     and all(c >= 2 * (cp.cell_div + 1) + 1 for c in per_cells))
         if reuse_cells and not can_reuse:
             raise ValueError("reuse_cells needs the symplectic integrator, DBC walls, no "
-                             "shifting and no precision-study arm")
+                             "precision-study arm and periodic components of at least "
+                             "2 (cell_div + 1) + 1 cells")
         self.reuse_cells = can_reuse if reuse_cells is None else bool(reuse_cells)
         self.bodies = None
         if getattr(case, "bodies", None):
@@ -195,6 +201,9 @@ class Simulation:
         if self.bodies is not None:
             call("floating", S.sph_floating_step, P, n, 1, self.dt, self.bodies, s0, b, self.ace,
                  self.ws, stream=stream)
+        if self.shifting:
+            call("shifting", S.sph_shifting, P, n, b, self.key, self.cell_start, self.dt, self.ws,
+                 flags=S.SPH_INTERACT_REUSE_CELLS, stream=stream)
         self.states = [b, a]
         self.steps_done += 1
 

@@ -113,8 +113,8 @@ def _load() -> C.CDLL:
     L.sph_floating_step.argtypes = [P(SphParams), C.c_int64, C.c_int32, VP, VP, C.c_int32,
                                     P(SphState), P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_shifting.restype = C.c_int32
-    L.sph_shifting.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP, VP,
-                               C.c_size_t, VP]
+    L.sph_shifting.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP,
+                               C.c_uint32, VP, C.c_size_t, VP]
     L.sph_read_error.restype = C.c_int32
     L.sph_read_error.argtypes = [VP]
     L.sph_clear_error.restype = C.c_int32
@@ -341,9 +341,9 @@ def sph_floating_step(params: SphParams, n: int, phase: int, dt: torch.Tensor,
 def sph_shifting(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
                  cell_start: torch.Tensor, dt: torch.Tensor, ws: torch.Tensor,
                  conc: Optional[torch.Tensor] = None, shift: Optional[torch.Tensor] = None,
-                 stream=None):
+                 flags: int = 0, stream=None):
     _check(lib.sph_shifting(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
-                            _ptr(dt), _ptr(conc), _ptr(shift), _ptr(ws), ws.numel(),
+                            _ptr(dt), _ptr(conc), _ptr(shift), int(flags), _ptr(ws), ws.numel(),
                             _stream(stream)), "sph_shifting")
 
 

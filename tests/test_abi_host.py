@@ -294,6 +294,17 @@ def test_periodic_params_validate_without_device(S):
     small = cases.periodic_box(2, shape=(8, 10), periodic=(0,), cell_div=2)
     assert small.params.ncell[0] < 5
     assert interact(S.make_params(small.params)) == S.SPH_E_ARG
+    # 6 cells: enough for the cells' own reach of 2, not for the reach of 3 of
+    # a walk on reused cells (which would meet a cell twice)
+    six = cases.periodic_box(2, shape=(12, 10), periodic=(0,), cell_div=2)
+    assert six.params.ncell[0] // six.params.x_sub == 6
+    P6 = S.make_params(six.params)
+    need6 = S.sph_workspace_bytes(P6, 1000)
+    assert lib.sph_interact(C.byref(P6), 1000, C.byref(st), d, d, d, d, None, None,
+                            S.SPH_INTERACT_REUSE_CELLS, d, need6, None) == S.SPH_E_ARG
+    P6s = S.make_params(dataclasses.replace(six.params, shift_coef=2.0))
+    assert lib.sph_shifting(C.byref(P6s), 1000, C.byref(st), d, d, d, None, None,
+                            S.SPH_INTERACT_REUSE_CELLS, d, need6, None) == S.SPH_E_ARG
     for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32):
         assert interact(P, flags) == S.SPH_E_ARG
     with pytest.raises(S.SphError):
@@ -314,11 +325,15 @@ def test_shifting_validates_without_device(S):
     need = S.sph_workspace_bytes(S.make_params(cp), 1000)
 
     def shifting(p, ws=need):
-        return lib.sph_shifting(C.byref(p), 1000, C.byref(st), d, d, d, None, None, d, ws, None)
+        return lib.sph_shifting(C.byref(p), 1000, C.byref(st), d, d, d, None, None, 0, d, ws, None)
 
     assert shifting(S.make_params(cp)) == S.SPH_E_ARG                 # shift_coef = 0
     ok = dataclasses.replace(cp, shift_coef=2.0)
     assert shifting(S.make_params(ok), ws=need - 1) == S.SPH_E_WORKSPACE
+    # flags other than reusing the cells (rejected before any device work)
+    for fl in (S.SPH_DIAG_COUNT_F64, S.SPH_INTERACT_ONE_LANE, 1 << 7):
+        assert lib.sph_shifting(C.byref(S.make_params(ok)), 1000, C.byref(st), d, d, d, None,
+                                None, fl, d, need, None) == S.SPH_E_ARG
     for kw in (dict(shift_coef=-1.0), dict(shift_coef=2.0, shift_fs=-0.5),
                dict(shift_coef=float("inf"))):
         P = S.make_params(dataclasses.replace(cp, **kw))
