@@ -10,6 +10,8 @@ summation order differs); particles moved by up to 0.3 cell; a move of half
 a cell or more raises SPH_ERR_MARGIN; whole runs with and without reused
 cells agree to 1e-6 of the tank length.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -152,10 +154,15 @@ def test_moves_beyond_the_margin_raise_the_error():
     assert err & S.SPH_ERR_MARGIN
 
 
-@pytest.mark.parametrize("name", ["dam2d", "floating2d", "periodic3d"])
+@pytest.mark.parametrize("name", ["dam2d", "floating2d", "periodic3d", "shifting2d"])
 def test_runs_with_and_without_reused_cells_agree(name):
     if name == "dam2d":
         c = cases.dam_break_2d(cell_div=2, x_sub=4)
+    elif name == "shifting2d":
+        # shifting after the corrector on the reused cells, surface correction on
+        d = cases.dam_break_2d(cell_div=2, x_sub=4)
+        c = cases.Case(dataclasses.replace(d.params, shift_coef=2.0, shift_fs=0.9), d.pos, d.vel,
+                       d.rho, d.type, dict(d.meta), d.normal)
     elif name == "floating2d":
         c = cases.floating_box(2, dp=0.02, cell_div=2, x_sub=4)
     else:
