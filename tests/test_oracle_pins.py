@@ -7,6 +7,7 @@ library routine that computes the same definition.  A plausible mistake
 (a wrong normalisation, a dropped term, a flipped sign, a swapped index)
 fails at least one of them.
 """
+import dataclasses
 import math
 from fractions import Fraction
 
@@ -309,6 +310,110 @@ def test_density_diffusion_conserves_and_diffuses():
     cp0.ddt = 0
     _, arho0, _, _ = oracle.interact(cp0, pos, vel, rho, typ)
     assert np.abs(arho0).max() == 0.0
+
+
+def _centred_lattice(dim, h_over_dp, dp):
+    """An exact lattice of spacing dp wide enough to hold the whole support
+    (2h) of its centre particle; returns (pos, index of the centre)."""
+    side = 2 * int(math.ceil(2 * h_over_dp)) + 3
+    shape = (side,) * dim
+    return _lattice(dim, shape, dp), int(np.ravel_multi_index((side // 2,) * dim, shape))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_density_diffusion_magnitude_is_the_laplacian(dim):
+    """Magnitude of the density diffusion term (Eq. 17-18, diffusive
+    reading).  At rest (no continuity part) with rho = rho0 + c (z - z_a)^2
+    about the target a, rho_b - rho_a = c s_z^2 for s = r_b - r_a, and the
+    lattice sum tends to the integral c int s_z^2 |F(|s|)| ds.  Integrating
+    grad W = F(|s|) s by parts against s gives int s_i s_j F ds = -delta_ij
+    int W = -delta_ij (Eq. 3), so that integral is c, and
+    D_a = 2 delta h c0 c = delta h c0 lap(rho): the continuum limit of the
+    Molteni-Colagrossi term.  h = 3 dp puts the lattice sum within 0.2 % of
+    its limit; a dropped factor 2 in psi_ab.grad W halves D_a."""
+    cp = cases.block_case(dim, (3,) * dim).params
+    dp = cp.dp
+    h = 3.0 * dp
+    cp = dataclasses.replace(cp, h=h, eta2=1e-3 * h * h)
+    pos, a = _centred_lattice(dim, 3.0, dp)
+    n = pos.shape[1]
+    c = 0.02 * cp.rho0 / (4.0 * h) ** 2  # 2 % density change across the support
+    rho = cp.rho0 + c * (pos[-1] - pos[-1, a]) ** 2
+    _, arho, _, _ = oracle.interact(cp, pos, np.zeros_like(pos), rho, np.zeros(n, np.uint8),
+                                    targets=[a])
+    lap = 2.0 * c
+    assert arho[0] == pytest.approx(cp.delta * h * cp.c0 * lap, rel=5e-3)
+    # the identity used above, checked by quadrature: int |s|^2 |F| ds = d
+    shell = (lambda r: 2 * math.pi * r) if dim == 2 else (lambda r: 4 * math.pi * r * r)
+    val, _ = integrate.quad(lambda r: -oracle.wendland_fab(r, h, dim) * r * r * shell(r),
+                            0, 2 * h, epsabs=0, epsrel=1e-13, limit=200)
+    assert val == pytest.approx(dim, rel=1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_viscosity_maximum_of_a_uniform_expansion(dim):
+    """Magnitude of mu_ab (Eq. 21) and the viscous branch of Eq. 35.  For
+    v = k (r - r_c) every pair has v_ab.r_ab = k r_ab^2, so
+    mu_ab = h k r^2/(r^2 + eta^2) exactly, increasing in r: visc_a is reached
+    at the farthest lattice neighbour, r^2 = 5 dp^2 in 2-D and 11 dp^2 in
+    3-D (h = sqrt(d) dp, shrunk by 1e-9 so that the lattice ties at exactly
+    2h drop out; every particle of the lattice has such a neighbour), and
+    dt = C_CFL h/(c0 + visc).  Dropping h from mu_ab scales visc by 1/h."""
+    cp = cases.block_case(dim, (3,) * dim).params
+    dp = cp.dp
+    h = math.sqrt(dim) * dp * (1 - 1e-9)
+    cp = dataclasses.replace(cp, h=h, eta2=1e-3 * h * h)
+    pos = _lattice(dim, (9,) * dim, dp)
+    n = pos.shape[1]
+    k = 0.5 * cp.c0 / h  # visc about c0 / 2
+    vel = k * (pos - pos.mean(1, keepdims=True))
+    typ = np.zeros(n, np.uint8)
+    ace, _, visc, _ = oracle.interact(cp, pos, vel, np.full(n, cp.rho0), typ)
+    r2 = (5.0 if dim == 2 else 11.0) * dp * dp
+    closed = h * k * r2 / (r2 + cp.eta2)
+    assert np.abs(visc - closed).max() <= 1e-12 * closed
+    # a diverging flow at P = 0 feels gravity only, and the viscous branch sets dt
+    g = np.array(cp.gravity[:dim])[:, None]
+    assert np.abs(ace - g).max() < 1e-9
+    dt = oracle.time_step(cp, typ, ace, visc)
+    assert dt == pytest.approx(cp.cfl * h / (cp.c0 + closed), rel=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_artificial_viscosity_magnitude_in_a_quadratic_shear(dim):
+    """Magnitude of Pi_ab (Eq. 21-22) against its continuum integral.  At
+    rho = rho0 (P = 0) and v_x = c (z - z_a)^2, with s = r_b - r_a,
+    v_ab.r_ab = c s_x s_z^2: only pairs with s_x < 0 approach (c > 0), and
+    there Pi_ab = -alpha c0 h c s_x s_z^2/((s^2 + eta^2) rho0).  The momentum
+    sum -sum_b m_b Pi_ab F_ab r_ab with m_b = rho0 V_b tends to
+    -alpha c0 h c int_{s_x<0} s_x^2 s_z^2 F/(s^2 + eta^2) ds along x (zero
+    across), half the integral over all s, whose angular mean of
+    s_x^2 s_z^2 is s^4/15 in 3-D and s^4/8 in 2-D: a radial quadrature.
+    h = 4 dp puts the lattice within 0.3 % of it.  A mean density
+    rho_a + rho_b in place of (rho_a + rho_b)/2 halves the result."""
+    cp = cases.block_case(dim, (3,) * dim).params
+    dp = cp.dp
+    h = 4.0 * dp
+    cp = dataclasses.replace(cp, h=h, eta2=1e-3 * h * h)
+    pos, a = _centred_lattice(dim, 4.0, dp)
+    n = pos.shape[1]
+    c = 3.0
+    vel = np.zeros_like(pos)
+    vel[0] = c * (pos[-1] - pos[-1, a]) ** 2
+    ace, _, _, _ = oracle.interact(cp, pos, vel, np.full(n, cp.rho0), np.zeros(n, np.uint8),
+                                   targets=[a])
+    if dim == 3:
+        radial = (lambda s: 4 * math.pi * s * s / 15.0)
+    else:
+        radial = (lambda s: 2 * math.pi * s / 8.0)
+    integral, _ = integrate.quad(
+        lambda s: radial(s) * s ** 4 * oracle.wendland_fab(s, h, dim) / (s * s + cp.eta2),
+        0, 2 * h, epsabs=0, epsrel=1e-12, limit=200)
+    expect = -0.5 * cp.alpha * cp.c0 * h * c * integral
+    assert expect > 0
+    acc = ace[:, 0] - np.array(cp.gravity[:dim])
+    assert acc[0] == pytest.approx(expect, rel=1e-2)
+    assert np.abs(acc[1:]).max() < 1e-12 * expect
 
 
 def test_artificial_viscosity_dissipates():
