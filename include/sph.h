@@ -77,9 +77,12 @@ enum {
                                in no body's range, a body whose particles are
                                not all present, body counts summing above n,
                                or a singular inertia */
-  SPH_ERR_MARGIN = 16u      /* an interaction with SPH_INTERACT_REUSE_CELLS after
-                               particles moved half a cell or more since the
-                               binning: neighbours may have been missed */
+  SPH_ERR_MARGIN = 16u      /* an interaction or shifting with
+                               SPH_INTERACT_REUSE_CELLS after particles moved
+                               half a cell or more since the binning, or one
+                               without that flag after particles moved at all
+                               since the binning (a predictor ran): neighbours
+                               may have been missed */
 };
 
 /* flags of sph_interact */

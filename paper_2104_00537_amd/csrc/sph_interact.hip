@@ -2,10 +2,11 @@
 // continuity and momentum sums over neighbours within 2h, on gfx950.
 //
 // One lane per target particle in sorted order walks the rows of its
-// neighbour cells (gather_walk).  Consecutive blocks cover consecutive targets
-// and are placed so that each XCD runs one contiguous share of them: the
-// neighbour views a block reads were then mostly brought into that XCD's L2
-// by its predecessors.  Sums are gathered per target (no atomics): results are
+// neighbour cells (gather_walk).  Blocks cover consecutive targets and are
+// dealt to the XCDs in chunks of 16 consecutive blocks (xcd_block): the blocks
+// of a chunk share neighbour views through their XCD's L2, and every XCD gets
+// chunks from every part of the domain, which balances the work across the
+// XCDs.  Sums are gathered per target (no atomics): results are
 // deterministic.
 #include "sph_kernels.h"
 #include "sph_dev.h"
@@ -66,6 +67,10 @@ __global__ __launch_bounds__(kBlock) void k_interact_gather(
     cull2 = rc * rc;
     if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)
       set_error(&hdr->err, SPH_ERR_MARGIN);
+  } else if (blockIdx.x == 0 && threadIdx.x == 0 && read_displacement(disp) > 0.f) {
+    // particles moved since the binning (a predictor ran) but the walk keeps
+    // the cells' own reach: pairs may be missed
+    set_error(&hdr->err, SPH_ERR_MARGIN);
   }
   if constexpr (LPT == 1) {
     if (i < n) {

@@ -126,11 +126,18 @@ __device__ inline void target_cell(const KParams& kp, uint32_t k, int& cx, int& 
 // The culling radius squared of a walk: the support (with a margin above the
 // FP32 error of the offsets) when the cells are those of the view's own
 // binning; widened by the largest recorded displacement when they are reused
-// (R above the cells' stencil), with SPH_ERR_MARGIN past half a cell.
+// (R above the cells' stencil), with SPH_ERR_MARGIN past half a cell, or
+// when particles moved since the binning but the cells' own reach is used.
 template <int R>
 __device__ inline float shift_cull2(const KParams& kp, const uint32_t* __restrict__ disp,
                                     uint32_t* __restrict__ err) {
-  if (R <= kp.cell_div) return kp.support2_f * 1.0002f;
+  if (R <= kp.cell_div) {
+    // the cells' own reach after particles moved since the binning: pairs
+    // may be missed
+    if (blockIdx.x == 0 && threadIdx.x == 0 && read_displacement(disp) > 0.f)
+      set_error(err, SPH_ERR_MARGIN);
+    return kp.support2_f * 1.0002f;
+  }
   const float delta = read_displacement(disp);
   const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
   if (!(2.f * delta < kp.cs_f) && blockIdx.x == 0 && threadIdx.x == 0)

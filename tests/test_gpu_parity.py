@@ -463,12 +463,34 @@ def test_failure_words():
 
 
 # ------------------------------------------------------- full-size sampling
+def _developed_flow(c, seed):
+    """Velocities of a developed flow on a case (a smooth field of up to
+    about 2 m/s plus 0.05 m/s of noise, fluid and walls alike) and densities
+    perturbed by 0.3 %, so that every velocity- and density-difference term
+    of the interaction is non-zero."""
+    rng = np.random.default_rng(seed)
+    x, y, z = c.pos
+    v = np.stack([1.5 * np.sin(2 * np.pi * z / 0.3) + 0.5,
+                  0.4 * np.cos(2 * np.pi * x / 0.6),
+                  -0.8 * np.sin(2 * np.pi * y / 0.6) * np.cos(np.pi * x / 1.6)])
+    v += rng.uniform(-0.05, 0.05, v.shape)
+    c.vel[:] = v.astype(np.float32)
+    c.rho[:] = (c.rho * (1 + rng.uniform(-0.003, 0.003, c.n))).astype(np.float32)
+    return c
+
+
+def _sampled_targets(typ, rng, nf=500, nb=100):
+    return np.concatenate([rng.choice(np.flatnonzero(typ == 0), nf, replace=False),
+                           rng.choice(np.flatnonzero(typ != 0), nb, replace=False)])
+
+
 def test_dam_break_3d_1m_sampled():
     """The 1M-fluid 3-D dam break at full size, in the launch configuration
-    the benchmark times: keys/perm/ranges bit-exact against the oracle,
-    interaction outputs on 600 sampled targets."""
+    the benchmark times, with the velocities of a developed flow:
+    keys/perm/ranges bit-exact against the oracle, interaction outputs on
+    600 sampled targets."""
     _say("3d 1M sampled")
-    c = cases.dam_break_3d(cell_div=2, x_sub=4)
+    c = _developed_flow(cases.dam_break_3d(cell_div=2, x_sub=4), 3)
     b = Binned(c)
     n = c.n
     key_ref = oracle.cell_keys(c.params, c.pos)
@@ -480,20 +502,88 @@ def test_dam_break_3d_1m_sampled():
     ace_g, arho_g, visc_g, nbr_g = b.interact(flags=S.SPH_DIAG_COUNT_F64)
     ace_t, arho_t, visc_t, nbr_t = b.interact(flags=0)
     rng = np.random.default_rng(0)
-    tg = np.concatenate([rng.choice(np.flatnonzero(typ == 0), 500, replace=False),
-                         rng.choice(np.flatnonzero(typ != 0), 100, replace=False)])
+    tg = _sampled_targets(typ, rng)
     ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ, targets=tg)
     assert np.array_equal(nbr_g[tg], nbr_o)
     fl = typ[tg] == 0
-    ea = np.abs(ace_g[:, tg] - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
-    er = np.abs(arho_g[tg] - arho_o).max() / np.abs(arho_o).max()
-    _say(f"  rel err ace {ea:.2e} arho {er:.2e}; interior nbr {np.median(nbr_o[fl])}")
-    assert ea < 1e-4 and er < 1e-4
-    ea = np.abs(ace_t[:, tg] - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
-    er = np.abs(arho_t[tg] - arho_o).max() / np.abs(arho_o).max()
-    _say(f"  production kernel rel err ace {ea:.2e} arho {er:.2e}")
-    assert ea < 1e-4 and er < 1e-4
+    for name, (ace, arho, visc) in (("diag", (ace_g, arho_g, visc_g)),
+                                    ("production", (ace_t, arho_t, visc_t))):
+        ea, er, ev = _rel_errors((ace[:, tg], arho[tg], visc[tg]), (ace_o, arho_o, visc_o), fl)
+        _say(f"  {name}: rel err ace {ea:.2e} arho {er:.2e} visc {ev:.2e}; interior nbr "
+             f"{np.median(nbr_o[fl])}")
+        assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
     assert np.abs(nbr_t.astype(np.int64) - nbr_g.astype(np.int64)).sum() <= FLIP_FRACTION * nbr_g.sum()
+
+
+def test_dam_break_3d_1m_production_step_sampled():
+    """The symplectic step of the 1M dam break as the benchmark runs it, in
+    its launch configuration (cells of h split in 4 along x, one lane per
+    target above 131,072 particles): bin, interaction at n, dt (Eq. 35),
+    predictor, the view refreshed on the cells of n and the interaction at
+    n+1/2 with SPH_INTERACT_REUSE_CELLS (reach cell_div + 1 = 3 cells).
+    Both passes against the oracle on 600 sampled targets of their own
+    state (FP64 counts bit-exact, rates within 1e-4), with the velocities of
+    a developed flow; then the same with a forced move of 0.3 cell."""
+    _say("3d 1M production step sampled")
+    c = _developed_flow(cases.dam_break_3d(cell_div=2, x_sub=4), 4)
+    cp, n = c.params, c.n
+    assert n > 131_072  # one lane per target
+    b = Binned(c)
+    rng = np.random.default_rng(1)
+    pos, vel, rho, typ = b.sorted_host()
+    tg = _sampled_targets(typ, rng)
+    fl = typ[tg] == 0
+    ace = torch.empty((3, n), dtype=torch.float32, device=DEV)
+    arho = torch.empty(n, dtype=torch.float32, device=DEV)
+    visc = torch.empty(n, dtype=torch.float32, device=DEV)
+    S.sph_interact(b.P, n, b.dst, b.key, b.start, ace, arho, b.ws, visc=visc)
+    ace_o, arho_o, visc_o, _ = oracle.interact(cp, pos, vel, rho, typ, targets=tg)
+    torch.cuda.synchronize()
+    g = (ace.cpu().numpy()[:, tg].astype(np.float64), arho.cpu().numpy()[tg].astype(np.float64),
+         visc.cpu().numpy()[tg].astype(np.float64))
+    ea, er, ev = _rel_errors(g, (ace_o, arho_o, visc_o), fl)
+    _say(f"  pass at n: rel err ace {ea:.2e} arho {er:.2e} visc {ev:.2e}")
+    assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    S.sph_reduce_dt(b.P, n, dt, b.ws)
+    t = torch.zeros(1, dtype=torch.float64, device=DEV)
+    saved = S.DeviceState.empty(3, n, DEV, with_type=False, with_id=False)
+    S.sph_symplectic_step(b.P, n, 0, dt, t, saved, b.dst, ace, arho, b.ws)
+    S.sph_refresh_view(b.P, n, b.dst, b.key, b.ws)
+    torch.cuda.synchronize()
+    out = {f: b.interact(flags=f | S.SPH_INTERACT_REUSE_CELLS) for f in (S.SPH_DIAG_COUNT_F64, 0)}
+    assert S.sph_read_error(b.ws) == 0
+    pos, vel, rho, typ = b.sorted_host()
+    moved = np.sqrt(((pos - saved.pos.cpu().numpy()) ** 2).sum(axis=0)).max()
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(cp, pos, vel, rho, typ, targets=tg)
+    assert np.array_equal(out[S.SPH_DIAG_COUNT_F64][3][tg], nbr_o)
+    for f, (a_g, r_g, v_g, _) in out.items():
+        ea, er, ev = _rel_errors((a_g[:, tg], r_g[tg], v_g[tg]), (ace_o, arho_o, visc_o), fl)
+        _say(f"  pass at n+1/2 (dt {dt.item():.3e}, moved {moved / cp.cell_size:.4f} cell), "
+             f"flags {f}: rel err ace {ea:.2e} arho {er:.2e} visc {ev:.2e}")
+        assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
+    flips = np.abs(out[0][3].astype(np.int64) - out[S.SPH_DIAG_COUNT_F64][3].astype(np.int64))
+    assert flips.sum() <= FLIP_FRACTION * out[S.SPH_DIAG_COUNT_F64][3].sum()
+    # a longer move: 0.3 of a cell for the fastest particle, rates zeroed
+    b2 = Binned(c)
+    vmax = float(np.sqrt((c.vel.astype(np.float64) ** 2).sum(axis=0)).max())
+    dt2 = torch.full((1,), 2.0 * 0.3 * cp.cell_size / vmax, dtype=torch.float64, device=DEV)
+    zero_a = torch.zeros((3, n), dtype=torch.float32, device=DEV)
+    zero_r = torch.zeros(n, dtype=torch.float32, device=DEV)
+    S.sph_symplectic_step(b2.P, n, 0, dt2, t.zero_(), saved, b2.dst, zero_a, zero_r, b2.ws)
+    S.sph_refresh_view(b2.P, n, b2.dst, b2.key, b2.ws)
+    a_g, r_g, v_g, nb_g = b2.interact(flags=S.SPH_DIAG_COUNT_F64 | S.SPH_INTERACT_REUSE_CELLS)
+    a_t, r_t, v_t, _ = b2.interact(flags=S.SPH_INTERACT_REUSE_CELLS)
+    assert S.sph_read_error(b2.ws) == 0
+    pos, vel, rho, typ = b2.sorted_host()
+    moved = np.sqrt(((pos - saved.pos.cpu().numpy()) ** 2).sum(axis=0)).max()
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(cp, pos, vel, rho, typ, targets=tg)
+    assert np.array_equal(nb_g[tg], nbr_o)
+    for name, (a_x, r_x, v_x) in (("diag", (a_g, r_g, v_g)), ("production", (a_t, r_t, v_t))):
+        ea, er, ev = _rel_errors((a_x[:, tg], r_x[tg], v_x[tg]), (ace_o, arho_o, visc_o), fl)
+        _say(f"  forced move {moved / cp.cell_size:.3f} cell, {name}: rel err ace {ea:.2e} "
+             f"arho {er:.2e} visc {ev:.2e}")
+        assert ea < 1e-4 and er < 1e-4 and ev < 1e-4
 
 
 def test_sloshing_3d_64m_sampled():

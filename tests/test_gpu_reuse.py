@@ -105,7 +105,12 @@ def test_reused_cells_find_the_oracles_pairs(name, move):
     hs = HalfStep(c, move)
     S.sph_refresh_view(hs.P, hs.n, hs.st, hs.key, hs.ws)
     torch.cuda.synchronize()
-    res = {f: hs.interact(f | S.SPH_INTERACT_REUSE_CELLS) for f in (S.SPH_DIAG_COUNT_F64, 0)}
+    # the default lane count (four lanes per target for the small cases here)
+    # and one lane per target, the kernel that runs the n+1/2 pass of large
+    # cases
+    one = S.SPH_INTERACT_ONE_LANE
+    res = {f: hs.interact(f | S.SPH_INTERACT_REUSE_CELLS)
+           for f in (S.SPH_DIAG_COUNT_F64, 0, S.SPH_DIAG_COUNT_F64 | one, one)}
     err = S.sph_read_error(hs.ws)
     assert err == 0, err
     pos = hs.st.pos.cpu().numpy()
@@ -115,6 +120,7 @@ def test_reused_cells_find_the_oracles_pairs(name, move):
     moved = np.sqrt(((pos - hs.saved.pos.cpu().numpy()) ** 2).sum(axis=0)).max()
     ace_o, arho_o, visc_o, nbr_o = oracle.interact(hs.cp, pos, vel, rho, typ)
     assert np.array_equal(res[S.SPH_DIAG_COUNT_F64][3], nbr_o)
+    assert np.array_equal(res[S.SPH_DIAG_COUNT_F64 | one][3], nbr_o)
     fl = typ == cases.FLUID
     for f, (ace, arho, visc, _) in res.items():
         ea, er, ev = _rel_errors((ace, arho, visc), (ace_o, arho_o, visc_o), fl)
@@ -143,6 +149,30 @@ def test_reused_cells_find_the_oracles_pairs(name, move):
     ace_r, arho_r = res[0][0], res[0][1]
     assert np.abs(ace_r - ace_b)[:, fl].max() <= 1e-5 * np.abs(ace_o[:, fl]).max()
     assert np.abs(arho_r - arho_b).max() <= 1e-5 * np.abs(arho_o).max()
+
+
+def test_cells_of_a_moved_state_without_reuse_raise_the_error():
+    """After a predictor moved the particles, an interaction that keeps the
+    cells' own reach (no SPH_INTERACT_REUSE_CELLS) may miss pairs: it sets
+    SPH_ERR_MARGIN; a new binning clears the record."""
+    hs = HalfStep(_case("3d_block"), 0.05)
+    S.sph_refresh_view(hs.P, hs.n, hs.st, hs.key, hs.ws)
+    hs.interact(S.SPH_INTERACT_REUSE_CELLS)
+    assert S.sph_read_error(hs.ws) == 0
+    for flags in (0, S.SPH_INTERACT_ONE_LANE):
+        S.sph_clear_error(hs.ws)
+        hs.interact(flags)
+        err = S.sph_read_error(hs.ws)
+        _say(f"  error word, interaction without reuse after a move (flags {flags}): {err}")
+        assert err == S.SPH_ERR_MARGIN
+    S.sph_clear_error(hs.ws)
+    dst = S.DeviceState.empty(hs.cp.dim, hs.n, DEV)
+    S.sph_bin_cells(hs.P, hs.n, hs.st, dst, hs.key, hs.perm, hs.start, hs.ws)
+    ace = torch.empty_like(hs.ace)
+    arho = torch.empty_like(hs.arho)
+    S.sph_interact(hs.P, hs.n, dst, hs.key, hs.start, ace, arho, hs.ws)
+    torch.cuda.synchronize()
+    assert S.sph_read_error(hs.ws) == 0
 
 
 def test_moves_beyond_the_margin_raise_the_error():

@@ -115,3 +115,61 @@ def test_dam_break_with_shifting_matches_oracle():
     assert st["t"] == pytest.approx(out["t"], rel=1e-4)
     plain = oracle.run(c.params, c.pos, c.vel, c.rho, c.type, 150)
     assert np.abs(plain["pos"] - out["pos"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("name", ["3d_block", "3d_periodic"])
+@pytest.mark.parametrize("move", [0.05, 0.3])
+def test_shifting_on_reused_cells_matches_oracle(name, move):
+    """Shifting after the corrector in a step that bins once: the view of
+    the moved state is refreshed on the cells of state n and both passes
+    search them with SPH_INTERACT_REUSE_CELLS (one more cell of reach, the
+    cut widened by the recorded displacement).  C and the shifts against the
+    oracle's shifting of the moved positions, particles moved by 0.05 and 0.3
+    of a cell; half a cell raises SPH_ERR_MARGIN."""
+    from test_gpu_reuse import HalfStep, _case
+    c = _with(_case(name), shift_coef=2.0, shift_fs=0.9)
+    hs = HalfStep(c, move)
+    cp, n = hs.cp, hs.n
+    S.sph_refresh_view(hs.P, n, hs.st, hs.key, hs.ws)
+    torch.cuda.synchronize()
+    pos = hs.st.pos.cpu().numpy()
+    vel = hs.st.vel.cpu().numpy().astype(np.float64)
+    rho = hs.st.rho.cpu().numpy().astype(np.float64)
+    typ = hs.st.type.cpu().numpy()
+    moved = np.sqrt(((pos - hs.saved.pos.cpu().numpy()) ** 2).sum(axis=0)).max()
+    dt_v = 2e-4
+    dt = torch.full((1,), dt_v, dtype=torch.float64, device=DEV)
+    conc = torch.full((n,), float("nan"), dtype=torch.float32, device=DEV)
+    shift = torch.full((cp.dim, n), float("nan"), dtype=torch.float32, device=DEV)
+    S.sph_shifting(hs.P, n, hs.st, hs.key, hs.start, dt, hs.ws, conc=conc, shift=shift,
+                   flags=S.SPH_INTERACT_REUSE_CELLS)
+    torch.cuda.synchronize()
+    assert S.sph_read_error(hs.ws) == 0
+    cg = conc.cpu().numpy().astype(np.float64)
+    dg = shift.cpu().numpy().astype(np.float64)
+    co, _, do = oracle.shift(cp, pos, vel, rho, typ, dt_v)
+    fl = typ == cases.FLUID
+    same = (cg < cp.shift_fs) == (co < cp.shift_fs)
+    scale = np.abs(do[:, fl]).max()
+    ec = np.abs(cg - co).max()
+    ed = np.abs(dg - do)[:, fl & same].max() / scale
+    _say(f"  {name} move {move} cell (max {moved / cp.cell_size:.3f}): C err {ec:.2e}, shift "
+         f"rel err {ed:.2e}, surface decisions differing {(~same & fl).sum()}")
+    assert ec < 1e-5
+    assert ed < 1e-4
+    assert (~same & fl).sum() <= max(2, fl.sum() // 1000)
+    assert np.array_equal(hs.st.pos.cpu().numpy(), pos + dg)
+
+
+def test_shifting_on_reused_cells_beyond_the_margin_raises_the_error():
+    from test_gpu_reuse import HalfStep, _case
+    c = _with(_case("3d_block"), shift_coef=2.0, shift_fs=0.9)
+    hs = HalfStep(c, 0.6)
+    S.sph_refresh_view(hs.P, hs.n, hs.st, hs.key, hs.ws)
+    dt = torch.full((1,), 2e-4, dtype=torch.float64, device=DEV)
+    S.sph_shifting(hs.P, hs.n, hs.st, hs.key, hs.start, dt, hs.ws,
+                   flags=S.SPH_INTERACT_REUSE_CELLS)
+    torch.cuda.synchronize()
+    err = S.sph_read_error(hs.ws)
+    _say(f"  shifting after a 0.6-cell move: error word {err}")
+    assert err & S.SPH_ERR_MARGIN
