@@ -264,6 +264,31 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s,
                         uint32_t* nbr_count, uint32_t flags, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory: code recorded into a HIP
+ * graph under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  sph_interact without a workspace: the regions the pass needs
+ * besides its inputs and outputs (the interaction view, built here from s;
+ * the per-block partial results; an error word) live in one device array of
+ * the library, 68 MB (for SPH_NOALLOC_MAX_N particles), which each GPU the
+ * library runs on holds until the process ends.
+ *   s, key, cell_start   as sph_bin_cells left them (s sorted; positions,
+ *                        velocities, densities and types not changed since)
+ *   ace, arho, visc, nbr_count, flags   as sph_interact (the same kernels:
+ *                        the same results), except SPH_INTERACT_REUSE_CELLS
+ * n must be at most SPH_NOALLOC_MAX_N and p->boundary 0 (modified DBC takes
+ * its wall entries from sph_mdbc), else SPH_E_ARG.  Nothing is allocated:
+ * the array's device address is looked up on the first call on each device
+ * (the current device, to which `stream` must belong); do one call before a
+ * capture.  The array keeps the last call's contents and each call clears
+ * what must start at zero; its partial results and error word cannot be read
+ * (sph_reduce_dt does not apply).  Calls that overlap on one GPU (other
+ * streams or threads) race on the array: serialise them. */
+#define SPH_NOALLOC_MAX_N 2097152
+sph_status sph_interact_noalloc(const sph_params* p, int64_t n, const sph_state* s,
+                                const uint32_t* key, const uint32_t* cell_start, float* ace,
+                                float* arho, float* visc, uint32_t* nbr_count, uint32_t flags,
+                                void* stream);
+
 /* Rewrites the interaction view that sph_bin_cells left in the workspace
  * from the state's current positions, velocities and densities, keeping the
  * sorted order and the cells of that binning (key, cell_start unchanged),

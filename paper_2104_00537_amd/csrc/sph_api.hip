@@ -147,7 +147,7 @@ static bool periodic_reach_ok(const sph_params* p, int reach) {
   return true;
 }
 
-static bool params_ok(const sph_params* p) {
+bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
   if (p->cell_div != 1 && p->cell_div != 2) return false;

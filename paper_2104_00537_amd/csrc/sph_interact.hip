@@ -258,11 +258,21 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
                            const uint32_t* cell_start, float* ace, float* arho, float* visc,
                            uint32_t* nbr, uint32_t flags, void* ws, hipStream_t st) {
   const WsLayout L = ws_layout(n);
-  const float4* pr = ws_ptr<float4>(ws, L.view_pr);
-  const float4* vp = ws_ptr<float4>(ws, L.view_vp);
-  BlockRed* red = ws_ptr<BlockRed>(ws, L.red);
-  WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
-  const unsigned grid = (unsigned)L.nblk_interact;
+  const InteractScratch w{ws_ptr<float4>(ws, L.view_pr), ws_ptr<float4>(ws, L.view_vp),
+                          ws_ptr<BlockRed>(ws, L.red), ws_ptr<WsHeader>(ws, L.err),
+                          ws_ptr<uint32_t>(ws, L.disp)};
+  return launch_interact_on(kp, n, s, key, cell_start, ace, arho, visc, nbr, flags, w, st);
+}
+
+hipError_t launch_interact_on(const KParams& kp, int64_t n, const sph_state& s,
+                              const uint32_t* key, const uint32_t* cell_start, float* ace,
+                              float* arho, float* visc, uint32_t* nbr, uint32_t flags,
+                              const InteractScratch& w, hipStream_t st) {
+  const float4* pr = w.pr;
+  const float4* vp = w.vp;
+  BlockRed* red = w.red;
+  WsHeader* hdr = w.hdr;
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1);
   const uint32_t arm = flags & ~(uint32_t)SPH_INTERACT_ONE_LANE;  // the arms take one lane
   if (arm == SPH_INTERACT_F64 || arm == SPH_INTERACT_ABS_F32) {
     const bool f64 = arm == SPH_INTERACT_F64;
@@ -293,7 +303,7 @@ hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, con
   hipLaunchKernelGGL((k_interact_gather<D, RR, G, PP, GG, PE, LP>),                          \
                      dim3(LP == 1 ? grid : (grid4 > 0 ? grid4 : 1)), dim3(kBlock), 0, st, kp, n, \
                      pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr,   \
-                     ws_ptr<uint32_t>(ws, L.disp))
+                     w.disp)
 #define SPH_LAUNCH_G(D, RR, G, PP)                                       \
   if (per) SPH_LAUNCH(D, RR, G, PP, true, true, 1);                      \
   else if (gen) SPH_LAUNCH(D, RR, G, PP, true, false, 1);                \

@@ -32,6 +32,21 @@ hipError_t launch_refresh_view(const KParams& kp, int64_t n, const sph_state& s,
 hipError_t launch_interact(const KParams& kp, int64_t n, const sph_state& s, const uint32_t* key,
                            const uint32_t* cell_start, float* ace, float* arho, float* visc,
                            uint32_t* nbr, uint32_t flags, void* ws, hipStream_t st);
+// The device regions an interaction pass reads and writes besides its inputs
+// and outputs: the view, the per-block partial results, the header with the
+// error word and the displacement record.
+struct InteractScratch {
+  const float4* pr;
+  const float4* vp;
+  BlockRed* red;
+  WsHeader* hdr;
+  const uint32_t* disp;
+};
+hipError_t launch_interact_on(const KParams& kp, int64_t n, const sph_state& s,
+                              const uint32_t* key, const uint32_t* cell_start, float* ace,
+                              float* arho, float* visc, uint32_t* nbr, uint32_t flags,
+                              const InteractScratch& w, hipStream_t st);
+bool params_ok(const sph_params* p);
 hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* interactions,
                             float* maxima, void* ws, hipStream_t st);
 hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const double* dt, double* t,

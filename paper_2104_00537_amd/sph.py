@@ -30,7 +30,7 @@ SPH_INTERACT_REUSE_CELLS = 8
 SPH_INTERACT_ONE_LANE = 16
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_interact",
-           "sph_reduce_dt",
+           "sph_interact_noalloc", "sph_reduce_dt",
            "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_floating_step",
            "sph_shifting",
            "sph_read_error", "sph_clear_error", "sph_strerror",
@@ -40,6 +40,7 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
 SPH_BATCH_MAX_SLOTS = 4096
 SPH_BATCH_WAVE_ALIGNED = 1
+SPH_NOALLOC_MAX_N = 2097152
 
 
 class SphParams(C.Structure):
@@ -97,6 +98,9 @@ def _load() -> C.CDLL:
     L.sph_interact.restype = C.c_int32
     L.sph_interact.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP, VP,
                                C.c_uint32, VP, C.c_size_t, VP]
+    L.sph_interact_noalloc.restype = C.c_int32
+    L.sph_interact_noalloc.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP,
+                                       VP, C.c_uint32, VP]
     L.sph_refresh_view.restype = C.c_int32
     L.sph_refresh_view.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_reduce_dt.restype = C.c_int32
@@ -262,6 +266,15 @@ def sph_interact(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
     _check(lib.sph_interact(C.byref(params), int(n), C.byref(s.c()), _ptr(key), _ptr(cell_start),
                             _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr), int(flags), _ptr(ws),
                             ws.numel(), _stream(stream)), "sph_interact")
+
+
+def sph_interact_noalloc(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                         cell_start: torch.Tensor, ace: torch.Tensor, arho: torch.Tensor,
+                         visc: Optional[torch.Tensor] = None, nbr: Optional[torch.Tensor] = None,
+                         flags: int = 0, stream=None):
+    _check(lib.sph_interact_noalloc(C.byref(params), int(n), C.byref(s.c()), _ptr(key),
+                                    _ptr(cell_start), _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr),
+                                    int(flags), _stream(stream)), "sph_interact_noalloc")
 
 
 def sph_refresh_view(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,

@@ -187,6 +187,26 @@ def test_workspace_and_pointer_checks_without_device(S):
     assert lib.sph_strerror(S.SPH_E_WORKSPACE) == b"workspace too small"
 
 
+def test_noalloc_validates_without_device(S):
+    """sph_interact_noalloc rejects sizes beyond its array, modified DBC,
+    reused cells and bad parameters before any HIP call."""
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d().params)
+    lib = S.lib
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, None)
+    call = lambda P, n, fl=0: lib.sph_interact_noalloc(C.byref(P), n, C.byref(st), d, d, d, d,
+                                                       None, None, fl, None)
+    assert call(P, S.SPH_NOALLOC_MAX_N + 1) == S.SPH_E_ARG
+    assert call(P, -1) == S.SPH_E_ARG
+    assert call(P, 1000, S.SPH_INTERACT_REUSE_CELLS) == S.SPH_E_ARG
+    assert call(P, 1000, 0x20) == S.SPH_E_ARG
+    assert call(_bad_params(S, h=0.0), 1000) == S.SPH_E_ARG
+    assert call(_bad_params(S, boundary=1), 1000) == S.SPH_E_ARG
+    assert lib.sph_interact_noalloc(C.byref(P), 1000, C.byref(st), d, d, None, d, None, None, 0,
+                                    None) == S.SPH_E_ARG
+
+
 def test_batch_describe_host_only(S):
     """The slot table is built on the host: key ranges are the cells of the
     slots before plus one each, offsets are validated, cell_div must agree."""
