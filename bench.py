@@ -113,7 +113,7 @@ def cpu_baseline(case, sim, seconds):
     omp = os.environ.get("OMP_NUM_THREADS")
     cores = min(aff, int(omp)) if omp and omp.isdigit() else aff
     return {"value": float(pairs / el), "unit": "interactions/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"one interaction pass for {k} random targets of {n} particles "
                       f"(all {n} as candidate neighbours, brute force FP64), {el:.1f} s"}
 
@@ -328,6 +328,11 @@ def serving(args):
     print("[bench] serving: plain path", file=sys.stderr, flush=True)
     reqs2 = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
     out["plain"] = V.serve_plain(reqs2)
+    # offered load: arrival rate x the mean service time of the plain path
+    # (above 1 the stream queues on that path)
+    svc = [r.finish - r.start for r in reqs2]
+    out["stream"]["plain_mean_service_s"] = float(np.mean(svc))
+    out["stream"]["offered_load_plain"] = float(args.serve_rate * np.mean(svc))
     out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
     out["p50_ratio_plain_over_batched"] = out["plain"]["p50_latency_s"] / out["batched"]["p50_latency_s"]
     out["p99_ratio_plain_over_batched"] = out["plain"]["p99_latency_s"] / out["batched"]["p99_latency_s"]
@@ -378,6 +383,127 @@ def profile_mode(args):
     return 0
 
 
+def _front(sim, case):
+    """Largest x over fluid particles, relative to the tank length (the
+    dam-break front) and its value in metres."""
+    import numpy as np
+    st = sim.state
+    fl = (st.type == 0)
+    x = float(st.pos[0][fl].max().item())
+    x0 = float(case.pos[0].min())
+    return x, (x - x0)
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's."""
+    import platform
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def run_mode(args):
+    """A whole run of a workload from its initial state: every one of
+    --steps steps is timed (no warm-up beyond the kernels' first launch on a
+    copy of the case), with the interactions counted on the device.  For the
+    2-D dam break, --oracle also runs the CPU oracle over the same steps
+    (timed, on the host cores) and compares the fronts."""
+    import numpy as np
+    import torch
+    from paper_2104_00537_amd.runner import Simulation
+    case = workload(args.workload, args.cell_div, args.x_sub)
+    print(f"[bench] run {args.workload}: n={case.n} fluid={case.n_fluid} "
+          f"cells={case.params.ncell} steps={args.steps}", file=sys.stderr, flush=True)
+    # first launches (module load, code paths) on a throw-away copy of a
+    # small case of the same kind, so that the timed run starts warm
+    warm = workload("dam_break_2d", args.cell_div, args.x_sub)
+    w = Simulation(warm, "cuda:0")
+    for _ in range(4):
+        w.step()
+    del w
+    sim = Simulation(case, "cuda:0")
+    torch.cuda.synchronize()
+    # every step is timed; the device is synchronised after every chunk of
+    # steps (a few microseconds per chunk) to record how the cost per step
+    # evolves with the flow
+    t0 = time.perf_counter()
+    last = t0
+    done = 0
+    chunk = max(1, min(args.steps, args.run_chunk))
+    by_chunk = []
+    i_prev, c_prev = 0, t0
+    while done < args.steps:
+        k = min(chunk, args.steps - done)
+        for _ in range(k):
+            sim.step()
+        done += k
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        i_now = int(sim.interactions[0].item())
+        by_chunk.append({"steps": k, "ms_per_step": (now - c_prev) / k * 1e3,
+                         "interactions_per_s": (i_now - i_prev) / (now - c_prev),
+                         "t_end_s": sim.time(), "dt": float(sim.dt.item())})
+        i_prev, c_prev = i_now, time.perf_counter()
+        if now - last > 20.0 or done == args.steps:
+            last = now
+            print(f"[bench] step {done}/{args.steps} t={sim.time():.5f} s", file=sys.stderr,
+                  flush=True)
+    el = time.perf_counter() - t0
+    err = sim.error()
+    if err != 0:
+        raise SystemExit(f"device error word {err} during the run")
+    d_inter = sim.interactions.cpu().numpy().astype(np.int64)
+    xf, front = _front(sim, case)
+    length = float(case.meta.get("tank", (1.0,))[0])
+    res = {"mode": "run", "workload": args.workload, "n_particles": case.n,
+           "n_fluid": case.n_fluid, "steps": args.steps, "seconds": el,
+           "ms_per_step": el / args.steps * 1e3, "steps_per_s": args.steps / el,
+           "interactions": int(d_inter[0]), "interactions_per_s": float(d_inter[0]) / el,
+           "sim_time_s": sim.time(), "dt_last": float(sim.dt.item()),
+           "front_x_m": xf, "front_over_length": front / length,
+           "cell_div": args.cell_div, "x_sub": args.x_sub, "by_chunk": by_chunk}
+    if args.oracle:
+        import oracle
+        if case.n > 20000:
+            raise SystemExit("--oracle runs the brute-force oracle: small cases only")
+        gpu = sim.host_state()
+        cp = case.params
+        print(f"[bench] oracle: {args.steps} steps on the host", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        out = oracle.run(cp, case.pos, case.vel.astype(np.float64),
+                         case.rho.astype(np.float64), case.type, args.steps)
+        el_o = time.perf_counter() - t1
+        pos, t_end = out["pos"], out["t"]
+        fl = case.type == 0
+        xo = float(pos[0][fl].max())
+        try:
+            aff = len(os.sched_getaffinity(0))
+        except AttributeError:
+            aff = os.cpu_count() or 1
+        omp = os.environ.get("OMP_NUM_THREADS")
+        cores = min(aff, int(omp)) if omp and omp.isdigit() else aff
+        res["oracle"] = {"seconds": el_o, "ms_per_step": el_o / args.steps * 1e3,
+                         "cores": cores, "cpu": cpu_model(), "sim_time_s": float(t_end),
+                         "front_x_m": xo,
+                         "front_diff_over_length": abs(xo - float(gpu["pos"][0][fl].max())) / length,
+                         "max_pos_diff_m": float(np.abs(pos - gpu["pos"]).max()),
+                         "interactions": int(out["interactions"]), "status": int(out["status"]),
+                         "gpu_speedup": el_o / el}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def serve_mode(args):
+    """The serving stream alone (both paths, same seeded trace)."""
+    res = {"mode": "serve", "serving": serving(args)}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,8 +513,15 @@ def main():
     ap.add_argument("--cell-div", type=int, default=2)
     ap.add_argument("--x-sub", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--mode", choices=["step", "interact", "copy"], default="step",
-                    help="step: the benchmark; interact/copy: kernel-only runs for counters")
+    ap.add_argument("--mode", choices=["step", "interact", "copy", "run", "serve"],
+                    default="step",
+                    help="step: the benchmark; interact/copy: kernel-only runs for counters; "
+                         "run: a whole run of --steps steps from t = 0; serve: the serving "
+                         "stream alone")
+    ap.add_argument("--run-chunk", type=int, default=100,
+                    help="run mode: steps between synchronisations (cost per chunk reported)")
+    ap.add_argument("--oracle", action="store_true",
+                    help="run mode: also run the CPU oracle over the same steps (2-D case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
@@ -414,6 +547,10 @@ def main():
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         return 2
 
+    if args.mode == "run":
+        return run_mode(args)
+    if args.mode == "serve":
+        return serve_mode(args)
     if args.mode != "step":
         return profile_mode(args)
 

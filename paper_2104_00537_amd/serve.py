@@ -333,16 +333,33 @@ def make_stream(n_requests: int, rate: float, seed: int = 0, n_min=2000, n_max=5
     return out
 
 
+class _Progress:
+    """A line on stderr at most every `every` seconds (long streams)."""
+
+    def __init__(self, label: str, total: int, every: float = 30.0):
+        self.label, self.total, self.every = label, total, every
+        self.last = time.perf_counter()
+
+    def __call__(self, done: int, now: float):
+        if self.every > 0 and time.perf_counter() - self.last >= self.every:
+            self.last = time.perf_counter()
+            import sys
+            print(f"[serve] {self.label}: {done}/{self.total} requests done at {now:.1f} s",
+                  file=sys.stderr, flush=True)
+
+
 def serve_batched(reqs: List[Request], engine: BatchEngine, max_chunk: int = 64,
-                  keep_results: bool = False) -> dict:
+                  keep_results: bool = False, progress_s: float = 30.0) -> dict:
     """Continuous batching: admit arrived requests whenever a slot and memory
     are free, run the batch until the next case finishes (at most max_chunk
     steps, so that arrivals wait briefly), retire finished cases, repeat."""
     pending = sorted(reqs, key=lambda r: r.arrival)
     left = {}
+    prog = _Progress("batched", len(reqs), progress_s)
     t0 = time.perf_counter()
     while pending or engine.slots:
         now = time.perf_counter() - t0
+        prog(sum(1 for r in reqs if r.finish is not None), now)
         done = [k for k, r in enumerate(engine.slots) if left[r.rid] == 0]
         keep = [r for r in engine.slots if left[r.rid] > 0]
         add = []
@@ -378,12 +395,14 @@ def serve_batched(reqs: List[Request], engine: BatchEngine, max_chunk: int = 64,
 
 
 def serve_plain(reqs: List[Request], device="cuda", use_graph: bool = True,
-                keep_results: bool = False) -> dict:
+                keep_results: bool = False, progress_s: float = 30.0) -> dict:
     """One case at a time, in arrival order, with the single-case calls."""
+    prog = _Progress("plain", len(reqs), progress_s)
     t0 = time.perf_counter()
     inter_total = 0
-    for r in sorted(reqs, key=lambda x: x.arrival):
+    for k, r in enumerate(sorted(reqs, key=lambda x: x.arrival)):
         now = time.perf_counter() - t0
+        prog(k, now)
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.start = time.perf_counter() - t0
