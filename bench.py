@@ -323,19 +323,24 @@ def serving(args):
     V.serve_plain(V.make_stream(1, 1e6, seed=98, n_min=2000, n_max=3000, steps_min=4,
                                 steps_max=4))
     torch.cuda.synchronize()
-    print("[bench] serving: batched engine", file=sys.stderr, flush=True)
-    out["batched"] = V.serve_batched(reqs, eng)
-    print("[bench] serving: plain path", file=sys.stderr, flush=True)
-    reqs2 = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
-    out["plain"] = V.serve_plain(reqs2)
-    # offered load: arrival rate x the mean service time of the plain path
-    # (above 1 the stream queues on that path)
-    svc = [r.finish - r.start for r in reqs2]
-    out["stream"]["plain_mean_service_s"] = float(np.mean(svc))
-    out["stream"]["offered_load_plain"] = float(args.serve_rate * np.mean(svc))
-    out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
-    out["p50_ratio_plain_over_batched"] = out["plain"]["p50_latency_s"] / out["batched"]["p50_latency_s"]
-    out["p99_ratio_plain_over_batched"] = out["plain"]["p99_latency_s"] / out["batched"]["p99_latency_s"]
+    if args.serve_legs in ("both", "batched"):
+        print("[bench] serving: batched engine", file=sys.stderr, flush=True)
+        out["batched"] = V.serve_batched(reqs, eng)
+    if args.serve_legs in ("both", "plain"):
+        print("[bench] serving: plain path", file=sys.stderr, flush=True)
+        reqs2 = V.make_stream(args.serve_requests, args.serve_rate, seed=7, **kw)
+        out["plain"] = V.serve_plain(reqs2)
+        # offered load: arrival rate x the mean service time of the plain
+        # path (above 1 the stream queues on that path)
+        svc = [r.finish - r.start for r in reqs2]
+        out["stream"]["plain_mean_service_s"] = float(np.mean(svc))
+        out["stream"]["offered_load_plain"] = float(args.serve_rate * np.mean(svc))
+    if "batched" in out and "plain" in out:
+        out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["plain"]["solves_per_s"]
+        out["p50_ratio_plain_over_batched"] = (out["plain"]["p50_latency_s"]
+                                               / out["batched"]["p50_latency_s"])
+        out["p99_ratio_plain_over_batched"] = (out["plain"]["p99_latency_s"]
+                                               / out["batched"]["p99_latency_s"])
     return out
 
 
@@ -534,6 +539,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="> 0: replay the timed steps as HIP graphs of this many steps")
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-legs", choices=["both", "batched", "plain"], default="both")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-steps-scale", type=float, default=1.0)
     ap.add_argument("--serve-n-min", type=int, default=2000)

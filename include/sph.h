@@ -121,7 +121,15 @@ enum {
    * their results, which shortens each lane's chain of dependent loads;
    * results agree up to the order of the FP32 sums (FP64 counts are
    * identical).  Combines with every other flag. */
-  SPH_INTERACT_ONE_LANE = 16u
+  SPH_INTERACT_ONE_LANE = 16u,
+  /* The all-FP64 arm of the precision study (Section 5.1): as
+   * SPH_INTERACT_F64, but velocities and densities come from the state's
+   * FP64 copies (s->vel64, s->rho64, required) instead of the stored FP32
+   * values, and the rates are written in FP64: `ace` and `arho` then point to
+   * double arrays ([dim][n] and [n]) that sph_symplectic_step reads for an
+   * all-FP64 state.  visc stays FP32.  Same restrictions as SPH_INTERACT_F64;
+   * not with SPH_INTERACT_REUSE_CELLS. */
+  SPH_INTERACT_F64_STATE = 32u
 };
 
 /* Case constants, passed by pointer to host memory and copied by value into
@@ -206,6 +214,15 @@ typedef struct sph_state {
                        node (mirror image across the wall face), 0 for
                        fluid; carried through the sort (nullable; needed by
                        sph_mdbc) */
+  double* vel64;    /* [dim][n] and [n], nullable as a pair: an all-FP64     */
+  double* rho64;    /* state (the precision study's reference arm).  When
+                       set they are the velocities and densities, carried
+                       through the sort (in and out, and the carried pair,
+                       when both sides have them), advanced in FP64 by
+                       sph_symplectic_step, which also writes their FP32
+                       roundings to vel and rho; read by sph_interact with
+                       SPH_INTERACT_F64_STATE.  Not with sph_verlet_step,
+                       sph_refresh_view, floating bodies or the batch calls. */
 } sph_state;
 
 /* Bytes of workspace the calls need for a case of n particles. */
@@ -323,7 +340,10 @@ sph_status sph_reduce_dt(const sph_params* p, int64_t n, double* dt,
  *   Moving walls take x = x_n + D(t') - D(t), v_x = (A/w) sin(w t') at
  *   t' = t + dt/2 (predictor) or t + dt (corrector), D(t) = (A/w^2)(1-cos wt).
  *   dt, t: device FP64 scalars (t is read by both phases, advanced by phase 1).
- * Position arithmetic is FP64; velocity and density are stored in FP32. */
+ * Position arithmetic is FP64; velocity and density are stored in FP32.  An
+ * all-FP64 state (s->vel64 and s->rho64 set; then `saved` needs them too)
+ * is advanced in FP64 from FP64 rates: ace and arho are then double arrays
+ * (those of sph_interact with SPH_INTERACT_F64_STATE). */
 sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase,
                                const double* dt, double* t, sph_state* saved,
                                sph_state* s, const float* ace,
@@ -470,8 +490,11 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
 enum {
   /* every slot's particle range starts and ends at a multiple of 64 (whole
    * wavefronts): the interaction then runs a leaner kernel in which each
-   * wavefront lies in one slot.  Pad a case's range with excluded particles
-   * (type SPH_EXCLUDED) to get it. */
+   * wavefront lies in one slot, and a slot of at most 131,072 particles gets
+   * four lanes per target (as the single-case pass; the choice depends on
+   * the slot's own size only, so a case's results do not depend on the
+   * batch).  Pad a case's range with excluded particles (type SPH_EXCLUDED)
+   * to get it. */
   SPH_BATCH_WAVE_ALIGNED = 1u
 };
 
@@ -483,7 +506,8 @@ typedef struct sph_batch {
                            key_cells + 1 entries */
   const void* table;    /* DEVICE copy of the slot table (see below) */
   uint32_t flags;       /* SPH_BATCH_* flags */
-  uint32_t pad;
+  uint32_t lanes;       /* interaction lanes over all slots (set by
+                           sph_batch_describe) */
 } sph_batch;
 
 /* Bytes of the slot table for n_slots cases. */

@@ -191,8 +191,12 @@ bool params_ok(const sph_params* p) {
 static bool n_ok(int64_t n) { return n >= 0 && n < (int64_t)0xfffffff0ll; }
 
 static bool state_ok(const sph_state* s, bool need_type) {
-  return s && s->pos && s->vel && s->rho && (!need_type || s->type);
+  return s && s->pos && s->vel && s->rho && (!need_type || s->type) &&
+         (s->vel64 == nullptr) == (s->rho64 == nullptr);
 }
+
+// an all-FP64 state (the precision study's reference arm)
+static bool f64_state(const sph_state* s) { return s && s->vel64 != nullptr; }
 
 static sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
 
@@ -236,16 +240,18 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
   const uint32_t reuse = flags & SPH_INTERACT_REUSE_CELLS;
   const uint32_t base =
       flags & ~(uint32_t)(SPH_INTERACT_REUSE_CELLS | SPH_INTERACT_ONE_LANE);
-  if (base != 0 && base != SPH_DIAG_COUNT_F64 && base != SPH_INTERACT_F64 &&
-      base != SPH_INTERACT_ABS_F32)
-    return SPH_E_ARG;
-  if (reuse && (base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 || p->boundary != 0 ||
-                !periodic_reach_ok(p, p->cell_div + 1)))
+  const bool arm = base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32 ||
+                   base == SPH_INTERACT_F64_STATE;
+  if (base != 0 && base != SPH_DIAG_COUNT_F64 && !arm) return SPH_E_ARG;
+  if (reuse && (arm || p->boundary != 0 || !periodic_reach_ok(p, p->cell_div + 1)))
     return SPH_E_ARG;
   // the precision-study arms implement the default formulation only
-  if ((base == SPH_INTERACT_F64 || base == SPH_INTERACT_ABS_F32) &&
-      (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0 ||
-       p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0))
+  if (arm && (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->floating != 0 ||
+              p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0))
+    return SPH_E_ARG;
+  // the all-FP64 arm reads the state's FP64 copies (not with modified DBC,
+  // which writes FP32 wall densities)
+  if (base == SPH_INTERACT_F64_STATE && n > 0 && (!f64_state(s) || p->boundary != 0))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   const KParams kp = make_kparams(*p);
@@ -257,7 +263,7 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
 sph_status sph_refresh_view(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                             void* ws, size_t ws_bytes, void* stream) {
   if (!params_ok(p) || !n_ok(n) || !ws) return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || f64_state(s))) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   sph_state s0 = n > 0 ? *s : sph_state{};
   return hip_status(launch_refresh_view(make_kparams(*p), n, s0, key, ws, (hipStream_t)stream));
@@ -278,6 +284,8 @@ sph_status sph_symplectic_step(const sph_params* p, int64_t n, int32_t phase, co
   if (phase != 0 && phase != 1) return SPH_E_ARG;
   if (n > 0 && (!state_ok(s, true) || !state_ok(saved, false) || !ace || !arho))
     return SPH_E_ARG;
+  // an all-FP64 state needs an all-FP64 saved state (no floating bodies)
+  if (n > 0 && f64_state(s) && (!f64_state(saved) || p->floating != 0)) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   sph_state sv = n > 0 ? *saved : sph_state{}, st = n > 0 ? *s : sph_state{};
   return hip_status(launch_symplectic(make_kparams(*p), n, phase, dt, t, sv, st, ace, arho, ws,
@@ -289,7 +297,8 @@ sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const d
                            const float* arho, void* ws, size_t ws_bytes, void* stream) {
   if (!params_ok(p) || !n_ok(n) || !dt || !t || !ws) return SPH_E_ARG;
   if (mode != 0 && mode != 1) return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !prev || !prev->vel || !prev->rho || !ace || !arho))
+  if (n > 0 && (!state_ok(s, true) || !prev || !prev->vel || !prev->rho || !ace || !arho ||
+                f64_state(s)))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   sph_state pv = n > 0 ? *prev : sph_state{}, st = n > 0 ? *s : sph_state{};
@@ -300,7 +309,7 @@ sph_status sph_verlet_step(const sph_params* p, int64_t n, int32_t mode, const d
 sph_status sph_mdbc(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                     const uint32_t* cell_start, void* ws, size_t ws_bytes, void* stream) {
   if (!params_ok(p) || !n_ok(n) || !cell_start || !ws || p->boundary != 1) return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !s->normal || !key)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !s->normal || !key || f64_state(s))) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   if (n == 0) return SPH_OK;
   return hip_status(launch_mdbc(make_kparams(*p), n, *s, key, cell_start, ws, (hipStream_t)stream));
@@ -313,7 +322,7 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
   if (!params_ok(p) || !n_ok(n) || !dt || !ws || !bodies || p->floating != 1) return SPH_E_ARG;
   if (phase != 0 && phase != 1) return SPH_E_ARG;
   if (n_bodies < 1 || n_bodies > SPH_MAX_BODIES) return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !s->id || !saved || !saved->pos || !ace))
+  if (n > 0 && (!state_ok(s, true) || !s->id || !saved || !saved->pos || !ace || f64_state(s)))
     return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   sph_state sv = n > 0 ? *saved : sph_state{}, st = n > 0 ? *s : sph_state{};
@@ -330,7 +339,7 @@ sph_status sph_shifting(const sph_params* p, int64_t n, sph_state* s, const uint
   if ((flags & SPH_INTERACT_REUSE_CELLS) &&
       (p->boundary != 0 || !periodic_reach_ok(p, p->cell_div + 1)))
     return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || f64_state(s))) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
   if (n == 0) return SPH_OK;
   return hip_status(launch_shifting(make_kparams(*p), n, *s, key, cell_start, dt, conc, shift,
@@ -360,7 +369,8 @@ static bool batch_ok(const sph_batch* b) {
 }
 
 static BatchDesc batch_desc(const sph_batch* b) {
-  return BatchDesc{b->n_slots, b->cell_div, b->n_total, b->key_cells, b->table, b->flags};
+  return BatchDesc{b->n_slots, b->cell_div, b->n_total, b->key_cells, b->table, b->flags,
+                   b->lanes};
 }
 
 size_t sph_batch_table_bytes(int32_t n_slots) {
@@ -397,9 +407,17 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   if (offsets[n_slots] >= ((int64_t)1 << 27)) return SPH_E_ARG;
   bool aligned = true;
   for (int s = 0; s <= n_slots; ++s) aligned = aligned && offsets[s] % 64 == 0;
+  // interaction lanes: with wave-aligned slots, four per target for a slot
+  // of at most kLanesMaxN particles (by its own size only), else one
+  int64_t lanes = 0;
+  for (int s = 0; s < n_slots; ++s) {
+    tab[s].lpt = aligned && tab[s].n <= kLanesMaxN ? kMaxLanes : 1;
+    tab[s].loff = lanes;
+    lanes += tab[s].n * tab[s].lpt;
+  }
   batch->n_slots = n_slots;
   batch->flags = aligned ? SPH_BATCH_WAVE_ALIGNED : 0u;
-  batch->pad = 0;
+  batch->lanes = (uint32_t)lanes;
   batch->cell_div = params[0].cell_div;
   batch->n_total = offsets[n_slots];
   batch->key_cells = (int64_t)cbase;
@@ -423,6 +441,8 @@ sph_status sph_batch_bin_cells(const sph_batch* b, const sph_state* in, sph_stat
   if ((carry_in == nullptr) != (carry_out == nullptr)) return SPH_E_ARG;
   if (carry_in && n > 0 && (!state_ok(carry_in, false) || !state_ok(carry_out, false)))
     return SPH_E_ARG;
+  if (n > 0 && (f64_state(in) || f64_state(out) || f64_state(carry_in) || f64_state(carry_out)))
+    return SPH_E_ARG;
   if (ws_bytes < batch_ws_layout(b->n_slots, n).total) return SPH_E_WORKSPACE;
   sph_state i0 = n > 0 ? *in : sph_state{}, o0 = n > 0 ? *out : sph_state{};
   return hip_status(launch_batch_bin_cells(batch_desc(b), i0, o0, carry_in, carry_out, key, perm,
@@ -435,7 +455,8 @@ sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint
                               void* stream) {
   if (!batch_ok(b) || !cell_start || !ws) return SPH_E_ARG;
   if (flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS) return SPH_E_ARG;
-  if (b->n_total > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !key || !ace || !arho || f64_state(s)))
+    return SPH_E_ARG;
   if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
   return hip_status(launch_batch_interact(batch_desc(b), key, cell_start, ace, arho, visc,
                                           nbr_count, (flags & SPH_INTERACT_REUSE_CELLS) != 0, ws,
@@ -445,7 +466,7 @@ sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint
 sph_status sph_batch_refresh_view(const sph_batch* b, sph_state* s, const uint32_t* key, void* ws,
                                   size_t ws_bytes, void* stream) {
   if (!batch_ok(b) || !ws) return SPH_E_ARG;
-  if (b->n_total > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !key || f64_state(s))) return SPH_E_ARG;
   if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
   sph_state s0 = b->n_total > 0 ? *s : sph_state{};
   return hip_status(launch_batch_refresh_view(batch_desc(b), s0, key, ws, (hipStream_t)stream));
@@ -464,7 +485,8 @@ sph_status sph_batch_symplectic_step(const sph_batch* b, int32_t phase, const do
                                      const float* arho, void* ws, size_t ws_bytes, void* stream) {
   if (!batch_ok(b) || !dt || !t || !ws) return SPH_E_ARG;
   if (phase != 0 && phase != 1) return SPH_E_ARG;
-  if (b->n_total > 0 && (!state_ok(s, true) || !state_ok(saved, false) || !ace || !arho))
+  if (b->n_total > 0 && (!state_ok(s, true) || !state_ok(saved, false) || !ace || !arho ||
+                         f64_state(s) || f64_state(saved)))
     return SPH_E_ARG;
   if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
   sph_state sv = b->n_total > 0 ? *saved : sph_state{}, st = b->n_total > 0 ? *s : sph_state{};

@@ -22,15 +22,29 @@ __device__ inline int find_slot(const SlotEntry* __restrict__ tab, int ns, int64
   return lo;
 }
 
-// The slots of the block's first and last particle (uniform over the block;
-// -1, -1 for a block wholly past n).  Slots are in particle order, so equal
-// values mean the whole block lies in one slot.
+// The slot owning interaction lane t (slots are in lane order as well).
+__device__ inline int find_slot_lane(const SlotEntry* __restrict__ tab, int ns, int64_t t) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].loff <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The slots of the block's first and last particle (LANES: interaction
+// lane) -- uniform over the block; -1, -1 for a block wholly past n.  Slots
+// are in particle (and lane) order, so equal values mean the whole block
+// lies in one slot.
+template <bool LANES = false>
 __device__ inline int2 block_slots(const SlotEntry* __restrict__ tab, int ns, int64_t n,
                                    int64_t first) {
   if (first >= n) return make_int2(-1, -1);
   const int64_t last = first + kBlock - 1 < n ? first + kBlock - 1 : n - 1;
-  return make_int2(__builtin_amdgcn_readfirstlane(find_slot(tab, ns, first)),
-                   __builtin_amdgcn_readfirstlane(find_slot(tab, ns, last)));
+  const int s0 = LANES ? find_slot_lane(tab, ns, first) : find_slot(tab, ns, first);
+  const int s1 = LANES ? find_slot_lane(tab, ns, last) : find_slot(tab, ns, last);
+  return make_int2(__builtin_amdgcn_readfirstlane(s0), __builtin_amdgcn_readfirstlane(s1));
 }
 
 __global__ void k_batch_cell_keys(const SlotEntry* __restrict__ tab, int ns, int64_t n,
@@ -95,15 +109,18 @@ __global__ void k_batch_refresh_view(const SlotEntry* __restrict__ tab, int ns, 
 // constants: each lane walks its own cells (gather_walk) and writes its
 // target; returns the lane's contributions to the slot's sums.  The slot's
 // error words get SPH_ERR_MARGIN (STALE: cells reused after particles moved
-// half a cell or more) from lane `leader`.
-template <int R, bool STALE>
+// half a cell or more) from lane `leader`.  LPT > 1: LPT adjacent lanes
+// share target a, each walking every LPT-th stencil row (lane `sub`); every
+// lane of the wave takes part (the lanes' sums are combined by shuffles),
+// and lane sub = 0 writes the target.
+template <int R, bool STALE, int LPT = 1>
 __device__ __forceinline__ void batch_slot_pass(
     const SlotEntry* __restrict__ tab, int rs, int leader, bool mine, int64_t n, int64_t a,
     const float4* __restrict__ pr, const float4* __restrict__ vp, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
     float* __restrict__ visc, uint32_t* __restrict__ nbr, const uint32_t* __restrict__ disp,
     uint32_t* __restrict__ err, uint32_t* __restrict__ slot_err, float& fmag, float& vmx,
-    uint32_t& cnt, uint32_t& cntw, uint32_t& nfl) {
+    uint32_t& cnt, uint32_t& cntw, uint32_t& nfl, int sub = 0) {
   const KParams kp = tab[rs].kp;
   const uint32_t cbase = tab[rs].cbase;
   float cull2 = kp.support2_f * 1.0002f;
@@ -116,29 +133,38 @@ __device__ __forceinline__ void batch_slot_pass(
       set_error(&slot_err[rs], SPH_ERR_MARGIN);
     }
   }
-  if (!mine) return;
-  const uint32_t lk = key[a] - cbase;
-  // a particle the view refresh excluded keeps its cell but has density 0
-  const float4 pa = pr[a];
-  if (lk < kp.ncell_total && (!STALE || pa.w != 0.f)) {
-    PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
-    TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
-    const float4 va = vp[a];
-    T.fluid = pa.w > 0.f;
-    T.rho = fabsf(pa.w);
-    T.irho = __builtin_amdgcn_rcpf(T.rho);
-    T.ik = kp.kvc_f * T.irho;
-    T.p = va.w;
-    T.vx = va.x;
-    T.vy = va.y;
-    T.vz = va.z;
-    const int cx = (int)(lk % (uint32_t)kp.ncx);
-    const uint32_t rest = lk / (uint32_t)kp.ncx;
-    const int cy = (int)(rest % (uint32_t)kp.ncy);
-    const int cz = (int)(rest / (uint32_t)kp.ncy);
-    uint32_t c64 = 0;
-    gather_walk<3, R, false, false, false, false>(kp, cbase, n, a, pa, T, cx, cy, cz, pr, vp,
-                                                  cstart, nullptr, acc, c64, cull2);
+  if (LPT == 1 && !mine) return;
+  PairAcc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0u};
+  TargetData T{false, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false, 0.f};
+  uint32_t c64 = 0;
+  bool active = false;
+  if (mine) {
+    const uint32_t lk = key[a] - cbase;
+    // a particle the view refresh excluded keeps its cell but has density 0
+    const float4 pa = pr[a];
+    active = lk < kp.ncell_total && (!STALE || pa.w != 0.f);
+    if (active) {
+      const float4 va = vp[a];
+      T.fluid = pa.w > 0.f;
+      T.rho = fabsf(pa.w);
+      T.irho = __builtin_amdgcn_rcpf(T.rho);
+      T.ik = kp.kvc_f * T.irho;
+      T.p = va.w;
+      T.vx = va.x;
+      T.vy = va.y;
+      T.vz = va.z;
+      const int cx = (int)(lk % (uint32_t)kp.ncx);
+      const uint32_t rest = lk / (uint32_t)kp.ncx;
+      const int cy = (int)(rest % (uint32_t)kp.ncy);
+      const int cz = (int)(rest / (uint32_t)kp.ncy);
+      gather_walk<3, R, false, false, false, false, LPT>(kp, cbase, n, a, pa, T, cx, cy, cz, pr,
+                                                         vp, cstart, nullptr, acc, c64, cull2,
+                                                         sub);
+    }
+  }
+  if (LPT > 1) combine_lanes<LPT>(acc, c64);  // every lane: its target's sums
+  if (!mine || sub != 0) return;
+  if (active) {
     if (T.fluid) acc.cnt -= 1u;  // the self pair: counted, added nothing
     write_target<3>(kp, n, a, T, acc, acc.cnt, ace, arho, visc, nbr, fmag, vmx, nfl);
     cnt = acc.cnt;
@@ -161,24 +187,41 @@ __device__ __forceinline__ void batch_slot_pass(
 // displacement).
 template <int R, bool STALE, bool ALIGNED>
 __global__ __launch_bounds__(kBlock) void k_batch_interact(
-    const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
-    const float4* __restrict__ vp, const uint32_t* __restrict__ key,
+    const SlotEntry* __restrict__ tab, int ns, int64_t n, int64_t lanes,
+    const float4* __restrict__ pr, const float4* __restrict__ vp, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ cstart, float* __restrict__ ace, float* __restrict__ arho,
     float* __restrict__ visc, uint32_t* __restrict__ nbr, SlotAccum* __restrict__ sacc,
     const uint32_t* __restrict__ disp, uint32_t* __restrict__ err,
     uint32_t* __restrict__ slot_err) {
   const int lane = threadIdx.x & 63;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t a = (int64_t)lb * kBlock + threadIdx.x;
-  const int sa = a < n ? find_slot(tab, ns, a) : -1;
+  // ALIGNED: thread = interaction lane (each slot's lanes are a whole number
+  // of wavefronts, with the slot's own lane count per target); otherwise
+  // thread = target particle
+  const int64_t t = (int64_t)lb * kBlock + threadIdx.x;
+  const int64_t lim = ALIGNED ? lanes : n;
+  int sa = t < lim ? (ALIGNED ? find_slot_lane(tab, ns, t) : find_slot(tab, ns, t)) : -1;
+  int64_t a = t;
   float fmag = 0.f, vmx = 0.f;
   uint32_t cnt = 0, cntw = 0, nfl = 0;
   if (ALIGNED) {
-    // one slot for the whole wave, or a wave wholly past n (sa = -1)
+    // one slot (and lane count) for the whole wave, or a wave wholly past
+    // the lanes (rs = -1)
     const int rs = __builtin_amdgcn_readfirstlane(sa);
-    if (rs >= 0)
-      batch_slot_pass<R, STALE>(tab, rs, 0, a < n, n, a, pr, vp, key, cstart, ace, arho, visc,
-                                nbr, disp, err, slot_err, fmag, vmx, cnt, cntw, nfl);
+    if (rs >= 0) {
+      const int lpt = __builtin_amdgcn_readfirstlane(tab[rs].lpt);
+      const int64_t u = t - tab[rs].loff;
+      if (lpt == kMaxLanes) {
+        a = tab[rs].off + u / kMaxLanes;
+        batch_slot_pass<R, STALE, kMaxLanes>(tab, rs, 0, t < lanes, n, a, pr, vp, key, cstart,
+                                             ace, arho, visc, nbr, disp, err, slot_err, fmag, vmx,
+                                             cnt, cntw, nfl, (int)(u % kMaxLanes));
+      } else {
+        a = tab[rs].off + u;
+        batch_slot_pass<R, STALE>(tab, rs, 0, t < lanes, n, a, pr, vp, key, cstart, ace, arho,
+                                  visc, nbr, disp, err, slot_err, fmag, vmx, cnt, cntw, nfl);
+      }
+    }
   } else {
     bool todo = a < n;
     while (__ballot(todo) != 0ull) {
@@ -193,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
   // per-slot combination into copy lb % kAccCopies of the slot's sums: the
   // block's waves combined in LDS when the block lies in one slot (one set
   // of atomics per block), else one set per wave and slot
-  const int2 bs = block_slots(tab, ns, n, (int64_t)lb * kBlock);
+  const int2 bs = block_slots<ALIGNED>(tab, ns, lim, (int64_t)lb * kBlock);
   if (bs.x >= 0 && bs.x == bs.y) {
     __shared__ float sf[kBlock / 64], sv[kBlock / 64];
     __shared__ uint32_t sc[kBlock / 64], sw[kBlock / 64], sk[kBlock / 64];
@@ -228,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
     }
     return;
   }
-  bool pend = a < n;
+  bool pend = t < lim;
   while (__ballot(pend) != 0ull) {
     const int leader = (int)__builtin_ctzll(__ballot(pend));
     const int rs = __builtin_amdgcn_readlane(sa, leader);
@@ -402,16 +445,18 @@ hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
   const int64_t n = B.n_total;
   const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
   const SlotEntry* tab = (const SlotEntry*)B.table;
-  const unsigned grid = grid_for(n);
+  const bool aligned = (B.flags & SPH_BATCH_WAVE_ALIGNED) != 0;
+  // aligned batches: one thread per interaction lane
+  const int64_t lanes = aligned ? (int64_t)B.lanes : n;
+  const unsigned grid = grid_for(lanes);
 #define SPH_BATCH_LAUNCH(RR, STALE, AL)                                                        \
   hipLaunchKernelGGL((k_batch_interact<RR, STALE, AL>), dim3(grid), dim3(kBlock), 0, st, tab,   \
-                     B.n_slots, n, ws_ptr<float4>(ws, W.base.view_pr),                          \
+                     B.n_slots, n, lanes, ws_ptr<float4>(ws, W.base.view_pr),                   \
                      ws_ptr<float4>(ws, W.base.view_vp), key, cell_start, ace, arho, visc, nbr, \
                      ws_ptr<SlotAccum>(ws, W.accum), ws_ptr<uint32_t>(ws, W.disp),              \
                      ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err))
 #define SPH_BATCH_LAUNCH_R(RR, STALE)                                                          \
   if (aligned) SPH_BATCH_LAUNCH(RR, STALE, true); else SPH_BATCH_LAUNCH(RR, STALE, false)
-  const bool aligned = (B.flags & SPH_BATCH_WAVE_ALIGNED) != 0;
   // reused cells: the search reaches one cell further than the cells' stencil
   const int reach = B.cell_div + (reuse ? 1 : 0);
   if (reach == 1) {

@@ -101,12 +101,20 @@ __device__ inline bool reorder_one(const KParams& kp, int64_t n, int64_t i, int6
   if (in.id && out.id) out.id[i] = in.id[src];
   if (in.normal && out.normal)
     for (int d = 0; d < kp.dim; ++d) out.normal[d * n + i] = in.normal[d * n + src];
+  if (in.vel64 && out.vel64) {  // an all-FP64 state's velocities and densities
+    for (int d = 0; d < kp.dim; ++d) out.vel64[d * n + i] = in.vel64[d * n + src];
+    out.rho64[i] = in.rho64[src];
+  }
   if (carry) {
     for (int d = 0; d < kp.dim; ++d) {
       cout.pos[d * n + i] = cin.pos[d * n + src];
       cout.vel[d * n + i] = cin.vel[d * n + src];
     }
     cout.rho[i] = cin.rho[src];
+    if (cin.vel64 && cout.vel64) {
+      for (int d = 0; d < kp.dim; ++d) cout.vel64[d * n + i] = cin.vel64[d * n + src];
+      cout.rho64[i] = cin.rho64[src];
+    }
   }
   if (t & SPH_EXCLUDED) {
     pr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -207,6 +215,63 @@ __device__ inline bool symplectic_one(const KParams& kp, int64_t n, int64_t i, d
   const float rf = (float)r;
   s.rho[i] = rf;
   return bad || !(rf > 0.f) || !isfinite(rf);
+}
+
+// As symplectic_one for an all-FP64 state (vel64 and rho64 set in s and
+// saved): the same update in FP64 from FP64 rates, with the FP32 copies of
+// velocity and density rewritten as their roundings.
+template <int PHASE>
+__device__ inline bool symplectic_one_f64(const KParams& kp, int64_t n, int64_t i, double dt,
+                                          double dmove, double vmove, const sph_state& saved,
+                                          const sph_state& s, const double* __restrict__ ace,
+                                          const double* __restrict__ arho, double& disp2) {
+  const uint8_t t = s.type[i];
+  if (PHASE == 0) {
+    for (int d = 0; d < kp.dim; ++d) {
+      saved.pos[d * n + i] = s.pos[d * n + i];
+      saved.vel[d * n + i] = s.vel[d * n + i];
+      saved.vel64[d * n + i] = s.vel64[d * n + i];
+    }
+    saved.rho[i] = s.rho[i];
+    saved.rho64[i] = s.rho64[i];
+  }
+  if (is_excluded(t)) return false;
+  bool bad = false;
+  if (is_fluid(t)) {
+    for (int d = 0; d < kp.dim; ++d) {
+      const double a = ace[d * n + i];
+      double v1;
+      if (PHASE == 0) {
+        const double v = s.vel64[d * n + i];
+        const double x0 = s.pos[d * n + i], x1 = x0 + 0.5 * dt * v;
+        s.pos[d * n + i] = x1;
+        disp2 += (x1 - x0) * (x1 - x0);
+        v1 = v + 0.5 * dt * a;
+      } else {
+        const double vn = saved.vel64[d * n + i];
+        v1 = vn + dt * a;
+        s.pos[d * n + i] = saved.pos[d * n + i] + dt * 0.5 * (v1 + vn);
+      }
+      s.vel64[d * n + i] = v1;
+      s.vel[d * n + i] = (float)v1;
+      bad |= !isfinite(v1);
+    }
+  } else if ((t & 0x7f) == SPH_BOUND_MOVING) {
+    s.pos[i] = saved.pos[i] + dmove;
+    s.vel64[i] = vmove;
+    s.vel[i] = (float)vmove;
+    if (PHASE == 0) disp2 += dmove * dmove;
+  }
+  double r;
+  if (PHASE == 0) {
+    r = s.rho64[i] + 0.5 * dt * arho[i];
+  } else {
+    const double eps = -(arho[i] / s.rho64[i]) * dt;
+    r = saved.rho64[i] * (2.0 - eps) / (2.0 + eps);
+  }
+  s.rho64[i] = r;
+  s.rho[i] = (float)r;
+  return bad || !(r > 0.0) || !isfinite(r);
 }
 
 // One particle of the Verlet update (Section 2.5.1): MODE 0 is Eq. 30

@@ -8,6 +8,8 @@
 // chunks from every part of the domain, which balances the work across the
 // XCDs.  Sums are gathered per target (no atomics): results are
 // deterministic.
+#include <type_traits>
+
 #include "sph_kernels.h"
 #include "sph_dev.h"
 #include "sph_pair.h"
@@ -152,13 +154,21 @@ struct ArmAcc {
   uint32_t cnt;
 };
 
-template <int DIM, int R, typename T>
+// F64S (with T = double): the all-FP64 arm, whose velocities and densities
+// come from the state's FP64 copies (vel64, rho64) and whose rates are
+// written as FP64 arrays; otherwise ace and arho are FP32 arrays.
+template <int DIM, int R, typename T, bool F64S>
 __global__ __launch_bounds__(kBlock) void k_interact_arm(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ cstart,
-    const uint8_t* __restrict__ type, const double* __restrict__ pos64, float* __restrict__ ace,
-    float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
+    const uint8_t* __restrict__ type, const double* __restrict__ pos64,
+    const double* __restrict__ vel64, const double* __restrict__ rho64, void* __restrict__ ace_out,
+    void* __restrict__ arho_out, float* __restrict__ visc, uint32_t* __restrict__ nbr,
     BlockRed* __restrict__ red, WsHeader* __restrict__ hdr) {
+  static_assert(!F64S || sizeof(T) == 8, "the all-FP64 arm evaluates pairs in FP64");
+  using Out = typename std::conditional<F64S, double, float>::type;
+  Out* ace = static_cast<Out*>(ace_out);
+  Out* arho = static_cast<Out*>(arho_out);
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
@@ -166,9 +176,11 @@ __global__ __launch_bounds__(kBlock) void k_interact_arm(
     if (!is_excluded(type[i]) && (kp.boundary == 0 || is_fluid(type[i]))) {
       const float4 pa = pr[i], va = vp[i];
       const bool fa = pa.w > 0.f;
-      const T rho_a = (T)fabsf(pa.w);
+      const T rho_a = F64S ? (T)rho64[i] : (T)fabsf(pa.w);
       const T p_a = sizeof(T) == 8 ? (T)(kp.b_tait * tait_ratio(kp, (double)rho_a)) : (T)va.w;
-      const T v_a[3] = {(T)va.x, (T)va.y, (T)va.z};
+      T v_a[3] = {(T)va.x, (T)va.y, (T)va.z};
+      if (F64S)
+        for (int d = 0; d < DIM; ++d) v_a[d] = (T)vel64[d * n + i];
       T x_a[3] = {0, 0, 0};
       for (int d = 0; d < DIM; ++d) x_a[d] = (T)pos64[d * n + i];
       const T h = (T)kp.h, support2 = (T)kp.support2, kfab = (T)kp.kfab;
@@ -203,9 +215,11 @@ __global__ __launch_bounds__(kBlock) void k_interact_arm(
             }
             if (!(r2 < support2)) continue;
             const float4 vb = vp[j];
-            const T rho_b = (T)fabsf(pb.w);
+            const T rho_b = F64S ? (T)rho64[j] : (T)fabsf(pb.w);
             const T p_b = sizeof(T) == 8 ? (T)(kp.b_tait * tait_ratio(kp, (double)rho_b)) : (T)vb.w;
-            const T v_b[3] = {(T)vb.x, (T)vb.y, (T)vb.z};
+            T v_b[3] = {(T)vb.x, (T)vb.y, (T)vb.z};
+            if (F64S)
+              for (int d = 0; d < DIM; ++d) v_b[d] = (T)vel64[d * n + j];
             const T m_b = (T)(fb ? kp.mass_f : kp.mass_b);
             const T q = sqrt(r2) / h;
             const T w = (T)1 - q / (T)2;
@@ -239,16 +253,21 @@ __global__ __launch_bounds__(kBlock) void k_interact_arm(
         vmax_out = (float)acc.vmax;
         nfl = 1;
       }
-      ace[i] = (float)ax;
-      ace[n + i] = (float)ay;
-      if (DIM == 3) ace[2 * n + i] = (float)az;
-      arho[i] = (float)ar;
+      ace[i] = (Out)ax;
+      ace[n + i] = (Out)ay;
+      if (DIM == 3) ace[2 * n + i] = (Out)az;
+      arho[i] = (Out)ar;
       if (visc) visc[i] = (float)acc.vmax;
       if (nbr) nbr[i] = acc.cnt;
       cnt_out = acc.cnt;
       cnt_wall = fa ? 0u : acc.cnt;
     } else {
-      write_zero<DIM>(n, i, ace, arho, visc, nbr);
+      ace[i] = 0;
+      ace[n + i] = 0;
+      if (DIM == 3) ace[2 * n + i] = 0;
+      arho[i] = 0;
+      if (visc) visc[i] = 0.f;
+      if (nbr) nbr[i] = 0u;
     }
   }
   write_block_red<kBlock / 64>(fmag, vmax_out, cnt_out, cnt_wall, nfl, red, hdr);
@@ -274,13 +293,17 @@ hipError_t launch_interact_on(const KParams& kp, int64_t n, const sph_state& s,
   WsHeader* hdr = w.hdr;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1);
   const uint32_t arm = flags & ~(uint32_t)SPH_INTERACT_ONE_LANE;  // the arms take one lane
-  if (arm == SPH_INTERACT_F64 || arm == SPH_INTERACT_ABS_F32) {
+  if (arm == SPH_INTERACT_F64 || arm == SPH_INTERACT_ABS_F32 || arm == SPH_INTERACT_F64_STATE) {
     const bool f64 = arm == SPH_INTERACT_F64;
-#define SPH_ARM(D, RR, T)                                                                  \
-  hipLaunchKernelGGL((k_interact_arm<D, RR, T>), dim3(grid), dim3(kBlock), 0, st, kp, n, pr, \
-                     vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr)
-#define SPH_ARM_T(D, RR) \
-  if (f64) SPH_ARM(D, RR, double); else SPH_ARM(D, RR, float)
+    const bool f64s = arm == SPH_INTERACT_F64_STATE;
+#define SPH_ARM(D, RR, T, FS)                                                                 \
+  hipLaunchKernelGGL((k_interact_arm<D, RR, T, FS>), dim3(grid), dim3(kBlock), 0, st, kp, n,   \
+                     pr, vp, key, cell_start, s.type, s.pos, s.vel64, s.rho64, (void*)ace,     \
+                     (void*)arho, visc, nbr, red, hdr)
+#define SPH_ARM_T(D, RR)                                                 \
+  if (f64s) SPH_ARM(D, RR, double, true);                                \
+  else if (f64) SPH_ARM(D, RR, double, false);                           \
+  else SPH_ARM(D, RR, float, false)
     if (kp.dim == 2) {
       if (kp.cell_div == 1) SPH_ARM_T(2, 1); else SPH_ARM_T(2, 2);
     } else {

@@ -89,9 +89,10 @@ constexpr int kDispSlots = 64;
 struct SlotEntry {
   KParams kp;
   uint32_t cbase;    // keys of the slot: cbase .. cbase + kp.ncell_total
-  uint32_t pad;
+  int32_t lpt;       // interaction lanes per target particle (1 or kMaxLanes)
   int64_t off;       // first particle of the slot
   int64_t n;         // particles of the slot
+  int64_t loff;      // first interaction lane of the slot (lanes in slot order)
 };
 
 // Per-slot results of one interaction pass (cleared by each binning);

@@ -16,6 +16,7 @@ struct BatchDesc {
   int64_t key_cells;
   const void* table;  // device SlotEntry[n_slots]
   uint32_t flags;     // SPH_BATCH_* flags of sph_batch_describe
+  uint32_t lanes;     // interaction lanes over all slots
 };
 int key_bits(uint32_t ncell_total);
 void exclusive_scan(uint32_t* data, int64_t len, uint32_t* part, hipStream_t st);

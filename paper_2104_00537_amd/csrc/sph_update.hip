@@ -62,14 +62,15 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_dt(KParams kp, const Blo
 
 // phase 0: predictor, saving state n; phase 1: corrector from the saved state.
 // The predictor also records the largest distance a particle moved (for an
-// interaction that reuses the cells of the last binning).
-template <int PHASE>
+// interaction that reuses the cells of the last binning).  F64S: an all-FP64
+// state, whose rates ace and arho are FP64 arrays.
+template <int PHASE, bool F64S>
 __global__ __launch_bounds__(kBlock) void k_symplectic(KParams kp, int64_t n,
                                                        const double* __restrict__ dtp,
                                                        const double* __restrict__ tp,
                                                        sph_state saved, sph_state s,
-                                                       const float* __restrict__ ace,
-                                                       const float* __restrict__ arho,
+                                                       const void* __restrict__ ace,
+                                                       const void* __restrict__ arho,
                                                        uint32_t* __restrict__ err,
                                                        uint32_t* __restrict__ disp) {
   __shared__ double shm[3];
@@ -83,9 +84,18 @@ __global__ __launch_bounds__(kBlock) void k_symplectic(KParams kp, int64_t n,
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double disp2 = 0.0;
-  if (i < n && symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s, ace, arho,
-                                     disp2))
-    set_error(err, SPH_ERR_NONFINITE);
+  bool bad = false;
+  if (i < n) {
+    if constexpr (F64S)
+      bad = symplectic_one_f64<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s,
+                                      static_cast<const double*>(ace),
+                                      static_cast<const double*>(arho), disp2);
+    else
+      bad = symplectic_one<PHASE>(kp, n, i, shm[0], shm[1], shm[2], saved, s,
+                                  static_cast<const float*>(ace),
+                                  static_cast<const float*>(arho), disp2);
+  }
+  if (bad) set_error(err, SPH_ERR_NONFINITE);
   if (PHASE == 0) record_displacement(disp2, disp);
 }
 
@@ -133,12 +143,17 @@ hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const doub
   WsHeader* hdr = ws_ptr<WsHeader>(ws, L.err);
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
-    if (phase == 0)
-      hipLaunchKernelGGL(k_symplectic<0>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, &hdr->err, ws_ptr<uint32_t>(ws, L.disp));
-    else
-      hipLaunchKernelGGL(k_symplectic<1>, dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, saved, s,
-                         ace, arho, &hdr->err, ws_ptr<uint32_t>(ws, L.disp));
+    uint32_t* disp = ws_ptr<uint32_t>(ws, L.disp);
+    const bool f64s = s.vel64 != nullptr;
+#define SPH_SYMP(PH, F)                                                                      \
+  hipLaunchKernelGGL((k_symplectic<PH, F>), dim3(grid), dim3(kBlock), 0, st, kp, n, dt, t, \
+                     saved, s, (const void*)ace, (const void*)arho, &hdr->err, disp)
+    if (phase == 0) {
+      if (f64s) SPH_SYMP(0, true); else SPH_SYMP(0, false);
+    } else {
+      if (f64s) SPH_SYMP(1, true); else SPH_SYMP(1, false);
+    }
+#undef SPH_SYMP
   }
   if (phase == 1) hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, dt, t);
   return hipGetLastError();

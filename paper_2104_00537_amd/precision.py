@@ -1,18 +1,19 @@
 """Precision study of Section 5.1 on the GPU.
 
-The 3-D dam break is advanced with three forms of the interaction that differ
-only in how pair distances are formed and evaluated:
+The 3-D dam break is advanced in four arms:
 
-  f64         every pair in FP64 from the FP64 positions (SPH_INTERACT_F64);
+  all_f64     all FP64: velocities and densities held and advanced in FP64,
+              every pair in FP64 from the FP64 positions, FP64 rates
+              (SPH_INTERACT_F64_STATE) -- the reference of the long run;
+  f64         every pair in FP64 (SPH_INTERACT_F64), with the production
+              state (FP32 velocities and densities, FP32 rates);
   offset_f32  the production pass: FP32 arithmetic on short offsets
               (fixed-point x modulo 8 cells, cell-relative y and z);
   abs_f32     FP32 arithmetic on positions rounded to FP32 as absolute
               coordinates (SPH_INTERACT_ABS_F32).
 
-The state (FP64 positions, FP32 velocities and densities) and the symplectic
-update are the same in all three.  The front x_f = max x over fluid particles
-is recorded every `--every` steps; the FP64 arm is the reference for the long
-run.  Usage:
+Positions are FP64 in every arm.  The front x_f = max x over fluid particles
+is recorded every `--every` steps.  Usage:
 
   python -m paper_2104_00537_amd.precision [--steps 20000] [--every 1000]
                                            [--workload dam_break_3d_1m]
@@ -33,7 +34,8 @@ from . import cases
 from . import sph as S
 from .runner import Simulation
 
-ARMS = {"f64": S.SPH_INTERACT_F64, "offset_f32": 0, "abs_f32": S.SPH_INTERACT_ABS_F32}
+ARMS = {"all_f64": S.SPH_INTERACT_F64_STATE, "f64": S.SPH_INTERACT_F64, "offset_f32": 0,
+        "abs_f32": S.SPH_INTERACT_ABS_F32}
 
 
 def _case(name):
@@ -54,7 +56,8 @@ def _front(sim):
 
 def run_arm(name, flags, steps, every):
     case = _case(name)
-    sim = Simulation(case, "cuda:0", flags=flags)
+    f64s = flags == S.SPH_INTERACT_F64_STATE
+    sim = Simulation(case, "cuda:0", flags=flags, f64_state=f64s)
     fronts = [(0, 0.0, _front(sim))]
     t0 = time.perf_counter()
     done = 0
@@ -83,7 +86,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--workload", default="dam_break_3d_1m")
-    ap.add_argument("--arms", default="f64,offset_f32,abs_f32")
+    ap.add_argument("--arms", default="all_f64,f64,offset_f32,abs_f32")
     args = ap.parse_args(argv)
     out = {}
     for arm in args.arms.split(","):
@@ -92,16 +95,18 @@ def main(argv=None):
         print(json.dumps({"arm": arm, "workload": args.workload, "steps": args.steps,
                           "ms_per_step": r["ms_per_step"], "excluded": r["excluded"],
                           "fronts": r["fronts"]}), flush=True)
-    if "f64" in out:
-        ref = out["f64"]
-        summary = {"workload": args.workload, "steps": args.steps}
+    refname = "all_f64" if "all_f64" in out else ("f64" if "f64" in out else None)
+    if refname:
+        ref = out[refname]
+        summary = {"workload": args.workload, "steps": args.steps, "reference": refname}
         for arm, r in out.items():
-            if arm == "f64":
+            if arm == refname:
                 continue
             d_front = [abs(a[2] - b[2]) for a, b in zip(r["fronts"], ref["fronts"])]
             # particle-wise differences of the final state against the FP64 arm
             dpos = np.abs(r["state"]["pos"] - ref["state"]["pos"]).max(axis=0)
-            drho = np.abs(r["state"]["rho"].astype(np.float64) - ref["state"]["rho"])
+            drho = np.abs(r["state"]["rho"].astype(np.float64)
+                          - ref["state"]["rho"].astype(np.float64))
             fl = (ref["state"]["type"] == cases.FLUID) & (r["state"]["type"] == cases.FLUID)
             summary[arm] = {"max_front_diff_m": max(d_front), "final_front_diff_m": d_front[-1],
                             "median_pos_diff_m": float(np.median(dpos[fl])),

@@ -24,8 +24,17 @@ from . import sph as S
 class Simulation:
     def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0,
                  integrator: str = "symplectic", verlet_ns: int = 40,
-                 reuse_cells: Optional[bool] = None):
+                 reuse_cells: Optional[bool] = None, f64_state: bool = False):
+        """f64_state: the all-FP64 arm of the precision study -- velocities
+        and densities held and advanced in FP64, every pair evaluated in FP64
+        (SPH_INTERACT_F64_STATE), FP64 rates."""
         cp = case.params
+        self.f64 = bool(f64_state)
+        if self.f64:
+            if flags not in (0, S.SPH_INTERACT_F64_STATE) or integrator != "symplectic":
+                raise ValueError("the all-FP64 state takes its own interaction arm and the "
+                                 "symplectic integrator")
+            flags = S.SPH_INTERACT_F64_STATE
         if cell_div is not None and cell_div != cp.cell_div:
             raise ValueError("cell_div is fixed by the case's grid")
         self.case = case
@@ -37,15 +46,22 @@ class Simulation:
         self.device = dev
         # modified DBC needs the wall ghost vectors, carried through the sorts
         self.mdbc = int(getattr(cp, "boundary", 0)) == 1
-        self.states = [S.DeviceState.from_case(case, dev, with_normal=self.mdbc),
-                       S.DeviceState.empty(self.dim, n, dev, with_normal=self.mdbc)]
-        self.saved = [S.DeviceState.empty(self.dim, n, dev, with_type=False, with_id=False)
+        if self.f64 and (self.mdbc or getattr(case, "bodies", None)
+                         or float(getattr(cp, "shift_coef", 0.0)) > 0.0):
+            raise ValueError("the all-FP64 state takes DBC walls, no floating bodies and no "
+                             "shifting")
+        self.states = [S.DeviceState.from_case(case, dev, with_normal=self.mdbc, f64=self.f64),
+                       S.DeviceState.empty(self.dim, n, dev, with_normal=self.mdbc,
+                                           f64=self.f64)]
+        self.saved = [S.DeviceState.empty(self.dim, n, dev, with_type=False, with_id=False,
+                                          f64=self.f64)
                       for _ in range(2)]
         self.key = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self.cell_start = torch.empty(cp.ncell_total() + 1, dtype=torch.int32, device=dev)
-        self.ace = torch.zeros((self.dim, max(n, 1)), dtype=torch.float32, device=dev)
-        self.arho = torch.zeros(max(n, 1), dtype=torch.float32, device=dev)
+        rate = torch.float64 if self.f64 else torch.float32
+        self.ace = torch.zeros((self.dim, max(n, 1)), dtype=rate, device=dev)
+        self.arho = torch.zeros(max(n, 1), dtype=rate, device=dev)
         self.ws = torch.zeros(S.sph_workspace_bytes(self.params, n), dtype=torch.uint8, device=dev)
         self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
         self.t = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -287,8 +303,10 @@ class Simulation:
         ids = st.id.cpu().numpy().view(np.uint32).astype(np.int64)
         inv = np.empty_like(ids)
         inv[ids] = np.arange(ids.shape[0])
-        return dict(pos=st.pos.cpu().numpy()[:, inv], vel=st.vel.cpu().numpy()[:, inv],
-                    rho=st.rho.cpu().numpy()[inv], type=st.type.cpu().numpy()[inv],
+        vel = st.vel64 if st.vel64 is not None else st.vel
+        rho = st.rho64 if st.rho64 is not None else st.rho
+        return dict(pos=st.pos.cpu().numpy()[:, inv], vel=vel.cpu().numpy()[:, inv],
+                    rho=rho.cpu().numpy()[inv], type=st.type.cpu().numpy()[inv],
                     t=self.time())
 
     def body_state(self) -> list:

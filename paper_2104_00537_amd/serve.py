@@ -435,4 +435,5 @@ def _summary(reqs, makespan, inter_total, extra) -> dict:
                 p50_latency_s=float(np.percentile(lat, 50)),
                 p99_latency_s=float(np.percentile(lat, 99)),
                 mean_latency_s=float(lat.mean()),
-                errors=int(sum(1 for r in reqs if r.error)), **extra)
+                errors=int(sum(1 for r in reqs if r.error)),
+                error_bits={str(r.rid): int(r.error) for r in reqs if r.error}, **extra)

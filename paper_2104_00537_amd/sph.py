@@ -28,6 +28,7 @@ SPH_INTERACT_F64 = 2
 SPH_INTERACT_ABS_F32 = 4
 SPH_INTERACT_REUSE_CELLS = 8
 SPH_INTERACT_ONE_LANE = 16
+SPH_INTERACT_F64_STATE = 32
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_interact",
            "sph_interact_noalloc", "sph_reduce_dt",
@@ -70,13 +71,14 @@ class SphBody(C.Structure):
 
 class SphState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("rho", C.c_void_p),
-                ("type", C.c_void_p), ("id", C.c_void_p), ("normal", C.c_void_p)]
+                ("type", C.c_void_p), ("id", C.c_void_p), ("normal", C.c_void_p),
+                ("vel64", C.c_void_p), ("rho64", C.c_void_p)]
 
 
 class SphBatch(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("cell_div", C.c_int32), ("n_total", C.c_int64),
                 ("key_cells", C.c_int64), ("table", C.c_void_p), ("flags", C.c_uint32),
-                ("pad", C.c_uint32)]
+                ("lanes", C.c_uint32)]
 
 
 class SphError(RuntimeError):
@@ -205,10 +207,12 @@ class DeviceState:
     type: Optional[torch.Tensor] = None  # (n,) uint8
     id: Optional[torch.Tensor] = None    # (n,) int32 (bit pattern of uint32)
     normal: Optional[torch.Tensor] = None  # (dim, n) float32 wall ghost vectors
+    vel64: Optional[torch.Tensor] = None   # (dim, n) float64: an all-FP64 state
+    rho64: Optional[torch.Tensor] = None   # (n,) float64
 
     @staticmethod
     def empty(dim: int, n: int, device, with_type=True, with_id=True,
-              with_normal=False) -> "DeviceState":
+              with_normal=False, f64=False) -> "DeviceState":
         return DeviceState(
             pos=torch.empty((dim, n), dtype=torch.float64, device=device),
             vel=torch.empty((dim, n), dtype=torch.float32, device=device),
@@ -216,10 +220,14 @@ class DeviceState:
             type=torch.empty((n,), dtype=torch.uint8, device=device) if with_type else None,
             id=torch.empty((n,), dtype=torch.int32, device=device) if with_id else None,
             normal=(torch.empty((dim, n), dtype=torch.float32, device=device)
-                    if with_normal else None))
+                    if with_normal else None),
+            vel64=torch.empty((dim, n), dtype=torch.float64, device=device) if f64 else None,
+            rho64=torch.empty((n,), dtype=torch.float64, device=device) if f64 else None)
 
     @staticmethod
-    def from_case(case, device, with_normal=False) -> "DeviceState":
+    def from_case(case, device, with_normal=False, f64=False) -> "DeviceState":
+        """The case's initial state; with f64, also FP64 copies of its
+        velocities and densities (an all-FP64 state)."""
         n = case.n
         normal = None
         if with_normal:
@@ -231,13 +239,15 @@ class DeviceState:
             vel=torch.from_numpy(case.vel).to(device),
             rho=torch.from_numpy(case.rho).to(device),
             type=torch.from_numpy(case.type).to(device),
-            id=torch.arange(n, dtype=torch.int32, device=device), normal=normal)
+            id=torch.arange(n, dtype=torch.int32, device=device), normal=normal,
+            vel64=(torch.from_numpy(case.vel.astype(np.float64)).to(device) if f64 else None),
+            rho64=(torch.from_numpy(case.rho.astype(np.float64)).to(device) if f64 else None))
 
     def c(self) -> SphState:
+        opt = lambda t: None if t is None else t.data_ptr()  # noqa: E731
         return SphState(self.pos.data_ptr(), self.vel.data_ptr(), self.rho.data_ptr(),
-                        None if self.type is None else self.type.data_ptr(),
-                        None if self.id is None else self.id.data_ptr(),
-                        None if self.normal is None else self.normal.data_ptr())
+                        opt(self.type), opt(self.id), opt(self.normal), opt(self.vel64),
+                        opt(self.rho64))
 
     @property
     def n(self) -> int:

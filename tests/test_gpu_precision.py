@@ -105,3 +105,89 @@ def test_arm_steps_2d():
     _say(f"  2d fronts after 300 steps {fronts}")
     for arm in ARMS:
         assert abs(fronts[arm] - fronts["f64"]) <= 1e-3 * 1.6
+
+
+def _binned_f64(case, seed):
+    """The case binned as an all-FP64 state whose velocities and densities
+    carry digits below FP32 resolution (so that an arm reading the FP32
+    copies would be seen)."""
+    rng = np.random.default_rng(seed)
+    n, dim = case.n, case.params.dim
+    P = S.make_params(case.params)
+    src = S.DeviceState.from_case(case, "cuda:0", f64=True)
+    src.vel64 += torch.from_numpy(rng.uniform(-1e-6, 1e-6, (dim, n))).to("cuda:0")
+    src.rho64 += torch.from_numpy(rng.uniform(-1e-4, 1e-4, n)).to("cuda:0")
+    dst = S.DeviceState.empty(dim, n, "cuda:0", f64=True)
+    key = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    perm = torch.empty_like(key)
+    start = torch.empty(case.params.ncell_total() + 1, dtype=torch.int32, device="cuda:0")
+    ws = torch.zeros(S.sph_workspace_bytes(P, n), dtype=torch.uint8, device="cuda:0")
+    S.sph_bin_cells(P, n, src, dst, key, perm, start, ws)
+    return P, n, dst, key, start, ws
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+def test_all_f64_arm_against_oracle(which):
+    """The all-FP64 arm reads the FP64 velocities and densities and writes
+    FP64 rates: they match the FP64 oracle on the same FP64 state to
+    summation-order rounding (bar 1e-11 of max|rate|), which no arm reading
+    FP32 copies could (the state's FP64 digits below FP32 resolution move the
+    rates by far more)."""
+    if which == "2d":
+        c = _perturbed(cases.dam_break_2d(cell_div=2, x_sub=4), 43)
+    else:
+        c = _perturbed(cases.block_case(3, (17, 13, 11), walls=True, seed=9, cell_div=2), 44,
+                       vel=0.3)
+    P, n, dst, key, start, ws = _binned_f64(c, 5)
+    dim = c.params.dim
+    ace = torch.full((dim, n), float("nan"), dtype=torch.float64, device="cuda:0")
+    arho = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+    visc = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    nbr = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    S.sph_interact(P, n, dst, key, start, ace, arho, ws, visc=visc, nbr=nbr,
+                   flags=S.SPH_INTERACT_F64_STATE)
+    torch.cuda.synchronize()
+    assert S.sph_read_error(ws) == 0
+    pos, vel, rho, typ = (dst.pos.cpu().numpy(), dst.vel64.cpu().numpy(),
+                          dst.rho64.cpu().numpy(), dst.type.cpu().numpy())
+    ace_o, arho_o, visc_o, nbr_o = oracle.interact(c.params, pos, vel, rho, typ)
+    fl = (typ & 0x7F) == cases.FLUID
+    a, r = ace.cpu().numpy(), arho.cpu().numpy()
+    ea = np.abs(a - ace_o)[:, fl].max() / np.abs(ace_o[:, fl]).max()
+    er = np.abs(r - arho_o).max() / np.abs(arho_o).max()
+    # the same pass on the FP32 copies (the FP64-pairs arm) for comparison
+    ace32 = torch.empty((dim, n), dtype=torch.float32, device="cuda:0")
+    arho32 = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    S.sph_interact(P, n, dst, key, start, ace32, arho32, ws, flags=S.SPH_INTERACT_F64)
+    torch.cuda.synchronize()
+    er32 = np.abs(arho32.cpu().numpy() - arho_o).max() / np.abs(arho_o).max()
+    _say(f"  all-FP64 arm {which}: rel err ace {ea:.2e} arho {er:.2e} (FP64 pairs on FP32 "
+         f"copies: arho {er32:.2e})")
+    assert ea < 1e-11 and er < 1e-11
+    assert er32 > 100 * er
+    assert np.array_equal(nbr.cpu().numpy().view(np.uint32), nbr_o)
+
+
+def test_all_f64_run_2d_against_oracle():
+    """300 symplectic steps of the 2-D dam break with the all-FP64 state stay
+    within 1e-7 m of the FP64 oracle's trajectory (dt is reduced from FP32
+    block maxima, about 1e-7 relative, which bounds the drift), at least 10
+    times closer than the production path."""
+    c = cases.dam_break_2d(cell_div=2, x_sub=4)
+    steps = 300
+    ref = oracle.run(c.params, c.pos, c.vel.astype(np.float64), c.rho.astype(np.float64),
+                     c.type, steps)
+    errs = {}
+    for name, kw in (("all_f64", dict(f64_state=True)), ("production", {})):
+        sim = Simulation(c, "cuda:0", **kw)
+        sim.run(steps)
+        torch.cuda.synchronize()
+        assert sim.error() == 0
+        st = sim.host_state()
+        errs[name] = (float(np.abs(st["pos"] - ref["pos"]).max()),
+                      float(np.abs(st["vel"] - ref["vel"]).max()),
+                      float(np.abs(st["rho"] - ref["rho"]).max()))
+        assert abs(st["t"] - ref["t"]) <= 1e-6 * ref["t"]
+    _say(f"  2d {steps} steps vs oracle (pos, vel, rho): {errs}")
+    assert errs["all_f64"][0] <= 1e-7
+    assert errs["all_f64"][0] * 10 <= errs["production"][0]
