@@ -274,7 +274,9 @@ sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in,
  * Along periodic components (p->period) pairs take the nearest image.
  * Arithmetic is FP32 on cell-relative FP32 positions (Section 5.1, precision
  * paragraph).  Per-block maxima of |ace| and visc over fluid targets and the
- * interaction count go to the workspace for sph_reduce_dt. */
+ * interaction count go to the workspace for sph_reduce_dt.  n must be below
+ * 2^28 and the grid below 2^30 cells (the walk addresses the view and the
+ * cell ranges with 32-bit byte offsets), else SPH_E_ARG. */
 sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s,
                         const uint32_t* key, const uint32_t* cell_start,
                         float* ace, float* arho, float* visc,

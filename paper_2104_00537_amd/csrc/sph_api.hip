@@ -229,11 +229,18 @@ sph_status sph_bin_cells(const sph_params* p, int64_t n, const sph_state* in, sp
                                      ws, (hipStream_t)stream));
 }
 
+// The interaction walk addresses the views and the cell ranges with 32-bit
+// byte offsets.
+static bool walk_size_ok(const sph_params* p, int64_t n) {
+  const uint64_t cells = (uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2];
+  return n < ((int64_t)1 << 28) && cells < ((uint64_t)1 << 30);
+}
+
 sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, const uint32_t* key,
                         const uint32_t* cell_start, float* ace, float* arho, float* visc,
                         uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
                         void* stream) {
-  if (!params_ok(p) || !n_ok(n) || !cell_start || !ws) return SPH_E_ARG;
+  if (!params_ok(p) || !n_ok(n) || !cell_start || !ws || !walk_size_ok(p, n)) return SPH_E_ARG;
   if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
   // none, the FP64 diagnostic count and/or reused cells, or one
   // precision-study arm alone
@@ -453,7 +460,7 @@ sph_status sph_batch_interact(const sph_batch* b, const sph_state* s, const uint
                               const uint32_t* cell_start, float* ace, float* arho, float* visc,
                               uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
                               void* stream) {
-  if (!batch_ok(b) || !cell_start || !ws) return SPH_E_ARG;
+  if (!batch_ok(b) || !cell_start || !ws || b->key_cells >= ((int64_t)1 << 30)) return SPH_E_ARG;
   if (flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS) return SPH_E_ARG;
   if (b->n_total > 0 && (!state_ok(s, true) || !key || !ace || !arho || f64_state(s)))
     return SPH_E_ARG;

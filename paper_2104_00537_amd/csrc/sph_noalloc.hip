@@ -88,6 +88,7 @@ extern "C" sph_status sph_interact_noalloc(const sph_params* p, int64_t n, const
                                            float* ace, float* arho, float* visc,
                                            uint32_t* nbr_count, uint32_t flags, void* stream) {
   if (!params_ok(p) || !cell_start) return SPH_E_ARG;
+  if ((uint64_t)p->ncell[0] * p->ncell[1] * p->ncell[2] >= ((uint64_t)1 << 30)) return SPH_E_ARG;
   if (n < 0 || n > kNaMaxN) return SPH_E_ARG;
   // the view is built from the state: not with modified DBC, whose wall
   // entries come from sph_mdbc, nor on reused cells

@@ -196,43 +196,60 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
 }
 
 // ---------------------------------------------------------- gather walk --
-// One group of 4 consecutive candidates j..j+3 of a row for one target lane:
-// the candidate positions are loaded together, tested, then the velocities of
-// the hits are loaded together and their pair terms accumulated.  TAIL masks
-// candidates at or past j1 (the views are padded, so the loads stay in
-// bounds).  Along x the views hold fixed-point offsets (units of
+// Element k of an array at a uniform base, addressed by a 32-bit byte offset
+// (k * sizeof(T) < 2^32, which the calls' size limits keep): the load then
+// takes the base from scalar registers and the offset from one vector
+// register, with no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* __restrict__ base, uint32_t k) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     (uint32_t)(k * (uint32_t)sizeof(T)));
+}
+// The element U places after byte offset o (U a compile-time constant, folded
+// into the load's immediate offset).
+template <int U, typename T>
+__device__ __forceinline__ const T& at_byte(const T* __restrict__ base, uint32_t o) {
+  return *(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o) + U);
+}
+
+// One group of NU (4, 2 or 1) consecutive candidates j..j+NU-1 of a row for
+// one target lane, all before the row's end j1 (o = 16 j and o1 = 16 j1 are
+// byte offsets into the views: 32 bits, which the calls' limit of n < 2^28
+// keeps exact): the candidate positions are loaded together, tested, then the
+// velocities of the hits are loaded together and their pair terms
+// accumulated.  Along x the views hold fixed-point offsets (units of
 // kFrameCells*cs / 2^32, periodic over kFrameCells cells): the 32-bit
 // difference of two offsets, read as signed, is x_a - x_b exactly modulo the
 // period, which exceeds twice the reach of the stencil.  Along y and z the
 // offsets are cell-relative and (ys, zs) carry the row's cell shift.  Wall
 // targets skip wall candidates (Eq. 36).
-template <int DIM, bool DIAG, bool EQM, bool GEN, bool PER, bool TAIL>
+template <int DIM, bool DIAG, bool EQM, bool GEN, bool PER, int NU = 4>
 __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64_t i,
                                              uint32_t xa, float ys, float zs,
-                                             const TargetData& T, uint32_t j, uint32_t j1,
+                                             const TargetData& T, uint32_t o,
                                              const float4* __restrict__ pr,
                                              const float4* __restrict__ vp,
                                              const double* pa64,
                                              const double* __restrict__ pos64, PairAcc& acc,
                                              uint32_t& c64) {
-  const float4* q = pr + j;
-  float4 pb[4];
+  float4 pb[NU];
+  pb[0] = at_byte<0>(pr, o);
+  if (NU > 1) pb[1 % NU] = at_byte<1>(pr, o);
+  if (NU > 2) pb[2 % NU] = at_byte<2>(pr, o);
+  if (NU > 3) pb[3 % NU] = at_byte<3>(pr, o);
+  bool hit[NU];
+  float dxs[NU], dys[NU], dzs[NU], r2s[NU];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) pb[u] = q[u];
-  bool hit[4];
-  float dxs[4], dys[4], dzs[4], r2s[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < NU; ++u) {
     dxs[u] = (float)(int32_t)(xa - __float_as_uint(pb[u].x)) * kp.unit_x_f;
     dys[u] = ys - pb[u].y;
     dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
     r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
     hit[u] = (T.fluid || pb[u].w > 0.f) && r2s[u] < kp.support2_f;
-    if (TAIL) hit[u] = hit[u] && j + u < j1;
     if (DIAG) {
-      const uint32_t jj = j + u;
+      const uint32_t jj = (o >> 4) + u;
       // (pb.w == 0: a particle excluded by a view refresh, no neighbour)
-      if (jj < j1 && (int64_t)jj != i && (T.fluid || pb[u].w > 0.f) && pb[u].w != 0.f) {
+      if ((int64_t)jj != i && (T.fluid || pb[u].w > 0.f) && pb[u].w != 0.f) {
         double r2d = 0.0;
         for (int d = 0; d < DIM; ++d) {
           double e = __dsub_rn(pa64[d], pos64[d * n + jj]);
@@ -247,13 +264,13 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
       }
     }
   }
-  const float4* qv = vp + j;
-  float4 vb[4];
+  float4 vb[NU];
+  if (hit[0]) vb[0] = at_byte<0>(vp, o);
+  if (NU > 1 && hit[1 % NU]) vb[1 % NU] = at_byte<1>(vp, o);
+  if (NU > 2 && hit[2 % NU]) vb[2 % NU] = at_byte<2>(vp, o);
+  if (NU > 3 && hit[3 % NU]) vb[3 % NU] = at_byte<3>(vp, o);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-    if (hit[u]) vb[u] = qv[u];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < NU; ++u)
     if (hit[u])
       pair_terms<DIM, EQM, GEN>(kp, T, dxs[u], dys[u], dzs[u], r2s[u], pb[u].w, vb[u], acc);
 }
@@ -267,8 +284,8 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
 // only |x_ab| < sqrt(4h^2 - e_y^2 - e_z^2) can hold a neighbour (rows with a
 // negative radicand are skipped).  The cut uses a support enlarged by 1e-4
 // relative, far above the FP32 error of the offsets, so that no pair within
-// 2h is ever cut.  Each range runs as whole groups of 4 and one masked tail
-// group.
+// 2h is ever cut.  Each range runs as whole groups of 4, then a group of 2
+// and a group of 1 for its last candidates.
 //
 // Periodic components (PER kernels only, Section 2.7): a row index along
 // y or z past either end wraps to the other end (the row's shift (ys, zs)
@@ -357,14 +374,22 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
     const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
     // the candidates of key cells [c0, c1] of the row, with target x bits xv
     auto walk = [&](int c0, int c1, uint32_t xv) {
-      const uint32_t j0 = cstart[row + c0], j1 = cstart[row + c1 + 1];
-      uint32_t j = j0;
-      for (; j + 4 <= j1; j += 4)
-        gather_group<DIM, DIAG, EQM, GEN, PER, false>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
-                                                      pa64, pos64, acc, c64);
-      if (j < j1)
-        gather_group<DIM, DIAG, EQM, GEN, PER, true>(kp, n, i, xv, ys, zs, T, j, j1, pr, vp,
-                                                     pa64, pos64, acc, c64);
+      // byte offsets of the range in the views
+      uint32_t o = at32(cstart, row + c0) * 16u;
+      const uint32_t o1 = at32(cstart, row + c1 + 1) * 16u;
+      for (; o + 64u <= o1; o += 64u)
+        gather_group<DIM, DIAG, EQM, GEN, PER>(kp, n, i, xv, ys, zs, T, o, pr, vp, pa64, pos64,
+                                               acc, c64);
+      // the last 0-3 candidates as a group of 2 and a group of 1 (a masked
+      // group of 4 would test up to 3 slots past the range)
+      if (o + 32u <= o1) {
+        gather_group<DIM, DIAG, EQM, GEN, PER, 2>(kp, n, i, xv, ys, zs, T, o, pr, vp, pa64,
+                                                  pos64, acc, c64);
+        o += 32u;
+      }
+      if (o < o1)
+        gather_group<DIM, DIAG, EQM, GEN, PER, 1>(kp, n, i, xv, ys, zs, T, o, pr, vp, pa64,
+                                                  pos64, acc, c64);
     };
     if (perx) {
       if (x0 < 0) {  // cells at the far end, one period below
