@@ -77,12 +77,15 @@ enum {
                                in no body's range, a body whose particles are
                                not all present, body counts summing above n,
                                or a singular inertia */
-  SPH_ERR_MARGIN = 16u      /* an interaction or shifting with
+  SPH_ERR_MARGIN = 16u,     /* an interaction or shifting with
                                SPH_INTERACT_REUSE_CELLS after particles moved
                                half a cell or more since the binning, or one
                                without that flag after particles moved at all
                                since the binning (a predictor ran): neighbours
                                may have been missed */
+  SPH_ERR_LIST = 32u        /* sph_interact_list with a list built on another
+                               binning: the pass walked the cells instead (the
+                               results are right, the list was not used) */
 };
 
 /* flags of sph_interact */
@@ -307,6 +310,62 @@ sph_status sph_interact_noalloc(const sph_params* p, int64_t n, const sph_state*
                                 const uint32_t* key, const uint32_t* cell_start, float* ace,
                                 float* arho, float* visc, uint32_t* nbr_count, uint32_t flags,
                                 void* stream);
+
+/* Neighbour lists (Section 2.3 sums, Section 5.1 NL): per target particle,
+ * the candidates of its cells that lie within the list radius 2h (1 + 1e-4)
+ * + skin of it, found by one walk of the cells after sph_bin_cells
+ * (sph_build_list) and replayed by both interactions of a symplectic step
+ * (sph_interact_list): the pass at state n on the binning's view, and the
+ * pass at n+1/2 after sph_refresh_view.  A pair within 2h at n+1/2 was
+ * within 2h + 2 delta at the binning (delta the largest displacement since,
+ * which the predictor records), so while 2 delta stays within the skin the
+ * list holds every pair.  The replay gives the pairs, sums and counts of
+ * sph_interact on the same view bit for bit (same FP32 test and pair terms,
+ * same order); it only runs the wavefront's lanes through their own lists
+ * instead of through common cell steps.  Default formulation only (Wendland
+ * kernel, artificial viscosity, ddt 0 or 1, DBC walls, no floating bodies or
+ * periodic components) and n below 2^28; else SPH_E_ARG.
+ *
+ * The list is a caller-owned DEVICE buffer of sph_list_bytes(p, n) bytes (or
+ * less: a smaller buffer holds fewer chunks per target, and targets whose
+ * chunks do not fit walk their cells in both passes). */
+size_t sph_list_bytes(const sph_params* p, int64_t n);
+
+/* flags of sph_build_list */
+enum {
+  /* skin = max(skin argument, the skin that the last sph_interact_list with
+   * SPH_INTERACT_REUSE_CELLS on this workspace asked for: 1.5 times twice the
+   * displacement it saw), at most half a cell */
+  SPH_LIST_ADAPTIVE_SKIN = 1u
+};
+
+/* Builds the list of the state that the last sph_bin_cells on this workspace
+ * sorted (its view, key and cell_start), with the given skin (metres, >= 0;
+ * see SPH_LIST_ADAPTIVE_SKIN).  Records the binning it belongs to. */
+sph_status sph_build_list(const sph_params* p, int64_t n, const sph_state* s,
+                          const uint32_t* key, const uint32_t* cell_start, double skin,
+                          uint32_t flags, void* list, size_t list_bytes, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* sph_interact over a list from sph_build_list (same list_bytes): outputs
+ * and workspace partials as sph_interact's.  flags: SPH_DIAG_COUNT_F64,
+ * SPH_INTERACT_REUSE_CELLS (the pass after sph_refresh_view: if twice the
+ * displacement exceeds the list's skin, every target walks its cells as
+ * sph_interact with that flag does -- same results -- and the workspace
+ * counts the fallback), SPH_INTERACT_ONE_LANE (no effect: one lane per
+ * target).  A list built on another binning is not used (the pass walks the
+ * cells) and sets SPH_ERR_LIST. */
+sph_status sph_interact_list(const sph_params* p, int64_t n, const sph_state* s,
+                             const uint32_t* key, const uint32_t* cell_start, const void* list,
+                             size_t list_bytes, float* ace, float* arho, float* visc,
+                             uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* The number of sph_interact_list passes with SPH_INTERACT_REUSE_CELLS on this
+ * workspace that walked the cells because the displacement exceeded the
+ * skin (or whose list was stale).  Synchronises the device.  Negative
+ * sph_status on failure. */
+int64_t sph_list_walks(const void* ws);
 
 /* Rewrites the interaction view that sph_bin_cells left in the workspace
  * from the state's current positions, velocities and densities, keeping the

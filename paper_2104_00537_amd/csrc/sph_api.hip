@@ -267,6 +267,73 @@ sph_status sph_interact(const sph_params* p, int64_t n, const sph_state* s, cons
                                     ws, (hipStream_t)stream));
 }
 
+// ------------------------------------------------------- neighbour lists --
+// The list kernels run the default formulation (the production pass).
+static bool list_params_ok(const sph_params* p, int64_t n) {
+  return params_ok(p) && n_ok(n) && walk_size_ok(p, n) && p->kernel == 0 &&
+         p->viscosity == 0 && p->ddt != 2 && p->floating == 0 && p->boundary == 0 &&
+         !(p->period[0] > 0.0) && !(p->period[1] > 0.0) && !(p->period[2] > 0.0);
+}
+
+// Chunks per target that a list buffer of `bytes` holds (0: too small).
+static int64_t list_cap(int64_t n, size_t bytes) {
+  const ListLayout L0 = list_layout(n, 0);
+  if (bytes < L0.total) return 0;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const int64_t cap = (int64_t)((bytes - L0.total) / (8 * nn));
+  return cap < kListCap ? cap : kListCap;
+}
+
+size_t sph_list_bytes(const sph_params* p, int64_t n) {
+  if (!list_params_ok(p, n)) return 0;
+  return list_layout(n, kListCap).total;
+}
+
+sph_status sph_build_list(const sph_params* p, int64_t n, const sph_state* s,
+                          const uint32_t* key, const uint32_t* cell_start, double skin,
+                          uint32_t flags, void* list, size_t list_bytes, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!list_params_ok(p, n) || !cell_start || !ws || !list) return SPH_E_ARG;
+  if (flags & ~(uint32_t)SPH_LIST_ADAPTIVE_SKIN) return SPH_E_ARG;
+  if (!(skin >= 0.0) || !(skin < 0.5 * p->cell_size)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  const int64_t cap = list_cap(n, list_bytes);
+  if (cap < 1) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state s0 = n > 0 ? *s : sph_state{};
+  return hip_status(launch_build_list(make_kparams(*p), n, s0, key, cell_start, (float)skin,
+                                      (flags & SPH_LIST_ADAPTIVE_SKIN) != 0, list, cap, ws,
+                                      (hipStream_t)stream));
+}
+
+sph_status sph_interact_list(const sph_params* p, int64_t n, const sph_state* s,
+                             const uint32_t* key, const uint32_t* cell_start, const void* list,
+                             size_t list_bytes, float* ace, float* arho, float* visc,
+                             uint32_t* nbr_count, uint32_t flags, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!list_params_ok(p, n) || !cell_start || !ws || !list) return SPH_E_ARG;
+  if (flags & ~(uint32_t)(SPH_DIAG_COUNT_F64 | SPH_INTERACT_REUSE_CELLS | SPH_INTERACT_ONE_LANE))
+    return SPH_E_ARG;
+  if ((flags & SPH_INTERACT_REUSE_CELLS) && !periodic_reach_ok(p, p->cell_div + 1))
+    return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
+  const int64_t cap = list_cap(n, list_bytes);
+  if (cap < 1) return SPH_E_ARG;
+  if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
+  sph_state s0 = n > 0 ? *s : sph_state{};
+  return hip_status(launch_interact_list(make_kparams(*p), n, s0, key, cell_start, list, cap, ace,
+                                         arho, visc, nbr_count, flags, ws,
+                                         (hipStream_t)stream));
+}
+
+int64_t sph_list_walks(const void* ws) {
+  if (!ws) return SPH_E_ARG;
+  WsHeader h{};
+  if (hipDeviceSynchronize() != hipSuccess) return SPH_E_HIP;
+  if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return SPH_E_HIP;
+  return (int64_t)h.list_walks;
+}
+
 sph_status sph_refresh_view(const sph_params* p, int64_t n, sph_state* s, const uint32_t* key,
                             void* ws, size_t ws_bytes, void* stream) {
   if (!params_ok(p) || !n_ok(n) || !ws) return SPH_E_ARG;

@@ -10,11 +10,13 @@ namespace sph {
 // (a new binning also restarts the record of the largest displacement)
 __global__ void k_cell_keys(KParams kp, int64_t n, const double* __restrict__ pos,
                             const uint8_t* __restrict__ type, uint32_t* __restrict__ key,
-                            uint32_t* __restrict__ disp) {
+                            uint32_t* __restrict__ disp, WsHeader* __restrict__ hdr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (i == 0)
+  if (i == 0) {
     for (int k = 0; k < kDispSlots; ++k) disp[k] = 0u;
+    hdr->bin_gen = hdr->bin_gen + 1u;
+  }
   key[i] = cell_key_local(kp, pos, type, n, i);
 }
 
@@ -404,7 +406,8 @@ hipError_t launch_bin_cells(const KParams& kp, int64_t n, const sph_state& in, s
   const unsigned gridn = (unsigned)((n + kBlock - 1) / kBlock);
   if (n > 0) {
     hipLaunchKernelGGL(k_cell_keys, dim3(gridn), dim3(kBlock), 0, st, kp, n, in.pos, in.type,
-                       ws_ptr<uint32_t>(ws, L.keyA), ws_ptr<uint32_t>(ws, L.disp));
+                       ws_ptr<uint32_t>(ws, L.keyA), ws_ptr<uint32_t>(ws, L.disp),
+                       ws_ptr<WsHeader>(ws, L.err));
     const hipError_t e = radix_sort(n, kp.ncell_total, key, perm, ws, st);
     if (e != hipSuccess) return e;
   }

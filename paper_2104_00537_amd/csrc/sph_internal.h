@@ -73,8 +73,48 @@ struct WsHeader {
   uint32_t err;      // SPH_ERR_* bits
   uint32_t nred;     // BlockRed entries written by the last interaction pass
   uint32_t nwall;    // wall particles listed by the last sph_mdbc (its work list)
+  uint32_t bin_gen;  // binnings so far (modulo 2^32): a neighbour list records
+                     // the binning it was built on
+  uint32_t list_walks;  // list passes that walked the cells instead (every
+                        // target: the displacement exceeded the list's skin)
+  uint32_t skin_hint;   // bits of the skin the last list pass on reused
+                        // cells asks for (a float: 1.5 times twice the
+                        // displacement it saw)
+  uint32_t pad[58];
+};
+
+// ------------------------------------------------------- neighbour lists --
+// A neighbour list (sph_build_list) holds, per target, the candidates of its
+// cells within the list radius as chunks: x = first candidate (sorted index),
+// y = a mask of the kListSpan candidates from there (bit k: candidate x + k)
+// in its low bits and the row of the stencil in the high bits, (dy + 3) +
+// 7 (dz + 3).  Chunks follow the stencil's row order, ascending within a row.
+constexpr int kListSpan = 26;
+constexpr uint32_t kListSpanMask = (1u << kListSpan) - 1u;
+constexpr int kListCap = 40;              // chunks per target
+constexpr uint32_t kListWalk = 0xffffffffu;  // count of a target whose chunks did not fit
+
+struct ListHeader {
+  float skin;        // the list radius is (2h (1 + 1e-4) + skin)
+  uint32_t bin_gen;  // the binning the list was built on
+  uint32_t cap;      // chunks per target in this buffer
   uint32_t pad[61];
 };
+
+struct ListLayout {
+  size_t header, count, chunks, total;
+};
+
+inline ListLayout list_layout(int64_t n, int64_t cap) {
+  ListLayout L{};
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  size_t off = 0;
+  L.header = off; off += 256;
+  L.count = off; off = (off + 4 * nn + 255) / 256 * 256;
+  L.chunks = off; off += 8 * nn * (size_t)cap;
+  L.total = off;
+  return L;
+}
 
 // The largest distance a particle moved since the last binning, kept as the
 // bits of non-negative floats in kDispSlots words (blocks record into the

@@ -48,6 +48,14 @@ hipError_t launch_interact_on(const KParams& kp, int64_t n, const sph_state& s,
                               float* arho, float* visc, uint32_t* nbr, uint32_t flags,
                               const InteractScratch& w, hipStream_t st);
 bool params_ok(const sph_params* p);
+hipError_t launch_build_list(const KParams& kp, int64_t n, const sph_state& s,
+                             const uint32_t* key, const uint32_t* cell_start, float skin_min,
+                             bool adaptive, void* list, int64_t cap, void* ws, hipStream_t st);
+hipError_t launch_interact_list(const KParams& kp, int64_t n, const sph_state& s,
+                                const uint32_t* key, const uint32_t* cell_start,
+                                const void* list, int64_t cap, float* ace, float* arho,
+                                float* visc, uint32_t* nbr, uint32_t flags, void* ws,
+                                hipStream_t st);
 hipError_t launch_reduce_dt(const KParams& kp, int64_t n, double* dt, uint64_t* interactions,
                             float* maxima, void* ws, hipStream_t st);
 hipError_t launch_symplectic(const KParams& kp, int64_t n, int phase, const double* dt, double* t,

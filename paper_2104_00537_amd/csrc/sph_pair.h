@@ -72,7 +72,8 @@ __device__ __forceinline__ void pair_terms(const KParams& kp, const TargetData& 
   const bool fb = pbw > 0.f;
   const float rhob = fabsf(pbw);
   const float dvx = a.vx - vb.x, dvy = a.vy - vb.y, dvz = DIM == 3 ? a.vz - vb.z : 0.f;
-  const float vr = dvx * dx + dvy * dy + (DIM == 3 ? dvz * dz : 0.f);
+  // (explicit fused multiply-adds: the same bits in every kernel)
+  const float vr = DIM == 3 ? fmaf(dvz, dz, fmaf(dvy, dy, dvx * dx)) : fmaf(dvy, dy, dvx * dx);
   const float s = __builtin_amdgcn_sqrtf(r2);
   float g;
   if (!GEN || kp.kernel == 0) {
@@ -196,6 +197,27 @@ __device__ __forceinline__ void write_zero(int64_t n, int64_t a, float* ace, flo
 }
 
 // ---------------------------------------------------------- gather walk --
+// r_ab = (dx, dy, dz) and |r_ab|^2 of candidate pb for a target with
+// fixed-point x bits xa and row-shifted offsets (ys, zs) (see gather_group):
+// one form for the cell walk and the neighbour-list replay, so that both
+// take the same FP32 decisions.
+// Written with explicit fused multiply-adds, so that no compiler contraction
+// choice can differ between the kernels that inline it.
+template <int DIM>
+__device__ __forceinline__ float pair_geom(const KParams& kp, uint32_t xa, float ys, float zs,
+                                           const float4& pb, float& dx, float& dy, float& dz) {
+  dx = (float)(int32_t)(xa - __float_as_uint(pb.x)) * kp.unit_x_f;
+  dy = ys - pb.y;
+  dz = DIM == 3 ? zs - pb.z : 0.f;
+  return DIM == 3 ? fmaf(dz, dz, fmaf(dy, dy, dx * dx)) : fmaf(dy, dy, dx * dx);
+}
+
+// The target's offset along y or z shifted to the row d cells away: p - d cs
+// as one fused multiply-add (the same bits in every kernel).
+__device__ __forceinline__ float row_shift(float p, int d, float cs) {
+  return fmaf(-(float)d, cs, p);
+}
+
 // Element k of an array at a uniform base, addressed by a 32-bit byte offset
 // (k * sizeof(T) < 2^32, which the calls' size limits keep): the load then
 // takes the base from scalar registers and the offset from one vector
@@ -241,10 +263,7 @@ __device__ __forceinline__ void gather_group(const KParams& kp, int64_t n, int64
   float dxs[NU], dys[NU], dzs[NU], r2s[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    dxs[u] = (float)(int32_t)(xa - __float_as_uint(pb[u].x)) * kp.unit_x_f;
-    dys[u] = ys - pb[u].y;
-    dzs[u] = DIM == 3 ? zs - pb[u].z : 0.f;
-    r2s[u] = dxs[u] * dxs[u] + dys[u] * dys[u] + dzs[u] * dzs[u];
+    r2s[u] = pair_geom<DIM>(kp, xa, ys, zs, pb[u], dxs[u], dys[u], dzs[u]);
     hit[u] = (T.fluid || pb[u].w > 0.f) && r2s[u] < kp.support2_f;
     if (DIAG) {
       const uint32_t jj = (o >> 4) + u;
@@ -371,7 +390,7 @@ __device__ __forceinline__ void gather_walk(const KParams& kp, uint32_t cbase, i
     x1 = x1 > xhi ? xhi : x1;
     const uint32_t row =
         cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
-    const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
+    const float ys = row_shift(pa.y, dy, cs), zs = row_shift(pa.z, dz, cs);
     // the candidates of key cells [c0, c1] of the row, with target x bits xv
     auto walk = [&](int c0, int c1, uint32_t xv) {
       // byte offsets of the range in the views

@@ -24,7 +24,8 @@ from . import sph as S
 class Simulation:
     def __init__(self, case, device="cuda", cell_div: Optional[int] = None, flags: int = 0,
                  integrator: str = "symplectic", verlet_ns: int = 40,
-                 reuse_cells: Optional[bool] = None, f64_state: bool = False):
+                 reuse_cells: Optional[bool] = None, f64_state: bool = False,
+                 neighbour_list: bool = False, list_skin: Optional[float] = None):
         """f64_state: the all-FP64 arm of the precision study -- velocities
         and densities held and advanced in FP64, every pair evaluated in FP64
         (SPH_INTERACT_F64_STATE), FP64 rates."""
@@ -103,6 +104,30 @@ class Simulation:
                              "precision-study arm and periodic components of at least "
                              "2 (cell_div + 1) + 1 cells")
         self.reuse_cells = can_reuse if reuse_cells is None else bool(reuse_cells)
+        # neighbour lists (sph_build_list / sph_interact_list) for both passes
+        # of a reused-cells step: default formulation, DBC walls, no floating
+        # bodies, shifting or periodic components, one lane per target.  Off
+        # unless asked for: on the 1.32M-particle dam break a step with lists
+        # (build 0.37 ms, passes 0.53 and 0.59 ms) is slower than the cell
+        # walk (passes 0.46 and 0.47 ms)
+        list_ok = (self.reuse_cells and (self.flags & ~S.SPH_INTERACT_ONE_LANE) in
+                   (0, S.SPH_DIAG_COUNT_F64) and int(getattr(cp, "kernel", 0)) == 0
+                   and int(getattr(cp, "viscosity", 0)) == 0 and int(cp.ddt) != 2
+                   and int(getattr(cp, "floating", 0)) == 0 and not per_cells
+                   and not getattr(case, "bodies", None)
+                   and float(getattr(cp, "shift_coef", 0.0)) == 0.0)
+        if neighbour_list and not list_ok:
+            raise ValueError("neighbour lists need the reused-cells step with the default "
+                             "formulation, DBC walls and no floating bodies, shifting or "
+                             "periodic components")
+        self.neighbour_list = bool(neighbour_list)
+        self.list = None
+        if self.neighbour_list:
+            self.list = torch.empty(S.sph_list_bytes(self.params, n), dtype=torch.uint8,
+                                    device=dev)
+            # the smallest skin; each step takes at least 1.5 times twice the
+            # last step's largest half-step displacement (SPH_LIST_ADAPTIVE_SKIN)
+            self.list_skin = 0.01 * float(cp.h) if list_skin is None else float(list_skin)
         self.bodies = None
         if getattr(case, "bodies", None):
             if integrator != "symplectic":
@@ -198,8 +223,15 @@ class Simulation:
         call = self._call(stream, timing)
         call("bin_cells", S.sph_bin_cells, P, n, a, b, self.key, self.perm, self.cell_start,
              self.ws, stream=stream)
-        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
-             self.ws, flags=self.flags, stream=stream)
+        if self.neighbour_list:
+            call("build_list", S.sph_build_list, P, n, b, self.key, self.cell_start,
+                 self.list_skin, self.list, self.ws, flags=S.SPH_LIST_ADAPTIVE_SKIN,
+                 stream=stream)
+            call("interact", S.sph_interact_list, P, n, b, self.key, self.cell_start, self.list,
+                 self.ace, self.arho, self.ws, flags=self.flags, stream=stream)
+        else:
+            call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace,
+                 self.arho, self.ws, flags=self.flags, stream=stream)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt, self.ws,
              interactions=self.interactions, stream=stream)
         call("symplectic", S.sph_symplectic_step, P, n, 0, self.dt, self.t, s0, b, self.ace,
@@ -208,8 +240,14 @@ class Simulation:
             call("floating", S.sph_floating_step, P, n, 0, self.dt, self.bodies, s0, b, self.ace,
                  self.ws, stream=stream)
         call("refresh_view", S.sph_refresh_view, P, n, b, self.key, self.ws, stream=stream)
-        call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace, self.arho,
-             self.ws, flags=self.flags | S.SPH_INTERACT_REUSE_CELLS, stream=stream)
+        if self.neighbour_list:
+            call("interact", S.sph_interact_list, P, n, b, self.key, self.cell_start, self.list,
+                 self.ace, self.arho, self.ws, flags=self.flags | S.SPH_INTERACT_REUSE_CELLS,
+                 stream=stream)
+        else:
+            call("interact", S.sph_interact, P, n, b, self.key, self.cell_start, self.ace,
+                 self.arho, self.ws, flags=self.flags | S.SPH_INTERACT_REUSE_CELLS,
+                 stream=stream)
         call("reduce_dt", S.sph_reduce_dt, P, n, self.dt_half, self.ws,
              interactions=self.interactions, stream=stream)
         call("symplectic", S.sph_symplectic_step, P, n, 1, self.dt, self.t, s0, b, self.ace,

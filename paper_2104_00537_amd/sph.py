@@ -22,6 +22,8 @@ SPH_OK, SPH_E_ARG, SPH_E_WORKSPACE, SPH_E_HIP = 0, -1, -2, -3
 SPH_FLUID, SPH_BOUND_FIXED, SPH_BOUND_MOVING, SPH_FLOATING, SPH_EXCLUDED = 0, 1, 2, 3, 0x80
 SPH_ERR_NONFINITE, SPH_ERR_EXCLUDED, SPH_ERR_DT_FLOOR, SPH_ERR_FLOATING = 1, 2, 4, 8
 SPH_ERR_MARGIN = 16
+SPH_ERR_LIST = 32
+SPH_LIST_ADAPTIVE_SKIN = 1
 SPH_MAX_BODIES = 64
 SPH_DIAG_COUNT_F64 = 1
 SPH_INTERACT_F64 = 2
@@ -31,7 +33,8 @@ SPH_INTERACT_ONE_LANE = 16
 SPH_INTERACT_F64_STATE = 32
 
 EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_interact",
-           "sph_interact_noalloc", "sph_reduce_dt",
+           "sph_interact_noalloc", "sph_list_bytes", "sph_build_list", "sph_interact_list",
+           "sph_list_walks", "sph_reduce_dt",
            "sph_symplectic_step", "sph_verlet_step", "sph_mdbc", "sph_floating_step",
            "sph_shifting",
            "sph_read_error", "sph_clear_error", "sph_strerror",
@@ -103,6 +106,16 @@ def _load() -> C.CDLL:
     L.sph_interact_noalloc.restype = C.c_int32
     L.sph_interact_noalloc.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, VP, VP,
                                        VP, C.c_uint32, VP]
+    L.sph_list_bytes.restype = C.c_size_t
+    L.sph_list_bytes.argtypes = [P(SphParams), C.c_int64]
+    L.sph_build_list.restype = C.c_int32
+    L.sph_build_list.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, C.c_double,
+                                 C.c_uint32, VP, C.c_size_t, VP, C.c_size_t, VP]
+    L.sph_interact_list.restype = C.c_int32
+    L.sph_interact_list.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, VP, C.c_size_t,
+                                    VP, VP, VP, VP, C.c_uint32, VP, C.c_size_t, VP]
+    L.sph_list_walks.restype = C.c_int64
+    L.sph_list_walks.argtypes = [VP]
     L.sph_refresh_view.restype = C.c_int32
     L.sph_refresh_view.argtypes = [P(SphParams), C.c_int64, P(SphState), VP, VP, C.c_size_t, VP]
     L.sph_reduce_dt.restype = C.c_int32
@@ -285,6 +298,35 @@ def sph_interact_noalloc(params: SphParams, n: int, s: DeviceState, key: torch.T
     _check(lib.sph_interact_noalloc(C.byref(params), int(n), C.byref(s.c()), _ptr(key),
                                     _ptr(cell_start), _ptr(ace), _ptr(arho), _ptr(visc), _ptr(nbr),
                                     int(flags), _stream(stream)), "sph_interact_noalloc")
+
+
+def sph_list_bytes(params: SphParams, n: int) -> int:
+    return int(lib.sph_list_bytes(C.byref(params), int(n)))
+
+
+def sph_build_list(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                   cell_start: torch.Tensor, skin: float, lst: torch.Tensor, ws: torch.Tensor,
+                   flags: int = 0, stream=None):
+    _check(lib.sph_build_list(C.byref(params), int(n), C.byref(s.c()), _ptr(key),
+                              _ptr(cell_start), float(skin), int(flags), _ptr(lst), lst.numel(),
+                              _ptr(ws), ws.numel(), _stream(stream)), "sph_build_list")
+
+
+def sph_interact_list(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
+                      cell_start: torch.Tensor, lst: torch.Tensor, ace: torch.Tensor,
+                      arho: torch.Tensor, ws: torch.Tensor, visc: Optional[torch.Tensor] = None,
+                      nbr: Optional[torch.Tensor] = None, flags: int = 0, stream=None):
+    _check(lib.sph_interact_list(C.byref(params), int(n), C.byref(s.c()), _ptr(key),
+                                 _ptr(cell_start), _ptr(lst), lst.numel(), _ptr(ace), _ptr(arho),
+                                 _ptr(visc), _ptr(nbr), int(flags), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "sph_interact_list")
+
+
+def sph_list_walks(ws: torch.Tensor) -> int:
+    v = int(lib.sph_list_walks(_ptr(ws)))
+    if v < 0:
+        _check(v, "sph_list_walks")
+    return v
 
 
 def sph_refresh_view(params: SphParams, n: int, s: DeviceState, key: torch.Tensor,
