@@ -316,7 +316,9 @@ def serving(args):
     out["stream"]["steps_mean"] = float(np.mean([r.steps for r in reqs]))
     cap_n = max(4 * max(r.n for r in reqs), args.serve_cap_particles)
     eng = V.BatchEngine(cap_particles=cap_n, cap_cells=args.serve_cap_cells,
-                        max_slots=args.serve_slots, device="cuda:0")
+                        max_slots=args.serve_slots, device="cuda:0",
+                        four_lanes=args.serve_four_lanes)
+    out["stream"]["four_lanes"] = bool(args.serve_four_lanes)
     # warm-up of the code paths (first kernel launches, graph capture)
     warm = V.make_stream(2, 1e6, seed=99, n_min=2000, n_max=3000, steps_min=4, steps_max=4)
     V.serve_batched(warm, eng)
@@ -527,6 +529,9 @@ def main():
                     help="run mode: steps between synchronisations (cost per chunk reported)")
     ap.add_argument("--oracle", action="store_true",
                     help="run mode: also run the CPU oracle over the same steps (2-D case)")
+    ap.add_argument("--neighbour-list", action="store_true",
+                    help="step mode: both passes replay per-target neighbour lists "
+                         "(sph_build_list / sph_interact_list) instead of walking the cells")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-verlet", action="store_true")
@@ -545,6 +550,9 @@ def main():
     ap.add_argument("--serve-n-min", type=int, default=2000)
     ap.add_argument("--serve-n-max", type=int, default=500_000)
     ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-four-lanes", action="store_true",
+                    help="batched leg: four lanes per target for slots of at most 131,072 "
+                         "particles (SPH_BATCH_FOUR_LANES)")
     ap.add_argument("--serve-cap-particles", type=int, default=6_000_000)
     ap.add_argument("--serve-cap-cells", type=int, default=120_000_000)
     args = ap.parse_args()
@@ -565,7 +573,7 @@ def main():
     from paper_2104_00537_amd.runner import Simulation
 
     case = workload(args.workload, args.cell_div, args.x_sub)
-    sim = Simulation(case, "cuda:0")
+    sim = Simulation(case, "cuda:0", neighbour_list=args.neighbour_list)
     print(f"[bench] {args.workload}: n={case.n} fluid={case.n_fluid} cells={case.params.ncell}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -618,9 +626,9 @@ def main():
     # algorithmic bytes of one interaction launch: per particle the view read
     # (2 x 16 B), ace + arho written (4 x 4 B), key and cell range reads (8 B)
     bytes_per_launch = case.n * (32 + 16 + 8)
-    kernel = "k_interact_gather"
+    kernel = "k_interact_list" if args.neighbour_list else "k_interact_gather"
     traffic = (measured_traffic(kernel, args.workload)
-               if (args.cell_div, args.x_sub) == (2, 4) else None)
+               if (args.cell_div, args.x_sub) == (2, 4) and not args.neighbour_list else None)
     res = {
         "metric": METRIC,
         "value": pairs / el,
@@ -636,7 +644,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_particles": case.n, "n_fluid": case.n_fluid,
                    "dp": case.params.dp, "h": case.params.h, "cell_div": args.cell_div,
-                   "x_sub": args.x_sub,
+                   "x_sub": args.x_sub, "neighbour_list": args.neighbour_list,
                    "parallelism": "single GPU", "positions": "fp64 state; fp32 offsets (fixed-point x, cell-relative y, z)"},
         "steps_per_s": args.steps / el,
         "interactions_per_step": pairs / args.steps,
@@ -648,7 +656,9 @@ def main():
                      "traffic_unit": "bytes/launch", "kernel": kernel,
                      "flops_per_launch": flops, "avg_launch_ms": phase_ms["interact"],
                      "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "hbm_algorithmic_GBs": bytes_per_launch / t_int / 1e9},
+                     "hbm_algorithmic_GBs": bytes_per_launch / t_int / 1e9,
+                     "hbm_frac": bytes_per_launch / t_int / 8e12,
+                     "hbm_measured_frac": (traffic / t_int / 8e12) if traffic else None},
     }
     print(f"[bench] timed {args.steps} steps: {pairs / el:.4g} interactions/s", file=sys.stderr,
           flush=True)

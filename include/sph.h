@@ -551,12 +551,17 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
 enum {
   /* every slot's particle range starts and ends at a multiple of 64 (whole
    * wavefronts): the interaction then runs a leaner kernel in which each
-   * wavefront lies in one slot, and a slot of at most 131,072 particles gets
-   * four lanes per target (as the single-case pass; the choice depends on
-   * the slot's own size only, so a case's results do not depend on the
-   * batch).  Pad a case's range with excluded particles (type SPH_EXCLUDED)
-   * to get it. */
-  SPH_BATCH_WAVE_ALIGNED = 1u
+   * wavefront lies in one slot.  Pad a case's range with excluded particles
+   * (type SPH_EXCLUDED) to get it. */
+  SPH_BATCH_WAVE_ALIGNED = 1u,
+  /* also an option of sph_batch_describe: in a wave-aligned batch, a slot of
+   * at most 131,072 particles gets four lanes per target (as the
+   * single-case pass for a small case), the others one.  The choice depends
+   * on the option and the slot's own size only, so a case's results do not
+   * depend on the other slots.  It shortens each target's chain of loads,
+   * which pays when the batch is too small to fill the GPU; when it fills
+   * the GPU, one lane per target does the same work in fewer instructions. */
+  SPH_BATCH_FOUR_LANES = 2u
 };
 
 typedef struct sph_batch {
@@ -581,9 +586,13 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * table stays valid while the slots keep their ranges.  Every slot must use
  * the same cell_div and the default formulation (kernel 0, viscosity 0, ddt
  * 0 or 1, boundary 0, no floating bodies, no periodic components);
- * otherwise SPH_E_ARG. */
+ * otherwise SPH_E_ARG.  options: 0 or SPH_BATCH_FOUR_LANES (else
+ * SPH_E_ARG); batch->flags gets SPH_BATCH_WAVE_ALIGNED when every range is
+ * whole wavefronts, and SPH_BATCH_FOUR_LANES when it was asked for and the
+ * batch is wave-aligned. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
-                              void* table_host, size_t table_bytes, sph_batch* batch);
+                              uint32_t options, void* table_host, size_t table_bytes,
+                              sph_batch* batch);
 
 /* Bytes of workspace for a batch (the single-case workspace of n_total
  * particles plus per-slot accumulators, motion and error words). */

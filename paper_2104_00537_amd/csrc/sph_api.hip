@@ -453,8 +453,10 @@ size_t sph_batch_table_bytes(int32_t n_slots) {
 }
 
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
-                              void* table_host, size_t table_bytes, sph_batch* batch) {
+                              uint32_t options, void* table_host, size_t table_bytes,
+                              sph_batch* batch) {
   if (!params || !offsets || !table_host || !batch) return SPH_E_ARG;
+  if (options & ~(uint32_t)SPH_BATCH_FOUR_LANES) return SPH_E_ARG;
   if (n_slots < 1 || n_slots > SPH_BATCH_MAX_SLOTS) return SPH_E_ARG;
   if (table_bytes < sph_batch_table_bytes(n_slots)) return SPH_E_ARG;
   if (offsets[0] != 0) return SPH_E_ARG;
@@ -481,16 +483,18 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   if (offsets[n_slots] >= ((int64_t)1 << 27)) return SPH_E_ARG;
   bool aligned = true;
   for (int s = 0; s <= n_slots; ++s) aligned = aligned && offsets[s] % 64 == 0;
-  // interaction lanes: with wave-aligned slots, four per target for a slot
-  // of at most kLanesMaxN particles (by its own size only), else one
+  // interaction lanes: with SPH_BATCH_FOUR_LANES and wave-aligned slots,
+  // four per target for a slot of at most kLanesMaxN particles (by its own
+  // size only), else one
+  const bool four = aligned && (options & SPH_BATCH_FOUR_LANES);
   int64_t lanes = 0;
   for (int s = 0; s < n_slots; ++s) {
-    tab[s].lpt = aligned && tab[s].n <= kLanesMaxN ? kMaxLanes : 1;
+    tab[s].lpt = four && tab[s].n <= kLanesMaxN ? kMaxLanes : 1;
     tab[s].loff = lanes;
     lanes += tab[s].n * tab[s].lpt;
   }
   batch->n_slots = n_slots;
-  batch->flags = aligned ? SPH_BATCH_WAVE_ALIGNED : 0u;
+  batch->flags = (aligned ? SPH_BATCH_WAVE_ALIGNED : 0u) | (four ? SPH_BATCH_FOUR_LANES : 0u);
   batch->lanes = (uint32_t)lanes;
   batch->cell_div = params[0].cell_div;
   batch->n_total = offsets[n_slots];

@@ -97,13 +97,18 @@ class BatchEngine:
 
     def __init__(self, cap_particles: int, cap_cells: int, max_slots: int = 256,
                  device="cuda", use_graph: bool = True, cell_div: int = 1,
-                 reuse_cells: bool = True, pad_slots: bool = True):
+                 reuse_cells: bool = True, pad_slots: bool = True, four_lanes: bool = False):
+        """four_lanes: slots of at most 131,072 particles take four lanes per
+        target in the interaction (SPH_BATCH_FOUR_LANES).  Off by default: on
+        a queued stream the batch fills the GPU, and one lane per target is
+        then faster (512-request stream: 3.26 against 3.08 solves/s)."""
         self.dev = torch.device(device)
         # one binning per step: the n+1/2 interaction reuses the cells of
         # state n (sph_batch_refresh_view, SPH_INTERACT_REUSE_CELLS); the
         # state then alternates between the two buffers, `cur` holding it
         self.reuse = bool(reuse_cells)
         self.pad = bool(pad_slots)
+        self.four_lanes = bool(four_lanes)
         self.cur = 0
         self.cap_n = int(cap_particles)
         self.cap_cells = int(cap_cells)
@@ -218,7 +223,7 @@ class BatchEngine:
             self.batch = None
             return
         params = [S.make_params(r.case.params) for r in new_slots]
-        b, host = S.sph_batch_describe(params, offsets)
+        b, host = S.sph_batch_describe(params, offsets, four_lanes=self.four_lanes)
         if b.key_cells + 1 > self.cell_start.numel():
             raise S.SphError("batch exceeds the cell capacity")
         self.table[: host.size] = torch.from_numpy(host).to(self.dev)

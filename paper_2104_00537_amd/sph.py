@@ -44,6 +44,7 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
            "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
 SPH_BATCH_MAX_SLOTS = 4096
 SPH_BATCH_WAVE_ALIGNED = 1
+SPH_BATCH_FOUR_LANES = 2
 SPH_NOALLOC_MAX_N = 2097152
 
 
@@ -143,8 +144,8 @@ def _load() -> C.CDLL:
     L.sph_batch_table_bytes.restype = C.c_size_t
     L.sph_batch_table_bytes.argtypes = [C.c_int32]
     L.sph_batch_describe.restype = C.c_int32
-    L.sph_batch_describe.argtypes = [P(SphParams), P(C.c_int64), C.c_int32, VP, C.c_size_t,
-                                     P(SphBatch)]
+    L.sph_batch_describe.argtypes = [P(SphParams), P(C.c_int64), C.c_int32, C.c_uint32, VP,
+                                     C.c_size_t, P(SphBatch)]
     L.sph_batch_workspace_bytes.restype = C.c_size_t
     L.sph_batch_workspace_bytes.argtypes = [P(SphBatch)]
     L.sph_batch_bin_cells.restype = C.c_int32
@@ -424,9 +425,9 @@ def sph_clear_error(ws: torch.Tensor, stream=None):
 
 
 # ------------------------------------------------------------------ batches
-def sph_batch_describe(params_list, offsets):
-    """Host-side slot table of a batch.  Returns (SphBatch without table,
-    table bytes as a uint8 numpy array)."""
+def sph_batch_describe(params_list, offsets, four_lanes: bool = False):
+    """Host-side slot table of a batch (four_lanes: SPH_BATCH_FOUR_LANES).
+    Returns (SphBatch without table, table bytes as a uint8 numpy array)."""
     import numpy as np
     ns = len(params_list)
     arr = (SphParams * ns)(*params_list)
@@ -436,7 +437,8 @@ def sph_batch_describe(params_list, offsets):
         raise SphError(f"sph_batch_table_bytes: bad slot count {ns}")
     host = np.zeros(nbytes, np.uint8)
     b = SphBatch()
-    _check(lib.sph_batch_describe(arr, offs, ns, host.ctypes.data_as(C.c_void_p), nbytes,
+    opts = SPH_BATCH_FOUR_LANES if four_lanes else 0
+    _check(lib.sph_batch_describe(arr, offs, ns, opts, host.ctypes.data_as(C.c_void_p), nbytes,
                                   C.byref(b)), "sph_batch_describe")
     return b, host
 

@@ -271,6 +271,30 @@ def test_batch_describe_sets_the_wave_alignment_flag(S):
         assert bool(b.flags & S.SPH_BATCH_WAVE_ALIGNED) == want, offs
 
 
+def test_batch_describe_lanes_per_slot(S):
+    """One lane per target unless SPH_BATCH_FOUR_LANES is asked for; then, in
+    a wave-aligned batch, four for each slot of at most 131,072 particles
+    (by its own size), one for larger slots."""
+    import ctypes as C
+    from paper_2104_00537_amd import cases
+    P = S.make_params(cases.dam_break_2d(dp=0.02).params)
+    small, big = 64 * 100, 64 * 2100  # 6,400 and 134,400 particles
+    offs = [0, small, small + big, 2 * small + big]
+    b, _ = S.sph_batch_describe([P, P, P], offs)
+    assert b.lanes == offs[-1] and not b.flags & S.SPH_BATCH_FOUR_LANES
+    b, _ = S.sph_batch_describe([P, P, P], offs, four_lanes=True)
+    assert b.flags & S.SPH_BATCH_FOUR_LANES and b.flags & S.SPH_BATCH_WAVE_ALIGNED
+    assert b.lanes == 4 * small + big + 4 * small
+    b, _ = S.sph_batch_describe([P, P], [0, 100, 228], four_lanes=True)  # not aligned
+    assert b.lanes == 228 and not b.flags & (S.SPH_BATCH_FOUR_LANES | S.SPH_BATCH_WAVE_ALIGNED)
+    ps = (S.SphParams * 1)(P)
+    o = (C.c_int64 * 2)(0, 64)
+    host = (C.c_uint8 * S.lib.sph_batch_table_bytes(1))()
+    bb = S.SphBatch()
+    assert S.lib.sph_batch_describe(ps, o, 1, 4, host, C.sizeof(host), C.byref(bb)) == S.SPH_E_ARG
+    assert S.lib.sph_batch_describe(ps, o, 1, 2, host, C.sizeof(host), C.byref(bb)) == S.SPH_OK
+
+
 def test_batch_rejects_formulation_options(S):
     """The batched path runs the default formulation only."""
     import dataclasses

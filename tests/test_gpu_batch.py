@@ -36,15 +36,15 @@ def _mix_cases():
     return out
 
 
-def _engine(cs, graph=False, reuse=True, pad=True):
+def _engine(cs, graph=False, reuse=True, pad=True, four=False):
     return V.BatchEngine(cap_particles=sum(V.padded(c.n) for c in cs) + 16,
                          cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
                          max_slots=8, device=DEV, use_graph=graph, reuse_cells=reuse,
-                         pad_slots=pad)
+                         pad_slots=pad, four_lanes=four)
 
 
-def _run_engine(cs, steps, graph, reuse=True, pad=True):
-    eng = _engine(cs, graph, reuse, pad)
+def _run_engine(cs, steps, graph, reuse=True, pad=True, four=False):
+    eng = _engine(cs, graph, reuse, pad, four)
     reqs = [V.Request(rid=k, case=c, steps=steps, arrival=0.0) for k, c in enumerate(cs)]
     eng.repack([], reqs)
     eng.run(steps)
@@ -53,17 +53,20 @@ def _run_engine(cs, steps, graph, reuse=True, pad=True):
     return [eng.slot_result(k) for k in range(len(cs))], errs, eng
 
 
-@pytest.mark.parametrize("reuse,pad", [(True, True), (False, True), (True, False)])
-def test_batch_alone_vs_mix_bit_identical(reuse, pad):
+@pytest.mark.parametrize("reuse,pad,four", [(True, True, False), (False, True, False),
+                                            (True, False, False), (True, True, True)])
+def test_batch_alone_vs_mix_bit_identical(reuse, pad, four):
     """pad: slots padded to whole wavefronts (the aligned kernel) or not (the
-    general kernel, wavefronts straddling slots)."""
+    general kernel, wavefronts straddling slots); four: four lanes per target
+    for the small slots (all of these)."""
     cs = _mix_cases()
     _say("mix of", [c.n for c in cs])
-    mix, errs, eng = _run_engine(cs, 7, graph=True, reuse=reuse, pad=pad)
+    mix, errs, eng = _run_engine(cs, 7, graph=True, reuse=reuse, pad=pad, four=four)
     assert not errs.any()
     assert bool(eng.batch.flags & S.SPH_BATCH_WAVE_ALIGNED) == pad
+    assert bool(eng.batch.flags & S.SPH_BATCH_FOUR_LANES) == four
     for k, c in enumerate(cs):
-        alone, e1, _ = _run_engine([c], 7, graph=False, reuse=reuse, pad=pad)
+        alone, e1, _ = _run_engine([c], 7, graph=False, reuse=reuse, pad=pad, four=four)
         assert not e1.any()
         for f in ("pos", "vel", "rho", "type"):
             assert np.array_equal(mix[k][f], alone[0][f]), (k, f)
@@ -95,10 +98,10 @@ def test_batch_matches_single_case_path(reuse):
         assert np.array_equal(b["type"], g["type"])
 
 
-@pytest.mark.parametrize("pad", [True, False])
-def test_batch_interaction_matches_oracle(pad):
+@pytest.mark.parametrize("pad,four", [(True, False), (False, False), (True, True)])
+def test_batch_interaction_matches_oracle(pad, four):
     cs = _mix_cases()
-    eng = _engine(cs, pad=pad)
+    eng = _engine(cs, pad=pad, four=four)
     reqs = [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)]
     eng.repack([], reqs)
     b = eng.batch
