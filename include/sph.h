@@ -84,8 +84,9 @@ enum {
                                since the binning (a predictor ran): neighbours
                                may have been missed */
   SPH_ERR_LIST = 32u        /* sph_interact_list with a list built on another
-                               binning: the pass walked the cells instead (the
-                               results are right, the list was not used) */
+                               binning or with another list_bytes: the pass
+                               walked the cells instead (the results are
+                               right, the list was not used) */
 };
 
 /* flags of sph_interact */
@@ -353,8 +354,8 @@ sph_status sph_build_list(const sph_params* p, int64_t n, const sph_state* s,
  * displacement exceeds the list's skin, every target walks its cells as
  * sph_interact with that flag does -- same results -- and the workspace
  * counts the fallback), SPH_INTERACT_ONE_LANE (no effect: one lane per
- * target).  A list built on another binning is not used (the pass walks the
- * cells) and sets SPH_ERR_LIST. */
+ * target).  A list built on another binning, or with another list_bytes,
+ * is not used (the pass walks the cells) and sets SPH_ERR_LIST. */
 sph_status sph_interact_list(const sph_params* p, int64_t n, const sph_state* s,
                              const uint32_t* key, const uint32_t* cell_start, const void* list,
                              size_t list_bytes, float* ace, float* arho, float* visc,

@@ -157,13 +157,14 @@ __global__ __launch_bounds__(kBlock) void k_interact_list(
     float* __restrict__ arho, float* __restrict__ visc, uint32_t* __restrict__ nbr,
     BlockRed* __restrict__ red, WsHeader* __restrict__ hdr, const uint32_t* __restrict__ disp,
     const uint32_t* __restrict__ count, const uint2* __restrict__ chunks,
-    const ListHeader* __restrict__ lh) {
+    const ListHeader* __restrict__ lh, uint32_t cap) {
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   float fmag = 0.f, vmax_out = 0.f;
   uint32_t cnt_out = 0, cnt_wall = 0, nfl = 0;
   const float skin = lh->skin;
-  const uint32_t cap = lh->cap;
-  const bool stale = lh->bin_gen != hdr->bin_gen;
+  // a list of another binning, or built for a buffer of another capacity,
+  // is not used
+  const bool stale = lh->bin_gen != hdr->bin_gen || lh->cap != cap;
   const float delta = read_displacement(disp);
   bool walk_all = stale;
   float cull2 = kp.support2_f * 1.0002f;
@@ -352,7 +353,7 @@ hipError_t launch_interact_list(const KParams& kp, int64_t n, const sph_state& s
 #define SPH_LIST(D, RW, G, PP, RU)                                                           \
   hipLaunchKernelGGL((k_interact_list<D, RW, G, PP, RU>), dim3(grid), dim3(kBlock), 0, st, kp, \
                      n, pr, vp, key, cell_start, s.type, s.pos, ace, arho, visc, nbr, red, hdr, \
-                     disp, count, chunks, lh)
+                     disp, count, chunks, lh, (uint32_t)cap)
 #define SPH_LIST_P(D, RW, G, RU) \
   if (eqm) SPH_LIST(D, RW, G, true, RU); else SPH_LIST(D, RW, G, false, RU)
 #define SPH_LIST_G(D, RW, RU) \

@@ -171,6 +171,19 @@ def test_stale_list_walks_and_reports():
     assert S.sph_read_error(s.ws) & S.SPH_ERR_LIST
 
 
+def test_other_list_bytes_walks_and_reports():
+    """A replay given another list_bytes than the build (another capacity)
+    does not use the list: it walks, with the walk's results, and reports."""
+    c = CASES["3d_block"]()
+    s = Setup(c)
+    s.bin()
+    s.build(0.02 * c.params.h)
+    full = s.lst
+    s.lst = full[: full.numel() - 8 * c.n]  # one chunk per target less
+    _equal(s.replay(0), s.walk(0), "other list_bytes")
+    assert S.sph_read_error(s.ws) & S.SPH_ERR_LIST
+
+
 def test_1m_both_passes_equal_walk():
     """The 3-D dam break at 1.32M particles in the benchmark's configuration,
     with the velocities of a developed flow: both passes of a step equal the
