@@ -37,10 +37,9 @@ __device__ __forceinline__ void row_of(uint32_t y, int& dy, int& dz) {
 // the cells' own: the list also serves the pass at n+1/2) cut to the list
 // radius rl, every candidate tested against rl (eligible: a fluid target
 // takes every particle, a wall target fluid ones; not itself), the hits of a
-// row collected in a 64-candidate mask over the row's window and written as
-// chunks of kListSpan.  A row window longer than 64 candidates, or more
-// chunks than the buffer holds, makes the target's count kListWalk (the
-// passes then walk its cells).
+// row collected in 64-candidate masks over the row's window and written as
+// chunks of kListSpan.  More chunks than the buffer holds make the target's
+// count kListWalk (the passes then walk its cells).
 template <int DIM, int R>
 __global__ __launch_bounds__(kBlock) void k_build_list(
     KParams kp, int64_t n, const float4* __restrict__ pr, const uint32_t* __restrict__ key,
@@ -78,7 +77,6 @@ __global__ __launch_bounds__(kBlock) void k_build_list(
   // chunk c of target i sits at c n + i: a wave's chunk accesses are coalesced
   uint2* out = chunks + i;
   uint32_t nc = 0;
-  bool walk = false;
   const int zlo = DIM == 3 ? -R : 0, zhi = DIM == 3 ? R : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     const int z = cz + dz;
@@ -99,44 +97,44 @@ __global__ __launch_bounds__(kBlock) void k_build_list(
       x1 = x1 > xhi ? xhi : x1;
       const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const float ys = row_shift(pa.y, dy, cs), zs = row_shift(pa.z, dz, cs);
-      const uint32_t o0 = at32(cstart, row + x0) * 16u;
-      const uint32_t o1 = at32(cstart, row + x1 + 1) * 16u;
-      if (o1 <= o0) continue;
-      if (o1 - o0 > 64u * 16u) {  // a window of more than 64 candidates
-        walk = true;
-        continue;
-      }
-      // groups of 4 candidates, their loads in flight together (the views
-      // are padded, so a group may read up to 3 entries past the row)
-      uint64_t m = 0;
-      for (uint32_t o = o0; o < o1; o += 64u) {
-        float4 pb[4];
-        pb[0] = at_byte<0>(pr, o);
-        pb[1] = at_byte<1>(pr, o);
-        pb[2] = at_byte<2>(pr, o);
-        pb[3] = at_byte<3>(pr, o);
-        uint32_t nib = 0;
+      const uint32_t r0 = at32(cstart, row + x0) * 16u;
+      const uint32_t r1 = at32(cstart, row + x1 + 1) * 16u;
+      const uint32_t rc = row_code(dy, dz);
+      // the row's window in segments of up to 64 candidates, each tested in
+      // groups of 4 with their loads in flight together (the views are
+      // padded, so a group may read up to 3 entries past the window)
+      for (uint32_t o0 = r0; o0 < r1; o0 += 64u * 16u) {
+        const uint32_t o1 = r1 - o0 > 64u * 16u ? o0 + 64u * 16u : r1;
+        uint64_t m = 0;
+        for (uint32_t o = o0; o < o1; o += 64u) {
+          float4 pb[4];
+          pb[0] = at_byte<0>(pr, o);
+          pb[1] = at_byte<1>(pr, o);
+          pb[2] = at_byte<2>(pr, o);
+          pb[3] = at_byte<3>(pr, o);
+          uint32_t nib = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          float dx, ddy, ddz;
-          const float r2 = pair_geom<DIM>(kp, xa, ys, zs, pb[u], dx, ddy, ddz);
-          const uint32_t ou = o + 16u * u;
-          const bool hit = (fa || pb[u].w > 0.f) && r2 < rl2 && ou != oi && ou < o1;
-          nib |= (hit ? 1u : 0u) << u;
+          for (int u = 0; u < 4; ++u) {
+            float dx, ddy, ddz;
+            const float r2 = pair_geom<DIM>(kp, xa, ys, zs, pb[u], dx, ddy, ddz);
+            const uint32_t ou = o + 16u * u;
+            const bool hit = (fa || pb[u].w > 0.f) && r2 < rl2 && ou != oi && ou < o1;
+            nib |= (hit ? 1u : 0u) << u;
+          }
+          m |= (uint64_t)nib << ((o - o0) >> 4);
         }
-        m |= (uint64_t)nib << ((o - o0) >> 4);
-      }
-      const uint32_t jw = o0 >> 4, rc = row_code(dy, dz);
-      while (m) {
-        const uint32_t f = (uint32_t)__builtin_ctzll(m);
-        const uint32_t bits = (uint32_t)(m >> f) & kListSpanMask;
-        m &= ~((uint64_t)kListSpanMask << f);
-        if (nc < cap) out[(size_t)nc * n] = make_uint2(jw + f, bits | rc);
-        ++nc;
+        const uint32_t jw = o0 >> 4;
+        while (m) {
+          const uint32_t f = (uint32_t)__builtin_ctzll(m);
+          const uint32_t bits = (uint32_t)(m >> f) & kListSpanMask;
+          m &= ~((uint64_t)kListSpanMask << f);
+          if (nc < cap) out[(size_t)nc * n] = make_uint2(jw + f, bits | rc);
+          ++nc;
+        }
       }
     }
   }
-  count[i] = (walk || nc > cap) ? kListWalk : nc;
+  count[i] = nc > cap ? kListWalk : nc;
 }
 
 // ------------------------------------------------------------------ replay --

@@ -72,6 +72,12 @@ class Setup:
                 torch.full((n,), float("nan"), dtype=torch.float32, device=DEV),
                 torch.full((n,), -1, dtype=torch.int32, device=DEV))
 
+    def walk_marked(self):
+        """Targets whose list did not fit (count = 0xffffffff after the
+        256-byte header): they walk their cells."""
+        cnt = self.lst[256: 256 + 4 * self.n].view(torch.int32)
+        return int((cnt == -1).sum().item())
+
     def walk(self, flags):
         o = self.out()
         S.sph_interact(self.P, self.n, self.dst, self.key, self.start, o[0], o[1], self.ws,
@@ -120,6 +126,7 @@ def test_replay_equals_walk_at_state_n(name, diag):
     s = Setup(c)
     s.bin()
     s.build(0.02 * c.params.h)
+    assert s.walk_marked() == 0  # every target replays (cells of 2h too)
     fl = S.SPH_DIAG_COUNT_F64 if diag else 0
     _equal(s.replay(fl), s.walk(fl), f"{name} state n")
     assert S.sph_read_error(s.ws) == 0
@@ -148,7 +155,7 @@ def test_replay_equals_walk_on_reused_cells(name, scale, expect_walk):
 
 def test_small_buffer_targets_walk():
     """A list buffer with room for 2 chunks per target: most targets do not
-    fit and walk their cells, the rest replay; the results equal the walk's."""
+    fit and walk their cells, any others replay; the results equal the walk's."""
     c = CASES["3d_block"]()
     P = S.make_params(c.params)
     n = c.n
@@ -158,6 +165,9 @@ def test_small_buffer_targets_walk():
     s = Setup(c, list_bytes=header_and_counts + 8 * n * 2)
     s.bin()
     s.build(0.02 * c.params.h)
+    marked = s.walk_marked()
+    _say(f"  cap 2: {marked} of {n} targets walk")
+    assert marked > 0
     _equal(s.replay(0), s.walk(0), "cap 2")
 
 
@@ -184,20 +194,25 @@ def test_other_list_bytes_walks_and_reports():
     assert S.sph_read_error(s.ws) & S.SPH_ERR_LIST
 
 
-def test_1m_both_passes_equal_walk():
+@pytest.mark.parametrize("skin_h,expect_walk", [(0.05, False), (0.01, True)])
+def test_1m_both_passes_equal_walk(skin_h, expect_walk):
     """The 3-D dam break at 1.32M particles in the benchmark's configuration,
-    with the velocities of a developed flow: both passes of a step equal the
-    walk's, and the adaptive skin of the next step covers the displacement."""
+    with the velocities of a developed flow (predictor displacement about
+    0.012 h): both passes of a step equal the walk's, replayed from the list
+    with a skin of 0.05 h, and walked (counted) with a skin of 0.01 h."""
     c = _perturbed(cases.dam_break_3d(cell_div=2, x_sub=4), 11, vel=2.0)
     s = Setup(c)
     s.bin()
-    s.build(0.01 * c.params.h)
+    s.build(skin_h * c.params.h)
+    assert s.walk_marked() == 0
     _equal(s.replay(0), s.walk(0), "1m state n")
     s.predictor_and_refresh(1.0)
     w0 = S.sph_list_walks(s.ws)
     fl = S.SPH_INTERACT_REUSE_CELLS
     _equal(s.replay(fl), s.walk(fl), "1m n+1/2")
-    _say(f"  1M: list walks {S.sph_list_walks(s.ws) - w0}")
+    walked = S.sph_list_walks(s.ws) - w0
+    _say(f"  1M, skin {skin_h} h: list walks {walked}")
+    assert walked == (1 if expect_walk else 0)
 
 
 def test_runner_trajectory_with_lists_equals_walk():
