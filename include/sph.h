@@ -325,7 +325,8 @@ sph_status sph_interact_noalloc(const sph_params* p, int64_t n, const sph_state*
  * same order); it only runs the wavefront's lanes through their own lists
  * instead of through common cell steps.  Default formulation only (Wendland
  * kernel, artificial viscosity, ddt 0 or 1, DBC walls, no floating bodies or
- * periodic components) and n below 2^28; else SPH_E_ARG.
+ * periodic components), FP32 state (no vel64/rho64) and n below 2^28; else
+ * SPH_E_ARG.
  *
  * The list is a caller-owned DEVICE buffer of sph_list_bytes(p, n) bytes (or
  * less: a smaller buffer holds fewer chunks per target, and targets whose

@@ -296,7 +296,7 @@ sph_status sph_build_list(const sph_params* p, int64_t n, const sph_state* s,
   if (!list_params_ok(p, n) || !cell_start || !ws || !list) return SPH_E_ARG;
   if (flags & ~(uint32_t)SPH_LIST_ADAPTIVE_SKIN) return SPH_E_ARG;
   if (!(skin >= 0.0) || !(skin < 0.5 * p->cell_size)) return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !key)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || f64_state(s))) return SPH_E_ARG;
   const int64_t cap = list_cap(n, list_bytes);
   if (cap < 1) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;
@@ -316,7 +316,7 @@ sph_status sph_interact_list(const sph_params* p, int64_t n, const sph_state* s,
     return SPH_E_ARG;
   if ((flags & SPH_INTERACT_REUSE_CELLS) && !periodic_reach_ok(p, p->cell_div + 1))
     return SPH_E_ARG;
-  if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho)) return SPH_E_ARG;
+  if (n > 0 && (!state_ok(s, true) || !key || !ace || !arho || f64_state(s))) return SPH_E_ARG;
   const int64_t cap = list_cap(n, list_bytes);
   if (cap < 1) return SPH_E_ARG;
   if (ws_bytes < ws_layout(n).total) return SPH_E_WORKSPACE;

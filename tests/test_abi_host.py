@@ -207,6 +207,52 @@ def test_noalloc_validates_without_device(S):
                                     None) == S.SPH_E_ARG
 
 
+def test_list_calls_validate_without_device(S):
+    """The neighbour-list calls reject what they do not take (formulation
+    options, FP64 state, bad skin or flags, short buffers) before any HIP
+    call, and size the buffer as header + counts + 40 chunks per target."""
+    from paper_2104_00537_amd import cases
+    c = cases.dam_break_2d()
+    P = S.make_params(c.params)
+    lib = S.lib
+    n = 1000
+    assert S.sph_list_bytes(P, n) == 256 + (4 * n + 255) // 256 * 256 + 8 * n * 40
+    for kw in (dict(kernel=1), dict(viscosity=1), dict(ddt=2), dict(boundary=1),
+               dict(floating=1), dict(h=0.0)):
+        assert S.sph_list_bytes(_bad_params(S, **kw), n) == 0, kw
+    assert S.sph_list_bytes(P, -1) == 0
+    d = C.c_void_p(16)
+    st = S.SphState(16, 16, 16, 16, None)
+    st64 = S.SphState(16, 16, 16, 16, None, None, 16, 16)
+    lb = S.sph_list_bytes(P, n)
+    ws = S.sph_workspace_bytes(P, n)
+    cs = float(c.params.cell_size)
+
+    def build(skin=0.0, fl=0, lbytes=lb, wbytes=ws, state=st, lst=d):
+        return lib.sph_build_list(C.byref(P), n, C.byref(state), d, d, skin, fl, lst, lbytes, d,
+                                  wbytes, None)
+
+    assert build(fl=2) == S.SPH_E_ARG
+    assert build(skin=-1e-9) == S.SPH_E_ARG
+    assert build(skin=0.5 * cs) == S.SPH_E_ARG
+    assert build(skin=float("nan")) == S.SPH_E_ARG
+    assert build(lbytes=lb - 8 * n * 40) == S.SPH_E_ARG  # no room for one chunk per target
+    assert build(lst=None) == S.SPH_E_ARG
+    assert build(state=st64) == S.SPH_E_ARG
+    assert build(wbytes=ws - 1) == S.SPH_E_WORKSPACE
+
+    def replay(fl=0, lbytes=lb, wbytes=ws, state=st, ace=d):
+        return lib.sph_interact_list(C.byref(P), n, C.byref(state), d, d, d, lbytes, ace, d, None,
+                                     None, fl, d, wbytes, None)
+
+    assert replay(fl=0x20) == S.SPH_E_ARG
+    assert replay(lbytes=lb - 8 * n * 40) == S.SPH_E_ARG
+    assert replay(ace=None) == S.SPH_E_ARG
+    assert replay(state=st64) == S.SPH_E_ARG
+    assert replay(wbytes=ws - 1) == S.SPH_E_WORKSPACE
+    assert lib.sph_list_walks(None) == S.SPH_E_ARG
+
+
 def test_batch_describe_host_only(S):
     """The slot table is built on the host: key ranges are the cells of the
     slots before plus one each, offsets are validated, cell_div must agree."""
