@@ -563,7 +563,13 @@ enum {
    * depend on the other slots.  It shortens each target's chain of loads,
    * which pays when the batch is too small to fill the GPU; when it fills
    * the GPU, one lane per target does the same work in fewer instructions. */
-  SPH_BATCH_FOUR_LANES = 2u
+  SPH_BATCH_FOUR_LANES = 2u,
+  /* some slot takes a formulation option (kernel 1, viscosity 1 or ddt 2):
+   * the interaction then runs the general pair terms, each slot with its own
+   * options.  A slot of the default formulation gets the same results there
+   * as in the default kernel (the same operations), so a case's results
+   * still do not depend on the other slots. */
+  SPH_BATCH_GENERAL = 4u
 };
 
 typedef struct sph_batch {
@@ -586,12 +592,13 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * to table_host and fills *batch except batch->table.  The caller copies the
  * table to device memory and sets batch->table before the calls below.  The
  * table stays valid while the slots keep their ranges.  Every slot must use
- * the same cell_div and the default formulation (kernel 0, viscosity 0, ddt
- * 0 or 1, boundary 0, no floating bodies, no periodic components);
- * otherwise SPH_E_ARG.  options: 0 or SPH_BATCH_FOUR_LANES (else
- * SPH_E_ARG); batch->flags gets SPH_BATCH_WAVE_ALIGNED when every range is
- * whole wavefronts, and SPH_BATCH_FOUR_LANES when it was asked for and the
- * batch is wave-aligned. */
+ * the same cell_div, DBC walls (boundary 0), no floating bodies and no
+ * periodic components; otherwise SPH_E_ARG.  Each slot may take its own
+ * formulation options (kernel, viscosity, ddt; see SPH_BATCH_GENERAL).
+ * options: 0 or SPH_BATCH_FOUR_LANES (else SPH_E_ARG); batch->flags gets
+ * SPH_BATCH_WAVE_ALIGNED when every range is whole wavefronts,
+ * SPH_BATCH_FOUR_LANES when it was asked for and the batch is wave-aligned,
+ * and SPH_BATCH_GENERAL when some slot takes a formulation option. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
                               uint32_t options, void* table_host, size_t table_bytes,
                               sph_batch* batch);

@@ -462,14 +462,17 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   if (offsets[0] != 0) return SPH_E_ARG;
   SlotEntry* tab = (SlotEntry*)table_host;
   uint64_t cbase = 0;
+  bool general = false;
   for (int s = 0; s < n_slots; ++s) {
     const sph_params* p = &params[s];
     if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
-    // the batched interaction runs the default formulation (Wendland kernel,
-    // artificial viscosity, ddt 0 or 1)
-    if (p->kernel != 0 || p->viscosity != 0 || p->ddt == 2 || p->boundary != 0 ||
-        p->floating != 0 || p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0)
+    // the batch takes DBC walls and no floating bodies or periodic
+    // components; formulation options (cubic spline kernel, laminar
+    // viscosity, Fourtakas DDT) per slot
+    if (p->boundary != 0 || p->floating != 0 || p->period[0] > 0.0 || p->period[1] > 0.0 ||
+        p->period[2] > 0.0)
       return SPH_E_ARG;
+    general = general || p->kernel != 0 || p->viscosity != 0 || p->ddt == 2;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};
     e.kp = make_slot_kparams(*p);
@@ -494,7 +497,8 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
     lanes += tab[s].n * tab[s].lpt;
   }
   batch->n_slots = n_slots;
-  batch->flags = (aligned ? SPH_BATCH_WAVE_ALIGNED : 0u) | (four ? SPH_BATCH_FOUR_LANES : 0u);
+  batch->flags = (aligned ? SPH_BATCH_WAVE_ALIGNED : 0u) | (four ? SPH_BATCH_FOUR_LANES : 0u) |
+                 (general ? SPH_BATCH_GENERAL : 0u);
   batch->lanes = (uint32_t)lanes;
   batch->cell_div = params[0].cell_div;
   batch->n_total = offsets[n_slots];

@@ -45,6 +45,7 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
 SPH_BATCH_MAX_SLOTS = 4096
 SPH_BATCH_WAVE_ALIGNED = 1
 SPH_BATCH_FOUR_LANES = 2
+SPH_BATCH_GENERAL = 4
 SPH_NOALLOC_MAX_N = 2097152
 
 

@@ -341,16 +341,28 @@ def test_batch_describe_lanes_per_slot(S):
     assert S.lib.sph_batch_describe(ps, o, 1, 2, host, C.sizeof(host), C.byref(bb)) == S.SPH_OK
 
 
-def test_batch_rejects_formulation_options(S):
-    """The batched path runs the default formulation only."""
+def test_batch_describe_formulation_options(S):
+    """Slots may take formulation options (cubic spline, laminar viscosity,
+    Fourtakas DDT): SPH_BATCH_GENERAL is set iff some slot does.  Modified
+    DBC, floating bodies and periodic components are rejected."""
     import dataclasses
     from paper_2104_00537_amd import cases
     base = cases.dam_break_2d(dp=0.05).params
-    for kw in (dict(kernel=1), dict(viscosity=1), dict(ddt=2)):
-        ps = [S.make_params(base), S.make_params(dataclasses.replace(base, **kw))]
+    P0 = S.make_params(base)
+    b, _ = S.sph_batch_describe([P0, P0], [0, 64, 128])
+    assert not b.flags & S.SPH_BATCH_GENERAL
+    for kw in (dict(kernel=1), dict(viscosity=1, visc_nu=1e-2), dict(ddt=2)):
+        ps = [P0, S.make_params(dataclasses.replace(base, **kw))]
+        b, _ = S.sph_batch_describe(ps, [0, 64, 128])
+        assert b.flags & S.SPH_BATCH_GENERAL, kw
+    for kw in (dict(boundary=1), dict(floating=1)):
+        ps = [P0, _bad_params(S, **kw)]
         with pytest.raises(S.SphError):
             S.sph_batch_describe(ps, [0, 10, 20])
-
+    per = S.make_params(base)
+    per.period[0] = float(base.ncell[0] // base.x_sub) * float(base.cell_size)
+    with pytest.raises(S.SphError):
+        S.sph_batch_describe([P0, per], [0, 10, 20])
 
 
 def test_periodic_params_validate_without_device(S):

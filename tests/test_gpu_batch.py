@@ -4,6 +4,8 @@ the oracle, and a small request stream is served end to end.  Steps bin once
 (the n+1/2 interaction reuses each slot's cells, widened by the slot's own
 recorded displacement) or twice; a slot that moved half a cell or more gets
 SPH_ERR_MARGIN in its own error word only."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -36,6 +38,27 @@ def _mix_cases():
     return out
 
 
+def _options_mix():
+    """The mix with formulation options per slot: cubic spline kernel,
+    laminar viscosity, Fourtakas DDT, and one slot of the default
+    formulation."""
+    rng = np.random.default_rng(6)
+    base = [cases.dam_break_2d(dp=0.02, seed=1),
+            cases.block_case(3, (12, 10, 9), walls=True, seed=2),
+            cases.dam_break_3d(dp=0.03, seed=4),
+            cases.sloshing_3d(dp=0.06, seed=3)]
+    opts = [dict(kernel=1), dict(viscosity=1, visc_nu=1e-2), dict(ddt=2), {}]
+    out = []
+    for c, kw in zip(base, opts):
+        c.vel[:] = rng.uniform(-0.2, 0.2, c.vel.shape).astype(np.float32)
+        out.append(cases.Case(dataclasses.replace(c.params, **kw), c.pos, c.vel, c.rho, c.type,
+                              dict(c.meta), c.normal))
+    return out
+
+
+MIXES = {"default": _mix_cases, "options": _options_mix}
+
+
 def _engine(cs, graph=False, reuse=True, pad=True, four=False):
     return V.BatchEngine(cap_particles=sum(V.padded(c.n) for c in cs) + 16,
                          cap_cells=sum(c.params.ncell_total() + 1 for c in cs) + 16,
@@ -53,18 +76,23 @@ def _run_engine(cs, steps, graph, reuse=True, pad=True, four=False):
     return [eng.slot_result(k) for k in range(len(cs))], errs, eng
 
 
-@pytest.mark.parametrize("reuse,pad,four", [(True, True, False), (False, True, False),
-                                            (True, False, False), (True, True, True)])
-def test_batch_alone_vs_mix_bit_identical(reuse, pad, four):
+@pytest.mark.parametrize("reuse,pad,four,mixname", [
+    (True, True, False, "default"), (False, True, False, "default"),
+    (True, False, False, "default"), (True, True, True, "default"),
+    (True, True, False, "options"), (True, False, False, "options")])
+def test_batch_alone_vs_mix_bit_identical(reuse, pad, four, mixname):
     """pad: slots padded to whole wavefronts (the aligned kernel) or not (the
-    general kernel, wavefronts straddling slots); four: four lanes per target
-    for the small slots (all of these)."""
-    cs = _mix_cases()
+    unaligned kernel, wavefronts straddling slots); four: four lanes per
+    target for the small slots (all of these).  In the options mix every
+    slot runs the general pair terms, and alone the default slot runs the
+    default kernel: the same bits either way."""
+    cs = MIXES[mixname]()
     _say("mix of", [c.n for c in cs])
     mix, errs, eng = _run_engine(cs, 7, graph=True, reuse=reuse, pad=pad, four=four)
     assert not errs.any()
     assert bool(eng.batch.flags & S.SPH_BATCH_WAVE_ALIGNED) == pad
     assert bool(eng.batch.flags & S.SPH_BATCH_FOUR_LANES) == four
+    assert bool(eng.batch.flags & S.SPH_BATCH_GENERAL) == (mixname == "options")
     for k, c in enumerate(cs):
         alone, e1, _ = _run_engine([c], 7, graph=False, reuse=reuse, pad=pad, four=four)
         assert not e1.any()
@@ -98,9 +126,11 @@ def test_batch_matches_single_case_path(reuse):
         assert np.array_equal(b["type"], g["type"])
 
 
-@pytest.mark.parametrize("pad,four", [(True, False), (False, False), (True, True)])
-def test_batch_interaction_matches_oracle(pad, four):
-    cs = _mix_cases()
+@pytest.mark.parametrize("pad,four,mixname", [(True, False, "default"), (False, False, "default"),
+                                              (True, True, "default"), (True, False, "options"),
+                                              (False, False, "options"), (True, True, "options")])
+def test_batch_interaction_matches_oracle(pad, four, mixname):
+    cs = MIXES[mixname]()
     eng = _engine(cs, pad=pad, four=four)
     reqs = [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)]
     eng.repack([], reqs)
