@@ -301,51 +301,62 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
   }
 }
 
-// Eq. 35 per slot.
-__global__ void k_batch_reduce_dt(const SlotEntry* __restrict__ tab, int ns,
-                                  const SlotAccum* __restrict__ sacc, double* __restrict__ dt,
-                                  uint64_t* __restrict__ inter, uint32_t* __restrict__ err,
-                                  uint32_t* __restrict__ slot_err) {
-  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-    const KParams& kp = tab[s].kp;
-    SlotAccum A{0u, 0u, 0u, 0u, 0ull, 0ull};
-    for (int q = 0; q < kAccCopies; ++q) {
-      const SlotAccum B = sacc[(size_t)s * kAccCopies + q];
-      A.fmax_bits = max(A.fmax_bits, B.fmax_bits);
-      A.vmax_bits = max(A.vmax_bits, B.vmax_bits);
-      A.nfluid += B.nfluid;
-      A.count += B.count;
-      A.count_wall += B.count_wall;
-    }
-    const double f = (double)__uint_as_float(A.fmax_bits);
-    const double v = (double)__uint_as_float(A.vmax_bits);
-    double d = INFINITY;
-    if (A.nfluid > 0) {
-      const double dtf = f > 0.0 ? sqrt(kp.h / f) : INFINITY;
-      const double dtcv = kp.h / (kp.c0 + v);
-      d = kp.cfl * (dtf < dtcv ? dtf : dtcv);
-    }
-    dt[s] = d;
-    if (!(d >= kp.dt_floor) || !isfinite(d)) {
-      set_error(err, SPH_ERR_DT_FLOOR);
-      set_error(&slot_err[s], SPH_ERR_DT_FLOOR);
-    }
-    if (inter) {
-      inter[2 * s] += (uint64_t)A.count;
-      inter[2 * s + 1] += (uint64_t)A.count_wall;
-    }
+// Eq. 35 per slot: one wavefront per slot (block s), lane q reading the
+// slot's accumulator copy q; maxima and integer sums, so the result does not
+// depend on the order of the copies.
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, off, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), off, 64);
+    v += ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_batch_reduce_dt(
+    const SlotEntry* __restrict__ tab, const SlotAccum* __restrict__ sacc,
+    double* __restrict__ dt, uint64_t* __restrict__ inter, uint32_t* __restrict__ err,
+    uint32_t* __restrict__ slot_err) {
+  static_assert(kAccCopies == 64, "one lane per accumulator copy");
+  const int s = blockIdx.x;
+  const SlotAccum B = sacc[(size_t)s * kAccCopies + threadIdx.x];
+  const uint32_t fb = wave_max_u32(B.fmax_bits), vb = wave_max_u32(B.vmax_bits);
+  const uint32_t nfl = wave_sum(B.nfluid);
+  const unsigned long long cnt = wave_sum_u64(B.count), cntw = wave_sum_u64(B.count_wall);
+  if (threadIdx.x != 0) return;
+  const KParams& kp = tab[s].kp;
+  const double f = (double)__uint_as_float(fb);
+  const double v = (double)__uint_as_float(vb);
+  double d = INFINITY;
+  if (nfl > 0) {
+    const double dtf = f > 0.0 ? sqrt(kp.h / f) : INFINITY;
+    const double dtcv = kp.h / (kp.c0 + v);
+    d = kp.cfl * (dtf < dtcv ? dtf : dtcv);
+  }
+  dt[s] = d;
+  if (!(d >= kp.dt_floor) || !isfinite(d)) {
+    set_error(err, SPH_ERR_DT_FLOOR);
+    set_error(&slot_err[s], SPH_ERR_DT_FLOOR);
+  }
+  if (inter) {
+    inter[2 * s] += (uint64_t)cnt;
+    inter[2 * s + 1] += (uint64_t)cntw;
   }
 }
 
+// The imposed wall motion of an update phase per slot (Eq. 37).  PHASE 1
+// also advances the slot's time by dt: the corrector that follows reads only
+// the motion written here.
 template <int PHASE>
 __global__ void k_batch_motion(const SlotEntry* __restrict__ tab, int ns,
-                               const double* __restrict__ dt, const double* __restrict__ t,
+                               const double* __restrict__ dt, double* __restrict__ t,
                                SlotMotion* __restrict__ mot) {
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     const KParams& kp = tab[s].kp;
     const double d = dt[s], t0 = t[s];
     const double t1 = PHASE == 0 ? t0 + 0.5 * d : t0 + d;
     mot[s] = SlotMotion{d, motion_disp(kp, t1) - motion_disp(kp, t0), motion_vel(kp, t1), 0.0};
+    if (PHASE == 1) t[s] = t1;
   }
 }
 
@@ -394,10 +405,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_symplectic(
     else
       record_displacement_slots(disp2, sl, disp);
   }
-}
-
-__global__ void k_batch_advance(int ns, const double* __restrict__ dt, double* __restrict__ t) {
-  for (int s = threadIdx.x; s < ns; s += blockDim.x) t[s] = t[s] + dt[s];
 }
 
 __global__ void k_batch_clear_errors(int ns, uint32_t* __restrict__ err,
@@ -510,9 +517,9 @@ hipError_t launch_batch_refresh_view(const BatchDesc& B, const sph_state& s, con
 hipError_t launch_batch_reduce_dt(const BatchDesc& B, double* dt, uint64_t* interactions, void* ws,
                                   hipStream_t st) {
   const BatchWsLayout W = batch_ws_layout(B.n_slots, B.n_total);
-  hipLaunchKernelGGL(k_batch_reduce_dt, dim3(1), dim3(kBlock), 0, st,
-                     (const SlotEntry*)B.table, B.n_slots, ws_ptr<SlotAccum>(ws, W.accum), dt,
-                     interactions, ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err));
+  hipLaunchKernelGGL(k_batch_reduce_dt, dim3(B.n_slots), dim3(64), 0, st,
+                     (const SlotEntry*)B.table, ws_ptr<SlotAccum>(ws, W.accum), dt, interactions,
+                     ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err));
   return hipGetLastError();
 }
 
@@ -537,7 +544,6 @@ hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* 
       hipLaunchKernelGGL(k_batch_symplectic<1>, dim3(grid_for(n)), dim3(kBlock), 0, st, tab,
                          B.n_slots, n, mot, saved, s, ace, arho, err, serr,
                          ws_ptr<uint32_t>(ws, W.disp));
-    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(kBlock), 0, st, B.n_slots, dt, t);
   }
   return hipGetLastError();
 }
