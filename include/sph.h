@@ -644,6 +644,19 @@ sph_status sph_batch_symplectic_step(const sph_batch* b, int32_t phase, const do
                                      double* t, sph_state* saved, sph_state* s, const float* ace,
                                      const float* arho, void* ws, size_t ws_bytes, void* stream);
 
+/* sph_shifting over a batch, right after sph_batch_symplectic_step phase 1:
+ * every slot whose shift_coef is positive is shifted with its own A_s,
+ * surface threshold, dt[n_slots] (device) and, with
+ * SPH_INTERACT_REUSE_CELLS, its own recorded displacement; other slots are
+ * left as they are (C = 0 and no shift in conc and shift).  conc[n_total]
+ * and shift[3][n_total] (packed layout) are nullable outputs as in
+ * sph_shifting.  A slot's results do not depend on the other slots.
+ * flags: 0 or SPH_INTERACT_REUSE_CELLS (else SPH_E_ARG). */
+sph_status sph_batch_shifting(const sph_batch* b, sph_state* s, const uint32_t* key,
+                              const uint32_t* cell_start, const double* dt, float* conc,
+                              float* shift, uint32_t flags, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* Per-slot error words (SPH_ERR_* bits) to host slot_errors[n_slots], after
  * synchronising the device; the workspace's global error word (read with
  * sph_read_error) holds their union. */

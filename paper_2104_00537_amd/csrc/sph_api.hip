@@ -576,6 +576,20 @@ sph_status sph_batch_symplectic_step(const sph_batch* b, int32_t phase, const do
                                             (hipStream_t)stream));
 }
 
+sph_status sph_batch_shifting(const sph_batch* b, sph_state* s, const uint32_t* key,
+                              const uint32_t* cell_start, const double* dt, float* conc,
+                              float* shift, uint32_t flags, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!batch_ok(b) || !cell_start || !dt || !ws) return SPH_E_ARG;
+  if (flags & ~(uint32_t)SPH_INTERACT_REUSE_CELLS) return SPH_E_ARG;
+  if (b->n_total > 0 && (!state_ok(s, true) || !key || f64_state(s))) return SPH_E_ARG;
+  if (ws_bytes < batch_ws_layout(b->n_slots, b->n_total).total) return SPH_E_WORKSPACE;
+  if (b->n_total == 0) return SPH_OK;
+  return hip_status(launch_batch_shifting(batch_desc(b), *s, key, cell_start, dt, conc, shift,
+                                          (flags & SPH_INTERACT_REUSE_CELLS) != 0, ws,
+                                          (hipStream_t)stream));
+}
+
 sph_status sph_batch_read_errors(const sph_batch* b, const void* ws, uint32_t* slot_errors) {
   if (!b || b->n_slots < 1 || b->n_slots > SPH_BATCH_MAX_SLOTS || !ws || !slot_errors)
     return SPH_E_ARG;

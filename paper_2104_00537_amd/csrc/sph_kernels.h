@@ -88,5 +88,8 @@ hipError_t launch_batch_symplectic(const BatchDesc& B, int phase, const double* 
                                    sph_state& saved, sph_state& s, const float* ace,
                                    const float* arho, void* ws, hipStream_t st);
 hipError_t launch_batch_clear_errors(const BatchDesc& B, void* ws, hipStream_t st);
+hipError_t launch_batch_shifting(const BatchDesc& B, const sph_state& s, const uint32_t* key,
+                                 const uint32_t* cell_start, const double* dt, float* conc,
+                                 float* shift, bool reuse, void* ws, hipStream_t st);
 
 }  // namespace sph

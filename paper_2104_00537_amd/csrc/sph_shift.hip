@@ -7,17 +7,19 @@
 // per particle in sorted order, blocks placed per XCD as in the
 // interaction; sums per lane, no atomics.
 #include "sph_kernels.h"
+#include "sph_slots.h"
 
 namespace sph {
 
 // Visits every candidate b within 2h of a target (view position pa, key
-// cell (cx, cy, cz)): the rows of the neighbour cells, each cut to the key
-// cells the support sphere reaches, as in the interaction's walk (periodic
-// components wrapped the same way when PER), in groups of 4 candidates.
-// Calls f(j, dx, dy, dz, r2, pb) with r_ab = (dx, dy, dz) and |r_ab|^2 < 4h^2.
+// cell (cx, cy, cz), cell keys offset by cbase): the rows of the neighbour
+// cells, each cut to the key cells the support sphere reaches, as in the
+// interaction's walk (periodic components wrapped the same way when PER), in
+// groups of 4 candidates.  Calls f(j, dx, dy, dz, r2, pb) with
+// r_ab = (dx, dy, dz) and |r_ab|^2 < 4h^2.
 template <int DIM, int R, bool PER, typename F>
-__device__ inline void visit_neighbours(const KParams& kp, const float4& pa, int cx, int cy,
-                                        int cz, const float4* __restrict__ pr,
+__device__ inline void visit_neighbours(const KParams& kp, uint32_t cbase, const float4& pa,
+                                        int cx, int cy, int cz, const float4* __restrict__ pr,
                                         const uint32_t* __restrict__ cstart, float cull2,
                                         F&& f) {
   const float cs = kp.cs_f;
@@ -55,7 +57,8 @@ __device__ inline void visit_neighbours(const KParams& kp, const float4& pa, int
       int x1 = cx + (int)floorf((fx + w) * kp.inv_csx_f);
       x0 = x0 < xlo ? xlo : x0;
       x1 = x1 > xhi ? xhi : x1;
-      const uint32_t row = (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
+      const uint32_t row =
+          cbase + (uint32_t)kp.ncx * ((uint32_t)y + (uint32_t)kp.ncy * (uint32_t)z);
       const float ys = pa.y - (float)dy * cs, zs = pa.z - (float)dz * cs;
       // candidates 4 at a time, all loads in flight (the view is padded by
       // kViewPad entries, so a group may read past the last particle;
@@ -145,6 +148,68 @@ __device__ inline float shift_cull2(const KParams& kp, const uint32_t* __restric
   return rc * rc;
 }
 
+// C_a of one non-excluded target (local key lk, cell keys offset by cbase).
+template <int DIM, int R, bool PER>
+__device__ inline float conc_one(const KParams& kp, uint32_t cbase, uint32_t lk, const float4& pa,
+                                 const float4* __restrict__ pr,
+                                 const uint32_t* __restrict__ cstart, float cull2) {
+  const float mf = (float)kp.mass_f, mw = (float)kp.mass_b;
+  int cx, cy, cz;
+  target_cell(kp, lk, cx, cy, cz);
+  float c = 0.f;
+  visit_neighbours<DIM, R, PER>(kp, cbase, pa, cx, cy, cz, pr, cstart, cull2,
+                                [&](uint32_t, float, float, float, float r2, const float4& pb) {
+                                  const float vb = (pb.w > 0.f ? mf : mw) *
+                                                   __builtin_amdgcn_rcpf(fabsf(pb.w));
+                                  c = fmaf(vb, kernel_w_f(kp, r2), c);
+                                });
+  return c;
+}
+
+// grad C_a = sum_b V_b (C_b - C_a) F_ab r_ab and dr_a = -A_s h |v_a| dt grad C_a
+// (Eq. 40-41, 53) for one fluid target i, with the tangential projection
+// below the surface threshold (Eq. 54, a_n = 0); dr_a is added to the
+// positions (and written to `shift` when given).
+template <int DIM, int R, bool PER>
+__device__ inline void shift_one(const KParams& kp, uint32_t cbase, uint32_t lk, int64_t n,
+                                 int64_t i, const float4* __restrict__ pr,
+                                 const float4* __restrict__ vp,
+                                 const uint32_t* __restrict__ cstart,
+                                 const float* __restrict__ conc, double dt, float cull2,
+                                 double* __restrict__ pos, float* __restrict__ shift) {
+  const float mf = (float)kp.mass_f, mw = (float)kp.mass_b, kfab = (float)kp.kfab;
+  const float4 pa = pr[i], va = vp[i];
+  const float ca = conc[i];
+  int cx, cy, cz;
+  target_cell(kp, lk, cx, cy, cz);
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  visit_neighbours<DIM, R, PER>(
+      kp, cbase, pa, cx, cy, cz, pr, cstart, cull2,
+      [&](uint32_t j, float dx, float dy, float dz, float r2, const float4& pb) {
+        const float vb = (pb.w > 0.f ? mf : mw) * __builtin_amdgcn_rcpf(fabsf(pb.w));
+        const float w = vb * (conc[j] - ca) * kernel_f_f(kp, kfab, r2);
+        g0 = fmaf(w, dx, g0);
+        g1 = fmaf(w, dy, g1);
+        g2 = fmaf(w, dz, g2);
+      });
+  const float speed = __builtin_amdgcn_sqrtf(va.x * va.x + va.y * va.y + va.z * va.z);
+  const float ds = kp.shift_k_f * speed * (float)dt;
+  float d[3] = {-ds * g0, -ds * g1, DIM == 3 ? -ds * g2 : 0.f};
+  if (kp.shift_fs_f > 0.f && ca < kp.shift_fs_f) {
+    const float gg = g0 * g0 + g1 * g1 + g2 * g2;
+    if (gg > 0.f) {
+      const float k = (d[0] * g0 + d[1] * g1 + d[2] * g2) / gg;
+      d[0] -= k * g0;
+      d[1] -= k * g1;
+      d[2] -= k * g2;
+    }
+  }
+  for (int c = 0; c < DIM; ++c) {
+    pos[c * n + i] += (double)d[c];
+    if (shift) shift[c * n + i] = d[c];
+  }
+}
+
 template <int DIM, int R, bool PER>
 __global__ __launch_bounds__(kBlock) void k_shift_conc(KParams kp, int64_t n,
                                                        const float4* __restrict__ pr,
@@ -157,27 +222,11 @@ __global__ __launch_bounds__(kBlock) void k_shift_conc(KParams kp, int64_t n,
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const float cull2 = shift_cull2<R>(kp, disp, err);
   if (i >= n) return;
-  if (is_excluded(type[i])) {
-    conc[i] = 0.f;
-    return;
-  }
-  const float mf = (float)kp.mass_f, mw = (float)kp.mass_b;
-  const float4 pa = pr[i];
-  int cx, cy, cz;
-  target_cell(kp, key[i], cx, cy, cz);
-  float c = 0.f;
-  visit_neighbours<DIM, R, PER>(kp, pa, cx, cy, cz, pr, cstart, cull2,
-                                [&](uint32_t, float, float, float, float r2, const float4& pb) {
-                                  const float vb = (pb.w > 0.f ? mf : mw) *
-                                                   __builtin_amdgcn_rcpf(fabsf(pb.w));
-                                  c = fmaf(vb, kernel_w_f(kp, r2), c);
-                                });
-  conc[i] = c;
+  conc[i] = is_excluded(type[i])
+                ? 0.f
+                : conc_one<DIM, R, PER>(kp, 0u, key[i], pr[i], pr, cstart, cull2);
 }
 
-// grad C_a = sum_b V_b (C_b - C_a) F_ab r_ab and dr_a = -A_s h |v_a| dt grad C_a
-// (Eq. 40-41, 53) for fluid particles, with the tangential projection below
-// the surface threshold (Eq. 54, a_n = 0); dr_a is added to the positions.
 template <int DIM, int R, bool PER>
 __global__ __launch_bounds__(kBlock) void k_shift_apply(
     KParams kp, int64_t n, const float4* __restrict__ pr, const float4* __restrict__ vp,
@@ -194,36 +243,78 @@ __global__ __launch_bounds__(kBlock) void k_shift_apply(
       for (int d = 0; d < DIM; ++d) shift[d * n + i] = 0.f;
     return;
   }
-  const float mf = (float)kp.mass_f, mw = (float)kp.mass_b, kfab = (float)kp.kfab;
-  const float4 pa = pr[i], va = vp[i];
-  const float ca = conc[i];
-  int cx, cy, cz;
-  target_cell(kp, key[i], cx, cy, cz);
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  visit_neighbours<DIM, R, PER>(
-      kp, pa, cx, cy, cz, pr, cstart, cull2,
-      [&](uint32_t j, float dx, float dy, float dz, float r2, const float4& pb) {
-        const float vb = (pb.w > 0.f ? mf : mw) * __builtin_amdgcn_rcpf(fabsf(pb.w));
-        const float w = vb * (conc[j] - ca) * kernel_f_f(kp, kfab, r2);
-        g0 = fmaf(w, dx, g0);
-        g1 = fmaf(w, dy, g1);
-        g2 = fmaf(w, dz, g2);
-      });
-  const float speed = __builtin_amdgcn_sqrtf(va.x * va.x + va.y * va.y + va.z * va.z);
-  const float ds = kp.shift_k_f * speed * (float)(*dtp);
-  float d[3] = {-ds * g0, -ds * g1, DIM == 3 ? -ds * g2 : 0.f};
-  if (kp.shift_fs_f > 0.f && ca < kp.shift_fs_f) {
-    const float gg = g0 * g0 + g1 * g1 + g2 * g2;
-    if (gg > 0.f) {
-      const float k = (d[0] * g0 + d[1] * g1 + d[2] * g2) / gg;
-      d[0] -= k * g0;
-      d[1] -= k * g1;
-      d[2] -= k * g2;
+  shift_one<DIM, R, PER>(kp, 0u, key[i], n, i, pr, vp, cstart, conc, *dtp, cull2, pos, shift);
+}
+
+// ------------------------------------------------------------- batches --
+// Shifting over the slots of a batch (packed 3-component arrays, cell keys
+// offset per slot): each slot with its own constants, dt and displacement
+// record; slots whose A_s is zero are left as they are (C = 0, no shift).
+// The lanes of a wave are taken slot by slot (one pass when the wave lies in
+// one slot), so every pass has its slot's constants uniform.
+
+// The culling radius squared of a slot's walk, as shift_cull2 with the
+// slot's own displacement record and error word (reported by lane `leader`).
+template <int R>
+__device__ inline float batch_shift_cull2(const KParams& kp, const uint32_t* __restrict__ disp,
+                                          uint32_t* __restrict__ err,
+                                          uint32_t* __restrict__ slot_err, int leader) {
+  const float delta = read_displacement(disp);
+  if (R <= kp.cell_div) {
+    // the cells' own reach after particles moved since the binning
+    if (delta > 0.f && (threadIdx.x & 63) == leader) {
+      set_error(err, SPH_ERR_MARGIN);
+      set_error(slot_err, SPH_ERR_MARGIN);
     }
+    return kp.support2_f * 1.0002f;
   }
-  for (int c = 0; c < DIM; ++c) {
-    pos[c * n + i] += (double)d[c];
-    if (shift) shift[c * n + i] = d[c];
+  const float rc = __builtin_amdgcn_sqrtf(kp.support2_f) * 1.0001f + delta;
+  if (!(2.f * delta < kp.cs_f) && (threadIdx.x & 63) == leader) {
+    set_error(err, SPH_ERR_MARGIN);
+    set_error(slot_err, SPH_ERR_MARGIN);
+  }
+  return rc * rc;
+}
+
+template <int R, bool APPLY>
+__global__ __launch_bounds__(kBlock) void k_batch_shift(
+    const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
+    const float4* __restrict__ vp, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ cstart, const uint8_t* __restrict__ type,
+    float* __restrict__ conc, const double* __restrict__ dt, double* __restrict__ pos,
+    float* __restrict__ shift, const uint32_t* __restrict__ disp, uint32_t* __restrict__ err,
+    uint32_t* __restrict__ slot_err) {
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int sa = i < n ? find_slot(tab, ns, i) : -1;
+  bool todo = i < n;
+  while (__ballot(todo) != 0ull) {
+    const int leader = (int)__builtin_ctzll(__ballot(todo));
+    const int rs = __builtin_amdgcn_readlane(sa, leader);
+    const bool mine = todo && sa == rs;
+    todo = todo && !mine;
+    const KParams& kp = tab[rs].kp;
+    if (!(kp.shift_k_f > 0.f)) {  // no shifting in this slot
+      if (mine && !APPLY) conc[i] = 0.f;
+      if (mine && APPLY && shift)
+        for (int d = 0; d < 3; ++d) shift[d * n + i] = 0.f;
+      continue;
+    }
+    const uint32_t cbase = tab[rs].cbase;
+    const float cull2 =
+        batch_shift_cull2<R>(kp, disp + (size_t)rs * kDispSlots, err, &slot_err[rs], leader);
+    if (!mine) continue;
+    const uint8_t t = type[i];
+    if (!APPLY) {
+      conc[i] = is_excluded(t)
+                    ? 0.f
+                    : conc_one<3, R, false>(kp, cbase, key[i] - cbase, pr[i], pr, cstart, cull2);
+    } else if (!is_fluid(t) || is_excluded(t)) {
+      if (shift)
+        for (int d = 0; d < 3; ++d) shift[d * n + i] = 0.f;
+    } else {
+      shift_one<3, R, false>(kp, cbase, key[i] - cbase, n, i, pr, vp, cstart, conc, dt[rs],
+                             cull2, pos, shift);
+    }
   }
 }
 
@@ -261,6 +352,42 @@ hipError_t launch_shifting(const KParams& kp, int64_t n, const sph_state& s, con
 #undef SPH_SHIFT_R
 #undef SPH_SHIFT_P
 #undef SPH_SHIFT
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_shifting(const BatchDesc& B, const sph_state& s, const uint32_t* key,
+                                 const uint32_t* cell_start, const double* dt, float* conc,
+                                 float* shift, bool reuse, void* ws, hipStream_t st) {
+  const int64_t n = B.n_total;
+  const BatchWsLayout W = batch_ws_layout(B.n_slots, n);
+  const SlotEntry* tab = (const SlotEntry*)B.table;
+  const float4* pr = ws_ptr<float4>(ws, W.base.view_pr);
+  const float4* vp = ws_ptr<float4>(ws, W.base.view_vp);
+  float* c = conc ? conc : ws_ptr<float>(ws, W.base.keyA);
+  const uint32_t* disp = ws_ptr<uint32_t>(ws, W.disp);
+  uint32_t* err = ws_ptr<uint32_t>(ws, W.base.err);
+  uint32_t* serr = ws_ptr<uint32_t>(ws, W.slot_err);
+  const int64_t g = (n + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)(g > 0 ? g : 1);
+  // reused cells: one more cell of reach, cut widened by each slot's record
+  const int reach = B.cell_div + (reuse ? 1 : 0);
+#define SPH_BSHIFT(RR)                                                                          \
+  do {                                                                                          \
+    hipLaunchKernelGGL((k_batch_shift<RR, false>), dim3(grid), dim3(kBlock), 0, st, tab,        \
+                       B.n_slots, n, pr, vp, key, cell_start, s.type, c, dt, s.pos, shift, disp, \
+                       err, serr);                                                              \
+    hipLaunchKernelGGL((k_batch_shift<RR, true>), dim3(grid), dim3(kBlock), 0, st, tab,         \
+                       B.n_slots, n, pr, vp, key, cell_start, s.type, c, dt, s.pos, shift, disp, \
+                       err, serr);                                                              \
+  } while (0)
+  if (reach == 1) {
+    SPH_BSHIFT(1);
+  } else if (reach == 2) {
+    SPH_BSHIFT(2);
+  } else {
+    SPH_BSHIFT(3);
+  }
+#undef SPH_BSHIFT
   return hipGetLastError();
 }
 

@@ -109,6 +109,7 @@ class BatchEngine:
         self.reuse = bool(reuse_cells)
         self.pad = bool(pad_slots)
         self.four_lanes = bool(four_lanes)
+        self.shifting = False
         self.cur = 0
         self.cap_n = int(cap_particles)
         self.cap_cells = int(cap_cells)
@@ -223,6 +224,9 @@ class BatchEngine:
             self.batch = None
             return
         params = [S.make_params(r.case.params) for r in new_slots]
+        # particle shifting after each corrector when some slot takes it
+        self.shifting = any(float(getattr(r.case.params, "shift_coef", 0.0)) > 0.0
+                            for r in new_slots)
         b, host = S.sph_batch_describe(params, offsets, four_lanes=self.four_lanes)
         if b.key_cells + 1 > self.cell_start.numel():
             raise S.SphError("batch exceeds the cell capacity")
@@ -259,12 +263,17 @@ class BatchEngine:
                                  flags=S.SPH_INTERACT_REUSE_CELLS)
             S.sph_batch_reduce_dt(b, dth, self.ws, interactions=inter)
             S.sph_batch_symplectic_step(b, 1, dt, t, s0, bb, ace, arho, self.ws)
+            if self.shifting:
+                S.sph_batch_shifting(b, bb, key, self.cell_start, dt, self.ws,
+                                     flags=S.SPH_INTERACT_REUSE_CELLS)
             return 1 - cur
         S.sph_batch_bin_cells(b, bb, a, key, perm, self.cell_start, self.ws, carry_in=s0,
                               carry_out=s1)
         S.sph_batch_interact(b, a, key, self.cell_start, ace, arho, self.ws)
         S.sph_batch_reduce_dt(b, dth, self.ws, interactions=inter)
         S.sph_batch_symplectic_step(b, 1, dt, t, s1, a, ace, arho, self.ws)
+        if self.shifting:
+            S.sph_batch_shifting(b, a, key, self.cell_start, dt, self.ws)
         return cur
 
     def run(self, k: int):

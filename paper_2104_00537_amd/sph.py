@@ -41,7 +41,8 @@ EXPORTS = ("sph_workspace_bytes", "sph_bin_cells", "sph_refresh_view", "sph_inte
            "sph_batch_table_bytes", "sph_batch_describe", "sph_batch_workspace_bytes",
            "sph_batch_bin_cells", "sph_batch_interact", "sph_batch_refresh_view",
            "sph_batch_reduce_dt",
-           "sph_batch_symplectic_step", "sph_batch_read_errors", "sph_batch_clear_errors")
+           "sph_batch_symplectic_step", "sph_batch_shifting", "sph_batch_read_errors",
+           "sph_batch_clear_errors")
 SPH_BATCH_MAX_SLOTS = 4096
 SPH_BATCH_WAVE_ALIGNED = 1
 SPH_BATCH_FOUR_LANES = 2
@@ -162,6 +163,9 @@ def _load() -> C.CDLL:
     L.sph_batch_symplectic_step.restype = C.c_int32
     L.sph_batch_symplectic_step.argtypes = [P(SphBatch), C.c_int32, VP, VP, P(SphState),
                                             P(SphState), VP, VP, VP, C.c_size_t, VP]
+    L.sph_batch_shifting.restype = C.c_int32
+    L.sph_batch_shifting.argtypes = [P(SphBatch), P(SphState), VP, VP, VP, VP, VP, C.c_uint32, VP,
+                                     C.c_size_t, VP]
     L.sph_batch_read_errors.restype = C.c_int32
     L.sph_batch_read_errors.argtypes = [P(SphBatch), VP, VP]
     L.sph_batch_clear_errors.restype = C.c_int32
@@ -480,6 +484,14 @@ def sph_batch_symplectic_step(batch: SphBatch, phase, dt, t, saved: DeviceState,
                                          C.byref(saved.c()), C.byref(s.c()), _ptr(ace),
                                          _ptr(arho), _ptr(ws), ws.numel(), _stream(stream)),
            "sph_batch_symplectic_step")
+
+
+def sph_batch_shifting(batch: SphBatch, s: DeviceState, key, cell_start, dt, ws,
+                       conc: Optional[torch.Tensor] = None, shift: Optional[torch.Tensor] = None,
+                       flags: int = 0, stream=None):
+    _check(lib.sph_batch_shifting(C.byref(batch), C.byref(s.c()), _ptr(key), _ptr(cell_start),
+                                  _ptr(dt), _ptr(conc), _ptr(shift), int(flags), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "sph_batch_shifting")
 
 
 def sph_batch_read_errors(batch: SphBatch, ws):

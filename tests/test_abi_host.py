@@ -305,6 +305,14 @@ def test_batch_calls_validate_without_device(S):
                                       None) == S.SPH_E_ARG
     assert lib.sph_batch_symplectic_step(C.byref(b), 3, d, d, C.byref(st), C.byref(st), d, d, d,
                                          1 << 30, None) == S.SPH_E_ARG
+    # shifting: flags other than reusing the cells, missing dt, FP64 state, small workspace
+    st64 = S.SphState(16, 16, 16, 16, None, None, 16, 16)
+    shift = lambda fl=0, dt=d, state=st, wb=1 << 40: lib.sph_batch_shifting(  # noqa: E731
+        C.byref(b), C.byref(state), d, d, dt, None, None, fl, d, wb, None)
+    assert shift(fl=S.SPH_DIAG_COUNT_F64) == S.SPH_E_ARG
+    assert shift(dt=None) == S.SPH_E_ARG
+    assert shift(state=st64) == S.SPH_E_ARG
+    assert shift(fl=S.SPH_INTERACT_REUSE_CELLS, wb=16) == S.SPH_E_WORKSPACE
 
 
 def test_batch_describe_sets_the_wave_alignment_flag(S):

@@ -302,3 +302,112 @@ def test_served_stream_small():
         assert np.abs(a["pos"] - b["pos"]).max() < 1e-6
     _say("  batched", {k: round(v, 4) for k, v in sb.items() if isinstance(v, float)})
     _say("  plain  ", {k: round(v, 4) for k, v in sp.items() if isinstance(v, float)})
+
+
+def _shifting_mix():
+    """Slots with particle shifting (A_s = 2; with and without the surface
+    correction) beside a slot without it."""
+    rng = np.random.default_rng(8)
+    base = [(cases.dam_break_2d(dp=0.02, seed=1), dict(shift_coef=2.0, shift_fs=0.9)),
+            (cases.block_case(3, (12, 10, 9), walls=True, seed=2), dict(shift_coef=2.0)),
+            (cases.sloshing_3d(dp=0.06, seed=3), {}),
+            (cases.dam_break_3d(dp=0.03, seed=4), dict(shift_coef=1.0, shift_fs=0.9,
+                                                      kernel=1))]
+    out = []
+    for c, kw in base:
+        c.vel[:] = rng.uniform(-0.3, 0.3, c.vel.shape).astype(np.float32)
+        out.append(cases.Case(dataclasses.replace(c.params, **kw), c.pos, c.vel, c.rho, c.type,
+                              dict(c.meta), c.normal))
+    return out
+
+
+@pytest.mark.parametrize("pad", [True, False])
+def test_batch_shifting_matches_oracle(pad):
+    """sph_batch_shifting on a freshly binned batch against the oracle's
+    shifting per slot (the single-case bars: C within 1e-5, the shift within
+    1e-4 of the slot's largest on matching surface decisions); the slot
+    without shifting is left as it is."""
+    cs = _shifting_mix()
+    eng = _engine(cs, pad=pad)
+    eng.repack([], [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)])
+    assert eng.shifting
+    b = eng.batch
+    n = b.n_total
+    a, bb = eng._dev_state(eng.cur, n), eng._dev_state(1 - eng.cur, n)
+    key, perm = eng._key.view(n), eng._perm.view(n)
+    S.sph_batch_bin_cells(b, a, bb, key, perm, eng.cell_start, eng.ws)
+    torch.cuda.synchronize()
+    pos0 = bb.pos.cpu().numpy()
+    vel_all = bb.vel.cpu().numpy().astype(np.float64)
+    rho_all = bb.rho.cpu().numpy().astype(np.float64)
+    typ_all = bb.type.cpu().numpy()
+    dts = [2e-4, 1.5e-4, 1e-4, 2.5e-4]
+    dt = torch.tensor(dts, dtype=torch.float64, device=DEV)
+    conc = torch.full((n,), float("nan"), dtype=torch.float32, device=DEV)
+    shift = torch.full((3, n), float("nan"), dtype=torch.float32, device=DEV)
+    S.sph_batch_shifting(b, bb, key, eng.cell_start, dt, eng.ws, conc=conc, shift=shift)
+    torch.cuda.synchronize()
+    assert not S.sph_batch_read_errors(b, eng.ws).any()
+    pos1 = bb.pos.cpu().numpy()
+    cg_all = conc.cpu().numpy().astype(np.float64)
+    dg_all = shift.cpu().numpy().astype(np.float64)
+    assert np.array_equal(pos1, pos0 + dg_all)
+    for k, c in enumerate(cs):
+        o0, o1 = eng.offsets[k], eng.offsets[k + 1]
+        cp, dim = c.params, c.params.dim
+        typ = typ_all[o0:o1]
+        cg, dg = cg_all[o0:o1], dg_all[:, o0:o1]
+        if not cp.shift_coef > 0:
+            assert np.all(cg == 0) and np.all(dg == 0), k
+            continue
+        pos, vel = V.from_3d(dim, pos0[:, o0:o1], vel_all[:, o0:o1])
+        co, _, do = oracle.shift(cp, pos, vel, rho_all[o0:o1], typ, dts[k])
+        d3 = dg if dim == 3 else dg[[0, 2]]
+        if dim == 2:
+            assert np.all(dg[1] == 0)
+        fl = typ == cases.FLUID
+        same = (cg < cp.shift_fs) == (co < cp.shift_fs) if cp.shift_fs > 0 else np.ones_like(fl)
+        ec = np.abs(cg - co).max()
+        ed = np.abs(d3 - do)[:, fl & same].max() / np.abs(do[:, fl]).max()
+        _say(f"  slot {k} (dim {dim}): C err {ec:.2e}, shift rel err {ed:.2e}, surface "
+             f"decisions differing {(~same & fl).sum()}")
+        assert ec < 1e-5 and ed < 1e-4
+        assert (~same & fl).sum() <= max(2, fl.sum() // 1000)
+        assert np.all(dg[:, ~fl] == 0)
+
+
+@pytest.mark.parametrize("reuse", [True, False])
+def test_batch_shifting_alone_vs_mix_bit_identical(reuse):
+    """Steps with shifting in some slots: every case gives the same bits
+    alone and in the mix."""
+    cs = _shifting_mix()
+    mix, errs, eng = _run_engine(cs, 6, graph=True, reuse=reuse)
+    assert not errs.any() and eng.shifting
+    for k, c in enumerate(cs):
+        alone, e1, _ = _run_engine([c], 6, graph=False, reuse=reuse)
+        assert not e1.any()
+        for f in ("pos", "vel", "rho", "type"):
+            assert np.array_equal(mix[k][f], alone[0][f]), (k, f)
+        assert mix[k]["t"] == alone[0]["t"]
+
+
+def test_batch_shifting_matches_single_case_path():
+    """A case with shifting in the batch follows the single-case runner's
+    trajectory (reused cells, shifting after each corrector) to FP32
+    summation order."""
+    cs = _shifting_mix()
+    mix, errs, eng = _run_engine(cs, 4, graph=False)
+    assert not errs.any()
+    for k in (0, 1):
+        c = cs[k]
+        sim = Simulation(c, DEV)
+        assert sim.shifting
+        sim.run(4)
+        g = sim.host_state()
+        assert sim.error() == 0
+        b = mix[k]
+        scale = max(np.abs(g["vel"]).max(), 1e-3)
+        dv = np.abs(b["vel"] - g["vel"]).max()
+        dx = np.abs(b["pos"] - g["pos"]).max()
+        _say(f"  slot {k}: |dv| {dv:.2e} |dx| {dx:.2e}")
+        assert dv <= 1e-4 * scale + 1e-6 and dx <= 1e-7
