@@ -620,6 +620,22 @@ def main():
         if not args.graph_steps and args.timing == "none":
             phase_src = "5 steps after the timed region"
     phase_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in timing.items()}
+    phase_med = {k: float(np.median([a.elapsed_time(b) for a, b in v]))
+                 for k, v in timing.items()}
+    phase_n = {k: len(v) for k, v in timing.items()}
+    graph_ms = None
+    if args.graph_steps == 0 and not args.neighbour_list:
+        # the whole step replayed from a HIP graph (two steps per graph: the
+        # state buffers alternate), after the timed region
+        sim.capture(2)
+        sim.replay(2)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        sim.replay(10)
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) / 20 * 1e3
+        if sim.error() != 0:
+            raise SystemExit(f"device error word {sim.error()} in the graph replay")
     t_int = phase_ms["interact"] * 1e-3
     flops = (FLOPS_FLUID_PAIR * (pairs - wall_pairs) + FLOPS_WALL_PAIR * wall_pairs) / launches
     achieved = flops / t_int / 1e12
@@ -650,6 +666,9 @@ def main():
         "interactions_per_step": pairs / args.steps,
         "phase_ms_per_call": phase_ms,
         "phase_ms_source": phase_src,
+        "phase_ms_median": phase_med,
+        "phase_calls_timed": phase_n,
+        "graph_replay_ms_per_step": graph_ms,
         "timing_mode": {"events": args.timing, "graph_steps": args.graph_steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
