@@ -569,7 +569,11 @@ enum {
    * options.  A slot of the default formulation gets the same results there
    * as in the default kernel (the same operations), so a case's results
    * still do not depend on the other slots. */
-  SPH_BATCH_GENERAL = 4u
+  SPH_BATCH_GENERAL = 4u,
+  /* some slot has periodic components (Section 2.7): the interaction and
+   * shifting then take the nearest image along each slot's own periodic
+   * components; slots without any see no difference. */
+  SPH_BATCH_PERIODIC = 8u
 };
 
 typedef struct sph_batch {
@@ -592,13 +596,16 @@ size_t sph_batch_table_bytes(int32_t n_slots);
  * to table_host and fills *batch except batch->table.  The caller copies the
  * table to device memory and sets batch->table before the calls below.  The
  * table stays valid while the slots keep their ranges.  Every slot must use
- * the same cell_div, DBC walls (boundary 0), no floating bodies and no
- * periodic components; otherwise SPH_E_ARG.  Each slot may take its own
- * formulation options (kernel, viscosity, ddt; see SPH_BATCH_GENERAL).
+ * the same cell_div, DBC walls (boundary 0) and no floating bodies;
+ * otherwise SPH_E_ARG.  Each slot may take its own formulation options
+ * (kernel, viscosity, ddt; see SPH_BATCH_GENERAL) and periodic components
+ * (see SPH_BATCH_PERIODIC), each of them at least 2 (cell_div + 1) + 1
+ * cells long so that the reused-cells pass can serve it (else SPH_E_ARG).
  * options: 0 or SPH_BATCH_FOUR_LANES (else SPH_E_ARG); batch->flags gets
  * SPH_BATCH_WAVE_ALIGNED when every range is whole wavefronts,
  * SPH_BATCH_FOUR_LANES when it was asked for and the batch is wave-aligned,
- * and SPH_BATCH_GENERAL when some slot takes a formulation option. */
+ * SPH_BATCH_GENERAL when some slot takes a formulation option and
+ * SPH_BATCH_PERIODIC when some slot has periodic components. */
 sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, int32_t n_slots,
                               uint32_t options, void* table_host, size_t table_bytes,
                               sph_batch* batch);

@@ -131,6 +131,10 @@ KParams make_slot_kparams(const sph_params& p) {
     k.gx_f = (float)k.gx;
     k.gy_f = 0.f;
     k.gz_f = (float)k.gz;
+    // a periodic vertical component moves from the second to the third
+    k.periodic = (k.periodic & 1) | ((k.periodic & 2) << 1);
+    k.pz = k.py;
+    k.py = 0.0;
   }
   return k;
 }
@@ -462,17 +466,18 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   if (offsets[0] != 0) return SPH_E_ARG;
   SlotEntry* tab = (SlotEntry*)table_host;
   uint64_t cbase = 0;
-  bool general = false;
+  bool general = false, periodic = false;
   for (int s = 0; s < n_slots; ++s) {
     const sph_params* p = &params[s];
     if (!params_ok(p) || p->cell_div != params[0].cell_div) return SPH_E_ARG;
-    // the batch takes DBC walls and no floating bodies or periodic
-    // components; formulation options (cubic spline kernel, laminar
-    // viscosity, Fourtakas DDT) per slot
-    if (p->boundary != 0 || p->floating != 0 || p->period[0] > 0.0 || p->period[1] > 0.0 ||
-        p->period[2] > 0.0)
-      return SPH_E_ARG;
+    // the batch takes DBC walls and no floating bodies; formulation options
+    // (cubic spline kernel, laminar viscosity, Fourtakas DDT) and periodic
+    // components per slot, the latter long enough for the reused-cells pass
+    if (p->boundary != 0 || p->floating != 0) return SPH_E_ARG;
+    const bool per = p->period[0] > 0.0 || p->period[1] > 0.0 || p->period[2] > 0.0;
+    if (per && !periodic_reach_ok(p, p->cell_div + 1)) return SPH_E_ARG;
     general = general || p->kernel != 0 || p->viscosity != 0 || p->ddt == 2;
+    periodic = periodic || per;
     if (offsets[s + 1] < offsets[s]) return SPH_E_ARG;
     SlotEntry e{};
     e.kp = make_slot_kparams(*p);
@@ -498,7 +503,7 @@ sph_status sph_batch_describe(const sph_params* params, const int64_t* offsets, 
   }
   batch->n_slots = n_slots;
   batch->flags = (aligned ? SPH_BATCH_WAVE_ALIGNED : 0u) | (four ? SPH_BATCH_FOUR_LANES : 0u) |
-                 (general ? SPH_BATCH_GENERAL : 0u);
+                 (general ? SPH_BATCH_GENERAL : 0u) | (periodic ? SPH_BATCH_PERIODIC : 0u);
   batch->lanes = (uint32_t)lanes;
   batch->cell_div = params[0].cell_div;
   batch->n_total = offsets[n_slots];

@@ -77,7 +77,7 @@ __global__ void k_batch_refresh_view(const SlotEntry* __restrict__ tab, int ns, 
 // share target a, each walking every LPT-th stencil row (lane `sub`); every
 // lane of the wave takes part (the lanes' sums are combined by shuffles),
 // and lane sub = 0 writes the target.
-template <int R, bool STALE, bool GEN, int LPT = 1>
+template <int R, bool STALE, bool GEN, bool PER, int LPT = 1>
 __device__ __forceinline__ void batch_slot_pass(
     const SlotEntry* __restrict__ tab, int rs, int leader, bool mine, int64_t n, int64_t a,
     const float4* __restrict__ pr, const float4* __restrict__ vp, const uint32_t* __restrict__ key,
@@ -121,9 +121,8 @@ __device__ __forceinline__ void batch_slot_pass(
       const uint32_t rest = lk / (uint32_t)kp.ncx;
       const int cy = (int)(rest % (uint32_t)kp.ncy);
       const int cz = (int)(rest / (uint32_t)kp.ncy);
-      gather_walk<3, R, false, false, GEN, false, LPT>(kp, cbase, n, a, pa, T, cx, cy, cz, pr,
-                                                       vp, cstart, nullptr, acc, c64, cull2,
-                                                       sub);
+      gather_walk<3, R, false, false, GEN, PER, LPT>(kp, cbase, n, a, pa, T, cx, cy, cz, pr,
+                                                     vp, cstart, nullptr, acc, c64, cull2, sub);
     }
   }
   if (LPT > 1) combine_lanes<LPT>(acc, c64);  // every lane: its target's sums
@@ -151,8 +150,11 @@ __device__ __forceinline__ void batch_slot_pass(
 // displacement).  GEN: some slot takes a formulation option (cubic spline
 // kernel, laminar viscosity, Fourtakas DDT); every slot then runs the
 // general pair terms with its own options, whose default-formulation
-// arithmetic is that of the default kernel, operation for operation.
-template <int R, bool STALE, bool ALIGNED, bool GEN>
+// arithmetic is that of the default kernel, operation for operation.  PER:
+// some slot has periodic components; each slot's walk then takes the
+// nearest image along its own (kp.periodic), and a slot without any walks as
+// in the plain kernel.
+template <int R, bool STALE, bool ALIGNED, bool GEN, bool PER>
 __global__ __launch_bounds__(kBlock) void k_batch_interact(
     const SlotEntry* __restrict__ tab, int ns, int64_t n, int64_t lanes,
     const float4* __restrict__ pr, const float4* __restrict__ vp, const uint32_t* __restrict__ key,
@@ -180,13 +182,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
       const int64_t u = t - tab[rs].loff;
       if (lpt == kMaxLanes) {
         a = tab[rs].off + u / kMaxLanes;
-        batch_slot_pass<R, STALE, GEN, kMaxLanes>(tab, rs, 0, t < lanes, n, a, pr, vp, key,
+        batch_slot_pass<R, STALE, GEN, PER, kMaxLanes>(tab, rs, 0, t < lanes, n, a, pr, vp, key,
                                                   cstart, ace, arho, visc, nbr, disp, err,
                                                   slot_err, fmag, vmx, cnt, cntw, nfl,
                                                   (int)(u % kMaxLanes));
       } else {
         a = tab[rs].off + u;
-        batch_slot_pass<R, STALE, GEN>(tab, rs, 0, t < lanes, n, a, pr, vp, key, cstart, ace,
+        batch_slot_pass<R, STALE, GEN, PER>(tab, rs, 0, t < lanes, n, a, pr, vp, key, cstart, ace,
                                        arho, visc, nbr, disp, err, slot_err, fmag, vmx, cnt,
                                        cntw, nfl);
       }
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_interact(
       const int leader = (int)__builtin_ctzll(__ballot(todo));
       const int rs = __builtin_amdgcn_readlane(sa, leader);
       const bool mine = todo && sa == rs;
-      batch_slot_pass<R, STALE, GEN>(tab, rs, leader, mine, n, a, pr, vp, key, cstart, ace,
+      batch_slot_pass<R, STALE, GEN, PER>(tab, rs, leader, mine, n, a, pr, vp, key, cstart, ace,
                                      arho, visc, nbr, disp, err, slot_err, fmag, vmx, cnt, cntw,
                                      nfl);
       todo = todo && !mine;
@@ -424,15 +426,24 @@ hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
   const SlotEntry* tab = (const SlotEntry*)B.table;
   const bool aligned = (B.flags & SPH_BATCH_WAVE_ALIGNED) != 0;
   const bool general = (B.flags & SPH_BATCH_GENERAL) != 0;
+  const bool per = (B.flags & SPH_BATCH_PERIODIC) != 0;
   // aligned batches: one thread per interaction lane
   const int64_t lanes = aligned ? (int64_t)B.lanes : n;
   const unsigned grid = grid_for(lanes);
-#define SPH_BATCH_LAUNCH_G(RR, STALE, AL, G)                                                   \
-  hipLaunchKernelGGL((k_batch_interact<RR, STALE, AL, G>), dim3(grid), dim3(kBlock), 0, st, tab, \
+#define SPH_BATCH_LAUNCH_GP(RR, STALE, AL, G, PE)                                              \
+  hipLaunchKernelGGL((k_batch_interact<RR, STALE, AL, G, PE>), dim3(grid), dim3(kBlock), 0, st,  \
+                     tab,                                                                       \
                      B.n_slots, n, lanes, ws_ptr<float4>(ws, W.base.view_pr),                   \
                      ws_ptr<float4>(ws, W.base.view_vp), key, cell_start, ace, arho, visc, nbr, \
                      ws_ptr<SlotAccum>(ws, W.accum), ws_ptr<uint32_t>(ws, W.disp),              \
                      ws_ptr<uint32_t>(ws, W.base.err), ws_ptr<uint32_t>(ws, W.slot_err))
+#define SPH_BATCH_LAUNCH_G(RR, STALE, AL, G)        \
+  do {                                              \
+    if (per)                                        \
+      SPH_BATCH_LAUNCH_GP(RR, STALE, AL, G, true);  \
+    else                                            \
+      SPH_BATCH_LAUNCH_GP(RR, STALE, AL, G, false); \
+  } while (0)
 #define SPH_BATCH_LAUNCH(RR, STALE, AL)      \
   do {                                       \
     if (general)                             \
@@ -461,6 +472,7 @@ hipError_t launch_batch_interact(const BatchDesc& B, const uint32_t* key,
 #undef SPH_BATCH_LAUNCH_R
 #undef SPH_BATCH_LAUNCH
 #undef SPH_BATCH_LAUNCH_G
+#undef SPH_BATCH_LAUNCH_GP
   return hipGetLastError();
 }
 

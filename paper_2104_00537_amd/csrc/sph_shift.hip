@@ -276,7 +276,7 @@ __device__ inline float batch_shift_cull2(const KParams& kp, const uint32_t* __r
   return rc * rc;
 }
 
-template <int R, bool APPLY>
+template <int R, bool APPLY, bool PER>
 __global__ __launch_bounds__(kBlock) void k_batch_shift(
     const SlotEntry* __restrict__ tab, int ns, int64_t n, const float4* __restrict__ pr,
     const float4* __restrict__ vp, const uint32_t* __restrict__ key,
@@ -307,13 +307,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_shift(
     if (!APPLY) {
       conc[i] = is_excluded(t)
                     ? 0.f
-                    : conc_one<3, R, false>(kp, cbase, key[i] - cbase, pr[i], pr, cstart, cull2);
+                    : conc_one<3, R, PER>(kp, cbase, key[i] - cbase, pr[i], pr, cstart, cull2);
     } else if (!is_fluid(t) || is_excluded(t)) {
       if (shift)
         for (int d = 0; d < 3; ++d) shift[d * n + i] = 0.f;
     } else {
-      shift_one<3, R, false>(kp, cbase, key[i] - cbase, n, i, pr, vp, cstart, conc, dt[rs],
-                             cull2, pos, shift);
+      shift_one<3, R, PER>(kp, cbase, key[i] - cbase, n, i, pr, vp, cstart, conc, dt[rs], cull2,
+                           pos, shift);
     }
   }
 }
@@ -371,14 +371,22 @@ hipError_t launch_batch_shifting(const BatchDesc& B, const sph_state& s, const u
   const unsigned grid = (unsigned)(g > 0 ? g : 1);
   // reused cells: one more cell of reach, cut widened by each slot's record
   const int reach = B.cell_div + (reuse ? 1 : 0);
-#define SPH_BSHIFT(RR)                                                                          \
+  const bool per = (B.flags & SPH_BATCH_PERIODIC) != 0;
+#define SPH_BSHIFT_P(RR, PE)                                                                    \
   do {                                                                                          \
-    hipLaunchKernelGGL((k_batch_shift<RR, false>), dim3(grid), dim3(kBlock), 0, st, tab,        \
+    hipLaunchKernelGGL((k_batch_shift<RR, false, PE>), dim3(grid), dim3(kBlock), 0, st, tab,    \
                        B.n_slots, n, pr, vp, key, cell_start, s.type, c, dt, s.pos, shift, disp, \
                        err, serr);                                                              \
-    hipLaunchKernelGGL((k_batch_shift<RR, true>), dim3(grid), dim3(kBlock), 0, st, tab,         \
+    hipLaunchKernelGGL((k_batch_shift<RR, true, PE>), dim3(grid), dim3(kBlock), 0, st, tab,     \
                        B.n_slots, n, pr, vp, key, cell_start, s.type, c, dt, s.pos, shift, disp, \
                        err, serr);                                                              \
+  } while (0)
+#define SPH_BSHIFT(RR)             \
+  do {                             \
+    if (per)                       \
+      SPH_BSHIFT_P(RR, true);      \
+    else                           \
+      SPH_BSHIFT_P(RR, false);     \
   } while (0)
   if (reach == 1) {
     SPH_BSHIFT(1);
@@ -388,6 +396,7 @@ hipError_t launch_batch_shifting(const BatchDesc& B, const sph_state& s, const u
     SPH_BSHIFT(3);
   }
 #undef SPH_BSHIFT
+#undef SPH_BSHIFT_P
   return hipGetLastError();
 }
 

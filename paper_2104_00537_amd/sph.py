@@ -47,6 +47,7 @@ SPH_BATCH_MAX_SLOTS = 4096
 SPH_BATCH_WAVE_ALIGNED = 1
 SPH_BATCH_FOUR_LANES = 2
 SPH_BATCH_GENERAL = 4
+SPH_BATCH_PERIODIC = 8
 SPH_NOALLOC_MAX_N = 2097152
 
 

@@ -351,8 +351,9 @@ def test_batch_describe_lanes_per_slot(S):
 
 def test_batch_describe_formulation_options(S):
     """Slots may take formulation options (cubic spline, laminar viscosity,
-    Fourtakas DDT): SPH_BATCH_GENERAL is set iff some slot does.  Modified
-    DBC, floating bodies and periodic components are rejected."""
+    Fourtakas DDT; SPH_BATCH_GENERAL iff some slot does) and periodic
+    components (SPH_BATCH_PERIODIC); modified DBC, floating bodies and
+    periodic components too short for the reused-cells pass are rejected."""
     import dataclasses
     from paper_2104_00537_amd import cases
     base = cases.dam_break_2d(dp=0.05).params
@@ -367,10 +368,14 @@ def test_batch_describe_formulation_options(S):
         ps = [P0, _bad_params(S, **kw)]
         with pytest.raises(S.SphError):
             S.sph_batch_describe(ps, [0, 10, 20])
-    per = S.make_params(base)
-    per.period[0] = float(base.ncell[0] // base.x_sub) * float(base.cell_size)
-    with pytest.raises(S.SphError):
-        S.sph_batch_describe([P0, per], [0, 10, 20])
+    # periodic components per slot, long enough for the reused-cells pass
+    per = S.make_params(cases.periodic_box(2, shape=(60, 14), periodic=(0,)).params)
+    b, _ = S.sph_batch_describe([P0, per], [0, 64, 128])
+    assert b.flags & S.SPH_BATCH_PERIODIC
+    assert not S.sph_batch_describe([P0, P0], [0, 64, 128])[0].flags & S.SPH_BATCH_PERIODIC
+    short = S.make_params(cases.periodic_box(2, shape=(12, 14), periodic=(0,)).params)
+    with pytest.raises(S.SphError):   # 4 cells along x: enough for a walk, not for reuse
+        S.sph_batch_describe([P0, short], [0, 64, 128])
 
 
 def test_periodic_params_validate_without_device(S):
@@ -417,10 +422,10 @@ def test_periodic_params_validate_without_device(S):
                             S.SPH_INTERACT_REUSE_CELLS, d, need6, None) == S.SPH_E_ARG
     for flags in (S.SPH_INTERACT_F64, S.SPH_INTERACT_ABS_F32):
         assert interact(P, flags) == S.SPH_E_ARG
+    # a batch slot must serve the reused-cells pass too: six cells are short
     with pytest.raises(S.SphError):
-        S.sph_batch_describe([S.make_params(cases.dam_break_2d(dp=0.05).params),
-                              S.make_params(cases.periodic_box(2, periodic=(0,)).params)],
-                             [0, 10, 20])
+        S.sph_batch_describe([S.make_params(cases.dam_break_2d(dp=0.05, cell_div=2).params),
+                              P6], [0, 10, 20])
 
 
 def test_shifting_validates_without_device(S):

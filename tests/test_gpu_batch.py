@@ -56,7 +56,25 @@ def _options_mix():
     return out
 
 
-MIXES = {"default": _mix_cases, "options": _options_mix}
+def _periodic_mix(shift=False):
+    """Slots with periodic components (a 2-D channel periodic along x, a
+    2-D column periodic along its vertical, a 3-D box periodic along x and
+    y) beside a slot without any; shift: with particle shifting."""
+    rng = np.random.default_rng(9)
+    base = [cases.periodic_box(2, shape=(60, 14), periodic=(0,), seed=1),
+            cases.periodic_box(2, shape=(14, 30), periodic=(1,), seed=2),
+            cases.periodic_box(3, shape=(24, 20, 10), periodic=(0, 1), seed=3),
+            cases.dam_break_2d(dp=0.02, seed=4)]
+    out = []
+    for c in base:
+        c.vel[:] = rng.uniform(-0.3, 0.3, c.vel.shape).astype(np.float32)
+        kw = dict(shift_coef=2.0) if shift else {}
+        out.append(cases.Case(dataclasses.replace(c.params, **kw), c.pos, c.vel, c.rho, c.type,
+                              dict(c.meta), c.normal))
+    return out
+
+
+MIXES = {"default": _mix_cases, "options": _options_mix, "periodic": _periodic_mix}
 
 
 def _engine(cs, graph=False, reuse=True, pad=True, four=False):
@@ -79,7 +97,9 @@ def _run_engine(cs, steps, graph, reuse=True, pad=True, four=False):
 @pytest.mark.parametrize("reuse,pad,four,mixname", [
     (True, True, False, "default"), (False, True, False, "default"),
     (True, False, False, "default"), (True, True, True, "default"),
-    (True, True, False, "options"), (True, False, False, "options")])
+    (True, True, False, "options"), (True, False, False, "options"),
+    (True, True, False, "periodic"), (False, True, False, "periodic"),
+    (True, True, True, "periodic")])
 def test_batch_alone_vs_mix_bit_identical(reuse, pad, four, mixname):
     """pad: slots padded to whole wavefronts (the aligned kernel) or not (the
     unaligned kernel, wavefronts straddling slots); four: four lanes per
@@ -93,6 +113,7 @@ def test_batch_alone_vs_mix_bit_identical(reuse, pad, four, mixname):
     assert bool(eng.batch.flags & S.SPH_BATCH_WAVE_ALIGNED) == pad
     assert bool(eng.batch.flags & S.SPH_BATCH_FOUR_LANES) == four
     assert bool(eng.batch.flags & S.SPH_BATCH_GENERAL) == (mixname == "options")
+    assert bool(eng.batch.flags & S.SPH_BATCH_PERIODIC) == (mixname == "periodic")
     for k, c in enumerate(cs):
         alone, e1, _ = _run_engine([c], 7, graph=False, reuse=reuse, pad=pad, four=four)
         assert not e1.any()
@@ -128,7 +149,9 @@ def test_batch_matches_single_case_path(reuse):
 
 @pytest.mark.parametrize("pad,four,mixname", [(True, False, "default"), (False, False, "default"),
                                               (True, True, "default"), (True, False, "options"),
-                                              (False, False, "options"), (True, True, "options")])
+                                              (False, False, "options"), (True, True, "options"),
+                                              (True, False, "periodic"),
+                                              (False, False, "periodic")])
 def test_batch_interaction_matches_oracle(pad, four, mixname):
     cs = MIXES[mixname]()
     eng = _engine(cs, pad=pad, four=four)
@@ -321,13 +344,15 @@ def _shifting_mix():
     return out
 
 
-@pytest.mark.parametrize("pad", [True, False])
-def test_batch_shifting_matches_oracle(pad):
+@pytest.mark.parametrize("pad,mixname", [(True, "shift"), (False, "shift"),
+                                         (True, "periodic")])
+def test_batch_shifting_matches_oracle(pad, mixname):
     """sph_batch_shifting on a freshly binned batch against the oracle's
     shifting per slot (the single-case bars: C within 1e-5, the shift within
-    1e-4 of the slot's largest on matching surface decisions); the slot
-    without shifting is left as it is."""
-    cs = _shifting_mix()
+    1e-4 of the slot's largest on matching surface decisions); a slot
+    without shifting is left as it is.  periodic: every slot shifted, three
+    of them with periodic components."""
+    cs = _shifting_mix() if mixname == "shift" else _periodic_mix(shift=True)
     eng = _engine(cs, pad=pad)
     eng.repack([], [V.Request(rid=k, case=c, steps=1, arrival=0.0) for k, c in enumerate(cs)])
     assert eng.shifting
@@ -341,7 +366,7 @@ def test_batch_shifting_matches_oracle(pad):
     vel_all = bb.vel.cpu().numpy().astype(np.float64)
     rho_all = bb.rho.cpu().numpy().astype(np.float64)
     typ_all = bb.type.cpu().numpy()
-    dts = [2e-4, 1.5e-4, 1e-4, 2.5e-4]
+    dts = [2e-4, 1.5e-4, 1e-4, 2.5e-4][: len(cs)]
     dt = torch.tensor(dts, dtype=torch.float64, device=DEV)
     conc = torch.full((n,), float("nan"), dtype=torch.float32, device=DEV)
     shift = torch.full((3, n), float("nan"), dtype=torch.float32, device=DEV)
