@@ -217,12 +217,14 @@ class BatchHalfStep:
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("mixname", ["default", "periodic"])
 @pytest.mark.parametrize("move", [0.05, 0.3])
-def test_batch_reused_cells_find_the_oracles_pairs(move):
+def test_batch_reused_cells_find_the_oracles_pairs(move, mixname):
     """The n+1/2 interaction on the cells of state n, per slot against the
     oracle on the half state: rates to the interaction's bar, FP32 neighbour
-    counts with flips only at near-ties."""
-    cs = _mix_cases()
+    counts with flips only at near-ties (periodic slots: pairs across their
+    periodic boundaries, particles moved past them not yet wrapped)."""
+    cs = MIXES[mixname]()
     hs = BatchHalfStep(cs, [move] * len(cs))
     eng, b, n = hs.eng, hs.b, hs.n
     S.sph_batch_refresh_view(b, hs.st, hs.key, eng.ws)
