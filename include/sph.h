@@ -21,9 +21,18 @@
  *                        after each phase of sph_symplectic_step.
  *   sph_shifting         particle shifting (Section 2.8, Eq. 40-41, 53) after
  *                        the corrector.
+ *   sph_refresh_view     the interaction's view of the half state on the cells
+ *                        of the last binning (the n+1/2 PI without a second NL).
+ *   sph_build_list,      per-target neighbour lists with a skin, built once per
+ *   sph_interact_list    NL and replayed by both PIs of a step (opt-in).
+ *   sph_interact_noalloc sph_interact for callers that cannot allocate.
+ *   sph_batch_*          the same steps over many independent cases at once
+ *                        (continuous batching).
  *
  * A full step is: bin, interact, reduce_dt, predictor, bin (carrying the saved
- * state along), interact, corrector.
+ * state along), interact, corrector; or, with one NL per step: bin, interact,
+ * reduce_dt, predictor, refresh_view, interact (SPH_INTERACT_REUSE_CELLS),
+ * corrector.
  *
  * Conventions
  *  - Every array argument is a DEVICE pointer to memory the caller owns (the
