@@ -554,7 +554,10 @@ sph_status sph_floating_step(const sph_params* p, int64_t n, int32_t phase, cons
  * sort; results of a case do not depend on the other cases in the batch.
  * Packed arrays always have three components: a 2-D case (x, z) is stored as
  * (x, 0, z) and gets one cell across y.  All slots share cell_div; at most
- * 2^27 - 1 particles in total.
+ * 2^27 - 1 particles in total.  With one lane per target (no
+ * SPH_BATCH_FOUR_LANES, and SPH_INTERACT_ONE_LANE on the single-case side)
+ * a slot's results are those of the single-case calls on the same case, bit
+ * for bit.
  */
 #define SPH_BATCH_MAX_SLOTS 4096
 

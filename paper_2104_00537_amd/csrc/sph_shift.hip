@@ -74,7 +74,10 @@ __device__ inline void visit_neighbours(const KParams& kp, uint32_t cbase, const
             const float dx = (float)(int32_t)(xv - __float_as_uint(pb[u].x)) * kp.unit_x_f;
             const float ddy = ys - pb[u].y;
             const float ddz = DIM == 3 ? zs - pb[u].z : 0.f;
-            const float r2 = dx * dx + ddy * ddy + ddz * ddz;
+            // explicit fma chains: a zero component (2-D cases, and 2-D
+            // slots of a batch in the packed (x, 0, z) layout) adds exactly
+            // nothing, so both layouts round alike
+            const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, dx * dx));
             if (j + u < j1 && r2 < kp.support2_f) f(j + u, dx, ddy, ddz, r2, pb[u]);
           }
         }
@@ -192,16 +195,18 @@ __device__ inline void shift_one(const KParams& kp, uint32_t cbase, uint32_t lk,
         g1 = fmaf(w, dy, g1);
         g2 = fmaf(w, dz, g2);
       });
-  const float speed = __builtin_amdgcn_sqrtf(va.x * va.x + va.y * va.y + va.z * va.z);
+  // sums over components as explicit fma chains (see visit_neighbours)
+  const float speed =
+      __builtin_amdgcn_sqrtf(fmaf(va.z, va.z, fmaf(va.y, va.y, va.x * va.x)));
   const float ds = kp.shift_k_f * speed * (float)dt;
   float d[3] = {-ds * g0, -ds * g1, DIM == 3 ? -ds * g2 : 0.f};
   if (kp.shift_fs_f > 0.f && ca < kp.shift_fs_f) {
-    const float gg = g0 * g0 + g1 * g1 + g2 * g2;
+    const float gg = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
     if (gg > 0.f) {
-      const float k = (d[0] * g0 + d[1] * g1 + d[2] * g2) / gg;
-      d[0] -= k * g0;
-      d[1] -= k * g1;
-      d[2] -= k * g2;
+      const float k = fmaf(d[2], g2, fmaf(d[1], g1, d[0] * g0)) / gg;
+      d[0] = fmaf(-k, g0, d[0]);
+      d[1] = fmaf(-k, g1, d[1]);
+      d[2] = fmaf(-k, g2, d[2]);
     }
   }
   for (int c = 0; c < DIM; ++c) {

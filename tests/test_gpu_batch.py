@@ -438,3 +438,27 @@ def test_batch_shifting_matches_single_case_path():
         dx = np.abs(b["pos"] - g["pos"]).max()
         _say(f"  slot {k}: |dv| {dv:.2e} |dx| {dx:.2e}")
         assert dv <= 1e-4 * scale + 1e-6 and dx <= 1e-7
+
+
+@pytest.mark.parametrize("reuse", [True, False])
+@pytest.mark.parametrize("mixname", ["default", "options", "periodic", "shift"])
+def test_batch_equals_single_case_path_bit_for_bit(reuse, mixname):
+    """With one lane per target on both sides, a case stepped in the batch
+    (one slot of a mix, 2-D cases in the packed (x, 0, z) layout) and the
+    same case stepped alone by the single-case runner
+    (SPH_INTERACT_ONE_LANE) have the same state bit for bit: the same keys,
+    stable order, view, pair terms in the same order, Δt, update and
+    shifting."""
+    cs = MIXES[mixname]() if mixname != "shift" else _shifting_mix()
+    mix, errs, eng = _run_engine(cs, 5, graph=False, reuse=reuse)
+    assert not errs.any()
+    for k, c in enumerate(cs):
+        sim = Simulation(c, DEV, reuse_cells=reuse, flags=S.SPH_INTERACT_ONE_LANE)
+        sim.run(5)
+        g = sim.host_state()
+        assert sim.error() == 0
+        b = mix[k]
+        for f in ("pos", "vel", "rho", "type"):
+            assert np.array_equal(b[f], g[f]), (k, f, np.abs(b[f].astype(np.float64)
+                                                             - g[f]).max())
+        assert b["t"] == g["t"], k
